@@ -1,0 +1,452 @@
+"""Pins of the FP64 oracle to facts fixed outside the oracle itself.
+
+Each test ties one part of the oracle to a closed form, a theorem, a textbook
+routine or brute force, so that a plausible slip (a dropped term, a sign, an
+index, a transposed operand) fails at least one of them.  CPU only.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _single_row(orc, a, lo, up, lam=1.0, box=None, obj=0, **kw):
+    a = np.asarray(a, float)
+    n = a.size
+    blo, bhi = (None, None) if box is None else box
+    return orc.Problem(
+        1, n, [0, n], np.arange(n), a, [lo], [up], box_lo=blo, box_hi=bhi, lam=lam, obj=obj, **kw
+    )
+
+
+def _dense_problem(orc, A, lo, up, **kw):
+    A = np.asarray(A, float)
+    m, n = A.shape
+    rows, cols = np.nonzero(A)
+    rp = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rp[1:])
+    return orc.Problem(m, n, rp, cols, A[rows, cols], lo, up, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Projection onto one band (Section 2.1.1) and its relaxation
+# ---------------------------------------------------------------------------
+
+def test_golden_halfspace_cases(orc):
+    """Hand-derived projections from the half-space formula (golden file)."""
+    path = os.path.join(GOLDEN, "halfspace_projection.txt")
+    n_cases = 0
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        name, a, lo, up, lam, x, tx, prox = [f.strip() for f in line.split(";")]
+        a = np.array(a.split(), float)
+        P = _single_row(orc, a, float(lo), float(up), lam=float(lam))
+        x = np.array(x.split(), float)
+        Tx, p = P.step(x)
+        np.testing.assert_allclose(Tx, np.array(tx.split(), float), rtol=0, atol=1e-14, err_msg=name)
+        assert p == pytest.approx(float(prox), abs=1e-14), name
+        n_cases += 1
+    assert n_cases == 6
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_single_band_is_euclidean_projection(orc, seed):
+    """For one row, lambda = 1 and no box, T(x) is the nearest point of the band:
+    compared with a generic constrained least-distance solve (SLSQP)."""
+    rng = np.random.default_rng(seed)
+    n = 5
+    a = rng.standard_normal(n)
+    x = rng.standard_normal(n) * 3
+    r = a @ x
+    lo, up = sorted(rng.uniform(-2, 2, 2))
+    if seed % 3 == 0:
+        lo = -np.inf
+    P = _single_row(orc, a, lo, up)
+    Tx, _ = P.step(x)
+    cons = []
+    if np.isfinite(lo):
+        cons.append({"type": "ineq", "fun": lambda y: a @ y - lo, "jac": lambda y: a})
+    cons.append({"type": "ineq", "fun": lambda y: up - a @ y, "jac": lambda y: -a})
+    res = minimize(
+        lambda y: 0.5 * np.sum((y - x) ** 2),
+        x,
+        jac=lambda y: y - x,
+        constraints=cons,
+        method="SLSQP",
+        options={"ftol": 1e-14, "maxiter": 200},
+    )
+    assert res.success
+    np.testing.assert_allclose(Tx, res.x, atol=1e-7)
+    # lands exactly on the violated bound, or stays put
+    assert a @ Tx == pytest.approx(min(max(r, lo), up), abs=1e-12)
+
+
+def test_reflection_lambda2_is_involution(orc):
+    """With l = u (a hyperplane) and lambda = 2, T is the reflection: T(T(x)) = x."""
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        a = rng.standard_normal(4)
+        b = rng.standard_normal()
+        P = _single_row(orc, a, b, b, lam=2.0)
+        x = rng.standard_normal(4)
+        y, _ = P.step(x)
+        z, _ = P.step(y)
+        np.testing.assert_allclose(z, x, atol=1e-13)
+        assert a @ (0.5 * (x + y)) == pytest.approx(b, abs=1e-13)
+
+
+def test_proximity_is_half_weighted_squared_distance(orc):
+    """Proximity equals 1/2 sum_i w_i dist(x, C_i)^2 with each distance measured
+    by a generic least-distance solve, and weights normalised to sum 1."""
+    rng = np.random.default_rng(5)
+    m, n = 4, 3
+    A = rng.standard_normal((m, n))
+    lo = rng.uniform(-1.0, 0.0, m)
+    up = lo + rng.uniform(0.1, 0.5, m)
+    wts = rng.uniform(0.5, 2.0, m)
+    P = _dense_problem(orc, A, lo, up, weights=wts)
+    x = rng.standard_normal(n) * 2
+    total = 0.0
+    for i in range(m):
+        a = A[i]
+        cons = [
+            {"type": "ineq", "fun": lambda y, a=a, l=lo[i]: a @ y - l},
+            {"type": "ineq", "fun": lambda y, a=a, u=up[i]: u - a @ y},
+        ]
+        res = minimize(lambda y: 0.5 * np.sum((y - x) ** 2), x, constraints=cons, method="SLSQP",
+                       options={"ftol": 1e-15, "maxiter": 300})
+        total += wts[i] / wts.sum() * np.sum((res.x - x) ** 2)
+    assert P.proximity(x) == pytest.approx(0.5 * total, rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# The simultaneous step
+# ---------------------------------------------------------------------------
+
+def test_weighted_least_squares_limit(orc):
+    """l = u = b, no box, full column rank: the simultaneous iteration is a
+    gradient method on 1/2 ||D^(1/2)(Ax - b)||^2, D = diag(w_i/||a_i||^2), so it
+    converges to the weighted least-squares solution (numpy lstsq)."""
+    rng = np.random.default_rng(3)
+    m, n = 8, 3
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)  # inconsistent
+    P = _dense_problem(orc, A, b, b, lam=1.5)
+    x, _, _ = P.run(np.zeros(n), 20000, perturb=False)
+    D = (1.0 / m) / np.sum(A * A, axis=1)
+    ref = np.linalg.lstsq(np.sqrt(D)[:, None] * A, np.sqrt(D) * b, rcond=None)[0]
+    np.testing.assert_allclose(x, ref, rtol=1e-9, atol=1e-10)
+
+
+@pytest.mark.parametrize("lam", [0.5, 1.0, 1.9])
+def test_proximity_nonincreasing_unperturbed(orc, lam):
+    """Projected gradient on P with step lambda <= 2/L, L <= sum w_i = 1:
+    the proximity never increases, on consistent and inconsistent systems."""
+    for seed in range(3):
+        w = W.random_sparse(60, 40, 6, seed=100 + seed, empty_frac=0.1)
+        P = orc.from_workload(w.with_params(lam=lam))
+        _, _, h = P.run(w.x0[:, 0], 200, perturb=False)
+        d = np.diff(h.prox)
+        assert np.all(d <= 1e-12 * h.prox[:-1] + 1e-300), (seed, d.max())
+
+
+def test_box_feasible_after_each_step(orc):
+    w = W.random_sparse(50, 30, 5, seed=7)
+    P = orc.from_workload(w)
+    x = w.x0[:, 0].astype(float) * 4 - 2
+    for _ in range(10):
+        x, _ = P.step(x)
+        assert np.all(x >= w.box_lo - 0) and np.all(x <= w.box_hi + 0)
+
+
+# ---------------------------------------------------------------------------
+# Brute-force LP feasibility on tiny instances
+# ---------------------------------------------------------------------------
+
+def _vertices(A, lo, up, box):
+    """All vertices of {lo <= Ax <= up, -box <= x <= box} by enumeration of
+    n-subsets of the bounding hyperplanes."""
+    m, n = A.shape
+    H, h = [], []
+    for i in range(m):
+        if np.isfinite(lo[i]):
+            H.append(A[i]); h.append(lo[i])
+        if np.isfinite(up[i]):
+            H.append(A[i]); h.append(up[i])
+    for j in range(n):
+        e = np.zeros(n); e[j] = 1
+        H.append(e); h.append(box); H.append(e); h.append(-box)
+    H, h = np.array(H), np.array(h)
+    out = []
+    for idx in itertools.combinations(range(len(h)), n):
+        M = H[list(idx)]
+        if abs(np.linalg.det(M)) < 1e-9:
+            continue
+        out.append(np.linalg.solve(M, h[list(idx)]))
+    return out
+
+
+def _feasible(A, lo, up, box, tol=1e-9):
+    for v in _vertices(A, lo, up, box):
+        r = A @ v
+        if np.all(r >= lo - tol) and np.all(r <= up + tol) and np.all(np.abs(v) <= box + tol):
+            return True
+    return False
+
+
+def test_lp_feasibility_brute_force(orc):
+    """Vertex enumeration decides feasibility of tiny systems; the unperturbed
+    simultaneous method must drive the proximity to 0 exactly on the feasible
+    ones, and to the box-constrained minimum of the proximity otherwise."""
+    n_feas = n_infeas = 0
+    for seed in range(100, 140):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(2, 4))
+        m = int(rng.integers(2, 7))
+        A = rng.integers(-3, 4, size=(m, n)).astype(float)
+        A[np.all(A == 0, axis=1), 0] = 1.0
+        box = 2.0
+        if seed % 2 == 0:  # feasible with a margin around a centre point
+            xc = rng.uniform(-1.5, 1.5, n)
+            r = A @ xc
+            marg = 0.05 * np.linalg.norm(A, axis=1) + rng.uniform(0, 0.5, m)
+            lo, up = r - marg, r + marg
+        else:
+            lo = rng.uniform(-4, 4, m)
+            up = lo + rng.uniform(0.0, 0.5, m)
+        feas = _feasible(A, lo, up, box)
+        P = _dense_problem(orc, A, lo, up, box_lo=np.full(n, -box), box_hi=np.full(n, box), lam=1.0)
+        x, _, _ = P.run(np.zeros(n), 100000, perturb=False)
+        pk = P.proximity(x)
+        if feas:
+            n_feas += 1
+            if seed % 2 == 0:
+                assert pk <= 1e-10, (seed, pk)
+            else:
+                assert pk <= 1e-5, (seed, pk)
+        else:
+            n_infeas += 1
+            best = np.inf
+            for s in range(8):
+                x0 = np.random.default_rng(s).uniform(-box, box, n)
+                res = minimize(P.proximity, x0, method="L-BFGS-B", bounds=[(-box, box)] * n,
+                               options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 2000})
+                best = min(best, res.fun)
+            assert best > 1e-8
+            assert pk == pytest.approx(best, rel=1e-5, abs=1e-9), (seed, pk, best)
+    assert n_feas >= 15 and n_infeas >= 5
+
+
+# ---------------------------------------------------------------------------
+# Perturbation schedule (Section 2.1.2, Algorithm 1)
+# ---------------------------------------------------------------------------
+
+def _unconstrained(orc, n, obj, **kw):
+    """A problem whose feasibility step is the identity (no finite bound)."""
+    return orc.Problem(1, n, [0, 0], [], [], [-np.inf], [np.inf], obj=obj, **kw)
+
+
+def test_sqnorm_norm_dynamics_closed_form(orc):
+    """f = ||x||^2 with the direction v = -u, u = x^k/||x^k||, fixed for the
+    phase: inside a phase x = s u for a signed scalar s (s = ||x^k|| at the
+    start), a trial beta is accepted iff (s - beta)^2 <= s^2, i.e. iff s > 0 and
+    beta <= 2 s, and then s <- s - beta.  beta = gamma alpha^ell with ell
+    advancing once per trial.  The final x is the product of the per-phase
+    factors s_end / s_start times x0."""
+    rng = np.random.default_rng(0)
+    x0 = rng.standard_normal(7)
+    gamma, alpha, n_red, J, K = 1.3, 0.9, 2, 40, 30
+    P = _unconstrained(orc, 7, W.OBJ_SQNORM, gamma=gamma, alpha=alpha, n_red=n_red, max_trials=J)
+    x, st, h = P.run(x0, K)
+    rho, ell, scale, trials, caps = np.linalg.norm(x0), 0, 1.0, 0, 0
+    for _ in range(K):
+        if rho == 0:
+            continue
+        s = rho
+        for _ in range(n_red):
+            ok = False
+            for _ in range(J):
+                beta = gamma * alpha**ell
+                ell += 1
+                trials += 1
+                if s > 0 and beta <= 2 * s:
+                    s -= beta
+                    ok = True
+                    break
+            if not ok:
+                caps += 1
+                break
+        scale *= s / rho
+        rho = abs(s)
+    assert st.ell == ell and st.trials == trials and st.cap_hits == caps
+    assert caps > 0  # the overshoot case is exercised
+    np.testing.assert_allclose(x, scale * x0, rtol=1e-12, atol=1e-14)
+
+
+def test_linear_objective_always_accepts(orc):
+    """f = c^T x: f(x + beta v) - f(x) = -beta ||c|| < 0, so every trial is
+    accepted, trials = accepts = n_red in each iteration."""
+    w = W.random_sparse(40, 25, 5, seed=9, obj=W.OBJ_LINEAR)
+    P = orc.from_workload(w.with_params(n_red=3, gamma=0.1))
+    _, st, h = P.run(w.x0[:, 0], 15)
+    assert np.all(h.trials == 3) and np.all(h.accepts == 3)
+    assert st.cap_hits == 0
+    assert np.all(h.f_end < h.f_start)
+
+
+def test_linear_objective_is_summed_dose(orc):
+    """With c = A^T 1 the linear objective is the summed 'dose' sum_i (Ax)_i."""
+    w = W.random_sparse(30, 20, 4, seed=10)
+    A = w.dense()
+    c = A.sum(axis=0)
+    P = orc.from_workload(w.with_params(obj=W.OBJ_LINEAR, linear_c=c.astype(np.float32)))
+    x = np.random.default_rng(1).uniform(0, 1, 20)
+    assert P.objective(x) == pytest.approx(np.sum(A @ x), rel=1e-6)
+
+
+def test_restart_schedule(orc):
+    """Restarts at k = n_rs, 2 n_rs, ...: r grows by one and ell <- r.  With every
+    trial accepted, ell after K iterations is r + (K - k_last) * n_red."""
+    n_red, n_rs, K = 2, 7, 30
+    P = _unconstrained(orc, 5, W.OBJ_SQNORM, gamma=1e-3, alpha=0.9, n_red=n_red, restart_every=n_rs)
+    x0 = np.full(5, 100.0)
+    _, st, h = P.run(x0, K)
+    r = (K - 1) // n_rs
+    assert st.restarts == r
+    assert st.ell == r + (K - r * n_rs) * n_red
+    assert np.all(h.accepts == n_red)
+
+
+def test_bounded_perturbations(orc):
+    """The accepted perturbations are summable: their total length is at most
+    gamma * sum_{q=0..R} alpha^q / (1 - alpha) for R restarts."""
+    rng = np.random.default_rng(2)
+    x0 = rng.standard_normal(6) * 50
+    gamma, alpha, n_rs, K = 2.0, 0.8, 10, 45
+    P = _unconstrained(orc, 6, W.OBJ_SQNORM, gamma=gamma, alpha=alpha, n_red=3, restart_every=n_rs)
+    x, st, _ = P.run(x0, K)
+    R = st.restarts
+    bound = gamma * sum(alpha**q for q in range(R + 1)) / (1 - alpha)
+    assert np.linalg.norm(x - x0) <= bound + 1e-12
+
+
+def test_phase_never_increases_objective(orc):
+    """Acceptance rule: every accepted trial satisfies f(z) <= f(x^{k,n})."""
+    w = W.random_sparse(40, 36, 5, seed=12, obj=W.OBJ_TV2D, tv_shape=(6, 6))
+    P = orc.from_workload(w)
+    x, _, h = P.run(w.x0[:, 0], 25)
+    ok = ~np.isnan(h.f_start)
+    assert np.all(h.f_end[ok] <= h.f_start[ok])
+    assert np.all(h.accepts <= h.trials)
+
+
+def test_checkpoint_resume_bitwise(orc):
+    w = W.random_sparse(40, 36, 5, seed=13, obj=W.OBJ_TV2D, tv_shape=(6, 6))
+    P = orc.from_workload(w)
+    xa, sa, _ = P.run(w.x0[:, 0], 20)
+    x1, s1, _ = P.run(w.x0[:, 0], 8)
+    xb, sb, _ = P.run(x1, 12, state=s1)
+    assert np.array_equal(xa, xb) and sa.as_dict() == sb.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# Total variation (Section 2.3.1)
+# ---------------------------------------------------------------------------
+
+def _tv_problem(orc, R, C, eps):
+    n = R * C
+    return orc.Problem(1, n, [0, 0], [], [], [-np.inf], [np.inf], obj=W.OBJ_TV2D, tv_rows=R, tv_cols=C, tv_eps=eps)
+
+
+def test_tv_constant_and_ramps(orc):
+    R, C, eps = 5, 8, 0.3
+    P = _tv_problem(orc, R, C, eps)
+    assert P.objective(np.full(R * C, 2.5)) == pytest.approx((R - 1) * (C - 1) * eps, rel=1e-14)
+    I, J = np.meshgrid(np.arange(R), np.arange(C), indexing="ij")
+    a, b = 0.7, -1.9
+    X = (a * I + b * J).reshape(-1)
+    assert P.objective(X) == pytest.approx((R - 1) * (C - 1) * math.sqrt(a * a + b * b + eps * eps), rel=1e-13)
+    # variation along rows only, on a non-square grid: pins the row-major layout
+    X = (1.0 * I).reshape(-1)
+    assert P.objective(X) == pytest.approx((R - 1) * (C - 1) * math.sqrt(1 + eps * eps), rel=1e-13)
+    # a single bright pixel in the interior
+    P0 = _tv_problem(orc, R, C, 0.0)
+    X = np.zeros((R, C)); X[2, 3] = 1.0
+    # terms touching (2,3): its own (sqrt 2), from above (i=1,j=3: dx=1), from the left (i=2,j=2: dy=1)
+    assert P0.objective(X.reshape(-1)) == pytest.approx(math.sqrt(2) + 2.0, rel=1e-14)
+
+
+def test_tv_gradient_matches_finite_differences(orc):
+    rng = np.random.default_rng(4)
+    R, C, eps = 7, 9, 0.05
+    P = _tv_problem(orc, R, C, eps)
+    x = rng.uniform(0, 1, R * C)
+    g = P.gradient(x)
+    h = 1e-6
+    fd = np.empty_like(x)
+    for p in range(x.size):
+        e = np.zeros_like(x); e[p] = h
+        fd[p] = (P.objective(x + e) - P.objective(x - e)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+
+
+def test_tv_transpose_invariance_and_zero_subgradient(orc):
+    rng = np.random.default_rng(6)
+    N = 6
+    P = _tv_problem(orc, N, N, 0.01)
+    X = rng.uniform(0, 1, (N, N))
+    assert P.objective(X.reshape(-1)) == pytest.approx(P.objective(X.T.reshape(-1)), rel=1e-14)
+    gX = P.gradient(X.reshape(-1)).reshape(N, N)
+    gXt = P.gradient(X.T.reshape(-1)).reshape(N, N)
+    np.testing.assert_allclose(gX.T, gXt, atol=1e-14)
+    P0 = _tv_problem(orc, N, N, 0.0)
+    assert np.all(P0.gradient(np.ones(N * N)) == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Products and storage rounding
+# ---------------------------------------------------------------------------
+
+def test_products_match_dense(orc):
+    w = W.random_sparse(70, 50, 8, seed=21, long_rows=2)
+    A = w.dense()
+    P = orc.from_workload(w)
+    x = np.random.default_rng(0).standard_normal(50)
+    c = np.random.default_rng(1).standard_normal(70)
+    np.testing.assert_allclose(P.matvec(x), A @ x, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(P.matvec_t(c), A.T @ c, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(P.row_sqnorms(), np.sum(A * A, axis=1), rtol=1e-14)
+
+
+def test_bf16_rounding_matches_torch(orc):
+    import torch
+
+    rng = np.random.default_rng(0)
+    v = np.concatenate([rng.standard_normal(20000), rng.uniform(-1e-30, 1e-30, 1000), [0.0, -0.0, 1.0, 65504.0]])
+    v = v.astype(np.float32)
+    # ties: mantissa ending exactly in 0x8000
+    ties = (np.arange(1, 200, dtype=np.uint32) << 16 | 0x8000 | (0x3F800000)).view(np.float32)
+    v = np.concatenate([v, ties])
+    ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    out = orc.round_bf16(v.astype(np.float64))
+    assert np.array_equal(out, ref)
+
+
+def test_f16_scaled_rounding_matches_numpy(orc):
+    rng = np.random.default_rng(1)
+    v = (rng.standard_normal(20000) * np.exp(rng.uniform(-12, 2, 20000))).astype(np.float32).astype(np.float64)
+    out, s = orc.round_f16_scaled(v)
+    amax = np.abs(v).max()
+    e = math.ceil(math.log2(amax))
+    assert s == 2.0 ** (14 - e)
+    ref = (v * s).astype(np.float16).astype(np.float64) / s
+    assert np.array_equal(out, ref)

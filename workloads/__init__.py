@@ -1,0 +1,629 @@
+"""Seeded synthetic inputs for the superiorized band+box projection method.
+
+This module only synthesises data: matrices from ray geometry or dose kernels,
+phantoms, noise, and the bands built around noisy measurements.  It holds none
+of the method's arithmetic (no projection, proximity, objective or perturbation
+step), so both the FP64 oracle and the HIP library can consume its arrays
+without sharing any part of the computation.
+
+Every generator is deterministic in its seed (``numpy.random.default_rng``).
+Shapes follow the workloads of the paper (Section 2.3): straight-ray seismic
+travel-time tomography, parallel-beam CT, and a radiotherapy dose-influence
+matrix; the datasets and toolboxes the paper used are replaced by these
+synthetic stand-ins.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+
+OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+OBJ_NAMES = {OBJ_NONE: "none", OBJ_SQNORM: "sqnorm", OBJ_TV2D: "tv2d", OBJ_LINEAR: "linear"}
+
+
+@dataclass
+class Workload:
+    """One band+box feasibility problem with a secondary objective.
+
+    Constraint rows are ``lower[i,s] <= <a_i, x_s> <= upper[i,s]`` for every slice
+    ``s`` (slices share ``A``), plus ``box_lo <= x <= box_hi``.  Arrays are float32
+    (the device precision); the oracle promotes them exactly to float64.
+    ``lower``/``upper`` are ``[m, B]`` and ``x0`` is ``[n, B]``.
+    """
+
+    name: str
+    m: int
+    n: int
+    row_ptr: np.ndarray  # int32 [m+1]
+    col_idx: np.ndarray  # int32 [nnz]
+    val: np.ndarray  # float32 [nnz]
+    lower: np.ndarray  # float32 [m, B]
+    upper: np.ndarray  # float32 [m, B]
+    box_lo: np.ndarray  # float32 [n]
+    box_hi: np.ndarray  # float32 [n]
+    x0: np.ndarray  # float32 [n, B]
+    lam: float = 1.0
+    obj: int = OBJ_NONE
+    tv_rows: int = 0
+    tv_cols: int = 0
+    tv_eps: float = 0.0
+    linear_c: Optional[np.ndarray] = None  # float32 [n]
+    gamma: float = 1.0
+    alpha: float = 0.99
+    n_red: int = 1
+    restart_every: int = 0
+    max_trials: int = 100
+    K: int = 100
+    weights: Optional[np.ndarray] = None  # float64 [m]; None means uniform 1/m
+    x_true: Optional[np.ndarray] = None  # float32 [n, B]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    @property
+    def B(self) -> int:
+        return int(self.lower.shape[1])
+
+    def with_params(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+    def slice(self, s: int) -> "Workload":
+        """The single-slice problem for slice ``s`` (same ``A``)."""
+        return replace(
+            self,
+            lower=np.ascontiguousarray(self.lower[:, s : s + 1]),
+            upper=np.ascontiguousarray(self.upper[:, s : s + 1]),
+            x0=np.ascontiguousarray(self.x0[:, s : s + 1]),
+            x_true=None if self.x_true is None else np.ascontiguousarray(self.x_true[:, s : s + 1]),
+        )
+
+    def dense(self) -> np.ndarray:
+        """Dense float64 copy of A (small problems only)."""
+        A = np.zeros((self.m, self.n), dtype=np.float64)
+        for i in range(self.m):
+            s, e = self.row_ptr[i], self.row_ptr[i + 1]
+            np.add.at(A[i], self.col_idx[s:e], self.val[s:e].astype(np.float64))
+        return A
+
+
+def _csr_from_dense(A: np.ndarray):
+    m, n = A.shape
+    mask = A != 0
+    counts = mask.sum(axis=1)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    rows, cols = np.nonzero(mask)
+    return row_ptr.astype(np.int32), cols.astype(np.int32), A[rows, cols].astype(np.float32)
+
+
+def _csr_matvec64(row_ptr, col_idx, val, x):
+    """Forward model used only to synthesise measurements (float64)."""
+    m = len(row_ptr) - 1
+    rows = np.repeat(np.arange(m), np.diff(row_ptr.astype(np.int64)))
+    prod = val.astype(np.float64) * x[col_idx]
+    return np.bincount(rows, weights=prod, minlength=m)
+
+
+# ---------------------------------------------------------------------------
+# Dense consistent problem (small CPU-scale case)
+# ---------------------------------------------------------------------------
+
+def dense_small(seed: int = 1, m: int = 256, n: int = 128, K: int = 100) -> Workload:
+    """Dense N(0,1) A with a hidden x* ~ U(0,1), bands A x* +- 0.05, box [0,1].
+
+    Consistent by construction (x* satisfies every band and the box), with the
+    squared-norm objective, lambda = 1, beta_k = 0.99^k and x0 = 0.5.
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    x_star = rng.uniform(0.0, 1.0, n)
+    r = A.astype(np.float64) @ x_star
+    row_ptr = np.arange(0, m * n + 1, n, dtype=np.int32)
+    col_idx = np.tile(np.arange(n, dtype=np.int32), m)
+    return Workload(
+        name=f"dense{m}x{n}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr,
+        col_idx=col_idx,
+        val=A.reshape(-1).copy(),
+        lower=(r - 0.05).astype(np.float32)[:, None],
+        upper=(r + 0.05).astype(np.float32)[:, None],
+        box_lo=np.zeros(n, np.float32),
+        box_hi=np.ones(n, np.float32),
+        x0=np.full((n, 1), 0.5, np.float32),
+        lam=1.0,
+        obj=OBJ_SQNORM,
+        gamma=1.0,
+        alpha=0.99,
+        n_red=1,
+        K=K,
+        x_true=x_star.astype(np.float32)[:, None],
+    )
+
+
+# ---------------------------------------------------------------------------
+# Random sparse matrices with skewed row lengths (kernel edge cases)
+# ---------------------------------------------------------------------------
+
+def random_sparse(
+    m: int,
+    n: int,
+    mean_row: float,
+    seed: int,
+    B: int = 1,
+    empty_frac: float = 0.05,
+    long_rows: int = 0,
+    long_len: Optional[int] = None,
+    obj: int = OBJ_SQNORM,
+    K: int = 20,
+    tv_shape: Optional[tuple] = None,
+    margin: float = 0.05,
+) -> Workload:
+    """Random CSR with geometric row lengths, some empty rows and a few long rows.
+
+    Bands surround A x* for a hidden x* ~ U(0,1) with a relative margin, and a
+    fraction of rows is made one-sided (infinite bound) or an equality band.
+    """
+    rng = np.random.default_rng(seed)
+    lens = rng.geometric(1.0 / max(mean_row, 1.0), size=m).astype(np.int64)
+    lens = np.minimum(lens, n)
+    lens[rng.random(m) < empty_frac] = 0
+    if long_rows:
+        L = n if long_len is None else min(long_len, n)
+        idx = rng.choice(m, size=min(long_rows, m), replace=False)
+        lens[idx] = L
+    row_ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(lens, out=row_ptr[1:])
+    cols = np.empty(row_ptr[-1], np.int32)
+    for i in range(m):
+        s, e = row_ptr[i], row_ptr[i + 1]
+        if e > s:
+            c = rng.choice(n, size=e - s, replace=False)
+            if rng.random() < 0.5:
+                c.sort()
+            cols[s:e] = c
+    vals = rng.uniform(-1.0, 1.0, row_ptr[-1]).astype(np.float32)
+    vals[vals == 0] = 0.5
+    x_star = rng.uniform(0.0, 1.0, (n, B))
+    lower = np.empty((m, B))
+    upper = np.empty((m, B))
+    for s in range(B):
+        r = _csr_matvec64(row_ptr, cols, vals, x_star[:, s])
+        scale = np.abs(r) * margin + 0.02
+        lower[:, s] = r - scale
+        upper[:, s] = r + scale
+    kind = rng.integers(0, 5, size=m)
+    lower[kind == 0, :] = -np.inf
+    upper[kind == 1, :] = np.inf
+    eq = kind == 2
+    upper[eq, :] = lower[eq, :] = 0.5 * (lower[eq, :] + upper[eq, :])
+    rows, cols_tv = (tv_shape if tv_shape is not None else (0, 0))
+    if obj == OBJ_TV2D:
+        assert tv_shape is not None and rows * cols_tv == n
+    lin_c = None
+    if obj == OBJ_LINEAR:
+        lin_c = rng.uniform(0.1, 1.0, n).astype(np.float32)
+    return Workload(
+        name=f"rand{m}x{n}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr.astype(np.int32),
+        col_idx=cols,
+        val=vals,
+        lower=lower.astype(np.float32),
+        upper=upper.astype(np.float32),
+        box_lo=np.full(n, -0.25, np.float32),
+        box_hi=np.full(n, 1.25, np.float32),
+        x0=rng.uniform(0.0, 1.0, (n, B)).astype(np.float32),
+        lam=1.0,
+        obj=obj,
+        tv_rows=rows,
+        tv_cols=cols_tv,
+        tv_eps=1e-2 if obj == OBJ_TV2D else 0.0,
+        linear_c=lin_c,
+        gamma=0.5,
+        alpha=0.95,
+        n_red=2,
+        restart_every=7,
+        K=K,
+        x_true=x_star.astype(np.float32),
+    )
+
+
+# ---------------------------------------------------------------------------
+# Exact ray/pixel intersection lengths on a regular grid
+# ---------------------------------------------------------------------------
+
+def trace_rays(p0, p1, nx, ny, xmin, ymin, hx, hy):
+    """Exact lengths of the segments p0->p1 inside each cell of an nx*ny grid.
+
+    Cell (i, j) spans x in [xmin + j hx, xmin + (j+1) hx], y in
+    [ymin + i hy, ymin + (i+1) hy] and has index ``i * nx + j``.  Returns
+    ``(counts[R], cols, lengths)`` with each ray's cells in order along the ray.
+    """
+    p0 = np.asarray(p0, np.float64)
+    p1 = np.asarray(p1, np.float64)
+    R = p0.shape[0]
+    d = p1 - p0
+    L = np.hypot(d[:, 0], d[:, 1])
+    xs = xmin + hx * np.arange(nx + 1)
+    ys = ymin + hy * np.arange(ny + 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tx = (xs[None, :] - p0[:, 0:1]) / d[:, 0:1]
+        ty = (ys[None, :] - p0[:, 1:2]) / d[:, 1:2]
+    t = np.concatenate([tx, ty, np.zeros((R, 1)), np.ones((R, 1))], axis=1)
+    t[~np.isfinite(t)] = np.nan
+    t = np.clip(t, 0.0, 1.0)
+    t.sort(axis=1)  # NaN sort last
+    seg = t[:, 1:] - t[:, :-1]
+    mid = 0.5 * (t[:, 1:] + t[:, :-1])
+    mx = p0[:, 0:1] + mid * d[:, 0:1]
+    my = p0[:, 1:2] + mid * d[:, 1:2]
+    with np.errstate(invalid="ignore"):
+        j = np.floor((mx - xmin) / hx)
+        i = np.floor((my - ymin) / hy)
+    valid = np.isfinite(seg) & (seg > 1e-12) & (j >= 0) & (j < nx) & (i >= 0) & (i < ny)
+    counts = valid.sum(axis=1)
+    cols = (i[valid] * nx + j[valid]).astype(np.int64)
+    lens = (seg * L[:, None])[valid]
+    return counts, cols, lens
+
+
+def _assemble(chunks, m):
+    counts = np.concatenate([c[0] for c in chunks])
+    cols = np.concatenate([c[1] for c in chunks]).astype(np.int32)
+    lens = np.concatenate([c[2] for c in chunks])
+    assert counts.size == m
+    row_ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    assert row_ptr[-1] < 2**31
+    return row_ptr.astype(np.int32), cols, lens
+
+
+# ---------------------------------------------------------------------------
+# Parallel-beam CT
+# ---------------------------------------------------------------------------
+
+def ellipse_phantom(N: int, seed: int, n_ellipses: int = 10) -> np.ndarray:
+    """Piecewise-constant N*N phantom on the unit square, values in [0, 1]."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / N
+    c = -0.5 + (np.arange(N) + 0.5) * h
+    Y, X = np.meshgrid(c, c, indexing="ij")  # Y varies along rows (i), X along cols (j)
+    img = np.zeros((N, N))
+    img[(X / 0.45) ** 2 + (Y / 0.38) ** 2 <= 1.0] = 0.2
+    for _ in range(n_ellipses):
+        rad = 0.35 * np.sqrt(rng.uniform())
+        ang = rng.uniform(0, 2 * np.pi)
+        cx, cy = rad * np.cos(ang), rad * np.sin(ang)
+        a, b = rng.uniform(0.03, 0.25, 2)
+        th = rng.uniform(0, np.pi)
+        v = rng.uniform(0, 1)
+        u = (X - cx) * np.cos(th) + (Y - cy) * np.sin(th)
+        w = -(X - cx) * np.sin(th) + (Y - cy) * np.cos(th)
+        img[(u / a) ** 2 + (w / b) ** 2 <= 1.0] = v
+    return np.clip(img, 0.0, 1.0)
+
+
+def ct_matrix(N: int, n_angles: int, n_det: int):
+    """System matrix of parallel-beam CT on the unit-square field of view.
+
+    Angles are theta_a = a*pi/n_angles, detector d sits at offset
+    (d - (n_det-1)/2) * h with h = 1/N, and entries are exact intersection lengths
+    (field-of-view units, so a full row sums to the chord through the square).
+    Row index is ``a * n_det + d``; pixel (i, j) is column ``i * N + j``.
+    """
+    h = 1.0 / N
+    offs = (np.arange(n_det) - (n_det - 1) / 2.0) * h
+    chunks = []
+    for a in range(n_angles):
+        th = a * np.pi / n_angles
+        nrm = np.array([np.cos(th), np.sin(th)])
+        dirv = np.array([-np.sin(th), np.cos(th)])
+        base = offs[:, None] * nrm[None, :]
+        p0 = base - 1.0 * dirv[None, :]
+        p1 = base + 1.0 * dirv[None, :]
+        chunks.append(trace_rays(p0, p1, N, N, -0.5, -0.5, h, h))
+    return _assemble(chunks, n_angles * n_det)
+
+
+def ct(
+    N: int = 256,
+    n_angles: int = 180,
+    n_det: Optional[int] = None,
+    seed: int = 2,
+    B: int = 1,
+    I0: float = 1e4,
+    nsigma: float = 3.0,
+    K: int = 200,
+    tv_eps: float = 1e-4,
+    variant: str = "default",
+) -> Workload:
+    """Low-dose parallel-beam CT with Poisson noise and +-3 sigma bands.
+
+    counts ~ Poisson(I0 exp(-A x_true)); b = -ln(max(counts,1)/I0);
+    sigma = 1/sqrt(max(counts,1)); bands b -+ nsigma*sigma; box [0, 1];
+    isotropic TV perturbation.  ``variant='paper'`` uses the CT perturbation
+    parameters of the paper's first experiment (gamma 5, alpha 0.99, four
+    reductions, restart every 50).
+    """
+    if n_det is None:
+        n_det = int(np.ceil(np.sqrt(2.0) * N))
+    row_ptr, cols, lens = ct_matrix(N, n_angles, n_det)
+    val = lens.astype(np.float32)
+    m, n = n_angles * n_det, N * N
+    rng = np.random.default_rng(seed + 7919)
+    lower = np.empty((m, B), np.float32)
+    upper = np.empty((m, B), np.float32)
+    xt = np.empty((n, B), np.float32)
+    for s in range(B):
+        x_true = ellipse_phantom(N, seed * 1000 + s).reshape(-1)
+        p = _csr_matvec64(row_ptr, cols, val, x_true)
+        counts = rng.poisson(I0 * np.exp(-p))
+        cc = np.maximum(counts, 1).astype(np.float64)
+        b = -np.log(cc / I0)
+        sig = 1.0 / np.sqrt(cc)
+        lower[:, s] = b - nsigma * sig
+        upper[:, s] = b + nsigma * sig
+        xt[:, s] = x_true
+    params = dict(gamma=1.0, alpha=0.99, n_red=1, restart_every=0)
+    if variant == "paper":
+        params = dict(gamma=5.0, alpha=0.99, n_red=4, restart_every=50)
+    return Workload(
+        name=f"ct{N}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr,
+        col_idx=cols,
+        val=val,
+        lower=lower,
+        upper=upper,
+        box_lo=np.zeros(n, np.float32),
+        box_hi=np.ones(n, np.float32),
+        x0=np.zeros((n, B), np.float32),
+        lam=1.0,
+        obj=OBJ_TV2D,
+        tv_rows=N,
+        tv_cols=N,
+        tv_eps=tv_eps,
+        K=K,
+        x_true=xt,
+        meta=dict(n_angles=n_angles, n_det=n_det, I0=I0),
+        **params,
+    )
+
+
+# ---------------------------------------------------------------------------
+# Straight-ray travel-time tomography
+# ---------------------------------------------------------------------------
+
+def slowness_field(rows: int, cols: int, seed: int) -> np.ndarray:
+    """Layered slowness (1.0 at the top to 0.6 at the bottom) plus four
+    Gaussian anomalies of +-10 %."""
+    rng = np.random.default_rng(seed)
+    depth = (np.arange(rows) + 0.5) / rows
+    layer = np.minimum((depth * 5).astype(int), 4)
+    base = np.array([1.0, 0.9, 0.8, 0.7, 0.6])[layer]
+    s = np.repeat(base[:, None], cols, axis=1)
+    I, J = np.meshgrid(np.arange(rows) + 0.5, np.arange(cols) + 0.5, indexing="ij")
+    bump = np.zeros_like(s)
+    for _ in range(4):
+        ci, cj = rng.uniform(0, rows), rng.uniform(0, cols)
+        sg = rng.uniform(10, 30)
+        amp = rng.choice([-0.1, 0.1])
+        bump += amp * np.exp(-((I - ci) ** 2 + (J - cj) ** 2) / (2 * sg * sg))
+    return s * (1.0 + bump)
+
+
+def seismic_matrix(rows: int, cols: int, n_src: int, n_rec: int):
+    """Straight rays from sources on the top edge to receivers on the bottom
+    edge of a rows*cols grid of unit cells.  Row index is ``src * n_rec + rec``."""
+    xs = (np.arange(n_src) + 0.5) * cols / n_src
+    xr = (np.arange(n_rec) + 0.5) * cols / n_rec
+    chunks = []
+    for a in range(n_src):
+        p0 = np.stack([np.full(n_rec, xs[a]), np.zeros(n_rec)], axis=1)
+        p1 = np.stack([xr, np.full(n_rec, float(rows))], axis=1)
+        chunks.append(trace_rays(p0, p1, cols, rows, 0.0, 0.0, 1.0, 1.0))
+    return _assemble(chunks, n_src * n_rec)
+
+
+def seismic(
+    rows: int = 200,
+    cols: int = 400,
+    n_src: int = 100,
+    n_rec: int = 200,
+    seed: int = 3,
+    B: int = 1,
+    noise: float = 0.01,
+    nsigma: float = 2.0,
+    K: int = 500,
+    variant: str = "default",
+) -> Workload:
+    """Travel-time tomography: t = A s, b = t (1 + noise*xi), bands b -+ 2 sigma
+    with sigma = noise*t, box [0, inf), TV perturbation.  ``variant='paper'``
+    uses the seismic perturbation parameters of the paper (gamma 1, alpha 0.975,
+    four reductions, restart every 50)."""
+    row_ptr, cols_idx, lens = seismic_matrix(rows, cols, n_src, n_rec)
+    val = lens.astype(np.float32)
+    m, n = n_src * n_rec, rows * cols
+    rng = np.random.default_rng(seed + 104729)
+    lower = np.empty((m, B), np.float32)
+    upper = np.empty((m, B), np.float32)
+    xt = np.empty((n, B), np.float32)
+    smax = 0.0
+    for s in range(B):
+        sl = slowness_field(rows, cols, seed * 1000 + s).reshape(-1)
+        smax = max(smax, float(sl.max()))
+        t = _csr_matvec64(row_ptr, cols_idx, val, sl)
+        b = t * (1.0 + noise * rng.standard_normal(m))
+        sig = noise * t
+        lower[:, s] = b - nsigma * sig
+        upper[:, s] = b + nsigma * sig
+        xt[:, s] = sl
+    params = dict(gamma=1.0, alpha=0.99, n_red=1, restart_every=0)
+    if variant == "paper":
+        params = dict(gamma=1.0, alpha=0.975, n_red=4, restart_every=50)
+    return Workload(
+        name=f"seismic{rows}x{cols}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr,
+        col_idx=cols_idx,
+        val=val,
+        lower=lower,
+        upper=upper,
+        box_lo=np.zeros(n, np.float32),
+        box_hi=np.full(n, np.inf, np.float32),
+        x0=np.zeros((n, B), np.float32),
+        lam=1.0,
+        obj=OBJ_TV2D,
+        tv_rows=rows,
+        tv_cols=cols,
+        tv_eps=1e-4 * smax,
+        K=K,
+        x_true=xt,
+        meta=dict(n_src=n_src, n_rec=n_rec),
+        **params,
+    )
+
+
+# ---------------------------------------------------------------------------
+# Radiotherapy dose-influence matrix
+# ---------------------------------------------------------------------------
+
+def rt(
+    grid=(40, 40, 20),
+    n_beams: int = 9,
+    beamlets=(12, 12),
+    spacing: float = 2.4,
+    mu: float = 0.005,
+    rho: float = 2.0,
+    r_cut: float = 6.4,
+    seed: int = 4,
+    infeasible: bool = True,
+    K: int = 300,
+    variant: str = "default",
+) -> Workload:
+    """Synthetic dose-influence matrix and dose bands for fluence planning.
+
+    Voxels of an X*Y*Z grid (unit spacing) are rows; beamlets of ``n_beams``
+    coplanar beams (equal angular steps around the z axis) on a
+    ``beamlets[0] x beamlets[1]`` grid of the given spacing are columns.
+    a_ij = exp(-mu * depth) * exp(-r / rho) for voxels within lateral distance
+    ``r_cut`` of the beamlet axis.  The matrix is scaled so that x = 1 gives a
+    mean target dose of 1.  Bands: target [0.95, 1.07], organ-at-risk voxels
+    (-inf, 0.5], other voxels (-inf, 1.07].  With ``infeasible`` every voxel of an
+    OAR/target overlap shell is duplicated as a second row with band
+    (-inf, 0.3], which cannot hold together with the target's lower bound.
+    Objective: summed dose over all voxels (a linear function of x with
+    c = A^T 1).  Box x >= 0.
+    """
+    rng = np.random.default_rng(seed)
+    X, Y, Z = grid
+    nv = X * Y * Z
+    ci = (np.arange(X) + 0.5) - X / 2.0
+    cj = (np.arange(Y) + 0.5) - Y / 2.0
+    ck = (np.arange(Z) + 0.5) - Z / 2.0
+    PX, PY, PZ = np.meshgrid(ci, cj, ck, indexing="ij")
+    PX, PY, PZ = PX.reshape(-1), PY.reshape(-1), PZ.reshape(-1)
+    nbu, nbw = beamlets
+    n = n_beams * nbu * nbw
+    half = 0.5 * max(X, Y)
+    # candidate beamlet offsets around the nearest beamlet
+    reach = int(np.ceil(r_cut / spacing)) + 1
+    offs = [(du, dw) for du in range(-reach, reach + 1) for dw in range(-reach, reach + 1)]
+    per_row_cols = []
+    per_row_vals = []
+    for b in range(n_beams):
+        th = 2 * np.pi * b / n_beams
+        e_d = np.array([np.cos(th), np.sin(th)])  # beam travels along +e_d
+        e_u = np.array([-np.sin(th), np.cos(th)])
+        depth = PX * e_d[0] + PY * e_d[1] + half
+        u = PX * e_u[0] + PY * e_u[1]
+        w = PZ
+        fu = u / spacing + (nbu - 1) / 2.0
+        fw = w / spacing + (nbw - 1) / 2.0
+        bu0 = np.rint(fu).astype(np.int64)
+        bw0 = np.rint(fw).astype(np.int64)
+        att = np.exp(-mu * np.maximum(depth, 0.0))
+        for du, dw in offs:
+            bu = bu0 + du
+            bw = bw0 + dw
+            r = spacing * np.hypot(fu - bu, fw - bw)
+            ok = (bu >= 0) & (bu < nbu) & (bw >= 0) & (bw < nbw) & (r <= r_cut)
+            col = np.where(ok, b * nbu * nbw + bu * nbw + bw, -1)
+            v = np.where(ok, att * np.exp(-r / rho), 0.0)
+            per_row_cols.append(col)
+            per_row_vals.append(v)
+    C = np.stack(per_row_cols, axis=1)  # [nv, n_beams*len(offs)]
+    V = np.stack(per_row_vals, axis=1)
+    ok = C >= 0
+    # structures
+    rr = np.sqrt(PX**2 + PY**2 + PZ**2)
+    R_t = 0.25 * min(X, Y, 2 * Z)
+    target = rr <= R_t
+    oar_c = np.array([R_t * 1.1, 0.0])
+    oar = (np.hypot(PX - oar_c[0], PY - oar_c[1]) <= 0.45 * R_t) & (np.abs(PZ) <= 0.8 * R_t)
+    overlap = target & oar
+    # scale A so that x = 1 gives a mean target dose of 1
+    d1 = (V * ok).sum(axis=1)
+    scale = 1.0 / max(d1[target].mean(), 1e-30)
+    V = V * scale
+    counts = ok.sum(axis=1)
+    up = np.where(oar, 0.5, 1.07)
+    lo = np.where(target, 0.95, -np.inf)
+    up = np.where(target & ~oar, 1.07, up)
+    row_ptr = np.zeros(nv + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    cols = C[ok].astype(np.int32)
+    vals = V[ok].astype(np.float32)
+    lower = lo.astype(np.float64)
+    upper = up.astype(np.float64)
+    meta = dict(n_target=int(target.sum()), n_oar=int(oar.sum()), n_overlap=int(overlap.sum()))
+    if infeasible and overlap.any():
+        dup = np.nonzero(overlap)[0]
+        lower[dup] = 0.95
+        upper[dup] = 1.07
+        dcounts = counts[dup]
+        drp = np.zeros(dup.size + 1, np.int64)
+        np.cumsum(dcounts, out=drp[1:])
+        dcols = np.concatenate([C[i, ok[i]] for i in dup]).astype(np.int32)
+        dvals = np.concatenate([V[i, ok[i]] for i in dup]).astype(np.float32)
+        row_ptr = np.concatenate([row_ptr, row_ptr[-1] + drp[1:]])
+        cols = np.concatenate([cols, dcols])
+        vals = np.concatenate([vals, dvals])
+        lower = np.concatenate([lower, np.full(dup.size, -np.inf)])
+        upper = np.concatenate([upper, np.full(dup.size, 0.3)])
+    m = row_ptr.size - 1
+    # summed body dose: c = A^T 1 over the voxel rows (duplicates excluded)
+    c = np.zeros(n)
+    np.add.at(c, C[ok], V[ok].astype(np.float32).astype(np.float64))
+    params = dict(gamma=1.0, alpha=0.99, n_red=1, restart_every=0)
+    if variant == "paper":
+        params = dict(gamma=1.0, alpha=0.99, n_red=1, restart_every=500)
+    assert row_ptr[-1] < 2**31
+    return Workload(
+        name=f"rt{X}x{Y}x{Z}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr.astype(np.int32),
+        col_idx=cols,
+        val=vals,
+        lower=lower.astype(np.float32)[:, None],
+        upper=upper.astype(np.float32)[:, None],
+        box_lo=np.zeros(n, np.float32),
+        box_hi=np.full(n, np.inf, np.float32),
+        x0=np.zeros((n, 1), np.float32),
+        lam=1.0,
+        obj=OBJ_LINEAR,
+        linear_c=c.astype(np.float32),
+        K=K,
+        meta=meta,
+        **params,
+    )
