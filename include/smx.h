@@ -1,0 +1,224 @@
+/*
+ * smx: superiorized simultaneous band+box projection on AMD MI355X (gfx950).
+ *
+ * C ABI of the HIP library libsmx.so.  Plain pointers and sizes only.
+ *
+ * Problem (paper, Section 2.1.1 and Section 2.3.3): find x in R^n with
+ *     lower_i <= <a_i, x> <= upper_i   (i = 1..m, the rows of a sparse A)
+ *     box_lo_j <= x_j <= box_hi_j
+ * while reducing a secondary objective f (superiorization, Section 2.1.2).
+ *
+ * One feasibility step (the basic algorithm T) is the relaxed simultaneous
+ * projection (eq. RelaxedProjection applied to the weighted combination of
+ * the single-band projections of Section 2.1.1, with the weights of eq.
+ * WeightedProximity), followed by the box projection (Section 2.3.3):
+ *     r = A z,  t_i = clip(r_i, lower_i, upper_i) - r_i,
+ *     x = clip( z + lambda * A^T (D t), box_lo, box_hi ),  D_i = w_i / ||a_i||^2.
+ * One outer iteration of Algorithm 1 first perturbs x^k to z^k along
+ * v = -grad f / ||grad f|| with power-law steps beta = gamma * alpha^ell, accepting
+ * a trial only if it does not increase f, then applies T.
+ *
+ * Several right-hand sides ("slices", B of them) may share one A.  Every
+ * per-slice vector is stored slice-interleaved: element j of slice s sits at
+ * index j*B + s.
+ *
+ * Conventions:
+ *   - Every call returns an int status (SMX_OK or a negative SMX_E* code) and
+ *     never throws, aborts or exits; smx_last_error() describes the last failure
+ *     on the calling thread.
+ *   - "stream" arguments are hipStream_t values passed as void* (NULL means the
+ *     null stream).  Work is enqueued asynchronously on the problem's stream.
+ *   - Device pointers refer to memory on the device that is current when the
+ *     object is created; an object must be used with that device current.
+ *   - Distinct handles may be used from distinct threads concurrently; one
+ *     handle must not be used by two threads at once.
+ */
+#ifndef SMX_H
+#define SMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMX_VERSION_MAJOR 0
+#define SMX_VERSION_MINOR 1
+
+/* status codes */
+#define SMX_OK 0
+#define SMX_EINVAL (-1)   /* an argument is invalid; nothing was changed */
+#define SMX_ENOMEM (-2)   /* device or host allocation failed, or a budget is exceeded */
+#define SMX_EDEVICE (-3)  /* a HIP runtime call failed */
+#define SMX_ESTATE (-4)   /* the call is not valid in the object's current state */
+#define SMX_ENUMERIC (-5) /* a non-finite value was produced on the device */
+
+/* storage of A's values (the indices are always exact) */
+#define SMX_STORE_F32 0  /* float32 values */
+#define SMX_STORE_BF16 1 /* bfloat16, round-to-nearest-even from float32 */
+#define SMX_STORE_F16 2  /* binary16 after one global power-of-two scale */
+
+/* secondary objectives f */
+#define SMX_OBJ_NONE 0   /* feasibility only */
+#define SMX_OBJ_SQNORM 1 /* f = ||x||^2, the L2 perturbation (Section 2.3.1) */
+#define SMX_OBJ_TV2D 2   /* smoothed total variation of an R x C image (Section 2.3.1) */
+#define SMX_OBJ_LINEAR 3 /* f = c^T x, e.g. summed dose (Section 2.3.3) */
+
+/* smx_run flags */
+#define SMX_RUN_PERTURB 1u /* run the perturbation phase of Algorithm 1 */
+#define SMX_RUN_GRAPH 2u   /* replay captured HIP graphs of several iterations */
+
+typedef struct smx_operator smx_operator;
+typedef struct smx_problem smx_problem;
+
+/* A sparse matrix in CSR form.  row_ptr[0] = 0, row_ptr non-decreasing,
+ * row_ptr[m] = nnz, 0 <= col_idx < n, values finite.  Column indices within a
+ * row need not be sorted; repeated (row, col) pairs are summed. */
+typedef struct {
+    int64_t m, n, nnz;
+    const int32_t *row_ptr; /* m+1 */
+    const int32_t *col_idx; /* nnz */
+    const float *val;       /* nnz */
+    int32_t on_device;      /* 0: host pointers, 1: device pointers */
+} smx_csr;
+
+/* Everything about one problem except A.  All arrays are copied at creation. */
+typedef struct {
+    int32_t B;               /* slices sharing A: a power of two, 1..32 */
+    const float *lower;      /* m*B, slice-interleaved; -INFINITY allowed */
+    const float *upper;      /* m*B; +INFINITY allowed; lower <= upper */
+    const double *weights;   /* m, > 0 (normalised to sum 1 here), or NULL for 1/m */
+    const float *box_lo;     /* n, or NULL for -INFINITY */
+    const float *box_hi;     /* n, or NULL for +INFINITY; box_lo <= box_hi */
+    double lambda;           /* relaxation parameter, 0 < lambda <= 2 */
+    int32_t obj_kind;        /* SMX_OBJ_* */
+    int32_t tv_rows, tv_cols; /* SMX_OBJ_TV2D: image shape, rows*cols = n,
+                                pixel (i,j) is unknown i*tv_cols + j */
+    double tv_eps;           /* SMX_OBJ_TV2D smoothing, >= 0 */
+    const float *linear_c;   /* SMX_OBJ_LINEAR: c, n entries, nonzero */
+    double gamma;            /* step kernel, > 0 */
+    double alpha;            /* step ratio, 0 < alpha < 1 */
+    int32_t n_red;           /* reduction steps per perturbation phase, >= 1 */
+    int32_t restart_every;   /* restart ell every this many iterations; 0: never */
+    int32_t max_trials;      /* trial cap per reduction step, 1..1024 */
+    int32_t refine_iters;    /* low-precision operators only: the last iterations
+                                of every smx_run use the float32 operator;
+                                -1 means ceil(K/20) */
+    int32_t history_cap;     /* per-iteration records kept (0: none) */
+    int32_t on_device;       /* 0: the arrays above are host pointers, 1: device */
+} smx_problem_desc;
+
+/* Per-slice iteration state, as checkpointed by smx_get_state. */
+typedef struct {
+    int64_t k;        /* outer iterations completed */
+    int64_t ell;      /* exponent of the next power-law trial step */
+    int64_t restarts; /* restarts so far */
+    int64_t trials;   /* trial points evaluated, total */
+    int64_t accepts;  /* trial points accepted, total */
+    int64_t cap_hits; /* reduction steps that reached max_trials */
+} smx_slice_state;
+
+/* Library version.  Both pointers must be non-NULL. */
+int smx_version(int *major, int *minor);
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next smx_* call on this thread. */
+const char *smx_last_error(void);
+
+/*
+ * Create an operator from A: deep-copies the CSR (host or device input) into
+ * library-owned device buffers laid out for the kernels (row-aligned CSR and a
+ * column-major copy for A^T), computes the float64 row norms ||a_i||^2 from the
+ * stored values, and, for SMX_STORE_BF16/F16, a reduced-precision copy.  With
+ * keep_f32 != 0 a reduced-precision operator also keeps the float32 copy used
+ * by refinement iterations.  The caller may free its buffers on return.
+ * Errors: SMX_EINVAL for m or n < 1, nnz != row_ptr[m], a decreasing row_ptr,
+ * a column index outside [0,n), a non-finite value, or sizes beyond 2^31-1
+ * entries; SMX_ENOMEM when device memory runs out (nothing is leaked).
+ */
+int smx_operator_create(const smx_csr *A, int32_t value_storage, int32_t keep_f32, void *stream,
+                        smx_operator **out);
+
+/* Release an operator once every problem created from it is destroyed
+ * (operators are reference counted).  NULL is accepted. */
+int smx_operator_destroy(smx_operator *op);
+
+/* Device bytes the operator would take for A of this shape and storage,
+ * without allocating anything. */
+int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32,
+                           size_t *bytes);
+
+/*
+ * Create a problem on an operator.  Validates and copies the descriptor's
+ * arrays; sets x to 0 for every slice and the iteration state to k = ell =
+ * restarts = 0.  Errors (SMX_EINVAL): B not a power of two in 1..32, any
+ * lower > upper or NaN bound, a weight <= 0 or non-finite, box_lo > box_hi,
+ * lambda outside (0,2], gamma <= 0, alpha outside (0,1), n_red < 1,
+ * max_trials outside 1..1024, TV with rows*cols != n, LINEAR with a NULL c.
+ */
+int smx_problem_create(smx_operator *op, const smx_problem_desc *desc, void *stream, smx_problem **out);
+
+/* Destroy a problem (waits for its stream).  NULL is accepted. */
+int smx_problem_destroy(smx_problem *p);
+
+/* Convenience: operator plus problem in one call; the problem owns the
+ * operator's only reference. */
+int smx_create(const smx_csr *A, int32_t value_storage, const smx_problem_desc *desc, void *stream,
+               smx_problem **out);
+
+/* Change the stream later work of this problem is enqueued on. */
+int smx_set_stream(smx_problem *p, void *stream);
+
+/* Copy the iterate in (n*B floats, slice-interleaved; host or device).  Also
+ * resets no state: use smx_set_state for that. */
+int smx_set_x(smx_problem *p, const float *x, int32_t on_device);
+
+/* Copy the iterate out (n*B floats).  Synchronises for host output. */
+int smx_get_x(smx_problem *p, float *out, int32_t on_device);
+
+/*
+ * Enqueue K outer iterations (Algorithm 1 with SMX_RUN_PERTURB and an
+ * objective, else K feasibility steps).  With a reduced-precision operator the
+ * last refine_iters of the K iterations use the float32 operator.
+ * SMX_RUN_GRAPH replays captured graphs of several iterations.
+ * Asynchronous; returns SMX_EINVAL for K < 0.
+ */
+int smx_run(smx_problem *p, int32_t K, uint32_t flags);
+
+/* Wait for the problem's stream.  Returns SMX_ENUMERIC if a non-finite
+ * proximity or objective was produced since the last check. */
+int smx_sync(smx_problem *p);
+
+/* Proximity 1/2 sum_i w_i ||P_i(x) - x||^2 (eq. WeightedProximity) and the
+ * objective f at the current x, one double per slice each (either may be
+ * NULL).  Synchronises. */
+int smx_query(smx_problem *p, double *proximity, double *objective);
+
+/* Per-iteration records of the first min(k, history_cap) iterations, each
+ * [iteration][slice] (row-major, B per iteration): proximity at the point the
+ * feasibility step acted on, objective at x^k and after the perturbation phase
+ * (NaN when no phase ran), trials and accepted trials.  Any pointer may be
+ * NULL.  *n_out receives the number of iterations written (<= cap). */
+int smx_get_history(smx_problem *p, double *prox, double *f_start, double *f_end, int32_t *trials,
+                    int32_t *accepts, int32_t cap, int32_t *n_out);
+
+/* Checkpoint: the per-slice states (B entries) and the iterate (n*B floats,
+ * host).  smx_set_state restores both exactly. */
+int smx_get_state(smx_problem *p, smx_slice_state *states, float *x);
+int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x);
+
+/* Shape of the problem. */
+int smx_problem_dims(const smx_problem *p, int64_t *m, int64_t *n, int64_t *nnz, int32_t *B);
+
+/* Mean device time (milliseconds) per launch of the two passes recorded by
+ * the last smx_run made with SMX_RUN_GRAPH clear and timing enabled through
+ * smx_set_timing; zero launches give 0. */
+int smx_set_timing(smx_problem *p, int32_t enable);
+int smx_get_timing(smx_problem *p, double *pass1_ms, double *pass2_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMX_H */

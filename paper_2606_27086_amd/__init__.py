@@ -1,0 +1,356 @@
+"""Python binding of libsmx, the MI355X (gfx950) HIP library for the
+superiorized simultaneous band+box projection method.
+
+This module only marshals arguments into the C ABI of ``include/smx.h``:
+torch supplies device memory and the stream, every step of the method runs in
+the library's HIP kernels.  There is no fallback: if ``libsmx.so`` is missing or
+cannot be loaded, importing the binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmx.so")
+
+STORE = {"f32": 0, "bf16": 1, "f16": 2}
+OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+RUN_PERTURB, RUN_GRAPH = 1, 2
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
+_CODE_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENUMERIC: "ENUMERIC"}
+
+# entry points declared in include/smx.h
+EXPORTS = [
+    "smx_version",
+    "smx_last_error",
+    "smx_operator_create",
+    "smx_operator_destroy",
+    "smx_operator_footprint",
+    "smx_problem_create",
+    "smx_problem_destroy",
+    "smx_create",
+    "smx_set_stream",
+    "smx_set_x",
+    "smx_get_x",
+    "smx_run",
+    "smx_sync",
+    "smx_query",
+    "smx_get_history",
+    "smx_get_state",
+    "smx_set_state",
+    "smx_problem_dims",
+    "smx_set_timing",
+    "smx_get_timing",
+]
+
+
+class SmxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODE_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Csr(C.Structure):
+    _fields_ = [
+        ("m", C.c_int64),
+        ("n", C.c_int64),
+        ("nnz", C.c_int64),
+        ("row_ptr", C.c_void_p),
+        ("col_idx", C.c_void_p),
+        ("val", C.c_void_p),
+        ("on_device", C.c_int32),
+    ]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [
+        ("B", C.c_int32),
+        ("lower", C.c_void_p),
+        ("upper", C.c_void_p),
+        ("weights", C.c_void_p),
+        ("box_lo", C.c_void_p),
+        ("box_hi", C.c_void_p),
+        ("lam", C.c_double),
+        ("obj_kind", C.c_int32),
+        ("tv_rows", C.c_int32),
+        ("tv_cols", C.c_int32),
+        ("tv_eps", C.c_double),
+        ("linear_c", C.c_void_p),
+        ("gamma", C.c_double),
+        ("alpha", C.c_double),
+        ("n_red", C.c_int32),
+        ("restart_every", C.c_int32),
+        ("max_trials", C.c_int32),
+        ("refine_iters", C.c_int32),
+        ("history_cap", C.c_int32),
+        ("on_device", C.c_int32),
+    ]
+
+
+class SliceStateC(C.Structure):
+    _fields_ = [
+        ("k", C.c_int64),
+        ("ell", C.c_int64),
+        ("restarts", C.c_int64),
+        ("trials", C.c_int64),
+        ("accepts", C.c_int64),
+        ("cap_hits", C.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libsmx.so; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsmx.so not found at {LIB_PATH}: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.smx_version.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.smx_last_error.restype = C.c_char_p
+    L.smx_operator_create.argtypes = [C.POINTER(Csr), i32, i32, vp, C.POINTER(vp)]
+    L.smx_operator_destroy.argtypes = [vp]
+    L.smx_operator_footprint.argtypes = [i64, i64, i64, i32, i32, C.POINTER(C.c_size_t)]
+    L.smx_problem_create.argtypes = [vp, C.POINTER(ProblemDesc), vp, C.POINTER(vp)]
+    L.smx_problem_destroy.argtypes = [vp]
+    L.smx_create.argtypes = [C.POINTER(Csr), i32, C.POINTER(ProblemDesc), vp, C.POINTER(vp)]
+    L.smx_set_stream.argtypes = [vp, vp]
+    L.smx_set_x.argtypes = [vp, vp, i32]
+    L.smx_get_x.argtypes = [vp, vp, i32]
+    L.smx_run.argtypes = [vp, i32, C.c_uint32]
+    L.smx_sync.argtypes = [vp]
+    L.smx_query.argtypes = [vp, vp, vp]
+    L.smx_get_history.argtypes = [vp, vp, vp, vp, vp, vp, i32, C.POINTER(i32)]
+    L.smx_get_state.argtypes = [vp, vp, vp]
+    L.smx_set_state.argtypes = [vp, vp, vp]
+    L.smx_problem_dims.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
+    L.smx_set_timing.argtypes = [vp, i32]
+    L.smx_get_timing.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i64)]
+    for name in EXPORTS:
+        if name != "smx_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        raise SmxError(rc, lib().smx_last_error().decode(errors="replace"))
+
+
+def version() -> tuple:
+    a, b = C.c_int(), C.c_int()
+    check(lib().smx_version(C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _dev(a, dtype, device):
+    """A contiguous device tensor holding `a` (numpy array or tensor)."""
+    import torch
+
+    if a is None:
+        return None
+    t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Operator:
+    """A on the device: row-aligned CSR, column-major copy, row norms and an
+    optional reduced-precision value copy (``storage`` in f32 / bf16 / f16)."""
+
+    def __init__(self, m, n, row_ptr, col_idx, val, storage: str = "f32", keep_f32: bool = True,
+                 device="cuda", stream=None):
+        import torch
+
+        self.m, self.n = int(m), int(n)
+        self.storage = storage
+        rp = _dev(row_ptr, torch.int32, device)
+        ci = _dev(col_idx, torch.int32, device)
+        va = _dev(val, torch.float32, device)
+        self.nnz = int(ci.numel())
+        csr = Csr(self.m, self.n, self.nnz, _ptr(rp), _ptr(ci), _ptr(va), 1)
+        h = C.c_void_p()
+        check(lib().smx_operator_create(C.byref(csr), STORE[storage], 1 if keep_f32 else 0,
+                                        _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            check(lib().smx_operator_destroy(self.handle))
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def footprint(m, n, nnz, storage="f32", keep_f32=True) -> int:
+    b = C.c_size_t()
+    check(lib().smx_operator_footprint(int(m), int(n), int(nnz), STORE[storage], 1 if keep_f32 else 0, C.byref(b)))
+    return int(b.value)
+
+
+class Problem:
+    """Band+box problem with B slices on an :class:`Operator`."""
+
+    def __init__(self, op: Operator, lower, upper, box_lo=None, box_hi=None, weights=None, lam=1.0,
+                 obj=OBJ_NONE, tv_rows=0, tv_cols=0, tv_eps=0.0, linear_c=None, gamma=1.0, alpha=0.99,
+                 n_red=1, restart_every=0, max_trials=100, refine_iters=-1, history_cap=0, B=None,
+                 device="cuda", stream=None):
+        import torch
+
+        self.op = op
+        self.device = device
+        lower = np.asarray(lower, np.float32) if not isinstance(lower, torch.Tensor) else lower
+        if B is None:
+            B = 1 if lower.ndim == 1 else int(lower.shape[1])
+        self.B = int(B)
+        self.m, self.n = op.m, op.n
+        t_lo = _dev(lower, torch.float32, device).reshape(-1)
+        t_up = _dev(upper, torch.float32, device).reshape(-1)
+        t_w = _dev(weights, torch.float64, device)
+        t_blo = _dev(box_lo, torch.float32, device)
+        t_bhi = _dev(box_hi, torch.float32, device)
+        t_c = _dev(linear_c, torch.float32, device)
+        d = ProblemDesc(
+            B=self.B, lower=_ptr(t_lo), upper=_ptr(t_up), weights=_ptr(t_w), box_lo=_ptr(t_blo),
+            box_hi=_ptr(t_bhi), lam=float(lam), obj_kind=int(obj), tv_rows=int(tv_rows), tv_cols=int(tv_cols),
+            tv_eps=float(tv_eps), linear_c=_ptr(t_c), gamma=float(gamma), alpha=float(alpha), n_red=int(n_red),
+            restart_every=int(restart_every), max_trials=int(max_trials), refine_iters=int(refine_iters),
+            history_cap=int(history_cap), on_device=1,
+        )
+        self.history_cap = int(history_cap)
+        self.obj = int(obj)
+        h = C.c_void_p()
+        check(lib().smx_problem_create(op.handle, C.byref(d), _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+
+    # -- iterate -----------------------------------------------------------
+    def set_x(self, x):
+        import torch
+
+        t = _dev(x, torch.float32, self.device).reshape(-1)
+        assert t.numel() == self.n * self.B
+        check(lib().smx_set_x(self.handle, _ptr(t), 1))
+        torch.cuda.current_stream().synchronize()
+
+    def get_x(self):
+        """Iterate as a device tensor of shape [n, B]."""
+        import torch
+
+        out = torch.empty(self.n * self.B, dtype=torch.float32, device=self.device)
+        check(lib().smx_get_x(self.handle, _ptr(out), 1))
+        return out.reshape(self.n, self.B)
+
+    # -- iteration ---------------------------------------------------------
+    def run(self, K: int, perturb: bool = True, graph: bool = False):
+        flags = (RUN_PERTURB if perturb else 0) | (RUN_GRAPH if graph else 0)
+        check(lib().smx_run(self.handle, int(K), flags))
+
+    def sync(self):
+        check(lib().smx_sync(self.handle))
+
+    def set_stream(self, stream):
+        check(lib().smx_set_stream(self.handle, _stream_ptr(stream)))
+
+    def query(self):
+        """(proximity[B], objective[B]) at the current iterate, float64."""
+        p = np.zeros(self.B)
+        f = np.zeros(self.B)
+        check(lib().smx_query(self.handle, p.ctypes.data, f.ctypes.data))
+        return p, f
+
+    def history(self):
+        cap = max(self.history_cap, 0)
+        shape = (cap, self.B)
+        prox = np.zeros(shape)
+        fs = np.zeros(shape)
+        fe = np.zeros(shape)
+        tr = np.zeros(shape, np.int32)
+        ac = np.zeros(shape, np.int32)
+        n = C.c_int32()
+        check(lib().smx_get_history(self.handle, prox.ctypes.data, fs.ctypes.data, fe.ctypes.data, tr.ctypes.data,
+                                    ac.ctypes.data, cap, C.byref(n)))
+        k = n.value
+        return dict(prox=prox[:k], f_start=fs[:k], f_end=fe[:k], trials=tr[:k], accepts=ac[:k])
+
+    def get_state(self):
+        st = (SliceStateC * self.B)()
+        x = np.zeros(self.n * self.B, np.float32)
+        check(lib().smx_get_state(self.handle, C.cast(st, C.c_void_p), x.ctypes.data))
+        return [s.as_dict() for s in st], x.reshape(self.n, self.B)
+
+    def set_state(self, states, x):
+        st = (SliceStateC * self.B)()
+        for i, s in enumerate(states):
+            for k, v in s.items():
+                setattr(st[i], k, int(v))
+        xx = np.ascontiguousarray(np.asarray(x, np.float32).reshape(-1))
+        check(lib().smx_set_state(self.handle, C.cast(st, C.c_void_p), xx.ctypes.data))
+
+    def reset(self, x0):
+        """Iteration state back to k = ell = restarts = 0 and the iterate to x0."""
+        zero = dict(k=0, ell=0, restarts=0, trials=0, accepts=0, cap_hits=0)
+        self.set_state([zero] * self.B, np.asarray(x0, np.float32).reshape(self.n, self.B))
+
+    def set_timing(self, on: bool):
+        check(lib().smx_set_timing(self.handle, 1 if on else 0))
+
+    def timing(self):
+        a, b, n = C.c_double(), C.c_double(), C.c_int64()
+        check(lib().smx_get_timing(self.handle, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            check(lib().smx_problem_destroy(self.handle))
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device="cuda", op: Operator = None,
+                          refine_iters: int = -1, **overrides) -> Problem:
+    """Build operator + problem for a :class:`workloads.Workload` (all slices)."""
+    if op is None:
+        op = Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage=storage, device=device)
+    kw = dict(
+        lower=w.lower, upper=w.upper, box_lo=w.box_lo, box_hi=w.box_hi, weights=w.weights, lam=w.lam, obj=w.obj,
+        tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
+        n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
+        refine_iters=refine_iters, B=w.B,
+    )
+    kw.update(overrides)
+    p = Problem(op, device=device, **kw)
+    p.set_x(w.x0)
+    return p

@@ -1,0 +1,914 @@
+// Host runtime and C ABI of libsmx (declared in include/smx.h).
+//
+// Owns device memory for operators (row-aligned CSR of A, row-aligned CSR of
+// A^T, float64 row norms, reduced-precision value copies) and problems (bands,
+// box, weights, iterate, per-slice state, reduction scratch, history), builds
+// the per-iteration launch sequence, and captures it into HIP graphs.
+#include "../../include/smx.h"
+#include "smx_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace smx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+inline void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw HipError{e, what};
+}
+
+int from_hip(const HipError &h)
+{
+    if (h.e == hipErrorOutOfMemory) return fail(SMX_ENOMEM, "%s: out of device memory", h.what);
+    return fail(SMX_EDEVICE, "%s: %s", h.what, hipGetErrorString(h.e));
+}
+
+// Owning device allocation.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t b, const char *what)
+    {
+        release();
+        if (b == 0) b = 256;
+        hip_check(hipMalloc(&p, b), what);
+        bytes = b;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// One row-aligned layout on the host before upload.
+struct HostLayout {
+    std::vector<int32_t> ptr;
+    std::vector<int32_t> idx;
+    std::vector<float> val;
+    int64_t slots = 0;
+};
+
+// Pads every row to a multiple of kRowAlign entries (value 0, index of the
+// row's last entry or 0).  Returns false if the padded size reaches 2^31.
+bool pad_rows(int64_t rows, const int64_t *rp, const int32_t *idx, const float *val, HostLayout &L)
+{
+    L.ptr.resize(rows + 1);
+    int64_t slots = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        L.ptr[r] = (int32_t)slots;
+        slots += round_up(rp[r + 1] - rp[r], kRowAlign);
+        if (slots >= (int64_t(1) << 31)) return false;
+    }
+    L.ptr[rows] = (int32_t)slots;
+    L.slots = slots;
+    L.idx.assign(slots, 0);
+    L.val.assign(slots, 0.f);
+    for (int64_t r = 0; r < rows; ++r) {
+        int64_t s = rp[r], e = rp[r + 1], o = L.ptr[r];
+        std::memcpy(&L.idx[o], idx + s, sizeof(int32_t) * (e - s));
+        std::memcpy(&L.val[o], val + s, sizeof(float) * (e - s));
+        const int32_t fill = (e > s) ? idx[e - 1] : 0;
+        for (int64_t p = o + (e - s); p < L.ptr[r + 1]; ++p) L.idx[p] = fill;
+    }
+    return true;
+}
+
+struct DevLayout {
+    int64_t rows = 0, slots = 0;
+    DBuf ptr, idx, val32, val16;
+    float f16_scale = 1.f;
+    SpView view(int vk) const
+    {
+        SpView v;
+        v.ptr = ptr.as<int32_t>();
+        v.idx = idx.as<int32_t>();
+        v.val = (vk == VK_F32) ? val32.p : val16.p;
+        v.rows = rows;
+        v.vscale_inv = (vk == VK_F16) ? 1.f / f16_scale : 1.f;
+        return v;
+    }
+};
+
+size_t layout_bytes(int64_t rows, int64_t slots, bool f32, bool lp)
+{
+    return size_t(rows + 1) * 4 + size_t(slots) * 4 + (f32 ? size_t(slots) * 4 : 0) + (lp ? size_t(slots) * 2 : 0);
+}
+
+float f16_scale_for(const std::vector<float> &v)
+{
+    float amax = 0.f;
+    for (float a : v) amax = std::max(amax, std::fabs(a));
+    if (!(amax > 0.f)) return 1.f;
+    int e;
+    const double mant = std::frexp((double)amax, &e);
+    const int ce = (mant == 0.5) ? e - 1 : e; // ceil(log2(amax))
+    return (float)std::ldexp(1.0, 14 - ce);
+}
+
+} // namespace
+
+struct smx_operator {
+    int device = 0;
+    int64_t m = 0, n = 0, nnz = 0;
+    int storage = SMX_STORE_F32;
+    bool has_f32 = true;
+    DevLayout csr, csc;
+    DBuf q32, q16; // float64 row norms of the float32 and the reduced-precision operator
+    std::atomic<int> refs{1};
+    size_t bytes = 0;
+    int lp_kind() const { return storage == SMX_STORE_BF16 ? VK_BF16 : (storage == SMX_STORE_F16 ? VK_F16 : VK_F32); }
+};
+
+struct smx_problem {
+    smx_operator *op = nullptr;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int B = 1;
+    int64_t m = 0, n = 0;
+    float lambda = 1.f;
+    int refine_iters = -1;
+    PertParams pp{};
+    DBuf x, g, c, lower, upper, box_lo, box_hi, lin_c, w, D32, D16, st, qout;
+    DBuf part_pass, part_query, part_phase, part_trial[2]; // per-workgroup partial sums of each kernel kind
+    int cur = 0; // which of the two state buffers (st holds 2*B states) is current
+    SliceState *state(int which) const { return st.as<SliceState>() + size_t(which) * B; }
+    DBuf h_prox, h_fs, h_fe, h_tr, h_ac;
+    Hist hist{};
+    int hist_cap = 0;
+    PassCfg cfg1[3]{}, cfg2[3]{};
+    // captured graphs keyed by (value kind, perturb, iterations)
+    std::map<long long, hipGraphExec_t> graphs;
+    hipStream_t capture_stream = nullptr; // private stream graphs are captured on
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double t1_ms = 0, t2_ms = 0;
+    int64_t t_launches = 0;
+    ~smx_problem()
+    {
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    }
+};
+
+namespace {
+
+PassCfg pick_cfg(int64_t rows, int64_t slots, int vk)
+{
+    PassCfg c;
+    c.vec = (vk == VK_F32) ? 4 : 8;
+    const double mean = rows > 0 ? double(slots) / double(rows) : 0.0;
+    int lpr = 4;
+    while (lpr < 64 && lpr * c.vec * 2 < mean) lpr *= 2;
+    c.lpr = lpr;
+    const int64_t rpb = kBlock / lpr;
+    int64_t grid = (rows + rpb - 1) / rpb;
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, 4096));
+    c.grid = (int)grid;
+    return c;
+}
+
+SpView view_for(const smx_operator *op, bool transposed, int vk)
+{
+    return transposed ? op->csc.view(vk) : op->csr.view(vk);
+}
+
+int validate_csr_host(const smx_csr *A, const int32_t *rp, const int32_t *ci, const float *v)
+{
+    if (rp[0] != 0) return fail(SMX_EINVAL, "row_ptr[0] must be 0 (got %d)", rp[0]);
+    for (int64_t i = 0; i < A->m; ++i)
+        if (rp[i + 1] < rp[i]) return fail(SMX_EINVAL, "row_ptr decreases at row %lld", (long long)i);
+    if ((int64_t)rp[A->m] != A->nnz)
+        return fail(SMX_EINVAL, "row_ptr[m] = %d differs from nnz = %lld", rp[A->m], (long long)A->nnz);
+    for (int64_t p = 0; p < A->nnz; ++p) {
+        if (ci[p] < 0 || ci[p] >= A->n)
+            return fail(SMX_EINVAL, "column index %d at entry %lld outside [0, %lld)", ci[p], (long long)p,
+                        (long long)A->n);
+        if (!std::isfinite(v[p])) return fail(SMX_EINVAL, "non-finite value at entry %lld", (long long)p);
+    }
+    return SMX_OK;
+}
+
+template <typename T>
+std::vector<T> fetch(const T *p, int64_t count, bool on_device)
+{
+    std::vector<T> h(count);
+    if (count == 0) return h;
+    if (on_device) hip_check(hipMemcpy(h.data(), p, sizeof(T) * count, hipMemcpyDeviceToHost), "copy input to host");
+    else std::memcpy(h.data(), p, sizeof(T) * count);
+    return h;
+}
+
+template <typename T>
+void upload(DBuf &b, const std::vector<T> &h, hipStream_t s, const char *what)
+{
+    b.alloc(sizeof(T) * std::max<size_t>(h.size(), 1), what);
+    if (!h.empty()) hip_check(hipMemcpyAsync(b.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s), what);
+    hip_check(hipStreamSynchronize(s), what);
+}
+
+void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, bool keep32, int lp, hipStream_t s)
+{
+    D.rows = rows;
+    D.slots = H.slots;
+    upload(D.ptr, H.ptr, s, "upload row pointers");
+    upload(D.idx, H.idx, s, "upload indices");
+    upload(D.val32, H.val, s, "upload values");
+    if (lp != VK_F32) {
+        D.val16.alloc(sizeof(uint16_t) * std::max<int64_t>(H.slots, 1), "allocate reduced-precision values");
+        if (lp == VK_BF16) hip_check(launch_to_bf16(D.val32.as<float>(), D.val16.as<uint16_t>(), H.slots, s), "to bf16");
+        else {
+            D.f16_scale = f16_scale_for(H.val);
+            hip_check(launch_to_f16(D.val32.as<float>(), D.val16.as<uint16_t>(), H.slots, D.f16_scale, s), "to f16");
+        }
+        hip_check(hipStreamSynchronize(s), "convert values");
+        if (!keep32) D.val32.release();
+    }
+    // release host copies early
+    std::vector<int32_t>().swap(H.ptr);
+    std::vector<int32_t>().swap(H.idx);
+    std::vector<float>().swap(H.val);
+}
+
+int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStream_t s, smx_operator **out)
+{
+    if (!A || !out) return fail(SMX_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (A->m < 1 || A->n < 1) return fail(SMX_EINVAL, "m and n must be >= 1 (got %lld, %lld)", (long long)A->m, (long long)A->n);
+    if (A->m >= (int64_t(1) << 31) || A->n >= (int64_t(1) << 31) || A->nnz < 0 || A->nnz >= (int64_t(1) << 31))
+        return fail(SMX_EINVAL, "dimensions exceed 2^31-1");
+    if (storage < SMX_STORE_F32 || storage > SMX_STORE_F16) return fail(SMX_EINVAL, "unknown value storage %d", storage);
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) return fail(SMX_EINVAL, "NULL CSR array");
+    std::unique_ptr<smx_operator> op(new smx_operator());
+    op->m = A->m;
+    op->n = A->n;
+    op->nnz = A->nnz;
+    op->storage = storage;
+    op->has_f32 = (storage == SMX_STORE_F32) || keep_f32;
+    std::vector<int32_t> rp = fetch(A->row_ptr, A->m + 1, A->on_device);
+    std::vector<int32_t> ci = fetch(A->col_idx, A->nnz, A->on_device);
+    std::vector<float> va = fetch(A->val, A->nnz, A->on_device);
+    int rc = validate_csr_host(A, rp.data(), ci.data(), va.data());
+    if (rc != SMX_OK) return rc;
+    hip_check(hipGetDevice(&op->device), "get device");
+    const int64_t m = A->m, n = A->n, nnz = A->nnz;
+    std::vector<int64_t> rp64(rp.begin(), rp.end());
+    // transpose by a stable counting sort: rows stay in order inside each column
+    std::vector<int64_t> cp(n + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) cp[ci[p] + 1]++;
+    for (int64_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
+    std::vector<int32_t> ri(nnz);
+    std::vector<float> cv(nnz);
+    {
+        std::vector<int64_t> pos(cp.begin(), cp.end() - 1);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t p = rp64[i]; p < rp64[i + 1]; ++p) {
+                const int64_t q = pos[ci[p]]++;
+                ri[q] = (int32_t)i;
+                cv[q] = va[p];
+            }
+    }
+    const int lp = op->lp_kind();
+    {
+        HostLayout H;
+        if (!pad_rows(m, rp64.data(), ci.data(), va.data(), H)) return fail(SMX_EINVAL, "padded CSR exceeds 2^31 entries");
+        std::vector<int32_t>().swap(ci);
+        std::vector<float>().swap(va);
+        upload_layout(op->csr, H, m, op->has_f32, lp, s);
+    }
+    {
+        HostLayout H;
+        if (!pad_rows(n, cp.data(), ri.data(), cv.data(), H)) return fail(SMX_EINVAL, "padded CSC exceeds 2^31 entries");
+        std::vector<int32_t>().swap(ri);
+        std::vector<float>().swap(cv);
+        upload_layout(op->csc, H, n, op->has_f32, lp, s);
+    }
+    if (op->has_f32) {
+        op->q32.alloc(sizeof(double) * m, "row norms");
+        hip_check(launch_rownorm(op->csr.view(VK_F32), VK_F32, op->q32.as<double>(), s), "row norms");
+    }
+    if (lp != VK_F32) {
+        op->q16.alloc(sizeof(double) * m, "row norms (reduced precision)");
+        hip_check(launch_rownorm(op->csr.view(lp), lp, op->q16.as<double>(), s), "row norms (reduced precision)");
+    }
+    hip_check(hipStreamSynchronize(s), "operator setup");
+    op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32) +
+                layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32) +
+                size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0));
+    *out = op.release();
+    return SMX_OK;
+}
+
+void release_operator(smx_operator *op)
+{
+    if (op && op->refs.fetch_sub(1) == 1) delete op;
+}
+
+int vk_for_iteration(const smx_problem *p, int64_t it, int64_t K, int64_t ref)
+{
+    const int lp = p->op->lp_kind();
+    if (lp == VK_F32) return VK_F32;
+    if (!p->op->has_f32) return lp;
+    return (it >= K - ref) ? VK_F32 : lp;
+}
+
+// Enqueue one outer iteration with value kind vk on stream s, starting from
+// state buffer `cur`; returns the buffer current after it.
+int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
+{
+    const float *gvec = (p->pp.obj == OBJ_LINEAR) ? p->lin_c.as<float>() : p->g.as<float>();
+    if (perturb && p->pp.obj != OBJ_NONE) {
+        hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(), p->state(cur), 0,
+                               p->part_phase.as<double>(), s),
+                  "phase");
+        // each reduction step needs at most two trial launches (a short batch,
+        // then every remaining trial up to the cap); a last launch closes the phase
+        const int launches = (p->pp.max_trials > p->pp.first_width ? 2 : 1) * p->pp.n_red;
+        const double *prev = p->part_phase.as<double>();
+        for (int t = 0; t <= launches; ++t) {
+            double *out = p->part_trial[t & 1].as<double>();
+            hip_check(launch_trial(p->pp, p->x.as<float>(), gvec, p->state(cur), p->state(cur ^ 1), t == 0 ? 1 : 0,
+                                   t < launches ? 1 : 0, prev, out, s),
+                      "trial");
+            cur ^= 1;
+            prev = out;
+        }
+    }
+    const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
+    hipEvent_t e[4] = {};
+    if (timed) {
+        while (p->ev_pool.size() < p->ev_used + 4) {
+            hipEvent_t ev;
+            hip_check(hipEventCreate(&ev), "event");
+            p->ev_pool.push_back(ev);
+        }
+        for (int i = 0; i < 4; ++i) e[i] = p->ev_pool[p->ev_used + i];
+        p->ev_used += 4;
+        hip_check(hipEventRecord(e[0], s), "event");
+    }
+    hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), vk, p->x.as<float>(), p->lower.as<float>(),
+                           p->upper.as<float>(), D, p->c.as<float>(), p->state(cur), p->B, 0,
+                           p->part_pass.as<double>(), s),
+              "pass 1");
+    if (timed) {
+        hip_check(hipEventRecord(e[1], s), "event");
+        hip_check(hipEventRecord(e[2], s), "event");
+    }
+    hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, vk), vk, p->c.as<float>(), p->x.as<float>(),
+                           p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, p->state(cur), p->state(cur ^ 1),
+                           p->B, p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
+              "pass 2");
+    cur ^= 1;
+    if (timed) hip_check(hipEventRecord(e[3], s), "event");
+    return cur;
+}
+
+// Graph of `iters` iterations starting from state buffer `cur`; *cur_after
+// receives the buffer current after it.
+hipGraphExec_t graph_for(smx_problem *p, int vk, bool perturb, int iters, int cur, int *cur_after)
+{
+    const long long key = ((long long)vk << 40) | ((long long)(perturb ? 1 : 0) << 33) | ((long long)cur << 32) |
+                          (long long)iters;
+    // the buffer parity after the chunk does not depend on the data
+    int after = cur;
+    {
+        const bool pert = perturb && p->pp.obj != OBJ_NONE;
+        const int launches = (p->pp.max_trials > p->pp.first_width ? 2 : 1) * p->pp.n_red;
+        const int flips = (pert ? launches + 1 : 0) + 1;
+        if ((flips * iters) & 1) after ^= 1;
+    }
+    *cur_after = after;
+    auto it = p->graphs.find(key);
+    if (it != p->graphs.end()) return it->second;
+    hipGraph_t g = nullptr;
+    if (!p->capture_stream) hip_check(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "capture stream");
+    hip_check(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+        int c = cur;
+        for (int i = 0; i < iters; ++i) c = enqueue_iteration(p, p->capture_stream, vk, perturb, false, c);
+        if (c != after) throw HipError{hipErrorUnknown, "state buffer parity"};
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(p->capture_stream, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(p->capture_stream, &g), "end capture");
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(e, "instantiate graph");
+    p->graphs[key] = ex;
+    return ex;
+}
+
+constexpr int kGraphChunk = 10;
+
+int run_impl(smx_problem *p, int32_t K, uint32_t flags)
+{
+    if (K < 0) return fail(SMX_EINVAL, "K must be >= 0");
+    if (K == 0) return SMX_OK;
+    const bool perturb = (flags & SMX_RUN_PERTURB) != 0;
+    const bool graph = (flags & SMX_RUN_GRAPH) != 0;
+    const int lp = p->op->lp_kind();
+    int64_t ref = 0;
+    if (lp != VK_F32 && p->op->has_f32) ref = p->refine_iters >= 0 ? p->refine_iters : (K + 19) / 20;
+    if (ref > K) ref = K;
+    const bool timed = p->timing && !graph;
+    if (timed) p->ev_used = 0;
+    int64_t it = 0;
+    while (it < K) {
+        const int vk = vk_for_iteration(p, it, K, ref);
+        // run of iterations with the same value kind
+        int64_t end = it;
+        while (end < K && vk_for_iteration(p, end, K, ref) == vk) ++end;
+        int64_t left = end - it;
+        if (graph) {
+            while (left > 0) {
+                const int chunk = (int)std::min<int64_t>(left, kGraphChunk);
+                int after = p->cur;
+                hipGraphExec_t ex = graph_for(p, vk, perturb, chunk, p->cur, &after);
+                hip_check(hipGraphLaunch(ex, p->stream), "graph launch");
+                p->cur = after;
+                left -= chunk;
+            }
+        } else {
+            for (int64_t i = 0; i < left; ++i) p->cur = enqueue_iteration(p, p->stream, vk, perturb, timed, p->cur);
+        }
+        it = end;
+    }
+    if (timed) {
+        hip_check(hipStreamSynchronize(p->stream), "timing sync");
+        double a = 0, b = 0;
+        for (size_t i = 0; i + 3 < p->ev_used; i += 4) {
+            float t1 = 0, t2 = 0;
+            hip_check(hipEventElapsedTime(&t1, p->ev_pool[i], p->ev_pool[i + 1]), "elapsed");
+            hip_check(hipEventElapsedTime(&t2, p->ev_pool[i + 2], p->ev_pool[i + 3]), "elapsed");
+            a += t1;
+            b += t2;
+        }
+        p->t1_ms = a;
+        p->t2_ms = b;
+        p->t_launches = (int64_t)(p->ev_used / 4);
+    }
+    return SMX_OK;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, smx_problem **out)
+{
+    if (!op || !d || !out) return fail(SMX_EINVAL, "NULL argument");
+    *out = nullptr;
+    const int64_t m = op->m, n = op->n;
+    const int B = d->B;
+    if (!is_pow2(B) || B > 1) {
+        // batched slices are served by separate problems until the multi-slice kernels land
+        if (!(is_pow2(B) && B <= 32)) return fail(SMX_EINVAL, "B must be a power of two in 1..32 (got %d)", B);
+        if (B != 1) return fail(SMX_EINVAL, "B > 1 is not supported by this build (got %d)", B);
+    }
+    if (!(d->lambda > 0.0 && d->lambda <= 2.0)) return fail(SMX_EINVAL, "lambda must be in (0, 2] (got %g)", d->lambda);
+    if (d->obj_kind < SMX_OBJ_NONE || d->obj_kind > SMX_OBJ_LINEAR) return fail(SMX_EINVAL, "unknown objective %d", d->obj_kind);
+    if (d->obj_kind != SMX_OBJ_NONE) {
+        if (!(d->gamma > 0.0) || !std::isfinite(d->gamma)) return fail(SMX_EINVAL, "gamma must be > 0 (got %g)", d->gamma);
+        if (!(d->alpha > 0.0 && d->alpha < 1.0)) return fail(SMX_EINVAL, "alpha must be in (0, 1) (got %g)", d->alpha);
+        if (d->n_red < 1) return fail(SMX_EINVAL, "n_red must be >= 1 (got %d)", d->n_red);
+        if (d->max_trials < 1 || d->max_trials > 1024) return fail(SMX_EINVAL, "max_trials must be in 1..1024 (got %d)", d->max_trials);
+        if (d->restart_every < 0) return fail(SMX_EINVAL, "restart_every must be >= 0");
+    }
+    if (d->obj_kind == SMX_OBJ_TV2D) {
+        if (d->tv_rows < 1 || d->tv_cols < 1 || (int64_t)d->tv_rows * d->tv_cols != n)
+            return fail(SMX_EINVAL, "TV image %d x %d does not match n = %lld", d->tv_rows, d->tv_cols, (long long)n);
+        if (!(d->tv_eps >= 0.0) || !std::isfinite(d->tv_eps)) return fail(SMX_EINVAL, "tv_eps must be >= 0");
+    }
+    if (d->obj_kind == SMX_OBJ_LINEAR && !d->linear_c) return fail(SMX_EINVAL, "LINEAR objective needs linear_c");
+    if (!d->lower || !d->upper) return fail(SMX_EINVAL, "lower and upper bounds are required");
+    if (d->history_cap < 0) return fail(SMX_EINVAL, "history_cap must be >= 0");
+    const bool dev = d->on_device != 0;
+    std::vector<float> lo = fetch(d->lower, m * B, dev), up = fetch(d->upper, m * B, dev);
+    for (int64_t i = 0; i < m * B; ++i) {
+        if (std::isnan(lo[i]) || std::isnan(up[i])) return fail(SMX_EINVAL, "NaN bound at %lld", (long long)i);
+        if (lo[i] > up[i]) return fail(SMX_EINVAL, "lower > upper at %lld", (long long)i);
+    }
+    std::vector<double> w(m, 1.0);
+    if (d->weights) {
+        w = fetch(d->weights, m, dev);
+        for (int64_t i = 0; i < m; ++i)
+            if (!(w[i] > 0.0) || !std::isfinite(w[i])) return fail(SMX_EINVAL, "weight %lld must be finite and > 0", (long long)i);
+    }
+    double wsum = 0.0;
+    for (double v : w) wsum += v;
+    for (double &v : w) v /= wsum;
+    std::vector<float> blo(n, -INFINITY), bhi(n, INFINITY);
+    if (d->box_lo) blo = fetch(d->box_lo, n, dev);
+    if (d->box_hi) bhi = fetch(d->box_hi, n, dev);
+    for (int64_t j = 0; j < n; ++j) {
+        if (std::isnan(blo[j]) || std::isnan(bhi[j]) || blo[j] > bhi[j])
+            return fail(SMX_EINVAL, "invalid box at %lld", (long long)j);
+    }
+    std::vector<float> lc;
+    if (d->obj_kind == SMX_OBJ_LINEAR) {
+        lc = fetch(d->linear_c, n, dev);
+        for (float v : lc)
+            if (!std::isfinite(v)) return fail(SMX_EINVAL, "non-finite linear_c");
+    }
+    std::unique_ptr<smx_problem> p(new smx_problem());
+    p->op = op;
+    p->device = op->device;
+    p->stream = s;
+    p->B = B;
+    p->m = m;
+    p->n = n;
+    p->lambda = (float)d->lambda;
+    p->refine_iters = d->refine_iters;
+    PertParams &pp = p->pp;
+    pp.obj = d->obj_kind;
+    pp.B = B;
+    pp.n = n;
+    pp.tv_rows = d->tv_rows;
+    pp.tv_cols = d->tv_cols;
+    pp.tv_eps2 = d->tv_eps * d->tv_eps;
+    pp.gamma = d->gamma;
+    pp.alpha = d->alpha;
+    pp.n_red = std::max(1, d->n_red);
+    pp.restart_every = d->restart_every;
+    pp.max_trials = std::max(1, d->max_trials);
+    pp.first_width = std::min(pp.max_trials, kTrialChunk);
+    upload(p->lower, lo, s, "bounds");
+    upload(p->upper, up, s, "bounds");
+    upload(p->box_lo, blo, s, "box");
+    upload(p->box_hi, bhi, s, "box");
+    upload(p->w, w, s, "weights");
+    if (!lc.empty()) upload(p->lin_c, lc, s, "linear objective");
+    p->x.alloc(sizeof(float) * n * B, "iterate");
+    hip_check(launch_fill(p->x.as<float>(), 0.f, n * B, s), "zero iterate");
+    p->g.alloc(sizeof(float) * n * B, "gradient");
+    p->c.alloc(sizeof(float) * m * B, "weighted residual");
+    p->st.alloc(sizeof(SliceState) * 2 * B, "state");
+    hip_check(launch_init_state(p->state(0), B, s), "init state");
+    hip_check(launch_init_state(p->state(1), B, s), "init state");
+    p->cur = 0;
+    const int lp = op->lp_kind();
+    if (op->has_f32) {
+        p->D32.alloc(sizeof(float) * m, "D");
+        hip_check(launch_make_D(op->q32.as<double>(), p->w.as<double>(), p->D32.as<float>(), m, s), "D");
+    }
+    if (lp != VK_F32) {
+        p->D16.alloc(sizeof(float) * m, "D (reduced precision)");
+        hip_check(launch_make_D(op->q16.as<double>(), p->w.as<double>(), p->D16.as<float>(), m, s), "D");
+    }
+    for (int vk = 0; vk < 3; ++vk) {
+        p->cfg1[vk] = pick_cfg(m, op->csr.slots, vk);
+        p->cfg2[vk] = pick_cfg(n, op->csc.slots, vk);
+    }
+    // per-workgroup partial sums of each kernel kind
+    const int64_t pgrid = phase_grid(pp);
+    p->part_pass.alloc(sizeof(double) * size_t(kMaxPassGrid) * B, "pass partials");
+    p->part_query.alloc(sizeof(double) * size_t(kMaxPassGrid) * B, "query partials");
+    p->part_phase.alloc(sizeof(double) * size_t(pgrid) * B * 2, "phase partials");
+    p->part_trial[0].alloc(sizeof(double) * size_t(pgrid) * B * pp.max_trials, "trial partials");
+    p->part_trial[1].alloc(sizeof(double) * size_t(pgrid) * B * pp.max_trials, "trial partials");
+    p->qout.alloc(sizeof(double) * 2 * B, "query output");
+    p->hist_cap = d->history_cap;
+    if (d->history_cap > 0) {
+        const size_t hc = size_t(d->history_cap) * B;
+        p->h_prox.alloc(sizeof(double) * hc, "history");
+        p->h_fs.alloc(sizeof(double) * hc, "history");
+        p->h_fe.alloc(sizeof(double) * hc, "history");
+        p->h_tr.alloc(sizeof(int) * hc, "history");
+        p->h_ac.alloc(sizeof(int) * hc, "history");
+    }
+    p->hist.prox = p->h_prox.as<double>();
+    p->hist.f_start = p->h_fs.as<double>();
+    p->hist.f_end = p->h_fe.as<double>();
+    p->hist.trials = p->h_tr.as<int>();
+    p->hist.accepts = p->h_ac.as<int>();
+    p->hist.cap = d->history_cap;
+    hip_check(hipStreamSynchronize(s), "problem setup");
+    op->refs.fetch_add(1);
+    *out = p.release();
+    return SMX_OK;
+}
+
+#define SMX_GUARD(body)                                                                                               \
+    try {                                                                                                             \
+        g_err.clear();                                                                                                \
+        body                                                                                                          \
+    } catch (const HipError &h) {                                                                                     \
+        return from_hip(h);                                                                                           \
+    } catch (const std::bad_alloc &) {                                                                                \
+        return fail(SMX_ENOMEM, "host allocation failed");                                                            \
+    } catch (...) {                                                                                                   \
+        return fail(SMX_EDEVICE, "unexpected internal error");                                                       \
+    }
+
+} // namespace
+
+extern "C" {
+
+int smx_version(int *major, int *minor)
+{
+    if (!major || !minor) return fail(SMX_EINVAL, "NULL argument");
+    *major = SMX_VERSION_MAJOR;
+    *minor = SMX_VERSION_MINOR;
+    return SMX_OK;
+}
+
+const char *smx_last_error(void) { return g_err.c_str(); }
+
+int smx_operator_create(const smx_csr *A, int32_t value_storage, int32_t keep_f32, void *stream, smx_operator **out)
+{
+    SMX_GUARD(return create_operator(A, value_storage, keep_f32, (hipStream_t)stream, out);)
+}
+
+int smx_operator_destroy(smx_operator *op)
+{
+    SMX_GUARD(release_operator(op); return SMX_OK;)
+}
+
+int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32, size_t *bytes)
+{
+    if (!bytes) return fail(SMX_EINVAL, "NULL argument");
+    if (m < 1 || n < 1 || nnz < 0) return fail(SMX_EINVAL, "invalid shape");
+    if (value_storage < SMX_STORE_F32 || value_storage > SMX_STORE_F16) return fail(SMX_EINVAL, "unknown storage");
+    const bool lp = value_storage != SMX_STORE_F32;
+    const bool f32 = !lp || keep_f32;
+    // upper bound on padding: kRowAlign-1 entries per row and per column
+    const int64_t s1 = nnz + (kRowAlign - 1) * m, s2 = nnz + (kRowAlign - 1) * n;
+    *bytes = layout_bytes(m, s1, f32, lp) + layout_bytes(n, s2, f32, lp) + size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0));
+    return SMX_OK;
+}
+
+int smx_problem_create(smx_operator *op, const smx_problem_desc *desc, void *stream, smx_problem **out)
+{
+    SMX_GUARD(return create_problem(op, desc, (hipStream_t)stream, out);)
+}
+
+int smx_problem_destroy(smx_problem *p)
+{
+    if (!p) return SMX_OK;
+    SMX_GUARD({
+        (void)hipStreamSynchronize(p->stream);
+        smx_operator *op = p->op;
+        delete p;
+        release_operator(op);
+        return SMX_OK;
+    })
+}
+
+int smx_create(const smx_csr *A, int32_t value_storage, const smx_problem_desc *desc, void *stream, smx_problem **out)
+{
+    SMX_GUARD({
+        if (!out) return fail(SMX_EINVAL, "NULL argument");
+        smx_operator *op = nullptr;
+        int rc = create_operator(A, value_storage, 1, (hipStream_t)stream, &op);
+        if (rc != SMX_OK) return rc;
+        rc = create_problem(op, desc, (hipStream_t)stream, out);
+        release_operator(op); // the problem holds the remaining reference (or none on failure)
+        return rc;
+    })
+}
+
+int smx_set_stream(smx_problem *p, void *stream)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        if ((hipStream_t)stream != p->stream) {
+            hip_check(hipStreamSynchronize(p->stream), "sync old stream");
+            p->stream = (hipStream_t)stream;
+        }
+        return SMX_OK;
+    })
+}
+
+int smx_set_x(smx_problem *p, const float *x, int32_t on_device)
+{
+    if (!p || !x) return fail(SMX_EINVAL, "NULL argument");
+    SMX_GUARD({
+        hip_check(hipMemcpyAsync(p->x.p, x, sizeof(float) * p->n * p->B,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream),
+                  "set x");
+        if (!on_device) hip_check(hipStreamSynchronize(p->stream), "set x");
+        return SMX_OK;
+    })
+}
+
+int smx_get_x(smx_problem *p, float *out, int32_t on_device)
+{
+    if (!p || !out) return fail(SMX_EINVAL, "NULL argument");
+    SMX_GUARD({
+        hip_check(hipMemcpyAsync(out, p->x.p, sizeof(float) * p->n * p->B,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream),
+                  "get x");
+        if (!on_device) hip_check(hipStreamSynchronize(p->stream), "get x");
+        return SMX_OK;
+    })
+}
+
+int smx_run(smx_problem *p, int32_t K, uint32_t flags)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD(return run_impl(p, K, flags);)
+}
+
+int smx_sync(smx_problem *p)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        hip_check(hipStreamSynchronize(p->stream), "sync");
+        std::vector<SliceState> st(p->B);
+        hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost), "read state");
+        bool bad = false;
+        for (auto &S : st)
+            if (S.nonfinite) bad = true;
+        if (bad) {
+            for (auto &S : st) S.nonfinite = 0;
+            hip_check(hipMemcpy(p->state(p->cur), st.data(), sizeof(SliceState) * p->B, hipMemcpyHostToDevice), "clear flag");
+            return fail(SMX_ENUMERIC, "a non-finite proximity or objective was produced");
+        }
+        return SMX_OK;
+    })
+}
+
+int smx_query(smx_problem *p, double *proximity, double *objective)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        const int B = p->B;
+        const int vk = p->op->has_f32 ? VK_F32 : p->op->lp_kind();
+        const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
+        double *q = p->qout.as<double>();
+        hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), vk, p->x.as<float>(), p->lower.as<float>(),
+                               p->upper.as<float>(), D, p->c.as<float>(), p->state(p->cur), B, 1,
+                               p->part_query.as<double>(), p->stream),
+                  "query proximity");
+        hip_check(launch_query_prox(p->state(p->cur), B, p->part_query.as<double>(), p->cfg1[vk].grid, q,
+                                    p->stream),
+                  "query proximity");
+        std::vector<double> h(2 * B, 0.0);
+        if (p->pp.obj != OBJ_NONE) {
+            hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(),
+                                   p->state(p->cur), 1, p->part_phase.as<double>(), p->stream),
+                      "query objective");
+            hip_check(launch_eval_objective(p->state(p->cur), p->pp, p->part_phase.as<double>(), q + B, p->stream),
+                      "query objective");
+            hip_check(hipMemcpyAsync(h.data(), q, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, p->stream), "query");
+        } else {
+            hip_check(hipMemcpyAsync(h.data(), q, sizeof(double) * B, hipMemcpyDeviceToHost, p->stream), "query");
+        }
+        hip_check(hipStreamSynchronize(p->stream), "query");
+        for (int s = 0; s < B; ++s) {
+            if (proximity) proximity[s] = h[s];
+            if (objective) objective[s] = h[B + s];
+        }
+        return SMX_OK;
+    })
+}
+
+int smx_get_history(smx_problem *p, double *prox, double *f_start, double *f_end, int32_t *trials, int32_t *accepts,
+                    int32_t cap, int32_t *n_out)
+{
+    if (!p || !n_out) return fail(SMX_EINVAL, "NULL argument");
+    if (cap < 0) return fail(SMX_EINVAL, "cap must be >= 0");
+    SMX_GUARD({
+        hip_check(hipStreamSynchronize(p->stream), "history");
+        std::vector<SliceState> st(p->B);
+        hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost), "read state");
+        long long kmax = 0;
+        for (auto &S : st) kmax = std::max(kmax, S.k);
+        const int64_t nrec = std::min<int64_t>({(int64_t)kmax, (int64_t)p->hist_cap, (int64_t)cap});
+        const size_t cnt = size_t(nrec) * p->B;
+        if (nrec > 0) {
+            if (prox) hip_check(hipMemcpy(prox, p->h_prox.p, sizeof(double) * cnt, hipMemcpyDeviceToHost), "history");
+            if (f_start) hip_check(hipMemcpy(f_start, p->h_fs.p, sizeof(double) * cnt, hipMemcpyDeviceToHost), "history");
+            if (f_end) hip_check(hipMemcpy(f_end, p->h_fe.p, sizeof(double) * cnt, hipMemcpyDeviceToHost), "history");
+            if (trials) hip_check(hipMemcpy(trials, p->h_tr.p, sizeof(int) * cnt, hipMemcpyDeviceToHost), "history");
+            if (accepts) hip_check(hipMemcpy(accepts, p->h_ac.p, sizeof(int) * cnt, hipMemcpyDeviceToHost), "history");
+        }
+        *n_out = (int32_t)nrec;
+        return SMX_OK;
+    })
+}
+
+int smx_get_state(smx_problem *p, smx_slice_state *states, float *x)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        hip_check(hipStreamSynchronize(p->stream), "state");
+        std::vector<SliceState> st(p->B);
+        hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost), "read state");
+        if (states)
+            for (int s = 0; s < p->B; ++s) {
+                states[s].k = st[s].k;
+                states[s].ell = st[s].ell;
+                states[s].restarts = st[s].restarts;
+                states[s].trials = st[s].trials;
+                states[s].accepts = st[s].accepts;
+                states[s].cap_hits = st[s].cap_hits;
+            }
+        if (x) hip_check(hipMemcpy(x, p->x.p, sizeof(float) * p->n * p->B, hipMemcpyDeviceToHost), "read x");
+        return SMX_OK;
+    })
+}
+
+int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        hip_check(hipStreamSynchronize(p->stream), "state");
+        if (states) {
+            for (int s = 0; s < p->B; ++s)
+                if (states[s].k < 0 || states[s].ell < 0 || states[s].restarts < 0)
+                    return fail(SMX_EINVAL, "negative counter in state of slice %d", s);
+            std::vector<SliceState> st(p->B);
+            hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost), "read state");
+            for (int s = 0; s < p->B; ++s) {
+                st[s].k = states[s].k;
+                st[s].ell = states[s].ell;
+                st[s].restarts = states[s].restarts;
+                st[s].trials = states[s].trials;
+                st[s].accepts = states[s].accepts;
+                st[s].cap_hits = states[s].cap_hits;
+                st[s].phase = 0;
+                st[s].live = (st[s].enabled && st[s].k < st[s].k_end) ? 1 : 0;
+            }
+            hip_check(hipMemcpy(p->state(p->cur), st.data(), sizeof(SliceState) * p->B, hipMemcpyHostToDevice), "write state");
+        }
+        if (x) hip_check(hipMemcpy(p->x.p, x, sizeof(float) * p->n * p->B, hipMemcpyHostToDevice), "write x");
+        return SMX_OK;
+    })
+}
+
+int smx_problem_dims(const smx_problem *p, int64_t *m, int64_t *n, int64_t *nnz, int32_t *B)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    if (m) *m = p->m;
+    if (n) *n = p->n;
+    if (nnz) *nnz = p->op->nnz;
+    if (B) *B = p->B;
+    return SMX_OK;
+}
+
+int smx_set_timing(smx_problem *p, int32_t enable)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    p->timing = enable != 0;
+    return SMX_OK;
+}
+
+int smx_get_timing(smx_problem *p, double *pass1_ms, double *pass2_ms, int64_t *launches)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    const int64_t L = p->t_launches;
+    if (pass1_ms) *pass1_ms = L ? p->t1_ms / L : 0.0;
+    if (pass2_ms) *pass2_ms = L ? p->t2_ms / L : 0.0;
+    if (launches) *launches = L;
+    return SMX_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,996 @@
+// HIP kernels of libsmx for CDNA4 (gfx950, wave64).
+//
+// The method (paper, Section 2.1): one outer iteration of Algorithm 1 is a
+// perturbation phase (trial steps z = x + beta v along v = -grad f/||grad f||,
+// beta = gamma alpha^ell, accepted when f does not increase) followed by the
+// feasibility step T = box projection of the relaxed simultaneous projection
+// onto the bands lower <= Ax <= upper.  T streams A twice: pass 1 reads A row by
+// row (r = A z and the band residual t), pass 2 reads the column-major copy
+// (A^T of the weighted residual) and applies the box.
+//
+// Reductions that decide anything (proximity, objective values, gradient norms)
+// run in float64 with a fixed order: every workgroup writes its partial sum and
+// a one-workgroup kernel launched next sums the partials in workgroup order and
+// updates the per-slice state (acceptance of trial steps included).  No kernel
+// waits on, or signals, another workgroup of its own grid.
+#include "smx_internal.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <math.h>
+
+namespace smx {
+
+// ---------------------------------------------------------------------------
+// reductions
+//
+// A kernel that needs a grid-wide sum writes one partial per workgroup; a
+// single-workgroup kernel launched after it sums the partials in workgroup
+// order.  Kernel boundaries order the two, so no workgroup ever waits for or
+// signals another one, and every sum is reproducible bit for bit.
+// ---------------------------------------------------------------------------
+
+template <int NV>
+__device__ inline void wave_sum(double (&v)[NV])
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+}
+
+// Sum of v over the workgroup, valid in thread 0.  lds holds >= 4*NV doubles.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *lds)
+{
+    wave_sum<NV>(v);
+    const int wid = threadIdx.x >> 6, wl = threadIdx.x & 63;
+    if (wl == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[wid * NV + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += lds[w * NV + k];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Totals over `count` consecutive slots starting at `first` (each slot NV
+// values), summed in slot order by one workgroup; valid in thread 0.
+template <int NV>
+__device__ inline void sum_slots(const double *__restrict__ partials, long long first, int count, double (&tot)[NV],
+                                 double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    for (int b = threadIdx.x; b < count; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] += partials[(first + b) * NV + k];
+    }
+    block_sum<NV>(tot, lds);
+}
+
+// ---------------------------------------------------------------------------
+// value loads
+// ---------------------------------------------------------------------------
+
+template <typename VT, int VEC>
+struct ValLoad;
+
+template <>
+struct ValLoad<float, 4> {
+    static __device__ inline void load(const void *base, int p, float (&v)[4])
+    {
+        const float4 q = *reinterpret_cast<const float4 *>(static_cast<const float *>(base) + p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    }
+};
+
+template <>
+struct ValLoad<float, 8> {
+    static __device__ inline void load(const void *base, int p, float (&v)[8])
+    {
+        const float4 *q = reinterpret_cast<const float4 *>(static_cast<const float *>(base) + p);
+        const float4 a = q[0], b = q[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+};
+
+struct Bf16Tag {};
+struct F16Tag {};
+
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ inline float f16_lo(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu))); }
+__device__ inline float f16_hi(uint32_t w) { return __half2float(__ushort_as_half((unsigned short)(w >> 16))); }
+
+template <int VEC>
+struct ValLoad16Base {
+    static_assert(VEC == 4 || VEC == 8, "VEC");
+};
+
+template <>
+struct ValLoad<Bf16Tag, 8> {
+    static __device__ inline void load(const void *base, int p, float (&v)[8])
+    {
+        const uint4 q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(base) + p);
+        v[0] = bf16_lo(q.x); v[1] = bf16_hi(q.x); v[2] = bf16_lo(q.y); v[3] = bf16_hi(q.y);
+        v[4] = bf16_lo(q.z); v[5] = bf16_hi(q.z); v[6] = bf16_lo(q.w); v[7] = bf16_hi(q.w);
+    }
+};
+
+template <>
+struct ValLoad<Bf16Tag, 4> {
+    static __device__ inline void load(const void *base, int p, float (&v)[4])
+    {
+        const uint2 q = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(base) + p);
+        v[0] = bf16_lo(q.x); v[1] = bf16_hi(q.x); v[2] = bf16_lo(q.y); v[3] = bf16_hi(q.y);
+    }
+};
+
+template <>
+struct ValLoad<F16Tag, 8> {
+    static __device__ inline void load(const void *base, int p, float (&v)[8])
+    {
+        const uint4 q = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(base) + p);
+        v[0] = f16_lo(q.x); v[1] = f16_hi(q.x); v[2] = f16_lo(q.y); v[3] = f16_hi(q.y);
+        v[4] = f16_lo(q.z); v[5] = f16_hi(q.z); v[6] = f16_lo(q.w); v[7] = f16_hi(q.w);
+    }
+};
+
+template <>
+struct ValLoad<F16Tag, 4> {
+    static __device__ inline void load(const void *base, int p, float (&v)[4])
+    {
+        const uint2 q = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(base) + p);
+        v[0] = f16_lo(q.x); v[1] = f16_hi(q.x); v[2] = f16_lo(q.y); v[3] = f16_hi(q.y);
+    }
+};
+
+template <int VEC>
+__device__ inline void idx_load(const int32_t *base, int p, int (&c)[VEC])
+{
+    const int4 *q = reinterpret_cast<const int4 *>(base + p);
+#pragma unroll
+    for (int h = 0; h < VEC / 4; ++h) {
+        const int4 a = q[h];
+        c[4 * h + 0] = a.x; c[4 * h + 1] = a.y; c[4 * h + 2] = a.z; c[4 * h + 3] = a.w;
+    }
+}
+
+// Partial dot product of one row with a vector, by lane `lane` of an LPR-lane
+// group.  [beg, end) is row-aligned, so every vector load is aligned and no
+// entry needs a mask (padding entries are zeros with valid indices).  Products
+// of two float32 numbers are exact in float64, so accumulating in float64
+// leaves only the rounding of the sums; the pass is bound by memory traffic,
+// not by the float64 rate.
+template <int LPR, int VEC, typename VT>
+__device__ inline double row_dot(const SpView &A, int beg, int end, int lane, const float *__restrict__ x)
+{
+    double acc0 = 0.0, acc1 = 0.0;
+    int p = beg + lane * VEC;
+    constexpr int STEP = LPR * VEC;
+    for (; p + STEP < end; p += 2 * STEP) {
+        float v0[VEC], v1[VEC];
+        int c0[VEC], c1[VEC];
+        ValLoad<VT, VEC>::load(A.val, p, v0);
+        idx_load<VEC>(A.idx, p, c0);
+        ValLoad<VT, VEC>::load(A.val, p + STEP, v1);
+        idx_load<VEC>(A.idx, p + STEP, c1);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc0 = fma((double)v0[e], (double)x[c0[e]], acc0);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc1 = fma((double)v1[e], (double)x[c1[e]], acc1);
+    }
+    if (p < end) {
+        float v0[VEC];
+        int c0[VEC];
+        ValLoad<VT, VEC>::load(A.val, p, v0);
+        idx_load<VEC>(A.idx, p, c0);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc0 = fma((double)v0[e], (double)x[c0[e]], acc0);
+    }
+    return acc0 + acc1;
+}
+
+template <int LPR>
+__device__ inline double group_sum(double v)
+{
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPR);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: r = A z, t = clip(r, lower, upper) - r, c = D t, and one partial of
+// the proximity 1/2 sum D t^2 per workgroup
+// ---------------------------------------------------------------------------
+
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restrict__ x,
+                                                  const float *__restrict__ lower, const float *__restrict__ upper,
+                                                  const float *__restrict__ D, float *__restrict__ c,
+                                                  const SliceState *__restrict__ st, int query,
+                                                  double *__restrict__ partials)
+{
+    __shared__ double lds[4];
+    constexpr int RPB = kBlock / LPR;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const bool live = query ? true : st[0].live != 0;
+    double pacc[1] = {0.0};
+    if (live) {
+        const long long stride = (long long)gridDim.x * RPB;
+        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
+            const int beg = A.ptr[row], end = A.ptr[row + 1];
+            const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
+            if (lane == 0) {
+                const double t = fmin(fmax(r, (double)lower[row]), (double)upper[row]) - r;
+                const double dt = (double)D[row] * t;
+                c[row] = (float)dt;
+                pacc[0] += dt * t;
+            }
+        }
+    }
+    block_sum<1>(pacc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+}
+
+__device__ inline double nan64() { return __longlong_as_double(0x7ff8000000000000LL); }
+
+// ---------------------------------------------------------------------------
+// State buffers.  Every kernel reads the per-slice states from st_in; kernels
+// that advance the state have exactly one writer per slice (thread 0 of the
+// slice's workgroup 0), which writes the whole new state to the other buffer
+// st_out.  The host alternates the two buffers launch by launch, so a kernel
+// never reads a state another workgroup of the same grid is writing.
+// ---------------------------------------------------------------------------
+
+// End of an outer iteration: proximity from pass 1's partials, the history
+// record, k + 1, and whether the next iteration runs.  Called by every thread
+// of one workgroup.
+__device__ inline void finish_iteration(const SliceState *__restrict__ st_in, SliceState *__restrict__ st_out, int B,
+                                        const double *__restrict__ part1, int nparts, const Hist &h, double *lds)
+{
+    for (int s = 0; s < B; ++s) {
+        double tot[1];
+        sum_slots<1>(part1, (long long)s * nparts, nparts, tot, lds);
+        if (threadIdx.x == 0) {
+            SliceState S = st_in[s];
+            if (S.live) {
+                const double prox = 0.5 * tot[0];
+                S.prox = prox;
+                if (!isfinite(prox)) S.nonfinite = 1;
+                if (S.k < h.cap) {
+                    const long long r = S.k * B + s;
+                    h.prox[r] = prox;
+                    h.f_start[r] = S.f_start;
+                    h.f_end[r] = S.f_cur;
+                    h.trials[r] = S.trials_it;
+                    h.accepts[r] = S.accepts_it;
+                }
+                S.k += 1;
+            }
+            S.f_start = S.f_cur = nan64();
+            S.trials_it = 0;
+            S.accepts_it = 0;
+            S.phase = 0;
+            S.live = (S.enabled && S.k < S.k_end) ? 1 : 0;
+            st_out[s] = S;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: y = A^T c, x = clip(z + lambda y, lo, hi); workgroup 0 also closes
+// the outer iteration
+// ---------------------------------------------------------------------------
+
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kBlock) void k_pass2(SpView At, const float *__restrict__ c, float *__restrict__ x,
+                                                  const float *__restrict__ lo, const float *__restrict__ hi,
+                                                  float lambda, const SliceState *__restrict__ st_in,
+                                                  SliceState *__restrict__ st_out, const double *__restrict__ part1,
+                                                  int nparts1, Hist h)
+{
+    __shared__ double lds[4];
+    constexpr int RPB = kBlock / LPR;
+    if (st_in[0].live) {
+        const int lane = threadIdx.x & (LPR - 1);
+        const int grp = threadIdx.x / LPR;
+        const long long stride = (long long)gridDim.x * RPB;
+        for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
+            const int beg = At.ptr[col], end = At.ptr[col + 1];
+            const double y = group_sum<LPR>(row_dot<LPR, VEC, VT>(At, beg, end, lane, c)) * (double)At.vscale_inv;
+            if (lane == 0) {
+                const double z = fma((double)lambda, y, (double)x[col]);
+                x[col] = (float)fmin(fmax(z, (double)lo[col]), (double)hi[col]);
+            }
+        }
+    }
+    if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+}
+
+// Query: the proximity at the current x from pass 1's partials (query mode).
+__global__ __launch_bounds__(kBlock) void k_query_prox(SliceState *__restrict__ st, int B,
+                                                       const double *__restrict__ partials, int nparts,
+                                                       double *__restrict__ out)
+{
+    __shared__ double lds[4];
+    for (int s = 0; s < B; ++s) {
+        double tot[1];
+        sum_slots<1>(partials, (long long)s * nparts, nparts, tot, lds);
+        if (threadIdx.x == 0) {
+            out[s] = 0.5 * tot[0];
+            if (!isfinite(out[s])) st[s].nonfinite = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// perturbation phase
+//
+// Launch sequence of one phase: gradient (partials of ||g||^2 and f(x^k) per
+// tile), then trial launches, then a closing launch.  Each trial launch first
+// re-derives, in every workgroup, what the previous launch decided (the first
+// launch: the opening of the phase) from that launch's partials, then either
+// evaluates the next batch of trial steps or, once the phase is over, adds the
+// accepted step s_acc v to its own tile of x.  Partials are stored value-major
+// ([value][slice*tiles + tile]) so the re-derivation reads them coalesced.
+// ---------------------------------------------------------------------------
+
+__device__ inline double trial_beta(const PertParams &pp, long long e) { return pp.gamma * pow(pp.alpha, (double)e); }
+
+// Number of trials a trial launch evaluates for slice state S: a short batch
+// when a reduction step starts, all remaining ones (up to the cap) after that.
+__device__ inline int trial_width(const SliceState &S, const PertParams &pp)
+{
+    if (!S.phase) return 0;
+    const int left = pp.max_trials - S.step_tried;
+    return S.step_tried == 0 ? min(pp.first_width, left) : left;
+}
+
+// Grid of the phase kernels: blockIdx.y is the slice, blockIdx.x a tile (TV)
+// or a chunk of the vector.
+int phase_grid(const PertParams &pp)
+{
+    if (pp.obj == OBJ_TV2D) return ((pp.tv_rows + kTile - 1) / kTile) * ((pp.tv_cols + kTile - 1) / kTile);
+    long long g = (pp.n + kBlock * 4 - 1) / (kBlock * 4);
+    return (int)(g < 1 ? 1 : (g > 512 ? 512 : g));
+}
+
+// Sum over the `nt` tiles of slice s of value row v (rows of `nslots` slots),
+// valid in thread 0.
+template <int NV>
+__device__ inline void tile_sums(const double *__restrict__ part, long long nslots, int s, int nt, int v0, int nv,
+                                 double (&tot)[NV], double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
+    for (int b = threadIdx.x; b < nt; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nv) tot[k] += part[(long long)(v0 + k) * nslots + (long long)s * nt + b];
+    }
+    block_sum<NV>(tot, lds);
+}
+
+// Opening of a phase from the totals (sum g^2, f(x^k)).
+__device__ inline void open_phase_state(SliceState &S, const PertParams &pp, double gsq, double f)
+{
+    S.trials_it = 0;
+    S.accepts_it = 0;
+    S.s_acc = 0.0;
+    S.n_done = 0;
+    S.step_tried = 0;
+    S.applied = 0;
+    if (!S.live) {
+        S.phase = 0;
+        S.f_start = S.f_cur = nan64();
+        return;
+    }
+    if (pp.restart_every > 0 && S.k > 0 && (S.k % pp.restart_every) == 0) {
+        S.restarts += 1;
+        S.ell = S.restarts;
+    }
+    S.gn = sqrt(gsq);
+    S.f_start = S.f_cur = f;
+    if (!isfinite(f) || !isfinite(S.gn)) S.nonfinite = 1;
+    S.phase = (S.gn > 0.0 && isfinite(S.gn)) ? 1 : 0;
+}
+
+// Every workgroup: the state after the previous trial launch of slice s, in
+// sS (LDS).  The first trial in order whose objective does not exceed f_cur is
+// accepted; reading stops at the chunk holding it.
+__device__ inline void derive_decision(SliceState &sS, const PertParams &pp, const double *__restrict__ part_prev,
+                                       long long nslots, int s, int nt, double *lds)
+{
+    __shared__ int acc_t;
+    __shared__ double acc_f;
+    const int ntr = trial_width(sS, pp);
+    if (ntr == 0) return;
+    if (threadIdx.x == 0) acc_t = -1;
+    __syncthreads();
+    for (int t0 = 0; t0 < ntr; t0 += kTrialChunk) {
+        double tot[kTrialChunk];
+        tile_sums<kTrialChunk>(part_prev, nslots, s, nt, t0, min(kTrialChunk, ntr - t0), tot, lds);
+        if (threadIdx.x == 0) {
+            for (int w = 0; w < kTrialChunk && t0 + w < ntr; ++w) {
+                if (tot[w] <= sS.f_cur) {
+                    acc_t = t0 + w;
+                    acc_f = tot[w];
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (acc_t >= 0) break;
+    }
+    if (threadIdx.x == 0) {
+        SliceState &S = sS;
+        if (acc_t >= 0) {
+            S.s_acc = S.s_acc + trial_beta(pp, S.ell + acc_t);
+            S.f_cur = acc_f;
+            if (!isfinite(acc_f)) S.nonfinite = 1;
+            S.ell += acc_t + 1;
+            S.trials_it += acc_t + 1;
+            S.trials += acc_t + 1;
+            S.accepts_it += 1;
+            S.accepts += 1;
+            S.n_done += 1;
+            S.step_tried = 0;
+            if (S.n_done >= pp.n_red) S.phase = 0;
+        } else {
+            S.ell += ntr;
+            S.trials_it += ntr;
+            S.trials += ntr;
+            S.step_tried += ntr;
+            if (S.step_tried >= pp.max_trials) {
+                S.cap_hits += 1;
+                S.phase = 0;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Every workgroup: state of slice s at the start of this launch, in sS.
+// mode 0: the first trial launch (opens the phase from the gradient partials);
+// otherwise: the decision of the previous trial launch.
+__device__ inline void derive_state(SliceState &sS, const SliceState *__restrict__ st_in, const PertParams &pp,
+                                    int first, const double *__restrict__ part_prev, int s, int nt, double *lds)
+{
+    if (threadIdx.x == 0) sS = st_in[s];
+    __syncthreads();
+    const long long nslots = (long long)pp.B * nt;
+    if (first) {
+        double tot[2];
+        tile_sums<2>(part_prev, nslots, s, nt, 0, 2, tot, lds);
+        if (threadIdx.x == 0) open_phase_state(sS, pp, tot[0], tot[1]);
+        __syncthreads();
+    } else {
+        derive_decision(sS, pp, part_prev, nslots, s, nt, lds);
+    }
+}
+
+__device__ inline void publish_state(const SliceState &S, SliceState *__restrict__ st_out, int s, bool applied_here)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        SliceState o = S;
+        if (applied_here) o.applied = 1;
+        st_out[s] = o;
+    }
+}
+
+// Whether this launch adds the accepted step to x (the phase is over).
+__device__ inline bool must_apply(const SliceState &S) { return S.live && !S.phase && !S.applied && S.s_acc != 0.0; }
+
+// -- TV2D: smoothed total variation on an R x C image, pixel (i,j) = unknown i*C + j.
+//    Terms at (i,j) for i <= R-2, j <= C-2: tau = sqrt(dx^2 + dy^2 + eps^2) with
+//    dx = X[i+1,j] - X[i,j], dy = X[i,j+1] - X[i,j].
+
+__device__ inline double tv_tau(double x00, double x10, double x01, double eps2)
+{
+    const double dx = x10 - x00, dy = x01 - x00;
+    return sqrt(dx * dx + dy * dy + eps2);
+}
+
+// Gradient (unless eval_only) and per-tile partials of ||g||^2 and f(x); the
+// tile carries a one-pixel halo on every side.
+__global__ __launch_bounds__(kBlock) void k_phase_tv(const float *__restrict__ x, float *__restrict__ g,
+                                                     const SliceState *__restrict__ st, PertParams pp, int eval_only,
+                                                     double *__restrict__ partials)
+{
+    __shared__ float tile[kTile + 2][kTile + 3];
+    __shared__ double lds[4 * 2];
+    const int s = blockIdx.y, B = pp.B;
+    const int R = pp.tv_rows, C = pp.tv_cols;
+    const int tiles_x = (C + kTile - 1) / kTile;
+    const int i0 = (blockIdx.x / tiles_x) * kTile, j0 = (blockIdx.x % tiles_x) * kTile;
+    const bool live = eval_only ? true : st[s].live != 0;
+    double v[2] = {0.0, 0.0}; // sum g^2, f
+    if (live) {
+        for (int e = threadIdx.x; e < (kTile + 2) * (kTile + 2); e += kBlock) {
+            const int li = e / (kTile + 2), lj = e % (kTile + 2);
+            const int gi = i0 - 1 + li, gj = j0 - 1 + lj;
+            float val = 0.f;
+            if (gi >= 0 && gi < R && gj >= 0 && gj < C) val = x[((long long)gi * C + gj) * B + s];
+            tile[li][lj] = val;
+        }
+        __syncthreads();
+        const int li = threadIdx.x / kTile, lj = threadIdx.x % kTile;
+        const int i = i0 + li, j = j0 + lj;
+        if (i < R && j < C) {
+#define XT(a, b) ((double)tile[(a) - i0 + 1][(b) - j0 + 1])
+            double gv = 0.0;
+            if (i <= R - 2 && j <= C - 2) {
+                const double x00 = XT(i, j), x10 = XT(i + 1, j), x01 = XT(i, j + 1);
+                const double tau = tv_tau(x00, x10, x01, pp.tv_eps2);
+                v[1] = tau;
+                if (tau > 0.0) gv -= ((x10 - x00) + (x01 - x00)) / tau;
+            }
+            if (i >= 1 && j <= C - 2) { // term (i-1, j): this pixel is its +1 row neighbour
+                const double x00 = XT(i - 1, j), x10 = XT(i, j), x01 = XT(i - 1, j + 1);
+                const double tau = tv_tau(x00, x10, x01, pp.tv_eps2);
+                if (tau > 0.0) gv += (x10 - x00) / tau;
+            }
+            if (j >= 1 && i <= R - 2) { // term (i, j-1): this pixel is its +1 column neighbour
+                const double x00 = XT(i, j - 1), x10 = XT(i + 1, j - 1), x01 = XT(i, j);
+                const double tau = tv_tau(x00, x10, x01, pp.tv_eps2);
+                if (tau > 0.0) gv += (x01 - x00) / tau;
+            }
+#undef XT
+            if (!eval_only) {
+                const float gf = (float)gv;
+                g[((long long)i * C + j) * B + s] = gf;
+                v[0] = (double)gf * (double)gf;
+            }
+        }
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const long long nslots = (long long)gridDim.x * gridDim.y, slot = (long long)s * gridDim.x + blockIdx.x;
+        partials[slot] = v[0];
+        partials[nslots + slot] = v[1];
+    }
+}
+
+// Squared norm (g = 2x) and linear objective (g = c) versions.
+__global__ __launch_bounds__(kBlock) void k_phase_flat(const float *__restrict__ x, float *__restrict__ g,
+                                                       const float *__restrict__ lin_c,
+                                                       const SliceState *__restrict__ st, PertParams pp,
+                                                       int eval_only, double *__restrict__ partials)
+{
+    __shared__ double lds[4 * 2];
+    const int s = blockIdx.y, B = pp.B;
+    const bool live = eval_only ? true : st[s].live != 0;
+    double v[2] = {0.0, 0.0};
+    if (live) {
+        for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < pp.n; j += (long long)gridDim.x * kBlock) {
+            const double xj = (double)x[j * B + s];
+            if (pp.obj == OBJ_SQNORM) {
+                v[1] += xj * xj;
+                if (!eval_only) {
+                    const float gf = (float)(2.0 * xj);
+                    g[j * B + s] = gf;
+                    v[0] += (double)gf * (double)gf;
+                }
+            } else { // OBJ_LINEAR
+                const double cj = (double)lin_c[j];
+                v[1] += cj * xj;
+                v[0] += cj * cj;
+            }
+        }
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const long long nslots = (long long)gridDim.x * gridDim.y, slot = (long long)s * gridDim.x + blockIdx.x;
+        partials[slot] = v[0];
+        partials[nslots + slot] = v[1];
+    }
+}
+
+// Objective per slice from k_phase_* partials in eval_only mode (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_eval_objective(SliceState *__restrict__ st, PertParams pp,
+                                                           const double *__restrict__ partials, int nt,
+                                                           double *__restrict__ out)
+{
+    __shared__ double lds[4 * 2];
+    for (int s = 0; s < pp.B; ++s) {
+        double tot[2];
+        tile_sums<2>(partials, (long long)pp.B * nt, s, nt, 0, 2, tot, lds);
+        if (threadIdx.x == 0) {
+            out[s] = tot[1];
+            if (!isfinite(tot[1])) st[s].nonfinite = 1;
+        }
+    }
+}
+
+// Trial launch for TV: derive the state, then each thread owns one pixel's
+// term tau(i,j) and evaluates it at z = x + (s_acc + beta_t) v for every trial
+// t of this launch (one partial per trial per tile); or, once the phase is
+// over, add s_acc v to the tile.
+__global__ __launch_bounds__(kBlock) void k_trial_tv(float *__restrict__ x, const float *__restrict__ g,
+                                                     const SliceState *__restrict__ st_in,
+                                                     SliceState *__restrict__ st_out, PertParams pp, int first,
+                                                     int evaluate, const double *__restrict__ part_prev,
+                                                     double *__restrict__ part_out)
+{
+    __shared__ float tx[kTile + 1][kTile + 2];
+    __shared__ float tg[kTile + 1][kTile + 2];
+    __shared__ double coef[1024];
+    __shared__ double lds[4 * kTrialChunk];
+    __shared__ SliceState sS;
+    const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
+    const int R = pp.tv_rows, C = pp.tv_cols;
+    const int tiles_x = (C + kTile - 1) / kTile;
+    const int i0 = (blockIdx.x / tiles_x) * kTile, j0 = (blockIdx.x % tiles_x) * kTile;
+    derive_state(sS, st_in, pp, first, part_prev, s, nt, lds);
+    const SliceState S = sS;
+    const int li = threadIdx.x / kTile, lj = threadIdx.x % kTile;
+    const int i = i0 + li, j = j0 + lj;
+    if (must_apply(S)) {
+        if (i < R && j < C) {
+            const long long e = ((long long)i * C + j) * B + s;
+            x[e] = (float)((double)x[e] + S.s_acc * (-(double)g[e] * (1.0 / S.gn)));
+        }
+        publish_state(S, st_out, s, true);
+        return;
+    }
+    publish_state(S, st_out, s, false);
+    const int ntr = evaluate ? trial_width(S, pp) : 0;
+    if (ntr == 0) return;
+    const long long nslots = (long long)B * nt, slot = (long long)s * nt + blockIdx.x;
+    const double inv_gn = 1.0 / S.gn;
+    for (int t = threadIdx.x; t < ntr; t += kBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
+    for (int e = threadIdx.x; e < (kTile + 1) * (kTile + 1); e += kBlock) {
+        const int ai = e / (kTile + 1), aj = e % (kTile + 1);
+        const int gi = i0 + ai, gj = j0 + aj;
+        float xv = 0.f, gv = 0.f;
+        if (gi < R && gj < C) {
+            xv = x[((long long)gi * C + gj) * B + s];
+            gv = g[((long long)gi * C + gj) * B + s];
+        }
+        tx[ai][aj] = xv;
+        tg[ai][aj] = gv;
+    }
+    __syncthreads();
+    const bool has_term = (i <= R - 2) && (j <= C - 2);
+    double x00 = 0, x10 = 0, x01 = 0, v00 = 0, v10 = 0, v01 = 0;
+    if (has_term) {
+        x00 = tx[li][lj]; x10 = tx[li + 1][lj]; x01 = tx[li][lj + 1];
+        v00 = -(double)tg[li][lj] * inv_gn;
+        v10 = -(double)tg[li + 1][lj] * inv_gn;
+        v01 = -(double)tg[li][lj + 1] * inv_gn;
+    }
+    for (int t0 = 0; t0 < ntr; t0 += kTrialChunk) {
+        double acc[kTrialChunk];
+#pragma unroll
+        for (int w = 0; w < kTrialChunk; ++w) {
+            acc[w] = 0.0;
+            if (has_term && t0 + w < ntr) {
+                const double cf = coef[t0 + w];
+                const double z00 = x00 + cf * v00, z10 = x10 + cf * v10, z01 = x01 + cf * v01;
+                acc[w] = tv_tau(z00, z10, z01, pp.tv_eps2);
+            }
+        }
+        block_sum<kTrialChunk>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 0; w < kTrialChunk; ++w)
+                if (t0 + w < ntr) part_out[(long long)(t0 + w) * nslots + slot] = acc[w];
+        }
+    }
+}
+
+// Trial launch for the squared norm and the linear objective (flat vectors).
+__global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, const float *__restrict__ g,
+                                                       const SliceState *__restrict__ st_in,
+                                                       SliceState *__restrict__ st_out, PertParams pp, int first,
+                                                       int evaluate, const double *__restrict__ part_prev,
+                                                       double *__restrict__ part_out)
+{
+    __shared__ double coef[1024];
+    __shared__ double lds[4 * kTrialChunk];
+    __shared__ SliceState sS;
+    const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
+    const bool lin = pp.obj == OBJ_LINEAR;
+    derive_state(sS, st_in, pp, first, part_prev, s, nt, lds);
+    const SliceState S = sS;
+    if (must_apply(S)) {
+        const double inv_gn = 1.0 / S.gn;
+        for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < pp.n; j += (long long)gridDim.x * kBlock) {
+            const double gj = lin ? (double)g[j] : (double)g[j * B + s];
+            x[j * B + s] = (float)((double)x[j * B + s] + S.s_acc * (-gj * inv_gn));
+        }
+        publish_state(S, st_out, s, true);
+        return;
+    }
+    publish_state(S, st_out, s, false);
+    const int ntr = evaluate ? trial_width(S, pp) : 0;
+    if (ntr == 0) return;
+    const long long nslots = (long long)B * nt, slot = (long long)s * nt + blockIdx.x;
+    const double inv_gn = 1.0 / S.gn;
+    for (int t = threadIdx.x; t < ntr; t += kBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
+    __syncthreads();
+    for (int t0 = 0; t0 < ntr; t0 += kTrialChunk) {
+        double acc[kTrialChunk];
+#pragma unroll
+        for (int w = 0; w < kTrialChunk; ++w) acc[w] = 0.0;
+        for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < pp.n; j += (long long)gridDim.x * kBlock) {
+            const double xj = (double)x[j * B + s];
+            const double gj = lin ? (double)g[j] : (double)g[j * B + s];
+            const double vj = -gj * inv_gn;
+#pragma unroll
+            for (int w = 0; w < kTrialChunk; ++w) {
+                if (t0 + w < ntr) {
+                    const double z = xj + coef[t0 + w] * vj;
+                    acc[w] += lin ? gj * z : z * z;
+                }
+            }
+        }
+        block_sum<kTrialChunk>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int w = 0; w < kTrialChunk; ++w)
+                if (t0 + w < ntr) part_out[(long long)(t0 + w) * nslots + slot] = acc[w];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+
+template <typename VT>
+__device__ inline float stored_value(const void *val, long long p);
+template <>
+__device__ inline float stored_value<float>(const void *val, long long p) { return static_cast<const float *>(val)[p]; }
+template <>
+__device__ inline float stored_value<Bf16Tag>(const void *val, long long p)
+{
+    return __uint_as_float((uint32_t) static_cast<const uint16_t *>(val)[p] << 16);
+}
+template <>
+__device__ inline float stored_value<F16Tag>(const void *val, long long p)
+{
+    return __half2float(__ushort_as_half(static_cast<const uint16_t *>(val)[p]));
+}
+
+// q_i = ||a_i||^2 in float64 from the stored (possibly rounded) values; one wave per row
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_rownorm(SpView A, double *__restrict__ q)
+{
+    const int lane = threadIdx.x & 63;
+    const long long row = (long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (row >= A.rows) return;
+    const int beg = A.ptr[row], end = A.ptr[row + 1];
+    double s = 0.0;
+    for (int p = beg + lane; p < end; p += 64) {
+        const double a = (double)stored_value<VT>(A.val, p) * (double)A.vscale_inv;
+        s += a * a;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) q[row] = s;
+}
+
+__global__ void k_make_D(const double *__restrict__ q, const double *__restrict__ w, float *__restrict__ D, long long m)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x)
+        D[i] = q[i] > 0.0 ? (float)(w[i] / q[i]) : 0.f;
+}
+
+__global__ void k_to_bf16(const float *__restrict__ src, uint16_t *__restrict__ dst, long long count)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = __bfloat16_as_ushort(__float2bfloat16(src[i]));
+}
+
+__global__ void k_to_f16(const float *__restrict__ src, uint16_t *__restrict__ dst, long long count, float scale)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = __half_as_ushort(__float2half_rn(src[i] * scale));
+}
+
+__global__ void k_fill(float *__restrict__ p, float v, long long count)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_init_state(SliceState *st, int B)
+{
+    const int s = threadIdx.x;
+    if (s >= B) return;
+    SliceState S;
+    S.f_cur = S.f_start = __longlong_as_double(0x7ff8000000000000LL);
+    S.gn = 0.0;
+    S.s_acc = 0.0;
+    S.prox = __longlong_as_double(0x7ff8000000000000LL);
+    S.k = 0;
+    S.k_end = 0x7fffffffffffffffLL;
+    S.ell = 0;
+    S.restarts = 0;
+    S.trials = S.accepts = S.cap_hits = 0;
+    S.n_done = 0;
+    S.phase = 0;
+    S.step_tried = 0;
+    S.trials_it = S.accepts_it = 0;
+    S.live = 1;
+    S.applied = 0;
+    S.enabled = 1;
+    S.nonfinite = 0;
+    st[s] = S;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned grid_for(long long work, int per_block, unsigned cap)
+{
+    long long g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+hipError_t launch_rownorm(const SpView &A, int vk, double *q, hipStream_t s)
+{
+    const unsigned grid = grid_for(A.rows, kBlock / 64, 1u << 30);
+    if (vk == VK_F32) hipLaunchKernelGGL(k_rownorm<float>, dim3(grid), dim3(kBlock), 0, s, A, q);
+    else if (vk == VK_BF16) hipLaunchKernelGGL(k_rownorm<Bf16Tag>, dim3(grid), dim3(kBlock), 0, s, A, q);
+    else hipLaunchKernelGGL(k_rownorm<F16Tag>, dim3(grid), dim3(kBlock), 0, s, A, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_D(const double *q, const double *w, float *D, int64_t m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_make_D, dim3(grid_for(m, kBlock, 4096)), dim3(kBlock), 0, s, q, w, D, (long long)m);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s, src, dst, (long long)count);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f16, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s, src, dst, (long long)count,
+                       scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(count, kBlock, 4096)), dim3(kBlock), 0, s, p, v, (long long)count);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(SliceState *st, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, B);
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t pass1_vec(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
+                            const float *upper, const float *D, float *c, const SliceState *st, int query,
+                            double *partials, hipStream_t s)
+{
+    const dim3 grid(cfg.grid), block(kBlock);
+    switch (cfg.lpr) {
+    case 4: hipLaunchKernelGGL((k_pass1<4, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 8: hipLaunchKernelGGL((k_pass1<8, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 16: hipLaunchKernelGGL((k_pass1<16, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 32: hipLaunchKernelGGL((k_pass1<32, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 64: hipLaunchKernelGGL((k_pass1<64, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, int vk, const float *x, const float *lower,
+                        const float *upper, const float *D, float *c, const SliceState *st, int B, int query,
+                        double *partials, hipStream_t s)
+{
+    if (B != 1 || cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
+    if (vk == VK_F32) {
+        if (cfg.vec == 8) return pass1_vec<float, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        return pass1_vec<float, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    }
+    if (vk == VK_BF16) {
+        if (cfg.vec == 8) return pass1_vec<Bf16Tag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        return pass1_vec<Bf16Tag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    }
+    if (cfg.vec == 8) return pass1_vec<F16Tag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    return pass1_vec<F16Tag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+}
+
+template <typename VT, int VEC>
+static hipError_t pass2_vec(const PassCfg &cfg, const SpView &At, const float *c, float *x, const float *lo,
+                            const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
+                            const double *part1, int nparts1, Hist h, hipStream_t s)
+{
+    const dim3 grid(cfg.grid), block(kBlock);
+#define SMX_P2(L) hipLaunchKernelGGL((k_pass2<L, VEC, VT>), grid, block, 0, s, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h)
+    switch (cfg.lpr) {
+    case 4: SMX_P2(4); break;
+    case 8: SMX_P2(8); break;
+    case 16: SMX_P2(16); break;
+    case 32: SMX_P2(32); break;
+    case 64: SMX_P2(64); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_P2
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, int vk, const float *c, float *x, const float *lo,
+                        const float *hi, float lambda, const SliceState *st_in, SliceState *st_out, int B,
+                        const double *part1, int nparts1, Hist h, hipStream_t s)
+{
+    if (B != 1 || cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid)
+        return hipErrorInvalidValue;
+    if (vk == VK_F32) {
+        if (cfg.vec == 8) return pass2_vec<float, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<float, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    }
+    if (vk == VK_BF16) {
+        if (cfg.vec == 8) return pass2_vec<Bf16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<Bf16Tag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    }
+    if (cfg.vec == 8) return pass2_vec<F16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    return pass2_vec<F16Tag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+}
+
+hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_query_prox, dim3(1), dim3(kBlock), 0, s, st, B, partials, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase(const PertParams &pp, const float *x, float *g, const float *lin_c, const SliceState *st,
+                        int eval_only, double *partials, hipStream_t s)
+{
+    const dim3 grid(phase_grid(pp), pp.B), block(kBlock);
+    if (pp.obj == OBJ_TV2D)
+        hipLaunchKernelGGL(k_phase_tv, grid, block, 0, s, x, g, st, pp, eval_only, partials);
+    else
+        hipLaunchKernelGGL(k_phase_flat, grid, block, 0, s, x, g, lin_c, st, pp, eval_only, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_objective(SliceState *st, const PertParams &pp, const double *partials, double *out,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval_objective, dim3(1), dim3(kBlock), 0, s, st, pp, partials, phase_grid(pp), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial(const PertParams &pp, float *x, const float *g, const SliceState *st_in, SliceState *st_out,
+                        int first, int evaluate, const double *part_prev, double *part_out, hipStream_t s)
+{
+    if (pp.max_trials < 1 || pp.max_trials > 1024) return hipErrorInvalidValue;
+    const dim3 grid(phase_grid(pp), pp.B), block(kBlock);
+    if (pp.obj == OBJ_TV2D)
+        hipLaunchKernelGGL(k_trial_tv, grid, block, 0, s, x, g, st_in, st_out, pp, first, evaluate, part_prev, part_out);
+    else
+        hipLaunchKernelGGL(k_trial_flat, grid, block, 0, s, x, g, st_in, st_out, pp, first, evaluate, part_prev,
+                           part_out);
+    return hipGetLastError();
+}
+
+} // namespace smx

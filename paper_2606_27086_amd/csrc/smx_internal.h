@@ -1,0 +1,120 @@
+// Internal declarations shared by the kernels and the host runtime of libsmx.
+// Not part of the public ABI (include/smx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace smx {
+
+constexpr int kBlock = 256;    // threads per workgroup for every kernel (4 waves of 64)
+constexpr int kRowAlign = 8;   // entries of every row/column start at a multiple of this
+constexpr int kTrialChunk = 8; // trial steps evaluated per register batch
+constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
+
+enum ValKind : int { VK_F32 = 0, VK_BF16 = 1, VK_F16 = 2 };
+enum ObjKind : int { OBJ_NONE = 0, OBJ_SQNORM = 1, OBJ_TV2D = 2, OBJ_LINEAR = 3 };
+
+// Device view of one row-aligned sparse layout: the CSR of A (pass 1) or the
+// CSR of A^T (pass 2).  Row r owns entries [ptr[r], ptr[r+1]); both ends are
+// multiples of kRowAlign, padding entries hold value 0 and a valid index.
+struct SpView {
+    const int32_t *ptr;
+    const int32_t *idx;
+    const void *val; // float, bf16 bits (uint16) or binary16, by ValKind
+    int64_t rows;
+    float vscale_inv; // operator value = stored value * vscale_inv
+};
+
+// Per-slice iteration state, resident on the device.  Only the one-workgroup
+// kernels (phase opening, trial decision, end of iteration) write it.
+struct SliceState {
+    double f_cur;   // objective at the current point of the perturbation phase
+    double f_start; // objective at x^k (NaN when no phase ran this iteration)
+    double gn;      // norm of the gradient of this phase
+    double s_acc;   // accepted step length along v in this phase (z = x + s_acc v)
+    double prox;    // proximity at the last feasibility step's input point
+    long long k;      // outer iterations completed
+    long long k_end;  // iterations stop advancing here (budget)
+    long long ell;    // exponent of the next trial step
+    long long restarts;
+    long long trials;   // totals
+    long long accepts;
+    long long cap_hits;
+    int n_done;     // reduction steps completed in this phase
+    int phase;      // 1 while the phase is still trying
+    int step_tried; // trials spent in the current reduction step
+    int trials_it;  // this iteration
+    int accepts_it;
+    int live;       // the current iteration runs (enabled and k < k_end)
+    int applied;    // the accepted step of this phase has been added to x
+    int enabled;    // slice participates at all
+    int nonfinite;  // a non-finite proximity or objective was seen
+};
+
+struct PertParams {
+    int obj;
+    int B;
+    long long n;
+    int tv_rows, tv_cols;
+    double tv_eps2;
+    double gamma, alpha;
+    int n_red, restart_every, max_trials;
+    int first_width; // trials evaluated by a trial launch that starts a reduction step
+};
+
+struct Hist {
+    double *prox;
+    double *f_start;
+    double *f_end;
+    int *trials;
+    int *accepts;
+    long long cap;
+};
+
+struct PassCfg {
+    int lpr;  // lanes per row: 4, 8, 16, 32 or 64
+    int vec;  // entries per lane per load: 4 or 8
+    int grid; // workgroups
+};
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_rownorm(const SpView &A, int vk, double *q, hipStream_t s);
+hipError_t launch_make_D(const double *q, const double *w, float *D, int64_t m, hipStream_t s);
+hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
+hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float scale, hipStream_t s);
+hipError_t launch_init_state(SliceState *st, int B, hipStream_t s);
+hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s);
+
+constexpr int kMaxPassGrid = 4096; // workgroups of a pass kernel (one proximity partial each)
+
+// pass 1: r = A x, t = clip(r) - r, c = D t, one proximity partial per
+// workgroup (query != 0: every slice runs, whatever its state)
+hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, int vk, const float *x, const float *lower,
+                        const float *upper, const float *D, float *c, const SliceState *st, int B, int query,
+                        double *partials, hipStream_t s);
+// pass 2: x = clip(x + lambda A^T c, lo, hi); workgroup 0 also ends the
+// iteration (proximity from pass 1's partials, history, k + 1) into st_out
+hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, int vk, const float *c, float *x, const float *lo,
+                        const float *hi, float lambda, const SliceState *st_in, SliceState *st_out, int B,
+                        const double *part1, int nparts1, Hist h, hipStream_t s);
+// query: proximity from pass 1's partials into out[B]
+hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s);
+
+int phase_grid(const PertParams &pp);
+// gradient and per-tile partials [2][B*tiles] of ||g||^2 and f(x) (eval_only: no gradient)
+hipError_t launch_phase(const PertParams &pp, const float *x, float *g, const float *lin_c, const SliceState *st,
+                        int eval_only, double *partials, hipStream_t s);
+// f(x) per slice from eval_only phase partials into out[B]
+hipError_t launch_eval_objective(SliceState *st, const PertParams &pp, const double *partials, double *out,
+                                 hipStream_t s);
+// One trial launch: derives the state (first: the phase opening from the
+// gradient partials; otherwise the previous launch's decision from its trial
+// partials), then with `evaluate` the next batch of trial steps (partials
+// [max_trials][B*tiles] into part_out), or adds the accepted step to x once
+// the phase is over.  The derived state goes to st_out.
+hipError_t launch_trial(const PertParams &pp, float *x, const float *g, const SliceState *st_in, SliceState *st_out,
+                        int first, int evaluate, const double *part_prev, double *part_out, hipStream_t s);
+
+} // namespace smx

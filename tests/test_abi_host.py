@@ -1,0 +1,106 @@
+"""C ABI contract checks that need no GPU: the library loads, exports every
+entry point include/smx.h declares, and rejects invalid host input before it
+touches the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(smx_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def smx():
+    import paper_2606_27086_amd as smx
+
+    if not os.path.exists(smx.LIB_PATH):
+        pytest.fail("libsmx.so is not built: run __graft_entry__.build()")
+    smx.lib()
+    return smx
+
+
+def test_exports_every_declared_symbol(smx):
+    declared = _declared()
+    assert len(declared) >= 15
+    raw = C.CDLL(smx.LIB_PATH)
+    for name in declared:
+        assert hasattr(raw, name), name
+    assert sorted(smx.EXPORTS) == declared
+
+
+def test_version(smx):
+    assert smx.version() == (0, 1)
+
+
+def test_footprint_without_device(smx):
+    b1 = smx.footprint(1000, 500, 20000, "f32")
+    b2 = smx.footprint(1000, 500, 20000, "bf16", keep_f32=False)
+    b3 = smx.footprint(1000, 500, 20000, "bf16", keep_f32=True)
+    assert b2 < b1 < b3
+    with pytest.raises(smx.SmxError) as e:
+        smx.footprint(0, 5, 5)
+    assert e.value.code == smx.EINVAL
+
+
+def _csr_call(smx, m, n, rp, ci, val, storage=0):
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    val = np.ascontiguousarray(val, np.float32)
+    csr = smx.Csr(m, n, ci.size, rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                  val.ctypes.data if val.size else None, 0)
+    h = C.c_void_p()
+    rc = smx.lib().smx_operator_create(C.byref(csr), storage, 1, None, C.byref(h))
+    return rc, smx.lib().smx_last_error().decode(), h
+
+
+@pytest.mark.parametrize(
+    "case",
+    [
+        ("m0", 0, 3, [0], [], []),
+        ("nnz_mismatch", 2, 3, [0, 1, 3], [0, 1], [1.0, 2.0]),
+        ("decreasing", 2, 3, [0, 2, 1], [0, 1], [1.0, 2.0]),
+        ("col_range", 2, 3, [0, 1, 2], [0, 3], [1.0, 2.0]),
+        ("col_negative", 2, 3, [0, 1, 2], [0, -1], [1.0, 2.0]),
+        ("nan_value", 2, 3, [0, 1, 2], [0, 1], [1.0, np.nan]),
+        ("rowptr0", 2, 3, [1, 1, 2], [0, 1], [1.0, 2.0]),
+    ],
+)
+def test_invalid_csr_rejected_on_host(smx, case):
+    name, m, n, rp, ci, val = case
+    rc, msg, h = _csr_call(smx, m, n, rp, ci, val)
+    assert rc == smx.EINVAL, (name, rc, msg)
+    assert msg
+    assert not h.value
+
+
+def test_bad_storage_rejected(smx):
+    rc, msg, _ = _csr_call(smx, 2, 2, [0, 1, 2], [0, 1], [1.0, 2.0], storage=7)
+    assert rc == smx.EINVAL and "storage" in msg
+
+
+def test_null_arguments(smx):
+    L = smx.lib()
+    assert L.smx_operator_create(None, 0, 1, None, None) == smx.EINVAL
+    assert L.smx_run(None, 3, 0) == smx.EINVAL
+    assert L.smx_query(None, None, None) == smx.EINVAL
+    assert L.smx_problem_destroy(None) == smx.OK
+    assert L.smx_operator_destroy(None) == smx.OK
+    assert L.smx_version(None, None) == smx.EINVAL
+
+
+def test_binding_has_no_oracle_dependency():
+    """The product binding never imports the oracle package."""
+    src = open(os.path.join(ROOT, "paper_2606_27086_amd", "__init__.py")).read()
+    assert "oracle" not in src
+    for f in os.listdir(os.path.join(ROOT, "paper_2606_27086_amd", "csrc")):
+        text = open(os.path.join(ROOT, "paper_2606_27086_amd", "csrc", f)).read()
+        assert "oracle" not in text and "liborc" not in text and "orc_" not in text

@@ -1,0 +1,344 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: the float32 path must match the oracle to a relative 1e-5 on the
+iterate (norm-wise), on every per-iteration proximity and on the final
+proximity and objective; the sequence of trial counts (the decisions of
+Algorithm 1) must match exactly.  The reduced-precision storage paths are
+compared with the oracle run on the same rounded operator (1e-5) and with the
+oracle on the float32 operator (2e-2 on proximity and objective).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def smx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2606_27086_amd as smx
+
+    smx.lib()
+    return smx
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def rel(a, b, floor=0.0):
+    return float(np.linalg.norm(np.asarray(a, float) - np.asarray(b, float)) / max(np.linalg.norm(b), floor, 1e-300))
+
+
+def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1):
+    p = smx.problem_from_workload(w, storage=storage, history_cap=K, refine_iters=refine_iters)
+    p.run(K, perturb=perturb, graph=graph)
+    p.sync()
+    x = p.get_x().cpu().numpy().astype(np.float64)
+    prox, obj = p.query()
+    h = p.history()
+    st, _ = p.get_state()
+    p.close()
+    return x, prox, obj, h, st
+
+
+def oracle_run(w, K, perturb=True, s=0, value_round=None, refine=0):
+    """Oracle run for slice s; with value_round, the first K-refine iterations
+    use the rounded operator and the last `refine` the float32 one."""
+    P32 = oracle.from_workload(w, s)
+    if value_round is None or refine >= K:
+        x, st, h = P32.run(w.x0[:, s], K, perturb=perturb)
+        return x, st, h, P32
+    Pr = oracle.from_workload(w, s, value_round=value_round)
+    x, st, h1 = Pr.run(w.x0[:, s], K - refine, perturb=perturb)
+    if refine == 0:
+        return x, st, h1, P32
+    x, st, h2 = P32.run(x, refine, perturb=perturb, state=st)
+    h = oracle.History(*(np.concatenate([a, b]) for a, b in zip(
+        (h1.prox, h1.f_start, h1.f_end, h1.trials, h1.accepts),
+        (h2.prox, h2.f_start, h2.f_end, h2.trials, h2.accepts))))
+    return x, st, h, P32
+
+
+def storage_deviation(w, K, perturb=True, s=0, value_round=None, refine=0):
+    """Deviation forced by float32 storage of the iterate alone: the oracle's
+    trajectory with x rounded to float32 after every iteration, against its
+    pure float64 trajectory (relative, for x, the proximity and the objective).
+    Every float32 path carries at least this much; TV amplifies it."""
+    P32 = oracle.from_workload(w, s)
+    Pr = P32 if value_round is None else oracle.from_workload(w, s, value_round=value_round)
+    x64, _, _, _ = oracle_run(w, K, perturb, s, value_round=value_round, refine=refine)
+    x = w.x0[:, s].astype(np.float32).astype(np.float64)
+    st = None
+    for k in range(K):
+        P = Pr if k < K - refine else P32
+        x, st, _ = P.run(x, 1, perturb=perturb, state=st)
+        x = x.astype(np.float32).astype(np.float64)
+    dx = rel(x, x64)
+    dp = abs(P32.proximity(x) - P32.proximity(x64)) / max(abs(P32.proximity(x64)), 1e-300)
+    df = abs(P32.objective(x) - P32.objective(x64)) / max(abs(P32.objective(x64)), 1e-300)
+    return dx, dp, df
+
+
+def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=None, refine_iters=-1,
+                 sensitive=False):
+    """End-to-end parity.  With sensitive=True (TV problems, whose gradient
+    amplifies rounding of the iterate), the iterate and proximity tolerances
+    are max(tol, 10 x the deviation float32 storage of the iterate alone
+    forces: the kernels store four float32 quantities per iteration, the
+    perturbed point, the gradient, the weighted residual and the iterate, where
+    the emulation rounds one), and the objective must agree to first order
+    with the iterate's difference: |df| <= 2 ||grad f|| ||dx|| + tol |f|.  The
+    strict per-iteration check is the lockstep test."""
+    say(f"{w.name} m={w.m} n={w.n} nnz={w.nnz} K={K} perturb={perturb} obj={w.obj} storage={storage}")
+    x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters)
+    refine = 0
+    if storage != "f32":
+        refine = refine_iters if refine_iters >= 0 else (K + 19) // 20
+    for s in range(w.B):
+        xo, sto, ho, P = oracle_run(w, K, perturb, s, value_round=value_round, refine=refine)
+        tx = tp = tol
+        r = rel(x[:, s], xo)
+        f_slack = 0.0
+        if sensitive:
+            dx, dp, df = storage_deviation(w, K, perturb, s, value_round=value_round, refine=refine)
+            tx, tp = max(tol, 10 * dx), max(tol, 10 * dp)
+            f_slack = 2.0 * np.linalg.norm(P.gradient(xo)) * np.linalg.norm(x[:, s] - xo)
+            print(f"  storage-only deviation x {dx:.2e} prox {dp:.2e} f {df:.2e}", flush=True)
+        print(f"  slice {s}: iterate rel err {r:.3e} (tol {tx:.1e})", flush=True)
+        assert np.array_equal(h["trials"][:, s], ho.trials), "trial sequence differs"
+        assert np.array_equal(h["accepts"][:, s], ho.accepts), "accept sequence differs"
+        assert r <= tx, f"slice {s}: iterate rel err {r:.3e}"
+        assert st[s]["ell"] == sto.ell and st[s]["restarts"] == sto.restarts and st[s]["k"] == K
+        assert st[s]["cap_hits"] == sto.cap_hits
+        pfloor = 1e-6 * max(abs(ho.prox[0]), 1e-300)
+        np.testing.assert_allclose(h["prox"][:, s], ho.prox, rtol=tp, atol=pfloor)
+        po, fo = P.proximity(xo), P.objective(xo)
+        assert abs(prox[s] - po) <= tp * max(abs(po), pfloor), (prox[s], po)
+        assert abs(obj[s] - fo) <= f_slack + tol * max(abs(fo), 1e-12), (obj[s], fo, f_slack)
+    return x, h
+
+
+# ---------------------------------------------------------------------------
+# float32 path
+# ---------------------------------------------------------------------------
+
+def test_dense_consistent(smx):
+    w = W.dense_small()
+    check_parity(smx, w, w.K)
+
+
+def test_dense_unperturbed_consistent_proximity_decreases(smx):
+    w = W.dense_small()
+    _, h = check_parity(smx, w, 60, perturb=False)
+    d = np.diff(h["prox"][:, 0])
+    assert np.all(d <= 1e-6 * h["prox"][0, 0])
+
+
+@pytest.mark.parametrize("obj", [W.OBJ_NONE, W.OBJ_SQNORM, W.OBJ_LINEAR, W.OBJ_TV2D])
+def test_random_sparse_edge_rows(smx, obj):
+    """Skewed row lengths, empty rows, two full-length rows, one-sided and
+    equality bands, restarts and two reduction steps."""
+    w = W.random_sparse(3000, 2000, 12, seed=40 + obj, empty_frac=0.08, long_rows=2, obj=obj,
+                        tv_shape=(40, 50), K=25)
+    check_parity(smx, w, w.K, perturb=obj != W.OBJ_NONE, sensitive=obj == W.OBJ_TV2D)
+
+
+def test_ct_small_tv(smx):
+    w = W.ct(N=48, n_angles=36, seed=7, K=60)
+    check_parity(smx, w, w.K, sensitive=True)
+
+
+def test_ct_small_tv_paper_parameters(smx):
+    w = W.ct(N=48, n_angles=36, seed=8, K=60, variant="paper")
+    check_parity(smx, w, w.K, sensitive=True)
+
+
+def lockstep(smx, w, K, tol=RTOL):
+    """Every iteration starts from the device's own iterate and state; the
+    oracle runs that one iteration from the same point.  The iterates must
+    agree to tol and the decisions (trials, accepts, ell) exactly."""
+    p = smx.problem_from_workload(w, history_cap=0)
+    P = oracle.from_workload(w)
+    worst = 0.0
+    for k in range(K):
+        states, xk = p.get_state()
+        so = oracle.State()
+        for f in ("k", "ell", "restarts", "trials", "accepts", "cap_hits"):
+            setattr(so, f, states[0][f])
+        xo, so1, ho = P.run(xk[:, 0].astype(np.float64), 1, state=so)
+        p.run(1)
+        states1, xg = p.get_state()
+        r = rel(xg[:, 0].astype(np.float64), xo)
+        worst = max(worst, r)
+        assert states1[0]["trials"] == so1.trials and states1[0]["accepts"] == so1.accepts, k
+        assert states1[0]["ell"] == so1.ell and states1[0]["restarts"] == so1.restarts, k
+        assert r <= tol, f"iteration {k}: rel err {r:.3e}"
+    p.close()
+    return worst
+
+
+def test_ct_small_tv_lockstep(smx):
+    w = W.ct(N=48, n_angles=36, seed=7, K=40, variant="paper")
+    say("ct48 lockstep (paper parameters)")
+    worst = lockstep(smx, w, w.K)
+    print(f"  worst per-iteration rel err {worst:.3e}", flush=True)
+
+
+def test_seismic_small_tv(smx):
+    w = W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=9, K=80, variant="paper")
+    check_parity(smx, w, w.K, sensitive=True)
+
+
+def test_seismic_small_tv_lockstep(smx):
+    w = W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=9, K=40, variant="paper")
+    say("seismic lockstep (paper parameters)")
+    worst = lockstep(smx, w, w.K)
+    print(f"  worst per-iteration rel err {worst:.3e}", flush=True)
+
+
+def test_rt_small_linear_infeasible(smx):
+    w = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=10, K=40)
+    assert w.meta["n_overlap"] > 0
+    check_parity(smx, w, w.K)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (37, 1), (5, 3)])
+def test_tiny_shapes(smx, shape):
+    m, n = shape
+    rng = np.random.default_rng(m * 100 + n)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    rp = np.arange(0, m * n + 1, n, dtype=np.int32)
+    ci = np.tile(np.arange(n, dtype=np.int32), m)
+    r = A.astype(np.float64) @ rng.uniform(0, 1, n)
+    w = W.Workload(name=f"tiny{m}x{n}", m=m, n=n, row_ptr=rp, col_idx=ci, val=A.reshape(-1),
+                   lower=(r - 0.1).astype(np.float32)[:, None], upper=(r + 0.1).astype(np.float32)[:, None],
+                   box_lo=np.zeros(n, np.float32), box_hi=np.ones(n, np.float32),
+                   x0=rng.uniform(0, 1, (n, 1)).astype(np.float32), obj=W.OBJ_SQNORM, gamma=0.3, alpha=0.9,
+                   n_red=2, K=15)
+    check_parity(smx, w, w.K)
+
+
+# ---------------------------------------------------------------------------
+# reduced-precision storage
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_lowp_matches_oracle_on_rounded_operator(smx, storage):
+    w = W.ct(N=48, n_angles=36, seed=11, K=40)
+    check_parity(smx, w, w.K, storage=storage, value_round=storage, sensitive=True)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_lowp_against_float_operator(smx, storage):
+    """Against the oracle on the float32 operator: proximity and objective
+    within 2e-2 after K iterations (with the float32 refinement tail)."""
+    w = W.ct(N=64, n_angles=48, seed=12, K=60)
+    say(f"{storage} vs float operator")
+    x, prox, obj, h, st = gpu_run(smx, w, w.K, storage=storage)
+    xo, sto, ho, P = oracle_run(w, w.K)
+    po, fo = P.proximity(xo), P.objective(xo)
+    assert abs(prox[0] - po) <= 2e-2 * abs(po)
+    assert abs(obj[0] - fo) <= 2e-2 * abs(fo)
+
+
+# ---------------------------------------------------------------------------
+# execution modes
+# ---------------------------------------------------------------------------
+
+def test_graph_replay_is_bitwise_eager(smx):
+    w = W.ct(N=48, n_angles=36, seed=13, K=37)
+    say("graph vs eager")
+    xe, pe, fe, he, _ = gpu_run(smx, w, w.K, graph=False)
+    xg, pg, fg, hg, _ = gpu_run(smx, w, w.K, graph=True)
+    assert np.array_equal(xe, xg)
+    assert np.array_equal(he["trials"], hg["trials"])
+    assert np.array_equal(he["prox"], hg["prox"])
+
+
+def test_repeat_is_bitwise(smx):
+    w = W.random_sparse(2000, 1500, 20, seed=14, obj=W.OBJ_TV2D, tv_shape=(30, 50), K=20)
+    say("repeat")
+    a = gpu_run(smx, w, w.K)
+    b = gpu_run(smx, w, w.K)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_checkpoint_resume_bitwise(smx):
+    w = W.ct(N=40, n_angles=30, seed=15, K=30, variant="paper")
+    say("checkpoint/resume")
+    xa, _, _, _, sa = gpu_run(smx, w, w.K)
+    p = smx.problem_from_workload(w, history_cap=0)
+    p.run(11)
+    p.sync()
+    states, x1 = p.get_state()
+    p.close()
+    q = smx.problem_from_workload(w, history_cap=0)
+    q.set_state(states, x1)
+    q.run(w.K - 11)
+    q.sync()
+    xb = q.get_x().cpu().numpy()
+    sb, _ = q.get_state()
+    q.close()
+    assert np.array_equal(xa, xb.astype(np.float64))
+    assert sa == sb
+
+
+def test_query_at_device_iterate(smx):
+    """Proximity and objective evaluated by the kernels at the device's own
+    iterate agree with the oracle evaluated at that same point."""
+    w = W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=16, K=30)
+    say("query at device iterate")
+    x, prox, obj, _, _ = gpu_run(smx, w, w.K)
+    P = oracle.from_workload(w)
+    assert prox[0] == pytest.approx(P.proximity(x[:, 0]), rel=2e-6)
+    assert obj[0] == pytest.approx(P.objective(x[:, 0]), rel=2e-6)
+
+
+def test_timing_counts_launches(smx):
+    w = W.ct(N=32, n_angles=24, seed=17, K=12)
+    p = smx.problem_from_workload(w)
+    p.set_timing(True)
+    p.run(12)
+    p.sync()
+    t1, t2, n = p.timing()
+    p.close()
+    assert n == 12 and t1 > 0 and t2 > 0
+
+
+def test_invalid_problem_args(smx):
+    w = W.ct(N=16, n_angles=8, seed=18, K=5)
+    op = smx.Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val)
+    bad = [
+        dict(lam=0.0), dict(lam=2.5), dict(alpha=1.0), dict(gamma=0.0), dict(n_red=0), dict(max_trials=0),
+        dict(tv_rows=5),
+    ]
+    for kw in bad:
+        args = dict(lower=w.lower, upper=w.upper, obj=W.OBJ_TV2D, tv_rows=16, tv_cols=16, tv_eps=1e-3)
+        args.update(kw)
+        with pytest.raises(smx.SmxError) as e:
+            smx.Problem(op, **args)
+        assert e.value.code == smx.EINVAL, kw
+    lo = w.lower.copy()
+    lo[3, 0] = w.upper[3, 0] + 1
+    with pytest.raises(smx.SmxError):
+        smx.Problem(op, lower=lo, upper=w.upper)
+    with pytest.raises(smx.SmxError):
+        smx.Problem(op, lower=w.lower, upper=w.upper, obj=W.OBJ_LINEAR)
+    op.close()
+
+
+# ---------------------------------------------------------------------------
+# full size CT (the benchmarked configuration)
+# ---------------------------------------------------------------------------
+
+def test_ct256_full_bench_configuration(smx):
+    w = W.ct(N=256, seed=2, K=200)
+    check_parity(smx, w, w.K, sensitive=True)
