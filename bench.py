@@ -46,10 +46,11 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_variant(smx, w, storage, steps, warmup, graph=True):
+def time_variant(smx, w, storage, steps, warmup, graph=True, tune=True):
     import torch
 
     p = smx.problem_from_workload(w, storage=storage, refine_iters=0)
+    shapes = p.autotune(reps=10) if tune else p.describe()
     # warm-up (also captures the graphs)
     p.run(warmup, perturb=True, graph=graph)
     p.sync()
@@ -70,7 +71,7 @@ def time_variant(smx, w, storage, steps, warmup, graph=True):
     p.set_timing(False)
     p.close()
     return dict(seconds=dt, it_s=steps / dt, ms_per_step=1e3 * dt / steps, pass1_ms=t1, pass2_ms=t2, launches=n,
-                prox=float(prox[0]), obj=float(obj[0]))
+                prox=float(prox[0]), obj=float(obj[0]), shapes=shapes)
 
 
 def cpu_baseline(w, K):
@@ -95,6 +96,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--storages", default="f32,bf16")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the method's single-GPU path is what is built "
@@ -111,7 +113,7 @@ def main():
     graph = not args.no_graph
     results = {}
     for st in args.storages.split(","):
-        results[st] = time_variant(smx, w, st, args.steps, args.warmup, graph=graph)
+        results[st] = time_variant(smx, w, st, args.steps, args.warmup, graph=graph, tune=not args.no_tune)
     main_r = results["f32"] if "f32" in results else next(iter(results.values()))
     main_st = "f32" if "f32" in results else next(iter(results))
     vb = {"f32": 4, "bf16": 2, "f16": 2}[main_st]
@@ -133,7 +135,7 @@ def main():
                             pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
                             pass1_gbs=round(c1 / (r["pass1_ms"] * 1e-3) / 1e9, 1),
                             pass2_gbs=round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1),
-                            prox=r["prox"], obj=r["obj"])
+                            prox=r["prox"], obj=r["obj"], launch=r["shapes"].get(st))
     cpu = None
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, min(args.steps, w.K))

@@ -211,6 +211,18 @@ int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x)
 /* Shape of the problem. */
 int smx_problem_dims(const smx_problem *p, int64_t *m, int64_t *n, int64_t *nnz, int32_t *B);
 
+/* Autotuner (batching pattern): times candidate launch shapes of both passes
+ * (row blocks streamed through LDS, or 8..64 lanes per row with 4 or 8
+ * entries per load, at several grid sizes) on this problem's operator, `reps`
+ * launches each, and keeps the fastest for later runs.  Runs on scratch
+ * copies, so the iterate, state and history are unchanged.  Synchronises.
+ * Results do not depend on the shape beyond float64 summation order. */
+int smx_autotune(smx_problem *p, int32_t reps);
+
+/* JSON description of the launch shapes in use (NUL-terminated, truncated to
+ * cap bytes); *need (if non-NULL) receives the full size. */
+int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need);
+
 /* Mean device time (milliseconds) per launch of the two passes recorded by
  * the last smx_run made with SMX_RUN_GRAPH clear and timing enabled through
  * smx_set_timing; zero launches give 0. */

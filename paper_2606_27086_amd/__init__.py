@@ -46,6 +46,8 @@ EXPORTS = [
     "smx_problem_dims",
     "smx_set_timing",
     "smx_get_timing",
+    "smx_autotune",
+    "smx_describe",
 ]
 
 
@@ -138,6 +140,8 @@ def lib() -> C.CDLL:
     L.smx_problem_dims.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]
     L.smx_set_timing.argtypes = [vp, i32]
     L.smx_get_timing.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i64)]
+    L.smx_autotune.argtypes = [vp, i32]
+    L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     for name in EXPORTS:
         if name != "smx_last_error":
             getattr(L, name).restype = C.c_int
@@ -318,6 +322,20 @@ class Problem:
         """Iteration state back to k = ell = restarts = 0 and the iterate to x0."""
         zero = dict(k=0, ell=0, restarts=0, trials=0, accepts=0, cap_hits=0)
         self.set_state([zero] * self.B, np.asarray(x0, np.float32).reshape(self.n, self.B))
+
+    def autotune(self, reps: int = 10) -> dict:
+        """Pick the fastest launch shapes of both passes on this operator."""
+        check(lib().smx_autotune(self.handle, int(reps)))
+        return self.describe()
+
+    def describe(self) -> dict:
+        import json
+
+        need = C.c_size_t()
+        check(lib().smx_describe(self.handle, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        check(lib().smx_describe(self.handle, buf, need.value, None))
+        return json.loads(buf.value.decode())
 
     def set_timing(self, on: bool):
         check(lib().smx_set_timing(self.handle, 1 if on else 0))

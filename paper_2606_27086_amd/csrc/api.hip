@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -117,10 +118,42 @@ bool pad_rows(int64_t rows, const int64_t *rp, const int32_t *idx, const float *
     return true;
 }
 
+// Row blocks for the streaming kernels: consecutive rows with at most kBlock
+// rows and kStreamEntries padded entries per block; a longer row is a block
+// of its own.
+std::vector<int32_t> build_row_blocks(const std::vector<int32_t> &ptr, int64_t rows)
+{
+    std::vector<int32_t> rb;
+    rb.push_back(0);
+    int64_t r = 0;
+    while (r < rows) {
+        const int64_t start = r;
+        if (ptr[r + 1] - ptr[r] > kStreamEntries) {
+            ++r;
+        } else {
+            int64_t ent = 0;
+            while (r < rows && r - start < kBlock && ent + (ptr[r + 1] - ptr[r]) <= kStreamEntries) {
+                ent += ptr[r + 1] - ptr[r];
+                ++r;
+            }
+        }
+        rb.push_back((int32_t)r);
+    }
+    return rb;
+}
+
 struct DevLayout {
     int64_t rows = 0, slots = 0;
-    DBuf ptr, idx, val32, val16;
+    DBuf ptr, idx, val32, val16, rowblk;
+    int nblk = 0;
     float f16_scale = 1.f;
+    RowBlocks blocks() const
+    {
+        RowBlocks r;
+        r.rb = rowblk.as<int32_t>();
+        r.nblk = nblk;
+        return r;
+    }
     SpView view(int vk) const
     {
         SpView v;
@@ -175,6 +208,7 @@ struct smx_problem {
     DBuf x, g, c, lower, upper, box_lo, box_hi, lin_c, w, D32, D16, st, qout;
     DBuf part_pass, part_query, part_phase, part_trial[2]; // per-workgroup partial sums of each kernel kind
     int cur = 0; // which of the two state buffers (st holds 2*B states) is current
+    bool tuned = false;
     SliceState *state(int which) const { return st.as<SliceState>() + size_t(which) * B; }
     DBuf h_prox, h_fs, h_fe, h_tr, h_ac;
     Hist hist{};
@@ -198,18 +232,30 @@ struct smx_problem {
 
 namespace {
 
-PassCfg pick_cfg(int64_t rows, int64_t slots, int vk)
+// Default launch shape of a pass: row blocks streamed through LDS.
+PassCfg pick_cfg(const DevLayout &L, int vk)
 {
     PassCfg c;
+    c.mode = 1;
     c.vec = (vk == VK_F32) ? 4 : 8;
-    const double mean = rows > 0 ? double(slots) / double(rows) : 0.0;
+    c.lpr = 64;
+    c.grid = std::max(1, std::min(L.nblk, kMaxPassGrid));
+    return c;
+}
+
+// The lanes-per-row shape (mode 0) for the same layout.
+PassCfg pick_cfg_rows(const DevLayout &L, int vk)
+{
+    PassCfg c;
+    c.mode = 0;
+    c.vec = (vk == VK_F32) ? 4 : 8;
+    const double mean = L.rows > 0 ? double(L.slots) / double(L.rows) : 0.0;
     int lpr = 4;
     while (lpr < 64 && lpr * c.vec * 2 < mean) lpr *= 2;
     c.lpr = lpr;
     const int64_t rpb = kBlock / lpr;
-    int64_t grid = (rows + rpb - 1) / rpb;
-    grid = std::max<int64_t>(1, std::min<int64_t>(grid, 4096));
-    c.grid = (int)grid;
+    int64_t grid = (L.rows + rpb - 1) / rpb;
+    c.grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, kMaxPassGrid));
     return c;
 }
 
@@ -256,6 +302,11 @@ void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, bool keep32, int l
 {
     D.rows = rows;
     D.slots = H.slots;
+    {
+        std::vector<int32_t> rb = build_row_blocks(H.ptr, rows);
+        D.nblk = (int)rb.size() - 1;
+        upload(D.rowblk, rb, s, "upload row blocks");
+    }
     upload(D.ptr, H.ptr, s, "upload row pointers");
     upload(D.idx, H.idx, s, "upload indices");
     upload(D.val32, H.val, s, "upload values");
@@ -391,15 +442,16 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
         p->ev_used += 4;
         hip_check(hipEventRecord(e[0], s), "event");
     }
-    hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), vk, p->x.as<float>(), p->lower.as<float>(),
-                           p->upper.as<float>(), D, p->c.as<float>(), p->state(cur), p->B, 0,
+    hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), p->op->csr.blocks(), vk, p->x.as<float>(),
+                           p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(), p->state(cur), p->B, 0,
                            p->part_pass.as<double>(), s),
               "pass 1");
     if (timed) {
         hip_check(hipEventRecord(e[1], s), "event");
         hip_check(hipEventRecord(e[2], s), "event");
     }
-    hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, vk), vk, p->c.as<float>(), p->x.as<float>(),
+    hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, vk), p->op->csc.blocks(), vk, p->c.as<float>(),
+                           p->x.as<float>(),
                            p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, p->state(cur), p->state(cur ^ 1),
                            p->B, p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
               "pass 2");
@@ -602,9 +654,11 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->D16.alloc(sizeof(float) * m, "D (reduced precision)");
         hip_check(launch_make_D(op->q16.as<double>(), p->w.as<double>(), p->D16.as<float>(), m, s), "D");
     }
+    const char *mode_env = getenv("SMX_PASS_MODE"); // "rows" selects the lanes-per-row kernels
+    const bool rows_mode = mode_env && std::strcmp(mode_env, "rows") == 0;
     for (int vk = 0; vk < 3; ++vk) {
-        p->cfg1[vk] = pick_cfg(m, op->csr.slots, vk);
-        p->cfg2[vk] = pick_cfg(n, op->csc.slots, vk);
+        p->cfg1[vk] = rows_mode ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk);
+        p->cfg2[vk] = rows_mode ? pick_cfg_rows(op->csc, vk) : pick_cfg(op->csc, vk);
     }
     // per-workgroup partial sums of each kernel kind
     const int64_t pgrid = phase_grid(pp);
@@ -632,6 +686,159 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     hip_check(hipStreamSynchronize(s), "problem setup");
     op->refs.fetch_add(1);
     *out = p.release();
+    return SMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate launch shapes of both passes on the problem's own
+// operator and keeps the fastest.  Timing runs on scratch copies of the
+// iterate, the weighted residual and the state, so the problem is unchanged.
+// ---------------------------------------------------------------------------
+
+std::vector<PassCfg> pass_candidates(const DevLayout &L, int vk)
+{
+    std::vector<PassCfg> out;
+    for (int g : {1024, 2048, 4096}) {
+        PassCfg c = pick_cfg(L, vk);
+        c.grid = std::max(1, std::min({L.nblk, g, kMaxPassGrid}));
+        bool dup = false;
+        for (auto &o : out) dup |= (o.mode == c.mode && o.grid == c.grid);
+        if (!dup) out.push_back(c);
+    }
+    for (int lpr : {8, 16, 32, 64})
+        for (int vec : {4, 8})
+            for (int g : {1024, 2048, 4096}) {
+                PassCfg c;
+                c.mode = 0;
+                c.lpr = lpr;
+                c.vec = vec;
+                const int64_t rpb = kBlock / lpr;
+                const int64_t need = std::max<int64_t>(1, (L.rows + rpb - 1) / rpb);
+                c.grid = (int)std::min<int64_t>({need, (int64_t)g, (int64_t)kMaxPassGrid});
+                bool dup = false;
+                for (auto &o : out) dup |= (o.mode == 0 && o.lpr == lpr && o.vec == vec && o.grid == c.grid);
+                if (!dup) out.push_back(c);
+            }
+    return out;
+}
+
+int autotune_impl(smx_problem *p, int reps)
+{
+    if (reps < 1) reps = 10;
+    hipStream_t s = p->stream;
+    const int64_t m = p->m, n = p->n;
+    DBuf xs, cs, sts;
+    xs.alloc(sizeof(float) * n * p->B, "tuning scratch");
+    cs.alloc(sizeof(float) * m * p->B, "tuning scratch");
+    sts.alloc(sizeof(SliceState) * 2 * p->B, "tuning scratch");
+    hip_check(hipMemcpyAsync(xs.p, p->x.p, sizeof(float) * n * p->B, hipMemcpyDeviceToDevice, s), "tuning copy");
+    SliceState *st0 = sts.as<SliceState>(), *st1 = st0 + p->B;
+    hip_check(launch_init_state(st0, p->B, s), "tuning state");
+    hip_check(launch_init_state(st1, p->B, s), "tuning state");
+    Hist none{};
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    auto elapsed = [&]() {
+        float ms = 0.f;
+        hip_check(hipEventSynchronize(e1), "tuning sync");
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "tuning elapsed");
+        return (double)ms / reps;
+    };
+    std::vector<int> kinds;
+    if (p->op->has_f32) kinds.push_back(VK_F32);
+    if (p->op->lp_kind() != VK_F32) kinds.push_back(p->op->lp_kind());
+    try {
+        for (int vk : kinds) {
+            const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
+            // pass 1
+            double best = 1e30;
+            PassCfg bestc = p->cfg1[vk];
+            for (const PassCfg &c : pass_candidates(p->op->csr, vk)) {
+                auto launch = [&]() {
+                    hip_check(launch_pass1(c, view_for(p->op, false, vk), p->op->csr.blocks(), vk, xs.as<float>(),
+                                           p->lower.as<float>(), p->upper.as<float>(), D, cs.as<float>(), st0, p->B, 1,
+                                           p->part_query.as<double>(), s),
+                              "tuning pass 1");
+                };
+                launch();
+                launch();
+                hip_check(hipEventRecord(e0, s), "event");
+                for (int r = 0; r < reps; ++r) launch();
+                hip_check(hipEventRecord(e1, s), "event");
+                const double t = elapsed();
+                if (t < best) {
+                    best = t;
+                    bestc = c;
+                }
+            }
+            p->cfg1[vk] = bestc;
+            // pass 2 (the residual from the chosen pass 1)
+            best = 1e30;
+            PassCfg bestc2 = p->cfg2[vk];
+            for (const PassCfg &c : pass_candidates(p->op->csc, vk)) {
+                auto launch = [&]() {
+                    hip_check(launch_pass2(c, view_for(p->op, true, vk), p->op->csc.blocks(), vk, cs.as<float>(),
+                                           xs.as<float>(), p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, st0,
+                                           st1, p->B, p->part_query.as<double>(), bestc.grid, none, s),
+                              "tuning pass 2");
+                };
+                launch();
+                launch();
+                hip_check(hipEventRecord(e0, s), "event");
+                for (int r = 0; r < reps; ++r) launch();
+                hip_check(hipEventRecord(e1, s), "event");
+                const double t = elapsed();
+                if (t < best) {
+                    best = t;
+                    bestc2 = c;
+                }
+            }
+            p->cfg2[vk] = bestc2;
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hip_check(hipStreamSynchronize(s), "tuning sync");
+    // launch shapes are baked into captured graphs
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    p->graphs.clear();
+    p->tuned = true;
+    return SMX_OK;
+}
+
+int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
+{
+    std::string out = "{";
+    const char *names[3] = {"f32", "bf16", "f16"};
+    bool first = true;
+    for (int vk = 0; vk < 3; ++vk) {
+        if (vk == VK_F32 && !p->op->has_f32) continue;
+        if (vk != VK_F32 && p->op->lp_kind() != vk) continue;
+        char tmp[256];
+        const PassCfg &a = p->cfg1[vk], &b = p->cfg2[vk];
+        snprintf(tmp, sizeof tmp,
+                 "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d}, "
+                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d}}",
+                 first ? "" : ", ", names[vk], a.mode ? "stream" : "rows", a.lpr, a.vec, a.grid,
+                 b.mode ? "stream" : "rows", b.lpr, b.vec, b.grid);
+        out += tmp;
+        first = false;
+    }
+    char tail[160];
+    snprintf(tail, sizeof tail, ", \"tuned\": %s, \"row_blocks\": [%d, %d]}", p->tuned ? "true" : "false",
+             p->op->csr.nblk, p->op->csc.nblk);
+    out += tail;
+    if (need) *need = out.size() + 1;
+    if (buf && cap > 0) {
+        const size_t k = std::min(cap - 1, out.size());
+        std::memcpy(buf, out.data(), k);
+        buf[k] = 0;
+    }
     return SMX_OK;
 }
 
@@ -783,8 +990,8 @@ int smx_query(smx_problem *p, double *proximity, double *objective)
         const int vk = p->op->has_f32 ? VK_F32 : p->op->lp_kind();
         const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
         double *q = p->qout.as<double>();
-        hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), vk, p->x.as<float>(), p->lower.as<float>(),
-                               p->upper.as<float>(), D, p->c.as<float>(), p->state(p->cur), B, 1,
+        hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), p->op->csr.blocks(), vk, p->x.as<float>(),
+                               p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(), p->state(p->cur), B, 1,
                                p->part_query.as<double>(), p->stream),
                   "query proximity");
         hip_check(launch_query_prox(p->state(p->cur), B, p->part_query.as<double>(), p->cfg1[vk].grid, q,
@@ -892,6 +1099,18 @@ int smx_problem_dims(const smx_problem *p, int64_t *m, int64_t *n, int64_t *nnz,
     if (nnz) *nnz = p->op->nnz;
     if (B) *B = p->B;
     return SMX_OK;
+}
+
+int smx_autotune(smx_problem *p, int32_t reps)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD(return autotune_impl(p, reps);)
+}
+
+int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD(return describe_impl(p, buf, cap, need);)
 }
 
 int smx_set_timing(smx_problem *p, int32_t enable)

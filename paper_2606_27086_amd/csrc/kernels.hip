@@ -232,13 +232,152 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
         const long long stride = (long long)gridDim.x * RPB;
         for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
             const int beg = A.ptr[row], end = A.ptr[row + 1];
+            float lo = 0.f, up = 0.f, d = 0.f;
+            if (lane == 0) { // epilogue operands, fetched while the row streams
+                lo = lower[row];
+                up = upper[row];
+                d = D[row];
+            }
             const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
             if (lane == 0) {
-                const double t = fmin(fmax(r, (double)lower[row]), (double)upper[row]) - r;
-                const double dt = (double)D[row] * t;
+                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+                const double dt = (double)d * t;
                 c[row] = (float)dt;
                 pacc[0] += dt * t;
             }
+        }
+    }
+    block_sum<1>(pacc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+}
+
+// ---------------------------------------------------------------------------
+// Streaming pass kernels.  A workgroup takes one row block (at most
+// kStreamEntries entries): every lane issues all of its value/index loads and
+// gathers at once, the exact float64 products go to LDS, and each row is then
+// summed from LDS by a group of G lanes (G the largest power of two with
+// G * rows <= kBlock).  A row longer than a block is summed by the whole
+// workgroup.  Rows of one block are consecutive, so the loads are one
+// contiguous stream per workgroup.
+// ---------------------------------------------------------------------------
+
+struct RowSplit {
+    int G, rl, lane;
+};
+
+__device__ inline RowSplit split_rows(int nr)
+{
+    int G = 64;
+    while (G > 1 && G * nr > kBlock) G >>= 1;
+    RowSplit r;
+    r.G = G;
+    r.rl = threadIdx.x / G;
+    r.lane = threadIdx.x & (G - 1);
+    return r;
+}
+
+// Sums of the VEC-entry chunks of [e0, e1) with v: chunk j (entries e0 + j*VEC
+// ..) into prod[j].  Rows start at multiples of kRowAlign (a multiple of VEC),
+// so no chunk straddles two rows; each product of two float32 numbers is exact
+// in float64.
+template <int VEC, typename VT>
+__device__ inline void stream_chunks(const SpView &A, int e0, int e1, const float *__restrict__ v, double *prod)
+{
+    constexpr int PER = kStreamEntries / (kBlock * VEC);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int j = k * kBlock + threadIdx.x;
+        const int q = j * VEC;
+        if (e0 + q < e1) {
+            float val[VEC];
+            int id[VEC];
+            ValLoad<VT, VEC>::load(A.val, e0 + q, val);
+            idx_load<VEC>(A.idx, e0 + q, id);
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc = fma((double)val[e], (double)v[id[e]], acc);
+            prod[j] = acc;
+        }
+    }
+}
+
+// Sum over lanes of the G-lane group (every thread of the workgroup calls it).
+__device__ inline double group_sum_rt(double s, int G)
+{
+    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+    return s;
+}
+
+// Whole-workgroup sum of one long row; valid in thread 0.
+template <int VEC, typename VT>
+__device__ inline double long_row_sum(const SpView &A, int e0, int e1, const float *__restrict__ v, double *lds)
+{
+    double acc = 0.0;
+    for (int p = e0 + threadIdx.x * VEC; p < e1; p += kBlock * VEC) {
+        float val[VEC];
+        int id[VEC];
+        ValLoad<VT, VEC>::load(A.val, p, val);
+        idx_load<VEC>(A.idx, p, id);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc = fma((double)val[e], (double)v[id[e]], acc);
+    }
+    double t[1] = {acc};
+    block_sum<1>(t, lds);
+    return t[0];
+}
+
+template <int VEC, typename VT>
+__global__ __launch_bounds__(kBlock) void k_pass1_stream(SpView A, RowBlocks RB, const float *__restrict__ x,
+                                                         const float *__restrict__ lower,
+                                                         const float *__restrict__ upper,
+                                                         const float *__restrict__ D, float *__restrict__ c,
+                                                         const SliceState *__restrict__ st, int query,
+                                                         double *__restrict__ partials)
+{
+    __shared__ double prod[kStreamEntries / VEC];
+    __shared__ int rp[kBlock + 1];
+    __shared__ double lds[4];
+    const bool live = query ? true : st[0].live != 0;
+    double pacc[1] = {0.0};
+    if (live) {
+        for (int b = blockIdx.x; b < RB.nblk; b += gridDim.x) {
+            const int r0 = RB.rb[b], r1 = RB.rb[b + 1];
+            const int e0 = A.ptr[r0], e1 = A.ptr[r1];
+            if (e1 - e0 > kStreamEntries) {
+                const double sum = long_row_sum<VEC, VT>(A, e0, e1, x, lds);
+                if (threadIdx.x == 0) {
+                    const double r = sum * (double)A.vscale_inv;
+                    const double t = fmin(fmax(r, (double)lower[r0]), (double)upper[r0]) - r;
+                    const double dt = (double)D[r0] * t;
+                    c[r0] = (float)dt;
+                    pacc[0] += dt * t;
+                }
+                continue;
+            }
+            const int nr = r1 - r0;
+            const RowSplit rs = split_rows(nr);
+            const bool owner = rs.rl < nr && rs.lane == 0;
+            float lo = 0.f, up = 0.f, d = 0.f;
+            if (owner) { // epilogue operands, fetched while the products stream
+                lo = lower[r0 + rs.rl];
+                up = upper[r0 + rs.rl];
+                d = D[r0 + rs.rl];
+            }
+            for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = (A.ptr[r0 + i] - e0) / VEC;
+            stream_chunks<VEC, VT>(A, e0, e1, x, prod);
+            __syncthreads();
+            double s = 0.0;
+            if (rs.rl < nr)
+                for (int q = rp[rs.rl] + rs.lane; q < rp[rs.rl + 1]; q += rs.G) s += prod[q];
+            s = group_sum_rt(s, rs.G);
+            if (owner) {
+                const double r = s * (double)A.vscale_inv;
+                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+                const double dt = (double)d * t;
+                c[r0 + rs.rl] = (float)dt;
+                pacc[0] += dt * t;
+            }
+            __syncthreads();
         }
     }
     block_sum<1>(pacc, lds);
@@ -310,11 +449,66 @@ __global__ __launch_bounds__(kBlock) void k_pass2(SpView At, const float *__rest
         const long long stride = (long long)gridDim.x * RPB;
         for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
             const int beg = At.ptr[col], end = At.ptr[col + 1];
+            float xo = 0.f, l = 0.f, u = 0.f;
+            if (lane == 0) { // epilogue operands, fetched while the column streams
+                xo = x[col];
+                l = lo[col];
+                u = hi[col];
+            }
             const double y = group_sum<LPR>(row_dot<LPR, VEC, VT>(At, beg, end, lane, c)) * (double)At.vscale_inv;
             if (lane == 0) {
-                const double z = fma((double)lambda, y, (double)x[col]);
-                x[col] = (float)fmin(fmax(z, (double)lo[col]), (double)hi[col]);
+                const double z = fma((double)lambda, y, (double)xo);
+                x[col] = (float)fmin(fmax(z, (double)l), (double)u);
             }
+        }
+    }
+    if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+}
+
+template <int VEC, typename VT>
+__global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB, const float *__restrict__ c,
+                                                         float *__restrict__ x, const float *__restrict__ lo,
+                                                         const float *__restrict__ hi, float lambda,
+                                                         const SliceState *__restrict__ st_in,
+                                                         SliceState *__restrict__ st_out,
+                                                         const double *__restrict__ part1, int nparts1, Hist h)
+{
+    __shared__ double prod[kStreamEntries / VEC];
+    __shared__ int rp[kBlock + 1];
+    __shared__ double lds[4];
+    if (st_in[0].live) {
+        for (int b = blockIdx.x; b < RB.nblk; b += gridDim.x) {
+            const int r0 = RB.rb[b], r1 = RB.rb[b + 1];
+            const int e0 = At.ptr[r0], e1 = At.ptr[r1];
+            if (e1 - e0 > kStreamEntries) {
+                const double sum = long_row_sum<VEC, VT>(At, e0, e1, c, lds);
+                if (threadIdx.x == 0) {
+                    const double z = fma((double)lambda, sum * (double)At.vscale_inv, (double)x[r0]);
+                    x[r0] = (float)fmin(fmax(z, (double)lo[r0]), (double)hi[r0]);
+                }
+                continue;
+            }
+            const int nr = r1 - r0;
+            const RowSplit rs = split_rows(nr);
+            const bool owner = rs.rl < nr && rs.lane == 0;
+            float xo = 0.f, l = 0.f, u = 0.f;
+            if (owner) {
+                xo = x[r0 + rs.rl];
+                l = lo[r0 + rs.rl];
+                u = hi[r0 + rs.rl];
+            }
+            for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = (At.ptr[r0 + i] - e0) / VEC;
+            stream_chunks<VEC, VT>(At, e0, e1, c, prod);
+            __syncthreads();
+            double s = 0.0;
+            if (rs.rl < nr)
+                for (int q = rp[rs.rl] + rs.lane; q < rp[rs.rl + 1]; q += rs.G) s += prod[q];
+            s = group_sum_rt(s, rs.G);
+            if (owner) {
+                const double z = fma((double)lambda, s * (double)At.vscale_inv, (double)xo);
+                x[r0 + rs.rl] = (float)fmin(fmax(z, (double)l), (double)u);
+            }
+            __syncthreads();
         }
     }
     if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
@@ -902,11 +1096,26 @@ static hipError_t pass1_vec(const PassCfg &cfg, const SpView &A, const float *x,
     return hipGetLastError();
 }
 
-hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, int vk, const float *x, const float *lower,
-                        const float *upper, const float *D, float *c, const SliceState *st, int B, int query,
-                        double *partials, hipStream_t s)
+template <typename VT, int VEC>
+static hipError_t pass1_stream(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, const float *x,
+                               const float *lower, const float *upper, const float *D, float *c,
+                               const SliceState *st, int query, double *partials, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pass1_stream<VEC, VT>), dim3(cfg.grid), dim3(kBlock), 0, s, A, RB, x, lower, upper, D, c,
+                       st, query, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
+                        const float *lower, const float *upper, const float *D, float *c, const SliceState *st, int B,
+                        int query, double *partials, hipStream_t s)
 {
     if (B != 1 || cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
+    if (cfg.mode == 1) {
+        if (vk == VK_F32) return pass1_stream<float, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+        if (vk == VK_BF16) return pass1_stream<Bf16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+        return pass1_stream<F16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+    }
     if (vk == VK_F32) {
         if (cfg.vec == 8) return pass1_vec<float, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
         return pass1_vec<float, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
@@ -938,12 +1147,27 @@ static hipError_t pass2_vec(const PassCfg &cfg, const SpView &At, const float *c
     return hipGetLastError();
 }
 
-hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, int vk, const float *c, float *x, const float *lo,
-                        const float *hi, float lambda, const SliceState *st_in, SliceState *st_out, int B,
-                        const double *part1, int nparts1, Hist h, hipStream_t s)
+template <typename VT, int VEC>
+static hipError_t pass2_stream(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, const float *c, float *x,
+                               const float *lo, const float *hi, float lambda, const SliceState *st_in,
+                               SliceState *st_out, const double *part1, int nparts1, Hist h, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pass2_stream<VEC, VT>), dim3(cfg.grid), dim3(kBlock), 0, s, At, RB, c, x, lo, hi, lambda,
+                       st_in, st_out, part1, nparts1, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
+                        const float *lo, const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
+                        int B, const double *part1, int nparts1, Hist h, hipStream_t s)
 {
     if (B != 1 || cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid)
         return hipErrorInvalidValue;
+    if (cfg.mode == 1) {
+        if (vk == VK_F32) return pass2_stream<float, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_BF16) return pass2_stream<Bf16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        return pass2_stream<F16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    }
     if (vk == VK_F32) {
         if (cfg.vec == 8) return pass2_vec<float, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
         return pass2_vec<float, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);

@@ -73,10 +73,21 @@ struct Hist {
     long long cap;
 };
 
+constexpr int kStreamEntries = 2048; // entries per row block of the streaming pass kernels
+
 struct PassCfg {
-    int lpr;  // lanes per row: 4, 8, 16, 32 or 64
+    int mode; // 0: a group of lpr lanes per row; 1: row blocks streamed through LDS
+    int lpr;  // lanes per row (mode 0): 4, 8, 16, 32 or 64
     int vec;  // entries per lane per load: 4 or 8
     int grid; // workgroups
+};
+
+// Row blocks of a row-aligned layout for the streaming kernels: block b holds
+// rows [rb[b], rb[b+1]), at most kBlock rows and at most kStreamEntries
+// entries, or a single longer row.
+struct RowBlocks {
+    const int32_t *rb;
+    int nblk;
 };
 
 // ---- launchers (kernels.hip) ----
@@ -91,14 +102,14 @@ constexpr int kMaxPassGrid = 4096; // workgroups of a pass kernel (one proximity
 
 // pass 1: r = A x, t = clip(r) - r, c = D t, one proximity partial per
 // workgroup (query != 0: every slice runs, whatever its state)
-hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, int vk, const float *x, const float *lower,
-                        const float *upper, const float *D, float *c, const SliceState *st, int B, int query,
-                        double *partials, hipStream_t s);
+hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
+                        const float *lower, const float *upper, const float *D, float *c, const SliceState *st, int B,
+                        int query, double *partials, hipStream_t s);
 // pass 2: x = clip(x + lambda A^T c, lo, hi); workgroup 0 also ends the
 // iteration (proximity from pass 1's partials, history, k + 1) into st_out
-hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, int vk, const float *c, float *x, const float *lo,
-                        const float *hi, float lambda, const SliceState *st_in, SliceState *st_out, int B,
-                        const double *part1, int nparts1, Hist h, hipStream_t s);
+hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
+                        const float *lo, const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
+                        int B, const double *part1, int nparts1, Hist h, hipStream_t s);
 // query: proximity from pass 1's partials into out[B]
 hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s);
 

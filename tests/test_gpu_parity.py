@@ -342,3 +342,44 @@ def test_invalid_problem_args(smx):
 def test_ct256_full_bench_configuration(smx):
     w = W.ct(N=256, seed=2, K=200)
     check_parity(smx, w, w.K, sensitive=True)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_lanes_per_row_kernels(smx, storage, monkeypatch):
+    """The lanes-per-row pass kernels (the alternative launch shape) give the
+    same results as the oracle too."""
+    monkeypatch.setenv("SMX_PASS_MODE", "rows")
+    w = W.random_sparse(2500, 1800, 30, seed=19, empty_frac=0.05, long_rows=3, obj=W.OBJ_SQNORM, K=15)
+    if storage == "f32":
+        check_parity(smx, w, w.K)
+    else:
+        check_parity(smx, w, w.K, storage="bf16", value_round="bf16")
+
+
+def test_long_rows_stream_kernel(smx):
+    """Rows and columns longer than one streamed row block (2048 entries)."""
+    w = W.random_sparse(600, 5000, 40, seed=20, empty_frac=0.05, long_rows=4, long_len=4500,
+                        obj=W.OBJ_LINEAR, K=12)
+    check_parity(smx, w, w.K)
+
+
+def test_autotuned_shapes_keep_parity(smx):
+    """After autotuning (launch shapes picked by timing), results still match
+    the oracle, and tuning leaves the iterate and state untouched."""
+    w = W.ct(N=64, n_angles=48, seed=21, K=30)
+    say("autotune")
+    p = smx.problem_from_workload(w, history_cap=w.K)
+    x_before = p.get_x().cpu().numpy().copy()
+    shapes = p.autotune(reps=3)
+    print(f"  shapes {shapes}", flush=True)
+    assert shapes["tuned"]
+    assert np.array_equal(p.get_x().cpu().numpy(), x_before)
+    p.run(w.K)
+    p.sync()
+    x = p.get_x().cpu().numpy()[:, 0].astype(np.float64)
+    h = p.history()
+    p.close()
+    xo, sto, ho, P = oracle_run(w, w.K)
+    assert np.array_equal(h["trials"][:, 0], ho.trials)
+    dx, _, _ = storage_deviation(w, w.K)
+    assert rel(x, xo) <= max(RTOL, 10 * dx)
