@@ -25,6 +25,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+PMC_TABLE = os.path.join(ROOT, "profiles", "pmc_ct256_pass_traffic.json")
+
+
+def kernel_name(pass_no, shape, storage):
+    vt = {"f32": "float", "bf16": "smx::Bf16Tag", "f16": "smx::F16Tag"}[storage]
+    if shape["mode"] == "stream":
+        return f"smx::k_pass{pass_no}_stream<{shape['vec']}, {vt}>"
+    return f"smx::k_pass{pass_no}<{shape['lpr']}, {shape['vec']}, {vt}>"
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed counter table, or None when the
+    table is missing, was taken on another workload, or on other kernel code."""
+    try:
+        import json as _json
+
+        from paper_2606_27086_amd.pmc_summary import kernel_source_hash
+
+        tab = _json.load(open(PMC_TABLE))
+        if tab.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        k = tab["kernels"].get(name)
+        return None if k is None else round(k["traffic_bytes"])
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def alg_bytes(m, n, nnz, val_bytes, idx_bytes=4):
@@ -120,13 +145,14 @@ def main():
     b1, b2 = alg_bytes(w.m, w.n, w.nnz, vb)
     t1, t2 = main_r["pass1_ms"], main_r["pass2_ms"]
     if t1 >= t2:
-        dom, dbytes, dms = "pass1_csr_clip", b1, t1
+        dom, dbytes, dms, dpass = "pass1_csr_clip", b1, t1, 1
     else:
-        dom, dbytes, dms = "pass2_csc_box", b2, t2
+        dom, dbytes, dms, dpass = "pass2_csc_box", b2, t2, 2
     achieved = dbytes / (dms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    both_passes_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
+    kname = kernel_name(dpass, main_r["shapes"][main_st][f"pass{dpass}"], main_st)
+    roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname),
+                    algorithmic_bytes=int(dbytes), both_passes_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
     variants = {}
     for st, r in results.items():
         vbs = {"f32": 4, "bf16": 2, "f16": 2}[st]

@@ -250,8 +250,8 @@ PassCfg pick_cfg_rows(const DevLayout &L, int vk)
     c.mode = 0;
     c.vec = (vk == VK_F32) ? 4 : 8;
     const double mean = L.rows > 0 ? double(L.slots) / double(L.rows) : 0.0;
-    int lpr = 4;
-    while (lpr < 64 && lpr * c.vec * 2 < mean) lpr *= 2;
+    int lpr = 2;
+    while (lpr < 64 && lpr * c.vec * 8 < mean) lpr *= 2;
     c.lpr = lpr;
     const int64_t rpb = kBlock / lpr;
     int64_t grid = (L.rows + rpb - 1) / rpb;
@@ -705,7 +705,7 @@ std::vector<PassCfg> pass_candidates(const DevLayout &L, int vk)
         for (auto &o : out) dup |= (o.mode == c.mode && o.grid == c.grid);
         if (!dup) out.push_back(c);
     }
-    for (int lpr : {8, 16, 32, 64})
+    for (int lpr : {2, 4, 8, 16, 32})
         for (int vec : {4, 8})
             for (int g : {1024, 2048, 4096}) {
                 PassCfg c;

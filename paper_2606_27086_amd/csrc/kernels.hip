@@ -176,30 +176,32 @@ __device__ inline void idx_load(const int32_t *base, int p, int (&c)[VEC])
 template <int LPR, int VEC, typename VT>
 __device__ inline double row_dot(const SpView &A, int beg, int end, int lane, const float *__restrict__ x)
 {
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int p = beg + lane * VEC;
     constexpr int STEP = LPR * VEC;
-    for (; p + STEP < end; p += 2 * STEP) {
-        float v0[VEC], v1[VEC];
-        int c0[VEC], c1[VEC];
-        ValLoad<VT, VEC>::load(A.val, p, v0);
-        idx_load<VEC>(A.idx, p, c0);
-        ValLoad<VT, VEC>::load(A.val, p + STEP, v1);
-        idx_load<VEC>(A.idx, p + STEP, c1);
+    // four independent loads in flight per lane
+    for (; p + 3 * STEP < end; p += 4 * STEP) {
+        float v[4][VEC];
+        int c[4][VEC];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc0 = fma((double)v0[e], (double)x[c0[e]], acc0);
+        for (int u = 0; u < 4; ++u) {
+            ValLoad<VT, VEC>::load(A.val, p + u * STEP, v[u]);
+            idx_load<VEC>(A.idx, p + u * STEP, c[u]);
+        }
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc1 = fma((double)v1[e], (double)x[c1[e]], acc1);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[u] = fma((double)v[u][e], (double)x[c[u][e]], acc[u]);
     }
-    if (p < end) {
+    for (; p < end; p += STEP) {
         float v0[VEC];
         int c0[VEC];
         ValLoad<VT, VEC>::load(A.val, p, v0);
         idx_load<VEC>(A.idx, p, c0);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc0 = fma((double)v0[e], (double)x[c0[e]], acc0);
+        for (int e = 0; e < VEC; ++e) acc[0] = fma((double)v0[e], (double)x[c0[e]], acc[0]);
     }
-    return acc0 + acc1;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 template <int LPR>
@@ -1086,6 +1088,7 @@ static hipError_t pass1_vec(const PassCfg &cfg, const SpView &A, const float *x,
 {
     const dim3 grid(cfg.grid), block(kBlock);
     switch (cfg.lpr) {
+    case 2: hipLaunchKernelGGL((k_pass1<2, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
     case 4: hipLaunchKernelGGL((k_pass1<4, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
     case 8: hipLaunchKernelGGL((k_pass1<8, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
     case 16: hipLaunchKernelGGL((k_pass1<16, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
@@ -1136,6 +1139,7 @@ static hipError_t pass2_vec(const PassCfg &cfg, const SpView &At, const float *c
     const dim3 grid(cfg.grid), block(kBlock);
 #define SMX_P2(L) hipLaunchKernelGGL((k_pass2<L, VEC, VT>), grid, block, 0, s, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h)
     switch (cfg.lpr) {
+    case 2: SMX_P2(2); break;
     case 4: SMX_P2(4); break;
     case 8: SMX_P2(8); break;
     case 16: SMX_P2(16); break;

@@ -77,7 +77,7 @@ constexpr int kStreamEntries = 2048; // entries per row block of the streaming p
 
 struct PassCfg {
     int mode; // 0: a group of lpr lanes per row; 1: row blocks streamed through LDS
-    int lpr;  // lanes per row (mode 0): 4, 8, 16, 32 or 64
+    int lpr;  // lanes per row (mode 0): 2, 4, 8, 16, 32 or 64
     int vec;  // entries per lane per load: 4 or 8
     int grid; // workgroups
 };
