@@ -211,6 +211,30 @@ int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x)
 /* Shape of the problem. */
 int smx_problem_dims(const smx_problem *p, int64_t *m, int64_t *n, int64_t *nnz, int32_t *B);
 
+/*
+ * Slots (serving): the B slices of a problem are independent slots sharing
+ * the operator.  smx_slot_load copies one slot's bands (m floats each) and
+ * starting point (n floats; host or device) into slot `slot`, resets its
+ * state (k = ell = restarts = 0, counters 0) and lets it run `budget` more
+ * iterations: later smx_run calls advance it until its k reaches budget, then
+ * leave it untouched.  budget = 0 loads the data and keeps the slot idle.
+ * Errors: slot outside [0,B), lower > upper, NaN bounds -> SMX_EINVAL.
+ * The copies are ordered on the problem's stream; smx_slot_load returns after
+ * they complete.  A slot's results do not depend on the other slots.
+ */
+int smx_slot_load(smx_problem *p, int32_t slot, const float *lower, const float *upper, const float *x0,
+                  int32_t on_device, int64_t budget);
+
+/* Stop advancing a slot (its iterate and state stay as they are). */
+int smx_slot_disable(smx_problem *p, int32_t slot);
+
+/* Per-slot iterations completed (k[B]) and whether the slot still runs
+ * (live[B]); either may be NULL.  Synchronises. */
+int smx_slot_status(smx_problem *p, int64_t *k, int32_t *live);
+
+/* One slot's iterate (n floats) to host or device memory. */
+int smx_slot_get_x(smx_problem *p, int32_t slot, float *out, int32_t on_device);
+
 /* Autotuner (batching pattern): times candidate launch shapes of both passes
  * (row blocks streamed through LDS, or 8..64 lanes per row with 4 or 8
  * entries per load, at several grid sizes) on this problem's operator, `reps`

@@ -48,6 +48,10 @@ EXPORTS = [
     "smx_get_timing",
     "smx_autotune",
     "smx_describe",
+    "smx_slot_load",
+    "smx_slot_disable",
+    "smx_slot_status",
+    "smx_slot_get_x",
 ]
 
 
@@ -141,6 +145,10 @@ def lib() -> C.CDLL:
     L.smx_set_timing.argtypes = [vp, i32]
     L.smx_get_timing.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i64)]
     L.smx_autotune.argtypes = [vp, i32]
+    L.smx_slot_load.argtypes = [vp, i32, vp, vp, vp, i32, i64]
+    L.smx_slot_disable.argtypes = [vp, i32]
+    L.smx_slot_status.argtypes = [vp, vp, vp]
+    L.smx_slot_get_x.argtypes = [vp, i32, vp, i32]
     L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     for name in EXPORTS:
         if name != "smx_last_error":
@@ -336,6 +344,36 @@ class Problem:
         buf = C.create_string_buffer(need.value)
         check(lib().smx_describe(self.handle, buf, need.value, None))
         return json.loads(buf.value.decode())
+
+    # -- slots (serving) ---------------------------------------------------
+    def slot_load(self, slot: int, lower, upper, x0, budget: int):
+        """Load one slot's bands and starting point; it then runs `budget` iterations."""
+        import torch
+
+        lo = _dev(np.asarray(lower, np.float32).reshape(-1) if not isinstance(lower, torch.Tensor) else lower,
+                  torch.float32, self.device)
+        up = _dev(np.asarray(upper, np.float32).reshape(-1) if not isinstance(upper, torch.Tensor) else upper,
+                  torch.float32, self.device)
+        xx = _dev(np.asarray(x0, np.float32).reshape(-1) if not isinstance(x0, torch.Tensor) else x0,
+                  torch.float32, self.device)
+        check(lib().smx_slot_load(self.handle, int(slot), _ptr(lo), _ptr(up), _ptr(xx), 1, int(budget)))
+
+    def slot_disable(self, slot: int):
+        check(lib().smx_slot_disable(self.handle, int(slot)))
+
+    def slot_status(self):
+        k = np.zeros(self.B, np.int64)
+        live = np.zeros(self.B, np.int32)
+        check(lib().smx_slot_status(self.handle, k.ctypes.data, live.ctypes.data))
+        return k, live
+
+    def slot_x(self, slot: int):
+        """Slot iterate as a device tensor [n]."""
+        import torch
+
+        out = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        check(lib().smx_slot_get_x(self.handle, int(slot), _ptr(out), 1))
+        return out
 
     def set_timing(self, on: bool):
         check(lib().smx_set_timing(self.handle, 1 if on else 0))

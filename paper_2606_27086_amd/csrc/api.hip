@@ -232,12 +232,20 @@ struct smx_problem {
 
 namespace {
 
-// Default launch shape of a pass: row blocks streamed through LDS.
-PassCfg pick_cfg(const DevLayout &L, int vk)
+// Default launch shape of a pass: row blocks streamed through LDS for one
+// slice; several slices use the multi-slice lanes-per-row kernels.
+PassCfg pick_cfg(const DevLayout &L, int vk, int B = 1)
 {
     PassCfg c;
-    c.mode = 1;
     c.vec = (vk == VK_F32) ? 4 : 8;
+    if (B > 1) {
+        c.mode = 0;
+        c.lpr = 8;
+        const int64_t rpb = kBlock / c.lpr;
+        c.grid = (int)std::max<int64_t>(1, std::min<int64_t>((L.rows + rpb - 1) / rpb, kMaxPassGrid));
+        return c;
+    }
+    c.mode = 1;
     c.lpr = 64;
     c.grid = std::max(1, std::min(L.nblk, kMaxPassGrid));
     return c;
@@ -559,11 +567,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     *out = nullptr;
     const int64_t m = op->m, n = op->n;
     const int B = d->B;
-    if (!is_pow2(B) || B > 1) {
-        // batched slices are served by separate problems until the multi-slice kernels land
-        if (!(is_pow2(B) && B <= 32)) return fail(SMX_EINVAL, "B must be a power of two in 1..32 (got %d)", B);
-        if (B != 1) return fail(SMX_EINVAL, "B > 1 is not supported by this build (got %d)", B);
-    }
+    if (!(is_pow2(B) && B <= 32)) return fail(SMX_EINVAL, "B must be a power of two in 1..32 (got %d)", B);
     if (!(d->lambda > 0.0 && d->lambda <= 2.0)) return fail(SMX_EINVAL, "lambda must be in (0, 2] (got %g)", d->lambda);
     if (d->obj_kind < SMX_OBJ_NONE || d->obj_kind > SMX_OBJ_LINEAR) return fail(SMX_EINVAL, "unknown objective %d", d->obj_kind);
     if (d->obj_kind != SMX_OBJ_NONE) {
@@ -657,8 +661,8 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     const char *mode_env = getenv("SMX_PASS_MODE"); // "rows" selects the lanes-per-row kernels
     const bool rows_mode = mode_env && std::strcmp(mode_env, "rows") == 0;
     for (int vk = 0; vk < 3; ++vk) {
-        p->cfg1[vk] = rows_mode ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk);
-        p->cfg2[vk] = rows_mode ? pick_cfg_rows(op->csc, vk) : pick_cfg(op->csc, vk);
+        p->cfg1[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk, B);
+        p->cfg2[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csc, vk) : pick_cfg(op->csc, vk, B);
     }
     // per-workgroup partial sums of each kernel kind
     const int64_t pgrid = phase_grid(pp);
@@ -695,18 +699,25 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
 // iterate, the weighted residual and the state, so the problem is unchanged.
 // ---------------------------------------------------------------------------
 
-std::vector<PassCfg> pass_candidates(const DevLayout &L, int vk)
+std::vector<PassCfg> pass_candidates(const DevLayout &L, int vk, int B)
 {
     std::vector<PassCfg> out;
-    for (int g : {1024, 2048, 4096}) {
-        PassCfg c = pick_cfg(L, vk);
-        c.grid = std::max(1, std::min({L.nblk, g, kMaxPassGrid}));
-        bool dup = false;
-        for (auto &o : out) dup |= (o.mode == c.mode && o.grid == c.grid);
-        if (!dup) out.push_back(c);
+    auto add = [&](const PassCfg &c) {
+        for (auto &o : out)
+            if (o.mode == c.mode && o.lpr == c.lpr && o.vec == c.vec && o.grid == c.grid) return;
+        out.push_back(c);
+    };
+    if (B == 1) {
+        for (int g : {1024, 2048, 4096}) {
+            PassCfg c = pick_cfg(L, vk, 1);
+            c.grid = std::max(1, std::min({L.nblk, g, kMaxPassGrid}));
+            add(c);
+        }
     }
-    for (int lpr : {2, 4, 8, 16, 32})
-        for (int vec : {4, 8})
+    const std::vector<int> lprs = (B == 1) ? std::vector<int>{2, 4, 8, 16, 32} : std::vector<int>{4, 8, 16};
+    const std::vector<int> vecs = (B == 1) ? std::vector<int>{4, 8} : std::vector<int>{(vk == VK_F32) ? 4 : 8};
+    for (int lpr : lprs)
+        for (int vec : vecs)
             for (int g : {1024, 2048, 4096}) {
                 PassCfg c;
                 c.mode = 0;
@@ -715,9 +726,7 @@ std::vector<PassCfg> pass_candidates(const DevLayout &L, int vk)
                 const int64_t rpb = kBlock / lpr;
                 const int64_t need = std::max<int64_t>(1, (L.rows + rpb - 1) / rpb);
                 c.grid = (int)std::min<int64_t>({need, (int64_t)g, (int64_t)kMaxPassGrid});
-                bool dup = false;
-                for (auto &o : out) dup |= (o.mode == 0 && o.lpr == lpr && o.vec == vec && o.grid == c.grid);
-                if (!dup) out.push_back(c);
+                add(c);
             }
     return out;
 }
@@ -754,7 +763,7 @@ int autotune_impl(smx_problem *p, int reps)
             // pass 1
             double best = 1e30;
             PassCfg bestc = p->cfg1[vk];
-            for (const PassCfg &c : pass_candidates(p->op->csr, vk)) {
+            for (const PassCfg &c : pass_candidates(p->op->csr, vk, p->B)) {
                 auto launch = [&]() {
                     hip_check(launch_pass1(c, view_for(p->op, false, vk), p->op->csr.blocks(), vk, xs.as<float>(),
                                            p->lower.as<float>(), p->upper.as<float>(), D, cs.as<float>(), st0, p->B, 1,
@@ -776,7 +785,7 @@ int autotune_impl(smx_problem *p, int reps)
             // pass 2 (the residual from the chosen pass 1)
             best = 1e30;
             PassCfg bestc2 = p->cfg2[vk];
-            for (const PassCfg &c : pass_candidates(p->op->csc, vk)) {
+            for (const PassCfg &c : pass_candidates(p->op->csc, vk, p->B)) {
                 auto launch = [&]() {
                     hip_check(launch_pass2(c, view_for(p->op, true, vk), p->op->csc.blocks(), vk, cs.as<float>(),
                                            xs.as<float>(), p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, st0,
@@ -842,10 +851,10 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
     return SMX_OK;
 }
 
-#define SMX_GUARD(body)                                                                                               \
+#define SMX_GUARD(...)                                                                                               \
     try {                                                                                                             \
         g_err.clear();                                                                                                \
-        body                                                                                                          \
+        __VA_ARGS__                                                                                                   \
     } catch (const HipError &h) {                                                                                     \
         return from_hip(h);                                                                                           \
     } catch (const std::bad_alloc &) {                                                                                \
@@ -1111,6 +1120,78 @@ int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need)
 {
     if (!p) return fail(SMX_EINVAL, "NULL problem");
     SMX_GUARD(return describe_impl(p, buf, cap, need);)
+}
+
+int smx_slot_load(smx_problem *p, int32_t slot, const float *lower, const float *upper, const float *x0,
+                  int32_t on_device, int64_t budget)
+{
+    if (!p || !lower || !upper || !x0) return fail(SMX_EINVAL, "NULL argument");
+    if (slot < 0 || slot >= p->B) return fail(SMX_EINVAL, "slot %d outside [0, %d)", slot, p->B);
+    if (budget < 0) return fail(SMX_EINVAL, "budget must be >= 0");
+    SMX_GUARD({
+        const int64_t m = p->m, n = p->n;
+        std::vector<float> lo = fetch(lower, m, on_device != 0), up = fetch(upper, m, on_device != 0);
+        for (int64_t i = 0; i < m; ++i) {
+            if (std::isnan(lo[i]) || std::isnan(up[i])) return fail(SMX_EINVAL, "NaN bound at %lld", (long long)i);
+            if (lo[i] > up[i]) return fail(SMX_EINVAL, "lower > upper at %lld", (long long)i);
+        }
+        std::vector<float> xs = fetch(x0, n, on_device != 0);
+        DBuf tmp;
+        tmp.alloc(sizeof(float) * std::max(m, n), "slot staging");
+        hipStream_t s = p->stream;
+        hip_check(hipMemcpyAsync(tmp.p, lo.data(), sizeof(float) * m, hipMemcpyHostToDevice, s), "slot bounds");
+        hip_check(launch_put_column(p->lower.as<float>(), tmp.as<float>(), m, p->B, slot, s), "slot bounds");
+        hip_check(hipMemcpyAsync(tmp.p, up.data(), sizeof(float) * m, hipMemcpyHostToDevice, s), "slot bounds");
+        hip_check(launch_put_column(p->upper.as<float>(), tmp.as<float>(), m, p->B, slot, s), "slot bounds");
+        hip_check(hipMemcpyAsync(tmp.p, xs.data(), sizeof(float) * n, hipMemcpyHostToDevice, s), "slot x0");
+        hip_check(launch_put_column(p->x.as<float>(), tmp.as<float>(), n, p->B, slot, s), "slot x0");
+        hip_check(launch_reset_slot(p->state(p->cur), slot, budget, s), "slot reset");
+        hip_check(hipStreamSynchronize(s), "slot load");
+        return SMX_OK;
+    })
+}
+
+int smx_slot_disable(smx_problem *p, int32_t slot)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    if (slot < 0 || slot >= p->B) return fail(SMX_EINVAL, "slot %d outside [0, %d)", slot, p->B);
+    SMX_GUARD({
+        hip_check(launch_disable_slot(p->state(p->cur), slot, p->stream), "slot disable");
+        return SMX_OK;
+    })
+}
+
+int smx_slot_status(smx_problem *p, int64_t *k, int32_t *live)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        hip_check(hipStreamSynchronize(p->stream), "slot status");
+        std::vector<SliceState> st(p->B);
+        hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost), "state");
+        for (int s = 0; s < p->B; ++s) {
+            if (k) k[s] = st[s].k;
+            if (live) live[s] = st[s].live;
+        }
+        return SMX_OK;
+    })
+}
+
+int smx_slot_get_x(smx_problem *p, int32_t slot, float *out, int32_t on_device)
+{
+    if (!p || !out) return fail(SMX_EINVAL, "NULL argument");
+    if (slot < 0 || slot >= p->B) return fail(SMX_EINVAL, "slot %d outside [0, %d)", slot, p->B);
+    SMX_GUARD({
+        if (on_device) {
+            hip_check(launch_get_column(out, p->x.as<float>(), p->n, p->B, slot, p->stream), "slot x");
+            return SMX_OK;
+        }
+        DBuf tmp;
+        tmp.alloc(sizeof(float) * p->n, "slot staging");
+        hip_check(launch_get_column(tmp.as<float>(), p->x.as<float>(), p->n, p->B, slot, p->stream), "slot x");
+        hip_check(hipMemcpyAsync(out, tmp.p, sizeof(float) * p->n, hipMemcpyDeviceToHost, p->stream), "slot x");
+        hip_check(hipStreamSynchronize(p->stream), "slot x");
+        return SMX_OK;
+    })
 }
 
 int smx_set_timing(smx_problem *p, int32_t enable)

@@ -516,6 +516,132 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
     if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Multi-slice passes (B right-hand sides sharing A, slice-interleaved
+// vectors).  A is read once for all slices; each lane keeps one float64
+// accumulator per slice and reads the B values of the gathered vector at an
+// index as B/4 vector loads.  The summation order of a slice does not depend
+// on the other slices, so a slice's result is the same whichever slices run
+// beside it.  A slice that is not live is neither read back nor written.
+// ---------------------------------------------------------------------------
+
+template <int B>
+__device__ inline void load_slices(const float *__restrict__ v, int idx, float (&out)[B])
+{
+    if constexpr (B % 4 == 0) {
+        const float4 *q = reinterpret_cast<const float4 *>(v + (long long)idx * B);
+#pragma unroll
+        for (int h = 0; h < B / 4; ++h) {
+            const float4 a = q[h];
+            out[4 * h + 0] = a.x; out[4 * h + 1] = a.y; out[4 * h + 2] = a.z; out[4 * h + 3] = a.w;
+        }
+    } else if constexpr (B == 2) {
+        const float2 a = *reinterpret_cast<const float2 *>(v + (long long)idx * 2);
+        out[0] = a.x; out[1] = a.y;
+    } else {
+#pragma unroll
+        for (int s = 0; s < B; ++s) out[s] = v[(long long)idx * B + s];
+    }
+}
+
+template <int LPR, int VEC, typename VT, int B>
+__device__ inline void row_dot_mm(const SpView &A, int beg, int end, int lane, const float *__restrict__ v,
+                                  double (&acc)[B])
+{
+#pragma unroll
+    for (int s = 0; s < B; ++s) acc[s] = 0.0;
+    for (int p = beg + lane * VEC; p < end; p += LPR * VEC) {
+        float val[VEC];
+        int id[VEC];
+        ValLoad<VT, VEC>::load(A.val, p, val);
+        idx_load<VEC>(A.idx, p, id);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            float xs[B];
+            load_slices<B>(v, id[e], xs);
+            const double a = (double)val[e];
+#pragma unroll
+            for (int s = 0; s < B; ++s) acc[s] = fma(a, (double)xs[s], acc[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < B; ++s) acc[s] = group_sum<LPR>(acc[s]);
+}
+
+template <int LPR, int VEC, typename VT, int B>
+__global__ __launch_bounds__(kBlock) void k_pass1_mm(SpView A, const float *__restrict__ x,
+                                                     const float *__restrict__ lower, const float *__restrict__ upper,
+                                                     const float *__restrict__ D, float *__restrict__ c,
+                                                     const SliceState *__restrict__ st, int query,
+                                                     double *__restrict__ partials)
+{
+    __shared__ double lds[4 * B];
+    __shared__ int live[B];
+    constexpr int RPB = kBlock / LPR;
+    if (threadIdx.x < B) live[threadIdx.x] = query ? 1 : st[threadIdx.x].live;
+    __syncthreads();
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    double pacc[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) pacc[s] = 0.0;
+    const long long stride = (long long)gridDim.x * RPB;
+    for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
+        const int beg = A.ptr[row], end = A.ptr[row + 1];
+        double acc[B];
+        row_dot_mm<LPR, VEC, VT, B>(A, beg, end, lane, x, acc);
+        if (lane == 0) {
+            const double d = (double)D[row];
+#pragma unroll
+            for (int s = 0; s < B; ++s) {
+                if (!live[s]) continue;
+                const double r = acc[s] * (double)A.vscale_inv;
+                const double t = fmin(fmax(r, (double)lower[row * B + s]), (double)upper[row * B + s]) - r;
+                const double dt = d * t;
+                c[row * B + s] = (float)dt;
+                pacc[s] += dt * t;
+            }
+        }
+    }
+    block_sum<B>(pacc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int s = 0; s < B; ++s) partials[(long long)s * gridDim.x + blockIdx.x] = pacc[s];
+    }
+}
+
+template <int LPR, int VEC, typename VT, int B>
+__global__ __launch_bounds__(kBlock) void k_pass2_mm(SpView At, const float *__restrict__ c, float *__restrict__ x,
+                                                     const float *__restrict__ lo, const float *__restrict__ hi,
+                                                     float lambda, const SliceState *__restrict__ st_in,
+                                                     SliceState *__restrict__ st_out,
+                                                     const double *__restrict__ part1, int nparts1, Hist h)
+{
+    __shared__ double lds[4];
+    __shared__ int live[B];
+    constexpr int RPB = kBlock / LPR;
+    if (threadIdx.x < B) live[threadIdx.x] = st_in[threadIdx.x].live;
+    __syncthreads();
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const long long stride = (long long)gridDim.x * RPB;
+    for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
+        const int beg = At.ptr[col], end = At.ptr[col + 1];
+        double acc[B];
+        row_dot_mm<LPR, VEC, VT, B>(At, beg, end, lane, c, acc);
+        if (lane == 0) {
+            const double l = (double)lo[col], u = (double)hi[col];
+#pragma unroll
+            for (int s = 0; s < B; ++s) {
+                if (!live[s]) continue;
+                const double z = fma((double)lambda, acc[s] * (double)At.vscale_inv, (double)x[col * B + s]);
+                x[col * B + s] = (float)fmin(fmax(z, l), u);
+            }
+        }
+    }
+    if (blockIdx.x == 0) finish_iteration(st_in, st_out, B, part1, nparts1, h, lds);
+}
+
 // Query: the proximity at the current x from pass 1's partials (query mode).
 __global__ __launch_bounds__(kBlock) void k_query_prox(SliceState *__restrict__ st, int B,
                                                        const double *__restrict__ partials, int nparts,
@@ -1029,6 +1155,52 @@ __global__ void k_init_state(SliceState *st, int B)
     st[s] = S;
 }
 
+// Column s of a slice-interleaved [rows x B] array, in or out.
+__global__ void k_put_column(float *__restrict__ dst, const float *__restrict__ src, long long rows, int B, int s)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (long long)gridDim.x * blockDim.x)
+        dst[i * B + s] = src[i];
+}
+
+__global__ void k_get_column(float *__restrict__ dst, const float *__restrict__ src, long long rows, int B, int s)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i * B + s];
+}
+
+// Slot s starts afresh: k = ell = restarts = 0, counters 0, `budget`
+// iterations to run (0 disables the slot).
+__global__ void k_reset_slot(SliceState *st, int s, long long budget)
+{
+    if (threadIdx.x != 0) return;
+    SliceState S = st[s];
+    S.f_cur = S.f_start = __longlong_as_double(0x7ff8000000000000LL);
+    S.gn = 0.0;
+    S.s_acc = 0.0;
+    S.prox = __longlong_as_double(0x7ff8000000000000LL);
+    S.k = 0;
+    S.k_end = budget;
+    S.ell = 0;
+    S.restarts = 0;
+    S.trials = S.accepts = S.cap_hits = 0;
+    S.n_done = 0;
+    S.phase = 0;
+    S.step_tried = 0;
+    S.trials_it = S.accepts_it = 0;
+    S.enabled = budget > 0 ? 1 : 0;
+    S.live = S.enabled;
+    S.applied = 0;
+    S.nonfinite = 0;
+    st[s] = S;
+}
+
+__global__ void k_disable_slot(SliceState *st, int s)
+{
+    if (threadIdx.x != 0) return;
+    st[s].enabled = 0;
+    st[s].live = 0;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1075,6 +1247,32 @@ hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_put_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_put_column, dim3(grid_for(rows, kBlock, 2048)), dim3(kBlock), 0, s, dst, src, (long long)rows, B,
+                       slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_get_column, dim3(grid_for(rows, kBlock, 2048)), dim3(kBlock), 0, s, dst, src, (long long)rows, B,
+                       slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_slot(SliceState *st, int slot, int64_t budget, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_slot, dim3(1), dim3(64), 0, s, st, slot, (long long)budget);
+    return hipGetLastError();
+}
+
+hipError_t launch_disable_slot(SliceState *st, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_disable_slot, dim3(1), dim3(64), 0, s, st, slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_state(SliceState *st, int B, hipStream_t s)
 {
     hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, B);
@@ -1109,11 +1307,46 @@ static hipError_t pass1_stream(const PassCfg &cfg, const SpView &A, const RowBlo
     return hipGetLastError();
 }
 
+template <typename VT, int VEC, int B>
+static hipError_t pass1_mm(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
+                           const float *upper, const float *D, float *c, const SliceState *st, int query,
+                           double *partials, hipStream_t s)
+{
+    const dim3 grid(cfg.grid), block(kBlock);
+    switch (cfg.lpr) {
+    case 4: hipLaunchKernelGGL((k_pass1_mm<4, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 8: hipLaunchKernelGGL((k_pass1_mm<8, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 16: hipLaunchKernelGGL((k_pass1_mm<16, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t pass1_mm_b(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
+                             const float *upper, const float *D, float *c, const SliceState *st, int B, int query,
+                             double *partials, hipStream_t s)
+{
+    switch (B) {
+    case 2: return pass1_mm<VT, VEC, 2>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    case 4: return pass1_mm<VT, VEC, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    case 8: return pass1_mm<VT, VEC, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    case 16: return pass1_mm<VT, VEC, 16>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    case 32: return pass1_mm<VT, VEC, 32>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
                         const float *lower, const float *upper, const float *D, float *c, const SliceState *st, int B,
                         int query, double *partials, hipStream_t s)
 {
-    if (B != 1 || cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
+    if (B > 1) {
+        if (vk == VK_F32) return pass1_mm_b<float, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
+        if (vk == VK_BF16) return pass1_mm_b<Bf16Tag, 8>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
+        return pass1_mm_b<F16Tag, 8>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
+    }
     if (cfg.mode == 1) {
         if (vk == VK_F32) return pass1_stream<float, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
         if (vk == VK_BF16) return pass1_stream<Bf16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
@@ -1161,12 +1394,48 @@ static hipError_t pass2_stream(const PassCfg &cfg, const SpView &At, const RowBl
     return hipGetLastError();
 }
 
+template <typename VT, int VEC, int B>
+static hipError_t pass2_mm(const PassCfg &cfg, const SpView &At, const float *c, float *x, const float *lo,
+                           const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
+                           const double *part1, int nparts1, Hist h, hipStream_t s)
+{
+    const dim3 grid(cfg.grid), block(kBlock);
+#define SMX_P2MM(L) hipLaunchKernelGGL((k_pass2_mm<L, VEC, VT, B>), grid, block, 0, s, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h)
+    switch (cfg.lpr) {
+    case 4: SMX_P2MM(4); break;
+    case 8: SMX_P2MM(8); break;
+    case 16: SMX_P2MM(16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_P2MM
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t pass2_mm_b(const PassCfg &cfg, const SpView &At, const float *c, float *x, const float *lo,
+                             const float *hi, float lambda, const SliceState *st_in, SliceState *st_out, int B,
+                             const double *part1, int nparts1, Hist h, hipStream_t s)
+{
+    switch (B) {
+    case 2: return pass2_mm<VT, VEC, 2>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    case 4: return pass2_mm<VT, VEC, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    case 8: return pass2_mm<VT, VEC, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    case 16: return pass2_mm<VT, VEC, 16>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    case 32: return pass2_mm<VT, VEC, 32>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
                         const float *lo, const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
                         int B, const double *part1, int nparts1, Hist h, hipStream_t s)
 {
-    if (B != 1 || cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid)
-        return hipErrorInvalidValue;
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
+    if (B > 1) {
+        if (vk == VK_F32) return pass2_mm_b<float, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_BF16) return pass2_mm_b<Bf16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
+        return pass2_mm_b<F16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
+    }
     if (cfg.mode == 1) {
         if (vk == VK_F32) return pass2_stream<float, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
         if (vk == VK_BF16) return pass2_stream<Bf16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);

@@ -97,6 +97,11 @@ hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t count, hipStr
 hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float scale, hipStream_t s);
 hipError_t launch_init_state(SliceState *st, int B, hipStream_t s);
 hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s);
+// slots of a multi-slice problem (serving)
+hipError_t launch_put_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s);
+hipError_t launch_get_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s);
+hipError_t launch_reset_slot(SliceState *st, int slot, int64_t budget, hipStream_t s);
+hipError_t launch_disable_slot(SliceState *st, int slot, hipStream_t s);
 
 constexpr int kMaxPassGrid = 4096; // workgroups of a pass kernel (one proximity partial each)
 
