@@ -347,16 +347,14 @@ class Problem:
 
     # -- slots (serving) ---------------------------------------------------
     def slot_load(self, slot: int, lower, upper, x0, budget: int):
-        """Load one slot's bands and starting point; it then runs `budget` iterations."""
-        import torch
-
-        lo = _dev(np.asarray(lower, np.float32).reshape(-1) if not isinstance(lower, torch.Tensor) else lower,
-                  torch.float32, self.device)
-        up = _dev(np.asarray(upper, np.float32).reshape(-1) if not isinstance(upper, torch.Tensor) else upper,
-                  torch.float32, self.device)
-        xx = _dev(np.asarray(x0, np.float32).reshape(-1) if not isinstance(x0, torch.Tensor) else x0,
-                  torch.float32, self.device)
-        check(lib().smx_slot_load(self.handle, int(slot), _ptr(lo), _ptr(up), _ptr(xx), 1, int(budget)))
+        """Load one slot's bands and starting point (host arrays, copied in order
+        on the problem's stream); the slot then runs `budget` iterations."""
+        lo = np.ascontiguousarray(np.asarray(lower, np.float32).reshape(-1))
+        up = np.ascontiguousarray(np.asarray(upper, np.float32).reshape(-1))
+        xx = np.ascontiguousarray(np.asarray(x0, np.float32).reshape(-1))
+        assert lo.size == self.m and up.size == self.m and xx.size == self.n
+        check(lib().smx_slot_load(self.handle, int(slot), lo.ctypes.data, up.ctypes.data, xx.ctypes.data, 0,
+                                  int(budget)))
 
     def slot_disable(self, slot: int):
         check(lib().smx_slot_disable(self.handle, int(slot)))
@@ -366,6 +364,12 @@ class Problem:
         live = np.zeros(self.B, np.int32)
         check(lib().smx_slot_status(self.handle, k.ctypes.data, live.ctypes.data))
         return k, live
+
+    def slot_x_host(self, slot: int) -> np.ndarray:
+        """Slot iterate copied to the host [n] (waits for the problem's stream)."""
+        out = np.empty(self.n, np.float32)
+        check(lib().smx_slot_get_x(self.handle, int(slot), out.ctypes.data, 0))
+        return out
 
     def slot_x(self, slot: int):
         """Slot iterate as a device tensor [n]."""

@@ -627,3 +627,53 @@ def rt(
         meta=meta,
         **params,
     )
+
+
+# ---------------------------------------------------------------------------
+# Serving stream
+# ---------------------------------------------------------------------------
+
+def serving_mix(
+    sizes=(128, 256, 512),
+    n_requests: int = 64,
+    slices=(8, 32),
+    pool: int = 32,
+    K: int = 200,
+    rate_hz: float = 0.0,
+    seed: int = 5,
+    n_angles: int = 180,
+):
+    """A stream of CT solve requests for a serving run.
+
+    One operator per image size (parallel beam, `n_angles` angles); each request
+    picks a size uniformly, a slice count uniformly in `slices`, and that many
+    slices (own bands and starting point) from a pool of `pool` seeded phantoms
+    of that size.  Arrivals are Poisson with `rate_hz` (all at t = 0 when 0).
+    Returns (operators, requests): operators map a key to a dict of CSR arrays
+    and problem parameters; each request is a dict with op_key, lower [m,S],
+    upper [m,S], x0 [n,S], K and t_arrival.
+    """
+    rng = np.random.default_rng(seed)
+    ops = {}
+    pools = {}
+    for N in sizes:
+        w = ct(N=N, n_angles=n_angles, seed=seed * 100 + N, B=pool, K=K)
+        key = f"ct{N}"
+        ops[key] = dict(m=w.m, n=w.n, row_ptr=w.row_ptr, col_idx=w.col_idx, val=w.val,
+                        params=dict(box_lo=w.box_lo, box_hi=w.box_hi, lam=w.lam, obj=w.obj, tv_rows=w.tv_rows,
+                                    tv_cols=w.tv_cols, tv_eps=w.tv_eps, gamma=w.gamma, alpha=w.alpha,
+                                    n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials))
+        pools[key] = w
+    reqs = []
+    t = 0.0
+    for i in range(n_requests):
+        key = f"ct{sizes[rng.integers(len(sizes))]}"
+        S = int(rng.integers(slices[0], slices[1] + 1))
+        pick = rng.choice(pool, size=S, replace=S > pool)
+        w = pools[key]
+        if rate_hz > 0:
+            t += rng.exponential(1.0 / rate_hz)
+        reqs.append(dict(rid=i, op_key=key, lower=np.ascontiguousarray(w.lower[:, pick]),
+                         upper=np.ascontiguousarray(w.upper[:, pick]), x0=np.ascontiguousarray(w.x0[:, pick]),
+                         K=K, t_arrival=t if rate_hz > 0 else 0.0, pool_index=pick))
+    return ops, reqs, pools
