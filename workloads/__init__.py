@@ -14,6 +14,7 @@ synthetic stand-ins.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
@@ -101,11 +102,15 @@ def _csr_from_dense(A: np.ndarray):
 
 
 def _csr_matvec64(row_ptr, col_idx, val, x):
-    """Forward model used only to synthesise measurements (float64)."""
+    """Forward model used only to synthesise measurements (float64); x may be
+    [n] or [n, k]."""
+    import scipy.sparse as sp
+
     m = len(row_ptr) - 1
-    rows = np.repeat(np.arange(m), np.diff(row_ptr.astype(np.int64)))
-    prod = val.astype(np.float64) * x[col_idx]
-    return np.bincount(rows, weights=prod, minlength=m)
+    n = int(np.max(col_idx)) + 1 if col_idx.size else 1
+    n = max(n, x.shape[0])
+    A = sp.csr_matrix((val.astype(np.float64), col_idx, row_ptr.astype(np.int64)), shape=(m, n))
+    return A @ np.asarray(x, np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -677,3 +682,126 @@ def serving_mix(
                          upper=np.ascontiguousarray(w.upper[:, pick]), x0=np.ascontiguousarray(w.x0[:, pick]),
                          K=K, t_arrival=t if rate_hz > 0 else 0.0, pool_index=pick))
     return ops, reqs, pools
+
+
+# ---------------------------------------------------------------------------
+# Full-size radiotherapy matrix (C++ generator, same model as rt())
+# ---------------------------------------------------------------------------
+
+_RT_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rt_gen.cpp")
+_RT_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librtgen.so")
+
+
+def build_rt_generator(force: bool = False) -> str:
+    import subprocess
+
+    if force or not os.path.exists(_RT_LIB):
+        tmp = _RT_LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _RT_SRC])
+        os.replace(tmp, _RT_LIB)
+    return _RT_LIB
+
+
+def rt_large(
+    grid=(160, 160, 80),
+    n_beams: int = 9,
+    beamlets=(47, 47),
+    spacing: float = 3.4,
+    mu: float = 0.005,
+    rho: float = 2.5,
+    r_cut: float = 9.2,
+    seed: int = 4,
+    infeasible: bool = True,
+    K: int = 300,
+    variant: str = "default",
+) -> Workload:
+    """The rt() model at full size, generated row by row in C++ (OpenMP).
+
+    Defaults: 160 x 160 x 80 voxels (2.05M rows), 9 beams of 47 x 47 beamlets
+    (19,881 columns); spacing and cutoff give about 1 % density.  Structures,
+    bands, the infeasible duplicated overlap rows, the scaling to a mean target
+    dose of 1 and the summed-dose objective are those of rt().
+    """
+    import ctypes as C
+
+    lib = C.CDLL(build_rt_generator())
+
+    class _P(C.Structure):
+        _fields_ = [("X", C.c_int32), ("Y", C.c_int32), ("Z", C.c_int32), ("n_beams", C.c_int32),
+                    ("nbu", C.c_int32), ("nbw", C.c_int32), ("spacing", C.c_double), ("mu", C.c_double),
+                    ("rho", C.c_double), ("r_cut", C.c_double)]
+
+    X, Y, Z = grid
+    P = _P(X, Y, Z, n_beams, beamlets[0], beamlets[1], spacing, mu, rho, r_cut)
+    nv = X * Y * Z
+    n = n_beams * beamlets[0] * beamlets[1]
+    counts = np.zeros(nv, np.int64)
+    lib.rt_count(C.byref(P), counts.ctypes.data_as(C.POINTER(C.c_int64)))
+    row_ptr = np.zeros(nv + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    cols = np.empty(nnz, np.int32)
+    vals = np.empty(nnz, np.float64)
+    lib.rt_fill(C.byref(P), row_ptr.ctypes.data_as(C.POINTER(C.c_int64)), cols.ctypes.data_as(C.POINTER(C.c_int32)),
+                vals.ctypes.data_as(C.POINTER(C.c_double)))
+    # structures (as in rt())
+    ci = (np.arange(X) + 0.5) - X / 2.0
+    cj = (np.arange(Y) + 0.5) - Y / 2.0
+    ck = (np.arange(Z) + 0.5) - Z / 2.0
+    PX, PY, PZ = np.meshgrid(ci, cj, ck, indexing="ij")
+    PX, PY, PZ = PX.reshape(-1), PY.reshape(-1), PZ.reshape(-1)
+    rr = np.sqrt(PX**2 + PY**2 + PZ**2)
+    R_t = 0.25 * min(X, Y, 2 * Z)
+    target = rr <= R_t
+    oar = (np.hypot(PX - R_t * 1.1, PY) <= 0.45 * R_t) & (np.abs(PZ) <= 0.8 * R_t)
+    overlap = target & oar
+    nonempty = counts > 0
+    d1 = np.zeros(nv)
+    d1[nonempty] = np.add.reduceat(vals, row_ptr[:-1][nonempty])
+    scale = 1.0 / max(d1[target].mean(), 1e-30)
+    vals *= scale
+    val32 = vals.astype(np.float32)
+    del vals
+    up = np.where(oar, 0.5, 1.07)
+    lo = np.where(target, 0.95, -np.inf)
+    up = np.where(target & ~oar, 1.07, up)
+    c = np.bincount(cols, weights=val32.astype(np.float64), minlength=n)
+    lower, upper = lo.astype(np.float64), up.astype(np.float64)
+    meta = dict(n_target=int(target.sum()), n_oar=int(oar.sum()), n_overlap=int(overlap.sum()))
+    if infeasible and overlap.any():
+        dup = np.nonzero(overlap)[0]
+        lower[dup] = 0.95
+        upper[dup] = 1.07
+        seg = [np.arange(row_ptr[i], row_ptr[i + 1]) for i in dup]
+        take = np.concatenate(seg)
+        drp = np.zeros(dup.size + 1, np.int64)
+        np.cumsum(counts[dup], out=drp[1:])
+        row_ptr = np.concatenate([row_ptr, row_ptr[-1] + drp[1:]])
+        cols = np.concatenate([cols, cols[take]])
+        val32 = np.concatenate([val32, val32[take]])
+        lower = np.concatenate([lower, np.full(dup.size, -np.inf)])
+        upper = np.concatenate([upper, np.full(dup.size, 0.3)])
+    m = row_ptr.size - 1
+    assert row_ptr[-1] < 2**31
+    params = dict(gamma=1.0, alpha=0.99, n_red=1, restart_every=0)
+    if variant == "paper":
+        params = dict(gamma=1.0, alpha=0.99, n_red=1, restart_every=500)
+    return Workload(
+        name=f"rt{X}x{Y}x{Z}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr.astype(np.int32),
+        col_idx=cols,
+        val=val32,
+        lower=lower.astype(np.float32)[:, None],
+        upper=upper.astype(np.float32)[:, None],
+        box_lo=np.zeros(n, np.float32),
+        box_hi=np.full(n, np.inf, np.float32),
+        x0=np.zeros((n, 1), np.float32),
+        lam=1.0,
+        obj=OBJ_LINEAR,
+        linear_c=c.astype(np.float32),
+        K=K,
+        meta=meta,
+        **params,
+    )
