@@ -3,14 +3,24 @@
 A step is one outer iteration of Algorithm 1 over the whole workload: the
 perturbation phase (TV gradient, trial steps, acceptance, apply) followed by the
 feasibility step (pass 1: r = A z with the band clip and weights; pass 2:
-A^T of the weighted residual with the box).  The default workload is
-parallel-beam CT on a 256 x 256 image (180 angles x 363 detectors, about 15M
+A^T of the weighted residual with the box).  The headline workload is
+parallel-beam CT on a 256 x 256 image (180 angles x 363 detectors, 15.0M
 nonzeros, float32 A) with TV perturbations, 200 iterations.
 
 Prints one JSON line.  `value` is SM iterations per second of the float32 path
-with every input resident in HBM; the line also carries the reduced-precision
-(bf16) variant, the roofline of the dominant kernel measured with HIP events on
-the problem's stream, and the FP64 CPU oracle timed on this host.
+with every input resident in HBM.  The line also carries
+  variants    the bf16-storage path on the same workload;
+  roofline    the dominant pass kernel: algorithmic bytes per launch / its mean
+              launch time (HIP events on the problem's stream), HBM traffic
+              from the committed counter table when it matches the kernels;
+  cpu_baseline the FP64 oracle on this host (the same 200 iterations);
+  batched     8 and 32 CT slices sharing A in one multi-slice problem;
+  serving     a stream of 64 mixed CT solves (128^2/256^2/512^2, 8-32 slices
+              each) through the continuous-batching server: p50/p99 latency
+              and aggregate slice iterations per second;
+  hbm_config  the radiotherapy configuration (2.06M x 19,881, ~400M
+              nonzeros), whose operator does not fit any cache: pass GB/s
+              against the 8 TB/s HBM peak.
 """
 from __future__ import annotations
 
@@ -26,10 +36,20 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 PMC_TABLE = os.path.join(ROOT, "profiles", "pmc_ct256_pass_traffic.json")
+VAL_BYTES = {"f32": 4, "bf16": 2, "f16": 2}
 
 
-def kernel_name(pass_no, shape, storage):
+def alg_bytes(m, n, nnz, val_bytes, B=1, idx_bytes=4):
+    """Algorithmic bytes of one launch of each pass: A once, each vector once."""
+    p1 = nnz * (val_bytes + idx_bytes) + 4 * (m + 1) + 4 * m + B * (8 * m + 4 * m + 4 * n)
+    p2 = nnz * (val_bytes + idx_bytes) + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
+    return p1, p2
+
+
+def kernel_name(pass_no, shape, storage, B=1):
     vt = {"f32": "float", "bf16": "smx::Bf16Tag", "f16": "smx::F16Tag"}[storage]
+    if B > 1:
+        return f"smx::k_pass{pass_no}_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
     if shape["mode"] == "stream":
         return f"smx::k_pass{pass_no}_stream<{shape['vec']}, {vt}>"
     return f"smx::k_pass{pass_no}<{shape['lpr']}, {shape['vec']}, {vt}>"
@@ -37,13 +57,11 @@ def kernel_name(pass_no, shape, storage):
 
 def measured_traffic(name):
     """HBM bytes per launch from the committed counter table, or None when the
-    table is missing, was taken on another workload, or on other kernel code."""
+    table is missing, was taken on other kernel code, or lacks the kernel."""
     try:
-        import json as _json
-
         from paper_2606_27086_amd.pmc_summary import kernel_source_hash
 
-        tab = _json.load(open(PMC_TABLE))
+        tab = json.load(open(PMC_TABLE))
         if tab.get("kernel_source_sha256") != kernel_source_hash():
             return None
         k = tab["kernels"].get(name)
@@ -52,32 +70,14 @@ def measured_traffic(name):
         return None
 
 
-def alg_bytes(m, n, nnz, val_bytes, idx_bytes=4):
-    """Algorithmic bytes of one launch of each pass (one slice)."""
-    p1 = nnz * (val_bytes + idx_bytes) + 4 * (m + 1) + 8 * m + 4 * m + 4 * m + 4 * n
-    p2 = nnz * (val_bytes + idx_bytes) + 4 * (n + 1) + 4 * m + 8 * n + 8 * n
-    return p1, p2
-
-
-def make_workload(name):
-    import workloads as W
-
-    if name == "ct256":
-        return W.ct(N=256, seed=2, K=200), "ct256_parallel_beam_180x363_tv"
-    if name == "seismic":
-        return W.seismic(seed=3, K=500), "seismic_200x400_100src_200rec_tv"
-    if name == "dense":
-        return W.dense_small(), "dense_256x128_sqnorm"
-    raise SystemExit(f"unknown workload {name}")
-
-
-def time_variant(smx, w, storage, steps, warmup, graph=True, tune=True):
+def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True):
+    """Timed run of `steps` iterations (inputs resident in HBM), then the same
+    iterations eagerly with HIP events around each pass launch."""
     import torch
 
     p = smx.problem_from_workload(w, storage=storage, refine_iters=0)
     shapes = p.autotune(reps=10) if tune else p.describe()
-    # warm-up (also captures the graphs)
-    p.run(warmup, perturb=True, graph=graph)
+    p.run(warmup, perturb=True, graph=graph)  # also captures the graphs
     p.sync()
     p.reset(w.x0)
     torch.cuda.synchronize()
@@ -87,7 +87,6 @@ def time_variant(smx, w, storage, steps, warmup, graph=True, tune=True):
     dt = time.perf_counter() - t0
     p.sync()
     prox, obj = p.query()
-    # kernel durations: the same iterations again, eager, HIP events around each pass
     p.reset(w.x0)
     p.set_timing(True)
     p.run(steps, perturb=True, graph=False)
@@ -96,7 +95,26 @@ def time_variant(smx, w, storage, steps, warmup, graph=True, tune=True):
     p.set_timing(False)
     p.close()
     return dict(seconds=dt, it_s=steps / dt, ms_per_step=1e3 * dt / steps, pass1_ms=t1, pass2_ms=t2, launches=n,
-                prox=float(prox[0]), obj=float(obj[0]), shapes=shapes)
+                prox=[float(v) for v in prox], obj=[float(v) for v in obj], shapes=shapes[storage])
+
+
+def summarise(w, r, storage, B=1):
+    c1, c2 = alg_bytes(w.m, w.n, w.nnz, VAL_BYTES[storage], B)
+    return dict(it_s=round(r["it_s"], 2), slice_it_s=round(r["it_s"] * B, 2), ms_per_step=round(r["ms_per_step"], 5),
+                pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
+                pass1_gbs=round(c1 / (r["pass1_ms"] * 1e-3) / 1e9, 1),
+                pass2_gbs=round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1), launch=r["shapes"])
+
+
+def roofline_of(w, r, storage, B=1):
+    b1, b2 = alg_bytes(w.m, w.n, w.nnz, VAL_BYTES[storage], B)
+    t1, t2 = r["pass1_ms"], r["pass2_ms"]
+    dpass, dbytes, dms = (1, b1, t1) if t1 >= t2 else (2, b2, t2)
+    achieved = dbytes / (dms * 1e-3) / 1e9
+    kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], storage, B)
+    return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname), algorithmic_bytes=int(dbytes),
+                both_passes_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
 
 
 def cpu_baseline(w, K):
@@ -112,67 +130,118 @@ def cpu_baseline(w, K):
                 prox=P.proximity(x), obj=P.objective(x))
 
 
+def section_batched(smx, steps, warmup, tune):
+    import workloads as W
+
+    out = {}
+    for B, storage in ((8, "f32"), (8, "bf16"), (32, "bf16")):
+        w = W.ct(N=256, seed=2, B=B, K=200)
+        r = time_problem(smx, w, storage, steps, warmup, tune=tune)
+        out[f"ct256_B{B}_{storage}"] = summarise(w, r, storage, B)
+    return out
+
+
+def section_serving(smx, tune):
+    import numpy as np
+
+    import paper_2606_27086_amd.serve as srv
+    import workloads as W
+
+    ops, reqs, _ = W.serving_mix(sizes=(128, 256, 512), n_requests=64, slices=(8, 32), pool=32, K=200, seed=5)
+    specs = {k: srv.OperatorSpec(key=k, m=o["m"], n=o["n"], row_ptr=o["row_ptr"], col_idx=o["col_idx"], val=o["val"],
+                                 params=o["params"]) for k, o in ops.items()}
+    server = srv.Server(specs, hbm_budget=200 << 30, slots=32, chunk=10, storage="bf16", autotune=tune)
+    warm = []
+    for i, k in enumerate(sorted(ops)):  # groups created, tuned and graphs captured before timing
+        r = next(r for r in reqs if r["op_key"] == k)
+        warm.append(srv.Request(rid=-1 - i, op_key=k, lower=r["lower"][:, :1], upper=r["upper"][:, :1],
+                                x0=r["x0"][:, :1], K=20))
+    server.run(warm)
+    server.done.clear()
+
+    def requests():
+        return [srv.Request(rid=r["rid"], op_key=r["op_key"], lower=r["lower"], upper=r["upper"], x0=r["x0"],
+                            K=r["K"], t_arrival=0.0) for r in reqs]
+
+    def clean(d):
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+
+    burst = server.run(requests())
+    server.done.clear()
+    rate = 0.8 * burst["requests"] / burst["elapsed_s"]
+    rq = requests()
+    rng = np.random.default_rng(1)
+    t = 0.0
+    for r in rq:
+        t += rng.exponential(1.0 / rate)
+        r.t_arrival = t
+    poisson = server.run(rq)
+    server.close()
+    return dict(workload="64 CT solves: 128^2/256^2/512^2, 8-32 slices each, K=200, bf16 A, 32 slots per operator",
+                burst=clean(burst), poisson=dict(rate_hz=round(rate, 3), **clean(poisson)))
+
+
+def section_hbm(smx, tune):
+    import workloads as W
+
+    t0 = time.time()
+    w = W.rt_large(seed=4, K=300)
+    gen = time.time() - t0
+    out = dict(workload="radiotherapy 160x160x80 voxels, 9 beams x 47x47 beamlets, linear dose objective",
+               m=w.m, n=w.n, nnz=w.nnz, generate_s=round(gen, 1))
+    for storage in ("f32", "bf16"):
+        t0 = time.time()
+        r = time_problem(smx, w, storage, 100, 5, tune=tune)
+        s = summarise(w, r, storage)
+        s["roofline"] = roofline_of(w, r, storage)
+        s["wall_s"] = round(time.time() - t0, 1)
+        out[storage] = s
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ct256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--storages", default="f32,bf16")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--sections", default="batched,serving,hbm",
+                    help="extra sections beside the headline: batched,serving,hbm (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this benchmark runs on one GPU only: the method's single-GPU path is what is built "
-              "(the multi-GPU row-sharded design is documented, not built)", file=sys.stderr)
+        print("this benchmark runs on one GPU: the single-GPU path is what is built "
+              "(the row-sharded multi-GPU design is documented, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
     import paper_2606_27086_amd as smx
+    import workloads as W
 
     smx.lib()
     torch.cuda.set_device(0)
-    w, wname = make_workload(args.workload)
+    tune = not args.no_tune
+    w = W.ct(N=256, seed=2, K=200)
+    wname = "ct256_parallel_beam_180x363_tv"
     graph = not args.no_graph
-    results = {}
-    for st in args.storages.split(","):
-        results[st] = time_variant(smx, w, st, args.steps, args.warmup, graph=graph, tune=not args.no_tune)
-    main_r = results["f32"] if "f32" in results else next(iter(results.values()))
-    main_st = "f32" if "f32" in results else next(iter(results))
-    vb = {"f32": 4, "bf16": 2, "f16": 2}[main_st]
-    b1, b2 = alg_bytes(w.m, w.n, w.nnz, vb)
-    t1, t2 = main_r["pass1_ms"], main_r["pass2_ms"]
-    if t1 >= t2:
-        dom, dbytes, dms, dpass = "pass1_csr_clip", b1, t1, 1
-    else:
-        dom, dbytes, dms, dpass = "pass2_csc_box", b2, t2, 2
-    achieved = dbytes / (dms * 1e-3) / 1e9
-    kname = kernel_name(dpass, main_r["shapes"][main_st][f"pass{dpass}"], main_st)
-    roofline = dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname),
-                    algorithmic_bytes=int(dbytes), both_passes_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
-    variants = {}
+    results = {st: time_problem(smx, w, st, args.steps, args.warmup, graph=graph, tune=tune) for st in ("f32", "bf16")}
+    main_r = results["f32"]
+    variants = {st: summarise(w, r, st) for st, r in results.items()}
     for st, r in results.items():
-        vbs = {"f32": 4, "bf16": 2, "f16": 2}[st]
-        c1, c2 = alg_bytes(w.m, w.n, w.nnz, vbs)
-        variants[st] = dict(it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5),
-                            pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
-                            pass1_gbs=round(c1 / (r["pass1_ms"] * 1e-3) / 1e9, 1),
-                            pass2_gbs=round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1),
-                            prox=r["prox"], obj=r["obj"], launch=r["shapes"].get(st))
+        variants[st]["prox"], variants[st]["obj"] = r["prox"][0], r["obj"][0]
     cpu = None
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, min(args.steps, w.K))
         cpu = dict(value=round(cb["value"], 3), unit=cb["unit"], cores=cb["cores"], kind="oracle",
                    sample=cb["sample"], seconds=round(cb["seconds"], 2))
-        for st, r in results.items():
-            if args.steps == w.K:
-                variants[st]["prox_rel_err_vs_oracle"] = abs(r["prox"] - cb["prox"]) / abs(cb["prox"])
-                variants[st]["obj_rel_err_vs_oracle"] = abs(r["obj"] - cb["obj"]) / abs(cb["obj"])
+        if args.steps == w.K:
+            for st, r in results.items():
+                variants[st]["prox_rel_err_vs_oracle"] = abs(r["prox"][0] - cb["prox"]) / abs(cb["prox"])
+                variants[st]["obj_rel_err_vs_oracle"] = abs(r["obj"][0] - cb["obj"]) / abs(cb["obj"])
     line = {
-        "metric": "SM iterations/s (Ax/A^T r passes, FP32 vs BF16-A)",
+        "metric": "SM iterations/s (Ax/A^T r passes, FP32 vs BF16-A); p50/p99 solve latency",
         "value": round(main_r["it_s"], 2),
         "unit": "SM iterations/s",
         "n_gpus": 1,
@@ -182,14 +251,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": main_st,
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wname, "m": w.m, "n": w.n, "nnz": w.nnz, "B": w.B, "K": w.K,
-                   "graph": graph, "storage": main_st},
-        "roofline": roofline,
+        "config": {"workload": wname, "m": w.m, "n": w.n, "nnz": w.nnz, "B": w.B, "K": w.K, "graph": graph,
+                   "storage": "f32"},
+        "roofline": roofline_of(w, main_r, "f32"),
         "cpu_baseline": cpu,
         "variants": variants,
     }
+    sections = [s for s in args.sections.split(",") if s]
+    if "batched" in sections:
+        line["batched"] = section_batched(smx, 100, 10, tune)
+    if "serving" in sections:
+        line["serving"] = section_serving(smx, tune)
+    if "hbm" in sections:
+        line["hbm_config"] = section_hbm(smx, tune)
     print(json.dumps(line), flush=True)
 
 
