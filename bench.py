@@ -36,18 +36,23 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 PMC_TABLE = os.path.join(ROOT, "profiles", "pmc_ct256_pass_traffic.json")
-VAL_BYTES = {"f32": 4, "bf16": 2, "f16": 2}
+# bytes per stored entry (value + index) and the kernels' value-type tag, by format
+ENTRY_BYTES = {"f32+i32": 8, "bf16+i32": 6, "f16+i32": 6, "bf16+u16": 4, "f16+u16": 4}
+VALUE_TAG = {"f32+i32": "float", "bf16+i32": "smx::Bf16Tag", "f16+i32": "smx::F16Tag",
+             "bf16+u16": "smx::Bf16PTag", "f16+u16": "smx::F16PTag"}
 
 
-def alg_bytes(m, n, nnz, val_bytes, B=1, idx_bytes=4):
-    """Algorithmic bytes of one launch of each pass: A once, each vector once."""
-    p1 = nnz * (val_bytes + idx_bytes) + 4 * (m + 1) + 4 * m + B * (8 * m + 4 * m + 4 * n)
-    p2 = nnz * (val_bytes + idx_bytes) + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
+def alg_bytes(m, n, nnz, shapes, B=1):
+    """Algorithmic bytes of one launch of each pass: A once in the format that
+    pass reads, each vector once."""
+    e1, e2 = ENTRY_BYTES[shapes["pass1"]["format"]], ENTRY_BYTES[shapes["pass2"]["format"]]
+    p1 = nnz * e1 + 4 * (m + 1) + 4 * m + B * (8 * m + 4 * m + 4 * n)
+    p2 = nnz * e2 + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
     return p1, p2
 
 
-def kernel_name(pass_no, shape, storage, B=1):
-    vt = {"f32": "float", "bf16": "smx::Bf16Tag", "f16": "smx::F16Tag"}[storage]
+def kernel_name(pass_no, shape, B=1):
+    vt = VALUE_TAG[shape["format"]]
     if B > 1:
         return f"smx::k_pass{pass_no}_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
     if shape["mode"] == "stream":
@@ -99,7 +104,7 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True):
 
 
 def summarise(w, r, storage, B=1):
-    c1, c2 = alg_bytes(w.m, w.n, w.nnz, VAL_BYTES[storage], B)
+    c1, c2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B)
     return dict(it_s=round(r["it_s"], 2), slice_it_s=round(r["it_s"] * B, 2), ms_per_step=round(r["ms_per_step"], 5),
                 pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
                 pass1_gbs=round(c1 / (r["pass1_ms"] * 1e-3) / 1e9, 1),
@@ -107,11 +112,11 @@ def summarise(w, r, storage, B=1):
 
 
 def roofline_of(w, r, storage, B=1):
-    b1, b2 = alg_bytes(w.m, w.n, w.nnz, VAL_BYTES[storage], B)
+    b1, b2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B)
     t1, t2 = r["pass1_ms"], r["pass2_ms"]
     dpass, dbytes, dms = (1, b1, t1) if t1 >= t2 else (2, b2, t2)
     achieved = dbytes / (dms * 1e-3) / 1e9
-    kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], storage, B)
+    kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], B)
     return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname), algorithmic_bytes=int(dbytes),
                 both_passes_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))

@@ -132,7 +132,11 @@ const char *smx_last_error(void);
  * column-major copy for A^T), computes the float64 row norms ||a_i||^2 from the
  * stored values, and, for SMX_STORE_BF16/F16, a reduced-precision copy.  With
  * keep_f32 != 0 a reduced-precision operator also keeps the float32 copy used
- * by refinement iterations.  The caller may free its buffers on return.
+ * by refinement iterations.  A reduced-precision layout whose index range fits
+ * in 16 bits (the CSR when n <= 65536, the column copy when m <= 65536) is
+ * also held packed: each entry one 32-bit word, value in the low half and
+ * index in the high half; the passes read that copy, 4 bytes per entry.
+ * The caller may free its buffers on return.
  * Errors: SMX_EINVAL for m or n < 1, nnz != row_ptr[m], a decreasing row_ptr,
  * a column index outside [0,n), a non-finite value, or sizes beyond 2^31-1
  * entries; SMX_ENOMEM when device memory runs out (nothing is leaked).
@@ -145,7 +149,8 @@ int smx_operator_create(const smx_csr *A, int32_t value_storage, int32_t keep_f3
 int smx_operator_destroy(smx_operator *op);
 
 /* Device bytes the operator would take for A of this shape and storage,
- * without allocating anything. */
+ * without allocating anything (an upper bound: row and column padding is
+ * counted at its maximum). */
 int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32,
                            size_t *bytes);
 

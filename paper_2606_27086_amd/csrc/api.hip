@@ -144,7 +144,7 @@ std::vector<int32_t> build_row_blocks(const std::vector<int32_t> &ptr, int64_t r
 
 struct DevLayout {
     int64_t rows = 0, slots = 0;
-    DBuf ptr, idx, val32, val16, rowblk;
+    DBuf ptr, idx, val32, val16, packed, rowblk; // packed: 16-bit value | 16-bit index << 16
     int nblk = 0;
     float f16_scale = 1.f;
     RowBlocks blocks() const
@@ -159,16 +159,21 @@ struct DevLayout {
         SpView v;
         v.ptr = ptr.as<int32_t>();
         v.idx = idx.as<int32_t>();
-        v.val = (vk == VK_F32) ? val32.p : val16.p;
+        v.val = (vk == VK_F32) ? val32.p : ((vk == VK_BF16P || vk == VK_F16P) ? packed.p : val16.p);
         v.rows = rows;
-        v.vscale_inv = (vk == VK_F16) ? 1.f / f16_scale : 1.f;
+        v.vscale_inv = (vk == VK_F16 || vk == VK_F16P) ? 1.f / f16_scale : 1.f;
         return v;
     }
 };
 
-size_t layout_bytes(int64_t rows, int64_t slots, bool f32, bool lp)
+// Device bytes of one layout: offsets, then per entry the 32-bit index and value
+// when float32 is kept, and the reduced-precision value either alone (beside
+// the index) or packed with a 16-bit index into one word.
+size_t layout_bytes(int64_t rows, int64_t slots, bool f32, bool lp, bool packed)
 {
-    return size_t(rows + 1) * 4 + size_t(slots) * 4 + (f32 ? size_t(slots) * 4 : 0) + (lp ? size_t(slots) * 2 : 0);
+    const bool idx32 = f32 || !packed;
+    return size_t(rows + 1) * 4 + (idx32 ? size_t(slots) * 4 : 0) + (f32 ? size_t(slots) * 4 : 0) +
+           (lp ? size_t(slots) * (packed ? 4 : 2) : 0);
 }
 
 float f16_scale_for(const std::vector<float> &v)
@@ -214,6 +219,7 @@ struct smx_problem {
     Hist hist{};
     int hist_cap = 0;
     PassCfg cfg1[3]{}, cfg2[3]{};
+    int fmt1[3] = {0, 1, 2}, fmt2[3] = {0, 1, 2}; // stored format each pass reads, per value kind
     // captured graphs keyed by (value kind, perturb, iterations)
     std::map<long long, hipGraphExec_t> graphs;
     hipStream_t capture_stream = nullptr; // private stream graphs are captured on
@@ -306,7 +312,7 @@ void upload(DBuf &b, const std::vector<T> &h, hipStream_t s, const char *what)
     hip_check(hipStreamSynchronize(s), what);
 }
 
-void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, bool keep32, int lp, hipStream_t s)
+void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, int64_t index_range, bool keep32, int lp, hipStream_t s)
 {
     D.rows = rows;
     D.slots = H.slots;
@@ -325,8 +331,18 @@ void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, bool keep32, int l
             D.f16_scale = f16_scale_for(H.val);
             hip_check(launch_to_f16(D.val32.as<float>(), D.val16.as<uint16_t>(), H.slots, D.f16_scale, s), "to f16");
         }
+        const bool pack = index_range <= 65536; // one 32-bit word per entry: value and index
+        if (pack) {
+            D.packed.alloc(sizeof(uint32_t) * std::max<int64_t>(H.slots, 1), "allocate packed entries");
+            hip_check(launch_pack16(D.val16.as<uint16_t>(), D.idx.as<int32_t>(), D.packed.as<uint32_t>(), H.slots, s),
+                      "pack entries");
+        }
         hip_check(hipStreamSynchronize(s), "convert values");
         if (!keep32) D.val32.release();
+        if (pack) { // the packed words replace the separate reduced-precision values
+            D.val16.release();
+            if (!keep32) D.idx.release();
+        }
     }
     // release host copies early
     std::vector<int32_t>().swap(H.ptr);
@@ -378,14 +394,14 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
         if (!pad_rows(m, rp64.data(), ci.data(), va.data(), H)) return fail(SMX_EINVAL, "padded CSR exceeds 2^31 entries");
         std::vector<int32_t>().swap(ci);
         std::vector<float>().swap(va);
-        upload_layout(op->csr, H, m, op->has_f32, lp, s);
+        upload_layout(op->csr, H, m, n, op->has_f32, lp, s);
     }
     {
         HostLayout H;
         if (!pad_rows(n, cp.data(), ri.data(), cv.data(), H)) return fail(SMX_EINVAL, "padded CSC exceeds 2^31 entries");
         std::vector<int32_t>().swap(ri);
         std::vector<float>().swap(cv);
-        upload_layout(op->csc, H, n, op->has_f32, lp, s);
+        upload_layout(op->csc, H, n, m, op->has_f32, lp, s);
     }
     if (op->has_f32) {
         op->q32.alloc(sizeof(double) * m, "row norms");
@@ -393,11 +409,12 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
     }
     if (lp != VK_F32) {
         op->q16.alloc(sizeof(double) * m, "row norms (reduced precision)");
-        hip_check(launch_rownorm(op->csr.view(lp), lp, op->q16.as<double>(), s), "row norms (reduced precision)");
+        const int fmt = op->csr.packed.p ? (lp == VK_BF16 ? VK_BF16P : VK_F16P) : lp; // the copy the passes read
+        hip_check(launch_rownorm(op->csr.view(fmt), fmt, op->q16.as<double>(), s), "row norms (reduced precision)");
     }
     hip_check(hipStreamSynchronize(s), "operator setup");
-    op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32) +
-                layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32) +
+    op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32, op->csr.packed.p != nullptr) +
+                layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32, op->csc.packed.p != nullptr) +
                 size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0));
     *out = op.release();
     return SMX_OK;
@@ -450,16 +467,17 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
         p->ev_used += 4;
         hip_check(hipEventRecord(e[0], s), "event");
     }
-    hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), p->op->csr.blocks(), vk, p->x.as<float>(),
-                           p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(), p->state(cur), p->B, 0,
+    hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
+                           p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(),
+                           p->state(cur), p->B, 0,
                            p->part_pass.as<double>(), s),
               "pass 1");
     if (timed) {
         hip_check(hipEventRecord(e[1], s), "event");
         hip_check(hipEventRecord(e[2], s), "event");
     }
-    hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, vk), p->op->csc.blocks(), vk, p->c.as<float>(),
-                           p->x.as<float>(),
+    hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
+                           p->c.as<float>(), p->x.as<float>(),
                            p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, p->state(cur), p->state(cur ^ 1),
                            p->B, p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
               "pass 2");
@@ -658,6 +676,11 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->D16.alloc(sizeof(float) * m, "D (reduced precision)");
         hip_check(launch_make_D(op->q16.as<double>(), p->w.as<double>(), p->D16.as<float>(), m, s), "D");
     }
+    if (const int lk = op->lp_kind(); lk != VK_F32) { // the packed entries where the index range allows
+        const int pk = (lk == VK_BF16) ? VK_BF16P : VK_F16P;
+        p->fmt1[lk] = op->csr.packed.p ? pk : lk;
+        p->fmt2[lk] = op->csc.packed.p ? pk : lk;
+    }
     const char *mode_env = getenv("SMX_PASS_MODE"); // "rows" selects the lanes-per-row kernels
     const bool rows_mode = mode_env && std::strcmp(mode_env, "rows") == 0;
     for (int vk = 0; vk < 3; ++vk) {
@@ -765,7 +788,8 @@ int autotune_impl(smx_problem *p, int reps)
             PassCfg bestc = p->cfg1[vk];
             for (const PassCfg &c : pass_candidates(p->op->csr, vk, p->B)) {
                 auto launch = [&]() {
-                    hip_check(launch_pass1(c, view_for(p->op, false, vk), p->op->csr.blocks(), vk, xs.as<float>(),
+                    hip_check(launch_pass1(c, view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
+                                           xs.as<float>(),
                                            p->lower.as<float>(), p->upper.as<float>(), D, cs.as<float>(), st0, p->B, 1,
                                            p->part_query.as<double>(), s),
                               "tuning pass 1");
@@ -787,7 +811,8 @@ int autotune_impl(smx_problem *p, int reps)
             PassCfg bestc2 = p->cfg2[vk];
             for (const PassCfg &c : pass_candidates(p->op->csc, vk, p->B)) {
                 auto launch = [&]() {
-                    hip_check(launch_pass2(c, view_for(p->op, true, vk), p->op->csc.blocks(), vk, cs.as<float>(),
+                    hip_check(launch_pass2(c, view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
+                                           cs.as<float>(),
                                            xs.as<float>(), p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, st0,
                                            st1, p->B, p->part_query.as<double>(), bestc.grid, none, s),
                               "tuning pass 2");
@@ -820,6 +845,17 @@ int autotune_impl(smx_problem *p, int reps)
     return SMX_OK;
 }
 
+const char *fmt_name(int f)
+{
+    switch (f) {
+    case VK_F32: return "f32+i32";
+    case VK_BF16: return "bf16+i32";
+    case VK_F16: return "f16+i32";
+    case VK_BF16P: return "bf16+u16";
+    default: return "f16+u16";
+    }
+}
+
 int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
 {
     std::string out = "{";
@@ -828,13 +864,13 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
     for (int vk = 0; vk < 3; ++vk) {
         if (vk == VK_F32 && !p->op->has_f32) continue;
         if (vk != VK_F32 && p->op->lp_kind() != vk) continue;
-        char tmp[256];
+        char tmp[512];
         const PassCfg &a = p->cfg1[vk], &b = p->cfg2[vk];
         snprintf(tmp, sizeof tmp,
-                 "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d}, "
-                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d}}",
-                 first ? "" : ", ", names[vk], a.mode ? "stream" : "rows", a.lpr, a.vec, a.grid,
-                 b.mode ? "stream" : "rows", b.lpr, b.vec, b.grid);
+                 "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
+                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}}",
+                 first ? "" : ", ", names[vk], a.mode ? "stream" : "rows", a.lpr, a.vec, a.grid, fmt_name(p->fmt1[vk]),
+                 b.mode ? "stream" : "rows", b.lpr, b.vec, b.grid, fmt_name(p->fmt2[vk]));
         out += tmp;
         first = false;
     }
@@ -896,7 +932,8 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
     const bool f32 = !lp || keep_f32;
     // upper bound on padding: kRowAlign-1 entries per row and per column
     const int64_t s1 = nnz + (kRowAlign - 1) * m, s2 = nnz + (kRowAlign - 1) * n;
-    *bytes = layout_bytes(m, s1, f32, lp) + layout_bytes(n, s2, f32, lp) + size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0));
+    *bytes = layout_bytes(m, s1, f32, lp, lp && n <= 65536) + layout_bytes(n, s2, f32, lp, lp && m <= 65536) +
+             size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0));
     return SMX_OK;
 }
 
@@ -999,8 +1036,9 @@ int smx_query(smx_problem *p, double *proximity, double *objective)
         const int vk = p->op->has_f32 ? VK_F32 : p->op->lp_kind();
         const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
         double *q = p->qout.as<double>();
-        hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, vk), p->op->csr.blocks(), vk, p->x.as<float>(),
-                               p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(), p->state(p->cur), B, 1,
+        hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
+                               p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(),
+                               p->state(p->cur), B, 1,
                                p->part_query.as<double>(), p->stream),
                   "query proximity");
         hip_check(launch_query_prox(p->state(p->cur), B, p->part_query.as<double>(), p->cfg1[vk].grid, q,

@@ -167,6 +167,51 @@ __device__ inline void idx_load(const int32_t *base, int p, int (&c)[VEC])
     }
 }
 
+struct Bf16PTag {};
+struct F16PTag {};
+
+// VEC entries (values as float, indices) starting at p.
+template <typename VT, int VEC>
+struct Entries {
+    static __device__ inline void load(const SpView &A, int p, float (&v)[VEC], int (&c)[VEC])
+    {
+        ValLoad<VT, VEC>::load(A.val, p, v);
+        idx_load<VEC>(A.idx, p, c);
+    }
+};
+
+template <int VEC, bool BF>
+__device__ inline void packed_load(const SpView &A, int p, float (&v)[VEC], int (&c)[VEC])
+{
+    const uint4 *q = reinterpret_cast<const uint4 *>(static_cast<const uint32_t *>(A.val) + p);
+#pragma unroll
+    for (int h = 0; h < VEC / 4; ++h) {
+        const uint4 a = q[h];
+        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[4 * h + k] = BF ? bf16_lo(w[k]) : f16_lo(w[k]);
+            c[4 * h + k] = (int)(w[k] >> 16);
+        }
+    }
+}
+
+template <int VEC>
+struct Entries<Bf16PTag, VEC> {
+    static __device__ inline void load(const SpView &A, int p, float (&v)[VEC], int (&c)[VEC])
+    {
+        packed_load<VEC, true>(A, p, v, c);
+    }
+};
+
+template <int VEC>
+struct Entries<F16PTag, VEC> {
+    static __device__ inline void load(const SpView &A, int p, float (&v)[VEC], int (&c)[VEC])
+    {
+        packed_load<VEC, false>(A, p, v, c);
+    }
+};
+
 // Partial dot product of one row with a vector, by lane `lane` of an LPR-lane
 // group.  [beg, end) is row-aligned, so every vector load is aligned and no
 // entry needs a mask (padding entries are zeros with valid indices).  Products
@@ -185,8 +230,7 @@ __device__ inline double row_dot(const SpView &A, int beg, int end, int lane, co
         int c[4][VEC];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            ValLoad<VT, VEC>::load(A.val, p + u * STEP, v[u]);
-            idx_load<VEC>(A.idx, p + u * STEP, c[u]);
+            Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -196,8 +240,7 @@ __device__ inline double row_dot(const SpView &A, int beg, int end, int lane, co
     for (; p < end; p += STEP) {
         float v0[VEC];
         int c0[VEC];
-        ValLoad<VT, VEC>::load(A.val, p, v0);
-        idx_load<VEC>(A.idx, p, c0);
+        Entries<VT, VEC>::load(A, p, v0, c0);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc[0] = fma((double)v0[e], (double)x[c0[e]], acc[0]);
     }
@@ -293,8 +336,7 @@ __device__ inline void stream_chunks(const SpView &A, int e0, int e1, const floa
         if (e0 + q < e1) {
             float val[VEC];
             int id[VEC];
-            ValLoad<VT, VEC>::load(A.val, e0 + q, val);
-            idx_load<VEC>(A.idx, e0 + q, id);
+            Entries<VT, VEC>::load(A, e0 + q, val, id);
             double acc = 0.0;
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc = fma((double)val[e], (double)v[id[e]], acc);
@@ -318,8 +360,7 @@ __device__ inline double long_row_sum(const SpView &A, int e0, int e1, const flo
     for (int p = e0 + threadIdx.x * VEC; p < e1; p += kBlock * VEC) {
         float val[VEC];
         int id[VEC];
-        ValLoad<VT, VEC>::load(A.val, p, val);
-        idx_load<VEC>(A.idx, p, id);
+        Entries<VT, VEC>::load(A, p, val, id);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) acc = fma((double)val[e], (double)v[id[e]], acc);
     }
@@ -553,8 +594,7 @@ __device__ inline void row_dot_mm(const SpView &A, int beg, int end, int lane, c
     for (int p = beg + lane * VEC; p < end; p += LPR * VEC) {
         float val[VEC];
         int id[VEC];
-        ValLoad<VT, VEC>::load(A.val, p, val);
-        idx_load<VEC>(A.idx, p, id);
+        Entries<VT, VEC>::load(A, p, val, id);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             float xs[B];
@@ -1087,6 +1127,16 @@ __device__ inline float stored_value<F16Tag>(const void *val, long long p)
 {
     return __half2float(__ushort_as_half(static_cast<const uint16_t *>(val)[p]));
 }
+template <>
+__device__ inline float stored_value<Bf16PTag>(const void *val, long long p)
+{
+    return bf16_lo(static_cast<const uint32_t *>(val)[p]);
+}
+template <>
+__device__ inline float stored_value<F16PTag>(const void *val, long long p)
+{
+    return f16_lo(static_cast<const uint32_t *>(val)[p]);
+}
 
 // q_i = ||a_i||^2 in float64 from the stored (possibly rounded) values; one wave per row
 template <typename VT>
@@ -1122,6 +1172,13 @@ __global__ void k_to_f16(const float *__restrict__ src, uint16_t *__restrict__ d
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
         dst[i] = __half_as_ushort(__float2half_rn(src[i] * scale));
+}
+
+__global__ void k_pack16(const uint16_t *__restrict__ val16, const int32_t *__restrict__ idx,
+                         uint32_t *__restrict__ packed, long long count)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        packed[i] = (uint32_t)val16[i] | ((uint32_t)idx[i] << 16);
 }
 
 __global__ void k_fill(float *__restrict__ p, float v, long long count)
@@ -1216,9 +1273,14 @@ static inline unsigned grid_for(long long work, int per_block, unsigned cap)
 hipError_t launch_rownorm(const SpView &A, int vk, double *q, hipStream_t s)
 {
     const unsigned grid = grid_for(A.rows, kBlock / 64, 1u << 30);
-    if (vk == VK_F32) hipLaunchKernelGGL(k_rownorm<float>, dim3(grid), dim3(kBlock), 0, s, A, q);
-    else if (vk == VK_BF16) hipLaunchKernelGGL(k_rownorm<Bf16Tag>, dim3(grid), dim3(kBlock), 0, s, A, q);
-    else hipLaunchKernelGGL(k_rownorm<F16Tag>, dim3(grid), dim3(kBlock), 0, s, A, q);
+    switch (vk) {
+    case VK_F32: hipLaunchKernelGGL(k_rownorm<float>, dim3(grid), dim3(kBlock), 0, s, A, q); break;
+    case VK_BF16: hipLaunchKernelGGL(k_rownorm<Bf16Tag>, dim3(grid), dim3(kBlock), 0, s, A, q); break;
+    case VK_F16: hipLaunchKernelGGL(k_rownorm<F16Tag>, dim3(grid), dim3(kBlock), 0, s, A, q); break;
+    case VK_BF16P: hipLaunchKernelGGL(k_rownorm<Bf16PTag>, dim3(grid), dim3(kBlock), 0, s, A, q); break;
+    case VK_F16P: hipLaunchKernelGGL(k_rownorm<F16PTag>, dim3(grid), dim3(kBlock), 0, s, A, q); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1238,6 +1300,13 @@ hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float s
 {
     hipLaunchKernelGGL(k_to_f16, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s, src, dst, (long long)count,
                        scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack16(const uint16_t *val16, const int32_t *idx, uint32_t *packed, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack16, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s, val16, idx, packed,
+                       (long long)count);
     return hipGetLastError();
 }
 
@@ -1345,12 +1414,24 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
     if (B > 1) {
         if (vk == VK_F32) return pass1_mm_b<float, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
         if (vk == VK_BF16) return pass1_mm_b<Bf16Tag, 8>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
+        if (vk == VK_BF16P) return pass1_mm_b<Bf16PTag, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
+        if (vk == VK_F16P) return pass1_mm_b<F16PTag, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
         return pass1_mm_b<F16Tag, 8>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
     }
     if (cfg.mode == 1) {
         if (vk == VK_F32) return pass1_stream<float, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
         if (vk == VK_BF16) return pass1_stream<Bf16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+        if (vk == VK_BF16P) return pass1_stream<Bf16PTag, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+        if (vk == VK_F16P) return pass1_stream<F16PTag, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
         return pass1_stream<F16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+    }
+    if (vk == VK_BF16P) {
+        if (cfg.vec == 8) return pass1_vec<Bf16PTag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        return pass1_vec<Bf16PTag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    }
+    if (vk == VK_F16P) {
+        if (cfg.vec == 8) return pass1_vec<F16PTag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        return pass1_vec<F16PTag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
     }
     if (vk == VK_F32) {
         if (cfg.vec == 8) return pass1_vec<float, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
@@ -1434,12 +1515,24 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
     if (B > 1) {
         if (vk == VK_F32) return pass2_mm_b<float, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
         if (vk == VK_BF16) return pass2_mm_b<Bf16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_BF16P) return pass2_mm_b<Bf16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_F16P) return pass2_mm_b<F16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
         return pass2_mm_b<F16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
     }
     if (cfg.mode == 1) {
         if (vk == VK_F32) return pass2_stream<float, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
         if (vk == VK_BF16) return pass2_stream<Bf16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_BF16P) return pass2_stream<Bf16PTag, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_F16P) return pass2_stream<F16PTag, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
         return pass2_stream<F16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    }
+    if (vk == VK_BF16P) {
+        if (cfg.vec == 8) return pass2_vec<Bf16PTag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<Bf16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    }
+    if (vk == VK_F16P) {
+        if (cfg.vec == 8) return pass2_vec<F16PTag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<F16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
     }
     if (vk == VK_F32) {
         if (cfg.vec == 8) return pass2_vec<float, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);

@@ -13,7 +13,10 @@ constexpr int kRowAlign = 8;   // entries of every row/column start at a multipl
 constexpr int kTrialChunk = 8; // trial steps evaluated per register batch
 constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
 
-enum ValKind : int { VK_F32 = 0, VK_BF16 = 1, VK_F16 = 2 };
+// Stored formats of A's entries.  The packed kinds hold one 32-bit word per
+// entry: the 16-bit value in the low half, a 16-bit index in the high half
+// (used when the layout's index range fits in 16 bits).
+enum ValKind : int { VK_F32 = 0, VK_BF16 = 1, VK_F16 = 2, VK_BF16P = 3, VK_F16P = 4 };
 enum ObjKind : int { OBJ_NONE = 0, OBJ_SQNORM = 1, OBJ_TV2D = 2, OBJ_LINEAR = 3 };
 
 // Device view of one row-aligned sparse layout: the CSR of A (pass 1) or the
@@ -22,7 +25,7 @@ enum ObjKind : int { OBJ_NONE = 0, OBJ_SQNORM = 1, OBJ_TV2D = 2, OBJ_LINEAR = 3 
 struct SpView {
     const int32_t *ptr;
     const int32_t *idx;
-    const void *val; // float, bf16 bits (uint16) or binary16, by ValKind
+    const void *val; // float, bf16 bits (uint16), binary16, or packed words, by ValKind
     int64_t rows;
     float vscale_inv; // operator value = stored value * vscale_inv
 };
@@ -95,6 +98,7 @@ hipError_t launch_rownorm(const SpView &A, int vk, double *q, hipStream_t s);
 hipError_t launch_make_D(const double *q, const double *w, float *D, int64_t m, hipStream_t s);
 hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
 hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float scale, hipStream_t s);
+hipError_t launch_pack16(const uint16_t *val16, const int32_t *idx, uint32_t *packed, int64_t count, hipStream_t s);
 hipError_t launch_init_state(SliceState *st, int B, hipStream_t s);
 hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s);
 // slots of a multi-slice problem (serving)
