@@ -42,16 +42,37 @@ VALUE_TAG = {"f32+i32": "float", "bf16+i32": "smx::Bf16Tag", "f16+i32": "smx::F1
              "bf16+u16": "smx::Bf16PTag", "f16+u16": "smx::F16PTag"}
 
 
+def fused_in_use(shapes):
+    f = shapes.get("fused")
+    return bool(f and f["in_use"])
+
+
 def alg_bytes(m, n, nnz, shapes, B=1):
-    """Algorithmic bytes of one launch of each pass: A once in the format that
-    pass reads, each vector once."""
-    e1, e2 = ENTRY_BYTES[shapes["pass1"]["format"]], ENTRY_BYTES[shapes["pass2"]["format"]]
+    """Algorithmic bytes of one launch of each kernel of the feasibility step:
+    A once in the format that kernel reads, each vector once.  Two passes:
+    pass 1 and pass 2.  Fused pass: the fused kernel (A once, the row vectors,
+    the gather of z, y once) and its apply kernel (z, the box, x, and the
+    per-workgroup partial vectors it has to sum)."""
+    e1 = ENTRY_BYTES[shapes["pass1"]["format"]]
+    if fused_in_use(shapes):
+        f = shapes["fused"]
+        acc = 8 if f["acc"] == "f64" else 4
+        p1 = nnz * e1 + 4 * (m + 1) + 12 * m + 4 * n + 8 * n
+        p2 = acc * n * f["grid"] + 16 * n
+        return p1, p2
+    e2 = ENTRY_BYTES[shapes["pass2"]["format"]]
     p1 = nnz * e1 + 4 * (m + 1) + 4 * m + B * (8 * m + 4 * m + 4 * n)
     p2 = nnz * e2 + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
     return p1, p2
 
 
-def kernel_name(pass_no, shape, B=1):
+def kernel_name(pass_no, shape, B=1, shapes=None):
+    if shapes is not None and fused_in_use(shapes):
+        f = shapes["fused"]
+        acc = "double" if f["acc"] == "f64" else "float"
+        if pass_no == 1:
+            return f"smx::k_fused<{f['lpr']}, {f['vec']}, {VALUE_TAG[shapes['pass1']['format']]}, {acc}>"
+        return f"smx::k_fused_apply<{acc}>"
     vt = VALUE_TAG[shape["format"]]
     if B > 1:
         return f"smx::k_pass{pass_no}_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
@@ -75,12 +96,12 @@ def measured_traffic(name):
         return None
 
 
-def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True):
+def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=True):
     """Timed run of `steps` iterations (inputs resident in HBM), then the same
     iterations eagerly with HIP events around each pass launch."""
     import torch
 
-    p = smx.problem_from_workload(w, storage=storage, refine_iters=0)
+    p = smx.problem_from_workload(w, storage=storage, refine_iters=0, fused=fused)
     shapes = p.autotune(reps=10) if tune else p.describe()
     p.run(warmup, perturb=True, graph=graph)  # also captures the graphs
     p.sync()
@@ -105,10 +126,13 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True):
 
 def summarise(w, r, storage, B=1):
     c1, c2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B)
-    return dict(it_s=round(r["it_s"], 2), slice_it_s=round(r["it_s"] * B, 2), ms_per_step=round(r["ms_per_step"], 5),
-                pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
-                pass1_gbs=round(c1 / (r["pass1_ms"] * 1e-3) / 1e9, 1),
-                pass2_gbs=round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1), launch=r["shapes"])
+    fused = fused_in_use(r["shapes"])
+    k1, k2 = ("fused", "apply") if fused else ("pass1", "pass2")
+    return {"it_s": round(r["it_s"], 2), "slice_it_s": round(r["it_s"] * B, 2),
+            "ms_per_step": round(r["ms_per_step"], 5), "feasibility_step": "fused" if fused else "two passes",
+            f"{k1}_ms": round(r["pass1_ms"], 5), f"{k2}_ms": round(r["pass2_ms"], 5),
+            f"{k1}_gbs": round(c1 / (r["pass1_ms"] * 1e-3) / 1e9, 1),
+            f"{k2}_gbs": round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1), "launch": r["shapes"]}
 
 
 def roofline_of(w, r, storage, B=1):
@@ -116,10 +140,10 @@ def roofline_of(w, r, storage, B=1):
     t1, t2 = r["pass1_ms"], r["pass2_ms"]
     dpass, dbytes, dms = (1, b1, t1) if t1 >= t2 else (2, b2, t2)
     achieved = dbytes / (dms * 1e-3) / 1e9
-    kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], B)
+    kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], B, shapes=r["shapes"])
     return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname), algorithmic_bytes=int(dbytes),
-                both_passes_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
+                step_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
 
 
 def cpu_baseline(w, K):
@@ -195,12 +219,13 @@ def section_hbm(smx, tune):
     out = dict(workload="radiotherapy 160x160x80 voxels, 9 beams x 47x47 beamlets, linear dose objective",
                m=w.m, n=w.n, nnz=w.nnz, generate_s=round(gen, 1))
     for storage in ("f32", "bf16"):
-        t0 = time.time()
-        r = time_problem(smx, w, storage, 100, 5, tune=tune)
-        s = summarise(w, r, storage)
-        s["roofline"] = roofline_of(w, r, storage)
-        s["wall_s"] = round(time.time() - t0, 1)
-        out[storage] = s
+        for fused in (True, False):
+            t0 = time.time()
+            r = time_problem(smx, w, storage, 100, 5, tune=tune, fused=fused)
+            s = summarise(w, r, storage)
+            s["roofline"] = roofline_of(w, r, storage)
+            s["wall_s"] = round(time.time() - t0, 1)
+            out[storage if fused else f"{storage}_two_passes"] = s
     return out
 
 

@@ -248,12 +248,29 @@ int smx_slot_get_x(smx_problem *p, int32_t slot, float *out, int32_t on_device);
  * Results do not depend on the shape beyond float64 summation order. */
 int smx_autotune(smx_problem *p, int32_t reps);
 
+/* Fused single pass for one-slice problems (B = 1).  The two passes of a
+ * feasibility step read the same entries, so when an LDS copy of y = A^T c
+ * fits on a CU (n up to about 20k unknowns in float64, 40k in float32) one
+ * pass over the CSR forms c and adds c_i a_i into per-workgroup copies of y,
+ * reading A once per iteration instead of twice; a small kernel sums the
+ * copies and applies the box.
+ *   mode 1 (the default): use the fused pass where it is available (the
+ *          autotuner may still keep the two passes when they time faster);
+ *   mode 0: always the two passes.
+ * The two passes add in a fixed order, so repeated runs, graph replays and
+ * checkpoint/resume are bitwise reproducible.  The fused pass adds into LDS
+ * with atomics, so its results are reproducible up to float64 summation
+ * order only.  Errors: SMX_EINVAL for another mode.  SMX_OK also where no
+ * fused pass is available (mode 1 then changes nothing). */
+int smx_set_fused(smx_problem *p, int32_t mode);
+
 /* JSON description of the launch shapes in use (NUL-terminated, truncated to
  * cap bytes); *need (if non-NULL) receives the full size. */
 int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need);
 
-/* Mean device time (milliseconds) per launch of the two passes recorded by
- * the last smx_run made with SMX_RUN_GRAPH clear and timing enabled through
+/* Mean device time (milliseconds) per launch of the two passes (with the
+ * fused pass: of the fused pass and of its apply kernel) recorded by the last
+ * smx_run made with SMX_RUN_GRAPH clear and timing enabled through
  * smx_set_timing; zero launches give 0. */
 int smx_set_timing(smx_problem *p, int32_t enable);
 int smx_get_timing(smx_problem *p, double *pass1_ms, double *pass2_ms, int64_t *launches);

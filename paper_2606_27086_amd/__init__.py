@@ -48,6 +48,7 @@ EXPORTS = [
     "smx_get_timing",
     "smx_autotune",
     "smx_describe",
+    "smx_set_fused",
     "smx_slot_load",
     "smx_slot_disable",
     "smx_slot_status",
@@ -150,6 +151,7 @@ def lib() -> C.CDLL:
     L.smx_slot_status.argtypes = [vp, vp, vp]
     L.smx_slot_get_x.argtypes = [vp, i32, vp, i32]
     L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.smx_set_fused.argtypes = [vp, i32]
     for name in EXPORTS:
         if name != "smx_last_error":
             getattr(L, name).restype = C.c_int
@@ -379,6 +381,16 @@ class Problem:
         check(lib().smx_slot_get_x(self.handle, int(slot), _ptr(out), 1))
         return out
 
+    def set_fused(self, on: bool):
+        """Fused single pass for one-slice problems where it is available (on),
+        or always the two bitwise-reproducible passes (off)."""
+        check(lib().smx_set_fused(self.handle, 1 if on else 0))
+
+    def fused_in_use(self) -> bool:
+        d = self.describe()
+        return any(isinstance(v, dict) and isinstance(v.get("fused"), dict) and v["fused"]["in_use"]
+                   for v in d.values())
+
     def set_timing(self, on: bool):
         check(lib().smx_set_timing(self.handle, 1 if on else 0))
 
@@ -400,8 +412,9 @@ class Problem:
 
 
 def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device="cuda", op: Operator = None,
-                          refine_iters: int = -1, **overrides) -> Problem:
-    """Build operator + problem for a :class:`workloads.Workload` (all slices)."""
+                          refine_iters: int = -1, fused: bool = True, **overrides) -> Problem:
+    """Build operator + problem for a :class:`workloads.Workload` (all slices);
+    fused=False keeps the two bitwise-reproducible passes."""
     if op is None:
         op = Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage=storage, device=device)
     kw = dict(
@@ -412,5 +425,7 @@ def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device=
     )
     kw.update(overrides)
     p = Problem(op, device=device, **kw)
+    if not fused:
+        p.set_fused(False)
     p.set_x(w.x0)
     return p

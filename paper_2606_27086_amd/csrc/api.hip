@@ -220,6 +220,11 @@ struct smx_problem {
     int hist_cap = 0;
     PassCfg cfg1[3]{}, cfg2[3]{};
     int fmt1[3] = {0, 1, 2}, fmt2[3] = {0, 1, 2}; // stored format each pass reads, per value kind
+    // fused single pass (one slice, y in LDS): usable, and in use, per value kind
+    bool fused_ok[3] = {false, false, false}, fused[3] = {false, false, false};
+    int fused_mode = 1; // 0: always the two passes
+    FusedCfg fcfg[3]{};
+    DBuf ypart; // grid x n partial vectors of y = A^T c
     // captured graphs keyed by (value kind, perturb, iterations)
     std::map<long long, hipGraphExec_t> graphs;
     hipStream_t capture_stream = nullptr; // private stream graphs are captured on
@@ -467,6 +472,23 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
         p->ev_used += 4;
         hip_check(hipEventRecord(e[0], s), "event");
     }
+    if (p->fused[vk]) {
+        hip_check(launch_fused(p->fcfg[vk], view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], p->n, p->x.as<float>(),
+                               p->lower.as<float>(), p->upper.as<float>(), D, p->state(cur),
+                               p->part_pass.as<double>(), p->ypart.p, s),
+                  "fused pass");
+        if (timed) {
+            hip_check(hipEventRecord(e[1], s), "event");
+            hip_check(hipEventRecord(e[2], s), "event");
+        }
+        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, p->x.as<float>(), p->box_lo.as<float>(),
+                                     p->box_hi.as<float>(), p->lambda, p->state(cur), p->state(cur ^ 1),
+                                     p->part_pass.as<double>(), p->hist, s),
+                  "fused apply");
+        cur ^= 1;
+        if (timed) hip_check(hipEventRecord(e[3], s), "event");
+        return cur;
+    }
     hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
                            p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(),
                            p->state(cur), p->B, 0,
@@ -579,6 +601,48 @@ int run_impl(smx_problem *p, int32_t K, uint32_t flags)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Fused single pass for one slice when an LDS copy of y fits (float64 if it
+// can, else float32).  Lanes per row follow the mean row length; one or two
+// workgroups per CU, as many as the LDS allows.
+void setup_fused(smx_problem *p)
+{
+    if (p->B != 1) return;
+    const size_t lim = fused_lds_limit();
+    int acc64 = -1;
+    if (fused_lds_bytes(p->n, 1) <= lim) acc64 = 1;
+    else if (fused_lds_bytes(p->n, 0) <= lim) acc64 = 0;
+    if (acc64 < 0) return;
+    int dev = 0, cus = 0, lds_cu = 0;
+    hip_check(hipGetDevice(&dev), "device");
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        lds_cu = 0;
+    const size_t bytes = fused_lds_bytes(p->n, acc64);
+    const int per_cu = (lds_cu > 0 && size_t(lds_cu) >= 2 * (bytes + 1024)) ? 2 : 1;
+    const DevLayout &L = p->op->csr;
+    const double mean = L.rows > 0 ? double(L.slots) / double(L.rows) : 0.0;
+    FusedCfg c;
+    c.lpr = mean <= 64 ? 8 : (mean <= 256 ? 16 : 32);
+    c.grid = std::max(1, std::min(cus * per_cu, kMaxPassGrid));
+    c.acc64 = acc64;
+    bool any = false;
+    for (int vk = 0; vk < 3; ++vk) {
+        const bool present = (vk == VK_F32) ? p->op->has_f32 : (vk == p->op->lp_kind());
+        if (!present) continue;
+        bool ok = true;
+        for (int lpr : {8, 16, 32}) {
+            FusedCfg t = c;
+            t.lpr = lpr;
+            if (prepare_fused(t, p->fmt1[vk], p->n) != hipSuccess) ok = false;
+        }
+        (void)hipGetLastError();
+        p->fused_ok[vk] = p->fused[vk] = ok;
+        p->fcfg[vk] = c;
+        any = any || ok;
+    }
+    if (any) p->ypart.alloc(bytes * size_t(c.grid), "fused partial vectors");
+}
+
 int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, smx_problem **out)
 {
     if (!op || !d || !out) return fail(SMX_EINVAL, "NULL argument");
@@ -687,6 +751,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->cfg1[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk, B);
         p->cfg2[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csc, vk) : pick_cfg(op->csc, vk, B);
     }
+    setup_fused(p.get());
     // per-workgroup partial sums of each kernel kind
     const int64_t pgrid = phase_grid(pp);
     p->part_pass.alloc(sizeof(double) * size_t(kMaxPassGrid) * B, "pass partials");
@@ -806,6 +871,7 @@ int autotune_impl(smx_problem *p, int reps)
                 }
             }
             p->cfg1[vk] = bestc;
+            const double two_pass1 = best;
             // pass 2 (the residual from the chosen pass 1)
             best = 1e30;
             PassCfg bestc2 = p->cfg2[vk];
@@ -829,6 +895,37 @@ int autotune_impl(smx_problem *p, int reps)
                 }
             }
             p->cfg2[vk] = bestc2;
+            // the fused single pass, timed with its apply kernel, against the two passes
+            if (p->fused_ok[vk] && p->fused_mode == 1) {
+                double bestf = 1e30;
+                FusedCfg bestfc = p->fcfg[vk];
+                for (int lpr : {8, 16, 32}) {
+                    FusedCfg c = p->fcfg[vk];
+                    c.lpr = lpr;
+                    auto launch = [&]() {
+                        hip_check(launch_fused(c, view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], n, xs.as<float>(),
+                                               p->lower.as<float>(), p->upper.as<float>(), D, st0,
+                                               p->part_query.as<double>(), p->ypart.p, s),
+                                  "tuning fused pass");
+                        hip_check(launch_fused_apply(c, n, p->ypart.p, xs.as<float>(), p->box_lo.as<float>(),
+                                                     p->box_hi.as<float>(), p->lambda, st0, st1,
+                                                     p->part_query.as<double>(), none, s),
+                                  "tuning fused apply");
+                    };
+                    launch();
+                    launch();
+                    hip_check(hipEventRecord(e0, s), "event");
+                    for (int r = 0; r < reps; ++r) launch();
+                    hip_check(hipEventRecord(e1, s), "event");
+                    const double t = elapsed();
+                    if (t < bestf) {
+                        bestf = t;
+                        bestfc = c;
+                    }
+                }
+                p->fcfg[vk] = bestfc;
+                p->fused[vk] = bestf < two_pass1 + best;
+            }
         }
     } catch (...) {
         (void)hipEventDestroy(e0);
@@ -856,6 +953,9 @@ const char *fmt_name(int f)
     }
 }
 
+// entries per load of the fused kernel for a stored format
+int fused_vec(int fmt) { return (fmt == VK_BF16 || fmt == VK_F16) ? 8 : 4; }
+
 int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
 {
     std::string out = "{";
@@ -864,13 +964,22 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
     for (int vk = 0; vk < 3; ++vk) {
         if (vk == VK_F32 && !p->op->has_f32) continue;
         if (vk != VK_F32 && p->op->lp_kind() != vk) continue;
-        char tmp[512];
+        char tmp[768];
         const PassCfg &a = p->cfg1[vk], &b = p->cfg2[vk];
+        char fz[160];
+        if (p->fused_ok[vk]) {
+            const FusedCfg &f = p->fcfg[vk];
+            snprintf(fz, sizeof fz, "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"acc\": \"%s\"}",
+                     p->fused[vk] ? "true" : "false", f.lpr, fused_vec(p->fmt1[vk]), f.grid, f.acc64 ? "f64" : "f32");
+        } else {
+            snprintf(fz, sizeof fz, "null");
+        }
         snprintf(tmp, sizeof tmp,
                  "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
-                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}}",
+                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
+                 "\"fused\": %s}",
                  first ? "" : ", ", names[vk], a.mode ? "stream" : "rows", a.lpr, a.vec, a.grid, fmt_name(p->fmt1[vk]),
-                 b.mode ? "stream" : "rows", b.lpr, b.vec, b.grid, fmt_name(p->fmt2[vk]));
+                 b.mode ? "stream" : "rows", b.lpr, b.vec, b.grid, fmt_name(p->fmt2[vk]), fz);
         out += tmp;
         first = false;
     }
@@ -1228,6 +1337,21 @@ int smx_slot_get_x(smx_problem *p, int32_t slot, float *out, int32_t on_device)
         hip_check(launch_get_column(tmp.as<float>(), p->x.as<float>(), p->n, p->B, slot, p->stream), "slot x");
         hip_check(hipMemcpyAsync(out, tmp.p, sizeof(float) * p->n, hipMemcpyDeviceToHost, p->stream), "slot x");
         hip_check(hipStreamSynchronize(p->stream), "slot x");
+        return SMX_OK;
+    })
+}
+
+int smx_set_fused(smx_problem *p, int32_t mode)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    if (mode != 0 && mode != 1) return fail(SMX_EINVAL, "fused mode must be 0 or 1 (got %d)", mode);
+    SMX_GUARD({
+        p->fused_mode = mode;
+        for (int vk = 0; vk < 3; ++vk) p->fused[vk] = p->fused_ok[vk] && mode == 1;
+        // the kernel choice is baked into captured graphs
+        hip_check(hipStreamSynchronize(p->stream), "sync");
+        for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+        p->graphs.clear();
         return SMX_OK;
     })
 }

@@ -41,8 +41,9 @@ __device__ inline void wave_sum(double (&v)[NV])
     }
 }
 
-// Sum of v over the workgroup, valid in thread 0.  lds holds >= 4*NV doubles.
-template <int NV>
+// Sum of v over a workgroup of BS threads, valid in thread 0.  lds holds
+// >= (BS/64)*NV doubles.
+template <int NV, int BS = kBlock>
 __device__ inline void block_sum(double (&v)[NV], double *lds)
 {
     wave_sum<NV>(v);
@@ -56,7 +57,7 @@ __device__ inline void block_sum(double (&v)[NV], double *lds)
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             double s = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) s += lds[w * NV + k];
+            for (int w = 0; w < BS / 64; ++w) s += lds[w * NV + k];
             v[k] = s;
         }
     }
@@ -550,6 +551,123 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
             if (owner) {
                 const double z = fma((double)lambda, s * (double)At.vscale_inv, (double)xo);
                 x[r0 + rs.rl] = (float)fmin(fmax(z, (double)l), (double)u);
+            }
+            __syncthreads();
+        }
+    }
+    if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Fused single pass (one slice; y = A^T c small enough to live in LDS).  The
+// two passes of the feasibility step touch the same entries: row i gives r_i,
+// then t_i and c_i = D_i t_i, and c_i a_i is exactly row i's contribution to
+// y = A^T c.  So each workgroup streams a contiguous range of CSR rows once,
+// forms c_i as pass 1 does and, while the row is still in the cache, adds
+// c_i a_i into its own copy of y in LDS (float64 atomics, or float32 when a
+// float64 copy does not fit).  Rows inside their band (t_i = 0) add nothing.
+// The workgroup's y leaves as one partial vector; k_fused_apply sums the
+// partials in workgroup order and applies x = clip(z + lambda y).  A is read
+// from memory once per iteration instead of twice, and the column copy of A
+// is not read at all.  Summation order inside a workgroup follows the LDS
+// atomics, so results agree with the two-pass kernels up to float64 rounding.
+// ---------------------------------------------------------------------------
+
+// smallest r in [0, rows] with ptr[r] >= target (ptr[rows] >= target)
+__device__ inline int first_row_at(const int *__restrict__ ptr, int rows, long long target)
+{
+    int lo = 0, hi = rows;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ptr[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ inline void lds_add(double *a, double v) { atomicAdd(a, v); }
+__device__ inline void lds_add(float *a, double v) { atomicAdd(a, (float)v); }
+
+template <int LPR, int VEC, typename VT, typename AccT>
+__global__ __launch_bounds__(kFusedBlock) void k_fused(SpView A, int n, const float *__restrict__ x,
+                                                       const float *__restrict__ lower,
+                                                       const float *__restrict__ upper, const float *__restrict__ D,
+                                                       const SliceState *__restrict__ st,
+                                                       double *__restrict__ partials, AccT *__restrict__ ypart)
+{
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+    AccT *y = reinterpret_cast<AccT *>(fused_lds);
+    __shared__ double lds[kFusedBlock / 64];
+    __shared__ int range[2];
+    constexpr int RPB = kFusedBlock / LPR;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const bool live = st[0].live != 0;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = AccT(0);
+    if (threadIdx.x == 0) { // an equal share of the stored entries
+        const long long total = A.ptr[A.rows];
+        range[0] = first_row_at(A.ptr, (int)A.rows, total * blockIdx.x / gridDim.x);
+        range[1] = first_row_at(A.ptr, (int)A.rows, total * (blockIdx.x + 1) / gridDim.x);
+    }
+    __syncthreads();
+    const int r0 = range[0], r1 = range[1];
+    double pacc[1] = {0.0};
+    if (live) {
+        for (int row = r0 + grp; row < r1; row += RPB) {
+            const int beg = A.ptr[row], end = A.ptr[row + 1];
+            const float lo = lower[row], up = upper[row], d = D[row];
+            const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
+            const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+            const double dt = (double)d * t;
+            if (lane == 0) pacc[0] += dt * t;
+            if (dt != 0.0) { // the same entries again, now from the cache
+                const double sc = dt * (double)A.vscale_inv;
+                for (int p = beg + lane * VEC; p < end; p += LPR * VEC) {
+                    float v[VEC];
+                    int c[VEC];
+                    Entries<VT, VEC>::load(A, p, v, c);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (v[e] != 0.f) lds_add(&y[c[e]], sc * (double)v[e]);
+                }
+            }
+        }
+    }
+    block_sum<1, kFusedBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
+    if (!live) return;
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+    AccT *out = ypart + (long long)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
+}
+
+// x = clip(z + lambda * sum_g ypart[g], lo, hi); 64 unknowns per workgroup, the
+// four waves each sum every fourth partial and the four sums are added in a
+// fixed order.  Workgroup 0 also closes the outer iteration.
+template <typename AccT>
+__global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__ ypart, int G, int n,
+                                                        float *__restrict__ x, const float *__restrict__ lo,
+                                                        const float *__restrict__ hi, float lambda,
+                                                        const SliceState *__restrict__ st_in,
+                                                        SliceState *__restrict__ st_out,
+                                                        const double *__restrict__ part1, int nparts1, Hist h)
+{
+    __shared__ double red[kBlock / 64][64];
+    __shared__ double lds[4];
+    const int wid = threadIdx.x >> 6, wl = threadIdx.x & 63;
+    if (st_in[0].live) {
+        for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
+            const int j = j0 + wl;
+            double sum = 0.0;
+            if (j < n)
+                for (int g = wid; g < G; g += kBlock / 64) sum += (double)ypart[(long long)g * n + j];
+            red[wid][wl] = sum;
+            __syncthreads();
+            if (wid == 0 && j < n) {
+                double yv = 0.0;
+#pragma unroll
+                for (int w = 0; w < kBlock / 64; ++w) yv += red[w][wl];
+                const double z = fma((double)lambda, yv, (double)x[j]);
+                x[j] = (float)fmin(fmax(z, (double)lo[j]), (double)hi[j]);
             }
             __syncthreads();
         }
@@ -1544,6 +1662,105 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
     }
     if (cfg.vec == 8) return pass2_vec<F16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
     return pass2_vec<F16Tag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+}
+
+size_t fused_lds_bytes(int64_t n, int acc64) { return size_t(n) * (acc64 ? sizeof(double) : sizeof(float)); }
+
+size_t fused_lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    const size_t reserve = 1024; // the fused kernel's own static LDS
+    return size_t(v) > reserve ? size_t(v) - reserve : 0;
+}
+
+namespace {
+
+struct FusedArgs {
+    const SpView *A;
+    int64_t n;
+    const float *x, *lower, *upper, *D;
+    const SliceState *st;
+    double *partials;
+    void *ypart;
+};
+
+// prepare != 0: only raise the kernel's dynamic-LDS attribute (done outside
+// any stream capture, before the first launch of this shape)
+template <int LPR, typename VT, int VEC, typename AccT>
+hipError_t fused_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
+{
+    auto kern = k_fused<LPR, VEC, VT, AccT>;
+    const size_t bytes = fused_lds_bytes(a.n, sizeof(AccT) == sizeof(double));
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)bytes);
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kFusedBlock), bytes, s, *a.A, (int)a.n, a.x, a.lower, a.upper, a.D,
+                       a.st, a.partials, static_cast<AccT *>(a.ypart));
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC, typename AccT>
+hipError_t fused_lpr(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
+{
+    switch (cfg.lpr) {
+    case 8: return fused_go<8, VT, VEC, AccT>(cfg, a, prepare, s);
+    case 16: return fused_go<16, VT, VEC, AccT>(cfg, a, prepare, s);
+    case 32: return fused_go<32, VT, VEC, AccT>(cfg, a, prepare, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename VT, int VEC>
+hipError_t fused_acc(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
+{
+    return cfg.acc64 ? fused_lpr<VT, VEC, double>(cfg, a, prepare, s) : fused_lpr<VT, VEC, float>(cfg, a, prepare, s);
+}
+
+hipError_t fused_dispatch(const FusedCfg &cfg, int vk, const FusedArgs &a, int prepare, hipStream_t s)
+{
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || a.n < 1 || a.n > (int64_t(1) << 30)) return hipErrorInvalidValue;
+    switch (vk) {
+    case VK_F32: return fused_acc<float, 4>(cfg, a, prepare, s);
+    case VK_BF16: return fused_acc<Bf16Tag, 8>(cfg, a, prepare, s);
+    case VK_F16: return fused_acc<F16Tag, 8>(cfg, a, prepare, s);
+    case VK_BF16P: return fused_acc<Bf16PTag, 4>(cfg, a, prepare, s);
+    case VK_F16P: return fused_acc<F16PTag, 4>(cfg, a, prepare, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace
+
+hipError_t prepare_fused(const FusedCfg &cfg, int vk, int64_t n)
+{
+    SpView none{};
+    FusedArgs a{&none, n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    return fused_dispatch(cfg, vk, a, 1, nullptr);
+}
+
+hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
+                        const float *upper, const float *D, const SliceState *st, double *partials, void *ypart,
+                        hipStream_t s)
+{
+    FusedArgs a{&A, n, x, lower, upper, D, st, partials, ypart};
+    return fused_dispatch(cfg, vk, a, 0, s);
+}
+
+hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, const float *lo,
+                              const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
+                              const double *part1, Hist h, hipStream_t s)
+{
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1) return hipErrorInvalidValue;
+    const unsigned grid = grid_for(n, 64, 4096);
+    if (cfg.acc64)
+        hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kBlock), 0, s, static_cast<const double *>(ypart),
+                           cfg.grid, (int)n, x, lo, hi, lambda, st_in, st_out, part1, cfg.grid, h);
+    else
+        hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kBlock), 0, s, static_cast<const float *>(ypart),
+                           cfg.grid, (int)n, x, lo, hi, lambda, st_in, st_out, part1, cfg.grid, h);
+    return hipGetLastError();
 }
 
 hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s)

@@ -12,6 +12,7 @@ constexpr int kBlock = 256;    // threads per workgroup for every kernel (4 wave
 constexpr int kRowAlign = 8;   // entries of every row/column start at a multiple of this
 constexpr int kTrialChunk = 8; // trial steps evaluated per register batch
 constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
+constexpr int kFusedBlock = 1024; // threads of a fused-pass workgroup (one per CU: its LDS holds y)
 
 // Stored formats of A's entries.  The packed kinds hold one 32-bit word per
 // entry: the 16-bit value in the low half, a 16-bit index in the high half
@@ -85,6 +86,13 @@ struct PassCfg {
     int grid; // workgroups
 };
 
+// Launch shape of the fused single pass (one slice).
+struct FusedCfg {
+    int lpr;   // lanes per row: 8, 16 or 32
+    int grid;  // workgroups, each with an LDS copy of y
+    int acc64; // 1: float64 LDS accumulators, 0: float32
+};
+
 // Row blocks of a row-aligned layout for the streaming kernels: block b holds
 // rows [rb[b], rb[b+1]), at most kBlock rows and at most kStreamEntries
 // entries, or a single longer row.
@@ -119,6 +127,23 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
                         const float *lo, const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
                         int B, const double *part1, int nparts1, Hist h, hipStream_t s);
+// fused pass over the CSR: r = A z, t, c = D t, the proximity partial per
+// workgroup, and one partial vector of y = A^T c per workgroup in ypart
+// (grid x n, float64 or float32 by cfg.acc64).  lds_bytes: dynamic LDS it needs.
+size_t fused_lds_bytes(int64_t n, int acc64);
+hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
+                        const float *upper, const float *D, const SliceState *st, double *partials, void *ypart,
+                        hipStream_t s);
+// x = clip(z + lambda * sum of the partial vectors, lo, hi); closes the iteration
+hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, const float *lo,
+                              const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
+                              const double *part1, Hist h, hipStream_t s);
+// largest dynamic LDS one fused workgroup may take on the current device, after
+// the kernel's attributes are raised to it (0 if that fails)
+size_t fused_lds_limit();
+// raise the dynamic-LDS attribute of the fused kernel of this shape (call
+// before its first launch, outside stream capture)
+hipError_t prepare_fused(const FusedCfg &cfg, int vk, int64_t n);
 // query: proximity from pass 1's partials into out[B]
 hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s);
 

@@ -90,6 +90,10 @@ class Group:
             zeros_m = np.zeros((spec.m, B), np.float32)
             self.prob = Problem(self.op, lower=zeros_m, upper=zeros_m, B=B, device=device, stream=self.stream,
                                 refine_iters=0, **spec.params)
+        # the two passes sum in a fixed order: a request's result does not depend
+        # on what shares its group (a one-slot group would otherwise take the
+        # fused pass, whose LDS atomics sum in a varying order)
+        self.prob.set_fused(False)
         for s in range(B):
             self.prob.slot_disable(s)
         self.free = list(range(B))

@@ -37,8 +37,8 @@ def rel(a, b, floor=0.0):
     return float(np.linalg.norm(np.asarray(a, float) - np.asarray(b, float)) / max(np.linalg.norm(b), floor, 1e-300))
 
 
-def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1):
-    p = smx.problem_from_workload(w, storage=storage, history_cap=K, refine_iters=refine_iters)
+def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1, fused=True):
+    p = smx.problem_from_workload(w, storage=storage, history_cap=K, refine_iters=refine_iters, fused=fused)
     p.run(K, perturb=perturb, graph=graph)
     p.sync()
     x = p.get_x().cpu().numpy().astype(np.float64)
@@ -88,7 +88,7 @@ def storage_deviation(w, K, perturb=True, s=0, value_round=None, refine=0):
 
 
 def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=None, refine_iters=-1,
-                 sensitive=False):
+                 sensitive=False, fused=True):
     """End-to-end parity.  With sensitive=True (TV problems, whose gradient
     amplifies rounding of the iterate), the iterate and proximity tolerances
     are max(tol, 10 x the deviation float32 storage of the iterate alone
@@ -97,8 +97,9 @@ def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=N
     the emulation rounds one), and the objective must agree to first order
     with the iterate's difference: |df| <= 2 ||grad f|| ||dx|| + tol |f|.  The
     strict per-iteration check is the lockstep test."""
-    say(f"{w.name} m={w.m} n={w.n} nnz={w.nnz} K={K} perturb={perturb} obj={w.obj} storage={storage}")
-    x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters)
+    say(f"{w.name} m={w.m} n={w.n} nnz={w.nnz} K={K} perturb={perturb} obj={w.obj} storage={storage} "
+        f"fused={fused}")
+    x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters, fused=fused)
     refine = 0
     if storage != "f32":
         refine = refine_iters if refine_iters >= 0 else (K + 19) // 20
@@ -255,9 +256,9 @@ def test_lowp_against_float_operator(smx, storage):
 
 def test_graph_replay_is_bitwise_eager(smx):
     w = W.ct(N=48, n_angles=36, seed=13, K=37)
-    say("graph vs eager")
-    xe, pe, fe, he, _ = gpu_run(smx, w, w.K, graph=False)
-    xg, pg, fg, hg, _ = gpu_run(smx, w, w.K, graph=True)
+    say("graph vs eager (two passes)")
+    xe, pe, fe, he, _ = gpu_run(smx, w, w.K, graph=False, fused=False)
+    xg, pg, fg, hg, _ = gpu_run(smx, w, w.K, graph=True, fused=False)
     assert np.array_equal(xe, xg)
     assert np.array_equal(he["trials"], hg["trials"])
     assert np.array_equal(he["prox"], hg["prox"])
@@ -265,22 +266,22 @@ def test_graph_replay_is_bitwise_eager(smx):
 
 def test_repeat_is_bitwise(smx):
     w = W.random_sparse(2000, 1500, 20, seed=14, obj=W.OBJ_TV2D, tv_shape=(30, 50), K=20)
-    say("repeat")
-    a = gpu_run(smx, w, w.K)
-    b = gpu_run(smx, w, w.K)
+    say("repeat (two passes)")
+    a = gpu_run(smx, w, w.K, fused=False)
+    b = gpu_run(smx, w, w.K, fused=False)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
 def test_checkpoint_resume_bitwise(smx):
     w = W.ct(N=40, n_angles=30, seed=15, K=30, variant="paper")
-    say("checkpoint/resume")
-    xa, _, _, _, sa = gpu_run(smx, w, w.K)
-    p = smx.problem_from_workload(w, history_cap=0)
+    say("checkpoint/resume (two passes)")
+    xa, _, _, _, sa = gpu_run(smx, w, w.K, fused=False)
+    p = smx.problem_from_workload(w, history_cap=0, fused=False)
     p.run(11)
     p.sync()
     states, x1 = p.get_state()
     p.close()
-    q = smx.problem_from_workload(w, history_cap=0)
+    q = smx.problem_from_workload(w, history_cap=0, fused=False)
     q.set_state(states, x1)
     q.run(w.K - 11)
     q.sync()
@@ -383,3 +384,93 @@ def test_autotuned_shapes_keep_parity(smx):
     assert np.array_equal(h["trials"][:, 0], ho.trials)
     dx, _, _ = storage_deviation(w, w.K)
     assert rel(x, xo) <= max(RTOL, 10 * dx)
+
+
+# ---------------------------------------------------------------------------
+# fused single pass (one slice, y = A^T c accumulated in LDS)
+# ---------------------------------------------------------------------------
+
+def _fused_info(smx, w, storage="f32"):
+    p = smx.problem_from_workload(w, storage=storage)
+    d = p.describe()
+    p.close()
+    kind = storage if storage != "f32" else "f32"
+    return d[kind]["fused"]
+
+
+@pytest.mark.parametrize("case", ["rt", "ct_tv", "edge_rows", "sqnorm_paper"])
+def test_fused_pass_parity(smx, case):
+    """The fused pass against the oracle on each objective, with empty rows,
+    rows longer than a lane group's reach and an infeasible band set."""
+    if case == "rt":
+        w = W.rt(grid=(24, 24, 12), beamlets=(7, 7), seed=50, K=25)
+    elif case == "ct_tv":
+        w = W.ct(N=40, n_angles=30, seed=51, K=30)
+    elif case == "edge_rows":
+        w = W.random_sparse(3000, 2500, 25, seed=52, empty_frac=0.05, long_rows=4, long_len=2200,
+                            obj=W.OBJ_LINEAR, K=15)
+    else:
+        w = W.random_sparse(2000, 1200, 30, seed=53, obj=W.OBJ_SQNORM, K=20).with_params(
+            gamma=5.0, n_red=4, restart_every=7)
+    info = _fused_info(smx, w)
+    assert info is not None and info["in_use"] and info["acc"] == "f64", info
+    check_parity(smx, w, w.K, sensitive=(w.obj == W.OBJ_TV2D))
+
+
+def test_fused_float32_accumulators(smx):
+    """n too large for a float64 LDS copy of y but within a float32 one."""
+    w = W.random_sparse(4000, 30000, 40, seed=54, obj=W.OBJ_SQNORM, K=12)
+    info = _fused_info(smx, w)
+    assert info is not None and info["in_use"] and info["acc"] == "f32", info
+    check_parity(smx, w, w.K)
+
+
+def test_fused_absent_when_y_does_not_fit(smx):
+    w = W.random_sparse(500, 70000, 20, seed=55, obj=W.OBJ_NONE, K=3)
+    assert _fused_info(smx, w) is None
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_fused_reduced_precision(smx, storage):
+    w = W.rt(grid=(24, 24, 12), beamlets=(7, 7), seed=56, K=20)
+    info = _fused_info(smx, w, storage)
+    assert info is not None and info["in_use"], info
+    check_parity(smx, w, w.K, storage=storage, value_round=storage, refine_iters=0)
+
+
+def test_fused_agrees_with_two_passes(smx):
+    w = W.ct(N=48, n_angles=36, seed=57, K=25)
+    say("fused vs two passes")
+    xf, pf, ff, hf, _ = gpu_run(smx, w, w.K, fused=True)
+    xt, pt, ft, ht, _ = gpu_run(smx, w, w.K, fused=False)
+    assert np.array_equal(hf["trials"], ht["trials"])
+    dx, _, _ = storage_deviation(w, w.K)
+    assert rel(xf, xt) <= max(RTOL, 10 * dx)
+    np.testing.assert_allclose(hf["prox"], ht["prox"], rtol=max(RTOL, 10 * dx))
+
+
+def test_fused_graph_replay_and_tiny_grids(smx):
+    """Graph replay of the fused pass, and an operator with fewer rows than
+    fused workgroups (most workgroups get no rows)."""
+    w = W.random_sparse(40, 30, 6, seed=58, obj=W.OBJ_SQNORM, K=23)
+    info = _fused_info(smx, w)
+    assert info is not None and info["in_use"] and info["grid"] > w.m
+    say("fused graph replay, tiny grid")
+    xe, _, _, he, _ = gpu_run(smx, w, w.K, graph=False)
+    xg, _, _, hg, _ = gpu_run(smx, w, w.K, graph=True)
+    assert np.array_equal(he["trials"], hg["trials"])
+    assert rel(xg, xe) <= RTOL
+    check_parity(smx, w, w.K)
+
+
+def test_set_fused_switches_kernels(smx):
+    w = W.ct(N=24, n_angles=16, seed=59, K=5)
+    p = smx.problem_from_workload(w)
+    assert p.fused_in_use()
+    p.set_fused(False)
+    assert not p.fused_in_use()
+    p.set_fused(True)
+    assert p.fused_in_use()
+    with pytest.raises(smx.SmxError):
+        smx.check(smx.lib().smx_set_fused(p.handle, 2))
+    p.close()
