@@ -264,6 +264,15 @@ int smx_autotune(smx_problem *p, int32_t reps);
  * fused pass is available (mode 1 then changes nothing). */
 int smx_set_fused(smx_problem *p, int32_t mode);
 
+/* Pin the launch shape of the fused pass instead of the default or the
+ * autotuner's choice: lanes per row (8, 16, 32), entries per load (4, 8) and
+ * cap: 0 to read a row's entries again for the scatter, or 256/(lpr*vec) (16
+ * or 32 lanes only) to keep 256 entries of each row in registers.  Results
+ * do not depend on the shape beyond float64 summation order.  Errors:
+ * SMX_ESTATE when the problem has no fused pass, SMX_EINVAL for another
+ * shape. */
+int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap);
+
 /* JSON description of the launch shapes in use (NUL-terminated, truncated to
  * cap bytes); *need (if non-NULL) receives the full size. */
 int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need);

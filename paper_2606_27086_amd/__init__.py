@@ -49,6 +49,7 @@ EXPORTS = [
     "smx_autotune",
     "smx_describe",
     "smx_set_fused",
+    "smx_set_fused_shape",
     "smx_slot_load",
     "smx_slot_disable",
     "smx_slot_status",
@@ -152,6 +153,7 @@ def lib() -> C.CDLL:
     L.smx_slot_get_x.argtypes = [vp, i32, vp, i32]
     L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.smx_set_fused.argtypes = [vp, i32]
+    L.smx_set_fused_shape.argtypes = [vp, i32, i32, i32]
     for name in EXPORTS:
         if name != "smx_last_error":
             getattr(L, name).restype = C.c_int
@@ -385,6 +387,10 @@ class Problem:
         """Fused single pass for one-slice problems where it is available (on),
         or always the two bitwise-reproducible passes (off)."""
         check(lib().smx_set_fused(self.handle, 1 if on else 0))
+
+    def set_fused_shape(self, lpr: int, vec: int, cap: int):
+        """Pin the fused pass's launch shape (see smx_set_fused_shape)."""
+        check(lib().smx_set_fused_shape(self.handle, int(lpr), int(vec), int(cap)))
 
     def fused_in_use(self) -> bool:
         d = self.describe()

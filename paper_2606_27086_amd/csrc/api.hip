@@ -601,6 +601,28 @@ int run_impl(smx_problem *p, int32_t K, uint32_t flags)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Launch shapes of the fused pass tried by the autotuner (same grid and
+// accumulator type as `base`): 8/16/32 lanes per row with 4 or 8 entries per
+// load re-reading the entries for the scatter, and the register-cached shapes
+// (256 entries of a row in registers).
+std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
+{
+    std::vector<FusedCfg> out;
+    for (int lpr : {8, 16, 32})
+        for (int vec : {4, 8}) {
+            FusedCfg t = base;
+            t.lpr = lpr;
+            t.vec = vec;
+            t.cap = 0;
+            out.push_back(t);
+            if (lpr >= 16) {
+                t.cap = 256 / (lpr * vec);
+                out.push_back(t);
+            }
+        }
+    return out;
+}
+
 // Fused single pass for one slice when an LDS copy of y fits (float64 if it
 // can, else float32).  Lanes per row follow the mean row length; one or two
 // workgroups per CU, as many as the LDS allows.
@@ -623,6 +645,8 @@ void setup_fused(smx_problem *p)
     const double mean = L.rows > 0 ? double(L.slots) / double(L.rows) : 0.0;
     FusedCfg c;
     c.lpr = mean <= 64 ? 8 : (mean <= 256 ? 16 : 32);
+    c.vec = 4;
+    c.cap = 0;
     c.grid = std::max(1, std::min(cus * per_cu, kMaxPassGrid));
     c.acc64 = acc64;
     bool any = false;
@@ -630,11 +654,8 @@ void setup_fused(smx_problem *p)
         const bool present = (vk == VK_F32) ? p->op->has_f32 : (vk == p->op->lp_kind());
         if (!present) continue;
         bool ok = true;
-        for (int lpr : {8, 16, 32}) {
-            FusedCfg t = c;
-            t.lpr = lpr;
+        for (const FusedCfg &t : fused_candidates(c))
             if (prepare_fused(t, p->fmt1[vk], p->n) != hipSuccess) ok = false;
-        }
         (void)hipGetLastError();
         p->fused_ok[vk] = p->fused[vk] = ok;
         p->fcfg[vk] = c;
@@ -716,7 +737,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     pp.n_red = std::max(1, d->n_red);
     pp.restart_every = d->restart_every;
     pp.max_trials = std::max(1, d->max_trials);
-    pp.first_width = std::min(pp.max_trials, kTrialChunk);
+    pp.first_width = std::min(pp.max_trials, kFirstWidth);
     upload(p->lower, lo, s, "bounds");
     upload(p->upper, up, s, "bounds");
     upload(p->box_lo, blo, s, "box");
@@ -899,9 +920,7 @@ int autotune_impl(smx_problem *p, int reps)
             if (p->fused_ok[vk] && p->fused_mode == 1) {
                 double bestf = 1e30;
                 FusedCfg bestfc = p->fcfg[vk];
-                for (int lpr : {8, 16, 32}) {
-                    FusedCfg c = p->fcfg[vk];
-                    c.lpr = lpr;
+                for (const FusedCfg &c : fused_candidates(p->fcfg[vk])) {
                     auto launch = [&]() {
                         hip_check(launch_fused(c, view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], n, xs.as<float>(),
                                                p->lower.as<float>(), p->upper.as<float>(), D, st0,
@@ -953,9 +972,6 @@ const char *fmt_name(int f)
     }
 }
 
-// entries per load of the fused kernel for a stored format
-int fused_vec(int fmt) { return (fmt == VK_BF16 || fmt == VK_F16) ? 8 : 4; }
-
 int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
 {
     std::string out = "{";
@@ -969,8 +985,9 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         char fz[160];
         if (p->fused_ok[vk]) {
             const FusedCfg &f = p->fcfg[vk];
-            snprintf(fz, sizeof fz, "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"acc\": \"%s\"}",
-                     p->fused[vk] ? "true" : "false", f.lpr, fused_vec(p->fmt1[vk]), f.grid, f.acc64 ? "f64" : "f32");
+            snprintf(fz, sizeof fz,
+                     "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"cap\": %d, \"grid\": %d, \"acc\": \"%s\"}",
+                     p->fused[vk] ? "true" : "false", f.lpr, f.vec, f.cap, f.grid, f.acc64 ? "f64" : "f32");
         } else {
             snprintf(fz, sizeof fz, "null");
         }
@@ -1349,6 +1366,31 @@ int smx_set_fused(smx_problem *p, int32_t mode)
         p->fused_mode = mode;
         for (int vk = 0; vk < 3; ++vk) p->fused[vk] = p->fused_ok[vk] && mode == 1;
         // the kernel choice is baked into captured graphs
+        hip_check(hipStreamSynchronize(p->stream), "sync");
+        for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+        p->graphs.clear();
+        return SMX_OK;
+    })
+}
+
+int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    SMX_GUARD({
+        bool any = false;
+        for (int vk = 0; vk < 3; ++vk) any = any || p->fused_ok[vk];
+        if (!any) return fail(SMX_ESTATE, "this problem has no fused pass");
+        bool found = false;
+        for (int vk = 0; vk < 3; ++vk) {
+            if (!p->fused_ok[vk]) continue;
+            for (const FusedCfg &c : fused_candidates(p->fcfg[vk]))
+                if (c.lpr == lpr && c.vec == vec && c.cap == cap) {
+                    p->fcfg[vk] = c;
+                    found = true;
+                }
+        }
+        if (!found)
+            return fail(SMX_EINVAL, "unsupported fused shape lpr %d vec %d cap %d", lpr, vec, cap);
         hip_check(hipStreamSynchronize(p->stream), "sync");
         for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
         p->graphs.clear();

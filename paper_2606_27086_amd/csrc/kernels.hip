@@ -31,13 +31,51 @@ namespace smx {
 // signals another one, and every sum is reproducible bit for bit.
 // ---------------------------------------------------------------------------
 
+// A float64 value moved across lanes by one DPP control (lanes with no source,
+// and lanes outside row_mask, receive 0).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline double dpp_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ inline double lane_value(double v, int lane)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane.  Register-to-
+// register DPP steps: prefix sums inside each row of 16 lanes (shifts by 1, 2,
+// 4, 8), then row 0's total into row 1 and row 2's into row 3 (broadcast of
+// lane 15), then lane 31's into rows 2 and 3; lane 63 ends with the total.
+// The NV sums are independent, so their steps interleave.  Every lane of the
+// wave must be active.
 template <int NV>
 __device__ inline void wave_sum(double (&v)[NV])
 {
+    constexpr int G = NV < 8 ? NV : 8; // values interleaved at a time (bounds the temporaries)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
+    for (int k0 = 0; k0 < NV; k0 += G) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] += dpp_f64<0x111>(v[k]);
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] += dpp_f64<0x112>(v[k]);
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] += dpp_f64<0x114>(v[k]);
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] += dpp_f64<0x118>(v[k]);
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] += dpp_f64<0x142, 0xA>(v[k]);
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] += dpp_f64<0x143, 0xC>(v[k]);
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < NV; ++k) v[k] = lane_value(v[k], 63);
     }
 }
 
@@ -620,9 +658,18 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused(SpView A, int n, const fl
             const double t = fmin(fmax(r, (double)lo), (double)up) - r;
             const double dt = (double)d * t;
             if (lane == 0) pacc[0] += dt * t;
-            if (dt != 0.0) { // the same entries again, now from the cache
+            if (dt != 0.0 && end > beg) { // the same entries again, now from the cache
+                // Neighbouring rows tend to share columns in the same order, so the
+                // groups of a wave start at different chunks of their rows: at any
+                // moment they add into different parts of y.
                 const double sc = dt * (double)A.vscale_inv;
-                for (int p = beg + lane * VEC; p < end; p += LPR * VEC) {
+                constexpr int STEP = LPR * VEC;
+                const int nch = (end - beg + STEP - 1) / STEP;
+                int k = grp % nch;
+                for (int q = 0; q < nch; ++q) {
+                    const int p = beg + k * STEP + lane * VEC;
+                    if (++k == nch) k = 0;
+                    if (p >= end) continue;
                     float v[VEC];
                     int c[VEC];
                     Entries<VT, VEC>::load(A, p, v, c);
@@ -638,6 +685,154 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused(SpView A, int n, const fl
     if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
     AccT *out = ypart + (long long)blockIdx.x * n;
     for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
+}
+
+// Register-cached, software-pipelined form of the fused pass.  A group of
+// LPR lanes keeps up to CAP chunks (LPR*VEC entries each) of its row in
+// registers, so the scatter of c_i a_i reuses the loaded entries instead of
+// reading them again.  While row i is being reduced and scattered, the
+// entries of the group's next row and the offsets and band of the row after
+// it are already in flight.  Within a group, lane l holds the chunk slots of
+// lane (l + group) mod LPR: the groups of a wave (neighbouring rows, which
+// often list the same columns in the same order) then touch different
+// columns in the same LDS atomic instruction, and each group still reads one
+// contiguous stretch of its row.  Entries past CAP chunks (rows longer than
+// CAP*LPR*VEC) are streamed and re-read from the cache as in k_fused.  Two
+// rows in registers need more than the 128 registers a 1024-thread
+// workgroup leaves a lane, so these workgroups have 512 threads.
+template <int VEC, int CAP>
+struct RowRegs {
+    float v[CAP][VEC];
+    int c[CAP][VEC];
+};
+
+template <int LPR, int VEC, int CAP, typename VT>
+__device__ inline void fetch_entries(const SpView &A, int beg, int end, int slot, RowRegs<VEC, CAP> &R)
+{
+#pragma unroll
+    for (int q = 0; q < CAP; ++q) {
+        const int p = beg + (q * LPR + slot) * VEC;
+        if (p < end) {
+            Entries<VT, VEC>::load(A, p, R.v[q], R.c[q]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                R.v[q][e] = 0.f;
+                R.c[q][e] = 0;
+            }
+        }
+    }
+}
+
+template <int LPR, int VEC, int CAP, typename VT, typename AccT>
+__global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, const float *__restrict__ x,
+                                                          const float *__restrict__ lower,
+                                                          const float *__restrict__ upper,
+                                                          const float *__restrict__ D,
+                                                          const SliceState *__restrict__ st,
+                                                          double *__restrict__ partials, AccT *__restrict__ ypart)
+{
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+    AccT *y = reinterpret_cast<AccT *>(fused_lds);
+    __shared__ double lds[kFusedRcBlock / 64];
+    __shared__ int range[2];
+    constexpr int RPB = kFusedRcBlock / LPR;
+    constexpr int STEP = LPR * VEC;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const int slot = (lane + grp) & (LPR - 1);
+    const bool live = st[0].live != 0;
+    for (int j = threadIdx.x; j < n; j += kFusedRcBlock) y[j] = AccT(0);
+    if (threadIdx.x == 0) {
+        const long long total = A.ptr[A.rows];
+        range[0] = first_row_at(A.ptr, (int)A.rows, total * blockIdx.x / gridDim.x);
+        range[1] = first_row_at(A.ptr, (int)A.rows, total * (blockIdx.x + 1) / gridDim.x);
+    }
+    __syncthreads();
+    const int r0 = range[0], r1 = range[1];
+    double pacc[1] = {0.0};
+    int row = r0 + grp;
+    if (live && row < r1) {
+        // row `row`: entries in cur; row + RPB: offsets/band in nb..; entries follow
+        RowRegs<VEC, CAP> cur, nxt;
+        int beg = A.ptr[row], end = A.ptr[row + 1];
+        float lo = lower[row], up = upper[row], d = D[row];
+        fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, cur);
+        int nb = 0, ne = 0;
+        float nlo = 0.f, nup = 0.f, nd = 0.f;
+        if (row + RPB < r1) {
+            nb = A.ptr[row + RPB];
+            ne = A.ptr[row + RPB + 1];
+            nlo = lower[row + RPB];
+            nup = upper[row + RPB];
+            nd = D[row + RPB];
+        }
+        for (;;) {
+            float xg[CAP][VEC];
+#pragma unroll
+            for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) xg[q][e] = x[cur.c[q][e]];
+            const int rn = row + RPB, rnn = row + 2 * RPB;
+            if (rn < r1) fetch_entries<LPR, VEC, CAP, VT>(A, nb, ne, slot, nxt);
+            int hb = 0, he = 0;
+            float hlo = 0.f, hup = 0.f, hd = 0.f;
+            if (rnn < r1) {
+                hb = A.ptr[rnn];
+                he = A.ptr[rnn + 1];
+                hlo = lower[rnn];
+                hup = upper[rnn];
+                hd = D[rnn];
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc = fma((double)cur.v[q][e], (double)xg[q][e], acc);
+            const bool tail = end - beg > CAP * STEP;
+            if (tail) acc += row_dot<LPR, VEC, VT>(A, beg + CAP * STEP, end, lane, x);
+            const double r = group_sum<LPR>(acc) * (double)A.vscale_inv;
+            const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+            const double dt = (double)d * t;
+            if (lane == 0) pacc[0] += dt * t;
+            if (dt != 0.0) {
+                const double sc = dt * (double)A.vscale_inv;
+#pragma unroll
+                for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (cur.v[q][e] != 0.f) lds_add(&y[cur.c[q][e]], sc * (double)cur.v[q][e]);
+                if (tail) {
+                    for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
+                        float v[VEC];
+                        int c[VEC];
+                        Entries<VT, VEC>::load(A, p, v, c);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            if (v[e] != 0.f) lds_add(&y[c[e]], sc * (double)v[e]);
+                    }
+                }
+            }
+            if (rn >= r1) break;
+            row = rn;
+            beg = nb;
+            end = ne;
+            lo = nlo;
+            up = nup;
+            d = nd;
+            cur = nxt;
+            nb = hb;
+            ne = he;
+            nlo = hlo;
+            nup = hup;
+            nd = hd;
+        }
+    }
+    block_sum<1, kFusedRcBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
+    if (!live) return;
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+    AccT *out = ypart + (long long)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kFusedRcBlock) out[j] = y[j];
 }
 
 // x = clip(z + lambda * sum_g ypart[g], lo, hi); 64 unknowns per workgroup, the
@@ -832,11 +1027,21 @@ __device__ inline double trial_beta(const PertParams &pp, long long e) { return 
 
 // Number of trials a trial launch evaluates for slice state S: a short batch
 // when a reduction step starts, all remaining ones (up to the cap) after that.
+// Trials a launch evaluates: the first batch of a reduction step is the
+// default width, widened to 1.5x the trials the previous step needed (step
+// sizes shrink along the phase, so that is usually enough); a second batch
+// takes every trial left up to the cap.  The width only decides how many
+// trials are evaluated speculatively: the accepted trial is the first
+// acceptable one in order whatever the width.
 __device__ inline int trial_width(const SliceState &S, const PertParams &pp)
 {
     if (!S.phase) return 0;
     const int left = pp.max_trials - S.step_tried;
-    return S.step_tried == 0 ? min(pp.first_width, left) : left;
+    if (S.step_tried != 0) return left;
+    int w = pp.first_width;
+    const int want = S.need_last + (S.need_last >> 1);
+    if (want > w) w = ((want + kFirstWidth - 1) / kFirstWidth) * kFirstWidth;
+    return min(w, left);
 }
 
 // Grid of the phase kernels: blockIdx.y is the slice, blockIdx.x a tile (TV)
@@ -857,9 +1062,14 @@ __device__ inline void tile_sums(const double *__restrict__ part, long long nslo
 #pragma unroll
     for (int k = 0; k < NV; ++k) tot[k] = 0.0;
     for (int b = threadIdx.x; b < nt; b += kBlock) {
+        // every load issued before any is used (rows past nv repeat the last
+        // row and are dropped), so the loads overlap instead of queueing
+        double v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = part[(long long)(v0 + min(k, nv - 1)) * nslots + (long long)s * nt + b];
 #pragma unroll
         for (int k = 0; k < NV; ++k)
-            if (k < nv) tot[k] += part[(long long)(v0 + k) * nslots + (long long)s * nt + b];
+            if (k < nv) tot[k] += v[k];
     }
     block_sum<NV>(tot, lds);
 }
@@ -927,6 +1137,7 @@ __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, con
             S.accepts_it += 1;
             S.accepts += 1;
             S.n_done += 1;
+            S.need_last = S.step_tried + acc_t + 1;
             S.step_tried = 0;
             if (S.n_done >= pp.n_red) S.phase = 0;
         } else {
@@ -936,6 +1147,7 @@ __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, con
             S.step_tried += ntr;
             if (S.step_tried >= pp.max_trials) {
                 S.cap_hits += 1;
+                S.need_last = pp.max_trials;
                 S.phase = 0;
             }
         }
@@ -1114,35 +1326,52 @@ __global__ __launch_bounds__(kBlock) void k_trial_tv(float *__restrict__ x, cons
     const int R = pp.tv_rows, C = pp.tv_cols;
     const int tiles_x = (C + kTile - 1) / kTile;
     const int i0 = (blockIdx.x / tiles_x) * kTile, j0 = (blockIdx.x % tiles_x) * kTile;
+    // the tile of x and g (with its +1 row and column) is loaded while the state
+    // is derived; kept in registers until then
+    constexpr int TE = (kTile + 1) * (kTile + 1);
+    constexpr int TPT = (TE + kBlock - 1) / kBlock;
+    float pxv[TPT], pgv[TPT];
+#pragma unroll
+    for (int h = 0; h < TPT; ++h) {
+        const int e = threadIdx.x + h * kBlock;
+        const int gi = i0 + e / (kTile + 1), gj = j0 + e % (kTile + 1);
+        pxv[h] = pgv[h] = 0.f;
+        if (e < TE && gi < R && gj < C) {
+            pxv[h] = x[((long long)gi * C + gj) * B + s];
+            pgv[h] = g[((long long)gi * C + gj) * B + s];
+        }
+    }
     derive_state(sS, st_in, pp, first, part_prev, s, nt, lds);
-    const SliceState S = sS;
+    const SliceState &S = sS; // read from LDS (a register copy of the struct spills)
     const int li = threadIdx.x / kTile, lj = threadIdx.x % kTile;
     const int i = i0 + li, j = j0 + lj;
-    if (must_apply(S)) {
+    const bool apply = must_apply(S);
+    const int ntr = (evaluate && !apply) ? trial_width(S, pp) : 0;
+    if (!apply && ntr == 0) {
+        publish_state(S, st_out, s, false);
+        return;
+    }
+#pragma unroll
+    for (int h = 0; h < TPT; ++h) {
+        const int e = threadIdx.x + h * kBlock;
+        if (e < TE) {
+            tx[e / (kTile + 1)][e % (kTile + 1)] = pxv[h];
+            tg[e / (kTile + 1)][e % (kTile + 1)] = pgv[h];
+        }
+    }
+    if (apply) { // x and g at this pixel are the tile's (no other workgroup writes them)
+        __syncthreads();
         if (i < R && j < C) {
             const long long e = ((long long)i * C + j) * B + s;
-            x[e] = (float)((double)x[e] + S.s_acc * (-(double)g[e] * (1.0 / S.gn)));
+            x[e] = (float)((double)tx[li][lj] + S.s_acc * (-(double)tg[li][lj] * (1.0 / S.gn)));
         }
         publish_state(S, st_out, s, true);
         return;
     }
     publish_state(S, st_out, s, false);
-    const int ntr = evaluate ? trial_width(S, pp) : 0;
-    if (ntr == 0) return;
     const long long nslots = (long long)B * nt, slot = (long long)s * nt + blockIdx.x;
     const double inv_gn = 1.0 / S.gn;
     for (int t = threadIdx.x; t < ntr; t += kBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
-    for (int e = threadIdx.x; e < (kTile + 1) * (kTile + 1); e += kBlock) {
-        const int ai = e / (kTile + 1), aj = e % (kTile + 1);
-        const int gi = i0 + ai, gj = j0 + aj;
-        float xv = 0.f, gv = 0.f;
-        if (gi < R && gj < C) {
-            xv = x[((long long)gi * C + gj) * B + s];
-            gv = g[((long long)gi * C + gj) * B + s];
-        }
-        tx[ai][aj] = xv;
-        tg[ai][aj] = gv;
-    }
     __syncthreads();
     const bool has_term = (i <= R - 2) && (j <= C - 2);
     double x00 = 0, x10 = 0, x01 = 0, v00 = 0, v10 = 0, v01 = 0;
@@ -1185,7 +1414,7 @@ __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, co
     const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
     const bool lin = pp.obj == OBJ_LINEAR;
     derive_state(sS, st_in, pp, first, part_prev, s, nt, lds);
-    const SliceState S = sS;
+    const SliceState &S = sS; // read from LDS (a register copy of the struct spills)
     if (must_apply(S)) {
         const double inv_gn = 1.0 / S.gn;
         for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < pp.n; j += (long long)gridDim.x * kBlock) {
@@ -1327,6 +1556,7 @@ __global__ void k_init_state(SliceState *st, int B)
     S.applied = 0;
     S.enabled = 1;
     S.nonfinite = 0;
+    S.need_last = 0;
     st[s] = S;
 }
 
@@ -1366,6 +1596,7 @@ __global__ void k_reset_slot(SliceState *st, int s, long long budget)
     S.live = S.enabled;
     S.applied = 0;
     S.nonfinite = 0;
+    S.need_last = 0;
     st[s] = S;
 }
 
@@ -1692,12 +1923,23 @@ template <int LPR, typename VT, int VEC, typename AccT>
 hipError_t fused_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
 {
     auto kern = k_fused<LPR, VEC, VT, AccT>;
+    if (cfg.cap > 0) {
+        // register-cached shapes hold CAP*LPR*VEC = 256 entries of a row; with
+        // fewer than 16 lanes a row that takes more registers than a lane has
+        if constexpr (LPR * VEC >= 64 && LPR >= 16) {
+            constexpr int CAP = 256 / (LPR * VEC);
+            if (cfg.cap != CAP) return hipErrorInvalidValue;
+            kern = k_fused_rc<LPR, VEC, CAP, VT, AccT>;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     const size_t bytes = fused_lds_bytes(a.n, sizeof(AccT) == sizeof(double));
     if (prepare)
         return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)bytes);
-    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kFusedBlock), bytes, s, *a.A, (int)a.n, a.x, a.lower, a.upper, a.D,
-                       a.st, a.partials, static_cast<AccT *>(a.ypart));
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.cap > 0 ? kFusedRcBlock : kFusedBlock), bytes, s, *a.A,
+                       (int)a.n, a.x, a.lower, a.upper, a.D, a.st, a.partials, static_cast<AccT *>(a.ypart));
     return hipGetLastError();
 }
 
@@ -1713,20 +1955,28 @@ hipError_t fused_lpr(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipSt
 }
 
 template <typename VT, int VEC>
-hipError_t fused_acc(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
+hipError_t fused_acc_v(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
 {
     return cfg.acc64 ? fused_lpr<VT, VEC, double>(cfg, a, prepare, s) : fused_lpr<VT, VEC, float>(cfg, a, prepare, s);
+}
+
+template <typename VT>
+hipError_t fused_acc(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
+{
+    if (cfg.vec == 4) return fused_acc_v<VT, 4>(cfg, a, prepare, s);
+    if (cfg.vec == 8) return fused_acc_v<VT, 8>(cfg, a, prepare, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t fused_dispatch(const FusedCfg &cfg, int vk, const FusedArgs &a, int prepare, hipStream_t s)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || a.n < 1 || a.n > (int64_t(1) << 30)) return hipErrorInvalidValue;
     switch (vk) {
-    case VK_F32: return fused_acc<float, 4>(cfg, a, prepare, s);
-    case VK_BF16: return fused_acc<Bf16Tag, 8>(cfg, a, prepare, s);
-    case VK_F16: return fused_acc<F16Tag, 8>(cfg, a, prepare, s);
-    case VK_BF16P: return fused_acc<Bf16PTag, 4>(cfg, a, prepare, s);
-    case VK_F16P: return fused_acc<F16PTag, 4>(cfg, a, prepare, s);
+    case VK_F32: return fused_acc<float>(cfg, a, prepare, s);
+    case VK_BF16: return fused_acc<Bf16Tag>(cfg, a, prepare, s);
+    case VK_F16: return fused_acc<F16Tag>(cfg, a, prepare, s);
+    case VK_BF16P: return fused_acc<Bf16PTag>(cfg, a, prepare, s);
+    case VK_F16P: return fused_acc<F16PTag>(cfg, a, prepare, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -10,9 +10,11 @@ namespace smx {
 
 constexpr int kBlock = 256;    // threads per workgroup for every kernel (4 waves of 64)
 constexpr int kRowAlign = 8;   // entries of every row/column start at a multiple of this
-constexpr int kTrialChunk = 8; // trial steps evaluated per register batch
+constexpr int kTrialChunk = 32; // trial steps evaluated (and their totals read) per register batch
+constexpr int kFirstWidth = 8;  // least width of the first trial batch of a reduction step
 constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
 constexpr int kFusedBlock = 1024; // threads of a fused-pass workgroup (one per CU: its LDS holds y)
+constexpr int kFusedRcBlock = 512; // the same for the register-cached fused pass
 
 // Stored formats of A's entries.  The packed kinds hold one 32-bit word per
 // entry: the 16-bit value in the low half, a 16-bit index in the high half
@@ -55,6 +57,7 @@ struct SliceState {
     int applied;    // the accepted step of this phase has been added to x
     int enabled;    // slice participates at all
     int nonfinite;  // a non-finite proximity or objective was seen
+    int need_last;  // trials the last completed reduction step used (sizes the next first batch)
 };
 
 struct PertParams {
@@ -89,6 +92,9 @@ struct PassCfg {
 // Launch shape of the fused single pass (one slice).
 struct FusedCfg {
     int lpr;   // lanes per row: 8, 16 or 32
+    int vec;   // entries per lane per load: 4 or 8
+    int cap;   // 0: entries re-read for the scatter; else chunks per lane kept in
+               // registers (cap * lpr * vec = 256 entries)
     int grid;  // workgroups, each with an LDS copy of y
     int acc64; // 1: float64 LDS accumulators, 0: float32
 };

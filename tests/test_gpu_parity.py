@@ -474,3 +474,41 @@ def test_set_fused_switches_kernels(smx):
     with pytest.raises(smx.SmxError):
         smx.check(smx.lib().smx_set_fused(p.handle, 2))
     p.close()
+
+
+FUSED_SHAPES = [(8, 4, 0), (8, 8, 0), (16, 4, 0), (16, 4, 4), (16, 8, 0), (16, 8, 2), (32, 4, 0), (32, 4, 2),
+                (32, 8, 0), (32, 8, 1)]
+
+
+@pytest.mark.parametrize("case", ["rt", "long_rows"])
+def test_every_fused_shape(smx, case):
+    """Each launch shape of the fused pass (entries re-read or kept in
+    registers, 8-32 lanes per row) against the oracle; the long-row case has
+    rows beyond the 256 entries the register-cached shapes hold."""
+    if case == "rt":
+        w = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=60, K=12)
+        storage, vr = "bf16", "bf16"
+    else:
+        w = W.random_sparse(1500, 3000, 40, seed=61, empty_frac=0.1, long_rows=6, long_len=700,
+                            obj=W.OBJ_SQNORM, K=10)
+        storage, vr = "f32", None
+    xo, sto, ho, P = oracle_run(w, w.K, value_round=vr)
+    for lpr, vec, cap in FUSED_SHAPES:
+        say(f"{case} fused shape lpr={lpr} vec={vec} cap={cap}")
+        p = smx.problem_from_workload(w, storage=storage, history_cap=w.K, refine_iters=0)
+        p.set_fused_shape(lpr, vec, cap)
+        info = p.describe()[storage]["fused"]
+        assert info["in_use"] and (info["lpr"], info["vec"], info["cap"]) == (lpr, vec, cap)
+        p.run(w.K)
+        p.sync()
+        x = p.get_x().cpu().numpy()[:, 0].astype(np.float64)
+        h = p.history()
+        p.close()
+        assert np.array_equal(h["trials"][:, 0], ho.trials)
+        r = rel(x, xo)
+        assert r <= RTOL, (lpr, vec, cap, r)
+        np.testing.assert_allclose(h["prox"][:, 0], ho.prox, rtol=RTOL, atol=1e-6 * abs(ho.prox[0]))
+    p = smx.problem_from_workload(w, storage=storage)
+    with pytest.raises(smx.SmxError):
+        p.set_fused_shape(8, 4, 8)
+    p.close()
