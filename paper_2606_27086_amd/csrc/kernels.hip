@@ -1053,25 +1053,38 @@ int phase_grid(const PertParams &pp)
     return (int)(g < 1 ? 1 : (g > 512 ? 512 : g));
 }
 
-// Sum over the `nt` tiles of slice s of value row v (rows of `nslots` slots),
-// valid in thread 0.
-template <int NV>
-__device__ inline void tile_sums(const double *__restrict__ part, long long nslots, int s, int nt, int v0, int nv,
-                                 double (&tot)[NV], double *lds)
+// Totals over the `nt` tiles of slice s of rows v0 .. v0+nv-1 (rows of
+// `nslots` slots, nv <= kTrialChunk) into tot[0..nv-1] (LDS), for a workgroup
+// of BS threads; every thread must call it, and tot is valid for every thread
+// on return.  Row v0+r is summed by wave r mod (BS/64): lane l adds tiles
+// l, l+64, ... in order, then the lanes are added by wave_sum.  The rows of a
+// wave are loaded together, so their loads overlap.
+template <int BS>
+__device__ inline void chunk_totals(const double *__restrict__ part, long long nslots, int s, int nt, int v0, int nv,
+                                    double *tot)
 {
+    constexpr int W = BS / 64, RPW = (kTrialChunk + W - 1) / W;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double a[RPW];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    for (int b = threadIdx.x; b < nt; b += kBlock) {
-        // every load issued before any is used (rows past nv repeat the last
-        // row and are dropped), so the loads overlap instead of queueing
-        double v[NV];
+    for (int q = 0; q < RPW; ++q) a[q] = 0.0;
+    if (wid < nv) {
+        for (int b = lane; b < nt; b += 64) {
+            double v[RPW];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = part[(long long)(v0 + min(k, nv - 1)) * nslots + (long long)s * nt + b];
+            for (int q = 0; q < RPW; ++q)
+                v[q] = part[(long long)(v0 + min(wid + W * q, nv - 1)) * nslots + (long long)s * nt + b];
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            if (k < nv) tot[k] += v[k];
+            for (int q = 0; q < RPW; ++q) a[q] += v[q];
+        }
+        wave_sum<RPW>(a);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < RPW; ++q)
+                if (wid + W * q < nv) tot[wid + W * q] = a[q];
+        }
     }
-    block_sum<NV>(tot, lds);
+    __syncthreads();
 }
 
 // Opening of a phase from the totals (sum g^2, f(x^k)).
@@ -1101,20 +1114,20 @@ __device__ inline void open_phase_state(SliceState &S, const PertParams &pp, dou
 // Every workgroup: the state after the previous trial launch of slice s, in
 // sS (LDS).  The first trial in order whose objective does not exceed f_cur is
 // accepted; reading stops at the chunk holding it.
+template <int BS>
 __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, const double *__restrict__ part_prev,
-                                       long long nslots, int s, int nt, double *lds)
+                                       long long nslots, int s, int nt, double *tot)
 {
     __shared__ int acc_t;
     __shared__ double acc_f;
     const int ntr = trial_width(sS, pp);
     if (ntr == 0) return;
     if (threadIdx.x == 0) acc_t = -1;
-    __syncthreads();
     for (int t0 = 0; t0 < ntr; t0 += kTrialChunk) {
-        double tot[kTrialChunk];
-        tile_sums<kTrialChunk>(part_prev, nslots, s, nt, t0, min(kTrialChunk, ntr - t0), tot, lds);
+        const int nv = min(kTrialChunk, ntr - t0);
+        chunk_totals<BS>(part_prev, nslots, s, nt, t0, nv, tot);
         if (threadIdx.x == 0) {
-            for (int w = 0; w < kTrialChunk && t0 + w < ntr; ++w) {
+            for (int w = 0; w < nv; ++w) {
                 if (tot[w] <= sS.f_cur) {
                     acc_t = t0 + w;
                     acc_f = tot[w];
@@ -1158,19 +1171,19 @@ __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, con
 // Every workgroup: state of slice s at the start of this launch, in sS.
 // mode 0: the first trial launch (opens the phase from the gradient partials);
 // otherwise: the decision of the previous trial launch.
+template <int BS>
 __device__ inline void derive_state(SliceState &sS, const SliceState *__restrict__ st_in, const PertParams &pp,
-                                    int first, const double *__restrict__ part_prev, int s, int nt, double *lds)
+                                    int first, const double *__restrict__ part_prev, int s, int nt, double *tot)
 {
     if (threadIdx.x == 0) sS = st_in[s];
     __syncthreads();
     const long long nslots = (long long)pp.B * nt;
     if (first) {
-        double tot[2];
-        tile_sums<2>(part_prev, nslots, s, nt, 0, 2, tot, lds);
+        chunk_totals<BS>(part_prev, nslots, s, nt, 0, 2, tot);
         if (threadIdx.x == 0) open_phase_state(sS, pp, tot[0], tot[1]);
         __syncthreads();
     } else {
-        derive_decision(sS, pp, part_prev, nslots, s, nt, lds);
+        derive_decision<BS>(sS, pp, part_prev, nslots, s, nt, tot);
     }
 }
 
@@ -1296,74 +1309,78 @@ __global__ __launch_bounds__(kBlock) void k_eval_objective(SliceState *__restric
                                                            const double *__restrict__ partials, int nt,
                                                            double *__restrict__ out)
 {
-    __shared__ double lds[4 * 2];
+    __shared__ double tot[kTrialChunk];
     for (int s = 0; s < pp.B; ++s) {
-        double tot[2];
-        tile_sums<2>(partials, (long long)pp.B * nt, s, nt, 0, 2, tot, lds);
+        chunk_totals<kBlock>(partials, (long long)pp.B * nt, s, nt, 0, 2, tot);
         if (threadIdx.x == 0) {
             out[s] = tot[1];
             if (!isfinite(tot[1])) st[s].nonfinite = 1;
         }
+        __syncthreads();
     }
 }
 
-// Trial launch for TV: derive the state, then each thread owns one pixel's
-// term tau(i,j) and evaluates it at z = x + (s_acc + beta_t) v for every trial
-// t of this launch (one partial per trial per tile); or, once the phase is
-// over, add s_acc v to the tile.
-__global__ __launch_bounds__(kBlock) void k_trial_tv(float *__restrict__ x, const float *__restrict__ g,
-                                                     const SliceState *__restrict__ st_in,
-                                                     SliceState *__restrict__ st_out, PertParams pp, int first,
-                                                     int evaluate, const double *__restrict__ part_prev,
-                                                     double *__restrict__ part_out)
+// Trial launch for TV (kTrialBlock threads per 16 x 16 tile): derive the
+// state, then evaluate tau at z = x + (s_acc + beta_t) v for every trial t of
+// this launch and every pixel term of the tile (one partial per trial per
+// tile); or, once the phase is over, add s_acc v to the tile.  Wave w takes
+// trials w*4 .. w*4+3, then the next 4 * (waves) trials, and so on; lane l of a
+// wave takes pixels l, l+64, l+128, l+192 of the tile, adds its terms in that
+// order, and wave_sum adds the lanes: each trial's tile sum is made by one
+// wave, with no workgroup barrier, and the 16 waves keep the float64 square
+// roots of different trials in flight together.
+__global__ __launch_bounds__(kTrialBlock) void k_trial_tv(float *__restrict__ x, const float *__restrict__ g,
+                                                          const SliceState *__restrict__ st_in,
+                                                          SliceState *__restrict__ st_out, PertParams pp, int first,
+                                                          int evaluate, const double *__restrict__ part_prev,
+                                                          double *__restrict__ part_out)
 {
+    static_assert(kTile * kTile == 256, "tile of 256 pixels");
     __shared__ float tx[kTile + 1][kTile + 2];
     __shared__ float tg[kTile + 1][kTile + 2];
     __shared__ double coef[1024];
-    __shared__ double lds[4 * kTrialChunk];
+    __shared__ double tot[kTrialChunk];
     __shared__ SliceState sS;
+    constexpr int W = kTrialBlock / 64;
     const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
     const int R = pp.tv_rows, C = pp.tv_cols;
     const int tiles_x = (C + kTile - 1) / kTile;
     const int i0 = (blockIdx.x / tiles_x) * kTile, j0 = (blockIdx.x % tiles_x) * kTile;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // the tile of x and g (with its +1 row and column) is loaded while the state
-    // is derived; kept in registers until then
+    // is derived
     constexpr int TE = (kTile + 1) * (kTile + 1);
-    constexpr int TPT = (TE + kBlock - 1) / kBlock;
-    float pxv[TPT], pgv[TPT];
-#pragma unroll
-    for (int h = 0; h < TPT; ++h) {
-        const int e = threadIdx.x + h * kBlock;
+    static_assert(TE <= kTrialBlock, "one tile element per thread");
+    float pxv = 0.f, pgv = 0.f;
+    {
+        const int e = threadIdx.x;
         const int gi = i0 + e / (kTile + 1), gj = j0 + e % (kTile + 1);
-        pxv[h] = pgv[h] = 0.f;
         if (e < TE && gi < R && gj < C) {
-            pxv[h] = x[((long long)gi * C + gj) * B + s];
-            pgv[h] = g[((long long)gi * C + gj) * B + s];
+            pxv = x[((long long)gi * C + gj) * B + s];
+            pgv = g[((long long)gi * C + gj) * B + s];
         }
     }
-    derive_state(sS, st_in, pp, first, part_prev, s, nt, lds);
+    derive_state<kTrialBlock>(sS, st_in, pp, first, part_prev, s, nt, tot);
     const SliceState &S = sS; // read from LDS (a register copy of the struct spills)
-    const int li = threadIdx.x / kTile, lj = threadIdx.x % kTile;
-    const int i = i0 + li, j = j0 + lj;
     const bool apply = must_apply(S);
     const int ntr = (evaluate && !apply) ? trial_width(S, pp) : 0;
     if (!apply && ntr == 0) {
         publish_state(S, st_out, s, false);
         return;
     }
-#pragma unroll
-    for (int h = 0; h < TPT; ++h) {
-        const int e = threadIdx.x + h * kBlock;
-        if (e < TE) {
-            tx[e / (kTile + 1)][e % (kTile + 1)] = pxv[h];
-            tg[e / (kTile + 1)][e % (kTile + 1)] = pgv[h];
-        }
+    if (threadIdx.x < TE) {
+        tx[threadIdx.x / (kTile + 1)][threadIdx.x % (kTile + 1)] = pxv;
+        tg[threadIdx.x / (kTile + 1)][threadIdx.x % (kTile + 1)] = pgv;
     }
-    if (apply) { // x and g at this pixel are the tile's (no other workgroup writes them)
+    if (apply) { // x and g at a pixel are the tile's (no other workgroup writes them)
         __syncthreads();
-        if (i < R && j < C) {
-            const long long e = ((long long)i * C + j) * B + s;
-            x[e] = (float)((double)tx[li][lj] + S.s_acc * (-(double)tg[li][lj] * (1.0 / S.gn)));
+        if (threadIdx.x < kTile * kTile) {
+            const int li = threadIdx.x / kTile, lj = threadIdx.x % kTile;
+            const int i = i0 + li, j = j0 + lj;
+            if (i < R && j < C) {
+                const long long e = ((long long)i * C + j) * B + s;
+                x[e] = (float)((double)tx[li][lj] + S.s_acc * (-(double)tg[li][lj] * (1.0 / S.gn)));
+            }
         }
         publish_state(S, st_out, s, true);
         return;
@@ -1371,32 +1388,42 @@ __global__ __launch_bounds__(kBlock) void k_trial_tv(float *__restrict__ x, cons
     publish_state(S, st_out, s, false);
     const long long nslots = (long long)B * nt, slot = (long long)s * nt + blockIdx.x;
     const double inv_gn = 1.0 / S.gn;
-    for (int t = threadIdx.x; t < ntr; t += kBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
+    for (int t = threadIdx.x; t < ntr; t += kTrialBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
     __syncthreads();
-    const bool has_term = (i <= R - 2) && (j <= C - 2);
-    double x00 = 0, x10 = 0, x01 = 0, v00 = 0, v10 = 0, v01 = 0;
-    if (has_term) {
-        x00 = tx[li][lj]; x10 = tx[li + 1][lj]; x01 = tx[li][lj + 1];
-        v00 = -(double)tg[li][lj] * inv_gn;
-        v10 = -(double)tg[li + 1][lj] * inv_gn;
-        v01 = -(double)tg[li][lj + 1] * inv_gn;
-    }
-    for (int t0 = 0; t0 < ntr; t0 += kTrialChunk) {
-        double acc[kTrialChunk];
+    double x00[4], x10[4], x01[4], v00[4], v10[4], v01[4];
+    bool has[4];
 #pragma unroll
-        for (int w = 0; w < kTrialChunk; ++w) {
-            acc[w] = 0.0;
-            if (has_term && t0 + w < ntr) {
-                const double cf = coef[t0 + w];
-                const double z00 = x00 + cf * v00, z10 = x10 + cf * v10, z01 = x01 + cf * v01;
-                acc[w] = tv_tau(z00, z10, z01, pp.tv_eps2);
+    for (int h = 0; h < 4; ++h) {
+        const int pix = lane + 64 * h;
+        const int li = pix / kTile, lj = pix % kTile;
+        const int i = i0 + li, j = j0 + lj;
+        has[h] = (i <= R - 2) && (j <= C - 2);
+        x00[h] = tx[li][lj];
+        x10[h] = tx[li + 1][lj];
+        x01[h] = tx[li][lj + 1];
+        v00[h] = -(double)tg[li][lj] * inv_gn;
+        v10[h] = -(double)tg[li + 1][lj] * inv_gn;
+        v01[h] = -(double)tg[li][lj + 1] * inv_gn;
+    }
+    for (int t0 = wid * 4; t0 < ntr; t0 += W * 4) {
+        double acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acc[k] = 0.0;
+            if (t0 + k < ntr) {
+                const double cf = coef[t0 + k];
+#pragma unroll
+                for (int h = 0; h < 4; ++h)
+                    if (has[h])
+                        acc[k] += tv_tau(x00[h] + cf * v00[h], x10[h] + cf * v10[h], x01[h] + cf * v01[h],
+                                         pp.tv_eps2);
             }
         }
-        block_sum<kTrialChunk>(acc, lds);
-        if (threadIdx.x == 0) {
+        wave_sum<4>(acc);
+        if (lane == 0) {
 #pragma unroll
-            for (int w = 0; w < kTrialChunk; ++w)
-                if (t0 + w < ntr) part_out[(long long)(t0 + w) * nslots + slot] = acc[w];
+            for (int k = 0; k < 4; ++k)
+                if (t0 + k < ntr) part_out[(long long)(t0 + k) * nslots + slot] = acc[k];
         }
     }
 }
@@ -1410,10 +1437,11 @@ __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, co
 {
     __shared__ double coef[1024];
     __shared__ double lds[4 * kTrialChunk];
+    __shared__ double tot[kTrialChunk];
     __shared__ SliceState sS;
     const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
     const bool lin = pp.obj == OBJ_LINEAR;
-    derive_state(sS, st_in, pp, first, part_prev, s, nt, lds);
+    derive_state<kBlock>(sS, st_in, pp, first, part_prev, s, nt, tot);
     const SliceState &S = sS; // read from LDS (a register copy of the struct spills)
     if (must_apply(S)) {
         const double inv_gn = 1.0 / S.gn;
@@ -2043,7 +2071,8 @@ hipError_t launch_trial(const PertParams &pp, float *x, const float *g, const Sl
     if (pp.max_trials < 1 || pp.max_trials > 1024) return hipErrorInvalidValue;
     const dim3 grid(phase_grid(pp), pp.B), block(kBlock);
     if (pp.obj == OBJ_TV2D)
-        hipLaunchKernelGGL(k_trial_tv, grid, block, 0, s, x, g, st_in, st_out, pp, first, evaluate, part_prev, part_out);
+        hipLaunchKernelGGL(k_trial_tv, grid, dim3(kTrialBlock), 0, s, x, g, st_in, st_out, pp, first, evaluate,
+                           part_prev, part_out);
     else
         hipLaunchKernelGGL(k_trial_flat, grid, block, 0, s, x, g, st_in, st_out, pp, first, evaluate, part_prev,
                            part_out);

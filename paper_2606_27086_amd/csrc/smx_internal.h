@@ -12,6 +12,7 @@ constexpr int kBlock = 256;    // threads per workgroup for every kernel (4 wave
 constexpr int kRowAlign = 8;   // entries of every row/column start at a multiple of this
 constexpr int kTrialChunk = 32; // trial steps evaluated (and their totals read) per register batch
 constexpr int kFirstWidth = 8;  // least width of the first trial batch of a reduction step
+constexpr int kTrialBlock = 1024; // threads of a TV trial workgroup (one 16 x 16 tile)
 constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
 constexpr int kFusedBlock = 1024; // threads of a fused-pass workgroup (one per CU: its LDS holds y)
 constexpr int kFusedRcBlock = 512; // the same for the register-cached fused pass
