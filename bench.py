@@ -35,7 +35,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
-PMC_TABLE = os.path.join(ROOT, "profiles", "pmc_ct256_pass_traffic.json")
+PMC_TABLE = os.path.join(ROOT, "profiles", "pmc_pass_traffic.json")
+CT_WORKLOAD = "ct256_parallel_beam_180x363_tv"
+RT_WORKLOAD = "rt_160x160x80_9beams_47x47"
 # bytes per stored entry (value + index) and the kernels' value-type tag, by format
 ENTRY_BYTES = {"f32+i32": 8, "bf16+i32": 6, "f16+i32": 6, "bf16+u16": 4, "f16+u16": 4}
 VALUE_TAG = {"f32+i32": "float", "bf16+i32": "smx::Bf16Tag", "f16+i32": "smx::F16Tag",
@@ -81,7 +83,7 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
     return f"smx::k_pass{pass_no}<{shape['lpr']}, {shape['vec']}, {vt}>"
 
 
-def measured_traffic(name):
+def measured_traffic(name, workload):
     """HBM bytes per launch from the committed counter table, or None when the
     table is missing, was taken on other kernel code, or lacks the kernel."""
     try:
@@ -90,7 +92,7 @@ def measured_traffic(name):
         tab = json.load(open(PMC_TABLE))
         if tab.get("kernel_source_sha256") != kernel_source_hash():
             return None
-        k = tab["kernels"].get(name)
+        k = tab["workloads"][workload]["kernels"].get(name)
         return None if k is None else round(k["traffic_bytes"])
     except (OSError, ValueError, KeyError):
         return None
@@ -135,14 +137,14 @@ def summarise(w, r, storage, B=1):
             f"{k2}_gbs": round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1), "launch": r["shapes"]}
 
 
-def roofline_of(w, r, storage, B=1):
+def roofline_of(w, r, storage, B=1, workload=None):
     b1, b2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B)
     t1, t2 = r["pass1_ms"], r["pass2_ms"]
     dpass, dbytes, dms = (1, b1, t1) if t1 >= t2 else (2, b2, t2)
     achieved = dbytes / (dms * 1e-3) / 1e9
     kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], B, shapes=r["shapes"])
     return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname), algorithmic_bytes=int(dbytes),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname, workload), algorithmic_bytes=int(dbytes),
                 step_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
 
 
@@ -223,7 +225,7 @@ def section_hbm(smx, tune):
             t0 = time.time()
             r = time_problem(smx, w, storage, 100, 5, tune=tune, fused=fused)
             s = summarise(w, r, storage)
-            s["roofline"] = roofline_of(w, r, storage)
+            s["roofline"] = roofline_of(w, r, storage, workload=RT_WORKLOAD)
             s["wall_s"] = round(time.time() - t0, 1)
             out[storage if fused else f"{storage}_two_passes"] = s
     return out
@@ -254,7 +256,7 @@ def main():
     torch.cuda.set_device(0)
     tune = not args.no_tune
     w = W.ct(N=256, seed=2, K=200)
-    wname = "ct256_parallel_beam_180x363_tv"
+    wname = CT_WORKLOAD
     graph = not args.no_graph
     results = {st: time_problem(smx, w, st, args.steps, args.warmup, graph=graph, tune=tune) for st in ("f32", "bf16")}
     main_r = results["f32"]
@@ -285,7 +287,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "m": w.m, "n": w.n, "nnz": w.nnz, "B": w.B, "K": w.K, "graph": graph,
                    "storage": "f32"},
-        "roofline": roofline_of(w, main_r, "f32"),
+        "roofline": roofline_of(w, main_r, "f32", workload=CT_WORKLOAD),
         "cpu_baseline": cpu,
         "variants": variants,
     }

@@ -1,6 +1,7 @@
-"""Per-dispatch HBM traffic of the pass kernels from two rocprofv3 --pmc runs
-of pmc_probe.py (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
-what the same counter reads for the probe's plain device copy of known size.
+"""Per-dispatch HBM traffic of the pass kernels (two passes and fused pass)
+from two rocprofv3 --pmc runs of pmc_probe.py (FETCH_SIZE, then WRITE_SIZE, KiB
+per dispatch), each scaled by what the same counter reads for the probe's plain
+device copy of known size, per workload (CT 256x256, radiotherapy).
 
 Writes a JSON table keyed by kernel template, stamped with the SHA-256 of the
 kernel source it was measured on (a changed kernel invalidates it).
@@ -24,33 +25,52 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def per_kernel(db: str, counter: str) -> dict:
+CT_WORKLOAD = "ct256_parallel_beam_180x363_tv"
+RT_WORKLOAD = "rt_160x160x80_9beams_47x47"
+
+
+def dispatches(db: str, counter: str):
     con = sqlite3.connect(db)
-    rows = con.execute(
-        "select kernel_name, avg(value), count(*), max(value) from counters_collection where counter_name = ? "
-        "group by kernel_name", (counter,)).fetchall()
-    return {r[0]: (float(r[1]), int(r[2]), float(r[3])) for r in rows}
+    return con.execute(
+        "select dispatch_id, kernel_name, value from counters_collection where counter_name = ? "
+        "order by dispatch_id", (counter,)).fetchall()
+
+
+def split(rows):
+    """(reference copy KiB, {workload: {kernel: [KiB per dispatch]}}): the
+    largest copy is the reference; dispatches after the marking copy belong to
+    the radiotherapy workload, the ones before it to CT."""
+    copies = [(d, v) for d, k, v in rows if "copyBuffer" in k]
+    ref = max(v for d, v in copies)
+    ref_id = max(copies, key=lambda c: c[1])[0]
+    # the marking copy moves COPY_BYTES / 8 (the solver's own small copies are
+    # far smaller)
+    later = [d for d, v in copies if d > ref_id and 0.5 * ref / 8 < v < 2.0 * ref / 8]
+    mark = min(later) if later else None
+    out = {CT_WORKLOAD: {}, RT_WORKLOAD: {}}
+    for d, k, v in rows:
+        if "k_pass" not in k and "k_fused" not in k:
+            continue
+        wl = RT_WORKLOAD if (mark is not None and d > mark) else CT_WORKLOAD
+        out[wl].setdefault(k.split("(")[0].replace("void ", ""), []).append(float(v))
+    return ref, out
 
 
 def summarise(fetch_db: str, write_db: str) -> dict:
-    f = per_kernel(fetch_db, "FETCH_SIZE")
-    w = per_kernel(write_db, "WRITE_SIZE")
-    # reference: the largest dispatch of the runtime's device-to-device copy kernel
-    cf = max(v[2] for k, v in f.items() if "copyBuffer" in k)
-    cw = max(v[2] for k, v in w.items() if "copyBuffer" in k)
+    cf, f = split(dispatches(fetch_db, "FETCH_SIZE"))
+    cw, w = split(dispatches(write_db, "WRITE_SIZE"))
     sf = COPY_BYTES / (cf * 1024.0)
     sw = COPY_BYTES / (cw * 1024.0)
-    out = {"workload": "ct256_parallel_beam_180x363_tv", "copy_bytes": COPY_BYTES, "copy_fetch_kib": cf,
-           "copy_write_kib": cw, "fetch_scale": sf, "write_scale": sw, "kernel_source_sha256": kernel_source_hash(),
-           "kernels": {}}
-    for name in sorted(set(f) | set(w)):
-        if "k_pass" not in name:
-            continue
-        key = name.split("(")[0].replace("void ", "")
-        fb = f[name][0] * 1024.0 * sf if name in f else None
-        wb = w[name][0] * 1024.0 * sw if name in w else None
-        out["kernels"][key] = {"fetch_bytes": fb, "write_bytes": wb,
-                               "traffic_bytes": (fb or 0.0) + (wb or 0.0)}
+    out = {"copy_bytes": COPY_BYTES, "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": sf,
+           "write_scale": sw, "kernel_source_sha256": kernel_source_hash(), "workloads": {}}
+    for wl in (CT_WORKLOAD, RT_WORKLOAD):
+        ks = {}
+        for name in sorted(set(f[wl]) | set(w[wl])):
+            fb = sum(f[wl][name]) / len(f[wl][name]) * 1024.0 * sf if name in f[wl] else None
+            wb = sum(w[wl][name]) / len(w[wl][name]) * 1024.0 * sw if name in w[wl] else None
+            ks[name] = {"fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": (fb or 0.0) + (wb or 0.0),
+                        "dispatches": len(f[wl].get(name, []))}
+        out["workloads"][wl] = {"kernels": ks}
     return out
 
 
