@@ -25,6 +25,7 @@ _SRC = os.path.join(_HERE, "orc.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 
 
 def build(force: bool = True) -> str:
@@ -61,6 +62,8 @@ class _Problem(C.Structure):
         ("alpha", C.c_double),
         ("n_red", C.c_int32),
         ("restart_every", C.c_int32),
+        ("basic", C.c_int32),
+        ("col_nnz", C.POINTER(C.c_double)),
     ]
 
 
@@ -161,6 +164,8 @@ class Problem:
         n_red=1,
         restart_every=0,
         max_trials=100,
+        basic=BASIC_SIMULT,
+        col_nnz=None,
     ):
         self.m, self.n = int(m), int(n)
         self.row_ptr = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
@@ -173,6 +178,7 @@ class Problem:
         w = np.full(self.m, 1.0 / max(self.m, 1)) if weights is None else _f64(weights)
         self.w = _f64(w / w.sum())
         self.linear_c = None if linear_c is None else _f64(linear_c)
+        self.col_nnz = None if col_nnz is None else _f64(col_nnz)
         self.s = _Problem(
             m=self.m,
             n=self.n,
@@ -195,6 +201,8 @@ class Problem:
             alpha=float(alpha),
             n_red=int(n_red),
             restart_every=int(restart_every),
+            basic=int(basic),
+            col_nnz=_dp(self.col_nnz),
         )
 
     # -- building blocks -------------------------------------------------
@@ -285,6 +293,8 @@ def from_workload(w, s: int = 0, value_round: Optional[str] = None) -> Problem:
     oracle's own rounding of them (the operator a reduced-precision store holds).
     """
     val = w.val.astype(np.float64)
+    # DROP counts the nonzeros of A as given, before any rounding of the values
+    col_nnz = np.bincount(np.asarray(w.col_idx)[w.val != 0], minlength=w.n).astype(np.float64)
     if value_round == "bf16":
         val = round_bf16(val)
     elif value_round == "f16":
@@ -313,4 +323,6 @@ def from_workload(w, s: int = 0, value_round: Optional[str] = None) -> Problem:
         n_red=w.n_red,
         restart_every=w.restart_every,
         max_trials=w.max_trials,
+        basic=getattr(w, "basic", BASIC_SIMULT),
+        col_nnz=col_nnz,
     )

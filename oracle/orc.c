@@ -13,7 +13,10 @@
  *     moves along a_i by (clip(r_i) - r_i)/||a_i||^2 with r_i = <a_i,x>;
  *   - the relaxed projection x + lambda (P(x) - x) (eq. RelaxedProjection),
  *     applied to the weighted simultaneous combination sum_i w_i P_i(x) with
- *     w_i > 0, sum w_i = 1 (the weights of eq. WeightedProximity);
+ *     w_i > 0, sum w_i = 1 (the weights of eq. WeightedProximity), and the
+ *     other simultaneous basic algorithms of the appendix's table of methods
+ *     (DROP, extrapolated Landweber, Landweber with error-minimising
+ *     relaxation) and the CQ iteration of Section 2.1.1;
  *   - the weighted proximity 1/2 sum_i w_i ||P_i(x) - x||^2 (eq. WeightedProximity);
  *   - a projection onto the box lo <= x <= hi after every step (Section 2.3.3,
  *     the BoxProjection applied after each iteration);
@@ -41,6 +44,13 @@
 #define ORC_OBJ_TV2D 2
 #define ORC_OBJ_LINEAR 3
 
+/* basic (feasibility-seeking) algorithms of the appendix's table of methods */
+#define ORC_BASIC_SIMULT 0 /* weighted simultaneous projection */
+#define ORC_BASIC_DROP 1   /* diagonally relaxed orthogonal projections */
+#define ORC_BASIC_CQ 2     /* CQ iteration with the Frobenius bound */
+#define ORC_BASIC_EL 3     /* extrapolated Landweber */
+#define ORC_BASIC_EMR 4    /* Landweber with error-minimising relaxation */
+
 typedef struct {
     int64_t m, n;
     const int64_t *row_ptr; /* m+1 */
@@ -59,6 +69,8 @@ typedef struct {
     const double *lin_c; /* n */
     double gamma, alpha;
     int32_t n_red, restart_every;
+    int32_t basic;          /* ORC_BASIC_*: the feasibility-seeking step */
+    const double *col_nnz;  /* n, nonzeros per column for DROP, or NULL to count them from val */
 } orc_problem;
 
 typedef struct {
@@ -132,34 +144,93 @@ double orc_proximity(const orc_problem *P, const double *x)
 }
 
 /*
- * One feasibility-seeking step T (in place):
- *   x <- P_box( x + lambda * sum_i w_i (P_i(x) - x) ).
- * Returns the proximity at the input point.  Scratch: r[m], c[m], y[n].
+ * One feasibility-seeking step T of the chosen basic algorithm (in place),
+ * then the box projection.  t_i = clip(r_i) - r_i is the band residual at the
+ * input point (for an equality band l_i = u_i = b_i it is b_i - <a_i,x>, the
+ * negative of the residual A x - b the table of methods writes).  With
+ * D = diag(w_i/||a_i||^2) and W = diag(w_i):
+ *   SIMULT  x + lambda A^T D t: the relaxed weighted sum of the single-band
+ *           projections, since P_i(x) - x = (t_i/||a_i||^2) a_i;
+ *   DROP    x + lambda Z A^T D t, Z_j = 1/(nonzeros in column j), 0 for an
+ *           empty column;
+ *   CQ      x + lambda A^T t / ||A||_F^2: the CQ iteration with Q the bands
+ *           and gamma = lambda / L*, L* the squared Frobenius norm bound
+ *           (Section 2.1.1); the box plays C;
+ *   EL      x + lambda sigma A^T D t, sigma = t^T D t / ||A^T D t||^2;
+ *   EMR     x + lambda sigma y, y = A^T W t, sigma = ||y||^2 / sum_i w_i (A y)_i^2;
+ * sigma = 0 when its denominator is 0 (then y = 0 too).  Returns the
+ * proximity at the input point.  Scratch: r[m], c[m], y[n]; zc[n] holds the
+ * DROP column factors (unused otherwise).
  */
-static double feas_step(const orc_problem *P, const double *q, double *x, double *r, double *c, double *y)
+static double feas_step(const orc_problem *P, const double *q, const double *zc, double *x, double *r, double *c,
+                        double *y)
 {
     orc_matvec(P, x, r);
     double prox = proximity_q(P, q, r);
+    double fro2 = 0.0;
+    if (P->basic == ORC_BASIC_CQ)
+        for (int64_t i = 0; i < P->m; ++i) fro2 += q[i];
     for (int64_t i = 0; i < P->m; ++i) {
         double t = clampd(r[i], P->lower[i], P->upper[i]) - r[i];
-        /* w_i (P_i(x) - x) = w_i * t / ||a_i||^2 * a_i */
-        c[i] = (q[i] > 0.0) ? P->w[i] * t / q[i] : 0.0;
+        r[i] = t; /* r now holds t */
+        switch (P->basic) {
+        case ORC_BASIC_CQ:
+            c[i] = fro2 > 0.0 ? t / fro2 : 0.0;
+            break;
+        case ORC_BASIC_EMR:
+            c[i] = P->w[i] * t;
+            break;
+        default: /* w_i (P_i(x) - x) = w_i * t / ||a_i||^2 * a_i */
+            c[i] = (q[i] > 0.0) ? P->w[i] * t / q[i] : 0.0;
+        }
     }
     orc_matvec_t(P, c, y);
-    for (int64_t j = 0; j < P->n; ++j) x[j] = clampd(x[j] + P->lambda * y[j], P->box_lo[j], P->box_hi[j]);
+    double sigma = 1.0;
+    if (P->basic == ORC_BASIC_EL) {
+        double num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < P->m; ++i) num += c[i] * r[i]; /* t^T D t */
+        for (int64_t j = 0; j < P->n; ++j) den += y[j] * y[j];
+        sigma = den > 0.0 ? num / den : 0.0;
+    } else if (P->basic == ORC_BASIC_EMR) {
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < P->n; ++j) num += y[j] * y[j];
+        orc_matvec(P, y, r); /* r = A y */
+        for (int64_t i = 0; i < P->m; ++i) den += P->w[i] * r[i] * r[i];
+        sigma = den > 0.0 ? num / den : 0.0;
+    }
+    for (int64_t j = 0; j < P->n; ++j) {
+        const double yj = (P->basic == ORC_BASIC_DROP) ? zc[j] * y[j] : y[j];
+        x[j] = clampd(x[j] + P->lambda * sigma * yj, P->box_lo[j], P->box_hi[j]);
+    }
     return prox;
+}
+
+/* DROP column factors Z_j = 1/(nonzeros in column j), 0 for an empty column. */
+static void drop_factors(const orc_problem *P, double *zc)
+{
+    for (int64_t j = 0; j < P->n; ++j) zc[j] = 0.0;
+    if (P->col_nnz) {
+        for (int64_t j = 0; j < P->n; ++j) zc[j] = P->col_nnz[j];
+    } else {
+        for (int64_t p = 0; p < P->row_ptr[P->m]; ++p)
+            if (P->val[p] != 0.0) zc[P->col[p]] += 1.0;
+    }
+    for (int64_t j = 0; j < P->n; ++j) zc[j] = zc[j] > 0.0 ? 1.0 / zc[j] : 0.0;
 }
 
 double orc_step(const orc_problem *P, double *x)
 {
     double *q = malloc(sizeof(double) * P->m), *r = malloc(sizeof(double) * P->m),
-           *c = malloc(sizeof(double) * P->m), *y = malloc(sizeof(double) * P->n);
+           *c = malloc(sizeof(double) * P->m), *y = malloc(sizeof(double) * P->n),
+           *zc = malloc(sizeof(double) * P->n);
     orc_row_sqnorms(P, q);
-    double v = feas_step(P, q, x, r, c, y);
+    drop_factors(P, zc);
+    double v = feas_step(P, q, zc, x, r, c, y);
     free(q);
     free(r);
     free(c);
     free(y);
+    free(zc);
     return v;
 }
 
@@ -264,12 +335,13 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
     const int64_t m = P->m, n = P->n;
     double *q = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m), *c = malloc(sizeof(double) * m),
            *y = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n), *v = malloc(sizeof(double) * n),
-           *z = malloc(sizeof(double) * n);
-    if (!q || !r || !c || !y || !g || !v || !z) {
-        free(q); free(r); free(c); free(y); free(g); free(v); free(z);
+           *z = malloc(sizeof(double) * n), *zc = malloc(sizeof(double) * n);
+    if (!q || !r || !c || !y || !g || !v || !z || !zc) {
+        free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc);
         return -2;
     }
     orc_row_sqnorms(P, q);
+    drop_factors(P, zc);
     for (int64_t it = 0; it < K; ++it) {
         const int64_t k = st->k;
         int32_t trials = 0, accepts = 0;
@@ -313,7 +385,7 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
                 f_end = f_cur;
             }
         }
-        double prox = feas_step(P, q, x, r, c, y);
+        double prox = feas_step(P, q, zc, x, r, c, y);
         if (hist_prox) hist_prox[it] = prox;
         if (hist_f_start) hist_f_start[it] = f_start;
         if (hist_f_end) hist_f_end[it] = f_end;
@@ -323,7 +395,7 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
         st->accepts += accepts;
         st->k += 1;
     }
-    free(q); free(r); free(c); free(y); free(g); free(v); free(z);
+    free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc);
     return 0;
 }
 

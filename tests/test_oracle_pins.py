@@ -450,3 +450,130 @@ def test_f16_scaled_rounding_matches_numpy(orc):
     assert s == 2.0 ** (14 - e)
     ref = (v * s).astype(np.float16).astype(np.float64) / s
     assert np.array_equal(out, ref)
+
+
+# ---------------------------------------------------------------------------
+# Other basic algorithms (appendix table of methods; CQ of Section 2.1.1)
+# ---------------------------------------------------------------------------
+
+BASIC = {"simult": W.BASIC_SIMULT, "drop": W.BASIC_DROP, "cq": W.BASIC_CQ, "el": W.BASIC_EL, "emr": W.BASIC_EMR}
+
+
+def test_golden_basic_operators(orc):
+    """Hand-derived single steps of each basic algorithm (golden file)."""
+    from fractions import Fraction
+
+    n_cases = 0
+    for line in open(os.path.join(GOLDEN, "basic_operators.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        name, method, rows, b, lam, tx = [f.strip() for f in line.split(";")]
+        A = np.array([[float(v) for v in r.split()] for r in rows.split("|")])
+        b = np.array(b.split(), float)
+        P = _dense_problem(orc, A, b, b, lam=float(lam), basic=BASIC[method])
+        Tx, _ = P.step(np.zeros(A.shape[1]))
+        want = np.array([float(Fraction(v)) for v in tx.split()])
+        np.testing.assert_allclose(Tx, want, rtol=1e-14, atol=1e-15, err_msg=name)
+        n_cases += 1
+    assert n_cases == 10
+
+
+@pytest.mark.parametrize("method", ["drop", "cq", "el", "emr"])
+def test_basic_single_band_is_projection(orc, method):
+    """With one band every basic algorithm at lambda = 1 is the Euclidean
+    projection onto it (Section 2.1.1 formula); DROP's column factors are 1
+    on the row's support and zero columns stay put."""
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        a = rng.normal(size=6)
+        a[rng.random(6) < 0.3] = 0.0
+        if not np.any(a):
+            continue
+        x = rng.normal(size=6) * 3
+        r = a @ x
+        lo, up = sorted(rng.normal(size=2))
+        t = min(max(r, lo), up) - r
+        want = x + (t / (a @ a)) * a
+        P = _single_row(orc, a, lo, up, basic=BASIC[method])
+        Tx, _ = P.step(x)
+        np.testing.assert_allclose(Tx, want, rtol=1e-12, atol=1e-12)
+
+
+def test_emr_residual_orthogonal_to_search_image(orc):
+    """EMR's step length minimises the W-weighted residual along y (equality
+    bands, no box): the new residual b - A x' is W-orthogonal to A y."""
+    rng = np.random.default_rng(8)
+    A = rng.normal(size=(9, 5))
+    b = rng.normal(size=9)
+    w = rng.random(9) + 0.5
+    w = w / w.sum()
+    x = rng.normal(size=5)
+    P = _dense_problem(orc, A, b, b, weights=w, basic=W.BASIC_EMR)
+    Tx, _ = P.step(x)
+    y = A.T @ (w * (b - A @ x))
+    r_new = b - A @ Tx
+    assert abs((A @ y) @ (w * r_new)) <= 1e-12 * np.linalg.norm(A @ y) * np.linalg.norm(b - A @ x)
+
+
+def test_el_extrapolation_at_least_one(orc):
+    """EL's extrapolation sigma = t^T D t / ||A^T D t||^2 is >= 1 when the
+    weights sum to 1 (Cauchy-Schwarz / convexity of the squared norm), so its
+    step is never shorter than the simultaneous projection's."""
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        A = rng.normal(size=(12, 6))
+        b = rng.normal(size=12)
+        x = rng.normal(size=6)
+        Ps = _dense_problem(orc, A, b, b, basic=W.BASIC_SIMULT)
+        Pe = _dense_problem(orc, A, b, b, basic=W.BASIC_EL)
+        ds = Ps.step(x)[0] - x
+        de = Pe.step(x)[0] - x
+        ratio = (de @ ds) / (ds @ ds)
+        assert ratio >= 1 - 1e-12
+        np.testing.assert_allclose(de, ratio * ds, rtol=1e-10, atol=1e-12)
+
+
+def _consistent_dense(orc, method, lam):
+    rng = np.random.default_rng(40)
+    A = rng.normal(size=(40, 15))
+    A[rng.random((40, 15)) < 0.5] = 0.0
+    xs = rng.uniform(0, 1, 15)
+    r = A @ xs
+    P = _dense_problem(orc, A, r - 0.1, r + 0.1, basic=BASIC[method], lam=lam, box_lo=np.full(15, -1.0),
+                       box_hi=np.full(15, 2.0))
+    return P, xs
+
+
+@pytest.mark.parametrize("method,lam", [("simult", 1.0), ("drop", 40.0), ("cq", 1.0), ("el", 1.0)])
+def test_basic_fejer_monotone(orc, method, lam):
+    """SIMULT, DROP (lambda = 1/max w, inside its range), CQ and EL are
+    Fejer-monotone on a consistent system: the distance to any point of the
+    bands and the box never grows."""
+    P, xs = _consistent_dense(orc, method, lam)
+    x = np.full(15, 1.8)
+    d = [np.linalg.norm(x - xs)]
+    for _ in range(40):
+        x, _ = P.step(x)
+        d.append(np.linalg.norm(x - xs))
+    assert np.all(np.diff(d) <= 1e-12)
+    assert d[-1] < 0.5 * d[0]
+
+
+def test_emr_reduces_proximity(orc):
+    P, _ = _consistent_dense(orc, "emr", 1.0)
+    x = np.full(15, 1.8)
+    p0 = P.proximity(x)
+    for _ in range(40):
+        x, _ = P.step(x)
+    assert P.proximity(x) < 1e-6 * p0
+
+
+def test_drop_counts_nonzeros_before_rounding(orc):
+    """DROP's column factors count the nonzeros of A as given: an explicit
+    column count overrides counting the (possibly rounded) values."""
+    A = np.array([[1.0, 1.0, 0.0], [2.0, 0.0, 1.0]])
+    b = np.array([2.0, 4.0])
+    P = _dense_problem(orc, A, b, b, basic=W.BASIC_DROP, col_nnz=np.array([1.0, 1.0, 1.0]))
+    Tx, _ = P.step(np.zeros(3))
+    np.testing.assert_allclose(Tx, [1.3, 0.5, 0.4], rtol=1e-14)

@@ -21,6 +21,7 @@ from typing import Optional
 import numpy as np
 
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 OBJ_NAMES = {OBJ_NONE: "none", OBJ_SQNORM: "sqnorm", OBJ_TV2D: "tv2d", OBJ_LINEAR: "linear"}
 
 
@@ -58,6 +59,7 @@ class Workload:
     max_trials: int = 100
     K: int = 100
     weights: Optional[np.ndarray] = None  # float64 [m]; None means uniform 1/m
+    basic: int = 0  # BASIC_*: the feasibility-seeking step
     x_true: Optional[np.ndarray] = None  # float32 [n, B]
     meta: dict = field(default_factory=dict)
 
