@@ -65,6 +65,21 @@ extern "C" {
 #define SMX_OBJ_TV2D 2   /* smoothed total variation of an R x C image (Section 2.3.1) */
 #define SMX_OBJ_LINEAR 3 /* f = c^T x, e.g. summed dose (Section 2.3.3) */
 
+/* basic (feasibility-seeking) algorithms: the step T applied after the
+ * perturbation (the appendix's table of methods; CQ from Section 2.1.1).  With
+ * t_i = clip(<a_i,z>, l_i, u_i) - <a_i,z>, D = diag(w_i/||a_i||^2), W = diag(w_i):
+ *   SIMULT  x = P_box(z + lambda A^T D t)              weighted simultaneous projection
+ *   DROP    x = P_box(z + lambda Z A^T D t)            Z_j = 1/(nonzeros in column j)
+ *   CQ      x = P_box(z + lambda A^T t / ||A||_F^2)    CQ with the Frobenius bound, C = the box
+ *   EL      x = P_box(z + lambda sigma A^T D t)        sigma = t^T D t / ||A^T D t||^2
+ *   EMR     x = P_box(z + lambda sigma y), y = A^T W t, sigma = ||y||^2 / sum_i w_i (A y)_i^2
+ * (sigma = 0 when its denominator is 0).  The proximity is the same for all. */
+#define SMX_BASIC_SIMULT 0
+#define SMX_BASIC_DROP 1
+#define SMX_BASIC_CQ 2
+#define SMX_BASIC_EL 3
+#define SMX_BASIC_EMR 4
+
 /* smx_run flags */
 #define SMX_RUN_PERTURB 1u /* run the perturbation phase of Algorithm 1 */
 #define SMX_RUN_GRAPH 2u   /* replay captured HIP graphs of several iterations */
@@ -91,7 +106,9 @@ typedef struct {
     const double *weights;   /* m, > 0 (normalised to sum 1 here), or NULL for 1/m */
     const float *box_lo;     /* n, or NULL for -INFINITY */
     const float *box_hi;     /* n, or NULL for +INFINITY; box_lo <= box_hi */
-    double lambda;           /* relaxation parameter, 0 < lambda <= 2 */
+    double lambda;           /* relaxation parameter, 0 < lambda <= 2 (DROP:
+                                0 < lambda <= 2 / max_i w_i with the weights
+                                normalised to sum 1) */
     int32_t obj_kind;        /* SMX_OBJ_* */
     int32_t tv_rows, tv_cols; /* SMX_OBJ_TV2D: image shape, rows*cols = n,
                                 pixel (i,j) is unknown i*tv_cols + j */
@@ -107,6 +124,7 @@ typedef struct {
                                 -1 means ceil(K/20) */
     int32_t history_cap;     /* per-iteration records kept (0: none) */
     int32_t on_device;       /* 0: the arrays above are host pointers, 1: device */
+    int32_t basic;           /* SMX_BASIC_*; SMX_BASIC_SIMULT (0) is the default */
 } smx_problem_desc;
 
 /* Per-slice iteration state, as checkpointed by smx_get_state. */
@@ -159,8 +177,10 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
  * arrays; sets x to 0 for every slice and the iteration state to k = ell =
  * restarts = 0.  Errors (SMX_EINVAL): B not a power of two in 1..32, any
  * lower > upper or NaN bound, a weight <= 0 or non-finite, box_lo > box_hi,
- * lambda outside (0,2], gamma <= 0, alpha outside (0,1), n_red < 1,
- * max_trials outside 1..1024, TV with rows*cols != n, LINEAR with a NULL c.
+ * lambda outside its range, an unknown basic algorithm, gamma <= 0, alpha
+ * outside (0,1), n_red < 1, max_trials outside 1..1024, TV with rows*cols !=
+ * n, LINEAR with a NULL c.  EL and EMR keep y (n*B floats) and run the two
+ * passes (never the fused pass); EMR adds a third pass over A per iteration.
  */
 int smx_problem_create(smx_operator *op, const smx_problem_desc *desc, void *stream, smx_problem **out);
 

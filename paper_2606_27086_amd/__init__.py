@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsmx.so")
 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 RUN_PERTURB, RUN_GRAPH = 1, 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
@@ -97,6 +98,7 @@ class ProblemDesc(C.Structure):
         ("refine_iters", C.c_int32),
         ("history_cap", C.c_int32),
         ("on_device", C.c_int32),
+        ("basic", C.c_int32),
     ]
 
 
@@ -238,7 +240,7 @@ class Problem:
     def __init__(self, op: Operator, lower, upper, box_lo=None, box_hi=None, weights=None, lam=1.0,
                  obj=OBJ_NONE, tv_rows=0, tv_cols=0, tv_eps=0.0, linear_c=None, gamma=1.0, alpha=0.99,
                  n_red=1, restart_every=0, max_trials=100, refine_iters=-1, history_cap=0, B=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, basic=0):
         import torch
 
         self.op = op
@@ -259,7 +261,7 @@ class Problem:
             box_hi=_ptr(t_bhi), lam=float(lam), obj_kind=int(obj), tv_rows=int(tv_rows), tv_cols=int(tv_cols),
             tv_eps=float(tv_eps), linear_c=_ptr(t_c), gamma=float(gamma), alpha=float(alpha), n_red=int(n_red),
             restart_every=int(restart_every), max_trials=int(max_trials), refine_iters=int(refine_iters),
-            history_cap=int(history_cap), on_device=1,
+            history_cap=int(history_cap), on_device=1, basic=int(basic),
         )
         self.history_cap = int(history_cap)
         self.obj = int(obj)
@@ -427,7 +429,7 @@ def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device=
         lower=w.lower, upper=w.upper, box_lo=w.box_lo, box_hi=w.box_hi, weights=w.weights, lam=w.lam, obj=w.obj,
         tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
         n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
-        refine_iters=refine_iters, B=w.B,
+        refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0),
     )
     kw.update(overrides)
     p = Problem(op, device=device, **kw)

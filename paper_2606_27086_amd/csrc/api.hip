@@ -196,6 +196,7 @@ struct smx_operator {
     bool has_f32 = true;
     DevLayout csr, csc;
     DBuf q32, q16; // float64 row norms of the float32 and the reduced-precision operator
+    DBuf zcol;     // DROP column factors 1/(nonzeros in column j), 0 for an empty column [n]
     std::atomic<int> refs{1};
     size_t bytes = 0;
     int lp_kind() const { return storage == SMX_STORE_BF16 ? VK_BF16 : (storage == SMX_STORE_F16 ? VK_F16 : VK_F32); }
@@ -225,6 +226,25 @@ struct smx_problem {
     int fused_mode = 1; // 0: always the two passes
     FusedCfg fcfg[3]{};
     DBuf ypart; // grid x n partial vectors of y = A^T c
+    // basic algorithm (SMX_BASIC_*) and what its step needs beyond D
+    int basic = SMX_BASIC_SIMULT;
+    DBuf S32, S16; // step weights when they differ from D (CQ: 1/||A||_F^2, EMR: w)
+    DBuf ybuf;     // EL / EMR: y = A^T c kept for the extrapolated step, float64 [n*B]
+    DBuf ybuf32;   // EMR: y rounded to float32, the vector its second product gathers [n*B]
+    DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
+    RowW row_weights(int vk) const
+    {
+        const float *D = (vk == VK_F32) ? D32.as<float>() : D16.as<float>();
+        const float *S = (vk == VK_F32) ? S32.as<float>() : S16.as<float>();
+        return RowW{D, S ? S : D, 0};
+    }
+    ColStep col_step(bool defer) const
+    {
+        return ColStep{box_lo.as<float>(), box_hi.as<float>(), lambda,
+                       basic == SMX_BASIC_DROP ? op->zcol.as<float>() : nullptr,
+                       defer ? ybuf.as<double>() : nullptr, defer ? ybuf32.as<float>() : nullptr,
+                       defer ? part_y.as<double>() : nullptr, defer ? 1 : 0};
+    }
     // captured graphs keyed by (value kind, perturb, iterations)
     std::map<long long, hipGraphExec_t> graphs;
     hipStream_t capture_stream = nullptr; // private stream graphs are captured on
@@ -385,6 +405,15 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
     std::vector<int32_t> ri(nnz);
     std::vector<float> cv(nnz);
     {
+        // DROP column factors count the nonzero values as given (before any rounding)
+        std::vector<float> zc(n, 0.f);
+        std::vector<int64_t> cnt(n, 0);
+        for (int64_t p = 0; p < nnz; ++p)
+            if (va[p] != 0.f) cnt[ci[p]]++;
+        for (int64_t j = 0; j < n; ++j) zc[j] = cnt[j] > 0 ? (float)(1.0 / (double)cnt[j]) : 0.f;
+        upload(op->zcol, zc, s, "column factors");
+    }
+    {
         std::vector<int64_t> pos(cp.begin(), cp.end() - 1);
         for (int64_t i = 0; i < m; ++i)
             for (int64_t p = rp64[i]; p < rp64[i + 1]; ++p) {
@@ -420,7 +449,7 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
     hip_check(hipStreamSynchronize(s), "operator setup");
     op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32, op->csr.packed.p != nullptr) +
                 layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32, op->csc.packed.p != nullptr) +
-                size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0));
+                size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0)) + size_t(n) * 4;
     *out = op.release();
     return SMX_OK;
 }
@@ -460,7 +489,8 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
             prev = out;
         }
     }
-    const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
+    const RowW rw = p->row_weights(vk);
+    const ColStep cstep = p->col_step(false);
     hipEvent_t e[4] = {};
     if (timed) {
         while (p->ev_pool.size() < p->ev_used + 4) {
@@ -474,23 +504,22 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
     }
     if (p->fused[vk]) {
         hip_check(launch_fused(p->fcfg[vk], view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], p->n, p->x.as<float>(),
-                               p->lower.as<float>(), p->upper.as<float>(), D, p->state(cur),
+                               p->lower.as<float>(), p->upper.as<float>(), rw, p->state(cur),
                                p->part_pass.as<double>(), p->ypart.p, s),
                   "fused pass");
         if (timed) {
             hip_check(hipEventRecord(e[1], s), "event");
             hip_check(hipEventRecord(e[2], s), "event");
         }
-        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, p->x.as<float>(), p->box_lo.as<float>(),
-                                     p->box_hi.as<float>(), p->lambda, p->state(cur), p->state(cur ^ 1),
-                                     p->part_pass.as<double>(), p->hist, s),
+        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, p->x.as<float>(), cstep, p->state(cur),
+                                     p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s),
                   "fused apply");
         cur ^= 1;
         if (timed) hip_check(hipEventRecord(e[3], s), "event");
         return cur;
     }
     hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
-                           p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(),
+                           p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), rw, p->c.as<float>(),
                            p->state(cur), p->B, 0,
                            p->part_pass.as<double>(), s),
               "pass 1");
@@ -498,13 +527,28 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
         hip_check(hipEventRecord(e[1], s), "event");
         hip_check(hipEventRecord(e[2], s), "event");
     }
+    const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
     hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
-                           p->c.as<float>(), p->x.as<float>(),
-                           p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, p->state(cur), p->state(cur ^ 1),
+                           p->c.as<float>(), p->x.as<float>(), p->col_step(extrap), p->state(cur), p->state(cur ^ 1),
                            p->B, p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
               "pass 2");
-    cur ^= 1;
     if (timed) hip_check(hipEventRecord(e[3], s), "event");
+    if (extrap) {
+        const bool emr = p->basic == SMX_BASIC_EMR;
+        if (emr) // the quadratic form sum_i w_i (A y)_i^2: pass 1's kernels gathering y
+            hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(),
+                                   p->fmt1[vk], p->ybuf32.as<float>(), p->lower.as<float>(), p->upper.as<float>(),
+                                   RowW{rw.D, rw.S, 1}, p->c.as<float>(), p->state(cur), p->B, 0,
+                                   p->part_q.as<double>(), s),
+                      "quadratic form");
+        hip_check(launch_step_apply(p->n, p->B, p->ybuf.as<double>(), p->x.as<float>(), p->box_lo.as<float>(),
+                                    p->box_hi.as<float>(), p->lambda, emr ? 1 : 0, p->part_pass.as<double>(),
+                                    p->cfg1[vk].grid, p->part_y.as<double>(), p->cfg2[vk].grid,
+                                    p->part_q.as<double>(), p->cfg1[vk].grid, p->state(cur), p->state(cur ^ 1),
+                                    p->hist, s),
+                  "extrapolated step");
+    }
+    cur ^= 1;
     return cur;
 }
 
@@ -628,7 +672,8 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
 // workgroups per CU, as many as the LDS allows.
 void setup_fused(smx_problem *p)
 {
-    if (p->B != 1) return;
+    // the extrapolated steps need ||y|| (and EMR A y) before x moves: two passes
+    if (p->B != 1 || p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR) return;
     const size_t lim = fused_lds_limit();
     int acc64 = -1;
     if (fused_lds_bytes(p->n, 1) <= lim) acc64 = 1;
@@ -671,7 +716,10 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     const int64_t m = op->m, n = op->n;
     const int B = d->B;
     if (!(is_pow2(B) && B <= 32)) return fail(SMX_EINVAL, "B must be a power of two in 1..32 (got %d)", B);
-    if (!(d->lambda > 0.0 && d->lambda <= 2.0)) return fail(SMX_EINVAL, "lambda must be in (0, 2] (got %g)", d->lambda);
+    if (d->basic < SMX_BASIC_SIMULT || d->basic > SMX_BASIC_EMR) return fail(SMX_EINVAL, "unknown basic algorithm %d", d->basic);
+    // DROP's range depends on the weights and is checked once they are normalised
+    if (!(d->lambda > 0.0) || (d->basic != SMX_BASIC_DROP && !(d->lambda <= 2.0)))
+        return fail(SMX_EINVAL, "lambda must be in (0, 2] (got %g)", d->lambda);
     if (d->obj_kind < SMX_OBJ_NONE || d->obj_kind > SMX_OBJ_LINEAR) return fail(SMX_EINVAL, "unknown objective %d", d->obj_kind);
     if (d->obj_kind != SMX_OBJ_NONE) {
         if (!(d->gamma > 0.0) || !std::isfinite(d->gamma)) return fail(SMX_EINVAL, "gamma must be > 0 (got %g)", d->gamma);
@@ -703,6 +751,12 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     double wsum = 0.0;
     for (double v : w) wsum += v;
     for (double &v : w) v /= wsum;
+    if (d->basic == SMX_BASIC_DROP) {
+        double wmax = 0.0;
+        for (double v : w) wmax = std::max(wmax, v);
+        if (!(d->lambda <= 2.0 / wmax))
+            return fail(SMX_EINVAL, "DROP needs lambda in (0, 2/max w] = (0, %g] (got %g)", 2.0 / wmax, d->lambda);
+    }
     std::vector<float> blo(n, -INFINITY), bhi(n, INFINITY);
     if (d->box_lo) blo = fetch(d->box_lo, n, dev);
     if (d->box_hi) bhi = fetch(d->box_hi, n, dev);
@@ -725,6 +779,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     p->n = n;
     p->lambda = (float)d->lambda;
     p->refine_iters = d->refine_iters;
+    p->basic = d->basic;
     PertParams &pp = p->pp;
     pp.obj = d->obj_kind;
     pp.B = B;
@@ -760,6 +815,34 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     if (lp != VK_F32) {
         p->D16.alloc(sizeof(float) * m, "D (reduced precision)");
         hip_check(launch_make_D(op->q16.as<double>(), p->w.as<double>(), p->D16.as<float>(), m, s), "D");
+    }
+    if (p->basic == SMX_BASIC_CQ || p->basic == SMX_BASIC_EMR) {
+        // step weights: CQ 1/||A||_F^2 (the squared Frobenius norm of the stored
+        // operator, the sum of its float64 row norms in row order), EMR the weights
+        std::vector<int> kinds;
+        if (op->has_f32) kinds.push_back(VK_F32);
+        if (op->lp_kind() != VK_F32) kinds.push_back(op->lp_kind());
+        for (int vk : kinds) {
+            std::vector<float> sw(m);
+            if (p->basic == SMX_BASIC_EMR) {
+                for (int64_t i = 0; i < m; ++i) sw[i] = (float)w[i];
+            } else {
+                std::vector<double> q(m);
+                const DBuf &qd = (vk == VK_F32) ? op->q32 : op->q16;
+                hip_check(hipMemcpy(q.data(), qd.p, sizeof(double) * m, hipMemcpyDeviceToHost), "row norms");
+                double fro2 = 0.0;
+                for (double v : q) fro2 += v;
+                const float f = fro2 > 0.0 ? (float)(1.0 / fro2) : 0.f;
+                for (int64_t i = 0; i < m; ++i) sw[i] = f;
+            }
+            upload(vk == VK_F32 ? p->S32 : p->S16, sw, s, "step weights");
+        }
+    }
+    if (p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR) {
+        p->ybuf.alloc(sizeof(double) * n * B, "extrapolated step");
+        if (p->basic == SMX_BASIC_EMR) p->ybuf32.alloc(sizeof(float) * n * B, "extrapolated step");
+        p->part_y.alloc(sizeof(double) * size_t(kMaxPassGrid) * B, "step partials");
+        p->part_q.alloc(sizeof(double) * size_t(kMaxPassGrid) * B, "step partials");
     }
     if (const int lk = op->lp_kind(); lk != VK_F32) { // the packed entries where the index range allows
         const int pk = (lk == VK_BF16) ? VK_BF16P : VK_F16P;
@@ -868,7 +951,8 @@ int autotune_impl(smx_problem *p, int reps)
     if (p->op->lp_kind() != VK_F32) kinds.push_back(p->op->lp_kind());
     try {
         for (int vk : kinds) {
-            const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
+            const RowW rw = p->row_weights(vk);
+            const ColStep cstep = p->col_step(false);
             // pass 1
             double best = 1e30;
             PassCfg bestc = p->cfg1[vk];
@@ -876,7 +960,7 @@ int autotune_impl(smx_problem *p, int reps)
                 auto launch = [&]() {
                     hip_check(launch_pass1(c, view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
                                            xs.as<float>(),
-                                           p->lower.as<float>(), p->upper.as<float>(), D, cs.as<float>(), st0, p->B, 1,
+                                           p->lower.as<float>(), p->upper.as<float>(), rw, cs.as<float>(), st0, p->B, 1,
                                            p->part_query.as<double>(), s),
                               "tuning pass 1");
                 };
@@ -899,9 +983,8 @@ int autotune_impl(smx_problem *p, int reps)
             for (const PassCfg &c : pass_candidates(p->op->csc, vk, p->B)) {
                 auto launch = [&]() {
                     hip_check(launch_pass2(c, view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
-                                           cs.as<float>(),
-                                           xs.as<float>(), p->box_lo.as<float>(), p->box_hi.as<float>(), p->lambda, st0,
-                                           st1, p->B, p->part_query.as<double>(), bestc.grid, none, s),
+                                           cs.as<float>(), xs.as<float>(), cstep, st0, st1, p->B,
+                                           p->part_query.as<double>(), bestc.grid, none, s),
                               "tuning pass 2");
                 };
                 launch();
@@ -923,11 +1006,10 @@ int autotune_impl(smx_problem *p, int reps)
                 for (const FusedCfg &c : fused_candidates(p->fcfg[vk])) {
                     auto launch = [&]() {
                         hip_check(launch_fused(c, view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], n, xs.as<float>(),
-                                               p->lower.as<float>(), p->upper.as<float>(), D, st0,
+                                               p->lower.as<float>(), p->upper.as<float>(), rw, st0,
                                                p->part_query.as<double>(), p->ypart.p, s),
                                   "tuning fused pass");
-                        hip_check(launch_fused_apply(c, n, p->ypart.p, xs.as<float>(), p->box_lo.as<float>(),
-                                                     p->box_hi.as<float>(), p->lambda, st0, st1,
+                        hip_check(launch_fused_apply(c, n, p->ypart.p, xs.as<float>(), cstep, st0, st1,
                                                      p->part_query.as<double>(), none, s),
                                   "tuning fused apply");
                     };
@@ -1001,8 +1083,9 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         first = false;
     }
     char tail[160];
-    snprintf(tail, sizeof tail, ", \"tuned\": %s, \"row_blocks\": [%d, %d]}", p->tuned ? "true" : "false",
-             p->op->csr.nblk, p->op->csc.nblk);
+    static const char *basics[5] = {"simult", "drop", "cq", "el", "emr"};
+    snprintf(tail, sizeof tail, ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\"}",
+             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic]);
     out += tail;
     if (need) *need = out.size() + 1;
     if (buf && cap > 0) {
@@ -1059,7 +1142,7 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
     // upper bound on padding: kRowAlign-1 entries per row and per column
     const int64_t s1 = nnz + (kRowAlign - 1) * m, s2 = nnz + (kRowAlign - 1) * n;
     *bytes = layout_bytes(m, s1, f32, lp, lp && n <= 65536) + layout_bytes(n, s2, f32, lp, lp && m <= 65536) +
-             size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0));
+             size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0)) + size_t(n) * 4;
     return SMX_OK;
 }
 
@@ -1163,7 +1246,8 @@ int smx_query(smx_problem *p, double *proximity, double *objective)
         const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
         double *q = p->qout.as<double>();
         hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
-                               p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), D, p->c.as<float>(),
+                               p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), RowW{D, D, 0},
+                               p->c.as<float>(),
                                p->state(p->cur), B, 1,
                                p->part_query.as<double>(), p->stream),
                   "query proximity");

@@ -295,14 +295,27 @@ __device__ inline double group_sum(double v)
 }
 
 // ---------------------------------------------------------------------------
-// pass 1: r = A z, t = clip(r, lower, upper) - r, c = D t, and one partial of
-// the proximity 1/2 sum D t^2 per workgroup
+// pass 1: r = A z, t = clip(r, lower, upper) - r, c = S t, and one partial of
+// the proximity 1/2 sum D t^2 per workgroup (or, in quadratic-form mode, of
+// sum S r^2)
 // ---------------------------------------------------------------------------
+
+// Pass-1 epilogue of one row from r = <a_i, v>: returns the row's partial term
+// and stores c_i (not in quadratic-form mode).  With S = D this is exactly
+// c_i = D_i t_i and the term D_i t_i^2.
+__device__ inline double epi1(const RowW &w, double r, float lo, float up, float d, float sw, float *c)
+{
+    if (w.qform) return (double)sw * r * r;
+    const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+    const double dt = (double)d * t;
+    *c = (float)((double)sw * t);
+    return dt * t;
+}
 
 template <int LPR, int VEC, typename VT>
 __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restrict__ x,
                                                   const float *__restrict__ lower, const float *__restrict__ upper,
-                                                  const float *__restrict__ D, float *__restrict__ c,
+                                                  RowW w, float *__restrict__ c,
                                                   const SliceState *__restrict__ st, int query,
                                                   double *__restrict__ partials)
 {
@@ -316,19 +329,15 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
         const long long stride = (long long)gridDim.x * RPB;
         for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
             const int beg = A.ptr[row], end = A.ptr[row + 1];
-            float lo = 0.f, up = 0.f, d = 0.f;
+            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
             if (lane == 0) { // epilogue operands, fetched while the row streams
                 lo = lower[row];
                 up = upper[row];
-                d = D[row];
+                d = w.D[row];
+                sw = w.S[row];
             }
             const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
-            if (lane == 0) {
-                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-                const double dt = (double)d * t;
-                c[row] = (float)dt;
-                pacc[0] += dt * t;
-            }
+            if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row);
         }
     }
     block_sum<1>(pacc, lds);
@@ -412,7 +421,7 @@ template <int VEC, typename VT>
 __global__ __launch_bounds__(kBlock) void k_pass1_stream(SpView A, RowBlocks RB, const float *__restrict__ x,
                                                          const float *__restrict__ lower,
                                                          const float *__restrict__ upper,
-                                                         const float *__restrict__ D, float *__restrict__ c,
+                                                         RowW w, float *__restrict__ c,
                                                          const SliceState *__restrict__ st, int query,
                                                          double *__restrict__ partials)
 {
@@ -427,23 +436,19 @@ __global__ __launch_bounds__(kBlock) void k_pass1_stream(SpView A, RowBlocks RB,
             const int e0 = A.ptr[r0], e1 = A.ptr[r1];
             if (e1 - e0 > kStreamEntries) {
                 const double sum = long_row_sum<VEC, VT>(A, e0, e1, x, lds);
-                if (threadIdx.x == 0) {
-                    const double r = sum * (double)A.vscale_inv;
-                    const double t = fmin(fmax(r, (double)lower[r0]), (double)upper[r0]) - r;
-                    const double dt = (double)D[r0] * t;
-                    c[r0] = (float)dt;
-                    pacc[0] += dt * t;
-                }
+                if (threadIdx.x == 0)
+                    pacc[0] += epi1(w, sum * (double)A.vscale_inv, lower[r0], upper[r0], w.D[r0], w.S[r0], c + r0);
                 continue;
             }
             const int nr = r1 - r0;
             const RowSplit rs = split_rows(nr);
             const bool owner = rs.rl < nr && rs.lane == 0;
-            float lo = 0.f, up = 0.f, d = 0.f;
+            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
             if (owner) { // epilogue operands, fetched while the products stream
                 lo = lower[r0 + rs.rl];
                 up = upper[r0 + rs.rl];
-                d = D[r0 + rs.rl];
+                d = w.D[r0 + rs.rl];
+                sw = w.S[r0 + rs.rl];
             }
             for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = (A.ptr[r0 + i] - e0) / VEC;
             stream_chunks<VEC, VT>(A, e0, e1, x, prod);
@@ -452,13 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_stream(SpView A, RowBlocks RB,
             if (rs.rl < nr)
                 for (int q = rp[rs.rl] + rs.lane; q < rp[rs.rl + 1]; q += rs.G) s += prod[q];
             s = group_sum_rt(s, rs.G);
-            if (owner) {
-                const double r = s * (double)A.vscale_inv;
-                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-                const double dt = (double)d * t;
-                c[r0 + rs.rl] = (float)dt;
-                pacc[0] += dt * t;
-            }
+            if (owner) pacc[0] += epi1(w, s * (double)A.vscale_inv, lo, up, d, sw, c + r0 + rs.rl);
             __syncthreads();
         }
     }
@@ -512,19 +511,52 @@ __device__ inline void finish_iteration(const SliceState *__restrict__ st_in, Sl
 }
 
 // ---------------------------------------------------------------------------
-// pass 2: y = A^T c, x = clip(z + lambda y, lo, hi); workgroup 0 also closes
-// the outer iteration
+// pass 2: y = A^T c, x = clip(z + lambda y, lo, hi) (DROP: lambda Z_j y);
+// workgroup 0 also closes the outer iteration.  For the extrapolated steps
+// (deferred mode) y itself is kept, with per-workgroup partials of ||y||^2,
+// and k_step_apply updates x and closes the iteration.
 // ---------------------------------------------------------------------------
+
+// Pass-2 epilogue of one column (x and ybuf index e); returns y^2 in deferred
+// mode, else 0.
+__device__ inline double epi2(const ColStep &cs, long long col, long long e, double y, float xo, float l, float u,
+                              float *__restrict__ x)
+{
+    if (cs.defer) {
+        cs.ybuf[e] = y;
+        if (cs.ybuf32) cs.ybuf32[e] = (float)y;
+        return y * y;
+    }
+    const double yy = cs.zcol ? y * (double)cs.zcol[col] : y;
+    const double z = fma((double)cs.lambda, yy, (double)xo);
+    x[e] = (float)fmin(fmax(z, (double)l), (double)u);
+    return 0.0;
+}
+
+// End of a pass-2 launch: the ||y||^2 partials (deferred mode), else workgroup
+// 0 closes the outer iteration.
+__device__ inline void end_pass2(const ColStep &cs, double yacc, const SliceState *__restrict__ st_in,
+                                 SliceState *__restrict__ st_out, const double *__restrict__ part1, int nparts1,
+                                 const Hist &h, double *lds)
+{
+    if (cs.defer) {
+        double v[1] = {yacc};
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) cs.ypart[blockIdx.x] = v[0];
+    } else if (blockIdx.x == 0) {
+        finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+    }
+}
 
 template <int LPR, int VEC, typename VT>
 __global__ __launch_bounds__(kBlock) void k_pass2(SpView At, const float *__restrict__ c, float *__restrict__ x,
-                                                  const float *__restrict__ lo, const float *__restrict__ hi,
-                                                  float lambda, const SliceState *__restrict__ st_in,
+                                                  ColStep cs, const SliceState *__restrict__ st_in,
                                                   SliceState *__restrict__ st_out, const double *__restrict__ part1,
                                                   int nparts1, Hist h)
 {
     __shared__ double lds[4];
     constexpr int RPB = kBlock / LPR;
+    double yacc = 0.0;
     if (st_in[0].live) {
         const int lane = threadIdx.x & (LPR - 1);
         const int grp = threadIdx.x / LPR;
@@ -532,25 +564,21 @@ __global__ __launch_bounds__(kBlock) void k_pass2(SpView At, const float *__rest
         for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
             const int beg = At.ptr[col], end = At.ptr[col + 1];
             float xo = 0.f, l = 0.f, u = 0.f;
-            if (lane == 0) { // epilogue operands, fetched while the column streams
+            if (lane == 0 && !cs.defer) { // epilogue operands, fetched while the column streams
                 xo = x[col];
-                l = lo[col];
-                u = hi[col];
+                l = cs.lo[col];
+                u = cs.hi[col];
             }
             const double y = group_sum<LPR>(row_dot<LPR, VEC, VT>(At, beg, end, lane, c)) * (double)At.vscale_inv;
-            if (lane == 0) {
-                const double z = fma((double)lambda, y, (double)xo);
-                x[col] = (float)fmin(fmax(z, (double)l), (double)u);
-            }
+            if (lane == 0) yacc += epi2(cs, col, col, y, xo, l, u, x);
         }
     }
-    if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+    end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
 }
 
 template <int VEC, typename VT>
 __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB, const float *__restrict__ c,
-                                                         float *__restrict__ x, const float *__restrict__ lo,
-                                                         const float *__restrict__ hi, float lambda,
+                                                         float *__restrict__ x, ColStep cs,
                                                          const SliceState *__restrict__ st_in,
                                                          SliceState *__restrict__ st_out,
                                                          const double *__restrict__ part1, int nparts1, Hist h)
@@ -558,16 +586,15 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
     __shared__ double prod[kStreamEntries / VEC];
     __shared__ int rp[kBlock + 1];
     __shared__ double lds[4];
+    double yacc = 0.0;
     if (st_in[0].live) {
         for (int b = blockIdx.x; b < RB.nblk; b += gridDim.x) {
             const int r0 = RB.rb[b], r1 = RB.rb[b + 1];
             const int e0 = At.ptr[r0], e1 = At.ptr[r1];
             if (e1 - e0 > kStreamEntries) {
                 const double sum = long_row_sum<VEC, VT>(At, e0, e1, c, lds);
-                if (threadIdx.x == 0) {
-                    const double z = fma((double)lambda, sum * (double)At.vscale_inv, (double)x[r0]);
-                    x[r0] = (float)fmin(fmax(z, (double)lo[r0]), (double)hi[r0]);
-                }
+                if (threadIdx.x == 0)
+                    yacc += epi2(cs, r0, r0, sum * (double)At.vscale_inv, x[r0], cs.lo[r0], cs.hi[r0], x);
                 continue;
             }
             const int nr = r1 - r0;
@@ -576,8 +603,8 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
             float xo = 0.f, l = 0.f, u = 0.f;
             if (owner) {
                 xo = x[r0 + rs.rl];
-                l = lo[r0 + rs.rl];
-                u = hi[r0 + rs.rl];
+                l = cs.lo[r0 + rs.rl];
+                u = cs.hi[r0 + rs.rl];
             }
             for (int i = threadIdx.x; i <= nr; i += kBlock) rp[i] = (At.ptr[r0 + i] - e0) / VEC;
             stream_chunks<VEC, VT>(At, e0, e1, c, prod);
@@ -586,14 +613,11 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
             if (rs.rl < nr)
                 for (int q = rp[rs.rl] + rs.lane; q < rp[rs.rl + 1]; q += rs.G) s += prod[q];
             s = group_sum_rt(s, rs.G);
-            if (owner) {
-                const double z = fma((double)lambda, s * (double)At.vscale_inv, (double)xo);
-                x[r0 + rs.rl] = (float)fmin(fmax(z, (double)l), (double)u);
-            }
+            if (owner) yacc += epi2(cs, r0 + rs.rl, r0 + rs.rl, s * (double)At.vscale_inv, xo, l, u, x);
             __syncthreads();
         }
     }
-    if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+    end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -629,7 +653,7 @@ __device__ inline void lds_add(float *a, double v) { atomicAdd(a, (float)v); }
 template <int LPR, int VEC, typename VT, typename AccT>
 __global__ __launch_bounds__(kFusedBlock) void k_fused(SpView A, int n, const float *__restrict__ x,
                                                        const float *__restrict__ lower,
-                                                       const float *__restrict__ upper, const float *__restrict__ D,
+                                                       const float *__restrict__ upper, RowW w,
                                                        const SliceState *__restrict__ st,
                                                        double *__restrict__ partials, AccT *__restrict__ ypart)
 {
@@ -653,16 +677,16 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused(SpView A, int n, const fl
     if (live) {
         for (int row = r0 + grp; row < r1; row += RPB) {
             const int beg = A.ptr[row], end = A.ptr[row + 1];
-            const float lo = lower[row], up = upper[row], d = D[row];
+            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row];
             const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
             const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-            const double dt = (double)d * t;
+            const double dt = (double)d * t, ct = (double)sw * t;
             if (lane == 0) pacc[0] += dt * t;
-            if (dt != 0.0 && end > beg) { // the same entries again, now from the cache
+            if (ct != 0.0 && end > beg) { // the same entries again, now from the cache
                 // Neighbouring rows tend to share columns in the same order, so the
                 // groups of a wave start at different chunks of their rows: at any
                 // moment they add into different parts of y.
-                const double sc = dt * (double)A.vscale_inv;
+                const double sc = ct * (double)A.vscale_inv;
                 constexpr int STEP = LPR * VEC;
                 const int nch = (end - beg + STEP - 1) / STEP;
                 int k = grp % nch;
@@ -727,8 +751,7 @@ __device__ inline void fetch_entries(const SpView &A, int beg, int end, int slot
 template <int LPR, int VEC, int CAP, typename VT, typename AccT>
 __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, const float *__restrict__ x,
                                                           const float *__restrict__ lower,
-                                                          const float *__restrict__ upper,
-                                                          const float *__restrict__ D,
+                                                          const float *__restrict__ upper, RowW w,
                                                           const SliceState *__restrict__ st,
                                                           double *__restrict__ partials, AccT *__restrict__ ypart)
 {
@@ -756,16 +779,17 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
         // row `row`: entries in cur; row + RPB: offsets/band in nb..; entries follow
         RowRegs<VEC, CAP> cur, nxt;
         int beg = A.ptr[row], end = A.ptr[row + 1];
-        float lo = lower[row], up = upper[row], d = D[row];
+        float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row];
         fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, cur);
         int nb = 0, ne = 0;
-        float nlo = 0.f, nup = 0.f, nd = 0.f;
+        float nlo = 0.f, nup = 0.f, nd = 0.f, nsw = 0.f;
         if (row + RPB < r1) {
             nb = A.ptr[row + RPB];
             ne = A.ptr[row + RPB + 1];
             nlo = lower[row + RPB];
             nup = upper[row + RPB];
-            nd = D[row + RPB];
+            nd = w.D[row + RPB];
+            nsw = w.S[row + RPB];
         }
         for (;;) {
             float xg[CAP][VEC];
@@ -776,13 +800,14 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
             const int rn = row + RPB, rnn = row + 2 * RPB;
             if (rn < r1) fetch_entries<LPR, VEC, CAP, VT>(A, nb, ne, slot, nxt);
             int hb = 0, he = 0;
-            float hlo = 0.f, hup = 0.f, hd = 0.f;
+            float hlo = 0.f, hup = 0.f, hd = 0.f, hsw = 0.f;
             if (rnn < r1) {
                 hb = A.ptr[rnn];
                 he = A.ptr[rnn + 1];
                 hlo = lower[rnn];
                 hup = upper[rnn];
-                hd = D[rnn];
+                hd = w.D[rnn];
+                hsw = w.S[rnn];
             }
             double acc = 0.0;
 #pragma unroll
@@ -793,10 +818,10 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
             if (tail) acc += row_dot<LPR, VEC, VT>(A, beg + CAP * STEP, end, lane, x);
             const double r = group_sum<LPR>(acc) * (double)A.vscale_inv;
             const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-            const double dt = (double)d * t;
+            const double dt = (double)d * t, ct = (double)sw * t;
             if (lane == 0) pacc[0] += dt * t;
-            if (dt != 0.0) {
-                const double sc = dt * (double)A.vscale_inv;
+            if (ct != 0.0) {
+                const double sc = ct * (double)A.vscale_inv;
 #pragma unroll
                 for (int q = 0; q < CAP; ++q)
 #pragma unroll
@@ -820,12 +845,14 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
             lo = nlo;
             up = nup;
             d = nd;
+            sw = nsw;
             cur = nxt;
             nb = hb;
             ne = he;
             nlo = hlo;
             nup = hup;
             nd = hd;
+            nsw = hsw;
         }
     }
     block_sum<1, kFusedRcBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
@@ -835,13 +862,13 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
     for (int j = threadIdx.x; j < n; j += kFusedRcBlock) out[j] = y[j];
 }
 
-// x = clip(z + lambda * sum_g ypart[g], lo, hi); 64 unknowns per workgroup, the
-// four waves each sum every fourth partial and the four sums are added in a
-// fixed order.  Workgroup 0 also closes the outer iteration.
+// x = clip(z + lambda * Z_j * sum_g ypart[g], lo, hi) (Z_j = 1 unless DROP);
+// 64 unknowns per workgroup, the four waves each sum every fourth partial
+// (loads issued four at a time, added in order) and the four sums are added in
+// a fixed order.  Workgroup 0 also closes the outer iteration.
 template <typename AccT>
 __global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__ ypart, int G, int n,
-                                                        float *__restrict__ x, const float *__restrict__ lo,
-                                                        const float *__restrict__ hi, float lambda,
+                                                        float *__restrict__ x, ColStep cs,
                                                         const SliceState *__restrict__ st_in,
                                                         SliceState *__restrict__ st_out,
                                                         const double *__restrict__ part1, int nparts1, Hist h)
@@ -852,22 +879,78 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__
     if (st_in[0].live) {
         for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
             const int j = j0 + wl;
+            constexpr int W = kBlock / 64;
             double sum = 0.0;
-            if (j < n)
-                for (int g = wid; g < G; g += kBlock / 64) sum += (double)ypart[(long long)g * n + j];
+            if (j < n) {
+                int g = wid;
+                for (; g + 3 * W < G; g += 4 * W) {
+                    double v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = (double)ypart[(long long)(g + u * W) * n + j];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) sum += v[u];
+                }
+                for (; g < G; g += W) sum += (double)ypart[(long long)g * n + j];
+            }
             red[wid][wl] = sum;
             __syncthreads();
             if (wid == 0 && j < n) {
                 double yv = 0.0;
 #pragma unroll
-                for (int w = 0; w < kBlock / 64; ++w) yv += red[w][wl];
-                const double z = fma((double)lambda, yv, (double)x[j]);
-                x[j] = (float)fmin(fmax(z, (double)lo[j]), (double)hi[j]);
+                for (int w = 0; w < W; ++w) yv += red[w][wl];
+                if (cs.zcol) yv *= (double)cs.zcol[j];
+                const double z = fma((double)cs.lambda, yv, (double)x[j]);
+                x[j] = (float)fmin(fmax(z, (double)cs.lo[j]), (double)cs.hi[j]);
             }
             __syncthreads();
         }
     }
     if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+}
+
+// Extrapolated steps (one launch after pass 2, or after the quadratic-form
+// pass): per slice, sigma from the totals of the partials, each summed in
+// workgroup order by every workgroup (EL: t^T D t / ||y||^2, with t^T D t
+// twice pass 1's proximity sum; EMR: ||y||^2 / sum_i w_i (A y)_i^2), 0 when the
+// denominator is 0 or the quotient is not finite; then
+// x = clip(z + lambda sigma y, lo, hi).  Workgroup 0 also closes the iteration.
+__global__ __launch_bounds__(kBlock) void k_step_apply(int n, int B, const double *__restrict__ y,
+                                                       float *__restrict__ x, const float *__restrict__ lo,
+                                                       const float *__restrict__ hi, float lambda, int emr,
+                                                       const double *__restrict__ part1, int nparts1,
+                                                       const double *__restrict__ party, int npartsy,
+                                                       const double *__restrict__ partq, int npartsq,
+                                                       const SliceState *__restrict__ st_in,
+                                                       SliceState *__restrict__ st_out, Hist h)
+{
+    __shared__ double lds[4];
+    __shared__ double sigma[32];
+    __shared__ int live[32];
+    for (int s = 0; s < B; ++s) {
+        double num[1], den[1];
+        if (emr) {
+            sum_slots<1>(party, (long long)s * npartsy, npartsy, num, lds);
+            sum_slots<1>(partq, (long long)s * npartsq, npartsq, den, lds);
+        } else {
+            sum_slots<1>(part1, (long long)s * nparts1, nparts1, num, lds);
+            sum_slots<1>(party, (long long)s * npartsy, npartsy, den, lds);
+        }
+        if (threadIdx.x == 0) {
+            const double q = num[0] / den[0];
+            sigma[s] = (den[0] > 0.0 && isfinite(q)) ? q : 0.0;
+            live[s] = st_in[s].live;
+        }
+    }
+    __syncthreads();
+    const long long total = (long long)n * B;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < total; e += (long long)gridDim.x * kBlock) {
+        const int s = (int)(e % B);
+        if (!live[s]) continue;
+        const long long j = e / B;
+        const double z = fma((double)lambda * sigma[s], y[e], (double)x[e]);
+        x[e] = (float)fmin(fmax(z, (double)lo[j]), (double)hi[j]);
+    }
+    if (blockIdx.x == 0) finish_iteration(st_in, st_out, B, part1, nparts1, h, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -924,7 +1007,7 @@ __device__ inline void row_dot_mm(const SpView &A, int beg, int end, int lane, c
 template <int LPR, int VEC, typename VT, int B>
 __global__ __launch_bounds__(kBlock) void k_pass1_mm(SpView A, const float *__restrict__ x,
                                                      const float *__restrict__ lower, const float *__restrict__ upper,
-                                                     const float *__restrict__ D, float *__restrict__ c,
+                                                     RowW w, float *__restrict__ c,
                                                      const SliceState *__restrict__ st, int query,
                                                      double *__restrict__ partials)
 {
@@ -944,15 +1027,12 @@ __global__ __launch_bounds__(kBlock) void k_pass1_mm(SpView A, const float *__re
         double acc[B];
         row_dot_mm<LPR, VEC, VT, B>(A, beg, end, lane, x, acc);
         if (lane == 0) {
-            const double d = (double)D[row];
+            const float d = w.D[row], sw = w.S[row];
 #pragma unroll
             for (int s = 0; s < B; ++s) {
                 if (!live[s]) continue;
-                const double r = acc[s] * (double)A.vscale_inv;
-                const double t = fmin(fmax(r, (double)lower[row * B + s]), (double)upper[row * B + s]) - r;
-                const double dt = d * t;
-                c[row * B + s] = (float)dt;
-                pacc[s] += dt * t;
+                pacc[s] += epi1(w, acc[s] * (double)A.vscale_inv, lower[row * B + s], upper[row * B + s], d, sw,
+                                c + row * B + s);
             }
         }
     }
@@ -965,34 +1045,43 @@ __global__ __launch_bounds__(kBlock) void k_pass1_mm(SpView A, const float *__re
 
 template <int LPR, int VEC, typename VT, int B>
 __global__ __launch_bounds__(kBlock) void k_pass2_mm(SpView At, const float *__restrict__ c, float *__restrict__ x,
-                                                     const float *__restrict__ lo, const float *__restrict__ hi,
-                                                     float lambda, const SliceState *__restrict__ st_in,
+                                                     ColStep cs, const SliceState *__restrict__ st_in,
                                                      SliceState *__restrict__ st_out,
                                                      const double *__restrict__ part1, int nparts1, Hist h)
 {
-    __shared__ double lds[4];
+    __shared__ double lds[4 * B];
     __shared__ int live[B];
     constexpr int RPB = kBlock / LPR;
     if (threadIdx.x < B) live[threadIdx.x] = st_in[threadIdx.x].live;
     __syncthreads();
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
+    double yacc[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) yacc[s] = 0.0;
     const long long stride = (long long)gridDim.x * RPB;
     for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
         const int beg = At.ptr[col], end = At.ptr[col + 1];
         double acc[B];
         row_dot_mm<LPR, VEC, VT, B>(At, beg, end, lane, c, acc);
         if (lane == 0) {
-            const double l = (double)lo[col], u = (double)hi[col];
+            const float l = cs.lo[col], u = cs.hi[col];
 #pragma unroll
             for (int s = 0; s < B; ++s) {
                 if (!live[s]) continue;
-                const double z = fma((double)lambda, acc[s] * (double)At.vscale_inv, (double)x[col * B + s]);
-                x[col * B + s] = (float)fmin(fmax(z, l), u);
+                yacc[s] += epi2(cs, col, col * B + s, acc[s] * (double)At.vscale_inv, x[col * B + s], l, u, x);
             }
         }
     }
-    if (blockIdx.x == 0) finish_iteration(st_in, st_out, B, part1, nparts1, h, lds);
+    if (cs.defer) {
+        block_sum<B>(yacc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int s = 0; s < B; ++s) cs.ypart[(long long)s * gridDim.x + blockIdx.x] = yacc[s];
+        }
+    } else if (blockIdx.x == 0) {
+        finish_iteration(st_in, st_out, B, part1, nparts1, h, lds);
+    }
 }
 
 // Query: the proximity at the current x from pass 1's partials (query mode).
@@ -1727,17 +1816,17 @@ hipError_t launch_init_state(SliceState *st, int B, hipStream_t s)
 
 template <typename VT, int VEC>
 static hipError_t pass1_vec(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
-                            const float *upper, const float *D, float *c, const SliceState *st, int query,
+                            const float *upper, RowW w, float *c, const SliceState *st, int query,
                             double *partials, hipStream_t s)
 {
     const dim3 grid(cfg.grid), block(kBlock);
     switch (cfg.lpr) {
-    case 2: hipLaunchKernelGGL((k_pass1<2, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 4: hipLaunchKernelGGL((k_pass1<4, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 8: hipLaunchKernelGGL((k_pass1<8, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 16: hipLaunchKernelGGL((k_pass1<16, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 32: hipLaunchKernelGGL((k_pass1<32, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 64: hipLaunchKernelGGL((k_pass1<64, VEC, VT>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 2: hipLaunchKernelGGL((k_pass1<2, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 4: hipLaunchKernelGGL((k_pass1<4, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 8: hipLaunchKernelGGL((k_pass1<8, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 16: hipLaunchKernelGGL((k_pass1<16, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 32: hipLaunchKernelGGL((k_pass1<32, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 64: hipLaunchKernelGGL((k_pass1<64, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1745,24 +1834,24 @@ static hipError_t pass1_vec(const PassCfg &cfg, const SpView &A, const float *x,
 
 template <typename VT, int VEC>
 static hipError_t pass1_stream(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, const float *x,
-                               const float *lower, const float *upper, const float *D, float *c,
+                               const float *lower, const float *upper, RowW w, float *c,
                                const SliceState *st, int query, double *partials, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pass1_stream<VEC, VT>), dim3(cfg.grid), dim3(kBlock), 0, s, A, RB, x, lower, upper, D, c,
+    hipLaunchKernelGGL((k_pass1_stream<VEC, VT>), dim3(cfg.grid), dim3(kBlock), 0, s, A, RB, x, lower, upper, w, c,
                        st, query, partials);
     return hipGetLastError();
 }
 
 template <typename VT, int VEC, int B>
 static hipError_t pass1_mm(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
-                           const float *upper, const float *D, float *c, const SliceState *st, int query,
+                           const float *upper, RowW w, float *c, const SliceState *st, int query,
                            double *partials, hipStream_t s)
 {
     const dim3 grid(cfg.grid), block(kBlock);
     switch (cfg.lpr) {
-    case 4: hipLaunchKernelGGL((k_pass1_mm<4, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 8: hipLaunchKernelGGL((k_pass1_mm<8, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
-    case 16: hipLaunchKernelGGL((k_pass1_mm<16, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, D, c, st, query, partials); break;
+    case 4: hipLaunchKernelGGL((k_pass1_mm<4, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 8: hipLaunchKernelGGL((k_pass1_mm<8, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+    case 16: hipLaunchKernelGGL((k_pass1_mm<16, VEC, VT, B>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1770,65 +1859,65 @@ static hipError_t pass1_mm(const PassCfg &cfg, const SpView &A, const float *x, 
 
 template <typename VT, int VEC>
 static hipError_t pass1_mm_b(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
-                             const float *upper, const float *D, float *c, const SliceState *st, int B, int query,
+                             const float *upper, RowW w, float *c, const SliceState *st, int B, int query,
                              double *partials, hipStream_t s)
 {
     switch (B) {
-    case 2: return pass1_mm<VT, VEC, 2>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-    case 4: return pass1_mm<VT, VEC, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-    case 8: return pass1_mm<VT, VEC, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-    case 16: return pass1_mm<VT, VEC, 16>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-    case 32: return pass1_mm<VT, VEC, 32>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    case 2: return pass1_mm<VT, VEC, 2>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+    case 4: return pass1_mm<VT, VEC, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+    case 8: return pass1_mm<VT, VEC, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+    case 16: return pass1_mm<VT, VEC, 16>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+    case 32: return pass1_mm<VT, VEC, 32>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
-                        const float *lower, const float *upper, const float *D, float *c, const SliceState *st, int B,
+                        const float *lower, const float *upper, RowW w, float *c, const SliceState *st, int B,
                         int query, double *partials, hipStream_t s)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
     if (B > 1) {
-        if (vk == VK_F32) return pass1_mm_b<float, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
-        if (vk == VK_BF16) return pass1_mm_b<Bf16Tag, 8>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
-        if (vk == VK_BF16P) return pass1_mm_b<Bf16PTag, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
-        if (vk == VK_F16P) return pass1_mm_b<F16PTag, 4>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
-        return pass1_mm_b<F16Tag, 8>(cfg, A, x, lower, upper, D, c, st, B, query, partials, s);
+        if (vk == VK_F32) return pass1_mm_b<float, 4>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
+        if (vk == VK_BF16) return pass1_mm_b<Bf16Tag, 8>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
+        if (vk == VK_BF16P) return pass1_mm_b<Bf16PTag, 4>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
+        if (vk == VK_F16P) return pass1_mm_b<F16PTag, 4>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
+        return pass1_mm_b<F16Tag, 8>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
     }
     if (cfg.mode == 1) {
-        if (vk == VK_F32) return pass1_stream<float, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
-        if (vk == VK_BF16) return pass1_stream<Bf16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
-        if (vk == VK_BF16P) return pass1_stream<Bf16PTag, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
-        if (vk == VK_F16P) return pass1_stream<F16PTag, 4>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
-        return pass1_stream<F16Tag, 8>(cfg, A, RB, x, lower, upper, D, c, st, query, partials, s);
+        if (vk == VK_F32) return pass1_stream<float, 4>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
+        if (vk == VK_BF16) return pass1_stream<Bf16Tag, 8>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
+        if (vk == VK_BF16P) return pass1_stream<Bf16PTag, 4>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
+        if (vk == VK_F16P) return pass1_stream<F16PTag, 4>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
+        return pass1_stream<F16Tag, 8>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_BF16P) {
-        if (cfg.vec == 8) return pass1_vec<Bf16PTag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-        return pass1_vec<Bf16PTag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        if (cfg.vec == 8) return pass1_vec<Bf16PTag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+        return pass1_vec<Bf16PTag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_F16P) {
-        if (cfg.vec == 8) return pass1_vec<F16PTag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-        return pass1_vec<F16PTag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        if (cfg.vec == 8) return pass1_vec<F16PTag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+        return pass1_vec<F16PTag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_F32) {
-        if (cfg.vec == 8) return pass1_vec<float, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-        return pass1_vec<float, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        if (cfg.vec == 8) return pass1_vec<float, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+        return pass1_vec<float, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_BF16) {
-        if (cfg.vec == 8) return pass1_vec<Bf16Tag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-        return pass1_vec<Bf16Tag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+        if (cfg.vec == 8) return pass1_vec<Bf16Tag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+        return pass1_vec<Bf16Tag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
-    if (cfg.vec == 8) return pass1_vec<F16Tag, 8>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
-    return pass1_vec<F16Tag, 4>(cfg, A, x, lower, upper, D, c, st, query, partials, s);
+    if (cfg.vec == 8) return pass1_vec<F16Tag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+    return pass1_vec<F16Tag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
 }
 
 template <typename VT, int VEC>
-static hipError_t pass2_vec(const PassCfg &cfg, const SpView &At, const float *c, float *x, const float *lo,
-                            const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
-                            const double *part1, int nparts1, Hist h, hipStream_t s)
+static hipError_t pass2_vec(const PassCfg &cfg, const SpView &At, const float *c, float *x, ColStep cs,
+                            const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                            hipStream_t s)
 {
     const dim3 grid(cfg.grid), block(kBlock);
-#define SMX_P2(L) hipLaunchKernelGGL((k_pass2<L, VEC, VT>), grid, block, 0, s, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h)
+#define SMX_P2(L) hipLaunchKernelGGL((k_pass2<L, VEC, VT>), grid, block, 0, s, At, c, x, cs, st_in, st_out, part1, nparts1, h)
     switch (cfg.lpr) {
     case 2: SMX_P2(2); break;
     case 4: SMX_P2(4); break;
@@ -1844,21 +1933,21 @@ static hipError_t pass2_vec(const PassCfg &cfg, const SpView &At, const float *c
 
 template <typename VT, int VEC>
 static hipError_t pass2_stream(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, const float *c, float *x,
-                               const float *lo, const float *hi, float lambda, const SliceState *st_in,
-                               SliceState *st_out, const double *part1, int nparts1, Hist h, hipStream_t s)
+                               ColStep cs, const SliceState *st_in, SliceState *st_out, const double *part1,
+                               int nparts1, Hist h, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pass2_stream<VEC, VT>), dim3(cfg.grid), dim3(kBlock), 0, s, At, RB, c, x, lo, hi, lambda,
+    hipLaunchKernelGGL((k_pass2_stream<VEC, VT>), dim3(cfg.grid), dim3(kBlock), 0, s, At, RB, c, x, cs,
                        st_in, st_out, part1, nparts1, h);
     return hipGetLastError();
 }
 
 template <typename VT, int VEC, int B>
-static hipError_t pass2_mm(const PassCfg &cfg, const SpView &At, const float *c, float *x, const float *lo,
-                           const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
-                           const double *part1, int nparts1, Hist h, hipStream_t s)
+static hipError_t pass2_mm(const PassCfg &cfg, const SpView &At, const float *c, float *x, ColStep cs,
+                           const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                           hipStream_t s)
 {
     const dim3 grid(cfg.grid), block(kBlock);
-#define SMX_P2MM(L) hipLaunchKernelGGL((k_pass2_mm<L, VEC, VT, B>), grid, block, 0, s, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h)
+#define SMX_P2MM(L) hipLaunchKernelGGL((k_pass2_mm<L, VEC, VT, B>), grid, block, 0, s, At, c, x, cs, st_in, st_out, part1, nparts1, h)
     switch (cfg.lpr) {
     case 4: SMX_P2MM(4); break;
     case 8: SMX_P2MM(8); break;
@@ -1870,57 +1959,57 @@ static hipError_t pass2_mm(const PassCfg &cfg, const SpView &At, const float *c,
 }
 
 template <typename VT, int VEC>
-static hipError_t pass2_mm_b(const PassCfg &cfg, const SpView &At, const float *c, float *x, const float *lo,
-                             const float *hi, float lambda, const SliceState *st_in, SliceState *st_out, int B,
-                             const double *part1, int nparts1, Hist h, hipStream_t s)
+static hipError_t pass2_mm_b(const PassCfg &cfg, const SpView &At, const float *c, float *x, ColStep cs,
+                             const SliceState *st_in, SliceState *st_out, int B, const double *part1, int nparts1,
+                             Hist h, hipStream_t s)
 {
     switch (B) {
-    case 2: return pass2_mm<VT, VEC, 2>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-    case 4: return pass2_mm<VT, VEC, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-    case 8: return pass2_mm<VT, VEC, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-    case 16: return pass2_mm<VT, VEC, 16>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-    case 32: return pass2_mm<VT, VEC, 32>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    case 2: return pass2_mm<VT, VEC, 2>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 4: return pass2_mm<VT, VEC, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 8: return pass2_mm<VT, VEC, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 16: return pass2_mm<VT, VEC, 16>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 32: return pass2_mm<VT, VEC, 32>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
-                        const float *lo, const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
-                        int B, const double *part1, int nparts1, Hist h, hipStream_t s)
+                        ColStep cs, const SliceState *st_in, SliceState *st_out, int B, const double *part1,
+                        int nparts1, Hist h, hipStream_t s)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
     if (B > 1) {
-        if (vk == VK_F32) return pass2_mm_b<float, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
-        if (vk == VK_BF16) return pass2_mm_b<Bf16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
-        if (vk == VK_BF16P) return pass2_mm_b<Bf16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
-        if (vk == VK_F16P) return pass2_mm_b<F16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
-        return pass2_mm_b<F16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_F32) return pass2_mm_b<float, 4>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_BF16) return pass2_mm_b<Bf16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_BF16P) return pass2_mm_b<Bf16PTag, 4>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_F16P) return pass2_mm_b<F16PTag, 4>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        return pass2_mm_b<F16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
     }
     if (cfg.mode == 1) {
-        if (vk == VK_F32) return pass2_stream<float, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        if (vk == VK_BF16) return pass2_stream<Bf16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        if (vk == VK_BF16P) return pass2_stream<Bf16PTag, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        if (vk == VK_F16P) return pass2_stream<F16PTag, 4>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        return pass2_stream<F16Tag, 8>(cfg, At, RB, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_F32) return pass2_stream<float, 4>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_BF16) return pass2_stream<Bf16Tag, 8>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_BF16P) return pass2_stream<Bf16PTag, 4>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        if (vk == VK_F16P) return pass2_stream<F16PTag, 4>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return pass2_stream<F16Tag, 8>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     }
     if (vk == VK_BF16P) {
-        if (cfg.vec == 8) return pass2_vec<Bf16PTag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        return pass2_vec<Bf16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (cfg.vec == 8) return pass2_vec<Bf16PTag, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<Bf16PTag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     }
     if (vk == VK_F16P) {
-        if (cfg.vec == 8) return pass2_vec<F16PTag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        return pass2_vec<F16PTag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (cfg.vec == 8) return pass2_vec<F16PTag, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<F16PTag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     }
     if (vk == VK_F32) {
-        if (cfg.vec == 8) return pass2_vec<float, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        return pass2_vec<float, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (cfg.vec == 8) return pass2_vec<float, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<float, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     }
     if (vk == VK_BF16) {
-        if (cfg.vec == 8) return pass2_vec<Bf16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-        return pass2_vec<Bf16Tag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+        if (cfg.vec == 8) return pass2_vec<Bf16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<Bf16Tag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     }
-    if (cfg.vec == 8) return pass2_vec<F16Tag, 8>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
-    return pass2_vec<F16Tag, 4>(cfg, At, c, x, lo, hi, lambda, st_in, st_out, part1, nparts1, h, s);
+    if (cfg.vec == 8) return pass2_vec<F16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    return pass2_vec<F16Tag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
 }
 
 size_t fused_lds_bytes(int64_t n, int acc64) { return size_t(n) * (acc64 ? sizeof(double) : sizeof(float)); }
@@ -1939,7 +2028,8 @@ namespace {
 struct FusedArgs {
     const SpView *A;
     int64_t n;
-    const float *x, *lower, *upper, *D;
+    const float *x, *lower, *upper;
+    RowW w;
     const SliceState *st;
     double *partials;
     void *ypart;
@@ -1967,7 +2057,7 @@ hipError_t fused_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStr
         return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)bytes);
     hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.cap > 0 ? kFusedRcBlock : kFusedBlock), bytes, s, *a.A,
-                       (int)a.n, a.x, a.lower, a.upper, a.D, a.st, a.partials, static_cast<AccT *>(a.ypart));
+                       (int)a.n, a.x, a.lower, a.upper, a.w, a.st, a.partials, static_cast<AccT *>(a.ypart));
     return hipGetLastError();
 }
 
@@ -2014,30 +2104,43 @@ hipError_t fused_dispatch(const FusedCfg &cfg, int vk, const FusedArgs &a, int p
 hipError_t prepare_fused(const FusedCfg &cfg, int vk, int64_t n)
 {
     SpView none{};
-    FusedArgs a{&none, n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    FusedArgs a{&none, n, nullptr, nullptr, nullptr, RowW{nullptr, nullptr, 0}, nullptr, nullptr, nullptr};
     return fused_dispatch(cfg, vk, a, 1, nullptr);
 }
 
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
-                        const float *upper, const float *D, const SliceState *st, double *partials, void *ypart,
+                        const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
                         hipStream_t s)
 {
-    FusedArgs a{&A, n, x, lower, upper, D, st, partials, ypart};
+    if (w.qform) return hipErrorInvalidValue; // the fused pass makes c, never the quadratic form
+    FusedArgs a{&A, n, x, lower, upper, w, st, partials, ypart};
     return fused_dispatch(cfg, vk, a, 0, s);
 }
 
-hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, const float *lo,
-                              const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
-                              const double *part1, Hist h, hipStream_t s)
+hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, ColStep cs,
+                              const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
+                              hipStream_t s)
 {
-    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1) return hipErrorInvalidValue;
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1 || cs.defer) return hipErrorInvalidValue;
     const unsigned grid = grid_for(n, 64, 4096);
     if (cfg.acc64)
         hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kBlock), 0, s, static_cast<const double *>(ypart),
-                           cfg.grid, (int)n, x, lo, hi, lambda, st_in, st_out, part1, cfg.grid, h);
+                           cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
     else
         hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kBlock), 0, s, static_cast<const float *>(ypart),
-                           cfg.grid, (int)n, x, lo, hi, lambda, st_in, st_out, part1, cfg.grid, h);
+                           cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_apply(int64_t n, int B, const double *y, float *x, const float *lo, const float *hi,
+                             float lambda, int emr, const double *part1, int nparts1, const double *party, int npartsy,
+                             const double *partq, int npartsq, const SliceState *st_in, SliceState *st_out, Hist h,
+                             hipStream_t s)
+{
+    if (n < 1 || B < 1 || B > 32 || nparts1 < 1 || npartsy < 1 || (emr && npartsq < 1)) return hipErrorInvalidValue;
+    const unsigned grid = grid_for(n * B, kBlock, 2048);
+    hipLaunchKernelGGL(k_step_apply, dim3(grid), dim3(kBlock), 0, s, (int)n, B, y, x, lo, hi, lambda, emr, part1,
+                       nparts1, party, npartsy, partq, npartsq, st_in, st_out, h);
     return hipGetLastError();
 }
 

@@ -90,6 +90,32 @@ struct PassCfg {
     int grid; // workgroups
 };
 
+// Row weights of pass 1: c_i = S_i t_i and the proximity term D_i t_i^2 (S = D
+// for the weighted simultaneous step; 1/||A||_F^2 for CQ; w for the
+// error-minimising step).  In quadratic-form mode the gathered vector is y
+// and the only output is the partial of sum_i S_i (A y)_i^2.
+struct RowW {
+    const float *D;
+    const float *S;
+    int qform;
+};
+
+// Column step of pass 2 (and of the fused pass's apply kernel):
+// x = clip(z + lambda * zcol_j * y_j, lo, hi) (zcol NULL: factor 1), or, when
+// defer != 0, y itself into ybuf (float64; also rounded into ybuf32 when that
+// is not NULL, the vector EMR's second product gathers) with per-workgroup
+// partials of ||y||^2 in ypart (the extrapolated steps apply x in
+// k_step_apply).
+struct ColStep {
+    const float *lo, *hi;
+    float lambda;
+    const float *zcol;
+    double *ybuf;
+    float *ybuf32;
+    double *ypart;
+    int defer;
+};
+
 // Launch shape of the fused single pass (one slice).
 struct FusedCfg {
     int lpr;   // lanes per row: 8, 16 or 32
@@ -127,24 +153,32 @@ constexpr int kMaxPassGrid = 4096; // workgroups of a pass kernel (one proximity
 // pass 1: r = A x, t = clip(r) - r, c = D t, one proximity partial per
 // workgroup (query != 0: every slice runs, whatever its state)
 hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
-                        const float *lower, const float *upper, const float *D, float *c, const SliceState *st, int B,
+                        const float *lower, const float *upper, RowW w, float *c, const SliceState *st, int B,
                         int query, double *partials, hipStream_t s);
 // pass 2: x = clip(x + lambda A^T c, lo, hi); workgroup 0 also ends the
 // iteration (proximity from pass 1's partials, history, k + 1) into st_out
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
-                        const float *lo, const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
-                        int B, const double *part1, int nparts1, Hist h, hipStream_t s);
+                        ColStep cs, const SliceState *st_in, SliceState *st_out, int B, const double *part1,
+                        int nparts1, Hist h, hipStream_t s);
+// x = clip(z + lambda * sigma_s * y, lo, hi) for the extrapolated steps, sigma_s
+// per slice from the partials: EL (emr = 0) t^T D t / ||y||^2 from pass 1's
+// and pass 2's partials, EMR (emr = 1) ||y||^2 / sum w (A y)^2 from pass 2's and
+// the quadratic-form pass's; closes the iteration.
+hipError_t launch_step_apply(int64_t n, int B, const double *y, float *x, const float *lo, const float *hi,
+                             float lambda, int emr, const double *part1, int nparts1, const double *party, int npartsy,
+                             const double *partq, int npartsq, const SliceState *st_in, SliceState *st_out, Hist h,
+                             hipStream_t s);
 // fused pass over the CSR: r = A z, t, c = D t, the proximity partial per
 // workgroup, and one partial vector of y = A^T c per workgroup in ypart
 // (grid x n, float64 or float32 by cfg.acc64).  lds_bytes: dynamic LDS it needs.
 size_t fused_lds_bytes(int64_t n, int acc64);
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
-                        const float *upper, const float *D, const SliceState *st, double *partials, void *ypart,
+                        const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
                         hipStream_t s);
 // x = clip(z + lambda * sum of the partial vectors, lo, hi); closes the iteration
-hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, const float *lo,
-                              const float *hi, float lambda, const SliceState *st_in, SliceState *st_out,
-                              const double *part1, Hist h, hipStream_t s);
+hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, ColStep cs,
+                              const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
+                              hipStream_t s);
 // largest dynamic LDS one fused workgroup may take on the current device, after
 // the kernel's attributes are raised to it (0 if that fails)
 size_t fused_lds_limit();
