@@ -212,6 +212,23 @@ def section_serving(smx, tune):
                 burst=clean(burst), poisson=dict(rate_hz=round(rate, 3), **clean(poisson)))
 
 
+def section_basic(smx, steps, warmup, tune):
+    """The other basic algorithms on the headline CT workload (float32, one
+    slice): SM iterations/s and the proximity after the run.  EMR reads A three
+    times per iteration, EL and EMR keep y between launches."""
+    import workloads as W
+
+    w = W.ct(N=256, seed=2, K=200)
+    out = {}
+    for name, basic in (("simult", W.BASIC_SIMULT), ("drop", W.BASIC_DROP), ("cq", W.BASIC_CQ),
+                        ("el", W.BASIC_EL), ("emr", W.BASIC_EMR)):
+        wb = w.with_params(basic=basic, lam=float(w.m) if basic == W.BASIC_DROP else w.lam)
+        r = time_problem(smx, wb, "f32", steps, warmup, tune=tune)
+        out[name] = dict(it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5), prox=r["prox"][0],
+                         obj=r["obj"][0], fused=fused_in_use(r["shapes"]))
+    return out
+
+
 def section_hbm(smx, tune):
     import workloads as W
 
@@ -239,8 +256,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--sections", default="batched,serving,hbm",
-                    help="extra sections beside the headline: batched,serving,hbm (empty for none)")
+    ap.add_argument("--sections", default="batched,serving,hbm,basic",
+                    help="extra sections beside the headline: batched,serving,hbm,basic (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the single-GPU path is what is built "
@@ -298,6 +315,8 @@ def main():
         line["serving"] = section_serving(smx, tune)
     if "hbm" in sections:
         line["hbm_config"] = section_hbm(smx, tune)
+    if "basic" in sections:
+        line["basic_algorithms"] = section_basic(smx, 100, 10, tune)
     print(json.dumps(line), flush=True)
 
 
