@@ -25,6 +25,7 @@ _SRC = os.path.join(_HERE, "orc.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 1, 2, 3, 4, 5
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 
 
@@ -64,6 +65,13 @@ class _Problem(C.Structure):
         ("restart_every", C.c_int32),
         ("basic", C.c_int32),
         ("col_nnz", C.POINTER(C.c_double)),
+        ("stop_on", C.c_int32),
+        ("stop_n", C.c_int32),
+        ("stop_max", C.c_int32),
+        ("stop_prox", C.c_double),
+        ("stop_dprox", C.c_double),
+        ("stop_dobj", C.c_double),
+        ("stop_var", C.c_double),
     ]
 
 
@@ -77,7 +85,21 @@ class State(C.Structure):
         ("trials", C.c_int64),
         ("accepts", C.c_int64),
         ("cap_hits", C.c_int64),
+        ("stop_reason", C.c_int32),
+        ("dp_run", C.c_int32),
+        ("feas_ok", C.c_int32),
+        ("pad_", C.c_int32),
+        ("p_last", C.c_double),
+        ("f_last", C.c_double),
+        ("var_n", C.c_double),
+        ("var_mean", C.c_double),
+        ("var_m2", C.c_double),
     ]
+
+    def __init__(self):
+        super().__init__()
+        self.p_last = float("nan")
+        self.f_last = float("nan")
 
     def copy(self) -> "State":
         s = State()
@@ -85,7 +107,12 @@ class State(C.Structure):
         return s
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        """Fields as Python numbers (NaN as None, so equal states compare equal)."""
+        out = {}
+        for f, t in self._fields_:
+            v = getattr(self, f)
+            out[f] = (None if v != v else float(v)) if t is C.c_double else int(v)
+        return out
 
 
 _lib = None
@@ -166,6 +193,7 @@ class Problem:
         max_trials=100,
         basic=BASIC_SIMULT,
         col_nnz=None,
+        stop=None,
     ):
         self.m, self.n = int(m), int(n)
         self.row_ptr = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
@@ -204,6 +232,14 @@ class Problem:
             basic=int(basic),
             col_nnz=_dp(self.col_nnz),
         )
+        if stop is not None:
+            self.s.stop_on = 1
+            self.s.stop_n = int(stop.get("n", 5))
+            self.s.stop_max = int(stop.get("max_iters", 0))
+            self.s.stop_prox = float(stop.get("prox", 1e-6))
+            self.s.stop_dprox = float(stop.get("dprox", 1e-8))
+            self.s.stop_dobj = float(stop.get("dobj", 1e-6))
+            self.s.stop_var = float(stop.get("var", 0.0))
 
     # -- building blocks -------------------------------------------------
     def matvec(self, x) -> np.ndarray:
@@ -325,4 +361,5 @@ def from_workload(w, s: int = 0, value_round: Optional[str] = None) -> Problem:
         max_trials=w.max_trials,
         basic=getattr(w, "basic", BASIC_SIMULT),
         col_nnz=col_nnz,
+        stop=getattr(w, "stop", None),
     )

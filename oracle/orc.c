@@ -71,6 +71,15 @@ typedef struct {
     int32_t n_red, restart_every;
     int32_t basic;          /* ORC_BASIC_*: the feasibility-seeking step */
     const double *col_nnz;  /* n, nonzeros per column for DROP, or NULL to count them from val */
+    /* stopping rules (Section 2.2 and the superiorized variant of Section
+     * 2.2.1; the variance rule of Section 2.3.2); stop_on = 0 disables all */
+    int32_t stop_on;
+    int32_t stop_n;      /* N: consecutive iterations with a small proximity change */
+    int32_t stop_max;    /* N_max (0: none) */
+    double stop_prox;    /* P* */
+    double stop_dprox;   /* Delta P* */
+    double stop_dobj;    /* Delta f* */
+    double stop_var;     /* variance threshold (0: rule off) */
 } orc_problem;
 
 typedef struct {
@@ -80,7 +89,21 @@ typedef struct {
     int64_t trials;   /* trial points evaluated, total */
     int64_t accepts;  /* trial points accepted, total */
     int64_t cap_hits; /* reduction steps that hit the trial cap */
+    /* stopping-rule bookkeeping */
+    int32_t stop_reason; /* ORC_STOP_*: 0 while running */
+    int32_t dp_run;      /* consecutive iterations with Delta P < Delta P* */
+    int32_t feas_ok;     /* the proximity rules held at the last iteration */
+    int32_t pad_;
+    double p_last;       /* proximity recorded at the last iteration (NaN before the first) */
+    double f_last;       /* f(x^k) of the last iteration's phase */
+    double var_n, var_mean, var_m2; /* running count, mean and squared deviations of omega */
 } orc_state;
+
+#define ORC_STOP_PROX 1    /* P <= P* */
+#define ORC_STOP_DPROX 2   /* Delta P < Delta P* for N consecutive iterations */
+#define ORC_STOP_MAXIT 3   /* N_max iterations */
+#define ORC_STOP_VAR 4     /* variance of the relative iterate changes below its threshold */
+#define ORC_STOP_SM 5      /* a proximity rule and Delta f < Delta f* (superiorized runs) */
 
 static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -329,24 +352,99 @@ void orc_gradient(const orc_problem *P, const double *x, double *g)
  * Per-iteration records (each may be NULL): proximity at the point T acts on,
  * objective at x^k, objective after the phase, trials and accepted trials.
  */
+/*
+ * Stopping rules, checked when P->stop_on (Section 2.2: P <= P*, or the
+ * relative proximity change |P^{k+1} - P^k| / max{1, P^k} below Delta P* for
+ * N consecutive iterations, or N_max iterations; Section 2.2.1: a superiorized
+ * run stops when one of the two proximity rules holds and the relative change
+ * of the objective |f^{k+1} - f^k| / max{1, f^k}, f^k = f(x^k), is below
+ * Delta f*; Section 2.3.2: the variance of omega_i = ||x^i - x^{i-1}|| /
+ * ||x^i||, i = 1..k, below a threshold).  P^k is the proximity recorded for
+ * iteration k.  A superiorized run learns f(x^{k+1}) when its next phase
+ * opens, so its rule is checked there, before that iteration perturbs.
+ * omega_i = 0 when x^i = 0.  A stopped run does nothing more.
+ */
+static int stop_after_step(const orc_problem *P, orc_state *st, int sm, double prox, double f_start,
+                           const double *x_prev, const double *x)
+{
+    if (st->stop_reason) return 1;
+    if (!isnan(st->p_last)) {
+        const double dp = fabs(prox - st->p_last) / fmax(1.0, st->p_last);
+        st->dp_run = dp < P->stop_dprox ? st->dp_run + 1 : 0;
+    }
+    st->p_last = prox;
+    const int by_prox = prox <= P->stop_prox, by_dprox = st->dp_run >= P->stop_n;
+    if (sm) {
+        st->feas_ok = by_prox || by_dprox;
+        st->f_last = f_start;
+    } else if (by_prox) {
+        st->stop_reason = ORC_STOP_PROX;
+    } else if (by_dprox) {
+        st->stop_reason = ORC_STOP_DPROX;
+    }
+    if (!st->stop_reason && P->stop_max > 0 && st->k >= P->stop_max) st->stop_reason = ORC_STOP_MAXIT;
+    if (P->stop_var > 0.0) {
+        double dd = 0.0, xx = 0.0;
+        for (int64_t j = 0; j < P->n; ++j) {
+            dd += (x[j] - x_prev[j]) * (x[j] - x_prev[j]);
+            xx += x[j] * x[j];
+        }
+        const double om = xx > 0.0 ? sqrt(dd) / sqrt(xx) : 0.0;
+        /* running mean and sum of squared deviations (Welford) */
+        st->var_n += 1.0;
+        const double delta = om - st->var_mean;
+        st->var_mean += delta / st->var_n;
+        st->var_m2 += delta * (om - st->var_mean);
+        if (!st->stop_reason && st->var_n >= 2.0 && st->var_m2 / (st->var_n - 1.0) < P->stop_var)
+            st->stop_reason = ORC_STOP_VAR;
+    }
+    return st->stop_reason != 0;
+}
+
+/* A fresh stopping-rule state. */
+void orc_stop_reset(orc_state *st)
+{
+    st->stop_reason = 0;
+    st->dp_run = 0;
+    st->feas_ok = 0;
+    st->p_last = NAN;
+    st->f_last = NAN;
+    st->var_n = st->var_mean = st->var_m2 = 0.0;
+}
+
 int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_state *st, double *hist_prox,
             double *hist_f_start, double *hist_f_end, int32_t *hist_trials, int32_t *hist_accepts)
 {
     const int64_t m = P->m, n = P->n;
     double *q = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m), *c = malloc(sizeof(double) * m),
            *y = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n), *v = malloc(sizeof(double) * n),
-           *z = malloc(sizeof(double) * n), *zc = malloc(sizeof(double) * n);
-    if (!q || !r || !c || !y || !g || !v || !z || !zc) {
-        free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc);
+           *z = malloc(sizeof(double) * n), *zc = malloc(sizeof(double) * n), *xp = malloc(sizeof(double) * n);
+    if (!q || !r || !c || !y || !g || !v || !z || !zc || !xp) {
+        free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc); free(xp);
         return -2;
     }
     orc_row_sqnorms(P, q);
     drop_factors(P, zc);
+    const int sm = perturb && P->obj != ORC_OBJ_NONE;
     for (int64_t it = 0; it < K; ++it) {
+        if (hist_prox) hist_prox[it] = NAN;
+        if (hist_f_start) hist_f_start[it] = NAN;
+        if (hist_f_end) hist_f_end[it] = NAN;
+        if (hist_trials) hist_trials[it] = 0;
+        if (hist_accepts) hist_accepts[it] = 0;
+        if (P->stop_on && st->stop_reason) continue;
         const int64_t k = st->k;
         int32_t trials = 0, accepts = 0;
         double f_start = NAN, f_end = NAN;
-        if (perturb && P->obj != ORC_OBJ_NONE) {
+        memcpy(xp, x, sizeof(double) * n);
+        if (sm) {
+            f_start = f_end = orc_objective(P, x);
+            if (P->stop_on && st->feas_ok && !isnan(st->f_last) &&
+                fabs(f_start - st->f_last) / fmax(1.0, st->f_last) < P->stop_dobj) {
+                st->stop_reason = ORC_STOP_SM; /* this iteration does not run */
+                if (hist_f_start) hist_f_start[it] = NAN;
+                continue;
+            }
             if (P->restart_every > 0 && k > 0 && k % P->restart_every == 0) {
                 st->restarts += 1;
                 st->ell = st->restarts;
@@ -355,7 +453,6 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
             double gg = 0.0;
             for (int64_t j = 0; j < n; ++j) gg += g[j] * g[j];
             double gn = sqrt(gg);
-            f_start = f_end = orc_objective(P, x);
             if (gn > 0.0) {
                 for (int64_t j = 0; j < n; ++j) v[j] = -g[j] / gn;
                 double f_cur = f_start;
@@ -394,8 +491,9 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
         st->trials += trials;
         st->accepts += accepts;
         st->k += 1;
+        if (P->stop_on) stop_after_step(P, st, sm, prox, f_start, xp, x);
     }
-    free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc);
+    free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc); free(xp);
     return 0;
 }
 

@@ -577,3 +577,71 @@ def test_drop_counts_nonzeros_before_rounding(orc):
     P = _dense_problem(orc, A, b, b, basic=W.BASIC_DROP, col_nnz=np.array([1.0, 1.0, 1.0]))
     Tx, _ = P.step(np.zeros(3))
     np.testing.assert_allclose(Tx, [1.3, 0.5, 0.4], rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Stopping rules (Section 2.2; superiorized rule of Section 2.2.1; variance
+# rule of Section 2.3.2)
+# ---------------------------------------------------------------------------
+
+NEVER = dict(prox=-1.0, dprox=-1.0, n=5, max_iters=0, dobj=-1.0, var=0.0)
+
+
+def test_stop_on_proximity_threshold(orc):
+    """One band, lambda = 1: x^1 is its projection, so P(x^1) = 0 <= P* and the
+    run stops after iteration 1 (k = 2) however large K is."""
+    P = _single_row(orc, [3.0, 4.0], -np.inf, 0.0, stop=dict(NEVER, prox=1e-12))
+    x, st, h = P.run(np.array([3.0, 4.0]), 50, perturb=False)
+    assert st.k == 2 and st.stop_reason == orc.STOP_PROX
+    assert h.prox[0] == pytest.approx(12.5) and h.prox[1] <= 1e-24
+    assert np.all(np.isnan(h.prox[2:]))
+
+
+def test_stop_on_stalled_proximity(orc):
+    """Two contradictory bands on one unknown (x >= 1, x <= 0) from x = 1/2:
+    the simultaneous step is 0, P stays 1/8, Delta P = 0 from iteration 1 on,
+    so N = 5 consecutive small changes end the run at k = 6."""
+    P = _dense_problem(orc, [[1.0], [1.0]], [1.0, -np.inf], [np.inf, 0.0], stop=dict(NEVER, dprox=1e-8, n=5))
+    x, st, h = P.run(np.array([0.5]), 40, perturb=False)
+    assert st.k == 6 and st.stop_reason == orc.STOP_DPROX
+    np.testing.assert_allclose(h.prox[:6], 0.125, rtol=1e-15)
+
+
+def test_stop_on_iteration_cap(orc):
+    P = _dense_problem(orc, [[1.0], [1.0]], [1.0, -np.inf], [np.inf, 0.0], stop=dict(NEVER, max_iters=7))
+    x, st, h = P.run(np.array([0.5]), 40, perturb=False)
+    assert st.k == 7 and st.stop_reason == orc.STOP_MAXIT
+
+
+def test_stop_on_iterate_variance(orc):
+    """x^k = b (1 - 2^-k) for one equality band with lambda = 1/2 from 0, so
+    omega_k = 2^-k / (1 - 2^-k); the run stops at the first k whose sample
+    variance of omega_1..omega_k is below the threshold."""
+    b, thr = 3.0, 0.05
+    P = _single_row(orc, [1.0], b, b, lam=0.5, stop=dict(NEVER, var=thr))
+    x, st, h = P.run(np.array([0.0]), 100, perturb=False)
+    k = np.arange(1, 101)
+    om = 0.5 ** k / (1.0 - 0.5 ** k)
+    want = next(kk for kk in range(2, 101) if np.var(om[:kk], ddof=1) < thr)
+    assert st.stop_reason == orc.STOP_VAR and st.k == want
+
+
+def test_stop_superiorized_needs_objective_change(orc):
+    """f = x^2 on the band [1, 2] from x = 1.5, gamma = 1, alpha = 0.9, one trial
+    per phase (always accepted): x^k = 1 for k >= 1, the recorded proximity is
+    P^0 = 1/8, P^k = 0.81^k / 2, and f^k = 1.  With Delta P* = 1e-3, N = 3 the
+    proximity rule first holds after N consecutive iterations with
+    0.095 * 0.81^(k-1) < 1e-3; the next phase sees Delta f = 0 and stops."""
+    P = _single_row(orc, [1.0], 1.0, 2.0, obj=W.OBJ_SQNORM, gamma=1.0, alpha=0.9, n_red=1,
+                    stop=dict(NEVER, dprox=1e-3, n=3, dobj=1e-6))
+    x, st, h = P.run(np.array([1.5]), 200, perturb=True)
+    pk = [0.125] + [0.5 * 0.81 ** k for k in range(1, 200)]
+    run, k_feas = 0, None
+    for k in range(1, 200):
+        run = run + 1 if abs(pk[k] - pk[k - 1]) / max(1.0, pk[k - 1]) < 1e-3 else 0
+        if run >= 3:
+            k_feas = k
+            break
+    # iteration k_feas completes (k = k_feas + 1); the next one stops at its phase
+    assert st.stop_reason == orc.STOP_SM and st.k == k_feas + 1
+    np.testing.assert_allclose(h.prox[:st.k], pk[:st.k], rtol=1e-12)

@@ -60,6 +60,7 @@ class Workload:
     K: int = 100
     weights: Optional[np.ndarray] = None  # float64 [m]; None means uniform 1/m
     basic: int = 0  # BASIC_*: the feasibility-seeking step
+    stop: Optional[dict] = None  # stopping rules: prox, dprox, n, max_iters, dobj, var (None: fixed K)
     x_true: Optional[np.ndarray] = None  # float32 [n, B]
     meta: dict = field(default_factory=dict)
 
