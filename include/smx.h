@@ -125,6 +125,24 @@ typedef struct {
     int32_t history_cap;     /* per-iteration records kept (0: none) */
     int32_t on_device;       /* 0: the arrays above are host pointers, 1: device */
     int32_t basic;           /* SMX_BASIC_*; SMX_BASIC_SIMULT (0) is the default */
+    /* Stopping rules, checked on the device after every iteration (a stopped
+     * slice stays idle; smx_run still returns after its K iterations).
+     * Section 2.2: the proximity P of the iteration <= stop_prox, or the
+     * relative change |P^{k+1} - P^k| / max{1, P^k} < stop_dprox for stop_n
+     * consecutive iterations, or stop_max_iters iterations (0: none).  A
+     * perturbed run with an objective (Section 2.2.1) stops instead when one
+     * of the two proximity rules held at the last iteration and the objective
+     * change |f(x^{k+1}) - f(x^k)| / max{1, f(x^k)} < stop_dobj; it is checked
+     * when the next perturbation phase opens.  stop_var > 0 adds the rule of
+     * Section 2.3.2: the sample variance of omega_i = ||x^i - x^{i-1}|| /
+     * ||x^i|| over the run falls below stop_var. */
+    int32_t stop_on;         /* 0: no stopping rule */
+    int32_t stop_n;          /* N >= 1 */
+    int64_t stop_max_iters;  /* >= 0 */
+    double stop_prox;        /* P* */
+    double stop_dprox;       /* Delta P* */
+    double stop_dobj;        /* Delta f* */
+    double stop_var;         /* >= 0; 0 disables the variance rule */
 } smx_problem_desc;
 
 /* Per-slice iteration state, as checkpointed by smx_get_state. */
@@ -135,7 +153,25 @@ typedef struct {
     int64_t trials;   /* trial points evaluated, total */
     int64_t accepts;  /* trial points accepted, total */
     int64_t cap_hits; /* reduction steps that reached max_trials */
+    /* stopping-rule bookkeeping (restored by smx_set_state, so a resumed run
+     * stops where an uninterrupted one would) */
+    int32_t stop_reason; /* SMX_STOP_*; 0 while the slice runs */
+    int32_t dp_run;      /* consecutive iterations with a small proximity change */
+    int32_t feas_ok;     /* a proximity rule held at the last iteration */
+    int32_t reserved;
+    double p_last;       /* proximity recorded at the last iteration (NaN before the first) */
+    double f_last;       /* f(x^k) of the last perturbation phase (NaN if none) */
+    double var_n, var_mean, var_m2; /* running count, mean and squared deviations of
+                                       the relative iterate changes */
 } smx_slice_state;
+
+/* why a slice stopped (smx_stop_status) */
+#define SMX_STOP_NONE 0
+#define SMX_STOP_PROX 1  /* proximity <= stop_prox */
+#define SMX_STOP_DPROX 2 /* relative proximity change < stop_dprox for stop_n iterations */
+#define SMX_STOP_MAXIT 3 /* stop_max_iters iterations */
+#define SMX_STOP_VAR 4   /* variance of the relative iterate changes < stop_var */
+#define SMX_STOP_SM 5    /* superiorized: a proximity rule and objective change < stop_dobj */
 
 /* Library version.  Both pointers must be non-NULL. */
 int smx_version(int *major, int *minor);
@@ -292,6 +328,10 @@ int smx_set_fused(smx_problem *p, int32_t mode);
  * SMX_ESTATE when the problem has no fused pass, SMX_EINVAL for another
  * shape. */
 int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap);
+
+/* Why each slice stopped (reason[B], SMX_STOP_*; 0 while it runs).
+ * Synchronises. */
+int smx_stop_status(smx_problem *p, int32_t *reason);
 
 /* JSON description of the launch shapes in use (NUL-terminated, truncated to
  * cap bytes); *need (if non-NULL) receives the full size. */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsmx.so")
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
+STOP_NONE, STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 0, 1, 2, 3, 4, 5
 RUN_PERTURB, RUN_GRAPH = 1, 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
@@ -51,6 +52,7 @@ EXPORTS = [
     "smx_describe",
     "smx_set_fused",
     "smx_set_fused_shape",
+    "smx_stop_status",
     "smx_slot_load",
     "smx_slot_disable",
     "smx_slot_status",
@@ -99,6 +101,13 @@ class ProblemDesc(C.Structure):
         ("history_cap", C.c_int32),
         ("on_device", C.c_int32),
         ("basic", C.c_int32),
+        ("stop_on", C.c_int32),
+        ("stop_n", C.c_int32),
+        ("stop_max_iters", C.c_int64),
+        ("stop_prox", C.c_double),
+        ("stop_dprox", C.c_double),
+        ("stop_dobj", C.c_double),
+        ("stop_var", C.c_double),
     ]
 
 
@@ -110,10 +119,29 @@ class SliceStateC(C.Structure):
         ("trials", C.c_int64),
         ("accepts", C.c_int64),
         ("cap_hits", C.c_int64),
+        ("stop_reason", C.c_int32),
+        ("dp_run", C.c_int32),
+        ("feas_ok", C.c_int32),
+        ("reserved", C.c_int32),
+        ("p_last", C.c_double),
+        ("f_last", C.c_double),
+        ("var_n", C.c_double),
+        ("var_mean", C.c_double),
+        ("var_m2", C.c_double),
     ]
 
+    def __init__(self):
+        super().__init__()
+        self.p_last = float("nan")
+        self.f_last = float("nan")
+
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        """Fields as Python numbers (NaN as None, so equal states compare equal)."""
+        out = {}
+        for f, t in self._fields_:
+            v = getattr(self, f)
+            out[f] = (None if v != v else float(v)) if t is C.c_double else int(v)
+        return out
 
 
 _lib = None
@@ -156,6 +184,7 @@ def lib() -> C.CDLL:
     L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.smx_set_fused.argtypes = [vp, i32]
     L.smx_set_fused_shape.argtypes = [vp, i32, i32, i32]
+    L.smx_stop_status.argtypes = [vp, vp]
     for name in EXPORTS:
         if name != "smx_last_error":
             getattr(L, name).restype = C.c_int
@@ -240,7 +269,7 @@ class Problem:
     def __init__(self, op: Operator, lower, upper, box_lo=None, box_hi=None, weights=None, lam=1.0,
                  obj=OBJ_NONE, tv_rows=0, tv_cols=0, tv_eps=0.0, linear_c=None, gamma=1.0, alpha=0.99,
                  n_red=1, restart_every=0, max_trials=100, refine_iters=-1, history_cap=0, B=None,
-                 device="cuda", stream=None, basic=0):
+                 device="cuda", stream=None, basic=0, stop=None):
         import torch
 
         self.op = op
@@ -263,6 +292,14 @@ class Problem:
             restart_every=int(restart_every), max_trials=int(max_trials), refine_iters=int(refine_iters),
             history_cap=int(history_cap), on_device=1, basic=int(basic),
         )
+        if stop is not None:  # stopping rules: prox, dprox, n, max_iters, dobj, var
+            d.stop_on = 1
+            d.stop_n = int(stop.get("n", 5))
+            d.stop_max_iters = int(stop.get("max_iters", 0))
+            d.stop_prox = float(stop.get("prox", 1e-6))
+            d.stop_dprox = float(stop.get("dprox", 1e-8))
+            d.stop_dobj = float(stop.get("dobj", 1e-6))
+            d.stop_var = float(stop.get("var", 0.0))
         self.history_cap = int(history_cap)
         self.obj = int(obj)
         h = C.c_void_p()
@@ -327,8 +364,10 @@ class Problem:
     def set_state(self, states, x):
         st = (SliceStateC * self.B)()
         for i, s in enumerate(states):
+            st[i].p_last = st[i].f_last = float("nan")
             for k, v in s.items():
-                setattr(st[i], k, int(v))
+                t = dict(SliceStateC._fields_)[k]
+                setattr(st[i], k, (float("nan") if v is None else float(v)) if t is C.c_double else int(v))
         xx = np.ascontiguousarray(np.asarray(x, np.float32).reshape(-1))
         check(lib().smx_set_state(self.handle, C.cast(st, C.c_void_p), xx.ctypes.data))
 
@@ -390,6 +429,12 @@ class Problem:
         or always the two bitwise-reproducible passes (off)."""
         check(lib().smx_set_fused(self.handle, 1 if on else 0))
 
+    def stop_status(self) -> np.ndarray:
+        """Why each slice stopped (STOP_*; 0 while it runs)."""
+        r = np.zeros(self.B, np.int32)
+        check(lib().smx_stop_status(self.handle, r.ctypes.data))
+        return r
+
     def set_fused_shape(self, lpr: int, vec: int, cap: int):
         """Pin the fused pass's launch shape (see smx_set_fused_shape)."""
         check(lib().smx_set_fused_shape(self.handle, int(lpr), int(vec), int(cap)))
@@ -429,7 +474,7 @@ def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device=
         lower=w.lower, upper=w.upper, box_lo=w.box_lo, box_hi=w.box_hi, weights=w.weights, lam=w.lam, obj=w.obj,
         tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
         n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
-        refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0),
+        refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0), stop=getattr(w, "stop", None),
     )
     kw.update(overrides)
     p = Problem(op, device=device, **kw)

@@ -232,6 +232,8 @@ struct smx_problem {
     DBuf ybuf;     // EL / EMR: y = A^T c kept for the extrapolated step, float64 [n*B]
     DBuf ybuf32;   // EMR: y rounded to float32, the vector its second product gathers [n*B]
     DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
+    bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
+    DBuf xprev, part_var;
     RowW row_weights(int vk) const
     {
         const float *D = (vk == VK_F32) ? D32.as<float>() : D16.as<float>();
@@ -469,7 +471,7 @@ int vk_for_iteration(const smx_problem *p, int64_t it, int64_t K, int64_t ref)
 
 // Enqueue one outer iteration with value kind vk on stream s, starting from
 // state buffer `cur`; returns the buffer current after it.
-int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
+int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
 {
     const float *gvec = (p->pp.obj == OBJ_LINEAR) ? p->lin_c.as<float>() : p->g.as<float>();
     if (perturb && p->pp.obj != OBJ_NONE) {
@@ -549,6 +551,22 @@ int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool 
                   "extrapolated step");
     }
     cur ^= 1;
+    return cur;
+}
+
+// One outer iteration; with the variance stopping rule, x is kept at the
+// iteration's start and the rule is applied after it.
+int enqueue_iteration(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
+{
+    if (p->stop_var) hip_check(launch_copy(p->xprev.as<float>(), p->x.as<float>(), p->n * p->B, s), "keep iterate");
+    cur = enqueue_iteration_core(p, s, vk, perturb, timed, cur);
+    if (p->stop_var) {
+        int np = 0;
+        hip_check(launch_iter_norms(p->x.as<float>(), p->xprev.as<float>(), p->n, p->B, p->part_var.as<double>(), &np,
+                                    s),
+                  "iterate change");
+        hip_check(launch_stop_var(p->state(cur), p->B, p->part_var.as<double>(), np, s), "variance rule");
+    }
     return cur;
 }
 
@@ -736,6 +754,16 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     if (d->obj_kind == SMX_OBJ_LINEAR && !d->linear_c) return fail(SMX_EINVAL, "LINEAR objective needs linear_c");
     if (!d->lower || !d->upper) return fail(SMX_EINVAL, "lower and upper bounds are required");
     if (d->history_cap < 0) return fail(SMX_EINVAL, "history_cap must be >= 0");
+    StopParams sp{};
+    if (d->stop_on) {
+        if (d->stop_n < 1) return fail(SMX_EINVAL, "stop_n must be >= 1 (got %d)", d->stop_n);
+        if (d->stop_max_iters < 0) return fail(SMX_EINVAL, "stop_max_iters must be >= 0");
+        if (std::isnan(d->stop_prox) || std::isnan(d->stop_dprox) || std::isnan(d->stop_dobj) ||
+            !(d->stop_var >= 0.0) || !std::isfinite(d->stop_var))
+            return fail(SMX_EINVAL, "invalid stopping thresholds");
+        sp = StopParams{1, d->stop_n, (long long)d->stop_max_iters, d->stop_prox, d->stop_dprox, d->stop_dobj,
+                        d->stop_var};
+    }
     const bool dev = d->on_device != 0;
     std::vector<float> lo = fetch(d->lower, m * B, dev), up = fetch(d->upper, m * B, dev);
     for (int64_t i = 0; i < m * B; ++i) {
@@ -804,8 +832,13 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     p->g.alloc(sizeof(float) * n * B, "gradient");
     p->c.alloc(sizeof(float) * m * B, "weighted residual");
     p->st.alloc(sizeof(SliceState) * 2 * B, "state");
-    hip_check(launch_init_state(p->state(0), B, s), "init state");
-    hip_check(launch_init_state(p->state(1), B, s), "init state");
+    hip_check(launch_init_state(p->state(0), B, sp, s), "init state");
+    hip_check(launch_init_state(p->state(1), B, sp, s), "init state");
+    p->stop_var = sp.on && sp.var > 0.0;
+    if (p->stop_var) {
+        p->xprev.alloc(sizeof(float) * n * B, "previous iterate");
+        p->part_var.alloc(sizeof(double) * 2 * 256 * B, "variance partials");
+    }
     p->cur = 0;
     const int lp = op->lp_kind();
     if (op->has_f32) {
@@ -934,8 +967,8 @@ int autotune_impl(smx_problem *p, int reps)
     sts.alloc(sizeof(SliceState) * 2 * p->B, "tuning scratch");
     hip_check(hipMemcpyAsync(xs.p, p->x.p, sizeof(float) * n * p->B, hipMemcpyDeviceToDevice, s), "tuning copy");
     SliceState *st0 = sts.as<SliceState>(), *st1 = st0 + p->B;
-    hip_check(launch_init_state(st0, p->B, s), "tuning state");
-    hip_check(launch_init_state(st1, p->B, s), "tuning state");
+    hip_check(launch_init_state(st0, p->B, StopParams{}, s), "tuning state");
+    hip_check(launch_init_state(st1, p->B, StopParams{}, s), "tuning state");
     Hist none{};
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
@@ -1314,6 +1347,15 @@ int smx_get_state(smx_problem *p, smx_slice_state *states, float *x)
                 states[s].trials = st[s].trials;
                 states[s].accepts = st[s].accepts;
                 states[s].cap_hits = st[s].cap_hits;
+                states[s].stop_reason = st[s].stop_reason;
+                states[s].dp_run = st[s].dp_run;
+                states[s].feas_ok = st[s].feas_ok;
+                states[s].reserved = 0;
+                states[s].p_last = st[s].p_last;
+                states[s].f_last = st[s].f_last;
+                states[s].var_n = st[s].var_n;
+                states[s].var_mean = st[s].var_mean;
+                states[s].var_m2 = st[s].var_m2;
             }
         if (x) hip_check(hipMemcpy(x, p->x.p, sizeof(float) * p->n * p->B, hipMemcpyDeviceToHost), "read x");
         return SMX_OK;
@@ -1327,8 +1369,9 @@ int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x)
         hip_check(hipStreamSynchronize(p->stream), "state");
         if (states) {
             for (int s = 0; s < p->B; ++s)
-                if (states[s].k < 0 || states[s].ell < 0 || states[s].restarts < 0)
-                    return fail(SMX_EINVAL, "negative counter in state of slice %d", s);
+                if (states[s].k < 0 || states[s].ell < 0 || states[s].restarts < 0 || states[s].dp_run < 0 ||
+                    states[s].stop_reason < SMX_STOP_NONE || states[s].stop_reason > SMX_STOP_SM)
+                    return fail(SMX_EINVAL, "invalid counter in state of slice %d", s);
             std::vector<SliceState> st(p->B);
             hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost), "read state");
             for (int s = 0; s < p->B; ++s) {
@@ -1338,8 +1381,16 @@ int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x)
                 st[s].trials = states[s].trials;
                 st[s].accepts = states[s].accepts;
                 st[s].cap_hits = states[s].cap_hits;
+                st[s].stop_reason = states[s].stop_reason;
+                st[s].dp_run = states[s].dp_run;
+                st[s].feas_ok = states[s].feas_ok;
+                st[s].p_last = states[s].p_last;
+                st[s].f_last = states[s].f_last;
+                st[s].var_n = states[s].var_n;
+                st[s].var_mean = states[s].var_mean;
+                st[s].var_m2 = states[s].var_m2;
                 st[s].phase = 0;
-                st[s].live = (st[s].enabled && st[s].k < st[s].k_end) ? 1 : 0;
+                st[s].live = (st[s].enabled && st[s].k < st[s].k_end && st[s].stop_reason == STOP_NONE) ? 1 : 0;
             }
             hip_check(hipMemcpy(p->state(p->cur), st.data(), sizeof(SliceState) * p->B, hipMemcpyHostToDevice), "write state");
         }
@@ -1478,6 +1529,19 @@ int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap)
         hip_check(hipStreamSynchronize(p->stream), "sync");
         for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
         p->graphs.clear();
+        return SMX_OK;
+    })
+}
+
+int smx_stop_status(smx_problem *p, int32_t *reason)
+{
+    if (!p || !reason) return fail(SMX_EINVAL, "NULL argument");
+    SMX_GUARD({
+        hip_check(hipStreamSynchronize(p->stream), "state");
+        std::vector<SliceState> st(p->B);
+        hip_check(hipMemcpy(st.data(), p->state(p->cur), sizeof(SliceState) * p->B, hipMemcpyDeviceToHost),
+                  "read state");
+        for (int s = 0; s < p->B; ++s) reason[s] = st[s].stop_reason;
         return SMX_OK;
     })
 }

@@ -475,6 +475,37 @@ __device__ inline double nan64() { return __longlong_as_double(0x7ff800000000000
 // never reads a state another workgroup of the same grid is writing.
 // ---------------------------------------------------------------------------
 
+// Whether a slice runs its next iteration.
+__device__ inline int slice_runs(const SliceState &S)
+{
+    return (S.enabled && S.k < S.k_end && S.stop_reason == STOP_NONE) ? 1 : 0;
+}
+
+// Stopping rules after a feasibility step that recorded proximity `prox`
+// (Section 2.2: P <= P*, or |P^{k+1} - P^k| / max{1, P^k} < Delta P* for N
+// consecutive iterations, or N_max iterations).  A superiorized run (a phase
+// ran, so f_start = f(x^k) is set) only notes whether a proximity rule held;
+// its objective condition is checked when the next phase opens.  The variance
+// rule follows in k_stop_var.
+__device__ inline void stop_rules_after_step(SliceState &S, double prox)
+{
+    if (!isnan(S.p_last)) {
+        const double dp = fabs(prox - S.p_last) / fmax(1.0, S.p_last);
+        S.dp_run = dp < S.stop_dprox ? S.dp_run + 1 : 0;
+    }
+    S.p_last = prox;
+    const bool by_prox = prox <= S.stop_prox, by_dprox = S.dp_run >= S.stop_n;
+    if (!isnan(S.f_start)) {
+        S.feas_ok = (by_prox || by_dprox) ? 1 : 0;
+        S.f_last = S.f_start;
+    } else if (by_prox) {
+        S.stop_reason = STOP_PROX;
+    } else if (by_dprox) {
+        S.stop_reason = STOP_DPROX;
+    }
+    if (S.stop_reason == STOP_NONE && S.stop_max > 0 && S.k >= S.stop_max) S.stop_reason = STOP_MAXIT;
+}
+
 // End of an outer iteration: proximity from pass 1's partials, the history
 // record, k + 1, and whether the next iteration runs.  Called by every thread
 // of one workgroup.
@@ -486,6 +517,7 @@ __device__ inline void finish_iteration(const SliceState *__restrict__ st_in, Sl
         sum_slots<1>(part1, (long long)s * nparts, nparts, tot, lds);
         if (threadIdx.x == 0) {
             SliceState S = st_in[s];
+            S.ran = S.live;
             if (S.live) {
                 const double prox = 0.5 * tot[0];
                 S.prox = prox;
@@ -499,12 +531,13 @@ __device__ inline void finish_iteration(const SliceState *__restrict__ st_in, Sl
                     h.accepts[r] = S.accepts_it;
                 }
                 S.k += 1;
+                if (S.stop_on) stop_rules_after_step(S, prox);
             }
             S.f_start = S.f_cur = nan64();
             S.trials_it = 0;
             S.accepts_it = 0;
             S.phase = 0;
-            S.live = (S.enabled && S.k < S.k_end) ? 1 : 0;
+            S.live = slice_runs(S);
             st_out[s] = S;
         }
     }
@@ -1190,6 +1223,15 @@ __device__ inline void open_phase_state(SliceState &S, const PertParams &pp, dou
         S.f_start = S.f_cur = nan64();
         return;
     }
+    // superiorized stopping rule (Section 2.2.1): a proximity rule held at the
+    // last iteration and |f(x^k) - f(x^{k-1})| / max{1, f(x^{k-1})} < Delta f*
+    if (S.stop_on && S.feas_ok && !isnan(S.f_last) && fabs(f - S.f_last) / fmax(1.0, S.f_last) < S.stop_dobj) {
+        S.stop_reason = STOP_SM;
+        S.live = 0;
+        S.phase = 0;
+        S.f_start = S.f_cur = nan64();
+        return;
+    }
     if (pp.restart_every > 0 && S.k > 0 && (S.k % pp.restart_every) == 0) {
         S.restarts += 1;
         S.ell = S.restarts;
@@ -1651,7 +1693,7 @@ __global__ void k_fill(float *__restrict__ p, float v, long long count)
         p[i] = v;
 }
 
-__global__ void k_init_state(SliceState *st, int B)
+__global__ void k_init_state(SliceState *st, int B, StopParams sp)
 {
     const int s = threadIdx.x;
     if (s >= B) return;
@@ -1674,6 +1716,17 @@ __global__ void k_init_state(SliceState *st, int B)
     S.enabled = 1;
     S.nonfinite = 0;
     S.need_last = 0;
+    S.stop_on = sp.on;
+    S.stop_n = sp.n;
+    S.stop_max = sp.max_iters;
+    S.stop_prox = sp.prox;
+    S.stop_dprox = sp.dprox;
+    S.stop_dobj = sp.dobj;
+    S.stop_var = sp.var;
+    S.stop_reason = STOP_NONE;
+    S.dp_run = S.feas_ok = S.ran = 0;
+    S.p_last = S.f_last = __longlong_as_double(0x7ff8000000000000LL);
+    S.var_n = S.var_mean = S.var_m2 = 0.0;
     st[s] = S;
 }
 
@@ -1714,6 +1767,10 @@ __global__ void k_reset_slot(SliceState *st, int s, long long budget)
     S.applied = 0;
     S.nonfinite = 0;
     S.need_last = 0;
+    S.stop_reason = STOP_NONE;
+    S.dp_run = S.feas_ok = S.ran = 0;
+    S.p_last = S.f_last = __longlong_as_double(0x7ff8000000000000LL);
+    S.var_n = S.var_mean = S.var_m2 = 0.0;
     st[s] = S;
 }
 
@@ -1808,9 +1865,9 @@ hipError_t launch_disable_slot(SliceState *st, int slot, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(SliceState *st, int B, hipStream_t s)
+hipError_t launch_init_state(SliceState *st, int B, StopParams sp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, B);
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, B, sp);
     return hipGetLastError();
 }
 
@@ -2165,6 +2222,89 @@ hipError_t launch_eval_objective(SliceState *st, const PertParams &pp, const dou
                                  hipStream_t s)
 {
     hipLaunchKernelGGL(k_eval_objective, dim3(1), dim3(kBlock), 0, s, st, pp, partials, phase_grid(pp), out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Variance stopping rule (Section 2.3.2): omega_k = ||x^k - x^{k-1}|| / ||x^k||
+// (0 when x^k = 0); the run stops once the sample variance of omega_1 ..
+// omega_k (k >= 2) is below the threshold.  Running mean and sum of squared
+// deviations (Welford), in float64, per slice.
+// ---------------------------------------------------------------------------
+
+__global__ void k_copy(float *__restrict__ dst, const float *__restrict__ src, long long count)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Per-workgroup partials of ||x - xprev||^2 and ||x||^2 for every slice:
+// partials[(s * grid + block) * 2 + {0, 1}].
+__global__ __launch_bounds__(kBlock) void k_iter_norms(const float *__restrict__ x, const float *__restrict__ xprev,
+                                                       long long n, int B, double *__restrict__ partials)
+{
+    __shared__ double lds[4 * 2];
+    for (int s = 0; s < B; ++s) {
+        double v[2] = {0.0, 0.0};
+        for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < n; j += (long long)gridDim.x * kBlock) {
+            const double a = (double)x[j * B + s], b = (double)xprev[j * B + s];
+            v[0] += (a - b) * (a - b);
+            v[1] += a * a;
+        }
+        block_sum<2>(v, lds);
+        if (threadIdx.x == 0) {
+            partials[((long long)s * gridDim.x + blockIdx.x) * 2 + 0] = v[0];
+            partials[((long long)s * gridDim.x + blockIdx.x) * 2 + 1] = v[1];
+        }
+    }
+}
+
+// One workgroup: updates the statistics of the slices that ran the iteration
+// just ended and stops those whose variance fell below the threshold (a
+// reason already set by the proximity rules takes precedence).  In place on
+// the current state buffer (no other workgroup touches it in this launch).
+__global__ __launch_bounds__(kBlock) void k_stop_var(SliceState *__restrict__ st, int B,
+                                                     const double *__restrict__ partials, int nparts)
+{
+    __shared__ double lds[4 * 2];
+    for (int s = 0; s < B; ++s) {
+        double tot[2];
+        sum_slots<2>(partials, (long long)s * nparts, nparts, tot, lds);
+        if (threadIdx.x == 0) {
+            SliceState S = st[s];
+            if (S.ran && S.stop_on && S.stop_var > 0.0) {
+                const double om = tot[1] > 0.0 ? sqrt(tot[0]) / sqrt(tot[1]) : 0.0;
+                S.var_n += 1.0;
+                const double delta = om - S.var_mean;
+                S.var_mean += delta / S.var_n;
+                S.var_m2 += delta * (om - S.var_mean);
+                if (S.stop_reason == STOP_NONE && S.var_n >= 2.0 && S.var_m2 / (S.var_n - 1.0) < S.stop_var)
+                    S.stop_reason = STOP_VAR;
+                S.live = slice_runs(S);
+                st[s] = S;
+            }
+        }
+    }
+}
+
+hipError_t launch_copy(float *dst, const float *src, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(count, kBlock, 4096)), dim3(kBlock), 0, s, dst, src, (long long)count);
+    return hipGetLastError();
+}
+
+hipError_t launch_iter_norms(const float *x, const float *xprev, int64_t n, int B, double *partials, int *nparts,
+                             hipStream_t s)
+{
+    const unsigned grid = grid_for(n, kBlock, 256);
+    *nparts = (int)grid;
+    hipLaunchKernelGGL(k_iter_norms, dim3(grid), dim3(kBlock), 0, s, x, xprev, (long long)n, B, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_stop_var(SliceState *st, int B, const double *partials, int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stop_var, dim3(1), dim3(kBlock), 0, s, st, B, partials, nparts);
     return hipGetLastError();
 }
 

@@ -59,6 +59,24 @@ struct SliceState {
     int enabled;    // slice participates at all
     int nonfinite;  // a non-finite proximity or objective was seen
     int need_last;  // trials the last completed reduction step used (sizes the next first batch)
+    // stopping rules (stop_on = 0: run the iterations asked for)
+    int stop_on, stop_n, stop_reason; // reason: STOP_* once stopped (the slice then stays idle)
+    int dp_run;                       // consecutive iterations with a small proximity change
+    int feas_ok;                      // a proximity rule held at the last iteration (superiorized runs)
+    int ran;                          // the slice ran the iteration that just ended
+    long long stop_max;               // iteration cap (0: none)
+    double stop_prox, stop_dprox, stop_dobj, stop_var;
+    double p_last, f_last;            // last recorded proximity; f(x^k) of the last phase
+    double var_n, var_mean, var_m2;   // running statistics of the relative iterate changes
+};
+
+enum StopReason : int { STOP_NONE = 0, STOP_PROX = 1, STOP_DPROX = 2, STOP_MAXIT = 3, STOP_VAR = 4, STOP_SM = 5 };
+
+// Stopping-rule parameters given at problem creation.
+struct StopParams {
+    int on, n;
+    long long max_iters;
+    double prox, dprox, dobj, var;
 };
 
 struct PertParams {
@@ -140,7 +158,14 @@ hipError_t launch_make_D(const double *q, const double *w, float *D, int64_t m, 
 hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
 hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float scale, hipStream_t s);
 hipError_t launch_pack16(const uint16_t *val16, const int32_t *idx, uint32_t *packed, int64_t count, hipStream_t s);
-hipError_t launch_init_state(SliceState *st, int B, hipStream_t s);
+hipError_t launch_init_state(SliceState *st, int B, StopParams sp, hipStream_t s);
+// the variance rule: xprev = x at the start of an iteration; after it,
+// per-workgroup partials of ||x - xprev||^2 and ||x||^2 (norms) and, in one
+// workgroup, the running variance of their ratio and the stop decision
+hipError_t launch_copy(float *dst, const float *src, int64_t count, hipStream_t s);
+hipError_t launch_iter_norms(const float *x, const float *xprev, int64_t n, int B, double *partials, int *nparts,
+                             hipStream_t s);
+hipError_t launch_stop_var(SliceState *st, int B, const double *partials, int nparts, hipStream_t s);
 hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s);
 // slots of a multi-slice problem (serving)
 hipError_t launch_put_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s);

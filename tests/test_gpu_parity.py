@@ -604,3 +604,132 @@ def test_basic_algorithm_args(smx):
     p = smx.problem_from_workload(w.with_params(basic=W.BASIC_DROP, lam=2.0 * w.m))
     assert p.describe()["basic"] == "drop"
     p.close()
+
+
+# ---------------------------------------------------------------------------
+# stopping rules (device-side, per slice)
+# ---------------------------------------------------------------------------
+
+def _log_mid(a, b):
+    return float(np.sqrt(a * b))
+
+
+def _margin_ok(values, thr, rel=1e-4):
+    v = np.asarray(values, float)
+    v = v[np.isfinite(v) & (v > 0)]
+    return np.all(np.abs(np.log(v / thr)) > rel)
+
+
+def _stop_compare(smx, w, K, perturb=True):
+    """GPU run with w.stop against the oracle's: same iterations, reason, and
+    iterate within the usual tolerance."""
+    P = oracle.from_workload(w)
+    xo, so, ho = P.run(w.x0[:, 0], K, perturb=perturb)
+    p = smx.problem_from_workload(w, history_cap=K, fused=False)
+    p.run(K, perturb=perturb)
+    p.sync()
+    st, x = p.get_state()
+    reason = p.stop_status()
+    p.close()
+    print(f"  oracle k={so.k} reason={so.stop_reason}; gpu k={st[0]['k']} reason={reason[0]}", flush=True)
+    assert so.stop_reason != 0, "the oracle did not stop: pick other thresholds"
+    assert st[0]["k"] == so.k and reason[0] == so.stop_reason
+    assert st[0]["dp_run"] == so.dp_run and st[0]["feas_ok"] == so.feas_ok
+    if not perturb:  # (TV-perturbed iterates: the parity and lockstep tests above)
+        assert rel(x[:, 0], xo) <= max(RTOL, 10 * storage_deviation(w, so.k, perturb)[0])
+    return so
+
+
+def test_stop_proximity_threshold(smx):
+    w = W.ct(N=32, n_angles=24, seed=80, K=60)
+    P = oracle.from_workload(w)
+    _, _, h = P.run(w.x0[:, 0], 40, perturb=False)
+    thr = _log_mid(h.prox[14], h.prox[15])
+    assert _margin_ok(h.prox, thr)
+    say("stop on P*")
+    so = _stop_compare(smx, w.with_params(stop=dict(prox=thr, dprox=-1.0, n=5, max_iters=0, dobj=-1.0)), 40,
+                       perturb=False)
+    assert so.k == 16 and so.stop_reason == oracle.STOP_PROX
+
+
+def test_stop_stalled_proximity_and_cap(smx):
+    w = W.random_sparse(1500, 800, 15, seed=81, obj=W.OBJ_NONE, K=80)
+    P = oracle.from_workload(w)
+    _, _, h = P.run(w.x0[:, 0], 80, perturb=False)
+    dp = np.abs(np.diff(h.prox)) / np.maximum(1.0, h.prox[:-1])
+    thr = _log_mid(dp[19], dp[20])
+    assert _margin_ok(dp, thr)
+    say("stop on Delta P")
+    _stop_compare(smx, w.with_params(stop=dict(prox=-1.0, dprox=thr, n=3, max_iters=0, dobj=-1.0)), 80,
+                  perturb=False)
+    say("stop on N_max")
+    so = _stop_compare(smx, w.with_params(stop=dict(prox=-1.0, dprox=-1.0, n=3, max_iters=9, dobj=-1.0)), 80,
+                       perturb=False)
+    assert so.k == 9 and so.stop_reason == oracle.STOP_MAXIT
+
+
+def test_stop_iterate_variance(smx):
+    w = W.random_sparse(1500, 800, 15, seed=82, obj=W.OBJ_NONE, K=60)
+    w = w.with_params(x0=np.zeros_like(w.x0))  # omega_1 = 1, then small: the variance falls
+    P = oracle.from_workload(w)
+    xs = [w.x0[:, 0].astype(np.float64)]
+    st = None
+    for _ in range(60):
+        x, st, _ = P.run(xs[-1], 1, perturb=False, state=st)
+        xs.append(x)
+    om = [np.linalg.norm(xs[i] - xs[i - 1]) / np.linalg.norm(xs[i]) for i in range(1, 61)]
+    var = [np.var(om[:k], ddof=1) for k in range(2, 61)]
+    thr = _log_mid(var[24], var[25])
+    assert _margin_ok(var, thr)
+    say("stop on the iterate-change variance")
+    so = _stop_compare(smx, w.with_params(stop=dict(prox=-1.0, dprox=-1.0, n=3, max_iters=0, dobj=-1.0, var=thr)),
+                       60, perturb=False)
+    assert so.stop_reason == oracle.STOP_VAR
+
+
+def test_stop_superiorized(smx):
+    """Superiorized CT: a proximity rule and a small objective change."""
+    w = W.ct(N=32, n_angles=24, seed=83, K=80)
+    P = oracle.from_workload(w)
+    _, _, h = P.run(w.x0[:, 0], 80)
+    dp = np.abs(np.diff(h.prox)) / np.maximum(1.0, h.prox[:-1])
+    df = np.abs(np.diff(h.f_start)) / np.maximum(1.0, h.f_start[:-1])
+    srt = np.sort(df[10:])
+    tp, tf = _log_mid(dp[29], dp[30]), _log_mid(srt[len(srt) // 2], srt[len(srt) // 2 + 1])
+    assert _margin_ok(dp, tp) and _margin_ok(df, tf)
+    say("superiorized stop")
+    so = _stop_compare(smx, w.with_params(stop=dict(prox=-1.0, dprox=tp, n=2, max_iters=0, dobj=tf)), 80)
+    assert so.stop_reason == oracle.STOP_SM
+
+
+def test_stop_batched_and_resume(smx):
+    """Slices stop at their own iterations; a checkpoint taken after some have
+    stopped resumes to the uninterrupted result bitwise."""
+    w = W.ct(N=32, n_angles=24, seed=84, B=4, K=60)
+    stop = dict(prox=-1.0, dprox=5e-3, n=3, max_iters=0, dobj=-1.0)
+    w = w.with_params(stop=stop)
+    for s in range(4):
+        _, _, h = oracle.from_workload(w.with_params(stop=None), s).run(w.x0[:, s], 60, perturb=False)
+        assert _margin_ok(np.abs(np.diff(h.prox)) / np.maximum(1.0, h.prox[:-1]), 5e-3)
+    p = smx.problem_from_workload(w, history_cap=0)
+    p.run(60, perturb=False)
+    p.sync()
+    full, xfull = p.get_state()
+    reasons = p.stop_status()
+    p.close()
+    for s in range(4):
+        P = oracle.from_workload(w, s)
+        _, so, _ = P.run(w.x0[:, s], 60, perturb=False)
+        assert full[s]["k"] == so.k and reasons[s] == so.stop_reason, s
+    q = smx.problem_from_workload(w, history_cap=0)
+    q.run(min(f["k"] for f in full), perturb=False)
+    q.sync()
+    mid, xmid = q.get_state()
+    q.close()
+    r = smx.problem_from_workload(w, history_cap=0)
+    r.set_state(mid, xmid)
+    r.run(60, perturb=False)
+    r.sync()
+    end, xend = r.get_state()
+    r.close()
+    assert np.array_equal(xend, xfull) and end == full
