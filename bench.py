@@ -20,7 +20,10 @@ with every input resident in HBM.  The line also carries
               and aggregate slice iterations per second;
   hbm_config  the radiotherapy configuration (2.06M x 19,881, ~400M
               nonzeros), whose operator does not fit any cache: pass GB/s
-              against the 8 TB/s HBM peak.
+              against the 8 TB/s HBM peak;
+  basic_algorithms  DROP, CQ, EL and EMR steps on the headline workload;
+  seismic     the seismic setup at the paper's shape (8192 x 65536 band
+              rows, DROP, L1 / squared-norm / TV, with and without noise).
 """
 from __future__ import annotations
 
@@ -98,9 +101,10 @@ def measured_traffic(name, workload):
         return None
 
 
-def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=True):
+def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=True, keep_x=False):
     """Timed run of `steps` iterations (inputs resident in HBM), then the same
-    iterations eagerly with HIP events around each pass launch."""
+    iterations eagerly with HIP events around each pass launch.  keep_x adds
+    the timed run's final iterate (host float64)."""
     import torch
 
     p = smx.problem_from_workload(w, storage=storage, refine_iters=0, fused=fused)
@@ -115,6 +119,7 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=Tr
     dt = time.perf_counter() - t0
     p.sync()
     prox, obj = p.query()
+    x = p.get_x().cpu().double().numpy() if keep_x else None
     p.reset(w.x0)
     p.set_timing(True)
     p.run(steps, perturb=True, graph=False)
@@ -123,7 +128,7 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=Tr
     p.set_timing(False)
     p.close()
     return dict(seconds=dt, it_s=steps / dt, ms_per_step=1e3 * dt / steps, pass1_ms=t1, pass2_ms=t2, launches=n,
-                prox=[float(v) for v in prox], obj=[float(v) for v in obj], shapes=shapes[storage])
+                prox=[float(v) for v in prox], obj=[float(v) for v in obj], shapes=shapes[storage], x=x)
 
 
 def summarise(w, r, storage, B=1):
@@ -229,6 +234,39 @@ def section_basic(smx, steps, warmup, tune):
     return out
 
 
+def section_seismic(smx, steps, warmup, tune):
+    """The seismic setup at the paper's shape (64 sources x 128 receivers over
+    a 256 x 256 grid: A is 8192 x 65536 with first-Fresnel-zone band rows),
+    DROP steps, noise-free and with 5 % noise, L1 / squared-norm / TV
+    perturbations: SM iterations/s and the relative error to the true
+    slowness after `steps` iterations."""
+    import numpy as np
+
+    import workloads as W
+
+    out = {}
+    t0 = time.time()
+    base = W.seismic_fresnel(K=steps)
+    out["workload"] = dict(m=base.m, n=base.n, nnz=base.nnz, generate_s=round(time.time() - t0, 1))
+    noisy_b = W.add_relative_noise(base.meta["t_clean"], 0.05, base.meta["seed"])
+    cases = [("l1", W.OBJ_L1, 0.0, "f32"), ("l1", W.OBJ_L1, 0.05, "f32"), ("l1", W.OBJ_L1, 0.0, "bf16"),
+             ("sqnorm", W.OBJ_SQNORM, 0.0, "f32"), ("tv", W.OBJ_TV2D, 0.0, "f32"), ("tv", W.OBJ_TV2D, 0.05, "f32")]
+    for name, obj, noise, storage in cases:
+        N = int(round(np.sqrt(base.n)))
+        w = base.with_params(obj=obj, tv_rows=N if obj == W.OBJ_TV2D else 0, tv_cols=N if obj == W.OBJ_TV2D else 0,
+                             tv_eps=1e-4 if obj == W.OBJ_TV2D else 0.0)
+        if noise:
+            w = w.with_params(lower=noisy_b, upper=noisy_b.copy())
+        r = time_problem(smx, w, storage, steps, warmup, tune=tune, keep_x=True)
+        xt = w.x_true[:, 0].astype(np.float64)
+        err = float(np.linalg.norm(r["x"][:, 0] - xt) / np.linalg.norm(xt))
+        out[f"{name}_noise{int(round(noise * 100))}_{storage}"] = dict(
+            it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5), rel_err_true=round(err, 5),
+            prox=r["prox"][0], obj=r["obj"][0], fused=fused_in_use(r["shapes"]),
+            format=r["shapes"]["pass1"]["format"])
+    return out
+
+
 def section_hbm(smx, tune):
     import workloads as W
 
@@ -256,8 +294,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--sections", default="batched,serving,hbm,basic",
-                    help="extra sections beside the headline: batched,serving,hbm,basic (empty for none)")
+    ap.add_argument("--sections", default="batched,serving,hbm,basic,seismic",
+                    help="extra sections beside the headline: batched,serving,hbm,basic,seismic (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the single-GPU path is what is built "
@@ -317,6 +355,8 @@ def main():
         line["hbm_config"] = section_hbm(smx, tune)
     if "basic" in sections:
         line["basic_algorithms"] = section_basic(smx, 100, 10, tune)
+    if "seismic" in sections:
+        line["seismic"] = section_seismic(smx, 200, 10, tune)
     print(json.dumps(line), flush=True)
 
 

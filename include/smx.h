@@ -64,6 +64,7 @@ extern "C" {
 #define SMX_OBJ_SQNORM 1 /* f = ||x||^2, the L2 perturbation (Section 2.3.1) */
 #define SMX_OBJ_TV2D 2   /* smoothed total variation of an R x C image (Section 2.3.1) */
 #define SMX_OBJ_LINEAR 3 /* f = c^T x, e.g. summed dose (Section 2.3.3) */
+#define SMX_OBJ_L1 4     /* f = ||x||_1, the L1 perturbation (Section 2.3.1); subgradient sign(x), 0 at 0 */
 
 /* basic (feasibility-seeking) algorithms: the step T applied after the
  * perturbation (the appendix's table of methods; CQ from Section 2.1.1).  With

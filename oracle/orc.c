@@ -22,7 +22,8 @@
  *     the BoxProjection applied after each iteration);
  *   - the superiorized iteration of Algorithm 1 with power-law step sizes
  *     beta = gamma * alpha^ell (Section 2.1.2) and restarts of ell;
- *   - the objectives: squared norm (the L2 perturbation of Section 2.3.1),
+ *   - the objectives: squared norm (the L2 perturbation of Section 2.3.1), the
+ *     L1 norm (the L1 perturbation of the same section, subgradient sign(x)),
  *     total variation of a 2-D image (Section 2.3.1, TV equation), and a linear
  *     dose objective c^T x (Section 2.3.3, mean-dose objective up to scale).
  *
@@ -43,6 +44,7 @@
 #define ORC_OBJ_SQNORM 1
 #define ORC_OBJ_TV2D 2
 #define ORC_OBJ_LINEAR 3
+#define ORC_OBJ_L1 4     /* ||x||_1 (Section 2.3.1), subgradient sign(x) with sign(0) = 0 */
 
 /* basic (feasibility-seeking) algorithms of the appendix's table of methods */
 #define ORC_BASIC_SIMULT 0 /* weighted simultaneous projection */
@@ -309,6 +311,9 @@ double orc_objective(const orc_problem *P, const double *x)
     case ORC_OBJ_LINEAR:
         for (int64_t j = 0; j < P->n; ++j) s += P->lin_c[j] * x[j];
         return s;
+    case ORC_OBJ_L1:
+        for (int64_t j = 0; j < P->n; ++j) s += fabs(x[j]);
+        return s;
     case ORC_OBJ_TV2D:
         return tv_value(P, x);
     default:
@@ -324,6 +329,9 @@ void orc_gradient(const orc_problem *P, const double *x, double *g)
         return;
     case ORC_OBJ_LINEAR:
         for (int64_t j = 0; j < P->n; ++j) g[j] = P->lin_c[j];
+        return;
+    case ORC_OBJ_L1:
+        for (int64_t j = 0; j < P->n; ++j) g[j] = x[j] > 0.0 ? 1.0 : (x[j] < 0.0 ? -1.0 : 0.0);
         return;
     case ORC_OBJ_TV2D:
         tv_grad(P, x, g);

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmx.so")
 
 STORE = {"f32": 0, "bf16": 1, "f16": 2}
-OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 STOP_NONE, STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 0, 1, 2, 3, 4, 5
 RUN_PERTURB, RUN_GRAPH = 1, 2

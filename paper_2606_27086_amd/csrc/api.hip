@@ -738,7 +738,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     // DROP's range depends on the weights and is checked once they are normalised
     if (!(d->lambda > 0.0) || (d->basic != SMX_BASIC_DROP && !(d->lambda <= 2.0)))
         return fail(SMX_EINVAL, "lambda must be in (0, 2] (got %g)", d->lambda);
-    if (d->obj_kind < SMX_OBJ_NONE || d->obj_kind > SMX_OBJ_LINEAR) return fail(SMX_EINVAL, "unknown objective %d", d->obj_kind);
+    if (d->obj_kind < SMX_OBJ_NONE || d->obj_kind > SMX_OBJ_L1) return fail(SMX_EINVAL, "unknown objective %d", d->obj_kind);
     if (d->obj_kind != SMX_OBJ_NONE) {
         if (!(d->gamma > 0.0) || !std::isfinite(d->gamma)) return fail(SMX_EINVAL, "gamma must be > 0 (got %g)", d->gamma);
         if (!(d->alpha > 0.0 && d->alpha < 1.0)) return fail(SMX_EINVAL, "alpha must be in (0, 1) (got %g)", d->alpha);

@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_tv(const float *__restrict__ x
     }
 }
 
-// Squared norm (g = 2x) and linear objective (g = c) versions.
+// Squared norm (g = 2x), L1 norm (g = sign x) and linear objective (g = c) versions.
 __global__ __launch_bounds__(kBlock) void k_phase_flat(const float *__restrict__ x, float *__restrict__ g,
                                                        const float *__restrict__ lin_c,
                                                        const SliceState *__restrict__ st, PertParams pp,
@@ -1417,6 +1417,13 @@ __global__ __launch_bounds__(kBlock) void k_phase_flat(const float *__restrict__
                 v[1] += xj * xj;
                 if (!eval_only) {
                     const float gf = (float)(2.0 * xj);
+                    g[j * B + s] = gf;
+                    v[0] += (double)gf * (double)gf;
+                }
+            } else if (pp.obj == OBJ_L1) { // subgradient sign(x), 0 at 0
+                v[1] += fabs(xj);
+                if (!eval_only) {
+                    const float gf = xj > 0.0 ? 1.f : (xj < 0.0 ? -1.f : 0.f);
                     g[j * B + s] = gf;
                     v[0] += (double)gf * (double)gf;
                 }
@@ -1602,7 +1609,7 @@ __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, co
             for (int w = 0; w < kTrialChunk; ++w) {
                 if (t0 + w < ntr) {
                     const double z = xj + coef[t0 + w] * vj;
-                    acc[w] += lin ? gj * z : z * z;
+                    acc[w] += lin ? gj * z : (pp.obj == OBJ_L1 ? fabs(z) : z * z);
                 }
             }
         }

@@ -21,7 +21,7 @@ constexpr int kFusedRcBlock = 512; // the same for the register-cached fused pas
 // entry: the 16-bit value in the low half, a 16-bit index in the high half
 // (used when the layout's index range fits in 16 bits).
 enum ValKind : int { VK_F32 = 0, VK_BF16 = 1, VK_F16 = 2, VK_BF16P = 3, VK_F16P = 4 };
-enum ObjKind : int { OBJ_NONE = 0, OBJ_SQNORM = 1, OBJ_TV2D = 2, OBJ_LINEAR = 3 };
+enum ObjKind : int { OBJ_NONE = 0, OBJ_SQNORM = 1, OBJ_TV2D = 2, OBJ_LINEAR = 3, OBJ_L1 = 4 };
 
 // Device view of one row-aligned sparse layout: the CSR of A (pass 1) or the
 // CSR of A^T (pass 2).  Row r owns entries [ptr[r], ptr[r+1]); both ends are

@@ -150,7 +150,7 @@ def test_dense_unperturbed_consistent_proximity_decreases(smx):
     assert np.all(d <= 1e-6 * h["prox"][0, 0])
 
 
-@pytest.mark.parametrize("obj", [W.OBJ_NONE, W.OBJ_SQNORM, W.OBJ_LINEAR, W.OBJ_TV2D])
+@pytest.mark.parametrize("obj", [W.OBJ_NONE, W.OBJ_SQNORM, W.OBJ_LINEAR, W.OBJ_TV2D, W.OBJ_L1])
 def test_random_sparse_edge_rows(smx, obj):
     """Skewed row lengths, empty rows, two full-length rows, one-sided and
     equality bands, restarts and two reduction steps."""
@@ -208,6 +208,23 @@ def test_seismic_small_tv(smx):
 def test_seismic_small_tv_lockstep(smx):
     w = W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=9, K=40, variant="paper")
     say("seismic lockstep (paper parameters)")
+    worst = lockstep(smx, w, w.K)
+    print(f"  worst per-iteration rel err {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("obj,noise", [(W.OBJ_L1, 0.0), (W.OBJ_L1, 0.05), (W.OBJ_SQNORM, 0.0),
+                                       (W.OBJ_TV2D, 0.05)])
+def test_seismic_fresnel_drop(smx, obj, noise):
+    """Band rows of the first-Fresnel-zone model, DROP steps, equality bands
+    (noise-free and with 5 % noise, Section 2.3.1) and the L1, squared-norm and
+    TV perturbations."""
+    w = W.seismic_fresnel(N=48, n_src=12, n_rec=24, seed=11, noise=noise, obj=obj, K=40)
+    check_parity(smx, w, w.K, sensitive=obj == W.OBJ_TV2D)
+
+
+def test_seismic_fresnel_l1_lockstep(smx):
+    w = W.seismic_fresnel(N=48, n_src=12, n_rec=24, seed=11, noise=0.05, obj=W.OBJ_L1, K=30)
+    say("seismic fresnel lockstep (DROP, L1)")
     worst = lockstep(smx, w, w.K)
     print(f"  worst per-iteration rel err {worst:.3e}", flush=True)
 

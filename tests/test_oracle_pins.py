@@ -645,3 +645,34 @@ def test_stop_superiorized_needs_objective_change(orc):
     # iteration k_feas completes (k = k_feas + 1); the next one stops at its phase
     assert st.stop_reason == orc.STOP_SM and st.k == k_feas + 1
     np.testing.assert_allclose(h.prox[:st.k], pk[:st.k], rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# L1 perturbation (Section 2.3.1)
+# ---------------------------------------------------------------------------
+
+def test_l1_value_and_subgradient(orc):
+    """f = sum |x_j|; its (sub)gradient sign(x) (0 at 0) satisfies the
+    subgradient inequality f(y) >= f(x) + g.(y - x) everywhere."""
+    rng = np.random.default_rng(12)
+    P = _unconstrained(orc, 9, W.OBJ_L1)
+    for _ in range(50):
+        x = rng.normal(size=9)
+        x[rng.random(9) < 0.3] = 0.0
+        y = rng.normal(size=9)
+        assert P.objective(x) == pytest.approx(np.abs(x).sum(), rel=1e-15)
+        g = P.gradient(x)
+        assert np.array_equal(g, np.sign(x))
+        assert P.objective(y) >= P.objective(x) + g @ (y - x) - 1e-12
+
+
+def test_l1_perturbation_closed_form(orc):
+    """Unconstrained, x = (3, -4, 0), gamma = 1, alpha = 1/2, one reduction
+    step: v = -sign(x)/sqrt(2); beta = 1 shrinks both nonzero entries by
+    1/sqrt(2) (f drops by sqrt(2)), accepted; the next phase uses beta = 1/2."""
+    P = _unconstrained(orc, 3, W.OBJ_L1, gamma=1.0, alpha=0.5, n_red=1)
+    x, st, h = P.run(np.array([3.0, -4.0, 0.0]), 2)
+    r2 = 1.0 / math.sqrt(2.0)
+    np.testing.assert_allclose(x, [3.0 - r2 - 0.5 * r2, -4.0 + r2 + 0.5 * r2, 0.0], rtol=1e-15, atol=1e-15)
+    assert list(h.trials) == [1, 1] and st.ell == 2
+    np.testing.assert_allclose(h.f_start, [7.0, 7.0 - math.sqrt(2.0)], rtol=1e-15)

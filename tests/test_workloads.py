@@ -111,3 +111,28 @@ def test_serving_mix_shapes():
         o = ops[r["op_key"]]
         S = r["lower"].shape[1]
         assert 2 <= S <= 4 and r["upper"].shape == (o["m"], S) and r["x0"].shape == (o["n"], S)
+
+
+def test_fresnel_rows_sum_to_ray_lengths():
+    """Constant slowness s gives travel times s * L, L the source-receiver
+    distance (each band row is scaled to sum to its ray's length)."""
+    N, ns, nr = 40, 6, 10
+    rp, ci, v = W.fresnel_matrix(N, ns, nr)
+    sums = np.add.reduceat(v, rp[:-1].astype(np.int64))
+    ys = (np.arange(ns) + 0.5) * N / ns
+    half = nr // 2
+    for a in range(ns):
+        for b in range(nr):
+            if b < half:
+                p1 = (0.0, (b + 0.5) * N / half)
+            else:
+                p1 = ((b - half + 0.5) * N / (nr - half), 0.0)
+            L = math.hypot(p1[0] - N, p1[1] - ys[a])
+            assert sums[a * nr + b] == pytest.approx(L, rel=1e-12)
+    assert np.all(v > 0) and np.all((ci >= 0) & (ci < N * N))
+
+
+def test_fresnel_paper_shape():
+    w = W.seismic_fresnel(N=32, n_src=8, n_rec=16, K=3)
+    assert (w.m, w.n) == (8 * 16, 32 * 32) and w.basic == W.BASIC_DROP and w.lam == w.m
+    np.testing.assert_array_equal(w.lower, w.upper)

@@ -20,9 +20,9 @@ from typing import Optional
 
 import numpy as np
 
-OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR = 0, 1, 2, 3
+OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
-OBJ_NAMES = {OBJ_NONE: "none", OBJ_SQNORM: "sqnorm", OBJ_TV2D: "tv2d", OBJ_LINEAR: "linear"}
+OBJ_NAMES = {OBJ_NONE: "none", OBJ_SQNORM: "sqnorm", OBJ_TV2D: "tv2d", OBJ_LINEAR: "linear", OBJ_L1: "l1"}
 
 
 @dataclass
@@ -439,6 +439,116 @@ def seismic_matrix(rows: int, cols: int, n_src: int, n_rec: int):
         p1 = np.stack([xr, np.full(n_rec, float(rows))], axis=1)
         chunks.append(trace_rays(p0, p1, cols, rows, 0.0, 0.0, 1.0, 1.0))
     return _assemble(chunks, n_src * n_rec)
+
+
+def fresnel_matrix(N: int, n_src: int, n_rec: int, wavelength: float = 1.0, w0: float = 0.5):
+    """Band rows of a cross-well / surface travel-time model on an N x N grid of
+    unit pixels (pixel (i, j) = unknown i*N + j, centre (j + 1/2, i + 1/2)):
+    sources on the right edge, receivers half on the left edge and half on the
+    top edge; row ``src * n_rec + rec``.  Each ray is widened to a band around
+    its segment p0 -> p1 of length L: at fraction t along it the half-width is
+    w(t) = sqrt(wavelength * L * t (1 - t)) + w0 (a first-Fresnel-zone-like
+    width); a pixel at distance d from the segment gets weight
+    exp(-(d / w(t))^2) if d <= 2 w(t), and the row is scaled to sum to L, so a
+    constant slowness s gives travel times s * L.  Returns (row_ptr, cols, vals)."""
+    ys = (np.arange(n_src) + 0.5) * N / n_src
+    half = n_rec // 2
+    rec = np.concatenate([np.stack([np.zeros(half), (np.arange(half) + 0.5) * N / half], 1),
+                          np.stack([(np.arange(n_rec - half) + 0.5) * N / (n_rec - half),
+                                    np.zeros(n_rec - half)], 1)])
+    counts, cols_all, vals_all = [], [], []
+    for a in range(n_src):
+        p0 = np.array([float(N), ys[a]])
+        for b in range(n_rec):
+            p1 = rec[b]
+            dv = p1 - p0
+            L = float(np.hypot(dv[0], dv[1]))
+            u = dv / L
+            wmax = np.sqrt(wavelength * L / 4.0) + w0
+            reach = 2.0 * wmax
+            # candidate pixels: every pixel whose centre lies within `reach` of the segment's bounding box
+            lo = np.floor(np.minimum(p0, p1) - reach).astype(int)
+            hi = np.ceil(np.maximum(p0, p1) + reach).astype(int)
+            jj = np.arange(max(lo[0], 0), min(hi[0], N))
+            ii = np.arange(max(lo[1], 0), min(hi[1], N))
+            J, I = np.meshgrid(jj, ii)
+            cx, cy = J.ravel() + 0.5, I.ravel() + 0.5
+            t = ((cx - p0[0]) * u[0] + (cy - p0[1]) * u[1]) / L
+            tc = np.clip(t, 0.0, 1.0)
+            d = np.hypot(cx - (p0[0] + tc * dv[0]), cy - (p0[1] + tc * dv[1]))
+            w = np.sqrt(wavelength * L * tc * (1.0 - tc)) + w0
+            keep = d <= 2.0 * w
+            om = np.exp(-(d[keep] / w[keep]) ** 2)
+            idx = (I.ravel()[keep] * N + J.ravel()[keep]).astype(np.int64)
+            order = np.argsort(idx)
+            counts.append(idx.size)
+            cols_all.append(idx[order])
+            vals_all.append((L * om / om.sum())[order])
+    row_ptr = np.zeros(len(counts) + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    assert row_ptr[-1] < 2**31
+    return row_ptr.astype(np.int32), np.concatenate(cols_all).astype(np.int32), np.concatenate(vals_all)
+
+
+def add_relative_noise(t: np.ndarray, noise: float, seed: int) -> np.ndarray:
+    """Travel times t (m x B) times (1 + noise * N(0, 1)), per entry, float32."""
+    rng = np.random.default_rng(seed + 7919)
+    return (t * (1.0 + noise * rng.standard_normal(t.shape))).astype(np.float32)
+
+
+def seismic_fresnel(
+    N: int = 256,
+    n_src: int = 64,
+    n_rec: int = 128,
+    seed: int = 6,
+    B: int = 1,
+    noise: float = 0.0,
+    obj: int = OBJ_L1,
+    basic: int = BASIC_DROP,
+    K: int = 200,
+) -> Workload:
+    """The seismic setup at the paper's shape (Section 2.3.1: 64 sources, 128
+    receivers, a 256 x 256 grid, A of 8192 x 65536) with band rows
+    (:func:`fresnel_matrix`).  The system A s = b is solved as equality bands,
+    noise-free (an exact solution exists) or with relative Gaussian noise (5 %
+    in the paper's second case); box s >= 0; DROP with lambda = m (1/w for the
+    uniform weights) and the L1, squared-norm or TV perturbation."""
+    row_ptr, cols_idx, vals = fresnel_matrix(N, n_src, n_rec)
+    val = vals.astype(np.float32)
+    m, n = n_src * n_rec, N * N
+    t = np.empty((m, B), np.float64)
+    xt = np.empty((n, B), np.float32)
+    for s in range(B):
+        sl = slowness_field(N, N, seed * 1000 + s).reshape(-1)
+        t[:, s] = _csr_matvec64(row_ptr, cols_idx, val, sl)
+        xt[:, s] = sl
+    b = add_relative_noise(t, noise, seed)
+    return Workload(
+        name=f"seismic_fresnel{N}",
+        m=m,
+        n=n,
+        row_ptr=row_ptr,
+        col_idx=cols_idx,
+        val=val,
+        lower=b.copy(),
+        upper=b.copy(),
+        box_lo=np.zeros(n, np.float32),
+        box_hi=np.full(n, np.inf, np.float32),
+        x0=np.zeros((n, B), np.float32),
+        lam=float(m) if basic == BASIC_DROP else 1.0,
+        obj=obj,
+        tv_rows=N if obj == OBJ_TV2D else 0,
+        tv_cols=N if obj == OBJ_TV2D else 0,
+        tv_eps=1e-4 if obj == OBJ_TV2D else 0.0,
+        gamma=1.0,
+        alpha=0.975,
+        n_red=4,
+        restart_every=50,
+        K=K,
+        x_true=xt,
+        basic=basic,
+        meta=dict(n_src=n_src, n_rec=n_rec, noise=noise, seed=seed, t_clean=t),
+    )
 
 
 def seismic(
