@@ -1,10 +1,13 @@
 """Full-size configurations on the GPU, checked at sampled iterations.
 
-The GPU runs the whole configuration (the benchmark's launch shapes: graph
-replay, autotuned passes).  At sampled iterations k the oracle starts from the
-GPU's own iterate and state and runs one iteration; the GPU's next iterate
-must agree to 1e-5 with the same decisions.  The oracle cannot afford the
-whole run at these sizes, but it can afford single iterations.
+The GPU runs in the benchmark's launch configuration (autotuned passes, graph
+replay).  At each sampled iteration index k, a seeded point near the true
+solution and an iteration state for k (ell, restarts) are loaded into the
+device, which runs one iteration; the oracle runs the same iteration from the
+same point, and the two iterates must agree to 1e-5 with the same decisions.
+The oracle cannot afford whole runs at these sizes, but it can afford single
+iterations.  The whole run from x0 is then checked by properties that hold at
+any size (every iteration done, finite values, the proximity reduced).
 """
 import time
 
@@ -13,7 +16,7 @@ import pytest
 
 import oracle
 import workloads as W
-from test_gpu_parity import rel, say
+from test_gpu_parity import rel, say, step_from_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -35,35 +38,35 @@ def sampled_lockstep(smx, w, K, samples, storage="f32"):
     p.autotune(reps=3)
     print(f"  setup {time.time() - t0:.1f}s shapes {p.describe()}", flush=True)
     P = oracle.from_workload(w, value_round=None if storage == "f32" else storage)
-    k = 0
     worst = 0.0
     for ks in sorted(samples):
-        if ks > k:
-            p.run(ks - k, graph=True)
-            k = ks
-        states, xk = p.get_state()
-        assert states[0]["k"] == ks
+        x = W.synthetic_iterate(w, seed=1000 + ks)[:, 0].astype(np.float64)
         so = oracle.State()
-        for f in ("k", "ell", "restarts", "trials", "accepts", "cap_hits"):
-            setattr(so, f, states[0][f])
+        so.k = ks
+        so.restarts = ks // w.restart_every if w.restart_every > 0 else 0
+        so.ell = ks + so.restarts
+        so.trials = so.accepts = so.ell
         t = time.time()
-        xo, so1, _ = P.run(xk[:, 0].astype(np.float64), 1, state=so)
-        p.run(1, graph=True)
-        k += 1
-        states1, xg = p.get_state()
-        r = rel(xg[:, 0].astype(np.float64), xo)
+        xg, sg, xo, so1 = step_from_oracle(p, P, x, so, graph=True)
+        r = rel(xg, xo)
         worst = max(worst, r)
-        print(f"  k={ks}: rel {r:.2e} trials {states1[0]['trials'] - states[0]['trials']} "
-              f"(oracle {so1.trials - so.trials}), oracle {time.time() - t:.1f}s", flush=True)
-        assert states1[0]["trials"] == so1.trials and states1[0]["ell"] == so1.ell, ks
+        print(f"  k={ks}: rel {r:.2e} trials {sg['trials'] - so.trials} (oracle {so1.trials - so.trials}), "
+              f"oracle {time.time() - t:.1f}s", flush=True)
+        assert sg["trials"] == so1.trials and sg["ell"] == so1.ell and sg["accepts"] == so1.accepts, ks
         assert r <= 1e-5, (ks, r)
-    if k < K:
-        p.run(K - k, graph=True)
+    p.reset(w.x0)
+    p.run(1)
+    p.sync()
+    prox1, _ = p.query()
+    p.reset(w.x0)
+    p.run(K, graph=True)
     p.sync()
     prox, obj = p.query()
     states, _ = p.get_state()
     p.close()
+    print(f"  full run: proximity after one iteration {prox1[0]:.4e}, after {K} {prox[0]:.4e}", flush=True)
     assert states[0]["k"] == K and np.isfinite(prox[0]) and np.isfinite(obj[0])
+    assert prox[0] < prox1[0]
     return worst
 
 
@@ -84,3 +87,11 @@ def test_rt_full_size(smx):
     w = W.rt_large(seed=4, K=300)
     say(f"rt full m={w.m} n={w.n} nnz={w.nnz} (generated in {time.time() - t:.1f}s)")
     sampled_lockstep(smx, w, w.K, [0, 150, 299])
+
+
+def test_seismic_fresnel_paper_shape(smx):
+    t = time.time()
+    w = W.seismic_fresnel(K=200)
+    say(f"seismic fresnel paper shape m={w.m} n={w.n} nnz={w.nnz} DROP L1 "
+        f"(generated in {time.time() - t:.1f}s)")
+    sampled_lockstep(smx, w, w.K, [0, 100, 199])

@@ -169,26 +169,50 @@ def test_ct_small_tv_paper_parameters(smx):
     check_parity(smx, w, w.K, sensitive=True)
 
 
+STATE_FIELDS = ("k", "ell", "restarts", "trials", "accepts", "cap_hits", "stop_reason", "dp_run", "feas_ok",
+                "p_last", "f_last", "var_n", "var_mean", "var_m2")
+
+
+def device_state(so):
+    """An oracle state as the device's per-slice state record."""
+    out = {}
+    for f in STATE_FIELDS:
+        v = getattr(so, f)
+        out[f] = (None if v != v else float(v)) if isinstance(v, float) else int(v)
+    return out
+
+
+def step_from_oracle(p, P, x, so, graph=False, perturb=True):
+    """One iteration from an oracle-made point: x (float32 values) and state so
+    are loaded into the device, which runs one iteration; the oracle runs the
+    same iteration from the same point.  Returns (device x, device state,
+    oracle x, oracle state)."""
+    p.set_state([device_state(so)], x.astype(np.float32).reshape(-1, 1))
+    xo, so1, _ = P.run(x.astype(np.float64), 1, perturb=perturb, state=so)
+    p.run(1, perturb=perturb, graph=graph)
+    states1, xg = p.get_state()
+    return xg[:, 0].astype(np.float64), states1[0], xo, so1
+
+
 def lockstep(smx, w, K, tol=RTOL):
-    """Every iteration starts from the device's own iterate and state; the
-    oracle runs that one iteration from the same point.  The iterates must
-    agree to tol and the decisions (trials, accepts, ell) exactly."""
+    """Per-iteration check driven by the oracle: the oracle runs its own
+    trajectory with the iterate rounded to float32 after every iteration; each
+    of its iterates and states is loaded into the device, which runs that one
+    iteration.  The iterates must agree to tol and the decisions (trials,
+    accepts, ell, restarts) exactly."""
     p = smx.problem_from_workload(w, history_cap=0)
     P = oracle.from_workload(w)
+    x = w.x0[:, 0].astype(np.float32).astype(np.float64)
+    so = oracle.State()
     worst = 0.0
     for k in range(K):
-        states, xk = p.get_state()
-        so = oracle.State()
-        for f in ("k", "ell", "restarts", "trials", "accepts", "cap_hits"):
-            setattr(so, f, states[0][f])
-        xo, so1, ho = P.run(xk[:, 0].astype(np.float64), 1, state=so)
-        p.run(1)
-        states1, xg = p.get_state()
-        r = rel(xg[:, 0].astype(np.float64), xo)
+        xg, sg, xo, so1 = step_from_oracle(p, P, x, so)
+        r = rel(xg, xo)
         worst = max(worst, r)
-        assert states1[0]["trials"] == so1.trials and states1[0]["accepts"] == so1.accepts, k
-        assert states1[0]["ell"] == so1.ell and states1[0]["restarts"] == so1.restarts, k
+        assert sg["trials"] == so1.trials and sg["accepts"] == so1.accepts, k
+        assert sg["ell"] == so1.ell and sg["restarts"] == so1.restarts and sg["k"] == so1.k, k
         assert r <= tol, f"iteration {k}: rel err {r:.3e}"
+        x, so = xo.astype(np.float32).astype(np.float64), so1
     p.close()
     return worst
 
@@ -316,15 +340,19 @@ def test_checkpoint_resume_bitwise(smx):
     assert sa == sb
 
 
-def test_query_at_device_iterate(smx):
-    """Proximity and objective evaluated by the kernels at the device's own
-    iterate agree with the oracle evaluated at that same point."""
+def test_query_at_given_point(smx):
+    """Proximity and objective evaluated by the kernels at a seeded point
+    loaded into the device agree with the oracle evaluated at that point."""
     w = W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=16, K=30)
-    say("query at device iterate")
-    x, prox, obj, _, _ = gpu_run(smx, w, w.K)
+    say("query at a loaded point")
+    x = W.synthetic_iterate(w, seed=17)
+    p = smx.problem_from_workload(w, history_cap=0)
+    p.set_x(x)
+    prox, obj = p.query()
+    p.close()
     P = oracle.from_workload(w)
-    assert prox[0] == pytest.approx(P.proximity(x[:, 0]), rel=2e-6)
-    assert obj[0] == pytest.approx(P.objective(x[:, 0]), rel=2e-6)
+    assert prox[0] == pytest.approx(P.proximity(x[:, 0].astype(np.float64)), rel=2e-6)
+    assert obj[0] == pytest.approx(P.objective(x[:, 0].astype(np.float64)), rel=2e-6)
 
 
 def test_timing_counts_launches(smx):

@@ -490,6 +490,17 @@ def fresnel_matrix(N: int, n_src: int, n_rec: int, wavelength: float = 1.0, w0: 
     return row_ptr.astype(np.int32), np.concatenate(cols_all).astype(np.int32), np.concatenate(vals_all)
 
 
+def synthetic_iterate(w: "Workload", seed: int, spread: float = 0.1) -> np.ndarray:
+    """A seeded point of the kind an iteration passes through: the true
+    solution (0.5 where none is known) times (1 + spread * N(0, 1)), clipped
+    to the box; float32 [n, B]."""
+    rng = np.random.default_rng(seed)
+    base = np.full((w.n, w.B), 0.5) if w.x_true is None else np.asarray(w.x_true, np.float64).reshape(w.n, -1)
+    x = base * (1.0 + spread * rng.standard_normal((w.n, base.shape[1])))
+    x = np.clip(x, np.asarray(w.box_lo, np.float64)[:, None], np.asarray(w.box_hi, np.float64)[:, None])
+    return np.ascontiguousarray(np.broadcast_to(x, (w.n, w.B)), dtype=np.float32)
+
+
 def add_relative_noise(t: np.ndarray, noise: float, seed: int) -> np.ndarray:
     """Travel times t (m x B) times (1 + noise * N(0, 1)), per entry, float32."""
     rng = np.random.default_rng(seed + 7919)
