@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 1, 2, 3, 4, 5
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
+DVC_MAX, DVC_MIN = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -38,6 +39,17 @@ def build(force: bool = True) -> str:
         )
         os.replace(tmp, _LIB)
     return _LIB
+
+
+class _Dvc(C.Structure):
+    _fields_ = [
+        ("row_begin", C.c_int64),
+        ("row_end", C.c_int64),
+        ("sense", C.c_int32),
+        ("pad_", C.c_int32),
+        ("fraction", C.c_double),
+        ("dose", C.c_double),
+    ]
 
 
 class _Problem(C.Structure):
@@ -72,6 +84,9 @@ class _Problem(C.Structure):
         ("stop_dprox", C.c_double),
         ("stop_dobj", C.c_double),
         ("stop_var", C.c_double),
+        ("n_dvc", C.c_int32),
+        ("pad_", C.c_int32),
+        ("dvc", C.POINTER(_Dvc)),
     ]
 
 
@@ -139,6 +154,9 @@ def lib():
         L.orc_gradient.argtypes = [P, dp, dp]
         L.orc_run.argtypes = [P, dp, C.c_int64, C.c_int32, C.POINTER(State), dp, dp, dp, ip, ip]
         L.orc_run.restype = C.c_int
+        L.orc_bands_at.argtypes = [P, dp, dp, dp]
+        L.orc_dvc_count.argtypes = [C.POINTER(_Dvc)]
+        L.orc_dvc_count.restype = C.c_int64
         L.orc_round_bf16.argtypes = [dp, dp, C.c_int64]
         L.orc_round_f16_scaled.argtypes = [dp, dp, C.c_int64]
         L.orc_round_f16_scaled.restype = C.c_double
@@ -194,6 +212,7 @@ class Problem:
         basic=BASIC_SIMULT,
         col_nnz=None,
         stop=None,
+        dvc=None,
     ):
         self.m, self.n = int(m), int(n)
         self.row_ptr = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
@@ -232,6 +251,14 @@ class Problem:
             basic=int(basic),
             col_nnz=_dp(self.col_nnz),
         )
+        self.dvc = None
+        if dvc:
+            self.dvc = (_Dvc * len(dvc))()
+            for i, g in enumerate(dvc):
+                self.dvc[i] = _Dvc(row_begin=int(g["row_begin"]), row_end=int(g["row_end"]), sense=int(g["sense"]),
+                                   fraction=float(g["fraction"]), dose=float(g["dose"]))
+            self.s.n_dvc = len(dvc)
+            self.s.dvc = C.cast(self.dvc, C.POINTER(_Dvc))
         if stop is not None:
             self.s.stop_on = 1
             self.s.stop_n = int(stop.get("n", 5))
@@ -261,6 +288,17 @@ class Problem:
 
     def proximity(self, x) -> float:
         return float(lib().orc_proximity(C.byref(self.s), _dp(_f64(x))))
+
+    def bands_at(self, x):
+        """The bands of every row at x (dose-volume rows: the bands their
+        projection sets there)."""
+        lo, up = np.empty(self.m), np.empty(self.m)
+        lib().orc_bands_at(C.byref(self.s), _dp(_f64(x)), _dp(lo), _dp(up))
+        return lo, up
+
+    def dvc_count(self, g: int) -> int:
+        """k of dose-volume constraint g: floor(V N_S) (MAX) or ceil(V N_S) (MIN)."""
+        return int(lib().orc_dvc_count(C.byref(self.dvc[g])))
 
     def objective(self, x) -> float:
         return float(lib().orc_objective(C.byref(self.s), _dp(_f64(x))))
@@ -362,4 +400,5 @@ def from_workload(w, s: int = 0, value_round: Optional[str] = None) -> Problem:
         basic=getattr(w, "basic", BASIC_SIMULT),
         col_nnz=col_nnz,
         stop=getattr(w, "stop", None),
+        dvc=getattr(w, "dvc", None),
     )

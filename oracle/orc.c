@@ -22,6 +22,10 @@
  *     the BoxProjection applied after each iteration);
  *   - the superiorized iteration of Algorithm 1 with power-law step sizes
  *     beta = gamma * alpha^ell (Section 2.1.2) and restarts of ell;
+ *   - dose-volume constraints (Section 2.3.3) as sets in the output space of
+ *     the split problem (eq. Split): for a structure S of N_S rows, "at most
+ *     V N_S rows above d" or "at least V N_S rows at or above d", with the
+ *     nearest-point projection of the structure's values A_S x onto that set;
  *   - the objectives: squared norm (the L2 perturbation of Section 2.3.1), the
  *     L1 norm (the L1 perturbation of the same section, subgradient sign(x)),
  *     total variation of a 2-D image (Section 2.3.1, TV equation), and a linear
@@ -53,6 +57,18 @@
 #define ORC_BASIC_EL 3     /* extrapolated Landweber */
 #define ORC_BASIC_EMR 4    /* Landweber with error-minimising relaxation */
 
+/* dose-volume constraint senses (Section 2.3.3) */
+#define ORC_DVC_MAX 0 /* D_V <= d: at most floor(V N_S) rows of the structure above d */
+#define ORC_DVC_MIN 1 /* D_V >= d: at least ceil(V N_S) rows of the structure at or above d */
+
+typedef struct {
+    int64_t row_begin, row_end; /* the structure's rows [row_begin, row_end) */
+    int32_t sense;              /* ORC_DVC_* */
+    int32_t pad_;
+    double fraction;            /* V in [0, 1] */
+    double dose;                /* d */
+} orc_dvc;
+
 typedef struct {
     int64_t m, n;
     const int64_t *row_ptr; /* m+1 */
@@ -82,6 +98,11 @@ typedef struct {
     double stop_dprox;   /* Delta P* */
     double stop_dobj;    /* Delta f* */
     double stop_var;     /* variance threshold (0: rule off) */
+    /* dose-volume constraints: each owns a block of rows whose lower/upper are
+     * replaced, at every point, by the bands its projection sets */
+    int32_t n_dvc;
+    int32_t pad_;
+    const orc_dvc *dvc;
 } orc_problem;
 
 typedef struct {
@@ -140,17 +161,86 @@ void orc_row_sqnorms(const orc_problem *P, double *q)
 }
 
 /*
+ * Dose-volume constraints.  The structure's values d_i = r_i (i in S) are
+ * ranked from the highest down; ties, and values that differ only below
+ * float32 resolution, are ranked by row index (the rank compares the values
+ * rounded to float32, so that the device, whose sums run in another order,
+ * takes the same decisions).  The nearest point of the set
+ *   MAX: at most k = floor(V N_S) values above d  keeps the k highest values
+ *        and lowers every other value above d to d;
+ *   MIN: at least k = ceil(V N_S) values at or above d  raises the k highest
+ *        values to d where they are below it and keeps the others;
+ * (changing the k highest is the cheapest choice in both cases, the squared
+ * distance being a sum over the changed values).  As bands on the rows: MAX
+ * gives (-inf, +inf) to the k highest and (-inf, d] to the rest, MIN gives
+ * [d, +inf) to the k highest and (-inf, +inf) to the rest.
+ */
+typedef struct {
+    float key;
+    int64_t row;
+} ranked;
+
+static int by_value_then_row(const void *a, const void *b)
+{
+    const ranked *p = a, *q = b;
+    if (p->key != q->key) return p->key > q->key ? -1 : 1; /* higher value first */
+    return p->row < q->row ? -1 : (p->row > q->row ? 1 : 0);
+}
+
+int64_t orc_dvc_count(const orc_dvc *g)
+{
+    const int64_t N = g->row_end - g->row_begin;
+    double kv = g->sense == ORC_DVC_MAX ? floor(g->fraction * (double)N) : ceil(g->fraction * (double)N);
+    if (kv < 0.0) kv = 0.0;
+    if (kv > (double)N) kv = (double)N;
+    return (int64_t)kv;
+}
+
+/* lo/up: the bands every row has at the point with row values r. */
+static void effective_bands(const orc_problem *P, const double *r, double *lo, double *up)
+{
+    for (int64_t i = 0; i < P->m; ++i) {
+        lo[i] = P->lower[i];
+        up[i] = P->upper[i];
+    }
+    for (int32_t g = 0; g < P->n_dvc; ++g) {
+        const orc_dvc *G = &P->dvc[g];
+        const int64_t N = G->row_end - G->row_begin, k = orc_dvc_count(G);
+        ranked *order = malloc(sizeof(ranked) * (N > 0 ? N : 1));
+        for (int64_t p = 0; p < N; ++p) {
+            order[p].key = (float)r[G->row_begin + p];
+            order[p].row = G->row_begin + p;
+        }
+        qsort(order, (size_t)N, sizeof(ranked), by_value_then_row);
+        for (int64_t p = 0; p < N; ++p) {
+            const int64_t i = order[p].row;
+            const int top = p < k;
+            if (G->sense == ORC_DVC_MAX) {
+                lo[i] = -INFINITY;
+                up[i] = top ? INFINITY : G->dose;
+            } else {
+                lo[i] = top ? G->dose : -INFINITY;
+                up[i] = INFINITY;
+            }
+        }
+        free(order);
+    }
+}
+
+/*
  * Weighted proximity (eq. WeightedProximity): 1/2 sum_i w_i ||P_i(x) - x||^2.
  * For a band, P_i(x) - x = ((clip(r_i) - r_i)/||a_i||^2) a_i, whose norm is
  * |clip(r_i) - r_i| / ||a_i||.  A row with a_i = 0 is the whole space when its
  * band holds 0 and is skipped here (it cannot be projected onto otherwise).
+ * lo/up are the bands at this point (effective_bands).
  */
-static double proximity_q(const orc_problem *P, const double *q, const double *r)
+static double proximity_q(const orc_problem *P, const double *q, const double *r, const double *lo,
+                          const double *up)
 {
     double s = 0.0;
     for (int64_t i = 0; i < P->m; ++i) {
         if (!(q[i] > 0.0)) continue;
-        double t = clampd(r[i], P->lower[i], P->upper[i]) - r[i];
+        double t = clampd(r[i], lo[i], up[i]) - r[i];
         double dist = fabs(t) / sqrt(q[i]);
         s += P->w[i] * dist * dist;
     }
@@ -159,13 +249,26 @@ static double proximity_q(const orc_problem *P, const double *q, const double *r
 
 double orc_proximity(const orc_problem *P, const double *x)
 {
-    double *q = malloc(sizeof(double) * P->m), *r = malloc(sizeof(double) * P->m);
+    double *q = malloc(sizeof(double) * P->m), *r = malloc(sizeof(double) * P->m),
+           *lo = malloc(sizeof(double) * P->m), *up = malloc(sizeof(double) * P->m);
     orc_row_sqnorms(P, q);
     orc_matvec(P, x, r);
-    double v = proximity_q(P, q, r);
+    effective_bands(P, r, lo, up);
+    double v = proximity_q(P, q, r, lo, up);
     free(q);
     free(r);
+    free(lo);
+    free(up);
     return v;
+}
+
+/* The bands at x (for tests): lo/up of length m. */
+void orc_bands_at(const orc_problem *P, const double *x, double *lo, double *up)
+{
+    double *r = malloc(sizeof(double) * P->m);
+    orc_matvec(P, x, r);
+    effective_bands(P, r, lo, up);
+    free(r);
 }
 
 /*
@@ -183,7 +286,9 @@ double orc_proximity(const orc_problem *P, const double *x)
  *           (Section 2.1.1); the box plays C;
  *   EL      x + lambda sigma A^T D t, sigma = t^T D t / ||A^T D t||^2;
  *   EMR     x + lambda sigma y, y = A^T W t, sigma = ||y||^2 / sum_i w_i (A y)_i^2;
- * sigma = 0 when its denominator is 0 (then y = 0 too).  Returns the
+ * sigma = 0 when its denominator is 0 (then y = 0 too).  The bands of
+ * dose-volume rows are those their projection sets at the input point (the
+ * split problem's P_Q).  Returns the
  * proximity at the input point.  Scratch: r[m], c[m], y[n]; zc[n] holds the
  * DROP column factors (unused otherwise).
  */
@@ -191,12 +296,14 @@ static double feas_step(const orc_problem *P, const double *q, const double *zc,
                         double *y)
 {
     orc_matvec(P, x, r);
-    double prox = proximity_q(P, q, r);
+    double *lo = malloc(sizeof(double) * P->m), *up = malloc(sizeof(double) * P->m);
+    effective_bands(P, r, lo, up);
+    double prox = proximity_q(P, q, r, lo, up);
     double fro2 = 0.0;
     if (P->basic == ORC_BASIC_CQ)
         for (int64_t i = 0; i < P->m; ++i) fro2 += q[i];
     for (int64_t i = 0; i < P->m; ++i) {
-        double t = clampd(r[i], P->lower[i], P->upper[i]) - r[i];
+        double t = clampd(r[i], lo[i], up[i]) - r[i];
         r[i] = t; /* r now holds t */
         switch (P->basic) {
         case ORC_BASIC_CQ:
@@ -209,6 +316,8 @@ static double feas_step(const orc_problem *P, const double *q, const double *zc,
             c[i] = (q[i] > 0.0) ? P->w[i] * t / q[i] : 0.0;
         }
     }
+    free(lo);
+    free(up);
     orc_matvec_t(P, c, y);
     double sigma = 1.0;
     if (P->basic == ORC_BASIC_EL) {

@@ -676,3 +676,118 @@ def test_l1_perturbation_closed_form(orc):
     np.testing.assert_allclose(x, [3.0 - r2 - 0.5 * r2, -4.0 + r2 + 0.5 * r2, 0.0], rtol=1e-15, atol=1e-15)
     assert list(h.trials) == [1, 1] and st.ell == 2
     np.testing.assert_allclose(h.f_start, [7.0, 7.0 - math.sqrt(2.0)], rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Dose-volume constraints (Section 2.3.3) as output-space sets of the split
+# problem: the projection is the nearest point of a nonconvex set
+# ---------------------------------------------------------------------------
+
+def _identity_dvc(orc, N, sense, frac, dose, basic=0, lam=1.0, extra_rows=0):
+    """N unit rows e_j (the row value is x_j), one dose-volume group over the
+    first N rows, and `extra_rows` plain bands [-1, 1] on the same unknowns."""
+    m = N + extra_rows
+    cols = np.concatenate([np.arange(N), np.arange(extra_rows) % N])
+    lo = np.concatenate([np.full(N, -np.inf), -np.ones(extra_rows)])
+    up = np.concatenate([np.full(N, np.inf), np.ones(extra_rows)])
+    return orc.Problem(m, N, np.arange(m + 1), cols, np.ones(m), lo, up, lam=lam, basic=basic,
+                       dvc=[dict(row_begin=0, row_end=N, sense=sense, fraction=frac, dose=dose)])
+
+
+def _dvc_brute_force(d, sense, k, dose):
+    """Nearest point of {at most k values above dose} (MAX) or {at least k
+    values at or above dose} (MIN) to d, by enumerating which values change."""
+    N = d.size
+    best, arg = np.inf, None
+    for T in itertools.chain.from_iterable(itertools.combinations(range(N), r) for r in range(N + 1)):
+        T = list(T)
+        p = d.copy()
+        if sense == W.DVC_MAX:
+            if len(T) > k:  # T = the values allowed above dose
+                continue
+            keep = np.zeros(N, bool)
+            keep[T] = True
+            p[~keep] = np.minimum(p[~keep], dose)
+        else:
+            if len(T) < k:  # T = the values required at or above dose
+                continue
+            p[T] = np.maximum(p[T], dose)
+        dist = float(np.sum((p - d) ** 2))
+        if dist < best - 1e-15:
+            best, arg = dist, p
+    return best, arg
+
+
+@pytest.mark.parametrize("sense", [0, 1])
+def test_dvc_projection_is_nearest_point(orc, sense):
+    """The proximity of a dose-volume group of unit rows is half the weighted
+    squared distance to the nearest point of its set, found by brute force over
+    which values change; one DROP step with lambda = N (unit columns, D = 1/N)
+    lands on that point exactly."""
+    rng = np.random.default_rng(90 + sense)
+    for trial in range(40):
+        N = int(rng.integers(1, 8))
+        frac = float(rng.choice([0.0, 0.05, 0.3, 0.5, 0.95, 1.0, rng.uniform()]))
+        dose = float(rng.uniform(0.2, 0.8))
+        d = rng.uniform(0.0, 1.0, N)
+        P = _identity_dvc(orc, N, sense, frac, dose)
+        k = P.dvc_count(0)
+        assert k == (math.floor(frac * N) if sense == W.DVC_MAX else math.ceil(frac * N))
+        best, p = _dvc_brute_force(d, sense, k, dose)
+        assert 2 * N * P.proximity(d) == pytest.approx(best, rel=1e-12, abs=1e-15), (trial, N, frac)
+        Pd = _identity_dvc(orc, N, sense, frac, dose, basic=W.BASIC_DROP, lam=float(N))
+        x1, _ = Pd.step(d)
+        np.testing.assert_allclose(x1, p, rtol=0, atol=1e-15)
+
+
+def test_dvc_ties_rank_by_row_index(orc):
+    """Equal values rank by row index: at x = 0 a 'at least 3 of 6 at or above
+    1' group raises the first three rows; 'at most 2 of 6 above 0.5' at equal
+    values 0.8 keeps the first two."""
+    P = _identity_dvc(orc, 6, W.DVC_MIN, 0.5, 1.0, basic=W.BASIC_DROP, lam=6.0)
+    x1, prox = P.step(np.zeros(6))
+    np.testing.assert_array_equal(x1, [1, 1, 1, 0, 0, 0])
+    assert prox == pytest.approx(0.5 * 3 / 6)
+    P = _identity_dvc(orc, 6, W.DVC_MAX, 2 / 6, 0.5, basic=W.BASIC_DROP, lam=6.0)
+    x1, _ = P.step(np.full(6, 0.8))
+    np.testing.assert_allclose(x1, [0.8, 0.8, 0.5, 0.5, 0.5, 0.5], rtol=0, atol=1e-15)
+    lo, up = P.bands_at(np.full(6, 0.8))
+    np.testing.assert_array_equal(up, [np.inf, np.inf, 0.5, 0.5, 0.5, 0.5])
+    assert np.all(lo == -np.inf)
+
+
+def test_dvc_limits_reduce_to_bands(orc):
+    """V = 0 of 'at most' is the plain band (-inf, d]; V = 1 of 'at least' is
+    [d, +inf); V = 1 of 'at most' and V = 0 of 'at least' constrain nothing.
+    Compared against plain band rows through a whole perturbed run on a
+    random operator with other band rows."""
+    rng = np.random.default_rng(95)
+    m0, n, N = 30, 12, 10
+    A = rng.uniform(0, 1, (m0 + N, n)) * (rng.uniform(size=(m0 + N, n)) < 0.5)
+    A[m0:] = A[:N]  # the group's rows repeat rows 0..N-1
+    lo0 = rng.uniform(0.5, 1.0, m0)
+    up0 = lo0 + rng.uniform(0.1, 1.0, m0)
+    x0 = rng.uniform(0, 1, n)
+    for sense, frac, blo, bup in ((W.DVC_MAX, 0.0, -np.inf, 0.7), (W.DVC_MIN, 1.0, 0.7, np.inf),
+                                  (W.DVC_MAX, 1.0, -np.inf, np.inf), (W.DVC_MIN, 0.0, -np.inf, np.inf)):
+        lo = np.concatenate([lo0, np.full(N, -np.inf)])
+        up = np.concatenate([up0, np.full(N, np.inf)])
+        kw = dict(obj=W.OBJ_SQNORM, box_lo=np.zeros(n), box_hi=np.full(n, 2.0), lam=1.5, n_red=2)
+        Pg = _dense_problem(orc, A, lo, up, dvc=[dict(row_begin=m0, row_end=m0 + N, sense=sense, fraction=frac,
+                                                      dose=0.7)], **kw)
+        Pb = _dense_problem(orc, A, np.concatenate([lo0, np.full(N, blo)]), np.concatenate([up0, np.full(N, bup)]),
+                            **kw)
+        xg, sg, hg = Pg.run(x0, 15)
+        xb, sb, hb = Pb.run(x0, 15)
+        np.testing.assert_allclose(xg, xb, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(hg.prox, hb.prox, rtol=1e-13)
+        assert sg.trials == sb.trials
+
+
+def test_dvc_rank_uses_float32_values(orc):
+    """Values equal in float32 but not in float64 rank by row index: 0.6 and
+    0.6 + 1e-12 on rows 0 and 1 of an 'at most 1 of 2 above 0.5' group keep
+    row 0 (the lower float64 value)."""
+    P = _identity_dvc(orc, 2, W.DVC_MAX, 0.5, 0.5)
+    lo, up = P.bands_at(np.array([0.6, 0.6 + 1e-12]))
+    np.testing.assert_array_equal(up, [np.inf, 0.5])

@@ -22,6 +22,7 @@ import numpy as np
 
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
+DVC_MAX, DVC_MIN = 0, 1  # dose-volume constraint senses: D_V <= d, D_V >= d
 OBJ_NAMES = {OBJ_NONE: "none", OBJ_SQNORM: "sqnorm", OBJ_TV2D: "tv2d", OBJ_LINEAR: "linear", OBJ_L1: "l1"}
 
 
@@ -61,6 +62,9 @@ class Workload:
     weights: Optional[np.ndarray] = None  # float64 [m]; None means uniform 1/m
     basic: int = 0  # BASIC_*: the feasibility-seeking step
     stop: Optional[dict] = None  # stopping rules: prox, dprox, n, max_iters, dobj, var (None: fixed K)
+    # dose-volume constraints: dicts with row_begin, row_end (the structure's
+    # rows), sense (DVC_MAX / DVC_MIN), fraction (V) and dose (d)
+    dvc: Optional[list] = None
     x_true: Optional[np.ndarray] = None  # float32 [n, B]
     meta: dict = field(default_factory=dict)
 
@@ -490,6 +494,52 @@ def fresnel_matrix(N: int, n_src: int, n_rec: int, wavelength: float = 1.0, w0: 
     return row_ptr.astype(np.int32), np.concatenate(cols_all).astype(np.int32), np.concatenate(vals_all)
 
 
+def with_dvc(w: "Workload", groups) -> "Workload":
+    """Append one dose-volume constraint per entry of ``groups`` =
+    [(rows, sense, fraction, dose), ...]: the rows ``rows`` of A are copied, in
+    order, to the end of A as the structure's block, with placeholder bands
+    (-inf, +inf) that the constraint replaces at every point."""
+    rp = np.asarray(w.row_ptr, np.int64)
+    cols, vals = [np.asarray(w.col_idx)], [np.asarray(w.val)]
+    counts = [np.diff(rp)]
+    dvc = list(w.dvc or [])
+    m = w.m
+    for rows, sense, fraction, dose in groups:
+        rows = np.asarray(rows, np.int64)
+        take = np.concatenate([np.arange(rp[i], rp[i + 1]) for i in rows]) if rows.size else np.zeros(0, np.int64)
+        cols.append(np.asarray(w.col_idx)[take])
+        vals.append(np.asarray(w.val)[take])
+        counts.append(rp[rows + 1] - rp[rows])
+        dvc.append(dict(row_begin=m, row_end=m + rows.size, sense=int(sense), fraction=float(fraction),
+                        dose=float(dose)))
+        m += rows.size
+    row_ptr = np.zeros(m + 1, np.int64)
+    np.cumsum(np.concatenate(counts), out=row_ptr[1:])
+    assert row_ptr[-1] < 2**31
+    extra = m - w.m
+    pad_lo = np.full((extra, w.B), -np.inf, np.float32)
+    pad_up = np.full((extra, w.B), np.inf, np.float32)
+    weights = None
+    if w.weights is not None:
+        weights = np.concatenate([np.asarray(w.weights, np.float64),
+                                  np.full(extra, float(np.mean(w.weights)))])
+    return replace(w, name=w.name + "_dvc", m=m, row_ptr=row_ptr.astype(np.int32),
+                   col_idx=np.concatenate(cols).astype(np.int32), val=np.concatenate(vals).astype(np.float32),
+                   lower=np.concatenate([w.lower, pad_lo]), upper=np.concatenate([w.upper, pad_up]),
+                   weights=weights, dvc=dvc)
+
+
+def rt_with_dvc(w: "Workload", basic: int = BASIC_EMR) -> "Workload":
+    """A radiotherapy workload with the dose-volume constraints of the paper's
+    horseshoe plan (Section 2.3.3) on the scale of a mean target dose of 1
+    (2.1 Gy): target D95% >= 0.97, target D5% <= 1.03, organ-at-risk D5% <=
+    0.16; the EMR step (the paper's choice for this case) and the horseshoe's
+    power law (gamma = 1, alpha = 0.7, restarts every 500 iterations)."""
+    t, o = w.meta["target_rows"], w.meta["oar_rows"]
+    out = with_dvc(w, [(t, DVC_MIN, 0.95, 0.97), (t, DVC_MAX, 0.05, 1.03), (o, DVC_MAX, 0.05, 0.16)])
+    return out.with_params(basic=basic, gamma=1.0, alpha=0.7, restart_every=500)
+
+
 def synthetic_iterate(w: "Workload", seed: int, spread: float = 0.1) -> np.ndarray:
     """A seeded point of the kind an iteration passes through: the true
     solution (0.5 where none is known) times (1 + spread * N(0, 1)), clipped
@@ -714,7 +764,8 @@ def rt(
     vals = V[ok].astype(np.float32)
     lower = lo.astype(np.float64)
     upper = up.astype(np.float64)
-    meta = dict(n_target=int(target.sum()), n_oar=int(oar.sum()), n_overlap=int(overlap.sum()))
+    meta = dict(n_target=int(target.sum()), n_oar=int(oar.sum()), n_overlap=int(overlap.sum()),
+                target_rows=np.nonzero(target)[0], oar_rows=np.nonzero(oar)[0])
     if infeasible and overlap.any():
         dup = np.nonzero(overlap)[0]
         lower[dup] = 0.95
@@ -891,7 +942,8 @@ def rt_large(
     up = np.where(target & ~oar, 1.07, up)
     c = np.bincount(cols, weights=val32.astype(np.float64), minlength=n)
     lower, upper = lo.astype(np.float64), up.astype(np.float64)
-    meta = dict(n_target=int(target.sum()), n_oar=int(oar.sum()), n_overlap=int(overlap.sum()))
+    meta = dict(n_target=int(target.sum()), n_oar=int(oar.sum()), n_overlap=int(overlap.sum()),
+                target_rows=np.nonzero(target)[0], oar_rows=np.nonzero(oar)[0])
     if infeasible and overlap.any():
         dup = np.nonzero(overlap)[0]
         lower[dup] = 0.95
