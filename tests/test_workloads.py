@@ -83,7 +83,9 @@ def test_rt_cpp_generator_matches_numpy_model():
         assert np.array_equal(getattr(a, f), getattr(b, f)), f
     np.testing.assert_allclose(b.val, a.val, rtol=1e-6)
     np.testing.assert_allclose(b.linear_c, a.linear_c, rtol=1e-6)
-    assert a.meta == b.meta
+    assert a.meta.keys() == b.meta.keys()
+    for k in a.meta:
+        assert np.array_equal(a.meta[k], b.meta[k]), k
 
 
 def test_rt_infeasible_rows_conflict():
