@@ -99,6 +99,32 @@ typedef struct {
     int32_t on_device;      /* 0: host pointers, 1: device pointers */
 } smx_csr;
 
+/*
+ * Dose-volume constraint (Section 2.3.3) on a structure whose voxels are the
+ * rows [row_begin, row_end) of A, N = row_end - row_begin of them.
+ * SMX_DVC_MAX (D_V <= dose): at most k = floor(fraction * N) rows may lie above
+ * dose.  SMX_DVC_MIN (D_V >= dose): at least k = ceil(fraction * N) rows must
+ * reach dose.  Such a constraint is a set in the output space of the split
+ * problem (eq. Split); at every point its rows are ranked by <a_i, x> rounded
+ * to float32, highest first, equal values by row index, and the nearest point
+ * of the set gives the k highest rows the band (-inf, +inf) (MAX) or
+ * [dose, +inf) (MIN) and the others (-inf, dose] (MAX) or (-inf, +inf) (MIN).
+ * These bands take the place of the rows' lower/upper entries, which are
+ * ignored; the rows otherwise take part in the step and the proximity like any
+ * other row (weights, D, the basic algorithm).
+ */
+typedef struct {
+    int64_t row_begin, row_end; /* 0 <= row_begin < row_end <= m */
+    int32_t sense;              /* SMX_DVC_MAX or SMX_DVC_MIN */
+    int32_t reserved;           /* 0 */
+    double fraction;            /* V, in [0, 1] */
+    double dose;                /* d, finite */
+} smx_dvc;
+
+#define SMX_DVC_MAX 0
+#define SMX_DVC_MIN 1
+#define SMX_MAX_DVC 16 /* constraints per problem */
+
 /* Everything about one problem except A.  All arrays are copied at creation. */
 typedef struct {
     int32_t B;               /* slices sharing A: a power of two, 1..32 */
@@ -144,6 +170,13 @@ typedef struct {
     double stop_dprox;       /* Delta P* */
     double stop_dobj;        /* Delta f* */
     double stop_var;         /* >= 0; 0 disables the variance rule */
+    /* Dose-volume constraints (host array of n_dvc entries, 0..SMX_MAX_DVC):
+     * their row blocks follow one another (dvc[g+1].row_begin ==
+     * dvc[g].row_end).  A problem with any runs the two passes (never the
+     * fused pass). */
+    int32_t n_dvc;
+    int32_t reserved_dvc;    /* 0 */
+    const smx_dvc *dvc;
 } smx_problem_desc;
 
 /* Per-slice iteration state, as checkpointed by smx_get_state. */
@@ -216,7 +249,9 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
  * lower > upper or NaN bound, a weight <= 0 or non-finite, box_lo > box_hi,
  * lambda outside its range, an unknown basic algorithm, gamma <= 0, alpha
  * outside (0,1), n_red < 1, max_trials outside 1..1024, TV with rows*cols !=
- * n, LINEAR with a NULL c.  EL and EMR keep y (n*B floats) and run the two
+ * n, LINEAR with a NULL c, dose-volume constraints whose row blocks are empty,
+ * outside [0, m) or not consecutive, whose fraction is outside [0, 1], whose
+ * dose is not finite or whose sense is unknown.  EL and EMR keep y (n*B floats) and run the two
  * passes (never the fused pass); EMR adds a third pass over A per iteration.
  */
 int smx_problem_create(smx_operator *op, const smx_problem_desc *desc, void *stream, smx_problem **out);

@@ -21,6 +21,7 @@ STORE = {"f32": 0, "bf16": 1, "f16": 2}
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 STOP_NONE, STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 0, 1, 2, 3, 4, 5
+DVC_MAX, DVC_MIN = 0, 1  # dose-volume constraints: D_V <= dose, D_V >= dose
 RUN_PERTURB, RUN_GRAPH = 1, 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
@@ -78,6 +79,17 @@ class Csr(C.Structure):
     ]
 
 
+class DvcC(C.Structure):
+    _fields_ = [
+        ("row_begin", C.c_int64),
+        ("row_end", C.c_int64),
+        ("sense", C.c_int32),
+        ("reserved", C.c_int32),
+        ("fraction", C.c_double),
+        ("dose", C.c_double),
+    ]
+
+
 class ProblemDesc(C.Structure):
     _fields_ = [
         ("B", C.c_int32),
@@ -108,6 +120,9 @@ class ProblemDesc(C.Structure):
         ("stop_dprox", C.c_double),
         ("stop_dobj", C.c_double),
         ("stop_var", C.c_double),
+        ("n_dvc", C.c_int32),
+        ("reserved_dvc", C.c_int32),
+        ("dvc", C.POINTER(DvcC)),
     ]
 
 
@@ -269,7 +284,9 @@ class Problem:
     def __init__(self, op: Operator, lower, upper, box_lo=None, box_hi=None, weights=None, lam=1.0,
                  obj=OBJ_NONE, tv_rows=0, tv_cols=0, tv_eps=0.0, linear_c=None, gamma=1.0, alpha=0.99,
                  n_red=1, restart_every=0, max_trials=100, refine_iters=-1, history_cap=0, B=None,
-                 device="cuda", stream=None, basic=0, stop=None):
+                 device="cuda", stream=None, basic=0, stop=None, dvc=None):
+        """dvc: dose-volume constraints, dicts with row_begin, row_end, sense
+        (DVC_MAX / DVC_MIN), fraction and dose; their row blocks consecutive."""
         import torch
 
         self.op = op
@@ -300,6 +317,13 @@ class Problem:
             d.stop_dprox = float(stop.get("dprox", 1e-8))
             d.stop_dobj = float(stop.get("dobj", 1e-6))
             d.stop_var = float(stop.get("var", 0.0))
+        if dvc:
+            tab = (DvcC * len(dvc))()
+            for i, g in enumerate(dvc):
+                tab[i] = DvcC(row_begin=int(g["row_begin"]), row_end=int(g["row_end"]), sense=int(g["sense"]),
+                              fraction=float(g["fraction"]), dose=float(g["dose"]))
+            d.n_dvc = len(dvc)
+            d.dvc = C.cast(tab, C.POINTER(DvcC))
         self.history_cap = int(history_cap)
         self.obj = int(obj)
         h = C.c_void_p()
@@ -475,6 +499,7 @@ def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device=
         tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
         n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
         refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0), stop=getattr(w, "stop", None),
+        dvc=getattr(w, "dvc", None),
     )
     kw.update(overrides)
     p = Problem(op, device=device, **kw)

@@ -234,11 +234,30 @@ struct smx_problem {
     DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
     bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
     DBuf xprev, part_var;
+    // dose-volume constraints: their rows' values, keys, per-constraint
+    // histograms and selection state, and the band kernel's partials
+    DvcTable dvc{};
+    DBuf dvc_dose, dvc_key, dvc_hist, dvc_sel, dvc_part;
     RowW row_weights(int vk) const
     {
         const float *D = (vk == VK_F32) ? D32.as<float>() : D16.as<float>();
         const float *S = (vk == VK_F32) ? S32.as<float>() : S16.as<float>();
-        return RowW{D, S ? S : D, 0};
+        RowW r{D, S ? S : D, 0, nullptr, 0, 0};
+        if (dvc.n > 0) {
+            r.dose = dvc_dose.as<double>();
+            r.dose_lo = dvc.lo;
+            r.dose_hi = dvc.lo + dvc.span;
+        }
+        return r;
+    }
+    // the dose-volume kernels after pass 1 (partials: pass 1's, nparts1 per slice)
+    void enqueue_dvc(int vk, double *partials, int nparts1, int which, int query, hipStream_t s)
+    {
+        const RowW rw = row_weights(vk);
+        hip_check(launch_dvc(dvc, dvc_dose.as<double>(), dvc_key.as<unsigned long long>(), dvc_hist.as<unsigned>(),
+                             dvc_sel.as<DvcSel>(), rw.D, rw.S, c.as<float>(), dvc_part.as<double>(), partials,
+                             nparts1, state(which), B, query, s),
+                  "dose-volume constraints");
     }
     ColStep col_step(bool defer) const
     {
@@ -525,10 +544,9 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
                            p->state(cur), p->B, 0,
                            p->part_pass.as<double>(), s),
               "pass 1");
-    if (timed) {
-        hip_check(hipEventRecord(e[1], s), "event");
-        hip_check(hipEventRecord(e[2], s), "event");
-    }
+    if (timed) hip_check(hipEventRecord(e[1], s), "event");
+    if (p->dvc.n > 0) p->enqueue_dvc(vk, p->part_pass.as<double>(), p->cfg1[vk].grid, cur, 0, s);
+    if (timed) hip_check(hipEventRecord(e[2], s), "event");
     const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
     hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
                            p->c.as<float>(), p->x.as<float>(), p->col_step(extrap), p->state(cur), p->state(cur ^ 1),
@@ -690,8 +708,9 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
 // workgroups per CU, as many as the LDS allows.
 void setup_fused(smx_problem *p)
 {
-    // the extrapolated steps need ||y|| (and EMR A y) before x moves: two passes
-    if (p->B != 1 || p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR) return;
+    // the extrapolated steps need ||y|| (and EMR A y) before x moves, and the
+    // dose-volume rows their ranking before c: two passes
+    if (p->B != 1 || p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR || p->dvc.n > 0) return;
     const size_t lim = fused_lds_limit();
     int acc64 = -1;
     if (fused_lds_bytes(p->n, 1) <= lim) acc64 = 1;
@@ -763,6 +782,39 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
             return fail(SMX_EINVAL, "invalid stopping thresholds");
         sp = StopParams{1, d->stop_n, (long long)d->stop_max_iters, d->stop_prox, d->stop_dprox, d->stop_dobj,
                         d->stop_var};
+    }
+    DvcTable dt{};
+    if (d->n_dvc < 0 || d->n_dvc > kMaxDvc || (d->n_dvc > 0 && !d->dvc))
+        return fail(SMX_EINVAL, "n_dvc must be in 0..%d with a table", kMaxDvc);
+    dt.n = d->n_dvc;
+    for (int g = 0; g < dt.n; ++g) {
+        const smx_dvc &G = d->dvc[g];
+        if (!(G.row_begin >= 0 && G.row_begin < G.row_end && G.row_end <= m))
+            return fail(SMX_EINVAL, "dose-volume constraint %d: rows [%lld, %lld) not a nonempty block of [0, %lld)", g,
+                        (long long)G.row_begin, (long long)G.row_end, (long long)m);
+        if (g > 0 && G.row_begin != d->dvc[g - 1].row_end)
+            return fail(SMX_EINVAL, "dose-volume constraint %d does not start where constraint %d ends", g, g - 1);
+        if (G.sense != SMX_DVC_MAX && G.sense != SMX_DVC_MIN)
+            return fail(SMX_EINVAL, "dose-volume constraint %d: unknown sense %d", g, G.sense);
+        if (!(G.fraction >= 0.0 && G.fraction <= 1.0))
+            return fail(SMX_EINVAL, "dose-volume constraint %d: fraction must be in [0, 1]", g);
+        if (!std::isfinite(G.dose)) return fail(SMX_EINVAL, "dose-volume constraint %d: dose must be finite", g);
+        if (G.row_end - G.row_begin > (int64_t)0xFFFFFFFFll)
+            return fail(SMX_EINVAL, "dose-volume constraint %d: too many rows", g);
+        const int64_t N = G.row_end - G.row_begin;
+        const double kv = (G.sense == SMX_DVC_MAX) ? std::floor(G.fraction * (double)N) : std::ceil(G.fraction * (double)N);
+        dt.begin[g] = G.row_begin;
+        dt.end[g] = G.row_end;
+        dt.k[g] = (long long)std::min<double>(std::max(kv, 0.0), (double)N);
+        dt.dose[g] = G.dose;
+        dt.sense[g] = G.sense == SMX_DVC_MAX ? 0 : 1;
+        dt.blk_begin[g + 1] = dt.blk_begin[g] + (int)((N + kDvcChunk - 1) / kDvcChunk);
+    }
+    if (dt.n > 0) {
+        dt.nblk = dt.blk_begin[dt.n];
+        dt.lo = dt.begin[0];
+        dt.span = dt.end[dt.n - 1] - dt.begin[0];
+        if (dt.nblk > 65535) return fail(SMX_EINVAL, "dose-volume constraints hold too many rows");
     }
     const bool dev = d->on_device != 0;
     std::vector<float> lo = fetch(d->lower, m * B, dev), up = fetch(d->upper, m * B, dev);
@@ -887,6 +939,17 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     for (int vk = 0; vk < 3; ++vk) {
         p->cfg1[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk, B);
         p->cfg2[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csc, vk) : pick_cfg(op->csc, vk, B);
+    }
+    p->dvc = dt;
+    if (dt.n > 0) {
+        p->dvc_dose.alloc(sizeof(double) * size_t(dt.span) * B, "dose-volume rows");
+        p->dvc_key.alloc(sizeof(unsigned long long) * size_t(dt.span) * B, "dose-volume keys");
+        p->dvc_hist.alloc(sizeof(unsigned) * size_t(kDvcBins) * dt.n * B, "dose-volume histograms");
+        hip_check(hipMemsetAsync(p->dvc_hist.p, 0, sizeof(unsigned) * size_t(kDvcBins) * dt.n * B, s),
+                  "dose-volume histograms");
+        p->dvc_sel.alloc(sizeof(DvcSel) * dt.n * B, "dose-volume selection");
+        hip_check(hipMemsetAsync(p->dvc_sel.p, 0, sizeof(DvcSel) * dt.n * B, s), "dose-volume selection");
+        p->dvc_part.alloc(sizeof(double) * size_t(dt.nblk) * B, "dose-volume partials");
     }
     setup_fused(p.get());
     // per-workgroup partial sums of each kernel kind
@@ -1115,10 +1178,11 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         out += tmp;
         first = false;
     }
-    char tail[160];
+    char tail[192];
     static const char *basics[5] = {"simult", "drop", "cq", "el", "emr"};
-    snprintf(tail, sizeof tail, ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\"}",
-             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic]);
+    snprintf(tail, sizeof tail,
+             ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\", \"dose_volume\": %d}",
+             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic], p->dvc.n);
     out += tail;
     if (need) *need = out.size() + 1;
     if (buf && cap > 0) {
@@ -1276,14 +1340,16 @@ int smx_query(smx_problem *p, double *proximity, double *objective)
     SMX_GUARD({
         const int B = p->B;
         const int vk = p->op->has_f32 ? VK_F32 : p->op->lp_kind();
-        const float *D = (vk == VK_F32) ? p->D32.as<float>() : p->D16.as<float>();
+        RowW qw = p->row_weights(vk); // the proximity terms D t^2 (c is scratch here)
+        qw.S = qw.D;
         double *q = p->qout.as<double>();
         hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
-                               p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), RowW{D, D, 0},
+                               p->x.as<float>(), p->lower.as<float>(), p->upper.as<float>(), qw,
                                p->c.as<float>(),
                                p->state(p->cur), B, 1,
                                p->part_query.as<double>(), p->stream),
                   "query proximity");
+        if (p->dvc.n > 0) p->enqueue_dvc(vk, p->part_query.as<double>(), p->cfg1[vk].grid, p->cur, 1, p->stream);
         hip_check(launch_query_prox(p->state(p->cur), B, p->part_query.as<double>(), p->cfg1[vk].grid, q,
                                     p->stream),
                   "query proximity");

@@ -300,12 +300,19 @@ __device__ inline double group_sum(double v)
 // sum S r^2)
 // ---------------------------------------------------------------------------
 
-// Pass-1 epilogue of one row from r = <a_i, v>: returns the row's partial term
-// and stores c_i (not in quadratic-form mode).  With S = D this is exactly
-// c_i = D_i t_i and the term D_i t_i^2.
-__device__ inline double epi1(const RowW &w, double r, float lo, float up, float d, float sw, float *c)
+// Pass-1 epilogue of row `row` (slice s of B) from r = <a_i, v>: returns the
+// row's partial term and stores c_i (not in quadratic-form mode).  With S = D
+// this is exactly c_i = D_i t_i and the term D_i t_i^2.  A dose-volume row
+// only keeps r: its bands are set after the pass, and the dose-volume kernels
+// write its c_i and its proximity term.
+__device__ inline double epi1(const RowW &w, double r, float lo, float up, float d, float sw, float *c,
+                              long long row, int s, int B)
 {
     if (w.qform) return (double)sw * r * r;
+    if (w.dose && row >= w.dose_lo && row < w.dose_hi) {
+        w.dose[(row - w.dose_lo) * B + s] = r;
+        return 0.0;
+    }
     const double t = fmin(fmax(r, (double)lo), (double)up) - r;
     const double dt = (double)d * t;
     *c = (float)((double)sw * t);
@@ -337,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
                 sw = w.S[row];
             }
             const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
-            if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row);
+            if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
         }
     }
     block_sum<1>(pacc, lds);
@@ -437,7 +444,8 @@ __global__ __launch_bounds__(kBlock) void k_pass1_stream(SpView A, RowBlocks RB,
             if (e1 - e0 > kStreamEntries) {
                 const double sum = long_row_sum<VEC, VT>(A, e0, e1, x, lds);
                 if (threadIdx.x == 0)
-                    pacc[0] += epi1(w, sum * (double)A.vscale_inv, lower[r0], upper[r0], w.D[r0], w.S[r0], c + r0);
+                    pacc[0] += epi1(w, sum * (double)A.vscale_inv, lower[r0], upper[r0], w.D[r0], w.S[r0], c + r0,
+                                    r0, 0, 1);
                 continue;
             }
             const int nr = r1 - r0;
@@ -457,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_stream(SpView A, RowBlocks RB,
             if (rs.rl < nr)
                 for (int q = rp[rs.rl] + rs.lane; q < rp[rs.rl + 1]; q += rs.G) s += prod[q];
             s = group_sum_rt(s, rs.G);
-            if (owner) pacc[0] += epi1(w, s * (double)A.vscale_inv, lo, up, d, sw, c + r0 + rs.rl);
+            if (owner) pacc[0] += epi1(w, s * (double)A.vscale_inv, lo, up, d, sw, c + r0 + rs.rl, r0 + rs.rl, 0, 1);
             __syncthreads();
         }
     }
@@ -1065,7 +1073,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_mm(SpView A, const float *__re
             for (int s = 0; s < B; ++s) {
                 if (!live[s]) continue;
                 pacc[s] += epi1(w, acc[s] * (double)A.vscale_inv, lower[row * B + s], upper[row * B + s], d, sw,
-                                c + row * B + s);
+                                c + row * B + s, row, s, B);
             }
         }
     }
@@ -2207,6 +2215,226 @@ hipError_t launch_step_apply(int64_t n, int B, const double *y, float *x, const 
                        nparts1, party, npartsy, partq, npartsq, st_in, st_out, h);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Dose-volume constraints (Section 2.3.3): sets in the output space of the
+// split problem (eq. Split).  A constraint owns the rows of one structure;
+// "at most k of them above d" (k = floor(V N)) or "at least k at or above d"
+// (k = ceil(V N)).  Its nearest point keeps (MAX) or raises to d (MIN) the k
+// highest values and lowers the other values above d to d (MAX) or keeps them
+// (MIN); as bands, the k highest rows get (-inf, inf) / [d, inf) and the
+// others (-inf, d] / (-inf, inf).  Rows rank by the float32-rounded value,
+// equal values by row.  Pass 1 stores the rows' values; a radix select over
+// 64-bit keys (value bits, then the complement of the row's position) finds
+// the k-th highest key; the band kernel then forms c_i and the proximity
+// terms, and a one-workgroup kernel per slice adds their sum to pass 1's
+// partial 0.  Histogram counts are integers, so their atomic sums are exact.
+// ---------------------------------------------------------------------------
+
+__device__ inline int dvc_group(const DvcTable &T, int blk)
+{
+    int g = 0;
+    while (g + 1 < T.n && blk >= T.blk_begin[g + 1]) ++g;
+    return g;
+}
+
+__device__ inline int dvc_shift(int round) { return round < kDvcRounds - 1 ? 53 - 11 * round : 0; }
+__device__ inline int dvc_bits(int round) { return round < kDvcRounds - 1 ? 11 : 9; }
+
+// Order-preserving key of a value rounded to float32 (higher value, higher
+// key; -0 counts as +0) with the row's position i in its block.
+__device__ inline unsigned long long dvc_key(double r, long long i)
+{
+    float f = (float)r;
+    if (f == 0.0f) f = 0.0f;
+    const unsigned u = __float_as_uint(f);
+    const unsigned o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((unsigned long long)o << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+}
+
+__device__ inline bool dvc_slice_runs(const SliceState *st, int s, int query) { return query || st[s].live != 0; }
+
+// One histogram round: the digit of every candidate key of each constraint
+// (round 0: every row, whose key it also stores; later rounds: the keys that
+// share the digits fixed so far) into hist[(g * B + s) * kDvcBins + digit].
+__global__ __launch_bounds__(kBlock) void k_dvc_hist(DvcTable T, int round, const double *__restrict__ dose,
+                                                     unsigned long long *__restrict__ key, unsigned *__restrict__ hist,
+                                                     const DvcSel *__restrict__ sel,
+                                                     const SliceState *__restrict__ st, int B, int query)
+{
+    __shared__ unsigned h[kDvcBins];
+    const int s = blockIdx.y;
+    if (!dvc_slice_runs(st, s, query)) return;
+    const int g = dvc_group(T, blockIdx.x);
+    const DvcSel S = sel[g * B + s];
+    if (round > 0 && S.mode != 0) return;
+    for (int b = threadIdx.x; b < kDvcBins; b += kBlock) h[b] = 0u;
+    __syncthreads();
+    const long long N = T.end[g] - T.begin[g];
+    const long long i0 = (long long)(blockIdx.x - T.blk_begin[g]) * kDvcChunk;
+    const long long i1 = i0 + kDvcChunk < N ? i0 + kDvcChunk : N;
+    const int shift = dvc_shift(round);
+    const unsigned mask = (1u << dvc_bits(round)) - 1u;
+    const int pshift = shift + dvc_bits(round); // the digits above this round's
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const long long at = (T.begin[g] + i - T.lo) * B + s;
+        unsigned long long kk;
+        if (round == 0) {
+            kk = dvc_key(dose[at], i);
+            key[at] = kk;
+        } else {
+            kk = key[at];
+            if ((kk >> pshift) != S.prefix) continue;
+        }
+        atomicAdd(&h[(unsigned)(kk >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    unsigned *H = hist + (size_t)(g * B + s) * kDvcBins;
+    for (int b = threadIdx.x; b < kDvcBins; b += kBlock)
+        if (h[b]) atomicAdd(&H[b], h[b]);
+}
+
+// One workgroup per constraint and slice: the digit that holds the k-th
+// highest key among the candidates, from the highest digit down; then the
+// histogram is cleared for the next round.  The selection ends once every
+// candidate of that digit ranks high (or after the last round, where a digit
+// holds one key).
+__global__ __launch_bounds__(kBlock) void k_dvc_pick(DvcTable T, int round, unsigned *__restrict__ hist,
+                                                     DvcSel *__restrict__ sel, const SliceState *__restrict__ st,
+                                                     int B, int query)
+{
+    __shared__ unsigned long long suf[kBlock];
+    const int g = blockIdx.x, s = blockIdx.y;
+    if (!dvc_slice_runs(st, s, query)) return;
+    DvcSel *S = sel + (g * B + s);
+    if (round > 0 && S->mode != 0) return;
+    unsigned *H = hist + (size_t)(g * B + s) * kDvcBins;
+    constexpr int PER = kDvcBins / kBlock;
+    const long long N = T.end[g] - T.begin[g], k = T.k[g];
+    unsigned cnt[PER];
+    unsigned long long tsum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        cnt[j] = H[threadIdx.x * PER + j];
+        tsum += cnt[j];
+    }
+    if (round == 0 && (k <= 0 || k >= N)) {
+        if (threadIdx.x == 0) {
+            S->mode = k <= 0 ? 1 : 3;
+            S->prefix = 0;
+            S->thr = 0;
+            S->krem = 0;
+        }
+    } else {
+        const long long krem = round == 0 ? k : S->krem;
+        const unsigned long long prefix = round == 0 ? 0ull : S->prefix;
+        // suffix sums over threads: suf[t] = counts of bins >= t * PER
+        suf[threadIdx.x] = tsum;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const unsigned long long v = suf[threadIdx.x] + (threadIdx.x + off < kBlock ? suf[threadIdx.x + off] : 0ull);
+            __syncthreads();
+            suf[threadIdx.x] = v;
+            __syncthreads();
+        }
+        const long long incl = (long long)suf[threadIdx.x], excl = incl - (long long)tsum;
+        if (excl < krem && krem <= incl) {
+            long long above = excl;
+            int dig = threadIdx.x * PER;
+            long long kr = 0;
+            unsigned c_dig = 0;
+            for (int j = PER - 1; j >= 0; --j) {
+                if (above + (long long)cnt[j] >= krem) {
+                    dig = threadIdx.x * PER + j;
+                    kr = krem - above;
+                    c_dig = cnt[j];
+                    break;
+                }
+                above += cnt[j];
+            }
+            const unsigned long long np = (prefix << dvc_bits(round)) | (unsigned long long)dig;
+            if ((long long)c_dig == kr || round == kDvcRounds - 1) {
+                S->mode = 2;
+                S->thr = np << dvc_shift(round);
+            } else {
+                S->mode = 0;
+                S->prefix = np;
+                S->krem = kr;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) H[threadIdx.x * PER + j] = 0u;
+}
+
+// The bands the selection gives, c_i = S_i t_i and per-workgroup partials of
+// the proximity terms D_i t_i^2 in epart[s * nblk + workgroup].
+__global__ __launch_bounds__(kBlock) void k_dvc_bands(DvcTable T, const double *__restrict__ dose,
+                                                      const unsigned long long *__restrict__ key,
+                                                      const DvcSel *__restrict__ sel, const float *__restrict__ D,
+                                                      const float *__restrict__ Sw, float *__restrict__ c,
+                                                      double *__restrict__ epart, const SliceState *__restrict__ st,
+                                                      int B, int query)
+{
+    __shared__ double lds[4];
+    const int s = blockIdx.y;
+    if (!dvc_slice_runs(st, s, query)) return;
+    const int g = dvc_group(T, blockIdx.x);
+    const DvcSel S = sel[g * B + s];
+    const long long N = T.end[g] - T.begin[g];
+    const long long i0 = (long long)(blockIdx.x - T.blk_begin[g]) * kDvcChunk;
+    const long long i1 = i0 + kDvcChunk < N ? i0 + kDvcChunk : N;
+    const double dref = T.dose[g];
+    const bool upper_kind = T.sense[g] == 0;
+    double pacc[1] = {0.0};
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const long long row = T.begin[g] + i;
+        const long long at = (row - T.lo) * B + s;
+        const double r = dose[at];
+        const bool high = S.mode == 3 || (S.mode == 2 && key[at] >= S.thr);
+        double lo = -INFINITY, up = INFINITY;
+        if (upper_kind) {
+            if (!high) up = dref;
+        } else if (high) {
+            lo = dref;
+        }
+        const double t = fmin(fmax(r, lo), up) - r;
+        c[row * B + s] = (float)((double)Sw[row] * t);
+        pacc[0] += (double)D[row] * t * t;
+    }
+    block_sum<1>(pacc, lds);
+    if (threadIdx.x == 0) epart[(long long)s * T.nblk + blockIdx.x] = pacc[0];
+}
+
+// Adds the band kernel's partials of slice s (summed in workgroup order) to
+// pass 1's partial 0 of that slice.
+__global__ __launch_bounds__(kBlock) void k_dvc_fold(const double *__restrict__ epart, int nblk,
+                                                     double *__restrict__ part1, int nparts1,
+                                                     const SliceState *__restrict__ st, int query)
+{
+    __shared__ double lds[4];
+    const int s = blockIdx.x;
+    if (!dvc_slice_runs(st, s, query)) return;
+    double tot[1];
+    sum_slots<1>(epart, (long long)s * nblk, nblk, tot, lds);
+    if (threadIdx.x == 0) part1[(long long)s * nparts1] += tot[0];
+}
+
+hipError_t launch_dvc(const DvcTable &T, const double *dose, unsigned long long *key, unsigned *hist, DvcSel *sel,
+                      const float *D, const float *S, float *c, double *epart, double *part1, int nparts1,
+                      const SliceState *st, int B, int query, hipStream_t s)
+{
+    if (T.n < 1 || T.n > kMaxDvc || T.nblk < 1 || B < 1 || B > 32) return hipErrorInvalidValue;
+    const dim3 blk(kBlock), gall(T.nblk, B), gsel(T.n, B);
+    for (int r = 0; r < kDvcRounds; ++r) {
+        hipLaunchKernelGGL(k_dvc_hist, gall, blk, 0, s, T, r, dose, key, hist, sel, st, B, query);
+        hipLaunchKernelGGL(k_dvc_pick, gsel, blk, 0, s, T, r, hist, sel, st, B, query);
+    }
+    hipLaunchKernelGGL(k_dvc_bands, gall, blk, 0, s, T, dose, key, sel, D, S, c, epart, st, B, query);
+    hipLaunchKernelGGL(k_dvc_fold, dim3(B), blk, 0, s, epart, T.nblk, part1, nparts1, st, query);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s)
 {

@@ -116,6 +116,43 @@ struct RowW {
     const float *D;
     const float *S;
     int qform;
+    // rows [dose_lo, dose_hi), the dose-volume rows, only store r = <a_i, z>
+    // (float64) into dose[(i - dose_lo) * B + s]: their bands are set after
+    // the pass (NULL: no such rows)
+    double *dose;
+    long long dose_lo, dose_hi;
+};
+
+// ---- dose-volume constraints ----
+// A constraint's rows are ranked by a 64-bit key: the order-preserving bits of
+// the float32-rounded value in the high half, the complement of the row's
+// position in its block in the low half (equal values rank by row), so keys are
+// unique.  The k-th highest key is found by a radix select over 11-bit digits
+// (at most six rounds: shifts 53, 42, 31, 20, 9 and a last 9-bit digit), one
+// launch per round; a round's last workgroup of a constraint picks the digit.
+constexpr int kMaxDvc = 16;
+constexpr int kDvcChunk = 2048; // rows per workgroup of the selection and band kernels
+constexpr int kDvcBins = 2048;  // 11-bit digits
+constexpr int kDvcRounds = 6;
+
+struct DvcTable {
+    int n;                       // constraints
+    int nblk;                    // workgroups per slice over all constraints
+    long long lo, span;          // rows [lo, lo + span) hold every constraint
+    long long begin[kMaxDvc], end[kMaxDvc];
+    long long k[kMaxDvc];        // rows ranked "high": floor(V N) (MAX) or ceil(V N) (MIN)
+    double dose[kMaxDvc];
+    int sense[kMaxDvc];          // 0: at most k above dose, 1: at least k at or above dose
+    int blk_begin[kMaxDvc + 1];  // workgroups [blk_begin[g], blk_begin[g+1]) cover constraint g
+};
+
+// Selection state of one constraint and slice.
+struct DvcSel {
+    unsigned long long prefix; // digits fixed so far
+    unsigned long long thr;    // mode 2: rows with key >= thr rank high
+    long long krem;            // rank still to find below the prefix
+    int mode;                  // 0: searching, 1: no row ranks high, 2: threshold, 3: every row ranks high
+    int pad;
 };
 
 // Column step of pass 2 (and of the fused pass's apply kernel):
@@ -211,6 +248,16 @@ size_t fused_lds_limit();
 // before its first launch, outside stream capture)
 hipError_t prepare_fused(const FusedCfg &cfg, int vk, int64_t n);
 // query: proximity from pass 1's partials into out[B]
+// dose-volume constraints after pass 1 (which stored the rows' values in
+// dose): the radix-select rounds (keys, per-constraint histograms in hist,
+// which must start zeroed and are left zeroed, selection state in sel), then
+// the bands of the rows, their c = S t, and their proximity terms (partials in
+// epart, nblk * B), added in a fixed order to pass 1's partial 0 of each slice
+// (part1 with nparts1 partials per slice).
+hipError_t launch_dvc(const DvcTable &T, const double *dose, unsigned long long *key, unsigned *hist, DvcSel *sel,
+                      const float *D, const float *S, float *c, double *epart, double *part1, int nparts1,
+                      const SliceState *st, int B, int query, hipStream_t s);
+
 hipError_t launch_query_prox(SliceState *st, int B, const double *partials, int nparts, double *out, hipStream_t s);
 
 int phase_grid(const PertParams &pp);

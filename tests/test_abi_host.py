@@ -104,3 +104,37 @@ def test_binding_has_no_oracle_dependency():
     for f in os.listdir(os.path.join(ROOT, "paper_2606_27086_amd", "csrc")):
         text = open(os.path.join(ROOT, "paper_2606_27086_amd", "csrc", f)).read()
         assert "oracle" not in text and "liborc" not in text and "orc_" not in text
+
+
+def test_struct_layouts_match_header(smx, tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets the
+    C compiler gives the header's structure."""
+    structs = {"smx_csr": smx.Csr, "smx_dvc": smx.DvcC, "smx_problem_desc": smx.ProblemDesc,
+               "smx_slice_state": smx.SliceStateC}
+    header_names = {  # binding field -> header field, where they differ
+        "smx_problem_desc": {"lam": "lambda"},
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            hf = header_names.get(cname, {}).get(f, f)
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {hf}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+
+    subprocess.check_call(["gcc", "-std=c11", "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, f, v = line.split()
+        py = structs[cname]
+        want = C.sizeof(py) if f == "size" else getattr(py, f).offset
+        assert int(v) == want, (cname, f, int(v), want)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())

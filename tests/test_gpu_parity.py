@@ -611,8 +611,8 @@ def test_basic_algorithm_parity(smx, method, case):
 @pytest.mark.parametrize("method", ["el", "emr"])
 @pytest.mark.parametrize("case", ["rt", "ct_tv"])
 def test_extrapolated_steps_lockstep(smx, method, case):
-    """Each iteration of EL / EMR from the device's own iterate and state
-    agrees with the oracle's to 1e-5, with the same decisions."""
+    """Each iteration of EL / EMR from the oracle's iterate and state agrees
+    with the oracle's to 1e-5, with the same decisions."""
     if case == "rt":
         w = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=70, K=15)
     else:
@@ -778,3 +778,94 @@ def test_stop_batched_and_resume(smx):
     end, xend = r.get_state()
     r.close()
     assert np.array_equal(xend, xfull) and end == full
+
+
+# ---------------------------------------------------------------------------
+# dose-volume constraints (split problem, Section 2.3.3)
+# ---------------------------------------------------------------------------
+
+def _dvc_random(B=1, K=20, obj=W.OBJ_SQNORM, seed=81):
+    """A random operator with two dose-volume constraints on (overlapping)
+    row sets, their doses between the true point's values."""
+    import scipy.sparse as sp
+
+    w = W.random_sparse(2000, 1500, 25, seed=seed, B=B, empty_frac=0.05, long_rows=2, long_len=1400, obj=obj, K=K)
+    A = sp.csr_matrix((w.val.astype(np.float64), w.col_idx, w.row_ptr), shape=(w.m, w.n))
+    r = A @ np.asarray(w.x_true, np.float64).reshape(w.n, -1)[:, 0]
+    rows1, rows2 = np.arange(0, 500), np.arange(300, 900)
+    return W.with_dvc(w, [(rows1, W.DVC_MAX, 0.2, float(np.quantile(r[rows1], 0.6))),
+                          (rows2, W.DVC_MIN, 0.8, float(np.quantile(r[rows2], 0.4)))])
+
+
+def _dvc_rt(basic, K=30):
+    return W.rt_with_dvc(W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=70, K=K), basic=basic)
+
+
+def test_dvc_random_parity(smx):
+    """Two dose-volume constraints beside ordinary bands, squared-norm
+    perturbations: the iterate, every proximity and the decisions match."""
+    w = _dvc_random()
+    assert _fused_info(smx, w) is None  # ranking before c: the two passes
+    check_parity(smx, w, w.K)
+
+
+@pytest.mark.parametrize("method", ["simult", "emr"])
+def test_dvc_rt_parity(smx, method):
+    """The radiotherapy case with the horseshoe plan's dose-volume constraints
+    (all doses 0 at x0 = 0: the first ranking is by row alone), the linear
+    objective, and the weighted simultaneous or the EMR step."""
+    w = _dvc_rt(BASIC_CASES.get(method, W.BASIC_SIMULT))
+    check_parity(smx, w, w.K, sensitive=method == "emr")
+
+
+def test_dvc_rt_emr_lockstep(smx):
+    w = _dvc_rt(W.BASIC_EMR, K=20)
+    say("rt dose-volume lockstep (EMR)")
+    worst = lockstep(smx, w, w.K)
+    print(f"  worst per-iteration rel err {worst:.3e}", flush=True)
+
+
+def test_dvc_batched(smx):
+    """Two slices (multi-slice pass kernels, a selection per slice)."""
+    check_parity(smx, _dvc_random(B=2, K=15, seed=82), 15)
+
+
+def test_dvc_bf16(smx):
+    w = _dvc_random(K=20, seed=83)
+    check_parity(smx, w, w.K, storage="bf16", value_round="bf16")
+
+
+def test_dvc_query_and_graph(smx):
+    """The proximity at a loaded point counts the constraints' projections;
+    graph replay equals eager bitwise."""
+    w = _dvc_random(K=25, seed=84)
+    say("dose-volume query and graph replay")
+    x = W.synthetic_iterate(w, seed=85)
+    p = smx.problem_from_workload(w, history_cap=0)
+    p.set_x(x)
+    prox, _ = p.query()
+    p.close()
+    P = oracle.from_workload(w)
+    assert prox[0] == pytest.approx(P.proximity(x[:, 0].astype(np.float64)), rel=2e-6)
+    xe, _, _, he, _ = gpu_run(smx, w, w.K, graph=False)
+    xg, _, _, hg, _ = gpu_run(smx, w, w.K, graph=True)
+    assert np.array_equal(xe, xg) and np.array_equal(he["prox"], hg["prox"])
+
+
+def test_dvc_invalid_args(smx):
+    w = _dvc_random(K=2, seed=86)
+    op = smx.Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val)
+    g0, g1 = w.dvc
+    bad = [
+        [dict(g0, row_end=g0["row_begin"])],                   # empty block
+        [dict(g0, row_end=w.m + 1)],                           # beyond m
+        [g0, dict(g1, row_begin=g1["row_begin"] + 1)],         # not consecutive
+        [dict(g0, fraction=1.5)], [dict(g0, fraction=-0.1)],
+        [dict(g0, sense=2)], [dict(g0, dose=float("nan"))],
+        [g0] * 17,
+    ]
+    for tab in bad:
+        with pytest.raises(smx.SmxError) as e:
+            smx.Problem(op, lower=w.lower, upper=w.upper, dvc=tab)
+        assert e.value.code == smx.EINVAL, tab
+    op.close()
