@@ -23,7 +23,9 @@ with every input resident in HBM.  The line also carries
               against the 8 TB/s HBM peak;
   basic_algorithms  DROP, CQ, EL and EMR steps on the headline workload;
   seismic     the seismic setup at the paper's shape (8192 x 65536 band
-              rows, DROP, L1 / squared-norm / TV, with and without noise).
+              rows, DROP, L1 / squared-norm / TV, with and without noise);
+  dose_volume the radiotherapy configuration with dose-volume constraints
+              (EMR), against the same problem without them.
 """
 from __future__ import annotations
 
@@ -267,6 +269,29 @@ def section_seismic(smx, steps, warmup, tune):
     return out
 
 
+def section_dvc(smx, tune):
+    """The radiotherapy configuration with the horseshoe plan's dose-volume
+    constraints (target D95% >= 0.97, target D5% <= 1.03, organ-at-risk
+    D5% <= 0.16: three structures' rows appended to A), EMR steps and the
+    linear dose objective (Section 2.3.3): SM iterations/s, and the same
+    problem without the constraints for the cost of the selection."""
+    import workloads as W
+
+    t0 = time.time()
+    base = W.rt_large(seed=4, K=300)
+    w = W.rt_with_dvc(base, basic=W.BASIC_EMR)
+    out = dict(workload="radiotherapy 160x160x80 + 3 dose-volume constraints, EMR, linear dose objective",
+               m=w.m, n=w.n, nnz=w.nnz, dvc_rows=int(sum(g["row_end"] - g["row_begin"] for g in w.dvc)),
+               generate_s=round(time.time() - t0, 1))
+    for name, wl in (("dvc", w), ("no_dvc", w.with_params(dvc=None))):
+        for storage in ("f32", "bf16"):
+            r = time_problem(smx, wl, storage, 50, 5, tune=tune)
+            out[f"{name}_{storage}"] = dict(it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5),
+                                            pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
+                                            prox=r["prox"][0], obj=r["obj"][0])
+    return out
+
+
 def section_hbm(smx, tune):
     import workloads as W
 
@@ -294,8 +319,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--sections", default="batched,serving,hbm,basic,seismic",
-                    help="extra sections beside the headline: batched,serving,hbm,basic,seismic (empty for none)")
+    ap.add_argument("--sections", default="batched,serving,hbm,basic,seismic,dvc",
+                    help="extra sections beside the headline: batched,serving,hbm,basic,seismic,dvc (empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the single-GPU path is what is built "
@@ -357,6 +382,8 @@ def main():
         line["basic_algorithms"] = section_basic(smx, 100, 10, tune)
     if "seismic" in sections:
         line["seismic"] = section_seismic(smx, 200, 10, tune)
+    if "dvc" in sections:
+        line["dose_volume"] = section_dvc(smx, tune)
     print(json.dumps(line), flush=True)
 
 

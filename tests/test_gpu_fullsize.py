@@ -95,3 +95,11 @@ def test_seismic_fresnel_paper_shape(smx):
     say(f"seismic fresnel paper shape m={w.m} n={w.n} nnz={w.nnz} DROP L1 "
         f"(generated in {time.time() - t:.1f}s)")
     sampled_lockstep(smx, w, w.K, [0, 100, 199])
+
+
+def test_rt_dose_volume_full_size(smx):
+    t = time.time()
+    w = W.rt_with_dvc(W.rt_large(seed=4, K=100), basic=W.BASIC_EMR)
+    say(f"rt full with dose-volume constraints m={w.m} n={w.n} nnz={w.nnz} EMR "
+        f"(generated in {time.time() - t:.1f}s)")
+    sampled_lockstep(smx, w, w.K, [0, 50, 99])
