@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 1, 2, 3, 4, 5
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
+BASIC_ART = 5  # sequential projections, one sweep per iteration (the oracle only)
 DVC_MAX, DVC_MIN = 0, 1
 
 

@@ -56,6 +56,7 @@
 #define ORC_BASIC_CQ 2     /* CQ iteration with the Frobenius bound */
 #define ORC_BASIC_EL 3     /* extrapolated Landweber */
 #define ORC_BASIC_EMR 4    /* Landweber with error-minimising relaxation */
+#define ORC_BASIC_ART 5    /* sequential projections (Kaczmarz / ART), one sweep per iteration; oracle only */
 
 /* dose-volume constraint senses (Section 2.3.3) */
 #define ORC_DVC_MAX 0 /* D_V <= d: at most floor(V N_S) rows of the structure above d */
@@ -286,6 +287,11 @@ void orc_bands_at(const orc_problem *P, const double *x, double *lo, double *up)
  *           (Section 2.1.1); the box plays C;
  *   EL      x + lambda sigma A^T D t, sigma = t^T D t / ||A^T D t||^2;
  *   EMR     x + lambda sigma y, y = A^T W t, sigma = ||y||^2 / sum_i w_i (A y)_i^2;
+ *   ART     one sweep over the rows in order, each projecting the current
+ *           point onto its band: x <- x + lambda (clip(<a_i,x>) - <a_i,x>) /
+ *           ||a_i||^2 a_i (the sequential row of the table of methods; rows
+ *           with a_i = 0 are skipped; dose-volume rows keep the bands set at
+ *           the sweep's start);
  * sigma = 0 when its denominator is 0 (then y = 0 too).  The bands of
  * dose-volume rows are those their projection sets at the input point (the
  * split problem's P_Q).  Returns the
@@ -299,6 +305,19 @@ static double feas_step(const orc_problem *P, const double *q, const double *zc,
     double *lo = malloc(sizeof(double) * P->m), *up = malloc(sizeof(double) * P->m);
     effective_bands(P, r, lo, up);
     double prox = proximity_q(P, q, r, lo, up);
+    if (P->basic == ORC_BASIC_ART) {
+        for (int64_t i = 0; i < P->m; ++i) {
+            if (!(q[i] > 0.0)) continue;
+            double ri = 0.0;
+            for (int64_t p = P->row_ptr[i]; p < P->row_ptr[i + 1]; ++p) ri += P->val[p] * x[P->col[p]];
+            const double step = P->lambda * (clampd(ri, lo[i], up[i]) - ri) / q[i];
+            for (int64_t p = P->row_ptr[i]; p < P->row_ptr[i + 1]; ++p) x[P->col[p]] += step * P->val[p];
+        }
+        for (int64_t j = 0; j < P->n; ++j) x[j] = clampd(x[j], P->box_lo[j], P->box_hi[j]);
+        free(lo);
+        free(up);
+        return prox;
+    }
     double fro2 = 0.0;
     if (P->basic == ORC_BASIC_CQ)
         for (int64_t i = 0; i < P->m; ++i) fro2 += q[i];

@@ -791,3 +791,51 @@ def test_dvc_rank_uses_float32_values(orc):
     P = _identity_dvc(orc, 2, W.DVC_MAX, 0.5, 0.5)
     lo, up = P.bands_at(np.array([0.6, 0.6 + 1e-12]))
     np.testing.assert_array_equal(up, [np.inf, 0.5])
+
+
+# ---------------------------------------------------------------------------
+# Sequential projections (Kaczmarz / ART, table of methods): the oracle only
+# ---------------------------------------------------------------------------
+
+def test_art_orthogonal_rows_one_sweep(orc):
+    """Rows orthogonal to each other: one sweep with lambda = 1 lands on the
+    solution of the square system (each projection leaves the others' values)."""
+    rng = np.random.default_rng(110)
+    Q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    A = Q * rng.uniform(0.5, 2.0, 6)[:, None]
+    xs = rng.standard_normal(6)
+    b = A @ xs
+    P = _dense_problem(orc, A, b, b, basic=orc.BASIC_ART)
+    x1, prox = P.step(np.zeros(6))
+    np.testing.assert_allclose(x1, xs, rtol=1e-12, atol=1e-12)
+    assert prox == pytest.approx(0.5 * np.mean((b / np.linalg.norm(A, axis=1)) ** 2), rel=1e-12)
+
+
+def test_art_converges_on_consistent_system(orc):
+    """Kaczmarz sweeps converge to the solution of a consistent nonsingular
+    system (numpy solve) and each sweep equals the rows' projections applied
+    in order by hand."""
+    rng = np.random.default_rng(111)
+    A = rng.standard_normal((8, 8)) + 4 * np.eye(8)
+    xs = rng.uniform(-1, 1, 8)
+    b = A @ xs
+    P = _dense_problem(orc, A, b, b, basic=orc.BASIC_ART, lam=1.2)
+    x = np.zeros(8)
+    by_hand = x.copy()
+    for i in range(8):
+        a = A[i]
+        by_hand = by_hand + 1.2 * (b[i] - a @ by_hand) / (a @ a) * a
+    x1, _ = P.step(x)
+    np.testing.assert_allclose(x1, by_hand, rtol=1e-13, atol=1e-14)
+    xK, _, h = P.run(x, 300, perturb=False)
+    np.testing.assert_allclose(xK, np.linalg.solve(A, b), rtol=1e-9, atol=1e-10)
+    assert h.prox[-1] < 1e-18
+
+
+def test_art_single_row_equals_simultaneous(orc):
+    """With one row the sweep is the simultaneous step (w = 1)."""
+    a = np.array([1.0, -2.0, 0.5])
+    Pa = _single_row(orc, a, 0.3, 0.6, lam=1.5, basic=orc.BASIC_ART)
+    Ps = _single_row(orc, a, 0.3, 0.6, lam=1.5)
+    x = np.array([0.7, 0.1, -0.4])
+    np.testing.assert_allclose(Pa.step(x)[0], Ps.step(x)[0], rtol=1e-15, atol=1e-15)
