@@ -44,9 +44,9 @@ PMC_TABLE = os.path.join(ROOT, "profiles", "pmc_pass_traffic.json")
 CT_WORKLOAD = "ct256_parallel_beam_180x363_tv"
 RT_WORKLOAD = "rt_160x160x80_9beams_47x47"
 # bytes per stored entry (value + index) and the kernels' value-type tag, by format
-ENTRY_BYTES = {"f32+i32": 8, "bf16+i32": 6, "f16+i32": 6, "bf16+u16": 4, "f16+u16": 4}
+ENTRY_BYTES = {"f32+i32": 8, "bf16+i32": 6, "f16+i32": 6, "bf16+u16": 4, "f16+u16": 4, "f32+u16": 6}
 VALUE_TAG = {"f32+i32": "float", "bf16+i32": "smx::Bf16Tag", "f16+i32": "smx::F16Tag",
-             "bf16+u16": "smx::Bf16PTag", "f16+u16": "smx::F16PTag"}
+             "bf16+u16": "smx::Bf16PTag", "f16+u16": "smx::F16PTag", "f32+u16": "smx::F32U16Tag"}
 
 
 def fused_in_use(shapes):
@@ -54,12 +54,14 @@ def fused_in_use(shapes):
     return bool(f and f["in_use"])
 
 
-def alg_bytes(m, n, nnz, shapes, B=1):
+def alg_bytes(m, n, nnz, shapes, B=1, tiles=None):
     """Algorithmic bytes of one launch of each kernel of the feasibility step:
     A once in the format that kernel reads, each vector once.  Two passes:
     pass 1 and pass 2.  Fused pass: the fused kernel (A once, the row vectors,
     the gather of z, y once) and its apply kernel (z, the box, x, and the
-    per-workgroup partial vectors it has to sum)."""
+    per-workgroup partial vectors it has to sum).  Pass 2 over image tiles
+    (tiles = the describe record: count, rows = the tiles' row lists' total
+    length): A once, the tile tables, and c read once per (tile, row) pair."""
     e1 = ENTRY_BYTES[shapes["pass1"]["format"]]
     if fused_in_use(shapes):
         f = shapes["fused"]
@@ -69,7 +71,11 @@ def alg_bytes(m, n, nnz, shapes, B=1):
         return p1, p2
     e2 = ENTRY_BYTES[shapes["pass2"]["format"]]
     p1 = nnz * e1 + 4 * (m + 1) + 4 * m + B * (8 * m + 4 * m + 4 * n)
-    p2 = nnz * e2 + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
+    if shapes["pass2"]["mode"] == "tiles":
+        R, T = tiles["rows"], tiles["count"]
+        p2 = nnz * e2 + 4 * (n + 1) + 4 * n + 8 * (T + 1) + 8 * R + 8 * n + 8 * n
+    else:
+        p2 = nnz * e2 + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
     return p1, p2
 
 
@@ -81,6 +87,8 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
             return f"smx::k_fused<{f['lpr']}, {f['vec']}, {VALUE_TAG[shapes['pass1']['format']]}, {acc}>"
         return f"smx::k_fused_apply<{acc}>"
     vt = VALUE_TAG[shape["format"]]
+    if shape["mode"] == "tiles":
+        return f"smx::k_pass2_tile<{shape['lpr']}, {shape['vec']}, {vt}>"
     if B > 1:
         return f"smx::k_pass{pass_no}_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
     if shape["mode"] == "stream":
@@ -111,6 +119,7 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=Tr
 
     p = smx.problem_from_workload(w, storage=storage, refine_iters=0, fused=fused)
     shapes = p.autotune(reps=10) if tune else p.describe()
+    tiles = shapes.get("tiles")
     p.run(warmup, perturb=True, graph=graph)  # also captures the graphs
     p.sync()
     p.reset(w.x0)
@@ -130,11 +139,12 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=Tr
     p.set_timing(False)
     p.close()
     return dict(seconds=dt, it_s=steps / dt, ms_per_step=1e3 * dt / steps, pass1_ms=t1, pass2_ms=t2, launches=n,
-                prox=[float(v) for v in prox], obj=[float(v) for v in obj], shapes=shapes[storage], x=x)
+                prox=[float(v) for v in prox], obj=[float(v) for v in obj], shapes=shapes[storage], x=x,
+                tiles=tiles)
 
 
 def summarise(w, r, storage, B=1):
-    c1, c2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B)
+    c1, c2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B, r.get("tiles"))
     fused = fused_in_use(r["shapes"])
     k1, k2 = ("fused", "apply") if fused else ("pass1", "pass2")
     return {"it_s": round(r["it_s"], 2), "slice_it_s": round(r["it_s"] * B, 2),
@@ -145,7 +155,7 @@ def summarise(w, r, storage, B=1):
 
 
 def roofline_of(w, r, storage, B=1, workload=None):
-    b1, b2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B)
+    b1, b2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B, r.get("tiles"))
     t1, t2 = r["pass1_ms"], r["pass2_ms"]
     dpass, dbytes, dms = (1, b1, t1) if t1 >= t2 else (2, b2, t2)
     achieved = dbytes / (dms * 1e-3) / 1e9

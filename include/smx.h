@@ -232,6 +232,21 @@ const char *smx_last_error(void);
 int smx_operator_create(const smx_csr *A, int32_t value_storage, int32_t keep_f32, void *stream,
                         smx_operator **out);
 
+/*
+ * smx_operator_create for an operator whose unknowns are the pixels of an
+ * image_rows x image_cols image (pixel (i, j) is unknown i * image_cols + j;
+ * image_rows * image_cols must equal n).  Beside the layouts above, the
+ * library groups A's columns by 8 x 8 pixel tiles with each tile's rows listed
+ * once: a ray crosses several pixels of a tile, so the transposed product
+ * stages the tile's rows of the residual in LDS and gathers from there.  One-
+ * slice problems on such an operator use that layout for A^T when it is the
+ * faster one (smx_autotune times both).  Errors as smx_operator_create, and
+ * SMX_EINVAL when the image does not match n.  A tile touching more than 16384
+ * rows leaves the operator without the tile layout (not an error).
+ */
+int smx_operator_create_image(const smx_csr *A, int32_t value_storage, int32_t keep_f32, int32_t image_rows,
+                              int32_t image_cols, void *stream, smx_operator **out);
+
 /* Release an operator once every problem created from it is destroyed
  * (operators are reference counted).  NULL is accepted. */
 int smx_operator_destroy(smx_operator *op);

@@ -32,6 +32,7 @@ EXPORTS = [
     "smx_version",
     "smx_last_error",
     "smx_operator_create",
+    "smx_operator_create_image",
     "smx_operator_destroy",
     "smx_operator_footprint",
     "smx_problem_create",
@@ -174,6 +175,7 @@ def lib() -> C.CDLL:
     L.smx_version.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.smx_last_error.restype = C.c_char_p
     L.smx_operator_create.argtypes = [C.POINTER(Csr), i32, i32, vp, C.POINTER(vp)]
+    L.smx_operator_create_image.argtypes = [C.POINTER(Csr), i32, i32, i32, i32, vp, C.POINTER(vp)]
     L.smx_operator_destroy.argtypes = [vp]
     L.smx_operator_footprint.argtypes = [i64, i64, i64, i32, i32, C.POINTER(C.c_size_t)]
     L.smx_problem_create.argtypes = [vp, C.POINTER(ProblemDesc), vp, C.POINTER(vp)]
@@ -245,7 +247,9 @@ class Operator:
     optional reduced-precision value copy (``storage`` in f32 / bf16 / f16)."""
 
     def __init__(self, m, n, row_ptr, col_idx, val, storage: str = "f32", keep_f32: bool = True,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, image=None):
+        """image = (rows, cols): the unknowns are the pixels of that image
+        (row-major), which adds the tiled column layout for A^T."""
         import torch
 
         self.m, self.n = int(m), int(n)
@@ -256,8 +260,12 @@ class Operator:
         self.nnz = int(ci.numel())
         csr = Csr(self.m, self.n, self.nnz, _ptr(rp), _ptr(ci), _ptr(va), 1)
         h = C.c_void_p()
-        check(lib().smx_operator_create(C.byref(csr), STORE[storage], 1 if keep_f32 else 0,
-                                        _stream_ptr(stream), C.byref(h)))
+        if image is None:
+            check(lib().smx_operator_create(C.byref(csr), STORE[storage], 1 if keep_f32 else 0,
+                                            _stream_ptr(stream), C.byref(h)))
+        else:
+            check(lib().smx_operator_create_image(C.byref(csr), STORE[storage], 1 if keep_f32 else 0,
+                                                  int(image[0]), int(image[1]), _stream_ptr(stream), C.byref(h)))
         self.handle = h
 
     def close(self):
@@ -493,7 +501,8 @@ def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device=
     """Build operator + problem for a :class:`workloads.Workload` (all slices);
     fused=False keeps the two bitwise-reproducible passes."""
     if op is None:
-        op = Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage=storage, device=device)
+        op = Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage=storage, device=device,
+                      image=getattr(w, "image", None))
     kw = dict(
         lower=w.lower, upper=w.upper, box_lo=w.box_lo, box_hi=w.box_hi, weights=w.weights, lam=w.lam, obj=w.obj,
         tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,

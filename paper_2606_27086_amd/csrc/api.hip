@@ -197,6 +197,26 @@ struct smx_operator {
     DevLayout csr, csc;
     DBuf q32, q16; // float64 row norms of the float32 and the reduced-precision operator
     DBuf zcol;     // DROP column factors 1/(nonzeros in column j), 0 for an empty column [n]
+    // image operators: the column layout grouped by image tiles (TileView);
+    // t_idx16 holds its 16-bit row positions for the float32 copy
+    int img_rows = 0, img_cols = 0;
+    DevLayout tiles;
+    DBuf t_tcol, t_pptr, t_rptr, t_rlist, t_idx16;
+    int t_ntiles = 0, t_max_rows = 0;
+    bool has_tiles() const { return t_ntiles > 0; }
+    TileView tile_view(int vk) const
+    {
+        TileView T;
+        T.A = tiles.view(vk);
+        if (vk == VK_F32) T.A.idx = t_idx16.as<int32_t>(); // read as uint16 by the float32 entries
+        T.tcol = t_tcol.as<int32_t>();
+        T.pptr = t_pptr.as<int32_t>();
+        T.rptr = t_rptr.as<int32_t>();
+        T.rlist = t_rlist.as<int32_t>();
+        T.ntiles = t_ntiles;
+        T.max_rows = t_max_rows;
+        return T;
+    }
     std::atomic<int> refs{1};
     size_t bytes = 0;
     int lp_kind() const { return storage == SMX_STORE_BF16 ? VK_BF16 : (storage == SMX_STORE_F16 ? VK_F16 : VK_F32); }
@@ -232,6 +252,7 @@ struct smx_problem {
     DBuf ybuf;     // EL / EMR: y = A^T c kept for the extrapolated step, float64 [n*B]
     DBuf ybuf32;   // EMR: y rounded to float32, the vector its second product gathers [n*B]
     DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
+    bool tiles_ok = false; // pass 2 may use the operator's image-tile layout (one slice)
     bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
     DBuf xprev, part_var;
     // dose-volume constraints: their rows' values, keys, per-constraint
@@ -396,7 +417,105 @@ void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, int64_t index_rang
     std::vector<float>().swap(H.val);
 }
 
-int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStream_t s, smx_operator **out)
+// Host form of the image-tile column layout (TileView).
+struct TileHost {
+    std::vector<int32_t> tcol, pptr, rptr, rlist, ptr, idx;
+    std::vector<float> val;
+    int max_rows = 0;
+};
+
+constexpr int kTileMaxRows = 16384; // rows of one tile: 64 KB of LDS, 16-bit positions
+
+// Groups the columns of A^T (cp/ri/cv: its unpadded CSR, rows ascending in
+// each column) by th x tw tiles of an R x C image (unknown i*C + j is pixel
+// (i, j)).  Each tile column's entries keep their order; their indices become
+// positions in the tile's ascending row list; columns are padded to
+// kRowAlign entries (value 0, the last position).  Returns false when a tile
+// touches more than kTileMaxRows rows or the layout reaches 2^31 entries.
+bool build_tiles(int64_t R, int64_t C, int th, int tw, const std::vector<int64_t> &cp, const std::vector<int32_t> &ri,
+                 const std::vector<float> &cv, TileHost &T)
+{
+    const int64_t ntr = (R + th - 1) / th, ntc = (C + tw - 1) / tw;
+    T.pptr.assign(1, 0);
+    T.rptr.assign(1, 0);
+    T.ptr.assign(1, 0);
+    std::vector<int32_t> rows;
+    for (int64_t ti = 0; ti < ntr; ++ti)
+        for (int64_t tj = 0; tj < ntc; ++tj) {
+            rows.clear();
+            const size_t c0 = T.tcol.size();
+            for (int64_t i = ti * th; i < std::min(R, ti * th + th); ++i)
+                for (int64_t j = tj * tw; j < std::min(C, tj * tw + tw); ++j) {
+                    const int64_t col = i * C + j;
+                    T.tcol.push_back((int32_t)col);
+                    rows.insert(rows.end(), ri.begin() + cp[col], ri.begin() + cp[col + 1]);
+                }
+            std::sort(rows.begin(), rows.end());
+            rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+            if ((int64_t)rows.size() > kTileMaxRows) return false;
+            T.max_rows = std::max(T.max_rows, (int)rows.size());
+            T.rlist.insert(T.rlist.end(), rows.begin(), rows.end());
+            T.rptr.push_back((int32_t)T.rlist.size());
+            for (size_t q = c0; q < T.tcol.size(); ++q) {
+                const int64_t col = T.tcol[q];
+                int32_t last = 0;
+                for (int64_t p = cp[col]; p < cp[col + 1]; ++p) {
+                    last = (int32_t)(std::lower_bound(rows.begin(), rows.end(), ri[p]) - rows.begin());
+                    T.idx.push_back(last);
+                    T.val.push_back(cv[p]);
+                }
+                while (T.val.size() % kRowAlign) {
+                    T.idx.push_back(last);
+                    T.val.push_back(0.f);
+                }
+                if (T.val.size() >= (size_t(1) << 31)) return false;
+                T.ptr.push_back((int32_t)T.val.size());
+            }
+            T.pptr.push_back((int32_t)T.tcol.size());
+        }
+    return true;
+}
+
+// Uploads the tile layout; the reduced-precision copy is always packed (the
+// positions fit in 16 bits).
+void upload_tiles(smx_operator *op, TileHost &T, int lp, hipStream_t s)
+{
+    DevLayout &D = op->tiles;
+    D.rows = op->n;
+    D.slots = (int64_t)T.val.size();
+    upload(D.ptr, T.ptr, s, "upload tile pointers");
+    upload(op->t_tcol, T.tcol, s, "upload tile columns");
+    upload(op->t_pptr, T.pptr, s, "upload tile columns");
+    upload(op->t_rptr, T.rptr, s, "upload tile rows");
+    upload(op->t_rlist, T.rlist, s, "upload tile rows");
+    op->t_ntiles = (int)T.pptr.size() - 1;
+    op->t_max_rows = T.max_rows;
+    upload(D.val32, T.val, s, "upload tile values");
+    if (op->has_f32) {
+        std::vector<uint16_t> i16(T.idx.size());
+        for (size_t p = 0; p < T.idx.size(); ++p) i16[p] = (uint16_t)T.idx[p];
+        upload(op->t_idx16, i16, s, "upload tile positions");
+    }
+    if (lp != VK_F32) {
+        upload(D.idx, T.idx, s, "upload tile positions");
+        DBuf v16;
+        v16.alloc(sizeof(uint16_t) * std::max<int64_t>(D.slots, 1), "tile reduced-precision values");
+        if (lp == VK_BF16) hip_check(launch_to_bf16(D.val32.as<float>(), v16.as<uint16_t>(), D.slots, s), "to bf16");
+        else {
+            D.f16_scale = op->csc.f16_scale;
+            hip_check(launch_to_f16(D.val32.as<float>(), v16.as<uint16_t>(), D.slots, D.f16_scale, s), "to f16");
+        }
+        D.packed.alloc(sizeof(uint32_t) * std::max<int64_t>(D.slots, 1), "tile packed entries");
+        hip_check(launch_pack16(v16.as<uint16_t>(), D.idx.as<int32_t>(), D.packed.as<uint32_t>(), D.slots, s),
+                  "pack tile entries");
+        hip_check(hipStreamSynchronize(s), "pack tile entries");
+        D.idx.release();
+        if (!op->has_f32) D.val32.release();
+    }
+}
+
+int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStream_t s, smx_operator **out,
+                    int32_t img_rows = 0, int32_t img_cols = 0)
 {
     if (!A || !out) return fail(SMX_EINVAL, "NULL argument");
     *out = nullptr;
@@ -444,6 +563,15 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
             }
     }
     const int lp = op->lp_kind();
+    TileHost TH;
+    bool tiled = false;
+    if (img_rows > 0) {
+        const char *te = getenv("SMX_TILE"); // tile edge (4, 8 or 16); default 8
+        const int edge = te ? std::max(4, std::min(16, atoi(te))) : 8;
+        tiled = build_tiles(img_rows, img_cols, edge, edge, cp, ri, cv, TH);
+        op->img_rows = img_rows;
+        op->img_cols = img_cols;
+    }
     {
         HostLayout H;
         if (!pad_rows(m, rp64.data(), ci.data(), va.data(), H)) return fail(SMX_EINVAL, "padded CSR exceeds 2^31 entries");
@@ -458,6 +586,7 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
         std::vector<float>().swap(cv);
         upload_layout(op->csc, H, n, m, op->has_f32, lp, s);
     }
+    if (tiled) upload_tiles(op.get(), TH, lp, s);
     if (op->has_f32) {
         op->q32.alloc(sizeof(double) * m, "row norms");
         hip_check(launch_rownorm(op->csr.view(VK_F32), VK_F32, op->q32.as<double>(), s), "row norms");
@@ -471,6 +600,9 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
     op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32, op->csr.packed.p != nullptr) +
                 layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32, op->csc.packed.p != nullptr) +
                 size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0)) + size_t(n) * 4;
+    if (op->has_tiles())
+        op->bytes += size_t(op->n + 1) * 4 + size_t(op->tiles.slots) * ((op->has_f32 ? 6 : 0) + (lp != VK_F32 ? 4 : 0)) +
+                     size_t(op->n) * 4 + size_t(op->t_rptr.bytes / 4 + op->t_rlist.bytes / 4 + op->t_ntiles + 1) * 4;
     *out = op.release();
     return SMX_OK;
 }
@@ -488,6 +620,20 @@ int vk_for_iteration(const smx_problem *p, int64_t it, int64_t K, int64_t ref)
     return (it >= K - ref) ? VK_F32 : lp;
 }
 
+// Pass 2 in launch shape c: the image-tile layout (mode 2) or the column copy.
+hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float *cres, float *x, ColStep cs,
+                     const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                     hipStream_t s)
+{
+    if (c.mode == 2) {
+        const int lp = p->op->lp_kind();
+        const int tk = vk == VK_F32 ? VK_F32 : (lp == VK_BF16 ? VK_BF16P : VK_F16P);
+        return launch_pass2_tiles(c, p->op->tile_view(tk), tk, cres, x, cs, st_in, st_out, part1, nparts1, h, s);
+    }
+    return launch_pass2(c, view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk], cres, x, cs, st_in,
+                        st_out, p->B, part1, nparts1, h, s);
+}
+
 // Enqueue one outer iteration with value kind vk on stream s, starting from
 // state buffer `cur`; returns the buffer current after it.
 int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
@@ -501,14 +647,17 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
         // then every remaining trial up to the cap); a last launch closes the phase
         const int launches = (p->pp.max_trials > p->pp.first_width ? 2 : 1) * p->pp.n_red;
         const double *prev = p->part_phase.as<double>();
-        for (int t = 0; t <= launches; ++t) {
+        for (int t = 0; t < launches; ++t) {
             double *out = p->part_trial[t & 1].as<double>();
             hip_check(launch_trial(p->pp, p->x.as<float>(), gvec, p->state(cur), p->state(cur ^ 1), t == 0 ? 1 : 0,
-                                   t < launches ? 1 : 0, prev, out, s),
+                                   1, prev, out, s),
                       "trial");
             cur ^= 1;
             prev = out;
         }
+        hip_check(launch_trial_close(p->pp, p->x.as<float>(), gvec, p->state(cur), p->state(cur ^ 1), prev, s),
+                  "close phase");
+        cur ^= 1;
     }
     const RowW rw = p->row_weights(vk);
     const ColStep cstep = p->col_step(false);
@@ -548,9 +697,8 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
     if (p->dvc.n > 0) p->enqueue_dvc(vk, p->part_pass.as<double>(), p->cfg1[vk].grid, cur, 0, s);
     if (timed) hip_check(hipEventRecord(e[2], s), "event");
     const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
-    hip_check(launch_pass2(p->cfg2[vk], view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
-                           p->c.as<float>(), p->x.as<float>(), p->col_step(extrap), p->state(cur), p->state(cur ^ 1),
-                           p->B, p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
+    hip_check(pass2_any(p, vk, p->cfg2[vk], p->c.as<float>(), p->x.as<float>(), p->col_step(extrap), p->state(cur),
+                        p->state(cur ^ 1), p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
               "pass 2");
     if (timed) hip_check(hipEventRecord(e[3], s), "event");
     if (extrap) {
@@ -934,11 +1082,28 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->fmt1[lk] = op->csr.packed.p ? pk : lk;
         p->fmt2[lk] = op->csc.packed.p ? pk : lk;
     }
-    const char *mode_env = getenv("SMX_PASS_MODE"); // "rows" selects the lanes-per-row kernels
+    // "rows" selects the lanes-per-row kernels, "interleaved" the interleaved-lane pass 1
+    const char *mode_env = getenv("SMX_PASS_MODE");
     const bool rows_mode = mode_env && std::strcmp(mode_env, "rows") == 0;
+    const bool inter_mode = mode_env && std::strcmp(mode_env, "interleaved") == 0;
+    const char *tiles_env = getenv("SMX_TILES"); // "0" keeps the column copy for pass 2
+    const bool use_tiles = op->has_tiles() && B == 1 && !(tiles_env && std::strcmp(tiles_env, "0") == 0);
+    p->tiles_ok = use_tiles;
     for (int vk = 0; vk < 3; ++vk) {
         p->cfg1[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk, B);
         p->cfg2[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csc, vk) : pick_cfg(op->csc, vk, B);
+        if (inter_mode && B == 1) {
+            p->cfg1[vk].mode = 0;
+            p->cfg1[vk].lpr = 16;
+            p->cfg1[vk].vec = 1;
+            p->cfg1[vk].grid = (int)std::min<int64_t>(std::max<int64_t>(1, (m + 15) / 16), kMaxPassGrid);
+        }
+        if (use_tiles) {
+            p->cfg2[vk].mode = 2;
+            p->cfg2[vk].lpr = 4;
+            p->cfg2[vk].vec = 4;
+            p->cfg2[vk].grid = std::max(1, std::min(op->t_ntiles, kMaxPassGrid));
+        }
     }
     p->dvc = dt;
     if (dt.n > 0) {
@@ -1049,10 +1214,25 @@ int autotune_impl(smx_problem *p, int reps)
         for (int vk : kinds) {
             const RowW rw = p->row_weights(vk);
             const ColStep cstep = p->col_step(false);
-            // pass 1
+            // pass 1 (also with interleaved lanes, vec = 1, for one slice)
             double best = 1e30;
             PassCfg bestc = p->cfg1[vk];
-            for (const PassCfg &c : pass_candidates(p->op->csr, vk, p->B)) {
+            std::vector<PassCfg> cands1 = pass_candidates(p->op->csr, vk, p->B);
+            if (p->B == 1)
+                for (int lpr : {8, 16, 32, 64})
+                    for (int g : {1024, 2048, 4096}) {
+                        PassCfg c;
+                        c.mode = 0;
+                        c.lpr = lpr;
+                        c.vec = 1;
+                        const int64_t rpb = kBlock / lpr;
+                        c.grid = (int)std::min<int64_t>({std::max<int64_t>(1, (p->m + rpb - 1) / rpb), (int64_t)g,
+                                                         (int64_t)kMaxPassGrid});
+                        bool dup = false;
+                        for (auto &o : cands1) dup = dup || (o.mode == 0 && o.lpr == lpr && o.vec == 1 && o.grid == c.grid);
+                        if (!dup) cands1.push_back(c);
+                    }
+            for (const PassCfg &c : cands1) {
                 auto launch = [&]() {
                     hip_check(launch_pass1(c, view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
                                            xs.as<float>(),
@@ -1076,11 +1256,24 @@ int autotune_impl(smx_problem *p, int reps)
             // pass 2 (the residual from the chosen pass 1)
             best = 1e30;
             PassCfg bestc2 = p->cfg2[vk];
-            for (const PassCfg &c : pass_candidates(p->op->csc, vk, p->B)) {
+            std::vector<PassCfg> cands2 = pass_candidates(p->op->csc, vk, p->B);
+            if (p->tiles_ok)
+                for (int lpr : {2, 4, 8, 16})
+                    for (int vec : {4, 8})
+                        for (int g : {1024, 2048, 4096}) {
+                            PassCfg c;
+                            c.mode = 2;
+                            c.lpr = lpr;
+                            c.vec = vec;
+                            c.grid = std::max(1, std::min({p->op->t_ntiles, g, kMaxPassGrid}));
+                            bool dup = false;
+                            for (auto &o : cands2) dup = dup || (o.mode == 2 && o.lpr == lpr && o.vec == vec && o.grid == c.grid);
+                            if (!dup) cands2.push_back(c);
+                        }
+            for (const PassCfg &c : cands2) {
                 auto launch = [&]() {
-                    hip_check(launch_pass2(c, view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk],
-                                           cs.as<float>(), xs.as<float>(), cstep, st0, st1, p->B,
-                                           p->part_query.as<double>(), bestc.grid, none, s),
+                    hip_check(pass2_any(p, vk, c, cs.as<float>(), xs.as<float>(), cstep, st0, st1,
+                                        p->part_query.as<double>(), bestc.grid, none, s),
                               "tuning pass 2");
                 };
                 launch();
@@ -1174,15 +1367,22 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
                  "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
                  "\"fused\": %s}",
                  first ? "" : ", ", names[vk], a.mode ? "stream" : "rows", a.lpr, a.vec, a.grid, fmt_name(p->fmt1[vk]),
-                 b.mode ? "stream" : "rows", b.lpr, b.vec, b.grid, fmt_name(p->fmt2[vk]), fz);
+                 b.mode == 2 ? "tiles" : (b.mode ? "stream" : "rows"), b.lpr, b.vec, b.grid,
+                 b.mode == 2 ? (vk == VK_F32 ? "f32+u16" : (vk == VK_BF16 ? "bf16+u16" : "f16+u16"))
+                             : fmt_name(p->fmt2[vk]),
+                 fz);
         out += tmp;
         first = false;
     }
-    char tail[192];
+    char tail[320];
     static const char *basics[5] = {"simult", "drop", "cq", "el", "emr"};
+    char tiles[96] = "null";
+    if (p->op->has_tiles())
+        snprintf(tiles, sizeof tiles, "{\"count\": %d, \"rows\": %lld, \"slots\": %lld}", p->op->t_ntiles,
+                 (long long)(p->op->t_rlist.bytes / 4), (long long)p->op->tiles.slots);
     snprintf(tail, sizeof tail,
-             ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\", \"dose_volume\": %d}",
-             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic], p->dvc.n);
+             ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\", \"dose_volume\": %d, \"tiles\": %s}",
+             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic], p->dvc.n, tiles);
     out += tail;
     if (need) *need = out.size() + 1;
     if (buf && cap > 0) {
@@ -1222,6 +1422,15 @@ const char *smx_last_error(void) { return g_err.c_str(); }
 int smx_operator_create(const smx_csr *A, int32_t value_storage, int32_t keep_f32, void *stream, smx_operator **out)
 {
     SMX_GUARD(return create_operator(A, value_storage, keep_f32, (hipStream_t)stream, out);)
+}
+
+int smx_operator_create_image(const smx_csr *A, int32_t value_storage, int32_t keep_f32, int32_t image_rows,
+                              int32_t image_cols, void *stream, smx_operator **out)
+{
+    if (!A) return fail(SMX_EINVAL, "NULL argument");
+    if (image_rows < 1 || image_cols < 1 || (int64_t)image_rows * image_cols != A->n)
+        return fail(SMX_EINVAL, "image %d x %d does not match n = %lld", image_rows, image_cols, (long long)A->n);
+    SMX_GUARD(return create_operator(A, value_storage, keep_f32, (hipStream_t)stream, out, image_rows, image_cols);)
 }
 
 int smx_operator_destroy(smx_operator *op)

@@ -208,6 +208,7 @@ __device__ inline void idx_load(const int32_t *base, int p, int (&c)[VEC])
 
 struct Bf16PTag {};
 struct F16PTag {};
+struct F32U16Tag {}; // float32 values beside a uint16 index array
 
 // VEC entries (values as float, indices) starting at p.
 template <typename VT, int VEC>
@@ -236,6 +237,27 @@ __device__ inline void packed_load(const SpView &A, int p, float (&v)[VEC], int 
 }
 
 template <int VEC>
+struct Entries<F32U16Tag, VEC> {
+    static __device__ inline void load(const SpView &A, int p, float (&v)[VEC], int (&c)[VEC])
+    {
+        ValLoad<float, VEC>::load(A.val, p, v);
+        const uint16_t *ib = reinterpret_cast<const uint16_t *>(A.idx) + p;
+        if constexpr (VEC == 4) {
+            const uint2 a = *reinterpret_cast<const uint2 *>(ib);
+            c[0] = (int)(a.x & 0xFFFFu); c[1] = (int)(a.x >> 16); c[2] = (int)(a.y & 0xFFFFu); c[3] = (int)(a.y >> 16);
+        } else {
+            const uint4 a = *reinterpret_cast<const uint4 *>(ib);
+            const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                c[2 * k] = (int)(w[k] & 0xFFFFu);
+                c[2 * k + 1] = (int)(w[k] >> 16);
+            }
+        }
+    }
+};
+
+template <int VEC>
 struct Entries<Bf16PTag, VEC> {
     static __device__ inline void load(const SpView &A, int p, float (&v)[VEC], int (&c)[VEC])
     {
@@ -251,6 +273,78 @@ struct Entries<F16PTag, VEC> {
     }
 };
 
+// One entry at p: its value as float and its index.
+template <typename VT>
+__device__ inline void entry1(const SpView &A, int p, float &v, int &c);
+template <>
+__device__ inline void entry1<float>(const SpView &A, int p, float &v, int &c)
+{
+    v = static_cast<const float *>(A.val)[p];
+    c = A.idx[p];
+}
+template <>
+__device__ inline void entry1<Bf16Tag>(const SpView &A, int p, float &v, int &c)
+{
+    v = bf16_lo(static_cast<const uint16_t *>(A.val)[p]);
+    c = A.idx[p];
+}
+template <>
+__device__ inline void entry1<F16Tag>(const SpView &A, int p, float &v, int &c)
+{
+    v = f16_lo(static_cast<const uint16_t *>(A.val)[p]);
+    c = A.idx[p];
+}
+template <>
+__device__ inline void entry1<Bf16PTag>(const SpView &A, int p, float &v, int &c)
+{
+    const uint32_t w = static_cast<const uint32_t *>(A.val)[p];
+    v = bf16_lo(w);
+    c = (int)(w >> 16);
+}
+template <>
+__device__ inline void entry1<F16PTag>(const SpView &A, int p, float &v, int &c)
+{
+    const uint32_t w = static_cast<const uint32_t *>(A.val)[p];
+    v = f16_lo(w);
+    c = (int)(w >> 16);
+}
+template <>
+__device__ inline void entry1<F32U16Tag>(const SpView &A, int p, float &v, int &c)
+{
+    v = static_cast<const float *>(A.val)[p];
+    c = reinterpret_cast<const uint16_t *>(A.idx)[p];
+}
+
+// Partial dot product of one row with a vector, lanes interleaved: lane l of
+// an LPR-lane group takes entries beg + l, beg + l + LPR, ...  Neighbouring
+// lanes read neighbouring entries (one coalesced load per instruction), and
+// their gathers land on neighbouring entries of the row, which for a ray are
+// often neighbouring pixels in one cache line.  Eight entries per lane in
+// flight; entries past the row's end are skipped (LPR may exceed the row
+// alignment).
+template <int LPR, typename VT>
+__device__ inline double row_dot_interleaved(const SpView &A, int beg, int end, int lane, const float *__restrict__ x)
+{
+    constexpr int U = 8;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int p = beg + lane;
+    for (; p + (U - 1) * LPR < end; p += U * LPR) {
+        float v[U];
+        int c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) entry1<VT>(A, p + u * LPR, v[u], c[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u & 3] = fma((double)v[u], (double)x[c[u]], acc[u & 3]);
+    }
+    for (; p < end; p += LPR) {
+        float v0;
+        int c0;
+        entry1<VT>(A, p, v0, c0);
+        acc[0] = fma((double)v0, (double)x[c0], acc[0]);
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 // Partial dot product of one row with a vector, by lane `lane` of an LPR-lane
 // group.  [beg, end) is row-aligned, so every vector load is aligned and no
 // entry needs a mask (padding entries are zeros with valid indices).  Products
@@ -258,7 +352,7 @@ struct Entries<F16PTag, VEC> {
 // leaves only the rounding of the sums; the pass is bound by memory traffic,
 // not by the float64 rate.
 template <int LPR, int VEC, typename VT>
-__device__ inline double row_dot(const SpView &A, int beg, int end, int lane, const float *__restrict__ x)
+__device__ inline double row_dot_chunked(const SpView &A, int beg, int end, int lane, const float *__restrict__ x)
 {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int p = beg + lane * VEC;
@@ -284,6 +378,14 @@ __device__ inline double row_dot(const SpView &A, int beg, int end, int lane, co
         for (int e = 0; e < VEC; ++e) acc[0] = fma((double)v0[e], (double)x[c0[e]], acc[0]);
     }
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// VEC 1: interleaved lanes; otherwise chunks of VEC entries per lane.
+template <int LPR, int VEC, typename VT>
+__device__ inline double row_dot(const SpView &A, int beg, int end, int lane, const float *__restrict__ x)
+{
+    if constexpr (VEC == 1) return row_dot_interleaved<LPR, VT>(A, beg, end, lane, x);
+    else return row_dot_chunked<LPR, VEC, VT>(A, beg, end, lane, x);
 }
 
 template <int LPR>
@@ -656,6 +758,47 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
             s = group_sum_rt(s, rs.G);
             if (owner) yacc += epi2(cs, r0 + rs.rl, r0 + rs.rl, s * (double)At.vscale_inv, xo, l, u, x);
             __syncthreads();
+        }
+    }
+    end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
+}
+
+// Pass 2 over the image-tile column layout: a workgroup takes one tile at a
+// time, copies the tile's rows of c into LDS (one gather per row instead of
+// one per entry: a ray crosses several pixels of a tile), then sums each
+// column of the tile with LPR lanes from LDS and applies the column step.
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kBlock) void k_pass2_tile(TileView T, const float *__restrict__ c,
+                                                       float *__restrict__ x, ColStep cs,
+                                                       const SliceState *__restrict__ st_in,
+                                                       SliceState *__restrict__ st_out,
+                                                       const double *__restrict__ part1, int nparts1, Hist h)
+{
+    extern __shared__ float cl[];
+    __shared__ double lds[4];
+    constexpr int RPB = kBlock / LPR;
+    double yacc = 0.0;
+    if (st_in[0].live) {
+        const int lane = threadIdx.x & (LPR - 1);
+        const int grp = threadIdx.x / LPR;
+        for (int t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
+            const int r0 = T.rptr[t], nr = T.rptr[t + 1] - r0;
+            __syncthreads(); // the previous tile's readers are done with cl
+            for (int i = threadIdx.x; i < nr; i += kBlock) cl[i] = c[T.rlist[r0 + i]];
+            __syncthreads();
+            const int p0 = T.pptr[t], np = T.pptr[t + 1] - p0;
+            for (int q = grp; q < np; q += RPB) {
+                const int col = T.tcol[p0 + q];
+                const int beg = T.A.ptr[p0 + q], end = T.A.ptr[p0 + q + 1];
+                float xo = 0.f, l = 0.f, u = 0.f;
+                if (lane == 0 && !cs.defer) {
+                    xo = x[col];
+                    l = cs.lo[col];
+                    u = cs.hi[col];
+                }
+                const double y = group_sum<LPR>(row_dot<LPR, VEC, VT>(T.A, beg, end, lane, cl)) * (double)T.A.vscale_inv;
+                if (lane == 0) yacc += epi2(cs, col, col, y, xo, l, u, x);
+            }
         }
     }
     end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
@@ -1574,6 +1717,34 @@ __global__ __launch_bounds__(kTrialBlock) void k_trial_tv(float *__restrict__ x,
     }
 }
 
+// Closing launch of a phase: the decision of the last trial launch and, when
+// the phase ends there, the accepted step added to the whole of x (the same
+// arithmetic as the trial launches' own apply).  One workgroup per slice: in
+// most iterations an earlier trial launch has applied the step already and
+// this launch only carries the state over.  nt: workgroups per slice of the
+// trial launches (their partials' layout).
+__global__ __launch_bounds__(kTrialBlock) void k_trial_close(float *__restrict__ x, const float *__restrict__ g,
+                                                             const SliceState *__restrict__ st_in,
+                                                             SliceState *__restrict__ st_out, PertParams pp, int nt,
+                                                             const double *__restrict__ part_prev)
+{
+    __shared__ double tot[kTrialChunk];
+    __shared__ SliceState sS;
+    const int s = blockIdx.y, B = pp.B;
+    const bool lin = pp.obj == OBJ_LINEAR;
+    derive_state<kTrialBlock>(sS, st_in, pp, 0, part_prev, s, nt, tot);
+    const SliceState &S = sS;
+    const bool apply = must_apply(S);
+    if (apply) {
+        const double inv_gn = 1.0 / S.gn;
+        for (long long j = threadIdx.x; j < pp.n; j += kTrialBlock) {
+            const double gj = lin ? (double)g[j] : (double)g[j * B + s];
+            x[j * B + s] = (float)((double)x[j * B + s] + S.s_acc * (-gj * inv_gn));
+        }
+    }
+    publish_state(S, st_out, s, apply);
+}
+
 // Trial launch for the squared norm and the linear objective (flat vectors).
 __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, const float *__restrict__ g,
                                                        const SliceState *__restrict__ st_in,
@@ -1892,6 +2063,16 @@ static hipError_t pass1_vec(const PassCfg &cfg, const SpView &A, const float *x,
                             double *partials, hipStream_t s)
 {
     const dim3 grid(cfg.grid), block(kBlock);
+    if constexpr (VEC == 1) { // interleaved lanes: 8 to 64 lanes per row
+        switch (cfg.lpr) {
+        case 8: hipLaunchKernelGGL((k_pass1<8, 1, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+        case 16: hipLaunchKernelGGL((k_pass1<16, 1, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+        case 32: hipLaunchKernelGGL((k_pass1<32, 1, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+        case 64: hipLaunchKernelGGL((k_pass1<64, 1, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (cfg.lpr) {
     case 2: hipLaunchKernelGGL((k_pass1<2, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
     case 4: hipLaunchKernelGGL((k_pass1<4, VEC, VT>), grid, block, 0, s, A, x, lower, upper, w, c, st, query, partials); break;
@@ -1964,21 +2145,26 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
         return pass1_stream<F16Tag, 8>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_BF16P) {
+        if (cfg.vec == 1) return pass1_vec<Bf16PTag, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         if (cfg.vec == 8) return pass1_vec<Bf16PTag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         return pass1_vec<Bf16PTag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_F16P) {
+        if (cfg.vec == 1) return pass1_vec<F16PTag, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         if (cfg.vec == 8) return pass1_vec<F16PTag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         return pass1_vec<F16PTag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_F32) {
+        if (cfg.vec == 1) return pass1_vec<float, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         if (cfg.vec == 8) return pass1_vec<float, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         return pass1_vec<float, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_BF16) {
+        if (cfg.vec == 1) return pass1_vec<Bf16Tag, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         if (cfg.vec == 8) return pass1_vec<Bf16Tag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         return pass1_vec<Bf16Tag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
+    if (cfg.vec == 1) return pass1_vec<F16Tag, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     if (cfg.vec == 8) return pass1_vec<F16Tag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     return pass1_vec<F16Tag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
 }
@@ -2043,6 +2229,41 @@ static hipError_t pass2_mm_b(const PassCfg &cfg, const SpView &At, const float *
     case 32: return pass2_mm<VT, VEC, 32>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <typename VT, int VEC>
+hipError_t pass2_tiles(const PassCfg &cfg, const TileView &T, const float *c, float *x, ColStep cs,
+                       const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                       hipStream_t s)
+{
+    const dim3 grid(cfg.grid), block(kBlock);
+    const size_t shm = sizeof(float) * size_t(T.max_rows > 0 ? T.max_rows : 1);
+#define SMX_P2T(L) hipLaunchKernelGGL((k_pass2_tile<L, VEC, VT>), grid, block, shm, s, T, c, x, cs, st_in, st_out, part1, nparts1, h)
+    switch (cfg.lpr) {
+    case 2: SMX_P2T(2); break;
+    case 4: SMX_P2T(4); break;
+    case 8: SMX_P2T(8); break;
+    case 16: SMX_P2T(16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_P2T
+    return hipGetLastError();
+}
+
+hipError_t launch_pass2_tiles(const PassCfg &cfg, const TileView &T, int vk, const float *c, float *x, ColStep cs,
+                              const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                              hipStream_t s)
+{
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
+    if (T.ntiles < 1 || T.max_rows < 0 || size_t(T.max_rows) * sizeof(float) > 65536) return hipErrorInvalidValue;
+    const bool v8 = cfg.vec == 8;
+    if (vk == VK_F32) return v8 ? pass2_tiles<F32U16Tag, 8>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s)
+                                : pass2_tiles<F32U16Tag, 4>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    if (vk == VK_BF16P) return v8 ? pass2_tiles<Bf16PTag, 8>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s)
+                                  : pass2_tiles<Bf16PTag, 4>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    if (vk == VK_F16P) return v8 ? pass2_tiles<F16PTag, 8>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s)
+                                 : pass2_tiles<F16PTag, 4>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
@@ -2540,6 +2761,15 @@ hipError_t launch_iter_norms(const float *x, const float *xprev, int64_t n, int 
 hipError_t launch_stop_var(SliceState *st, int B, const double *partials, int nparts, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stop_var, dim3(1), dim3(kBlock), 0, s, st, B, partials, nparts);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_close(const PertParams &pp, float *x, const float *g, const SliceState *st_in,
+                              SliceState *st_out, const double *part_prev, hipStream_t s)
+{
+    if (pp.max_trials < 1 || pp.max_trials > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_trial_close, dim3(1, pp.B), dim3(kTrialBlock), 0, s, x, g, st_in, st_out, pp,
+                       (int)phase_grid(pp), part_prev);
     return hipGetLastError();
 }
 

@@ -102,7 +102,8 @@ struct Hist {
 constexpr int kStreamEntries = 2048; // entries per row block of the streaming pass kernels
 
 struct PassCfg {
-    int mode; // 0: a group of lpr lanes per row; 1: row blocks streamed through LDS
+    int mode; // 0: a group of lpr lanes per row; 1: row blocks streamed through LDS;
+              // 2: (pass 2 of an image operator) image tiles, lpr lanes per column
     int lpr;  // lanes per row (mode 0): 2, 4, 8, 16, 32 or 64
     int vec;  // entries per lane per load: 4 or 8
     int grid; // workgroups
@@ -181,6 +182,24 @@ struct FusedCfg {
     int acc64; // 1: float64 LDS accumulators, 0: float32
 };
 
+// Column layout grouped by image tiles (A^T for an operator whose unknowns
+// are the pixels of an image): tile t owns the columns tcol[pptr[t] ..
+// pptr[t+1]) (its pixels, in row order inside the tile) and the rows
+// rlist[rptr[t] .. rptr[t+1]) that touch them (ascending).  A is the CSR of
+// the tile columns in that order, whose indices are 16-bit positions in the
+// tile's row list: a float32 copy (values beside a uint16 index array) and/or
+// packed 16-bit words.  Rays crossing a tile touch many of its pixels, so the
+// pass stages the tile's rows of c in LDS once and gathers from there.
+struct TileView {
+    SpView A;
+    const int32_t *tcol;
+    const int32_t *pptr;
+    const int32_t *rptr;
+    const int32_t *rlist;
+    int ntiles;
+    int max_rows; // most rows of one tile (LDS floats the pass needs)
+};
+
 // Row blocks of a row-aligned layout for the streaming kernels: block b holds
 // rows [rb[b], rb[b+1]), at most kBlock rows and at most kStreamEntries
 // entries, or a single longer row.
@@ -222,6 +241,11 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
                         ColStep cs, const SliceState *st_in, SliceState *st_out, int B, const double *part1,
                         int nparts1, Hist h, hipStream_t s);
+// pass 2 over the image-tile column layout (one slice): per tile, the rows of
+// c it needs staged in LDS, then y_j and the column step for its pixels
+hipError_t launch_pass2_tiles(const PassCfg &cfg, const TileView &T, int vk, const float *c, float *x, ColStep cs,
+                              const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                              hipStream_t s);
 // x = clip(z + lambda * sigma_s * y, lo, hi) for the extrapolated steps, sigma_s
 // per slice from the partials: EL (emr = 0) t^T D t / ||y||^2 from pass 1's
 // and pass 2's partials, EMR (emr = 1) ||y||^2 / sum w (A y)^2 from pass 2's and
@@ -272,6 +296,9 @@ hipError_t launch_eval_objective(SliceState *st, const PertParams &pp, const dou
 // partials), then with `evaluate` the next batch of trial steps (partials
 // [max_trials][B*tiles] into part_out), or adds the accepted step to x once
 // the phase is over.  The derived state goes to st_out.
+// the closing launch of a phase (one workgroup per slice)
+hipError_t launch_trial_close(const PertParams &pp, float *x, const float *g, const SliceState *st_in,
+                              SliceState *st_out, const double *part_prev, hipStream_t s);
 hipError_t launch_trial(const PertParams &pp, float *x, const float *g, const SliceState *st_in, SliceState *st_out,
                         int first, int evaluate, const double *part_prev, double *part_out, hipStream_t s);
 

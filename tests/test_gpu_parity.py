@@ -398,6 +398,21 @@ def test_ct256_full_bench_configuration(smx):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_interleaved_lane_pass1(smx, storage, monkeypatch):
+    """Pass 1 with interleaved lanes (lane l of a row takes entries l, l + 16,
+    ...) against the oracle, on skewed rows and on CT."""
+    monkeypatch.setenv("SMX_PASS_MODE", "interleaved")
+    w = W.random_sparse(3000, 2000, 12, seed=44, empty_frac=0.08, long_rows=2, obj=W.OBJ_SQNORM, K=20)
+    p = smx.problem_from_workload(w, storage=storage)
+    assert p.describe()[storage]["pass1"]["vec"] == 1
+    p.close()
+    vr = None if storage == "f32" else storage
+    check_parity(smx, w, w.K, storage=storage, value_round=vr)
+    wc = W.ct(N=48, n_angles=36, seed=45, K=30)
+    check_parity(smx, wc, wc.K, storage=storage, value_round=vr, sensitive=True)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_lanes_per_row_kernels(smx, storage, monkeypatch):
     """The lanes-per-row pass kernels (the alternative launch shape) give the
     same results as the oracle too."""
@@ -869,3 +884,42 @@ def test_dvc_invalid_args(smx):
             smx.Problem(op, lower=w.lower, upper=w.upper, dvc=tab)
         assert e.value.code == smx.EINVAL, tab
     op.close()
+
+
+# ---------------------------------------------------------------------------
+# image operators: A^T over 8 x 8 pixel tiles with each tile's rows in LDS
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_image_tiles_pass(smx, storage, monkeypatch):
+    """An image operator's one-slice problems take pass 2 over the tile layout
+    (ragged edge tiles: a 30 x 60 image); the results match the oracle and,
+    to float32 rounding, the column copy's pass."""
+    w = W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=9, K=40, variant="paper")
+    info = smx.problem_from_workload(w, storage=storage)
+    d = info.describe()[storage]["pass2"]
+    info.close()
+    assert d["mode"] == "tiles" and d["format"].endswith("+u16"), d
+    vr = None if storage == "f32" else storage
+    xt, ht = check_parity(smx, w, w.K, storage=storage, value_round=vr, sensitive=True)
+    monkeypatch.setenv("SMX_TILES", "0")
+    p = smx.problem_from_workload(w, storage=storage)
+    assert p.describe()[storage]["pass2"]["mode"] != "tiles"
+    p.close()
+    xc, hc = check_parity(smx, w, w.K, storage=storage, value_round=vr, sensitive=True)
+    assert np.array_equal(ht["trials"], hc["trials"])
+    assert rel(xt, xc) < 1e-5
+
+
+def test_image_tiles_autotuned_ct(smx):
+    """CT-64 with the autotuner choosing among tile and column shapes."""
+    w = W.ct(N=64, n_angles=48, seed=12, K=30)
+    p = smx.problem_from_workload(w, history_cap=w.K)
+    shapes = p.autotune(reps=2)
+    p.run(w.K)
+    p.sync()
+    x = p.get_x().cpu().numpy().astype(np.float64)
+    p.close()
+    say(f"ct64 autotuned pass 2: {shapes['f32']['pass2']}")
+    xo, _, _, _ = oracle_run(w, w.K)
+    assert rel(x[:, 0], xo) < max(RTOL, 10 * storage_deviation(w, w.K)[0])

@@ -65,6 +65,7 @@ class Workload:
     # dose-volume constraints: dicts with row_begin, row_end (the structure's
     # rows), sense (DVC_MAX / DVC_MIN), fraction (V) and dose (d)
     dvc: Optional[list] = None
+    image: Optional[tuple] = None  # (rows, cols) when the unknowns are the pixels of an image, row-major
     x_true: Optional[np.ndarray] = None  # float32 [n, B]
     meta: dict = field(default_factory=dict)
 
@@ -224,6 +225,7 @@ def random_sparse(
         name=f"rand{m}x{n}",
         m=m,
         n=n,
+        image=tuple(tv_shape) if tv_shape is not None else None,
         row_ptr=row_ptr.astype(np.int32),
         col_idx=cols,
         val=vals,
@@ -390,6 +392,7 @@ def ct(
         name=f"ct{N}",
         m=m,
         n=n,
+        image=(N, N),
         row_ptr=row_ptr,
         col_idx=cols,
         val=val,
@@ -588,6 +591,7 @@ def seismic_fresnel(
         name=f"seismic_fresnel{N}",
         m=m,
         n=n,
+        image=(N, N),
         row_ptr=row_ptr,
         col_idx=cols_idx,
         val=val,
@@ -652,6 +656,7 @@ def seismic(
         name=f"seismic{rows}x{cols}",
         m=m,
         n=n,
+        image=(rows, cols),
         row_ptr=row_ptr,
         col_idx=cols_idx,
         val=val,
