@@ -145,6 +145,7 @@ std::vector<int32_t> build_row_blocks(const std::vector<int32_t> &ptr, int64_t r
 struct DevLayout {
     int64_t rows = 0, slots = 0;
     DBuf ptr, idx, val32, val16, packed, rowblk; // packed: 16-bit value | 16-bit index << 16
+    DBuf idx16; // 16-bit copy of idx beside the float32 values (index range <= 65536)
     int nblk = 0;
     float f16_scale = 1.f;
     RowBlocks blocks() const
@@ -159,7 +160,8 @@ struct DevLayout {
         SpView v;
         v.ptr = ptr.as<int32_t>();
         v.idx = idx.as<int32_t>();
-        v.val = (vk == VK_F32) ? val32.p : ((vk == VK_BF16P || vk == VK_F16P) ? packed.p : val16.p);
+        v.val = (vk == VK_F32 || vk == VK_F32U16) ? val32.p : ((vk == VK_BF16P || vk == VK_F16P) ? packed.p : val16.p);
+        if (vk == VK_F32U16) v.idx = idx16.as<int32_t>(); // read as uint16 by the kernels
         v.rows = rows;
         v.vscale_inv = (vk == VK_F16 || vk == VK_F16P) ? 1.f / f16_scale : 1.f;
         return v;
@@ -169,11 +171,11 @@ struct DevLayout {
 // Device bytes of one layout: offsets, then per entry the 32-bit index and value
 // when float32 is kept, and the reduced-precision value either alone (beside
 // the index) or packed with a 16-bit index into one word.
-size_t layout_bytes(int64_t rows, int64_t slots, bool f32, bool lp, bool packed)
+size_t layout_bytes(int64_t rows, int64_t slots, bool f32, bool lp, bool packed, bool short_idx)
 {
     const bool idx32 = f32 || !packed;
     return size_t(rows + 1) * 4 + (idx32 ? size_t(slots) * 4 : 0) + (f32 ? size_t(slots) * 4 : 0) +
-           (lp ? size_t(slots) * (packed ? 4 : 2) : 0);
+           (lp ? size_t(slots) * (packed ? 4 : 2) : 0) + (f32 && short_idx ? size_t(slots) * 2 : 0);
 }
 
 float f16_scale_for(const std::vector<float> &v)
@@ -345,6 +347,10 @@ SpView view_for(const smx_operator *op, bool transposed, int vk)
     return transposed ? op->csc.view(vk) : op->csr.view(vk);
 }
 
+// Format the fused pass reads for value kind vk (its kernels take the 32-bit
+// indices of the float32 copy).
+int fused_fmt(const smx_problem *p, int vk);
+
 int validate_csr_host(const smx_csr *A, const int32_t *rp, const int32_t *ci, const float *v)
 {
     if (rp[0] != 0) return fail(SMX_EINVAL, "row_ptr[0] must be 0 (got %d)", rp[0]);
@@ -391,6 +397,11 @@ void upload_layout(DevLayout &D, HostLayout &H, int64_t rows, int64_t index_rang
     upload(D.ptr, H.ptr, s, "upload row pointers");
     upload(D.idx, H.idx, s, "upload indices");
     upload(D.val32, H.val, s, "upload values");
+    if (keep32 && index_range <= 65536) { // float32 values with 16-bit indices: 6 bytes per entry
+        std::vector<uint16_t> i16(H.idx.size());
+        for (size_t p = 0; p < H.idx.size(); ++p) i16[p] = (uint16_t)H.idx[p];
+        upload(D.idx16, i16, s, "upload 16-bit indices");
+    }
     if (lp != VK_F32) {
         D.val16.alloc(sizeof(uint16_t) * std::max<int64_t>(H.slots, 1), "allocate reduced-precision values");
         if (lp == VK_BF16) hip_check(launch_to_bf16(D.val32.as<float>(), D.val16.as<uint16_t>(), H.slots, s), "to bf16");
@@ -597,8 +608,10 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
         hip_check(launch_rownorm(op->csr.view(fmt), fmt, op->q16.as<double>(), s), "row norms (reduced precision)");
     }
     hip_check(hipStreamSynchronize(s), "operator setup");
-    op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32, op->csr.packed.p != nullptr) +
-                layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32, op->csc.packed.p != nullptr) +
+    op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32, op->csr.packed.p != nullptr,
+                             op->csr.idx16.p != nullptr) +
+                layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32, op->csc.packed.p != nullptr,
+                             op->csc.idx16.p != nullptr) +
                 size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0)) + size_t(n) * 4;
     if (op->has_tiles())
         op->bytes += size_t(op->n + 1) * 4 + size_t(op->tiles.slots) * ((op->has_f32 ? 6 : 0) + (lp != VK_F32 ? 4 : 0)) +
@@ -619,6 +632,8 @@ int vk_for_iteration(const smx_problem *p, int64_t it, int64_t K, int64_t ref)
     if (!p->op->has_f32) return lp;
     return (it >= K - ref) ? VK_F32 : lp;
 }
+
+int fused_fmt(const smx_problem *p, int vk) { return p->fmt1[vk] == VK_F32U16 ? VK_F32 : p->fmt1[vk]; }
 
 // Pass 2 in launch shape c: the image-tile layout (mode 2) or the column copy.
 hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float *cres, float *x, ColStep cs,
@@ -673,7 +688,7 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
         hip_check(hipEventRecord(e[0], s), "event");
     }
     if (p->fused[vk]) {
-        hip_check(launch_fused(p->fcfg[vk], view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], p->n, p->x.as<float>(),
+        hip_check(launch_fused(p->fcfg[vk], view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), p->n, p->x.as<float>(),
                                p->lower.as<float>(), p->upper.as<float>(), rw, p->state(cur),
                                p->part_pass.as<double>(), p->ypart.p, s),
                   "fused pass");
@@ -885,7 +900,7 @@ void setup_fused(smx_problem *p)
         if (!present) continue;
         bool ok = true;
         for (const FusedCfg &t : fused_candidates(c))
-            if (prepare_fused(t, p->fmt1[vk], p->n) != hipSuccess) ok = false;
+            if (prepare_fused(t, fused_fmt(p, vk), p->n) != hipSuccess) ok = false;
         (void)hipGetLastError();
         p->fused_ok[vk] = p->fused[vk] = ok;
         p->fcfg[vk] = c;
@@ -1088,6 +1103,10 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     const bool inter_mode = mode_env && std::strcmp(mode_env, "interleaved") == 0;
     const char *tiles_env = getenv("SMX_TILES"); // "0" keeps the column copy for pass 2
     const bool use_tiles = op->has_tiles() && B == 1 && !(tiles_env && std::strcmp(tiles_env, "0") == 0);
+    if (B == 1 && op->has_f32) { // one slice: the float32 passes read 16-bit indices where the range allows
+        if (op->csr.idx16.p) p->fmt1[VK_F32] = VK_F32U16;
+        if (op->csc.idx16.p) p->fmt2[VK_F32] = VK_F32U16;
+    }
     p->tiles_ok = use_tiles;
     for (int vk = 0; vk < 3; ++vk) {
         p->cfg1[vk] = (rows_mode && B == 1) ? pick_cfg_rows(op->csr, vk) : pick_cfg(op->csr, vk, B);
@@ -1294,7 +1313,7 @@ int autotune_impl(smx_problem *p, int reps)
                 FusedCfg bestfc = p->fcfg[vk];
                 for (const FusedCfg &c : fused_candidates(p->fcfg[vk])) {
                     auto launch = [&]() {
-                        hip_check(launch_fused(c, view_for(p->op, false, p->fmt1[vk]), p->fmt1[vk], n, xs.as<float>(),
+                        hip_check(launch_fused(c, view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), n, xs.as<float>(),
                                                p->lower.as<float>(), p->upper.as<float>(), rw, st0,
                                                p->part_query.as<double>(), p->ypart.p, s),
                                   "tuning fused pass");
@@ -1339,6 +1358,7 @@ const char *fmt_name(int f)
     case VK_BF16: return "bf16+i32";
     case VK_F16: return "f16+i32";
     case VK_BF16P: return "bf16+u16";
+    case VK_F32U16: return "f32+u16";
     default: return "f16+u16";
     }
 }
@@ -1447,7 +1467,8 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
     const bool f32 = !lp || keep_f32;
     // upper bound on padding: kRowAlign-1 entries per row and per column
     const int64_t s1 = nnz + (kRowAlign - 1) * m, s2 = nnz + (kRowAlign - 1) * n;
-    *bytes = layout_bytes(m, s1, f32, lp, lp && n <= 65536) + layout_bytes(n, s2, f32, lp, lp && m <= 65536) +
+    *bytes = layout_bytes(m, s1, f32, lp, lp && n <= 65536, n <= 65536) +
+             layout_bytes(n, s2, f32, lp, lp && m <= 65536, m <= 65536) +
              size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0)) + size_t(n) * 4;
     return SMX_OK;
 }

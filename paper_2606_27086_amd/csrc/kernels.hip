@@ -2131,6 +2131,7 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
     if (B > 1) {
+        if (vk == VK_F32U16) return hipErrorInvalidValue;
         if (vk == VK_F32) return pass1_mm_b<float, 4>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
         if (vk == VK_BF16) return pass1_mm_b<Bf16Tag, 8>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
         if (vk == VK_BF16P) return pass1_mm_b<Bf16PTag, 4>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
@@ -2138,6 +2139,7 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
         return pass1_mm_b<F16Tag, 8>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
     }
     if (cfg.mode == 1) {
+        if (vk == VK_F32U16) return pass1_stream<F32U16Tag, 4>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
         if (vk == VK_F32) return pass1_stream<float, 4>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
         if (vk == VK_BF16) return pass1_stream<Bf16Tag, 8>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
         if (vk == VK_BF16P) return pass1_stream<Bf16PTag, 4>(cfg, A, RB, x, lower, upper, w, c, st, query, partials, s);
@@ -2153,6 +2155,11 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
         if (cfg.vec == 1) return pass1_vec<F16PTag, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         if (cfg.vec == 8) return pass1_vec<F16PTag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
         return pass1_vec<F16PTag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+    }
+    if (vk == VK_F32U16) {
+        if (cfg.vec == 1) return pass1_vec<F32U16Tag, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+        if (cfg.vec == 8) return pass1_vec<F32U16Tag, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
+        return pass1_vec<F32U16Tag, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
     }
     if (vk == VK_F32) {
         if (cfg.vec == 1) return pass1_vec<float, 1>(cfg, A, x, lower, upper, w, c, st, query, partials, s);
@@ -2272,6 +2279,7 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
     if (B > 1) {
+        if (vk == VK_F32U16) return hipErrorInvalidValue;
         if (vk == VK_F32) return pass2_mm_b<float, 4>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
         if (vk == VK_BF16) return pass2_mm_b<Bf16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
         if (vk == VK_BF16P) return pass2_mm_b<Bf16PTag, 4>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
@@ -2279,6 +2287,7 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
         return pass2_mm_b<F16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
     }
     if (cfg.mode == 1) {
+        if (vk == VK_F32U16) return pass2_stream<F32U16Tag, 4>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
         if (vk == VK_F32) return pass2_stream<float, 4>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
         if (vk == VK_BF16) return pass2_stream<Bf16Tag, 8>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
         if (vk == VK_BF16P) return pass2_stream<Bf16PTag, 4>(cfg, At, RB, c, x, cs, st_in, st_out, part1, nparts1, h, s);
@@ -2292,6 +2301,10 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
     if (vk == VK_F16P) {
         if (cfg.vec == 8) return pass2_vec<F16PTag, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
         return pass2_vec<F16PTag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    }
+    if (vk == VK_F32U16) {
+        if (cfg.vec == 8) return pass2_vec<F32U16Tag, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return pass2_vec<F32U16Tag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     }
     if (vk == VK_F32) {
         if (cfg.vec == 8) return pass2_vec<float, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);

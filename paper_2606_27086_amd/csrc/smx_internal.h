@@ -20,7 +20,9 @@ constexpr int kFusedRcBlock = 512; // the same for the register-cached fused pas
 // Stored formats of A's entries.  The packed kinds hold one 32-bit word per
 // entry: the 16-bit value in the low half, a 16-bit index in the high half
 // (used when the layout's index range fits in 16 bits).
-enum ValKind : int { VK_F32 = 0, VK_BF16 = 1, VK_F16 = 2, VK_BF16P = 3, VK_F16P = 4 };
+// VK_F32U16: float32 values beside a uint16 index array (a layout whose
+// index range fits in 16 bits, one-slice passes).
+enum ValKind : int { VK_F32 = 0, VK_BF16 = 1, VK_F16 = 2, VK_BF16P = 3, VK_F16P = 4, VK_F32U16 = 5 };
 enum ObjKind : int { OBJ_NONE = 0, OBJ_SQNORM = 1, OBJ_TV2D = 2, OBJ_LINEAR = 3, OBJ_L1 = 4 };
 
 // Device view of one row-aligned sparse layout: the CSR of A (pass 1) or the
