@@ -65,6 +65,7 @@ def alg_bytes(m, n, nnz, shapes, B=1, tiles=None):
     e1 = ENTRY_BYTES[shapes["pass1"]["format"]]
     if fused_in_use(shapes):
         f = shapes["fused"]
+        e1 = ENTRY_BYTES[f["format"]]
         acc = 8 if f["acc"] == "f64" else 4
         p1 = nnz * e1 + 4 * (m + 1) + 12 * m + 4 * n + 8 * n
         p2 = acc * n * f["grid"] + 16 * n
@@ -84,7 +85,9 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
         f = shapes["fused"]
         acc = "double" if f["acc"] == "f64" else "float"
         if pass_no == 1:
-            return f"smx::k_fused<{f['lpr']}, {f['vec']}, {VALUE_TAG[shapes['pass1']['format']]}, {acc}>"
+            if f.get("cap", 0):
+                return f"smx::k_fused_rc<{f['lpr']}, {f['vec']}, {f['cap']}, {VALUE_TAG[f['format']]}, {acc}>"
+            return f"smx::k_fused<{f['lpr']}, {f['vec']}, {VALUE_TAG[f['format']]}, {acc}>"
         return f"smx::k_fused_apply<{acc}>"
     vt = VALUE_TAG[shape["format"]]
     if shape["mode"] == "tiles":

@@ -1373,12 +1373,14 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         if (vk != VK_F32 && p->op->lp_kind() != vk) continue;
         char tmp[768];
         const PassCfg &a = p->cfg1[vk], &b = p->cfg2[vk];
-        char fz[160];
+        char fz[224];
         if (p->fused_ok[vk]) {
             const FusedCfg &f = p->fcfg[vk];
             snprintf(fz, sizeof fz,
-                     "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"cap\": %d, \"grid\": %d, \"acc\": \"%s\"}",
-                     p->fused[vk] ? "true" : "false", f.lpr, f.vec, f.cap, f.grid, f.acc64 ? "f64" : "f32");
+                     "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"cap\": %d, \"grid\": %d, \"acc\": \"%s\", "
+                     "\"format\": \"%s\"}",
+                     p->fused[vk] ? "true" : "false", f.lpr, f.vec, f.cap, f.grid, f.acc64 ? "f64" : "f32",
+                     fmt_name(fused_fmt(p, vk)));
         } else {
             snprintf(fz, sizeof fz, "null");
         }
