@@ -347,8 +347,7 @@ SpView view_for(const smx_operator *op, bool transposed, int vk)
     return transposed ? op->csc.view(vk) : op->csr.view(vk);
 }
 
-// Format the fused pass reads for value kind vk (its kernels take the 32-bit
-// indices of the float32 copy).
+// Format the fused pass reads for value kind vk (the same copy as pass 1).
 int fused_fmt(const smx_problem *p, int vk);
 
 int validate_csr_host(const smx_csr *A, const int32_t *rp, const int32_t *ci, const float *v)
@@ -633,7 +632,7 @@ int vk_for_iteration(const smx_problem *p, int64_t it, int64_t K, int64_t ref)
     return (it >= K - ref) ? VK_F32 : lp;
 }
 
-int fused_fmt(const smx_problem *p, int vk) { return p->fmt1[vk] == VK_F32U16 ? VK_F32 : p->fmt1[vk]; }
+int fused_fmt(const smx_problem *p, int vk) { return p->fmt1[vk]; }
 
 // Pass 2 in launch shape c: the image-tile layout (mode 2) or the column copy.
 hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float *cres, float *x, ColStep cs,

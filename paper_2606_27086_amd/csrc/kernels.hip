@@ -2401,6 +2401,7 @@ hipError_t fused_dispatch(const FusedCfg &cfg, int vk, const FusedArgs &a, int p
     case VK_F16: return fused_acc<F16Tag>(cfg, a, prepare, s);
     case VK_BF16P: return fused_acc<Bf16PTag>(cfg, a, prepare, s);
     case VK_F16P: return fused_acc<F16PTag>(cfg, a, prepare, s);
+    case VK_F32U16: return fused_acc<F32U16Tag>(cfg, a, prepare, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -138,3 +138,17 @@ def test_struct_layouts_match_header(smx, tmp_path):
         assert int(v) == want, (cname, f, int(v), want)
         seen += 1
     assert seen == sum(len(p._fields_) + 1 for p in structs.values())
+
+
+@pytest.mark.parametrize("shape", [(0, 6), (2, 2), (3, 3), (-1, -6), (6, 0)])
+def test_image_shape_rejected_on_host(smx, shape):
+    """smx_operator_create_image checks that the image covers exactly n
+    unknowns before it touches the device."""
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 5, 1, 2], np.int32)
+    val = np.ones(4, np.float32)
+    csr = smx.Csr(2, 6, 4, rp.ctypes.data, ci.ctypes.data, val.ctypes.data, 0)
+    h = C.c_void_p()
+    rc = smx.lib().smx_operator_create_image(C.byref(csr), 0, 1, shape[0], shape[1], None, C.byref(h))
+    assert rc == smx.EINVAL and "image" in smx.lib().smx_last_error().decode()
+    assert not h.value

@@ -923,3 +923,29 @@ def test_image_tiles_autotuned_ct(smx):
     say(f"ct64 autotuned pass 2: {shapes['f32']['pass2']}")
     xo, _, _, _ = oracle_run(w, w.K)
     assert rel(x[:, 0], xo) < max(RTOL, 10 * storage_deviation(w, w.K)[0])
+
+
+def test_image_tiles_absent_when_a_tile_has_too_many_rows(smx):
+    """A tile touched by more rows than its LDS copy holds (16,384) leaves the
+    operator without the tile layout; pass 2 reads the column copy."""
+    m, R, C = 20000, 8, 8
+    rng = np.random.default_rng(48)
+    cols = rng.integers(0, R * C, size=(m, 2))
+    cols.sort(axis=1)
+    cols[:, 1] = np.where(cols[:, 1] == cols[:, 0], (cols[:, 0] + 1) % (R * C), cols[:, 1])
+    cols.sort(axis=1)
+    row_ptr = np.arange(0, 2 * m + 1, 2, dtype=np.int32)
+    val = rng.uniform(0.5, 1.5, 2 * m).astype(np.float32)
+    xs = rng.uniform(0, 1, R * C)
+    A = np.zeros((m, R * C))
+    A[np.repeat(np.arange(m), 2), cols.reshape(-1)] = val
+    b = A @ xs
+    w = W.Workload(name="dense_rows", m=m, n=R * C, row_ptr=row_ptr, col_idx=cols.reshape(-1).astype(np.int32),
+                   val=val, lower=(b - 0.05).astype(np.float32)[:, None], upper=(b + 0.05).astype(np.float32)[:, None],
+                   box_lo=np.zeros(R * C, np.float32), box_hi=np.ones(R * C, np.float32),
+                   x0=np.full((R * C, 1), 0.5, np.float32), obj=W.OBJ_SQNORM, K=10, image=(R, C))
+    p = smx.problem_from_workload(w)
+    d = p.describe()
+    p.close()
+    assert d["tiles"] is None and d["f32"]["pass2"]["mode"] != "tiles"
+    check_parity(smx, w, w.K)
