@@ -266,8 +266,10 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
  * outside (0,1), n_red < 1, max_trials outside 1..1024, TV with rows*cols !=
  * n, LINEAR with a NULL c, dose-volume constraints whose row blocks are empty,
  * outside [0, m) or not consecutive, whose fraction is outside [0, 1], whose
- * dose is not finite or whose sense is unknown.  EL and EMR keep y (n*B floats) and run the two
- * passes (never the fused pass); EMR adds a third pass over A per iteration.
+ * dose is not finite or whose sense is unknown.  EL and EMR keep y (n*B
+ * doubles) and apply the step after it is complete (with the fused pass, its
+ * apply kernel keeps y instead of moving x); EMR adds a pass over A per
+ * iteration for sum_i w_i (A y)_i^2.
  */
 int smx_problem_create(smx_operator *op, const smx_problem_desc *desc, void *stream, smx_problem **out);
 

@@ -648,6 +648,26 @@ hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float
                         st_out, p->B, part1, nparts1, h, s);
 }
 
+// The extrapolated steps after y is kept: EMR's quadratic form sum_i w_i
+// (A y)_i^2 (pass 1's kernels gathering y), then k_step_apply, which closes
+// the iteration into the other state buffer.  nparts1: partials of pass 1 (or
+// the fused pass), nparts_y: partials of ||y||^2.
+void enqueue_extrapolated_step(smx_problem *p, int vk, const RowW &rw, int nparts1, int nparts_y, int cur,
+                               hipStream_t s)
+{
+    const bool emr = p->basic == SMX_BASIC_EMR;
+    if (emr)
+        hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
+                               p->ybuf32.as<float>(), p->lower.as<float>(), p->upper.as<float>(), RowW{rw.D, rw.S, 1},
+                               p->c.as<float>(), p->state(cur), p->B, 0, p->part_q.as<double>(), s),
+                  "quadratic form");
+    hip_check(launch_step_apply(p->n, p->B, p->ybuf.as<double>(), p->x.as<float>(), p->box_lo.as<float>(),
+                                p->box_hi.as<float>(), p->lambda, emr ? 1 : 0, p->part_pass.as<double>(), nparts1,
+                                p->part_y.as<double>(), nparts_y, p->part_q.as<double>(), p->cfg1[vk].grid,
+                                p->state(cur), p->state(cur ^ 1), p->hist, s),
+              "extrapolated step");
+}
+
 // Enqueue one outer iteration with value kind vk on stream s, starting from
 // state buffer `cur`; returns the buffer current after it.
 int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
@@ -674,7 +694,6 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
         cur ^= 1;
     }
     const RowW rw = p->row_weights(vk);
-    const ColStep cstep = p->col_step(false);
     hipEvent_t e[4] = {};
     if (timed) {
         while (p->ev_pool.size() < p->ev_used + 4) {
@@ -686,6 +705,7 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
         p->ev_used += 4;
         hip_check(hipEventRecord(e[0], s), "event");
     }
+    const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
     if (p->fused[vk]) {
         hip_check(launch_fused(p->fcfg[vk], view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), p->n, p->x.as<float>(),
                                p->lower.as<float>(), p->upper.as<float>(), rw, p->state(cur),
@@ -695,11 +715,12 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
             hip_check(hipEventRecord(e[1], s), "event");
             hip_check(hipEventRecord(e[2], s), "event");
         }
-        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, p->x.as<float>(), cstep, p->state(cur),
-                                     p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s),
+        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, p->x.as<float>(), p->col_step(extrap),
+                                     p->state(cur), p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s),
                   "fused apply");
-        cur ^= 1;
         if (timed) hip_check(hipEventRecord(e[3], s), "event");
+        if (extrap) enqueue_extrapolated_step(p, vk, rw, p->fcfg[vk].grid, fused_apply_grid(p->n), cur, s);
+        cur ^= 1;
         return cur;
     }
     hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(), p->fmt1[vk],
@@ -710,26 +731,11 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
     if (timed) hip_check(hipEventRecord(e[1], s), "event");
     if (p->dvc.n > 0) p->enqueue_dvc(vk, p->part_pass.as<double>(), p->cfg1[vk].grid, cur, 0, s);
     if (timed) hip_check(hipEventRecord(e[2], s), "event");
-    const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
     hip_check(pass2_any(p, vk, p->cfg2[vk], p->c.as<float>(), p->x.as<float>(), p->col_step(extrap), p->state(cur),
                         p->state(cur ^ 1), p->part_pass.as<double>(), p->cfg1[vk].grid, p->hist, s),
               "pass 2");
     if (timed) hip_check(hipEventRecord(e[3], s), "event");
-    if (extrap) {
-        const bool emr = p->basic == SMX_BASIC_EMR;
-        if (emr) // the quadratic form sum_i w_i (A y)_i^2: pass 1's kernels gathering y
-            hip_check(launch_pass1(p->cfg1[vk], view_for(p->op, false, p->fmt1[vk]), p->op->csr.blocks(),
-                                   p->fmt1[vk], p->ybuf32.as<float>(), p->lower.as<float>(), p->upper.as<float>(),
-                                   RowW{rw.D, rw.S, 1}, p->c.as<float>(), p->state(cur), p->B, 0,
-                                   p->part_q.as<double>(), s),
-                      "quadratic form");
-        hip_check(launch_step_apply(p->n, p->B, p->ybuf.as<double>(), p->x.as<float>(), p->box_lo.as<float>(),
-                                    p->box_hi.as<float>(), p->lambda, emr ? 1 : 0, p->part_pass.as<double>(),
-                                    p->cfg1[vk].grid, p->part_y.as<double>(), p->cfg2[vk].grid,
-                                    p->part_q.as<double>(), p->cfg1[vk].grid, p->state(cur), p->state(cur ^ 1),
-                                    p->hist, s),
-                  "extrapolated step");
-    }
+    if (extrap) enqueue_extrapolated_step(p, vk, rw, p->cfg1[vk].grid, p->cfg2[vk].grid, cur, s);
     cur ^= 1;
     return cur;
 }
@@ -870,9 +876,9 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
 // workgroups per CU, as many as the LDS allows.
 void setup_fused(smx_problem *p)
 {
-    // the extrapolated steps need ||y|| (and EMR A y) before x moves, and the
-    // dose-volume rows their ranking before c: two passes
-    if (p->B != 1 || p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR || p->dvc.n > 0) return;
+    // the dose-volume rows need their ranking before c: two passes (the
+    // extrapolated steps use the fused pass with a deferred apply)
+    if (p->B != 1 || p->dvc.n > 0) return;
     const size_t lim = fused_lds_limit();
     int acc64 = -1;
     if (fused_lds_bytes(p->n, 1) <= lim) acc64 = 1;

@@ -1060,6 +1060,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__
     __shared__ double red[kBlock / 64][64];
     __shared__ double lds[4];
     const int wid = threadIdx.x >> 6, wl = threadIdx.x & 63;
+    double ysq = 0.0; // deferred mode: this thread's share of ||y||^2
     if (st_in[0].live) {
         for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
             const int j = j0 + wl;
@@ -1082,14 +1083,26 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__
                 double yv = 0.0;
 #pragma unroll
                 for (int w = 0; w < W; ++w) yv += red[w][wl];
-                if (cs.zcol) yv *= (double)cs.zcol[j];
-                const double z = fma((double)cs.lambda, yv, (double)x[j]);
-                x[j] = (float)fmin(fmax(z, (double)cs.lo[j]), (double)cs.hi[j]);
+                if (cs.defer) { // the extrapolated steps: keep y, x moves in k_step_apply
+                    cs.ybuf[j] = yv;
+                    if (cs.ybuf32) cs.ybuf32[j] = (float)yv;
+                    ysq += yv * yv;
+                } else {
+                    if (cs.zcol) yv *= (double)cs.zcol[j];
+                    const double z = fma((double)cs.lambda, yv, (double)x[j]);
+                    x[j] = (float)fmin(fmax(z, (double)cs.lo[j]), (double)cs.hi[j]);
+                }
             }
             __syncthreads();
         }
     }
-    if (blockIdx.x == 0) finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+    if (cs.defer) {
+        double v[1] = {ysq};
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) cs.ypart[blockIdx.x] = v[0];
+    } else if (blockIdx.x == 0) {
+        finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+    }
 }
 
 // Extrapolated steps (one launch after pass 2, or after the quadratic-form
@@ -2320,6 +2333,8 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
 
 size_t fused_lds_bytes(int64_t n, int acc64) { return size_t(n) * (acc64 ? sizeof(double) : sizeof(float)); }
 
+int fused_apply_grid(int64_t n) { return (int)grid_for(n, 64, 4096); }
+
 size_t fused_lds_limit()
 {
     int dev = 0, v = 0;
@@ -2428,8 +2443,8 @@ hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
                               hipStream_t s)
 {
-    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1 || cs.defer) return hipErrorInvalidValue;
-    const unsigned grid = grid_for(n, 64, 4096);
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)fused_apply_grid(n);
     if (cfg.acc64)
         hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kBlock), 0, s, static_cast<const double *>(ypart),
                            cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);

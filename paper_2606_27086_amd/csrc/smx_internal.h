@@ -263,7 +263,12 @@ size_t fused_lds_bytes(int64_t n, int acc64);
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
                         const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
                         hipStream_t s);
-// x = clip(z + lambda * sum of the partial vectors, lo, hi); closes the iteration
+// workgroups of the fused pass's apply kernel (its ||y||^2 partials in deferred mode)
+int fused_apply_grid(int64_t n);
+// x = clip(z + lambda * sum of the partial vectors, lo, hi), closing the
+// iteration; in deferred mode (cs.defer) y itself into cs.ybuf (and ybuf32)
+// with fused_apply_grid(n) partials of ||y||^2 in cs.ypart (the extrapolated
+// steps then apply x in k_step_apply)
 hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
                               hipStream_t s);

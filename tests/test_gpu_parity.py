@@ -609,18 +609,14 @@ def test_basic_algorithm_parity(smx, method, case):
         w = W.ct(N=32, n_angles=24, seed=72, K=15)
     w = _with_basic(w, method)
     info = _fused_info(smx, w)
-    if method in ("el", "emr"):
-        assert info is None
-    else:
-        assert info is not None and info["in_use"]
+    assert info is not None and info["in_use"]
     # the extrapolated steps multiply y by sigma >> 1 on inconsistent sets (the
     # paper notes EL's fluctuation there), amplifying float32 rounding: they take
     # the conditioning-aware tolerance, and their per-iteration check is the
     # lockstep test below
     sens = w.obj == W.OBJ_TV2D or method in ("el", "emr")
     check_parity(smx, w, w.K, sensitive=sens)
-    if method in ("drop", "cq"):
-        check_parity(smx, w, w.K, sensitive=sens, fused=False)
+    check_parity(smx, w, w.K, sensitive=sens, fused=False)
 
 
 @pytest.mark.parametrize("method", ["el", "emr"])
