@@ -357,25 +357,24 @@ __device__ inline double row_dot_chunked(const SpView &A, int beg, int end, int 
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int p = beg + lane * VEC;
     constexpr int STEP = LPR * VEC;
-    // four independent loads in flight per lane
-    for (; p + 3 * STEP < end; p += 4 * STEP) {
+    // four independent loads in flight per lane; the row's last chunks (fewer
+    // than four) are issued together as well, each under its own predicate,
+    // so a row costs one load-then-gather round trip per four chunks
+    for (; p < end; p += 4 * STEP) {
         float v[4][VEC];
         int c[4][VEC];
+        bool ok[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
+            ok[u] = p + u * STEP < end;
+            if (ok[u]) Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
+            if (ok[u]) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[u] = fma((double)v[u][e], (double)x[c[u][e]], acc[u]);
-    }
-    for (; p < end; p += STEP) {
-        float v0[VEC];
-        int c0[VEC];
-        Entries<VT, VEC>::load(A, p, v0, c0);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[0] = fma((double)v0[e], (double)x[c0[e]], acc[0]);
+                for (int e = 0; e < VEC; ++e) acc[u] = fma((double)v[u][e], (double)x[c[u][e]], acc[u]);
+            }
     }
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
