@@ -157,15 +157,34 @@ def summarise(w, r, storage, B=1):
             f"{k2}_gbs": round(c2 / (r["pass2_ms"] * 1e-3) / 1e9, 1), "launch": r["shapes"]}
 
 
+CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
+
+
+def gathers_of(w, shapes, dpass, tiles):
+    """Global gathers (one address each) a launch of the dominant kernel makes:
+    one per nonzero for the row passes and the fused pass, one per (tile, row)
+    pair for the image-tile pass 2."""
+    shape = shapes[f"pass{dpass}"]
+    if dpass == 2 and shape["mode"] == "tiles" and not fused_in_use(shapes):
+        return tiles["rows"]
+    return w.nnz
+
+
 def roofline_of(w, r, storage, B=1, workload=None):
+    """The dominant kernel against the HBM peak; beside it, the address floor:
+    the gathers of a launch at one address per CU per clock (the rate the
+    counters show the L1 address path sustaining on gathers), and the launch's
+    fraction of that floor."""
     b1, b2 = alg_bytes(w.m, w.n, w.nnz, r["shapes"], B, r.get("tiles"))
     t1, t2 = r["pass1_ms"], r["pass2_ms"]
     dpass, dbytes, dms = (1, b1, t1) if t1 >= t2 else (2, b2, t2)
     achieved = dbytes / (dms * 1e-3) / 1e9
     kname = kernel_name(dpass, r["shapes"][f"pass{dpass}"], B, shapes=r["shapes"])
+    floor_us = gathers_of(w, r["shapes"], dpass, r.get("tiles")) / (CUS * CLOCK_HZ) * 1e6
     return dict(bound="hbm", kernel=kname, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname, workload), algorithmic_bytes=int(dbytes),
-                step_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1))
+                step_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1),
+                address_floor_us=round(floor_us, 2), address_frac=round(floor_us / (dms * 1e3), 3))
 
 
 def cpu_baseline(w, K):
