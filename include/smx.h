@@ -354,7 +354,9 @@ int smx_slot_get_x(smx_problem *p, int32_t slot, float *out, int32_t on_device);
  * entries per load, at several grid sizes) on this problem's operator, `reps`
  * launches each, and keeps the fastest for later runs.  Runs on scratch
  * copies, so the iterate, state and history are unchanged.  Synchronises.
- * Results do not depend on the shape beyond float64 summation order. */
+ * Results do not depend on the shape beyond float64 summation order.  With
+ * the environment variable SMX_TUNE_LOG=1 each candidate's mean time is
+ * printed to stderr. */
 int smx_autotune(smx_problem *p, int32_t reps);
 
 /* Fused single pass for one-slice problems (B = 1).  The two passes of a

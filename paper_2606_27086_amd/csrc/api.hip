@@ -1225,6 +1225,8 @@ int autotune_impl(smx_problem *p, int reps)
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
+    const char *log_env = getenv("SMX_TUNE_LOG"); // "1" prints every candidate's time to stderr
+    const bool tune_log = log_env && std::strcmp(log_env, "1") == 0;
     auto elapsed = [&]() {
         float ms = 0.f;
         hip_check(hipEventSynchronize(e1), "tuning sync");
@@ -1270,6 +1272,9 @@ int autotune_impl(smx_problem *p, int reps)
                 for (int r = 0; r < reps; ++r) launch();
                 hip_check(hipEventRecord(e1, s), "event");
                 const double t = elapsed();
+                if (tune_log)
+                    fprintf(stderr, "smx tune: kind %d mode %d lpr %d vec %d grid %d: %.2f us\n", vk, c.mode, c.lpr, c.vec,
+                            c.grid, t * 1e3);
                 if (t < best) {
                     best = t;
                     bestc = c;
@@ -1306,6 +1311,9 @@ int autotune_impl(smx_problem *p, int reps)
                 for (int r = 0; r < reps; ++r) launch();
                 hip_check(hipEventRecord(e1, s), "event");
                 const double t = elapsed();
+                if (tune_log)
+                    fprintf(stderr, "smx tune: kind %d mode %d lpr %d vec %d grid %d: %.2f us\n", vk, c.mode, c.lpr, c.vec,
+                            c.grid, t * 1e3);
                 if (t < best) {
                     best = t;
                     bestc2 = c;
@@ -1332,6 +1340,9 @@ int autotune_impl(smx_problem *p, int reps)
                     for (int r = 0; r < reps; ++r) launch();
                     hip_check(hipEventRecord(e1, s), "event");
                     const double t = elapsed();
+                    if (tune_log)
+                        fprintf(stderr, "smx tune: kind %d fused lpr %d vec %d cap %d grid %d: %.2f us\n", vk, c.lpr, c.vec,
+                                c.cap, c.grid, t * 1e3);
                     if (t < bestf) {
                         bestf = t;
                         bestfc = c;
