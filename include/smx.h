@@ -225,7 +225,8 @@ const char *smx_last_error(void);
  * also held packed: each entry one 32-bit word, value in the low half and
  * index in the high half; the passes read that copy, 4 bytes per entry.
  * The caller may free its buffers on return.
- * Errors: SMX_EINVAL for m or n < 1, nnz != row_ptr[m], a decreasing row_ptr,
+ * Errors: SMX_EINVAL for m or n < 1, no nonzeros at all (nnz = 0: every band
+ * would be the constant 0), nnz != row_ptr[m], a decreasing row_ptr,
  * a column index outside [0,n), a non-finite value, or sizes beyond 2^31-1
  * entries; SMX_ENOMEM when device memory runs out (nothing is leaked).
  */

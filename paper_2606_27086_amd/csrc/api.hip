@@ -534,6 +534,7 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
         return fail(SMX_EINVAL, "dimensions exceed 2^31-1");
     if (storage < SMX_STORE_F32 || storage > SMX_STORE_F16) return fail(SMX_EINVAL, "unknown value storage %d", storage);
     if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) return fail(SMX_EINVAL, "NULL CSR array");
+    if (A->nnz == 0) return fail(SMX_EINVAL, "the operator has no nonzeros");
     std::unique_ptr<smx_operator> op(new smx_operator());
     op->m = A->m;
     op->n = A->n;

@@ -66,6 +66,7 @@ def _csr_call(smx, m, n, rp, ci, val, storage=0):
     "case",
     [
         ("m0", 0, 3, [0], [], []),
+        ("no_nonzeros", 2, 3, [0, 0, 0], [], []),
         ("nnz_mismatch", 2, 3, [0, 1, 3], [0, 1], [1.0, 2.0]),
         ("decreasing", 2, 3, [0, 2, 1], [0, 1], [1.0, 2.0]),
         ("col_range", 2, 3, [0, 1, 2], [0, 3], [1.0, 2.0]),
