@@ -61,7 +61,8 @@ def alg_bytes(m, n, nnz, shapes, B=1, tiles=None):
     the gather of z, y once) and its apply kernel (z, the box, x, and the
     per-workgroup partial vectors it has to sum).  Pass 2 over image tiles
     (tiles = the describe record: count, rows = the tiles' row lists' total
-    length): A once, the tile tables, and c read once per (tile, row) pair."""
+    length): A once, the tile tables, and c (B values) read once per (tile,
+    row) pair."""
     e1 = ENTRY_BYTES[shapes["pass1"]["format"]]
     if fused_in_use(shapes):
         f = shapes["fused"]
@@ -74,7 +75,7 @@ def alg_bytes(m, n, nnz, shapes, B=1, tiles=None):
     p1 = nnz * e1 + 4 * (m + 1) + 4 * m + B * (8 * m + 4 * m + 4 * n)
     if shapes["pass2"]["mode"] == "tiles":
         R, T = tiles["rows"], tiles["count"]
-        p2 = nnz * e2 + 4 * (n + 1) + 4 * n + 8 * (T + 1) + 8 * R + 8 * n + 8 * n
+        p2 = nnz * e2 + 4 * (n + 1) + 4 * n + 8 * (T + 1) + 4 * R + 4 * B * R + 8 * B * n + 8 * n
     else:
         p2 = nnz * e2 + 4 * (n + 1) + 8 * n + B * (4 * m + 8 * n)
     return p1, p2
@@ -91,6 +92,8 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
         return f"smx::k_fused_apply<{acc}>"
     vt = VALUE_TAG[shape["format"]]
     if shape["mode"] == "tiles":
+        if B > 1:
+            return f"smx::k_pass2_tile_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
         return f"smx::k_pass2_tile<{shape['lpr']}, {shape['vec']}, {vt}>"
     if B > 1:
         return f"smx::k_pass{pass_no}_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"

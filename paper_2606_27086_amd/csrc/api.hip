@@ -254,7 +254,7 @@ struct smx_problem {
     DBuf ybuf;     // EL / EMR: y = A^T c kept for the extrapolated step, float64 [n*B]
     DBuf ybuf32;   // EMR: y rounded to float32, the vector its second product gathers [n*B]
     DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
-    bool tiles_ok = false; // pass 2 may use the operator's image-tile layout (one slice)
+    bool tiles_ok = false; // pass 2 may use the operator's image-tile layout (a tile's rows x B fit in LDS)
     bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
     DBuf xprev, part_var;
     // dose-volume constraints: their rows' values, keys, per-constraint
@@ -643,7 +643,8 @@ hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float
     if (c.mode == 2) {
         const int lp = p->op->lp_kind();
         const int tk = vk == VK_F32 ? VK_F32 : (lp == VK_BF16 ? VK_BF16P : VK_F16P);
-        return launch_pass2_tiles(c, p->op->tile_view(tk), tk, cres, x, cs, st_in, st_out, part1, nparts1, h, s);
+        return launch_pass2_tiles(c, p->op->tile_view(tk), tk, cres, x, cs, st_in, st_out, p->B, part1, nparts1, h,
+                                  s);
     }
     return launch_pass2(c, view_for(p->op, true, p->fmt2[vk]), p->op->csc.blocks(), p->fmt2[vk], cres, x, cs, st_in,
                         st_out, p->B, part1, nparts1, h, s);
@@ -1107,8 +1108,14 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     const char *mode_env = getenv("SMX_PASS_MODE");
     const bool rows_mode = mode_env && std::strcmp(mode_env, "rows") == 0;
     const bool inter_mode = mode_env && std::strcmp(mode_env, "interleaved") == 0;
-    const char *tiles_env = getenv("SMX_TILES"); // "0" keeps the column copy for pass 2
-    const bool use_tiles = op->has_tiles() && B == 1 && !(tiles_env && std::strcmp(tiles_env, "0") == 0);
+    // SMX_TILES: "0" keeps the column copy for pass 2; "1" starts every problem
+    // whose tiles fit on the tile pass; unset, one-slice problems start there and
+    // the autotuner may move any problem whose tiles fit there
+    const char *tiles_env = getenv("SMX_TILES");
+    const bool tiles_off = tiles_env && std::strcmp(tiles_env, "0") == 0;
+    const bool tiles_on = tiles_env && std::strcmp(tiles_env, "1") == 0;
+    const bool use_tiles = op->has_tiles() && tiles_fit(op->t_max_rows, B) && !tiles_off;
+    const bool start_tiles = use_tiles && (B == 1 || tiles_on);
     if (B == 1 && op->has_f32) { // one slice: the float32 passes read 16-bit indices where the range allows
         if (op->csr.idx16.p) p->fmt1[VK_F32] = VK_F32U16;
         if (op->csc.idx16.p) p->fmt2[VK_F32] = VK_F32U16;
@@ -1123,7 +1130,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
             p->cfg1[vk].vec = 1;
             p->cfg1[vk].grid = (int)std::min<int64_t>(std::max<int64_t>(1, (m + 15) / 16), kMaxPassGrid);
         }
-        if (use_tiles) {
+        if (start_tiles) {
             p->cfg2[vk].mode = 2;
             p->cfg2[vk].lpr = 4;
             p->cfg2[vk].vec = 4;

@@ -13,6 +13,7 @@
 // a one-workgroup kernel launched next sums the partials in workgroup order and
 // updates the per-slice state (acceptance of trial steps included).  No kernel
 // waits on, or signals, another workgroup of its own grid.
+#include <type_traits>
 #include "smx_internal.h"
 
 #include <hip/hip_bf16.h>
@@ -762,6 +763,35 @@ __global__ __launch_bounds__(kBlock) void k_pass2_stream(SpView At, RowBlocks RB
     end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
 }
 
+// Copies a tile's nr rows of c (B floats each, slice-interleaved as in
+// memory) into LDS.  Rows are moved as float4 where B allows, and each thread
+// issues U loads before its first LDS store, so that a tile's staging costs a
+// few memory round trips rather than one per row a thread copies.
+template <int B>
+__device__ inline void stage_rows(float *__restrict__ cl, const float *__restrict__ c, const int *__restrict__ rlist,
+                                  int nr)
+{
+    constexpr bool V4 = B % 4 == 0;
+    constexpr int PER = V4 ? B / 4 : B; // loads per row
+    constexpr int U = V4 ? 4 : 8;
+    using V = typename std::conditional<V4, float4, float>::type;
+    const int units = nr * PER;
+    V *dst = reinterpret_cast<V *>(cl);
+    for (int e0 = threadIdx.x; e0 < units; e0 += kBlock * U) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * kBlock;
+            if (e < units) v[u] = reinterpret_cast<const V *>(c + (long long)rlist[e / PER] * B)[e % PER];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * kBlock;
+            if (e < units) dst[e] = v[u];
+        }
+    }
+}
+
 // Pass 2 over the image-tile column layout: a workgroup takes one tile at a
 // time, copies the tile's rows of c into LDS (one gather per row instead of
 // one per entry: a ray crosses several pixels of a tile), then sums each
@@ -783,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2_tile(TileView T, const float *
         for (int t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
             const int r0 = T.rptr[t], nr = T.rptr[t + 1] - r0;
             __syncthreads(); // the previous tile's readers are done with cl
-            for (int i = threadIdx.x; i < nr; i += kBlock) cl[i] = c[T.rlist[r0 + i]];
+            stage_rows<1>(cl, c, T.rlist + r0, nr);
             __syncthreads();
             const int p0 = T.pptr[t], np = T.pptr[t + 1] - p0;
             for (int q = grp; q < np; q += RPB) {
@@ -1266,6 +1296,67 @@ __global__ __launch_bounds__(kBlock) void k_pass2_mm(SpView At, const float *__r
             for (int s = 0; s < B; ++s) {
                 if (!live[s]) continue;
                 yacc[s] += epi2(cs, col, col * B + s, acc[s] * (double)At.vscale_inv, x[col * B + s], l, u, x);
+            }
+        }
+    }
+    if (cs.defer) {
+        block_sum<B>(yacc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int s = 0; s < B; ++s) cs.ypart[(long long)s * gridDim.x + blockIdx.x] = yacc[s];
+        }
+    } else if (blockIdx.x == 0) {
+        finish_iteration(st_in, st_out, B, part1, nparts1, h, lds);
+    }
+}
+
+// Pass 2 over the image-tile column layout for B slices: the tile's rows of
+// c (B values each, slice-interleaved as in memory) are staged in LDS, and
+// every entry of a column reads its B values from there, as k_pass2_tile does
+// for one slice.  Each slice's sums follow the same order as in k_pass2_tile.
+template <int LPR, int VEC, typename VT, int B>
+__global__ __launch_bounds__(kBlock) void k_pass2_tile_mm(TileView T, const float *__restrict__ c,
+                                                          float *__restrict__ x, ColStep cs,
+                                                          const SliceState *__restrict__ st_in,
+                                                          SliceState *__restrict__ st_out,
+                                                          const double *__restrict__ part1, int nparts1, Hist h)
+{
+    extern __shared__ float4 cl4[]; // 16-byte aligned: rows of B floats
+    float *cl = reinterpret_cast<float *>(cl4);
+    __shared__ double lds[4 * B];
+    __shared__ int live[B];
+    constexpr int RPB = kBlock / LPR;
+    if (threadIdx.x < B) live[threadIdx.x] = st_in[threadIdx.x].live;
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int s = 0; s < B; ++s) any = any || live[s];
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    double yacc[B];
+#pragma unroll
+    for (int s = 0; s < B; ++s) yacc[s] = 0.0;
+    if (any) {
+        for (int t = blockIdx.x; t < T.ntiles; t += gridDim.x) {
+            const int r0 = T.rptr[t], nr = T.rptr[t + 1] - r0;
+            __syncthreads(); // the previous tile's readers are done with cl
+            stage_rows<B>(cl, c, T.rlist + r0, nr);
+            __syncthreads();
+            const int p0 = T.pptr[t], np = T.pptr[t + 1] - p0;
+            for (int q = grp; q < np; q += RPB) {
+                const int col = T.tcol[p0 + q];
+                const int beg = T.A.ptr[p0 + q], end = T.A.ptr[p0 + q + 1];
+                double acc[B];
+                row_dot_mm<LPR, VEC, VT, B>(T.A, beg, end, lane, cl, acc);
+                if (lane == 0) {
+                    const float l = cs.lo[col], u = cs.hi[col];
+#pragma unroll
+                    for (int s = 0; s < B; ++s) {
+                        if (!live[s]) continue;
+                        yacc[s] += epi2(cs, col, (long long)col * B + s, acc[s] * (double)T.A.vscale_inv,
+                                        x[(long long)col * B + s], l, u, x);
+                    }
+                }
             }
         }
     }
@@ -2250,6 +2341,40 @@ static hipError_t pass2_mm_b(const PassCfg &cfg, const SpView &At, const float *
     }
 }
 
+template <typename VT, int VEC, int B>
+static hipError_t pass2_tiles_mm(const PassCfg &cfg, const TileView &T, const float *c, float *x, ColStep cs,
+                                 const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1,
+                                 Hist h, hipStream_t s)
+{
+    const dim3 grid(cfg.grid), block(kBlock);
+    const size_t shm = sizeof(float) * B * size_t(T.max_rows > 0 ? T.max_rows : 1);
+#define SMX_P2TM(L) hipLaunchKernelGGL((k_pass2_tile_mm<L, VEC, VT, B>), grid, block, shm, s, T, c, x, cs, st_in, st_out, part1, nparts1, h)
+    switch (cfg.lpr) {
+    case 2: SMX_P2TM(2); break;
+    case 4: SMX_P2TM(4); break;
+    case 8: SMX_P2TM(8); break;
+    case 16: SMX_P2TM(16); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_P2TM
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t pass2_tiles_b(const PassCfg &cfg, const TileView &T, const float *c, float *x, ColStep cs,
+                                const SliceState *st_in, SliceState *st_out, int B, const double *part1,
+                                int nparts1, Hist h, hipStream_t s)
+{
+    switch (B) {
+    case 2: return pass2_tiles_mm<VT, VEC, 2>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 4: return pass2_tiles_mm<VT, VEC, 4>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 8: return pass2_tiles_mm<VT, VEC, 8>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 16: return pass2_tiles_mm<VT, VEC, 16>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    case 32: return pass2_tiles_mm<VT, VEC, 32>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename VT, int VEC>
 hipError_t pass2_tiles(const PassCfg &cfg, const TileView &T, const float *c, float *x, ColStep cs,
                        const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
@@ -2270,12 +2395,21 @@ hipError_t pass2_tiles(const PassCfg &cfg, const TileView &T, const float *c, fl
 }
 
 hipError_t launch_pass2_tiles(const PassCfg &cfg, const TileView &T, int vk, const float *c, float *x, ColStep cs,
-                              const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
-                              hipStream_t s)
+                              const SliceState *st_in, SliceState *st_out, int B, const double *part1, int nparts1,
+                              Hist h, hipStream_t s)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
-    if (T.ntiles < 1 || T.max_rows < 0 || size_t(T.max_rows) * sizeof(float) > 65536) return hipErrorInvalidValue;
+    if (B < 1 || T.ntiles < 1 || T.max_rows < 0 || !tiles_fit(T.max_rows, B)) return hipErrorInvalidValue;
     const bool v8 = cfg.vec == 8;
+    if (B > 1) {
+        if (vk == VK_F32) return v8 ? pass2_tiles_b<F32U16Tag, 8>(cfg, T, c, x, cs, st_in, st_out, B, part1, nparts1, h, s)
+                                    : pass2_tiles_b<F32U16Tag, 4>(cfg, T, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_BF16P) return v8 ? pass2_tiles_b<Bf16PTag, 8>(cfg, T, c, x, cs, st_in, st_out, B, part1, nparts1, h, s)
+                                      : pass2_tiles_b<Bf16PTag, 4>(cfg, T, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        if (vk == VK_F16P) return v8 ? pass2_tiles_b<F16PTag, 8>(cfg, T, c, x, cs, st_in, st_out, B, part1, nparts1, h, s)
+                                     : pass2_tiles_b<F16PTag, 4>(cfg, T, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);
+        return hipErrorInvalidValue;
+    }
     if (vk == VK_F32) return v8 ? pass2_tiles<F32U16Tag, 8>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s)
                                 : pass2_tiles<F32U16Tag, 4>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s);
     if (vk == VK_BF16P) return v8 ? pass2_tiles<Bf16PTag, 8>(cfg, T, c, x, cs, st_in, st_out, part1, nparts1, h, s)

@@ -243,11 +243,14 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,
                         ColStep cs, const SliceState *st_in, SliceState *st_out, int B, const double *part1,
                         int nparts1, Hist h, hipStream_t s);
-// pass 2 over the image-tile column layout (one slice): per tile, the rows of
-// c it needs staged in LDS, then y_j and the column step for its pixels
+// pass 2 over the image-tile column layout: per tile, the rows of c it needs
+// (B values each) staged in LDS, then y_j and the column step for its pixels
 hipError_t launch_pass2_tiles(const PassCfg &cfg, const TileView &T, int vk, const float *c, float *x, ColStep cs,
-                              const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
-                              hipStream_t s);
+                              const SliceState *st_in, SliceState *st_out, int B, const double *part1, int nparts1,
+                              Hist h, hipStream_t s);
+// whether a tile's staged rows of c (B floats each) fit the 64 KB of LDS the
+// tile passes use
+inline bool tiles_fit(int max_rows, int B) { return int64_t(max_rows) * B * 4 <= 65536; }
 // x = clip(z + lambda * sigma_s * y, lo, hi) for the extrapolated steps, sigma_s
 // per slice from the partials: EL (emr = 0) t^T D t / ||y||^2 from pass 1's
 // and pass 2's partials, EMR (emr = 1) ||y||^2 / sum w (A y)^2 from pass 2's and

@@ -38,6 +38,43 @@ def test_batched_random_sparse(smx, obj):
     check_parity(smx, w, w.K, perturb=obj != W.OBJ_NONE)
 
 
+@pytest.mark.parametrize("storage,B", [("f32", 2), ("f32", 4), ("bf16", 4), ("f32", 8)])
+def test_batched_image_tiles(smx, storage, B, monkeypatch):
+    """Several slices of an image operator take pass 2 over the tile layout (a
+    44 x 44 image: ragged edge tiles); each slice matches the oracle, and the
+    column copy's pass to float32 rounding with the same trial decisions."""
+    w = W.ct(N=44, n_angles=30, seed=38, B=B, K=20)
+    monkeypatch.setenv("SMX_TILES", "1")
+    p = smx.problem_from_workload(w, storage=storage)
+    d = p.describe()[storage]["pass2"]
+    p.close()
+    assert d["mode"] == "tiles" and d["format"].endswith("+u16"), d
+    vr = None if storage == "f32" else storage
+    xt, ht = check_parity(smx, w, w.K, storage=storage, value_round=vr, sensitive=True)
+    monkeypatch.setenv("SMX_TILES", "0")
+    p = smx.problem_from_workload(w, storage=storage)
+    assert p.describe()[storage]["pass2"]["mode"] != "tiles"
+    p.close()
+    xc, hc = check_parity(smx, w, w.K, storage=storage, value_round=vr, sensitive=True)
+    assert np.array_equal(ht["trials"], hc["trials"])
+    assert rel(xt, xc) < 1e-5
+
+
+def test_batched_tiles_only_where_lds_holds_them(smx, monkeypatch):
+    """A tile's staged rows take B floats each: with 180 angles a tile of a
+    64 x 64 image is crossed by some 1,800 rays, which fit 64 KB of LDS for 8
+    slices but not for 32, where pass 2 keeps the column copy."""
+    monkeypatch.setenv("SMX_TILES", "1")
+    w8 = W.ct(N=64, n_angles=180, seed=39, B=8, K=5)
+    p = smx.problem_from_workload(w8)
+    assert p.describe()["f32"]["pass2"]["mode"] == "tiles"
+    p.close()
+    w32 = W.ct(N=64, n_angles=180, seed=39, B=32, K=5)
+    p = smx.problem_from_workload(w32)
+    assert p.describe()["f32"]["pass2"]["mode"] != "tiles"
+    p.close()
+
+
 def test_batched_bf16(smx):
     w = W.ct(N=32, n_angles=24, seed=36, B=4, K=20)
     check_parity(smx, w, w.K, storage="bf16", value_round="bf16", sensitive=True)

@@ -634,10 +634,17 @@ def test_extrapolated_steps_lockstep(smx, method, case):
     print(f"  worst per-iteration rel err {worst:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("tiles", [False, True])
 @pytest.mark.parametrize("method", ["el", "emr", "drop"])
-def test_basic_algorithm_batched(smx, method):
-    """Several slices (multi-slice kernels, per-slice sigma) against the oracle."""
+def test_basic_algorithm_batched(smx, method, tiles, monkeypatch):
+    """Several slices (multi-slice kernels, per-slice sigma) against the oracle;
+    with tiles, pass 2 (kept y for EL and EMR, column factors for DROP) runs
+    over the image-tile layout."""
+    monkeypatch.setenv("SMX_TILES", "1" if tiles else "0")
     w = _with_basic(W.ct(N=32, n_angles=24, seed=73, B=4, K=12), method)
+    p = smx.problem_from_workload(w)
+    assert (p.describe()["f32"]["pass2"]["mode"] == "tiles") == tiles
+    p.close()
     check_parity(smx, w, w.K, sensitive=True)
     if method == "drop":
         check_parity(smx, w, w.K, sensitive=True, fused=False)
