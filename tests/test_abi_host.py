@@ -3,7 +3,9 @@ entry point include/smx.h declares, and rejects invalid host input before it
 touches the device."""
 import ctypes as C
 import os
+import sys
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -105,6 +107,25 @@ def test_binding_has_no_oracle_dependency():
     for f in os.listdir(os.path.join(ROOT, "paper_2606_27086_amd", "csrc")):
         text = open(os.path.join(ROOT, "paper_2606_27086_amd", "csrc", f)).read()
         assert "oracle" not in text and "liborc" not in text and "orc_" not in text
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding raises on first use: there is no
+    other path to the kernels."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2606_27086_amd as smx\n"
+        "smx.LIB_PATH = %r\n"
+        "try:\n"
+        "    smx.lib()\n"
+        "except ImportError as e:\n"
+        "    print('raised', e)\n"
+        "else:\n"
+        "    sys.exit(3)\n"
+    ) % (ROOT, str(tmp_path / "absent" / "libsmx.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "raised" in r.stdout and "libsmx.so not found" in r.stdout
 
 
 def test_struct_layouts_match_header(smx, tmp_path):
