@@ -91,6 +91,8 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
             return f"smx::k_fused<{f['lpr']}, {f['vec']}, {VALUE_TAG[f['format']]}, {acc}>"
         return f"smx::k_fused_apply<{acc}>"
     vt = VALUE_TAG[shape["format"]]
+    if shape["mode"] == "lds":
+        return f"smx::k_pass1_lds<{shape['lpr']}, {shape['vec']}, {vt}>"
     if shape["mode"] == "tiles":
         if B > 1:
             return f"smx::k_pass2_tile_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
@@ -166,10 +168,15 @@ CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 def gathers_of(w, shapes, dpass, tiles):
     """Global gathers (one address each) a launch of the dominant kernel makes:
     one per nonzero for the row passes and the fused pass, one per (tile, row)
-    pair for the image-tile pass 2."""
+    pair for the image-tile pass 2, and for the LDS-staged pass 1 one per
+    nonzero whose column lies beyond the staged part of the vector."""
     shape = shapes[f"pass{dpass}"]
     if dpass == 2 and shape["mode"] == "tiles" and not fused_in_use(shapes):
         return tiles["rows"]
+    if dpass == 1 and shape["mode"] == "lds" and not fused_in_use(shapes):
+        import numpy as np
+
+        return int(np.count_nonzero(w.col_idx >= shape["xlds"]))  # the rest are LDS reads
     return w.nnz
 
 

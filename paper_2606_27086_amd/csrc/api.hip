@@ -254,6 +254,8 @@ struct smx_problem {
     DBuf ybuf;     // EL / EMR: y = A^T c kept for the extrapolated step, float64 [n*B]
     DBuf ybuf32;   // EMR: y rounded to float32, the vector its second product gathers [n*B]
     DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
+    int lds_grid = 0; // one slice: workgroups of the LDS-staged pass 1 (one per CU), 0 when unavailable
+    int lds_x = 0;    // entries of the gathered vector it holds in LDS
     bool tiles_ok = false; // pass 2 may use the operator's image-tile layout (a tile's rows x B fit in LDS)
     bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
     DBuf xprev, part_var;
@@ -1149,6 +1151,24 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->dvc_part.alloc(sizeof(double) * size_t(dt.nblk) * B, "dose-volume partials");
     }
     setup_fused(p.get());
+    if (B == 1 && fused_lds_limit() >= sizeof(float) * size_t(kPass1LdsFloats)) { // the LDS-staged pass 1
+        int dev = 0, cus = 0;
+        hip_check(hipGetDevice(&dev), "device");
+        hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+        hip_check(prepare_pass1_lds(), "LDS pass setup");
+        p->lds_grid = std::max(1, std::min(cus, kMaxPassGrid));
+        p->lds_x = (int)std::min<int64_t>(n, kPass1LdsFloats);
+        const char *me = getenv("SMX_PASS_MODE"); // "lds" starts pass 1 there
+        if (me && std::strcmp(me, "lds") == 0)
+            for (int vk = 0; vk < 3; ++vk) {
+                PassCfg &c = p->cfg1[vk];
+                c.mode = 3;
+                c.lpr = 8;
+                c.vec = 4;
+                c.grid = p->lds_grid;
+                c.xlds = p->lds_x;
+            }
+    }
     // per-workgroup partial sums of each kernel kind
     const int64_t pgrid = phase_grid(pp);
     p->part_pass.alloc(sizeof(double) * size_t(kMaxPassGrid) * B, "pass partials");
@@ -1265,6 +1285,17 @@ int autotune_impl(smx_problem *p, int reps)
                         bool dup = false;
                         for (auto &o : cands1) dup = dup || (o.mode == 0 && o.lpr == lpr && o.vec == 1 && o.grid == c.grid);
                         if (!dup) cands1.push_back(c);
+                    }
+            if (p->lds_grid > 0)
+                for (int lpr : {4, 8, 16, 32})
+                    for (int vec : {4, 8}) {
+                        PassCfg c;
+                        c.mode = 3;
+                        c.lpr = lpr;
+                        c.vec = vec;
+                        c.grid = p->lds_grid;
+                        c.xlds = p->lds_x;
+                        cands1.push_back(c);
                     }
             for (const PassCfg &c : cands1) {
                 auto launch = [&]() {
@@ -1409,10 +1440,12 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
             snprintf(fz, sizeof fz, "null");
         }
         snprintf(tmp, sizeof tmp,
-                 "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
+                 "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\", "
+                 "\"xlds\": %d}, "
                  "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
                  "\"fused\": %s}",
-                 first ? "" : ", ", names[vk], a.mode ? "stream" : "rows", a.lpr, a.vec, a.grid, fmt_name(p->fmt1[vk]),
+                 first ? "" : ", ", names[vk], a.mode == 3 ? "lds" : (a.mode ? "stream" : "rows"), a.lpr, a.vec, a.grid,
+                 fmt_name(p->fmt1[vk]), a.mode == 3 ? a.xlds : 0,
                  b.mode == 2 ? "tiles" : (b.mode ? "stream" : "rows"), b.lpr, b.vec, b.grid,
                  b.mode == 2 ? (vk == VK_F32 ? "f32+u16" : (vk == VK_BF16 ? "bf16+u16" : "f16+u16"))
                              : fmt_name(p->fmt2[vk]),

@@ -453,6 +453,94 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
     if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
 }
 
+// Row dot product whose gathers read the vector's first P entries from an
+// LDS copy (xl) and the rest from memory; otherwise row_dot_chunked.
+template <int LPR, int VEC, typename VT>
+__device__ inline double row_dot_split(const SpView &A, int beg, int end, int lane, const float *__restrict__ x,
+                                       const float *xl, int P)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int p = beg + lane * VEC;
+    constexpr int STEP = LPR * VEC;
+    for (; p < end; p += 4 * STEP) {
+        float v[4][VEC];
+        int c[4][VEC];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ok[u] = p + u * STEP < end;
+            if (ok[u]) Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u]) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int ci = c[u][e];
+                    float xv;
+                    if (ci < P) xv = xl[ci];
+                    else xv = x[ci];
+                    acc[u] = fma((double)v[u][e], (double)xv, acc[u]);
+                }
+            }
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Pass 1 with the gathered vector partly in LDS.  A gather through the
+// vector memory path costs about one address per CU per clock, whatever its
+// locality; an LDS read serves many lanes per clock.  So each workgroup (one
+// per CU, 1024 threads) first copies x[0, P) into LDS, P = min(n, 40,448),
+// then runs the rows as k_pass1 does, gathering x_j from LDS when j < P.
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kPass1LdsBlock) void k_pass1_lds(SpView A, const float *__restrict__ x, int P,
+                                                              const float *__restrict__ lower,
+                                                              const float *__restrict__ upper, RowW w,
+                                                              float *__restrict__ c,
+                                                              const SliceState *__restrict__ st, int query,
+                                                              double *__restrict__ partials)
+{
+    extern __shared__ float4 xl4[];
+    float *xl = reinterpret_cast<float *>(xl4);
+    __shared__ double lds[kPass1LdsBlock / 64];
+    constexpr int RPB = kPass1LdsBlock / LPR;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const bool live = query ? true : st[0].live != 0; // the same in every thread
+    double pacc[1] = {0.0};
+    if (live) {
+        // x[0, P): float4 loads, four in flight per thread, then the tail
+        const int q4 = P >> 2;
+        const float4 *x4 = reinterpret_cast<const float4 *>(x);
+        for (int e0 = threadIdx.x; e0 < q4; e0 += 4 * kPass1LdsBlock) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = x4[min(e0 + u * kPass1LdsBlock, q4 - 1)]; // in bounds, unpredicated
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + u * kPass1LdsBlock < q4) xl4[e0 + u * kPass1LdsBlock] = v[u];
+        }
+        if (threadIdx.x < (P & 3)) xl[4 * q4 + threadIdx.x] = x[4 * q4 + threadIdx.x];
+        __syncthreads();
+        const long long stride = (long long)gridDim.x * RPB;
+        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
+            const int beg = A.ptr[row], end = A.ptr[row + 1];
+            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
+            if (lane == 0) {
+                lo = lower[row];
+                up = upper[row];
+                d = w.D[row];
+                sw = w.S[row];
+            }
+            const double r =
+                group_sum<LPR>(row_dot_split<LPR, VEC, VT>(A, beg, end, lane, x, xl, P)) * (double)A.vscale_inv;
+            if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
+        }
+    }
+    block_sum<1, kPass1LdsBlock>(pacc, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+}
+
 // ---------------------------------------------------------------------------
 // Streaming pass kernels.  A workgroup takes one row block (at most
 // kStreamEntries entries): every lane issues all of its value/index loads and
@@ -780,9 +868,9 @@ __device__ inline void stage_rows(float *__restrict__ cl, const float *__restric
     for (int e0 = threadIdx.x; e0 < units; e0 += kBlock * U) {
         V v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * kBlock;
-            if (e < units) v[u] = reinterpret_cast<const V *>(c + (long long)rlist[e / PER] * B)[e % PER];
+        for (int u = 0; u < U; ++u) { // every load in bounds (the last unit again past the end), none predicated
+            const int e = min(e0 + u * kBlock, units - 1);
+            v[u] = reinterpret_cast<const V *>(c + (long long)rlist[e / PER] * B)[e % PER];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -2228,11 +2316,90 @@ static hipError_t pass1_mm_b(const PassCfg &cfg, const SpView &A, const float *x
     }
 }
 
+template <typename VT, int VEC, int LPR>
+static hipError_t pass1_lds_go(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
+                               const float *upper, RowW w, float *c, const SliceState *st, int query,
+                               double *partials, int prepare, hipStream_t s)
+{
+    auto kern = k_pass1_lds<LPR, VEC, VT>;
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(sizeof(float) * kPass1LdsFloats));
+    const size_t shm = sizeof(float4) * size_t((cfg.xlds + 3) / 4);
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kPass1LdsBlock), shm, s, A, x, cfg.xlds, lower, upper, w, c, st,
+                       query, partials);
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t pass1_lds(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
+                            const float *upper, RowW w, float *c, const SliceState *st, int query, double *partials,
+                            int prepare, hipStream_t s)
+{
+    switch (cfg.lpr) {
+    case 4: return pass1_lds_go<VT, VEC, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case 8: return pass1_lds_go<VT, VEC, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case 16: return pass1_lds_go<VT, VEC, 16>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case 32: return pass1_lds_go<VT, VEC, 32>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename VT>
+static hipError_t pass1_lds_v(const PassCfg &cfg, const SpView &A, const float *x, const float *lower,
+                              const float *upper, RowW w, float *c, const SliceState *st, int query, double *partials,
+                              int prepare, hipStream_t s)
+{
+    if (cfg.vec == 8) return pass1_lds<VT, 8>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    if (cfg.vec == 4) return pass1_lds<VT, 4>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    return hipErrorInvalidValue;
+}
+
+static hipError_t pass1_lds_kind(const PassCfg &cfg, int vk, const SpView &A, const float *x, const float *lower,
+                                 const float *upper, RowW w, float *c, const SliceState *st, int query,
+                                 double *partials, int prepare, hipStream_t s)
+{
+    switch (vk) {
+    case VK_F32U16: return pass1_lds_v<F32U16Tag>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case VK_F32: return pass1_lds_v<float>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case VK_BF16: return pass1_lds_v<Bf16Tag>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case VK_BF16P: return pass1_lds_v<Bf16PTag>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case VK_F16: return pass1_lds_v<F16Tag>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    case VK_F16P: return pass1_lds_v<F16PTag>(cfg, A, x, lower, upper, w, c, st, query, partials, prepare, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t prepare_pass1_lds()
+{
+    static hipError_t done = hipErrorNotReady;
+    if (done == hipSuccess) return done;
+    const SpView none{};
+    for (int vk : {VK_F32U16, VK_F32, VK_BF16, VK_BF16P, VK_F16, VK_F16P})
+        for (int lpr : {4, 8, 16, 32})
+            for (int vec : {4, 8}) {
+                PassCfg c;
+                c.mode = 3;
+                c.lpr = lpr;
+                c.vec = vec;
+                c.grid = 1;
+                const hipError_t e = pass1_lds_kind(c, vk, none, nullptr, nullptr, nullptr, RowW{}, nullptr, nullptr,
+                                                    0, nullptr, 1, nullptr);
+                if (e != hipSuccess) return e;
+            }
+    done = hipSuccess;
+    return done;
+}
+
 hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
                         const float *lower, const float *upper, RowW w, float *c, const SliceState *st, int B,
                         int query, double *partials, hipStream_t s)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
+    if (cfg.mode == 3) {
+        if (B != 1 || cfg.xlds < 1 || cfg.xlds > kPass1LdsFloats) return hipErrorInvalidValue;
+        return pass1_lds_kind(cfg, vk, A, x, lower, upper, w, c, st, query, partials, 0, s);
+    }
     if (B > 1) {
         if (vk == VK_F32U16) return hipErrorInvalidValue;
         if (vk == VK_F32) return pass1_mm_b<float, 4>(cfg, A, x, lower, upper, w, c, st, B, query, partials, s);
