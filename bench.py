@@ -92,7 +92,7 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
         return f"smx::k_fused_apply<{acc}>"
     vt = VALUE_TAG[shape["format"]]
     if shape["mode"] == "lds":
-        return f"smx::k_pass1_lds<{shape['lpr']}, {shape['vec']}, {vt}>"
+        return f"smx::k_pass{pass_no}_lds<{shape['lpr']}, {shape['vec']}, {vt}>"
     if shape["mode"] == "tiles":
         if B > 1:
             return f"smx::k_pass2_tile_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"
@@ -168,8 +168,9 @@ CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 def gathers_of(w, shapes, dpass, tiles):
     """Global gathers (one address each) a launch of the dominant kernel makes:
     one per nonzero for the row passes and the fused pass, one per (tile, row)
-    pair for the image-tile pass 2, and for the LDS-staged pass 1 one per
-    nonzero whose column lies beyond the staged part of the vector."""
+    pair for the image-tile pass 2, and for the LDS-staged passes one per
+    nonzero whose column (pass 1) or row (pass 2) lies beyond the staged part
+    of the gathered vector."""
     shape = shapes[f"pass{dpass}"]
     if dpass == 2 and shape["mode"] == "tiles" and not fused_in_use(shapes):
         return tiles["rows"]
@@ -177,6 +178,8 @@ def gathers_of(w, shapes, dpass, tiles):
         import numpy as np
 
         return int(np.count_nonzero(w.col_idx >= shape["xlds"]))  # the rest are LDS reads
+    if dpass == 2 and shape["mode"] == "lds" and not fused_in_use(shapes):
+        return int(w.nnz - w.row_ptr[min(shape["xlds"], w.m)])  # entries of rows beyond the staged part of c
     return w.nnz
 
 

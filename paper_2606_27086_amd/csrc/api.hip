@@ -255,7 +255,8 @@ struct smx_problem {
     DBuf ybuf32;   // EMR: y rounded to float32, the vector its second product gathers [n*B]
     DBuf part_y, part_q; // EL / EMR: partials of ||y||^2 and of sum w (A y)^2
     int lds_grid = 0; // one slice: workgroups of the LDS-staged pass 1 (one per CU), 0 when unavailable
-    int lds_x = 0;    // entries of the gathered vector it holds in LDS
+    int lds_x = 0;    // entries of the gathered vector it holds in LDS (pass 1: x)
+    int lds_c = 0;    // the same for pass 2 (c)
     bool tiles_ok = false; // pass 2 may use the operator's image-tile layout (a tile's rows x B fit in LDS)
     bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
     DBuf xprev, part_var;
@@ -1151,23 +1152,25 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->dvc_part.alloc(sizeof(double) * size_t(dt.nblk) * B, "dose-volume partials");
     }
     setup_fused(p.get());
-    if (B == 1 && fused_lds_limit() >= sizeof(float) * size_t(kPass1LdsFloats)) { // the LDS-staged pass 1
+    if (B == 1 && fused_lds_limit() >= sizeof(float) * size_t(kLdsPassFloats)) { // the LDS-staged pass 1
         int dev = 0, cus = 0;
         hip_check(hipGetDevice(&dev), "device");
         hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
-        hip_check(prepare_pass1_lds(), "LDS pass setup");
+        hip_check(prepare_lds_passes(), "LDS pass setup");
         p->lds_grid = std::max(1, std::min(cus, kMaxPassGrid));
-        p->lds_x = (int)std::min<int64_t>(n, kPass1LdsFloats);
-        const char *me = getenv("SMX_PASS_MODE"); // "lds" starts pass 1 there
+        p->lds_x = (int)std::min<int64_t>(n, kLdsPassFloats);
+        p->lds_c = (int)std::min<int64_t>(m, kLdsPassFloats);
+        const char *me = getenv("SMX_PASS_MODE"); // "lds" starts both passes there
         if (me && std::strcmp(me, "lds") == 0)
-            for (int vk = 0; vk < 3; ++vk) {
-                PassCfg &c = p->cfg1[vk];
-                c.mode = 3;
-                c.lpr = 8;
-                c.vec = 4;
-                c.grid = p->lds_grid;
-                c.xlds = p->lds_x;
-            }
+            for (int vk = 0; vk < 3; ++vk)
+                for (int k = 0; k < 2; ++k) {
+                    PassCfg &c = k ? p->cfg2[vk] : p->cfg1[vk];
+                    c.mode = 3;
+                    c.lpr = 8;
+                    c.vec = 4;
+                    c.grid = p->lds_grid;
+                    c.xlds = k ? p->lds_c : p->lds_x;
+                }
     }
     // per-workgroup partial sums of each kernel kind
     const int64_t pgrid = phase_grid(pp);
@@ -1325,6 +1328,17 @@ int autotune_impl(smx_problem *p, int reps)
             best = 1e30;
             PassCfg bestc2 = p->cfg2[vk];
             std::vector<PassCfg> cands2 = pass_candidates(p->op->csc, vk, p->B);
+            if (p->lds_grid > 0)
+                for (int lpr : {4, 8, 16, 32})
+                    for (int vec : {4, 8}) {
+                        PassCfg c;
+                        c.mode = 3;
+                        c.lpr = lpr;
+                        c.vec = vec;
+                        c.grid = p->lds_grid;
+                        c.xlds = p->lds_c;
+                        cands2.push_back(c);
+                    }
             if (p->tiles_ok)
                 for (int lpr : {2, 4, 8, 16})
                     for (int vec : {4, 8})
@@ -1442,13 +1456,15 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         snprintf(tmp, sizeof tmp,
                  "%s\"%s\": {\"pass1\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\", "
                  "\"xlds\": %d}, "
-                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\"}, "
+                 "\"pass2\": {\"mode\": \"%s\", \"lpr\": %d, \"vec\": %d, \"grid\": %d, \"format\": \"%s\", "
+                 "\"xlds\": %d}, "
                  "\"fused\": %s}",
                  first ? "" : ", ", names[vk], a.mode == 3 ? "lds" : (a.mode ? "stream" : "rows"), a.lpr, a.vec, a.grid,
                  fmt_name(p->fmt1[vk]), a.mode == 3 ? a.xlds : 0,
-                 b.mode == 2 ? "tiles" : (b.mode ? "stream" : "rows"), b.lpr, b.vec, b.grid,
+                 b.mode == 2 ? "tiles" : (b.mode == 3 ? "lds" : (b.mode ? "stream" : "rows")), b.lpr, b.vec, b.grid,
                  b.mode == 2 ? (vk == VK_F32 ? "f32+u16" : (vk == VK_BF16 ? "bf16+u16" : "f16+u16"))
                              : fmt_name(p->fmt2[vk]),
+                 b.mode == 3 ? b.xlds : 0,
                  fz);
         out += tmp;
         first = false;

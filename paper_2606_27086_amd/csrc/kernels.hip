@@ -104,18 +104,19 @@ __device__ inline void block_sum(double (&v)[NV], double *lds)
 }
 
 // Totals over `count` consecutive slots starting at `first` (each slot NV
-// values), summed in slot order by one workgroup; valid in thread 0.
-template <int NV>
+// values), summed in slot order by one workgroup of BS threads; valid in
+// thread 0.
+template <int NV, int BS = kBlock>
 __device__ inline void sum_slots(const double *__restrict__ partials, long long first, int count, double (&tot)[NV],
                                  double *lds)
 {
 #pragma unroll
     for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    for (int b = threadIdx.x; b < count; b += kBlock) {
+    for (int b = threadIdx.x; b < count; b += BS) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) tot[k] += partials[(first + b) * NV + k];
     }
-    block_sum<NV>(tot, lds);
+    block_sum<NV, BS>(tot, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,6 +454,25 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
     if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
 }
 
+// Copies v[0, P) into LDS (dst, 16-byte aligned) with BS threads: float4
+// loads, four in flight per thread (every load in bounds: past the end the
+// last float4 is read again, and not stored), then the last P mod 4 values.
+template <int BS>
+__device__ inline void stage_vector(float4 *dst, const float *__restrict__ v, int P)
+{
+    const int q4 = P >> 2;
+    const float4 *v4 = reinterpret_cast<const float4 *>(v);
+    for (int e0 = threadIdx.x; e0 < q4; e0 += 4 * BS) {
+        float4 t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = v4[min(e0 + u * BS, q4 - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + u * BS < q4) dst[e0 + u * BS] = t[u];
+    }
+    if (threadIdx.x < (P & 3)) reinterpret_cast<float *>(dst)[4 * q4 + threadIdx.x] = v[4 * q4 + threadIdx.x];
+}
+
 // Row dot product whose gathers read the vector's first P entries from an
 // LDS copy (xl) and the rest from memory; otherwise row_dot_chunked.
 template <int LPR, int VEC, typename VT>
@@ -493,7 +513,7 @@ __device__ inline double row_dot_split(const SpView &A, int beg, int end, int la
 // per CU, 1024 threads) first copies x[0, P) into LDS, P = min(n, 40,448),
 // then runs the rows as k_pass1 does, gathering x_j from LDS when j < P.
 template <int LPR, int VEC, typename VT>
-__global__ __launch_bounds__(kPass1LdsBlock) void k_pass1_lds(SpView A, const float *__restrict__ x, int P,
+__global__ __launch_bounds__(kLdsPassBlock) void k_pass1_lds(SpView A, const float *__restrict__ x, int P,
                                                               const float *__restrict__ lower,
                                                               const float *__restrict__ upper, RowW w,
                                                               float *__restrict__ c,
@@ -502,25 +522,14 @@ __global__ __launch_bounds__(kPass1LdsBlock) void k_pass1_lds(SpView A, const fl
 {
     extern __shared__ float4 xl4[];
     float *xl = reinterpret_cast<float *>(xl4);
-    __shared__ double lds[kPass1LdsBlock / 64];
-    constexpr int RPB = kPass1LdsBlock / LPR;
+    __shared__ double lds[kLdsPassBlock / 64];
+    constexpr int RPB = kLdsPassBlock / LPR;
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
     const bool live = query ? true : st[0].live != 0; // the same in every thread
     double pacc[1] = {0.0};
     if (live) {
-        // x[0, P): float4 loads, four in flight per thread, then the tail
-        const int q4 = P >> 2;
-        const float4 *x4 = reinterpret_cast<const float4 *>(x);
-        for (int e0 = threadIdx.x; e0 < q4; e0 += 4 * kPass1LdsBlock) {
-            float4 v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = x4[min(e0 + u * kPass1LdsBlock, q4 - 1)]; // in bounds, unpredicated
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (e0 + u * kPass1LdsBlock < q4) xl4[e0 + u * kPass1LdsBlock] = v[u];
-        }
-        if (threadIdx.x < (P & 3)) xl[4 * q4 + threadIdx.x] = x[4 * q4 + threadIdx.x];
+        stage_vector<kLdsPassBlock>(xl4, x, P);
         __syncthreads();
         const long long stride = (long long)gridDim.x * RPB;
         for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
@@ -537,7 +546,7 @@ __global__ __launch_bounds__(kPass1LdsBlock) void k_pass1_lds(SpView A, const fl
             if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
         }
     }
-    block_sum<1, kPass1LdsBlock>(pacc, lds);
+    block_sum<1, kLdsPassBlock>(pacc, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
 }
 
@@ -706,13 +715,14 @@ __device__ inline void stop_rules_after_step(SliceState &S, double prox)
 
 // End of an outer iteration: proximity from pass 1's partials, the history
 // record, k + 1, and whether the next iteration runs.  Called by every thread
-// of one workgroup.
+// of one workgroup (BS threads; lds holds BS/64 doubles).
+template <int BS = kBlock>
 __device__ inline void finish_iteration(const SliceState *__restrict__ st_in, SliceState *__restrict__ st_out, int B,
                                         const double *__restrict__ part1, int nparts, const Hist &h, double *lds)
 {
     for (int s = 0; s < B; ++s) {
         double tot[1];
-        sum_slots<1>(part1, (long long)s * nparts, nparts, tot, lds);
+        sum_slots<1, BS>(part1, (long long)s * nparts, nparts, tot, lds);
         if (threadIdx.x == 0) {
             SliceState S = st_in[s];
             S.ran = S.live;
@@ -764,18 +774,19 @@ __device__ inline double epi2(const ColStep &cs, long long col, long long e, dou
     return 0.0;
 }
 
-// End of a pass-2 launch: the ||y||^2 partials (deferred mode), else workgroup
-// 0 closes the outer iteration.
+// End of a pass-2 launch (workgroups of BS threads): the ||y||^2 partials
+// (deferred mode), else workgroup 0 closes the outer iteration.
+template <int BS = kBlock>
 __device__ inline void end_pass2(const ColStep &cs, double yacc, const SliceState *__restrict__ st_in,
                                  SliceState *__restrict__ st_out, const double *__restrict__ part1, int nparts1,
                                  const Hist &h, double *lds)
 {
     if (cs.defer) {
         double v[1] = {yacc};
-        block_sum<1>(v, lds);
+        block_sum<1, BS>(v, lds);
         if (threadIdx.x == 0) cs.ypart[blockIdx.x] = v[0];
     } else if (blockIdx.x == 0) {
-        finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+        finish_iteration<BS>(st_in, st_out, 1, part1, nparts1, h, lds);
     }
 }
 
@@ -805,6 +816,43 @@ __global__ __launch_bounds__(kBlock) void k_pass2(SpView At, const float *__rest
         }
     }
     end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
+}
+
+// Pass 2 with the gathered residual partly in LDS, as k_pass1_lds: one
+// workgroup per CU copies c[0, P) into LDS, P = min(m, 40,448), then sums
+// each column as k_pass2 does, reading c_i from LDS when i < P.
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kLdsPassBlock) void k_pass2_lds(SpView At, const float *__restrict__ c, int P,
+                                                             float *__restrict__ x, ColStep cs,
+                                                             const SliceState *__restrict__ st_in,
+                                                             SliceState *__restrict__ st_out,
+                                                             const double *__restrict__ part1, int nparts1, Hist h)
+{
+    extern __shared__ float4 cl4[];
+    float *cl = reinterpret_cast<float *>(cl4);
+    __shared__ double lds[kLdsPassBlock / 64];
+    constexpr int RPB = kLdsPassBlock / LPR;
+    double yacc = 0.0;
+    if (st_in[0].live) { // the same in every thread
+        stage_vector<kLdsPassBlock>(cl4, c, P);
+        __syncthreads();
+        const int lane = threadIdx.x & (LPR - 1);
+        const int grp = threadIdx.x / LPR;
+        const long long stride = (long long)gridDim.x * RPB;
+        for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
+            const int beg = At.ptr[col], end = At.ptr[col + 1];
+            float xo = 0.f, l = 0.f, u = 0.f;
+            if (lane == 0 && !cs.defer) {
+                xo = x[col];
+                l = cs.lo[col];
+                u = cs.hi[col];
+            }
+            const double y =
+                group_sum<LPR>(row_dot_split<LPR, VEC, VT>(At, beg, end, lane, c, cl, P)) * (double)At.vscale_inv;
+            if (lane == 0) yacc += epi2(cs, col, col, y, xo, l, u, x);
+        }
+    }
+    end_pass2<kLdsPassBlock>(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
 }
 
 template <int VEC, typename VT>
@@ -2324,9 +2372,9 @@ static hipError_t pass1_lds_go(const PassCfg &cfg, const SpView &A, const float 
     auto kern = k_pass1_lds<LPR, VEC, VT>;
     if (prepare)
         return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(sizeof(float) * kPass1LdsFloats));
+                                   (int)(sizeof(float) * kLdsPassFloats));
     const size_t shm = sizeof(float4) * size_t((cfg.xlds + 3) / 4);
-    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kPass1LdsBlock), shm, s, A, x, cfg.xlds, lower, upper, w, c, st,
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kLdsPassBlock), shm, s, A, x, cfg.xlds, lower, upper, w, c, st,
                        query, partials);
     return hipGetLastError();
 }
@@ -2370,7 +2418,56 @@ static hipError_t pass1_lds_kind(const PassCfg &cfg, int vk, const SpView &A, co
     }
 }
 
-hipError_t prepare_pass1_lds()
+template <typename VT, int VEC, int LPR>
+static hipError_t pass2_lds_go(const PassCfg &cfg, const SpView &At, const float *c, float *x, ColStep cs,
+                               const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                               int prepare, hipStream_t s)
+{
+    auto kern = k_pass2_lds<LPR, VEC, VT>;
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(sizeof(float) * kLdsPassFloats));
+    const size_t shm = sizeof(float4) * size_t((cfg.xlds + 3) / 4);
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kLdsPassBlock), shm, s, At, c, cfg.xlds, x, cs, st_in, st_out,
+                       part1, nparts1, h);
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t pass2_lds(const PassCfg &cfg, const SpView &At, const float *c, float *x, ColStep cs,
+                            const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                            int prepare, hipStream_t s)
+{
+    switch (cfg.lpr) {
+    case 4: return pass2_lds_go<VT, VEC, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, prepare, s);
+    case 8: return pass2_lds_go<VT, VEC, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, prepare, s);
+    case 16: return pass2_lds_go<VT, VEC, 16>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, prepare, s);
+    case 32: return pass2_lds_go<VT, VEC, 32>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, prepare, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t pass2_lds_kind(const PassCfg &cfg, int vk, const SpView &At, const float *c, float *x, ColStep cs,
+                                 const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
+                                 int prepare, hipStream_t s)
+{
+#define SMX_P2L(VT)                                                                                                    \
+    (cfg.vec == 8 ? pass2_lds<VT, 8>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, prepare, s)                 \
+                  : (cfg.vec == 4 ? pass2_lds<VT, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, prepare, s) \
+                                  : hipErrorInvalidValue))
+    switch (vk) {
+    case VK_F32U16: return SMX_P2L(F32U16Tag);
+    case VK_F32: return SMX_P2L(float);
+    case VK_BF16: return SMX_P2L(Bf16Tag);
+    case VK_BF16P: return SMX_P2L(Bf16PTag);
+    case VK_F16: return SMX_P2L(F16Tag);
+    case VK_F16P: return SMX_P2L(F16PTag);
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_P2L
+}
+
+hipError_t prepare_lds_passes()
 {
     static hipError_t done = hipErrorNotReady;
     if (done == hipSuccess) return done;
@@ -2383,8 +2480,11 @@ hipError_t prepare_pass1_lds()
                 c.lpr = lpr;
                 c.vec = vec;
                 c.grid = 1;
-                const hipError_t e = pass1_lds_kind(c, vk, none, nullptr, nullptr, nullptr, RowW{}, nullptr, nullptr,
-                                                    0, nullptr, 1, nullptr);
+                hipError_t e = pass1_lds_kind(c, vk, none, nullptr, nullptr, nullptr, RowW{}, nullptr, nullptr, 0,
+                                              nullptr, 1, nullptr);
+                if (e != hipSuccess) return e;
+                e = pass2_lds_kind(c, vk, none, nullptr, nullptr, ColStep{}, nullptr, nullptr, nullptr, 0, Hist{}, 1,
+                                   nullptr);
                 if (e != hipSuccess) return e;
             }
     done = hipSuccess;
@@ -2397,7 +2497,7 @@ hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid) return hipErrorInvalidValue;
     if (cfg.mode == 3) {
-        if (B != 1 || cfg.xlds < 1 || cfg.xlds > kPass1LdsFloats) return hipErrorInvalidValue;
+        if (B != 1 || cfg.xlds < 1 || cfg.xlds > kLdsPassFloats) return hipErrorInvalidValue;
         return pass1_lds_kind(cfg, vk, A, x, lower, upper, w, c, st, query, partials, 0, s);
     }
     if (B > 1) {
@@ -2591,6 +2691,10 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
                         int nparts1, Hist h, hipStream_t s)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
+    if (cfg.mode == 3) {
+        if (B != 1 || cfg.xlds < 1 || cfg.xlds > kLdsPassFloats) return hipErrorInvalidValue;
+        return pass2_lds_kind(cfg, vk, At, c, x, cs, st_in, st_out, part1, nparts1, h, 0, s);
+    }
     if (B > 1) {
         if (vk == VK_F32U16) return hipErrorInvalidValue;
         if (vk == VK_F32) return pass2_mm_b<float, 4>(cfg, At, c, x, cs, st_in, st_out, B, part1, nparts1, h, s);

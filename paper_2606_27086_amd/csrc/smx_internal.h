@@ -106,16 +106,16 @@ constexpr int kStreamEntries = 2048; // entries per row block of the streaming p
 struct PassCfg {
     int mode; // 0: a group of lpr lanes per row; 1: row blocks streamed through LDS;
               // 2: (pass 2 of an image operator) image tiles, lpr lanes per column;
-              // 3: (pass 1, one slice) lpr lanes per row, the vector's first xlds
+              // 3: (one slice) lpr lanes per row, the gathered vector's first xlds
               //    entries staged in LDS by every workgroup (one per CU)
     int lpr;  // lanes per row (mode 0): 2, 4, 8, 16, 32 or 64
     int vec;  // entries per lane per load: 4 or 8
     int grid; // workgroups
-    int xlds = 0; // mode 3: entries of the gathered vector held in LDS (<= kPass1LdsFloats)
+    int xlds = 0; // mode 3: entries of the gathered vector held in LDS (<= kLdsPassFloats)
 };
 
-constexpr int kPass1LdsBlock = 1024;   // threads of an LDS-staged pass-1 workgroup
-constexpr int kPass1LdsFloats = 40448; // its LDS copy of the gathered vector (158 KB)
+constexpr int kLdsPassBlock = 1024;   // threads of an LDS-staged pass workgroup
+constexpr int kLdsPassFloats = 40448; // its LDS copy of the gathered vector (158 KB)
 
 // Row weights of pass 1: c_i = S_i t_i and the proximity term D_i t_i^2 (S = D
 // for the weighted simultaneous step; 1/||A||_F^2 for CQ; w for the
@@ -244,9 +244,9 @@ constexpr int kMaxPassGrid = 4096; // workgroups of a pass kernel (one proximity
 hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
                         const float *lower, const float *upper, RowW w, float *c, const SliceState *st, int B,
                         int query, double *partials, hipStream_t s);
-// raises the dynamic-LDS limit of every LDS-staged pass-1 kernel (once per
+// raises the dynamic-LDS limit of every LDS-staged pass kernel (once per
 // process; outside any stream capture, before the first such launch)
-hipError_t prepare_pass1_lds();
+hipError_t prepare_lds_passes();
 // pass 2: x = clip(x + lambda A^T c, lo, hi); workgroup 0 also ends the
 // iteration (proximity from pass 1's partials, history, k + 1) into st_out
 hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &RB, int vk, const float *c, float *x,

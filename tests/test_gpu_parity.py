@@ -413,11 +413,12 @@ def test_interleaved_lane_pass1(smx, storage, monkeypatch):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_lds_staged_pass1(smx, storage, monkeypatch):
-    """Pass 1 with the gathered vector's first 40,448 entries staged in LDS:
-    a vector longer than that (gathers from LDS and from memory), one that
-    fits whole with a length not a multiple of four, CT with TV, and EMR with
-    dose-volume constraints (its quadratic-form pass gathers y the same way)."""
+def test_lds_staged_passes(smx, storage, monkeypatch):
+    """Both passes with the gathered vector's first 40,448 entries staged in
+    LDS (x for pass 1, c for pass 2): vectors longer than that (gathers from
+    LDS and from memory), ones that fit whole with a length not a multiple of
+    four, CT with TV, and EMR with dose-volume constraints (its kept y and
+    quadratic-form pass)."""
     monkeypatch.setenv("SMX_PASS_MODE", "lds")
     vr = None if storage == "f32" else storage
     wl = W.random_sparse(2500, 50001, 30, seed=46, empty_frac=0.05, long_rows=3, long_len=45000,
@@ -425,8 +426,12 @@ def test_lds_staged_pass1(smx, storage, monkeypatch):
     p = smx.problem_from_workload(wl, storage=storage, fused=False)
     d = p.describe()[storage]
     p.close()
-    assert d["pass1"]["mode"] == "lds" and not (d["fused"] or {}).get("in_use"), d
+    assert d["pass1"]["mode"] == "lds" and d["pass2"]["mode"] == "lds", d
+    assert d["pass1"]["xlds"] == 40448 and d["pass2"]["xlds"] == 2500, d
+    assert not (d["fused"] or {}).get("in_use"), d
     check_parity(smx, wl, wl.K, storage=storage, value_round=vr, fused=False)
+    wt = W.random_sparse(45001, 3000, 8, seed=49, empty_frac=0.05, long_rows=2, obj=W.OBJ_LINEAR, K=12)
+    check_parity(smx, wt, wt.K, storage=storage, value_round=vr, fused=False)
     ws = W.random_sparse(3000, 2001, 12, seed=47, empty_frac=0.08, long_rows=2, obj=W.OBJ_L1, K=20)
     check_parity(smx, ws, ws.K, storage=storage, value_round=vr, fused=False)
     wc = W.ct(N=48, n_angles=36, seed=48, K=30)
