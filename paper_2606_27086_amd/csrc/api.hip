@@ -1289,7 +1289,8 @@ int autotune_impl(smx_problem *p, int reps)
                         for (auto &o : cands1) dup = dup || (o.mode == 0 && o.lpr == lpr && o.vec == 1 && o.grid == c.grid);
                         if (!dup) cands1.push_back(c);
                     }
-            if (p->lds_grid > 0)
+            // the LDS-staged passes, where LDS holds at least half of the gathered vector
+            if (p->lds_grid > 0 && 2 * int64_t(p->lds_x) >= n)
                 for (int lpr : {4, 8, 16, 32})
                     for (int vec : {4, 8}) {
                         PassCfg c;
@@ -1328,7 +1329,7 @@ int autotune_impl(smx_problem *p, int reps)
             best = 1e30;
             PassCfg bestc2 = p->cfg2[vk];
             std::vector<PassCfg> cands2 = pass_candidates(p->op->csc, vk, p->B);
-            if (p->lds_grid > 0)
+            if (p->lds_grid > 0 && 2 * int64_t(p->lds_c) >= m)
                 for (int lpr : {4, 8, 16, 32})
                     for (int vec : {4, 8}) {
                         PassCfg c;
