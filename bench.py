@@ -93,6 +93,8 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
     vt = VALUE_TAG[shape["format"]]
     if shape["mode"] == "lds":
         return f"smx::k_pass{pass_no}_lds<{shape['lpr']}, {shape['vec']}, {vt}>"
+    if shape["mode"] == "panels":
+        return f"smx::k_pass2_panel<{shape['lpr']}, {shape['vec']}, {vt}>"
     if shape["mode"] == "tiles":
         if B > 1:
             return f"smx::k_pass2_tile_mm<{shape['lpr']}, {shape['vec']}, {vt}, {B}>"

@@ -197,6 +197,8 @@ struct smx_operator {
     int storage = SMX_STORE_F32;
     bool has_f32 = true;
     DevLayout csr, csc;
+    DBuf panel_ptr;              // row panels of the column copy (m > kLdsPassFloats): (np+1) x n entry offsets
+    int panel_np = 0, panel_P = 0;
     DBuf q32, q16; // float64 row norms of the float32 and the reduced-precision operator
     DBuf zcol;     // DROP column factors 1/(nonzeros in column j), 0 for an empty column [n]
     // image operators: the column layout grouped by image tiles (TileView);
@@ -257,6 +259,17 @@ struct smx_problem {
     int lds_grid = 0; // one slice: workgroups of the LDS-staged pass 1 (one per CU), 0 when unavailable
     int lds_x = 0;    // entries of the gathered vector it holds in LDS (pass 1: x)
     int lds_c = 0;    // the same for pass 2 (c)
+    DBuf ypanel;      // per-panel column sums of the panel pass 2 (np x n)
+    PanelView panels() const
+    {
+        PanelView v;
+        v.pp = op->panel_ptr.as<int32_t>();
+        v.np = op->panel_np;
+        v.P = op->panel_P;
+        v.m = m;
+        v.ypanel = ypanel.as<double>();
+        return v;
+    }
     bool tiles_ok = false; // pass 2 may use the operator's image-tile layout (a tile's rows x B fit in LDS)
     bool stop_var = false; // the variance stopping rule: x at each iteration's start, norms after it
     DBuf xprev, part_var;
@@ -596,6 +609,22 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
     {
         HostLayout H;
         if (!pad_rows(n, cp.data(), ri.data(), cv.data(), H)) return fail(SMX_EINVAL, "padded CSC exceeds 2^31 entries");
+        if (m > kLdsPassFloats) { // row panels of kLdsPassFloats rows for the panel pass 2
+            const int P = kLdsPassFloats;
+            const int np = (int)((m + P - 1) / P);
+            std::vector<int32_t> pp(size_t(np + 1) * n);
+            for (int64_t j = 0; j < n; ++j) {
+                int64_t k = cp[j];
+                for (int p = 0; p <= np; ++p) {
+                    const int64_t lim = (p == np) ? m : int64_t(p) * P;
+                    while (k < cp[j + 1] && ri[k] < lim) ++k;
+                    pp[size_t(p) * n + j] = (int32_t)(H.ptr[j] + (k - cp[j]));
+                }
+            }
+            upload(op->panel_ptr, pp, s, "upload row panels");
+            op->panel_np = np;
+            op->panel_P = P;
+        }
         std::vector<int32_t>().swap(ri);
         std::vector<float>().swap(cv);
         upload_layout(op->csc, H, n, m, op->has_f32, lp, s);
@@ -643,6 +672,9 @@ hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float
                      const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
                      hipStream_t s)
 {
+    if (c.mode == 5)
+        return launch_pass2_panels(c, view_for(p->op, true, p->fmt2[vk]), p->panels(), p->fmt2[vk], cres, x, cs, st_in,
+                                   st_out, part1, nparts1, h, s);
     if (c.mode == 2) {
         const int lp = p->op->lp_kind();
         const int tk = vk == VK_F32 ? VK_F32 : (lp == VK_BF16 ? VK_BF16P : VK_F16P);
@@ -1160,7 +1192,16 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->lds_grid = std::max(1, std::min(cus, kMaxPassGrid));
         p->lds_x = (int)std::min<int64_t>(n, kLdsPassFloats);
         p->lds_c = (int)std::min<int64_t>(m, kLdsPassFloats);
-        const char *me = getenv("SMX_PASS_MODE"); // "lds" starts both passes there
+        if (op->panel_np > 0) p->ypanel.alloc(sizeof(double) * size_t(op->panel_np) * n, "panel sums");
+        const char *me = getenv("SMX_PASS_MODE"); // "lds" starts both passes there, "panels" pass 2 in row panels
+        if (me && std::strcmp(me, "panels") == 0 && op->panel_np > 0)
+            for (int vk = 0; vk < 3; ++vk) {
+                PassCfg &c = p->cfg2[vk];
+                c.mode = 5;
+                c.lpr = 16;
+                c.vec = 4;
+                c.grid = p->lds_grid;
+            }
         if (me && std::strcmp(me, "lds") == 0)
             for (int vk = 0; vk < 3; ++vk)
                 for (int k = 0; k < 2; ++k) {
@@ -1329,6 +1370,16 @@ int autotune_impl(smx_problem *p, int reps)
             best = 1e30;
             PassCfg bestc2 = p->cfg2[vk];
             std::vector<PassCfg> cands2 = pass_candidates(p->op->csc, vk, p->B);
+            if (p->lds_grid > 0 && p->op->panel_np > 0)
+                for (int lpr : {8, 16, 32, 64})
+                    for (int vec : {4, 8}) {
+                        PassCfg c;
+                        c.mode = 5;
+                        c.lpr = lpr;
+                        c.vec = vec;
+                        c.grid = p->lds_grid;
+                        cands2.push_back(c);
+                    }
             if (p->lds_grid > 0 && 2 * int64_t(p->lds_c) >= m)
                 for (int lpr : {4, 8, 16, 32})
                     for (int vec : {4, 8}) {
@@ -1462,7 +1513,8 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
                  "\"fused\": %s}",
                  first ? "" : ", ", names[vk], a.mode == 3 ? "lds" : (a.mode ? "stream" : "rows"), a.lpr, a.vec, a.grid,
                  fmt_name(p->fmt1[vk]), a.mode == 3 ? a.xlds : 0,
-                 b.mode == 2 ? "tiles" : (b.mode == 3 ? "lds" : (b.mode ? "stream" : "rows")), b.lpr, b.vec, b.grid,
+                 b.mode == 2 ? "tiles" : (b.mode == 3 ? "lds" : (b.mode == 5 ? "panels" : (b.mode ? "stream" : "rows"))),
+                 b.lpr, b.vec, b.grid,
                  b.mode == 2 ? (vk == VK_F32 ? "f32+u16" : (vk == VK_BF16 ? "bf16+u16" : "f16+u16"))
                              : fmt_name(p->fmt2[vk]),
                  b.mode == 3 ? b.xlds : 0,

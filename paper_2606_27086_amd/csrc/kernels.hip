@@ -13,6 +13,7 @@
 // a one-workgroup kernel launched next sums the partials in workgroup order and
 // updates the per-slice state (acceptance of trial steps included).  No kernel
 // waits on, or signals, another workgroup of its own grid.
+#include <algorithm>
 #include <type_traits>
 #include "smx_internal.h"
 
@@ -853,6 +854,94 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass2_lds(SpView At, const fl
         }
     }
     end_pass2<kLdsPassBlock>(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
+}
+
+// Sum of one column segment [beg, end) of the column copy whose rows all lie
+// in the panel staged in LDS (cl[row - base]).  Segments start anywhere in a
+// column, so the chunks start at the aligned position before beg and the
+// entries outside [beg, end) are masked (they are in bounds: a column is
+// padded to a multiple of kRowAlign entries).
+template <int LPR, int VEC, typename VT>
+__device__ inline double seg_dot_lds(const SpView &A, int beg, int end, int lane, const float *cl, int base)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr int STEP = LPR * VEC;
+    for (int p = (beg / VEC) * VEC + lane * VEC; p < end; p += 4 * STEP) {
+        float v[4][VEC];
+        int c[4][VEC];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ok[u] = p + u * STEP < end;
+            if (ok[u]) Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u]) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int q = p + u * STEP + e;
+                    if (q >= beg && q < end) acc[u] = fma((double)v[u][e], (double)cl[c[u][e] - base], acc[u]);
+                }
+            }
+    }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Pass 2 for operators with many rows, over the column copy in row panels of
+// P rows: a work item is (panel p, a range of columns); the workgroup stages
+// c's rows of panel p in LDS, then each column's segment in that panel
+// (entries pp[p*n + j] .. pp[(p+1)*n + j]) is summed from LDS into
+// ypanel[p*n + j].  k_pass2_panel_sum adds a column's panel sums in panel
+// order and applies the column step.
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kLdsPassBlock) void k_pass2_panel(SpView At, const int32_t *__restrict__ pp, int np,
+                                                               int P, long long m, int cpt, int chunks,
+                                                               const float *__restrict__ c,
+                                                               double *__restrict__ ypanel,
+                                                               const SliceState *__restrict__ st_in)
+{
+    extern __shared__ float4 cl4[];
+    const float *cl = reinterpret_cast<const float *>(cl4);
+    constexpr int GROUPS = kLdsPassBlock / LPR;
+    if (!st_in[0].live) return; // the same in every workgroup: k_pass2_panel_sum skips the slice too
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const int n = (int)At.rows;
+    for (int t = blockIdx.x; t < np * chunks; t += gridDim.x) {
+        const int p = t / chunks, q = t % chunks;
+        const long long base = (long long)p * P;
+        const int len = (int)min((long long)P, m - base);
+        __syncthreads(); // the previous item's readers are done with the LDS copy
+        stage_vector<kLdsPassBlock>(cl4, c + base, len);
+        __syncthreads();
+        const int j1 = min(n, (q + 1) * cpt);
+        for (int j = q * cpt + grp; j < j1; j += GROUPS) {
+            const int beg = pp[(long long)p * n + j], end = pp[(long long)(p + 1) * n + j];
+            const double y = group_sum<LPR>(seg_dot_lds<LPR, VEC, VT>(At, beg, end, lane, cl, (int)base));
+            if (lane == 0) ypanel[(long long)p * n + j] = y;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pass2_panel_sum(int np, int n, const double *__restrict__ ypanel,
+                                                            float vscale_inv, float *__restrict__ x, ColStep cs,
+                                                            const SliceState *__restrict__ st_in,
+                                                            SliceState *__restrict__ st_out,
+                                                            const double *__restrict__ part1, int nparts1, Hist h)
+{
+    __shared__ double lds[4];
+    double yacc = 0.0;
+    if (st_in[0].live) {
+        for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
+            double y = 0.0;
+            for (int p = 0; p < np; ++p) y += ypanel[(long long)p * n + j];
+            float xo = 0.f;
+            if (!cs.defer) xo = x[j];
+            yacc += epi2(cs, j, j, y * (double)vscale_inv, xo, cs.lo[j], cs.hi[j], x);
+        }
+    }
+    end_pass2(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
 }
 
 template <int VEC, typename VT>
@@ -2467,6 +2556,71 @@ static hipError_t pass2_lds_kind(const PassCfg &cfg, int vk, const SpView &At, c
 #undef SMX_P2L
 }
 
+template <typename VT, int VEC, int LPR>
+static hipError_t panel_go(const PassCfg &cfg, const SpView &At, const PanelView &PV, const float *c,
+                           const SliceState *st_in, int prepare, hipStream_t s)
+{
+    auto kern = k_pass2_panel<LPR, VEC, VT>;
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(sizeof(float) * kLdsPassFloats));
+    const int n = (int)At.rows;
+    const int chunks = std::max(1, std::min(n, (4 * cfg.grid + PV.np - 1) / PV.np)); // ~4 work items per workgroup
+    const int cpt = (n + chunks - 1) / chunks;
+    const size_t shm = sizeof(float4) * size_t((PV.P + 3) / 4);
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kLdsPassBlock), shm, s, At, PV.pp, PV.np, PV.P, PV.m, cpt,
+                       (n + cpt - 1) / cpt, c, PV.ypanel, st_in);
+    return hipGetLastError();
+}
+
+template <typename VT, int VEC>
+static hipError_t panel_lpr(const PassCfg &cfg, const SpView &At, const PanelView &PV, const float *c,
+                            const SliceState *st_in, int prepare, hipStream_t s)
+{
+    switch (cfg.lpr) {
+    case 8: return panel_go<VT, VEC, 8>(cfg, At, PV, c, st_in, prepare, s);
+    case 16: return panel_go<VT, VEC, 16>(cfg, At, PV, c, st_in, prepare, s);
+    case 32: return panel_go<VT, VEC, 32>(cfg, At, PV, c, st_in, prepare, s);
+    case 64: return panel_go<VT, VEC, 64>(cfg, At, PV, c, st_in, prepare, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t panel_kind(const PassCfg &cfg, int vk, const SpView &At, const PanelView &PV, const float *c,
+                             const SliceState *st_in, int prepare, hipStream_t s)
+{
+#define SMX_PAN(VT)                                                                                                    \
+    (cfg.vec == 8 ? panel_lpr<VT, 8>(cfg, At, PV, c, st_in, prepare, s)                                              \
+                  : (cfg.vec == 4 ? panel_lpr<VT, 4>(cfg, At, PV, c, st_in, prepare, s) : hipErrorInvalidValue))
+    switch (vk) {
+    case VK_F32U16: return SMX_PAN(F32U16Tag);
+    case VK_F32: return SMX_PAN(float);
+    case VK_BF16: return SMX_PAN(Bf16Tag);
+    case VK_BF16P: return SMX_PAN(Bf16PTag);
+    case VK_F16: return SMX_PAN(F16Tag);
+    case VK_F16P: return SMX_PAN(F16PTag);
+    default: return hipErrorInvalidValue;
+    }
+#undef SMX_PAN
+}
+
+hipError_t launch_pass2_panels(const PassCfg &cfg, const SpView &At, const PanelView &PV, int vk, const float *c,
+                               float *x, ColStep cs, const SliceState *st_in, SliceState *st_out, const double *part1,
+                               int nparts1, Hist h, hipStream_t s)
+{
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || nparts1 < 1 || nparts1 > kMaxPassGrid) return hipErrorInvalidValue;
+    if (PV.np < 1 || PV.P < 1 || PV.P > kLdsPassFloats || PV.P % 4 != 0 || PV.m < 1 ||
+        (long long)PV.np * PV.P < PV.m || (long long)(PV.np - 1) * PV.P >= PV.m || !PV.pp || !PV.ypanel)
+        return hipErrorInvalidValue;
+    const hipError_t e = panel_kind(cfg, vk, At, PV, c, st_in, 0, s);
+    if (e != hipSuccess) return e;
+    // the column sums in the same grid, so that the ||y||^2 partials of the
+    // extrapolated steps number cfg.grid as for the other pass-2 shapes
+    hipLaunchKernelGGL(k_pass2_panel_sum, dim3(cfg.grid), dim3(kBlock), 0, s, PV.np, (int)At.rows, PV.ypanel,
+                       At.vscale_inv, x, cs, st_in, st_out, part1, nparts1, h);
+    return hipGetLastError();
+}
+
 hipError_t prepare_lds_passes()
 {
     static hipError_t done = hipErrorNotReady;
@@ -2486,6 +2640,12 @@ hipError_t prepare_lds_passes()
                 e = pass2_lds_kind(c, vk, none, nullptr, nullptr, ColStep{}, nullptr, nullptr, nullptr, 0, Hist{}, 1,
                                    nullptr);
                 if (e != hipSuccess) return e;
+                for (int plpr : {8, 16, 32, 64}) {
+                    PassCfg cp = c;
+                    cp.lpr = plpr;
+                    e = panel_kind(cp, vk, none, PanelView{}, nullptr, nullptr, 1, nullptr);
+                    if (e != hipSuccess) return e;
+                }
             }
     done = hipSuccess;
     return done;

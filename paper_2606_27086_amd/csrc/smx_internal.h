@@ -107,7 +107,9 @@ struct PassCfg {
     int mode; // 0: a group of lpr lanes per row; 1: row blocks streamed through LDS;
               // 2: (pass 2 of an image operator) image tiles, lpr lanes per column;
               // 3: (one slice) lpr lanes per row, the gathered vector's first xlds
-              //    entries staged in LDS by every workgroup (one per CU)
+              //    entries staged in LDS by every workgroup (one per CU);
+              // 5: (pass 2, one slice) the column copy in row panels, each
+              //    panel's rows of c staged in LDS
     int lpr;  // lanes per row (mode 0): 2, 4, 8, 16, 32 or 64
     int vec;  // entries per lane per load: 4 or 8
     int grid; // workgroups
@@ -244,6 +246,23 @@ constexpr int kMaxPassGrid = 4096; // workgroups of a pass kernel (one proximity
 hipError_t launch_pass1(const PassCfg &cfg, const SpView &A, const RowBlocks &RB, int vk, const float *x,
                         const float *lower, const float *upper, RowW w, float *c, const SliceState *st, int B,
                         int query, double *partials, hipStream_t s);
+// The column copy split into row panels of P rows (the last one shorter):
+// pp[p*n + j] is the first entry of column j whose row is >= p*P, for p = 0
+// .. np (pp[np*n + j] ends the column's entries); ypanel holds np*n partial
+// sums.
+struct PanelView {
+    const int32_t *pp = nullptr;
+    int np = 0, P = 0;
+    long long m = 0;
+    double *ypanel = nullptr;
+};
+
+// pass 2 in row panels (one slice): each panel's rows of c staged in LDS,
+// per-panel column sums, then the sums in panel order and the column step
+hipError_t launch_pass2_panels(const PassCfg &cfg, const SpView &At, const PanelView &PV, int vk, const float *c,
+                               float *x, ColStep cs, const SliceState *st_in, SliceState *st_out, const double *part1,
+                               int nparts1, Hist h, hipStream_t s);
+
 // raises the dynamic-LDS limit of every LDS-staged pass kernel (once per
 // process; outside any stream capture, before the first such launch)
 hipError_t prepare_lds_passes();

@@ -441,6 +441,26 @@ def test_lds_staged_passes(smx, storage, monkeypatch):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_row_panel_pass2(smx, storage, monkeypatch):
+    """Pass 2 over the column copy in row panels of 40,448 rows (c's rows of
+    a panel staged in LDS, per-panel sums added in panel order): 100,001 rows
+    make three panels, the last one short; the plain step, EMR's kept y and
+    DROP's column factors, against the oracle."""
+    monkeypatch.setenv("SMX_PASS_MODE", "panels")
+    vr = None if storage == "f32" else storage
+    w = W.random_sparse(100001, 700, 6, seed=50, empty_frac=0.05, long_rows=3, long_len=650, obj=W.OBJ_SQNORM,
+                        K=10)
+    p = smx.problem_from_workload(w, storage=storage, fused=False)
+    d = p.describe()[storage]
+    p.close()
+    assert d["pass2"]["mode"] == "panels" and not (d["fused"] or {}).get("in_use"), d
+    check_parity(smx, w, w.K, storage=storage, value_round=vr, fused=False)
+    for method in ("emr", "drop"):
+        wb = _with_basic(w, method)
+        check_parity(smx, wb, wb.K, storage=storage, value_round=vr, fused=False)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_lanes_per_row_kernels(smx, storage, monkeypatch):
     """The lanes-per-row pass kernels (the alternative launch shape) give the
     same results as the oracle too."""
