@@ -172,7 +172,7 @@ def gathers_of(w, shapes, dpass, tiles):
     one per nonzero for the row passes and the fused pass, one per (tile, row)
     pair for the image-tile pass 2, and for the LDS-staged passes one per
     nonzero whose column (pass 1) or row (pass 2) lies beyond the staged part
-    of the gathered vector."""
+    of the gathered vector (none for the row-panel pass 2)."""
     shape = shapes[f"pass{dpass}"]
     if dpass == 2 and shape["mode"] == "tiles" and not fused_in_use(shapes):
         return tiles["rows"]
@@ -182,6 +182,8 @@ def gathers_of(w, shapes, dpass, tiles):
         return int(np.count_nonzero(w.col_idx >= shape["xlds"]))  # the rest are LDS reads
     if dpass == 2 and shape["mode"] == "lds" and not fused_in_use(shapes):
         return int(w.nnz - w.row_ptr[min(shape["xlds"], w.m)])  # entries of rows beyond the staged part of c
+    if dpass == 2 and shape["mode"] == "panels" and not fused_in_use(shapes):
+        return 0  # every gather reads the staged panel in LDS
     return w.nnz
 
 
