@@ -198,6 +198,8 @@ struct smx_operator {
     bool has_f32 = true;
     DevLayout csr, csc;
     DBuf panel_ptr;              // row panels of the column copy (m > kLdsPassFloats): (np+1) x n entry offsets
+    DBuf panel_idx16;            // the column copy's rows as 16-bit offsets within their panel
+    DBuf panel_packed;           // reduced-precision value | panel offset << 16 (when values are stored so)
     int panel_np = 0, panel_P = 0;
     DBuf q32, q16; // float64 row norms of the float32 and the reduced-precision operator
     DBuf zcol;     // DROP column factors 1/(nonzeros in column j), 0 for an empty column [n]
@@ -622,12 +624,29 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
                 }
             }
             upload(op->panel_ptr, pp, s, "upload row panels");
+            if (m > 65536) { // rows need 32 bits in the column copy: a copy with 16-bit offsets within the panel
+                std::vector<uint16_t> lidx(size_t(H.slots), 0); // padding keeps offset 0
+                for (int64_t j = 0; j < n; ++j)
+                    for (int p = 0; p < np; ++p)
+                        for (int32_t k = pp[size_t(p) * n + j]; k < pp[size_t(p + 1) * n + j]; ++k)
+                            lidx[size_t(k)] = (uint16_t)(H.idx[size_t(k)] - p * P);
+                upload(op->panel_idx16, lidx, s, "upload panel row offsets");
+            }
             op->panel_np = np;
             op->panel_P = P;
         }
         std::vector<int32_t>().swap(ri);
         std::vector<float>().swap(cv);
         upload_layout(op->csc, H, n, m, op->has_f32, lp, s);
+        // with 32-bit rows the column copy keeps its separate reduced-precision
+        // values (it packs, and then drops them, only when rows fit 16 bits)
+        if (op->panel_idx16.p && lp != VK_F32 && op->csc.val16.p) {
+            op->panel_packed.alloc(sizeof(uint32_t) * size_t(std::max<int64_t>(op->csc.slots, 1)), "panel entries");
+            hip_check(launch_pack16u(op->csc.val16.as<uint16_t>(), op->panel_idx16.as<uint16_t>(),
+                                     op->panel_packed.as<uint32_t>(), op->csc.slots, s),
+                      "pack panel entries");
+            hip_check(hipStreamSynchronize(s), "pack panel entries");
+        }
     }
     if (tiled) upload_tiles(op.get(), TH, lp, s);
     if (op->has_f32) {
@@ -648,6 +667,7 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
     if (op->has_tiles())
         op->bytes += size_t(op->n + 1) * 4 + size_t(op->tiles.slots) * ((op->has_f32 ? 6 : 0) + (lp != VK_F32 ? 4 : 0)) +
                      size_t(op->n) * 4 + size_t(op->t_rptr.bytes / 4 + op->t_rlist.bytes / 4 + op->t_ntiles + 1) * 4;
+    op->bytes += op->panel_ptr.bytes + op->panel_idx16.bytes + op->panel_packed.bytes; // row panels (0 when absent)
     *out = op.release();
     return SMX_OK;
 }
@@ -667,14 +687,34 @@ int vk_for_iteration(const smx_problem *p, int64_t it, int64_t K, int64_t ref)
 
 int fused_fmt(const smx_problem *p, int vk) { return p->fmt1[vk]; }
 
+// Entry format of the row-panel pass 2 for value kind vk: 16-bit panel
+// offsets beside float32 values, or packed with the reduced-precision values.
+int panel_fmt(const smx_problem *p, int vk)
+{
+    if (vk == VK_F32) return p->op->panel_idx16.p ? VK_F32U16 : p->fmt2[vk];
+    if (p->op->panel_packed.p) return p->op->lp_kind() == VK_BF16 ? VK_BF16P : VK_F16P;
+    return p->fmt2[vk];
+}
+
 // Pass 2 in launch shape c: the image-tile layout (mode 2) or the column copy.
 hipError_t pass2_any(const smx_problem *p, int vk, const PassCfg &c, const float *cres, float *x, ColStep cs,
                      const SliceState *st_in, SliceState *st_out, const double *part1, int nparts1, Hist h,
                      hipStream_t s)
 {
-    if (c.mode == 5)
-        return launch_pass2_panels(c, view_for(p->op, true, p->fmt2[vk]), p->panels(), p->fmt2[vk], cres, x, cs, st_in,
-                                   st_out, part1, nparts1, h, s);
+    if (c.mode == 5) {
+        PanelView pv = p->panels();
+        const int fk = panel_fmt(p, vk);
+        SpView v = p->op->csc.view(fk); // rows <= 65536: the column copy's own 16-bit (global) rows
+        pv.local = 0;
+        if (fk == VK_F32U16 && p->op->panel_idx16.p) { // read as uint16 by the kernels
+            v.idx = p->op->panel_idx16.as<int32_t>();
+            pv.local = 1;
+        } else if ((fk == VK_BF16P || fk == VK_F16P) && p->op->panel_packed.p) {
+            v.val = p->op->panel_packed.p;
+            pv.local = 1;
+        }
+        return launch_pass2_panels(c, v, pv, fk, cres, x, cs, st_in, st_out, part1, nparts1, h, s);
+    }
     if (c.mode == 2) {
         const int lp = p->op->lp_kind();
         const int tk = vk == VK_F32 ? VK_F32 : (lp == VK_BF16 ? VK_BF16P : VK_F16P);
@@ -1516,7 +1556,7 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
                  b.mode == 2 ? "tiles" : (b.mode == 3 ? "lds" : (b.mode == 5 ? "panels" : (b.mode ? "stream" : "rows"))),
                  b.lpr, b.vec, b.grid,
                  b.mode == 2 ? (vk == VK_F32 ? "f32+u16" : (vk == VK_BF16 ? "bf16+u16" : "f16+u16"))
-                             : fmt_name(p->fmt2[vk]),
+                             : fmt_name(b.mode == 5 ? panel_fmt(p, vk) : p->fmt2[vk]),
                  b.mode == 3 ? b.xlds : 0,
                  fz);
         out += tmp;
@@ -1598,6 +1638,10 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
     *bytes = layout_bytes(m, s1, f32, lp, lp && n <= 65536, n <= 65536) +
              layout_bytes(n, s2, f32, lp, lp && m <= 65536, m <= 65536) +
              size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0)) + size_t(n) * 4;
+    if (m > kLdsPassFloats) { // row panels of the column copy: offsets (and 16-bit rows, packed entries)
+        const int64_t np = (m + kLdsPassFloats - 1) / kLdsPassFloats;
+        *bytes += size_t(np + 1) * size_t(n) * 4 + (m > 65536 ? size_t(s2) * (2 + (lp ? 4 : 0)) : 0);
+    }
     return SMX_OK;
 }
 

@@ -896,7 +896,7 @@ __device__ inline double seg_dot_lds(const SpView &A, int beg, int end, int lane
 // order and applies the column step.
 template <int LPR, int VEC, typename VT>
 __global__ __launch_bounds__(kLdsPassBlock) void k_pass2_panel(SpView At, const int32_t *__restrict__ pp, int np,
-                                                               int P, long long m, int cpt, int chunks,
+                                                               int P, long long m, int cpt, int chunks, int local,
                                                                const float *__restrict__ c,
                                                                double *__restrict__ ypanel,
                                                                const SliceState *__restrict__ st_in)
@@ -918,7 +918,8 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass2_panel(SpView At, const 
         const int j1 = min(n, (q + 1) * cpt);
         for (int j = q * cpt + grp; j < j1; j += GROUPS) {
             const int beg = pp[(long long)p * n + j], end = pp[(long long)(p + 1) * n + j];
-            const double y = group_sum<LPR>(seg_dot_lds<LPR, VEC, VT>(At, beg, end, lane, cl, (int)base));
+            const double y =
+                group_sum<LPR>(seg_dot_lds<LPR, VEC, VT>(At, beg, end, lane, cl, local ? 0 : (int)base));
             if (lane == 0) ypanel[(long long)p * n + j] = y;
         }
     }
@@ -2194,6 +2195,13 @@ __global__ void k_to_f16(const float *__restrict__ src, uint16_t *__restrict__ d
         dst[i] = __half_as_ushort(__float2half_rn(src[i] * scale));
 }
 
+__global__ void k_pack16u(const uint16_t *__restrict__ val16, const uint16_t *__restrict__ idx16,
+                          uint32_t *__restrict__ packed, long long count)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        packed[i] = (uint32_t)val16[i] | ((uint32_t)idx16[i] << 16);
+}
+
 __global__ void k_pack16(const uint16_t *__restrict__ val16, const int32_t *__restrict__ idx,
                          uint32_t *__restrict__ packed, long long count)
 {
@@ -2337,6 +2345,13 @@ hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float s
 {
     hipLaunchKernelGGL(k_to_f16, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s, src, dst, (long long)count,
                        scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack16u(const uint16_t *val16, const uint16_t *idx16, uint32_t *packed, int64_t count, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack16u, dim3(grid_for(count, kBlock, 8192)), dim3(kBlock), 0, s, val16, idx16, packed,
+                       (long long)count);
     return hipGetLastError();
 }
 
@@ -2569,7 +2584,7 @@ static hipError_t panel_go(const PassCfg &cfg, const SpView &At, const PanelView
     const int cpt = (n + chunks - 1) / chunks;
     const size_t shm = sizeof(float4) * size_t((PV.P + 3) / 4);
     hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kLdsPassBlock), shm, s, At, PV.pp, PV.np, PV.P, PV.m, cpt,
-                       (n + cpt - 1) / cpt, c, PV.ypanel, st_in);
+                       (n + cpt - 1) / cpt, PV.local, c, PV.ypanel, st_in);
     return hipGetLastError();
 }
 

@@ -223,6 +223,7 @@ hipError_t launch_rownorm(const SpView &A, int vk, double *q, hipStream_t s);
 hipError_t launch_make_D(const double *q, const double *w, float *D, int64_t m, hipStream_t s);
 hipError_t launch_to_bf16(const float *src, uint16_t *dst, int64_t count, hipStream_t s);
 hipError_t launch_to_f16(const float *src, uint16_t *dst, int64_t count, float scale, hipStream_t s);
+hipError_t launch_pack16u(const uint16_t *val16, const uint16_t *idx16, uint32_t *packed, int64_t count, hipStream_t s);
 hipError_t launch_pack16(const uint16_t *val16, const int32_t *idx, uint32_t *packed, int64_t count, hipStream_t s);
 hipError_t launch_init_state(SliceState *st, int B, StopParams sp, hipStream_t s);
 // the variance rule: xprev = x at the start of an iteration; after it,
@@ -255,6 +256,7 @@ struct PanelView {
     int np = 0, P = 0;
     long long m = 0;
     double *ypanel = nullptr;
+    int local = 0; // 1: the entries' indices are rows within their panel (16-bit copy), 0: global rows
 };
 
 // pass 2 in row panels (one slice): each panel's rows of c staged in LDS,

@@ -444,8 +444,9 @@ def test_lds_staged_passes(smx, storage, monkeypatch):
 def test_row_panel_pass2(smx, storage, monkeypatch):
     """Pass 2 over the column copy in row panels of 40,448 rows (c's rows of
     a panel staged in LDS, per-panel sums added in panel order): 100,001 rows
-    make three panels, the last one short; the plain step, EMR's kept y and
-    DROP's column factors, against the oracle."""
+    make three panels, the last one short, read through the copy with 16-bit
+    offsets within the panel; the plain step, EMR's kept y and DROP's column
+    factors, against the oracle; then 50,001 rows (two panels)."""
     monkeypatch.setenv("SMX_PASS_MODE", "panels")
     vr = None if storage == "f32" else storage
     w = W.random_sparse(100001, 700, 6, seed=50, empty_frac=0.05, long_rows=3, long_len=650, obj=W.OBJ_SQNORM,
@@ -458,6 +459,14 @@ def test_row_panel_pass2(smx, storage, monkeypatch):
     for method in ("emr", "drop"):
         wb = _with_basic(w, method)
         check_parity(smx, wb, wb.K, storage=storage, value_round=vr, fused=False)
+    # 50,001 rows fit 16 bits: the column copy's own rows (packed with the
+    # values for bf16), offset by the panel's first row
+    w2 = W.random_sparse(50001, 600, 6, seed=51, empty_frac=0.05, long_rows=2, long_len=550, obj=W.OBJ_LINEAR,
+                         K=10)
+    p = smx.problem_from_workload(w2, storage=storage, fused=False)
+    assert p.describe()[storage]["pass2"]["mode"] == "panels"
+    p.close()
+    check_parity(smx, w2, w2.K, storage=storage, value_round=vr, fused=False)
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
