@@ -357,7 +357,20 @@ int smx_slot_get_x(smx_problem *p, int32_t slot, float *out, int32_t on_device);
  * copies, so the iterate, state and history are unchanged.  Synchronises.
  * Results do not depend on the shape beyond float64 summation order.  With
  * the environment variable SMX_TUNE_LOG=1 each candidate's mean time is
- * printed to stderr. */
+ * printed to stderr.
+ *
+ * Other environment variables, read when an operator or problem is created
+ * (they pick starting shapes; smx_autotune may replace them):
+ *   SMX_PASS_MODE=rows|interleaved  lanes-per-row passes / interleaved-lane
+ *                                   pass 1 (one slice)
+ *   SMX_PASS_MODE=lds               both passes with the gathered vector's
+ *                                   first 40,448 entries in LDS (one slice)
+ *   SMX_PASS_MODE=panels            pass 2 in row panels of 40,448 rows, each
+ *                                   panel's residual in LDS (one slice,
+ *                                   m > 40,448)
+ *   SMX_TILES=0|1                   image operators: never use the tile pass 2,
+ *                                   or start every problem whose tiles fit on it
+ *   SMX_TILE=4|8|16                 image operators: tile edge (default 8) */
 int smx_autotune(smx_problem *p, int32_t reps);
 
 /* Fused single pass for one-slice problems (B = 1).  The two passes of a
