@@ -290,7 +290,8 @@ def section_seismic(smx, steps, warmup, tune):
     a 256 x 256 grid: A is 8192 x 65536 with first-Fresnel-zone band rows),
     DROP steps, noise-free and with 5 % noise, L1 / squared-norm / TV
     perturbations: SM iterations/s and the relative error to the true
-    slowness after `steps` iterations."""
+    slowness after `steps` iterations; then the straight-ray case, float32
+    and bf16 storage."""
     import numpy as np
 
     import workloads as W
@@ -315,6 +316,15 @@ def section_seismic(smx, steps, warmup, tune):
             it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5), rel_err_true=round(err, 5),
             prox=r["prox"][0], obj=r["obj"][0], fused=fused_in_use(r["shapes"]),
             format=r["shapes"]["pass1"]["format"])
+    # straight-ray travel-time tomography: 200 x 400 cells, 100 sources x 200
+    # receivers (20,000 rays), TV, float32 against bf16-stored A, 500 iterations
+    t0 = time.time()
+    sr = W.seismic(seed=3, K=500)
+    out["straight_ray"] = dict(m=sr.m, n=sr.n, nnz=sr.nnz, generate_s=round(time.time() - t0, 1))
+    for storage in ("f32", "bf16"):
+        r = time_problem(smx, sr, storage, sr.K, warmup, tune=tune)
+        out["straight_ray"][storage] = summarise(sr, r, storage)
+        out["straight_ray"][storage].update(prox=r["prox"][0], obj=r["obj"][0])
     return out
 
 
