@@ -110,7 +110,7 @@ def measured_traffic(name, workload):
     """HBM bytes per launch from the committed counter table, or None when the
     table is missing, was taken on other kernel code, or lacks the kernel."""
     try:
-        from paper_2606_27086_amd.pmc_summary import kernel_source_hash
+        from pmc_summary import kernel_source_hash
 
         tab = json.load(open(PMC_TABLE))
         if tab.get("kernel_source_sha256") != kernel_source_hash():

@@ -6,7 +6,7 @@ device copy of known size, per workload (CT 256x256, radiotherapy).
 Writes a JSON table keyed by kernel template, stamped with the SHA-256 of the
 kernel source it was measured on (a changed kernel invalidates it).
 
-    python paper_2606_27086_amd/pmc_summary.py FETCH_DB WRITE_DB OUT_JSON
+    python pmc_summary.py FETCH_DB WRITE_DB OUT_JSON
 """
 import hashlib
 import json
@@ -14,7 +14,7 @@ import os
 import sqlite3
 import sys
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2606_27086_amd")
 COPY_BYTES = 512 * 1024 * 1024
 
 
