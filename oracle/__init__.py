@@ -88,6 +88,9 @@ class _Problem(C.Structure):
         ("n_dvc", C.c_int32),
         ("pad_", C.c_int32),
         ("dvc", C.POINTER(_Dvc)),
+        ("csc_ptr", C.POINTER(C.c_int64)),
+        ("csc_row", C.POINTER(C.c_int32)),
+        ("csc_val", C.POINTER(C.c_double)),
     ]
 
 
@@ -155,6 +158,15 @@ def lib():
         L.orc_gradient.argtypes = [P, dp, dp]
         L.orc_run.argtypes = [P, dp, C.c_int64, C.c_int32, C.POINTER(State), dp, dp, dp, ip, ip]
         L.orc_run.restype = C.c_int
+        L.orc_prepare.argtypes = [P, dp, dp]
+        L.orc_run_prepared.argtypes = [P, dp, dp, dp, C.c_int64, C.c_int32, C.POINTER(State), dp, dp, dp, ip, ip]
+        L.orc_run_prepared.restype = C.c_int
+        L.orc_build_csc.argtypes = [P, C.POINTER(C.c_int64), ip, dp]
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_max_threads.restype = C.c_int32
+        L.orc_dvc_boundary.argtypes = [P, dp, dp, dp]
+        L.orc_perturb.argtypes = [P, dp, C.POINTER(State)]
+        L.orc_perturb.restype = C.c_int
         L.orc_bands_at.argtypes = [P, dp, dp, dp]
         L.orc_dvc_count.argtypes = [C.POINTER(_Dvc)]
         L.orc_dvc_count.restype = C.c_int64
@@ -163,6 +175,15 @@ def lib():
         L.orc_round_f16_scaled.restype = C.c_double
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _dp(a: Optional[np.ndarray]):
@@ -269,6 +290,34 @@ class Problem:
             self.s.stop_dobj = float(stop.get("dobj", 1e-6))
             self.s.stop_var = float(stop.get("var", 0.0))
 
+    # -- setup -----------------------------------------------------------
+    def build_csc(self) -> None:
+        """The column copy of A for the (then column-parallel) transposed
+        product; built once, on first use."""
+        if getattr(self, "_csc", None) is not None:
+            return
+        nnz = int(self.row_ptr[-1])
+        cp = np.empty(self.n + 1, np.int64)
+        rows = np.empty(max(nnz, 1), np.int32)
+        vals = np.empty(max(nnz, 1), np.float64)
+        lib().orc_build_csc(C.byref(self.s), cp.ctypes.data_as(C.POINTER(C.c_int64)),
+                            rows.ctypes.data_as(C.POINTER(C.c_int32)), _dp(vals))
+        self._csc = (cp, rows, vals)
+        self.s.csc_ptr = cp.ctypes.data_as(C.POINTER(C.c_int64))
+        self.s.csc_row = rows.ctypes.data_as(C.POINTER(C.c_int32))
+        self.s.csc_val = _dp(vals)
+
+    def prepare(self) -> None:
+        """Everything the iterations reuse: the column copy, the row norms and
+        the DROP column factors (done once; run() calls it)."""
+        if getattr(self, "_prep", None) is not None:
+            return
+        self.build_csc()
+        q = np.empty(self.m)
+        zc = np.empty(self.n)
+        lib().orc_prepare(C.byref(self.s), _dp(q), _dp(zc))
+        self._prep = (q, zc)
+
     # -- building blocks -------------------------------------------------
     def matvec(self, x) -> np.ndarray:
         x = _f64(x)
@@ -277,6 +326,7 @@ class Problem:
         return r
 
     def matvec_t(self, c) -> np.ndarray:
+        self.build_csc()
         c = _f64(c)
         y = np.empty(self.n)
         lib().orc_matvec_t(C.byref(self.s), _dp(c), _dp(y))
@@ -297,6 +347,14 @@ class Problem:
         lib().orc_bands_at(C.byref(self.s), _dp(_f64(x)), _dp(lo), _dp(up))
         return lo, up
 
+    def dvc_boundary(self, x):
+        """(kth, next): each dose-volume constraint's k-th and (k+1)-th
+        highest structure values at x (+inf / -inf where k = 0 / k = N)."""
+        k = np.empty(max(self.s.n_dvc, 1))
+        nx = np.empty(max(self.s.n_dvc, 1))
+        lib().orc_dvc_boundary(C.byref(self.s), _dp(_f64(x)), _dp(k), _dp(nx))
+        return k[: self.s.n_dvc], nx[: self.s.n_dvc]
+
     def dvc_count(self, g: int) -> int:
         """k of dose-volume constraint g: floor(V N_S) (MAX) or ceil(V N_S) (MIN)."""
         return int(lib().orc_dvc_count(C.byref(self.dvc[g])))
@@ -308,6 +366,16 @@ class Problem:
         g = np.empty(self.n)
         lib().orc_gradient(C.byref(self.s), _dp(_f64(x)), _dp(g))
         return g
+
+    def perturb(self, x, state: Optional[State] = None):
+        """The perturbation phase alone of the next outer iteration from x:
+        returns (z, state after the phase); k and the trial totals are not
+        advanced."""
+        z = _f64(x).reshape(-1).copy()
+        st = State() if state is None else state.copy()
+        if lib().orc_perturb(C.byref(self.s), _dp(z), C.byref(st)) != 0:
+            raise MemoryError("oracle perturbation failed to allocate")
+        return z, st
 
     def step(self, x):
         """One feasibility step T; returns (T(x), proximity at x)."""
@@ -329,8 +397,12 @@ class Problem:
             accepts=np.empty(K, np.int32),
         )
         ip = C.POINTER(C.c_int32)
-        rc = lib().orc_run(
+        self.prepare()
+        q, zc = self._prep
+        rc = lib().orc_run_prepared(
             C.byref(self.s),
+            _dp(q),
+            _dp(zc),
             _dp(x),
             K,
             1 if perturb else 0,

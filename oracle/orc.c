@@ -40,6 +40,7 @@
  * thread count.  All reductions are plain sequential loops.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -104,6 +105,11 @@ typedef struct {
     int32_t n_dvc;
     int32_t pad_;
     const orc_dvc *dvc;
+    /* optional column copy of A (orc_build_csc), used by the transposed
+     * product when present: col_ptr[n+1], each column's rows ascending */
+    const int64_t *csc_ptr;
+    const int32_t *csc_row;
+    const double *csc_val;
 } orc_problem;
 
 typedef struct {
@@ -142,13 +148,53 @@ void orc_matvec(const orc_problem *P, const double *x, double *r)
     }
 }
 
-/* y = A^T c: y_j = sum_i a_ij c_i, accumulated row after row. */
+/* y = A^T c: y_j = sum_i a_ij c_i, the terms added in ascending row order.
+ * With the column copy each column is one independent sum (the same terms in
+ * the same order as the row-after-row accumulation, so the result is the
+ * same bit for bit); without it the rows are accumulated one after another. */
 void orc_matvec_t(const orc_problem *P, const double *c, double *y)
 {
+    if (P->csc_ptr) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t j = 0; j < P->n; ++j) {
+            double s = 0.0;
+            for (int64_t p = P->csc_ptr[j]; p < P->csc_ptr[j + 1]; ++p) s += P->csc_val[p] * c[P->csc_row[p]];
+            y[j] = s;
+        }
+        return;
+    }
     for (int64_t j = 0; j < P->n; ++j) y[j] = 0.0;
     for (int64_t i = 0; i < P->m; ++i)
         for (int64_t p = P->row_ptr[i]; p < P->row_ptr[i + 1]; ++p) y[P->col[p]] += P->val[p] * c[i];
 }
+
+/* The column copy of A: a stable counting sort of the entries by column, so
+ * the rows of each column stay in ascending order.  col_ptr has n+1 entries,
+ * rows and vals nnz each (caller-owned). */
+void orc_build_csc(const orc_problem *P, int64_t *col_ptr, int32_t *rows, double *vals)
+{
+    const int64_t nnz = P->row_ptr[P->m];
+    for (int64_t j = 0; j <= P->n; ++j) col_ptr[j] = 0;
+    for (int64_t p = 0; p < nnz; ++p) col_ptr[P->col[p] + 1] += 1;
+    for (int64_t j = 0; j < P->n; ++j) col_ptr[j + 1] += col_ptr[j];
+    int64_t *next = malloc(sizeof(int64_t) * (P->n > 0 ? P->n : 1));
+    for (int64_t j = 0; j < P->n; ++j) next[j] = col_ptr[j];
+    for (int64_t i = 0; i < P->m; ++i)
+        for (int64_t p = P->row_ptr[i]; p < P->row_ptr[i + 1]; ++p) {
+            const int64_t q = next[P->col[p]]++;
+            rows[q] = (int32_t)i;
+            vals[q] = P->val[p];
+        }
+    free(next);
+}
+
+/* OpenMP threads used by the parallel loops (n > 0), and the current count. */
+void orc_set_threads(int32_t n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int32_t orc_max_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 /* q_i = ||a_i||^2 */
 void orc_row_sqnorms(const orc_problem *P, double *q)
@@ -163,21 +209,21 @@ void orc_row_sqnorms(const orc_problem *P, double *q)
 
 /*
  * Dose-volume constraints.  The structure's values d_i = r_i (i in S) are
- * ranked from the highest down; ties, and values that differ only below
- * float32 resolution, are ranked by row index (the rank compares the values
- * rounded to float32, so that the device, whose sums run in another order,
- * takes the same decisions).  The nearest point of the set
+ * ranked from the highest down by their exact (double) values; equal values
+ * are ranked by row index.  The nearest point of the set
  *   MAX: at most k = floor(V N_S) values above d  keeps the k highest values
  *        and lowers every other value above d to d;
  *   MIN: at least k = ceil(V N_S) values at or above d  raises the k highest
  *        values to d where they are below it and keeps the others;
  * (changing the k highest is the cheapest choice in both cases, the squared
- * distance being a sum over the changed values).  As bands on the rows: MAX
- * gives (-inf, +inf) to the k highest and (-inf, d] to the rest, MIN gives
- * [d, +inf) to the k highest and (-inf, +inf) to the rest.
+ * distance being a sum over the changed values; where the k-th and (k+1)-th
+ * values are equal the nearest point is not unique and the lower row index
+ * is kept among the k).  As bands on the rows: MAX gives (-inf, +inf) to the
+ * k highest and (-inf, d] to the rest, MIN gives [d, +inf) to the k highest
+ * and (-inf, +inf) to the rest.
  */
 typedef struct {
-    float key;
+    double key;
     int64_t row;
 } ranked;
 
@@ -209,7 +255,7 @@ static void effective_bands(const orc_problem *P, const double *r, double *lo, d
         const int64_t N = G->row_end - G->row_begin, k = orc_dvc_count(G);
         ranked *order = malloc(sizeof(ranked) * (N > 0 ? N : 1));
         for (int64_t p = 0; p < N; ++p) {
-            order[p].key = (float)r[G->row_begin + p];
+            order[p].key = r[G->row_begin + p];
             order[p].row = G->row_begin + p;
         }
         qsort(order, (size_t)N, sizeof(ranked), by_value_then_row);
@@ -226,6 +272,31 @@ static void effective_bands(const orc_problem *P, const double *r, double *lo, d
         }
         free(order);
     }
+}
+
+/* For each dose-volume constraint g at the point x: the k-th and (k+1)-th
+ * highest values of its structure (k as in orc_dvc_count; +inf when k = 0,
+ * -inf when k = N_S).  Where the two are close the nearest point of the set
+ * is nearly a tie, and a computation whose values carry rounding errors may
+ * keep the other row. */
+void orc_dvc_boundary(const orc_problem *P, const double *x, double *kth, double *next)
+{
+    double *r = malloc(sizeof(double) * P->m);
+    orc_matvec(P, x, r);
+    for (int32_t g = 0; g < P->n_dvc; ++g) {
+        const orc_dvc *G = &P->dvc[g];
+        const int64_t N = G->row_end - G->row_begin, k = orc_dvc_count(G);
+        ranked *order = malloc(sizeof(ranked) * (N > 0 ? N : 1));
+        for (int64_t p = 0; p < N; ++p) {
+            order[p].key = r[G->row_begin + p];
+            order[p].row = G->row_begin + p;
+        }
+        qsort(order, (size_t)N, sizeof(ranked), by_value_then_row);
+        kth[g] = k > 0 ? order[k - 1].key : INFINITY;
+        next[g] = k < N ? order[k].key : -INFINITY;
+        free(order);
+    }
+    free(r);
 }
 
 /*
@@ -548,19 +619,101 @@ void orc_stop_reset(orc_state *st)
     st->var_n = st->var_mean = st->var_m2 = 0.0;
 }
 
-int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_state *st, double *hist_prox,
-            double *hist_f_start, double *hist_f_end, int32_t *hist_trials, int32_t *hist_accepts)
+/*
+ * The perturbation phase of outer iteration st->k at x (in place), from
+ * f(x^k) = f_start:
+ *   - restarts: when restart_every > 0 and k is a positive multiple of it, the
+ *     restart count r grows by one and ell is set to r (Section 2.1.2);
+ *   - the direction is the normalised negative gradient v = -g/||g|| taken at
+ *     x^k and kept for the whole phase; if ||g|| = 0 the phase is skipped;
+ *   - each of the n_red reduction steps tries z = x^{k,n} + beta v with
+ *     beta = gamma * alpha^ell, ell growing by one per trial, and accepts the
+ *     first z with f(z) <= f(x^{k,n}); the number of trials per reduction step
+ *     is capped at max_trials, and a step that reaches the cap ends the phase.
+ * Returns f after the phase (f_start when nothing was accepted); counts the
+ * trials and accepted trials.  Scratch: g, v, z of length n.
+ */
+static double perturbation_phase(const orc_problem *P, double *x, orc_state *st, double f_start, double *g, double *v,
+                                 double *z, int32_t *trials, int32_t *accepts)
 {
-    const int64_t m = P->m, n = P->n;
-    double *q = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m), *c = malloc(sizeof(double) * m),
-           *y = malloc(sizeof(double) * n), *g = malloc(sizeof(double) * n), *v = malloc(sizeof(double) * n),
-           *z = malloc(sizeof(double) * n), *zc = malloc(sizeof(double) * n), *xp = malloc(sizeof(double) * n);
-    if (!q || !r || !c || !y || !g || !v || !z || !zc || !xp) {
-        free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc); free(xp);
+    const int64_t n = P->n, k = st->k;
+    if (P->restart_every > 0 && k > 0 && k % P->restart_every == 0) {
+        st->restarts += 1;
+        st->ell = st->restarts;
+    }
+    orc_gradient(P, x, g);
+    double gg = 0.0;
+    for (int64_t j = 0; j < n; ++j) gg += g[j] * g[j];
+    const double gn = sqrt(gg);
+    if (!(gn > 0.0)) return f_start;
+    for (int64_t j = 0; j < n; ++j) v[j] = -g[j] / gn;
+    double f_cur = f_start;
+    int32_t nr = 0;
+    while (nr < P->n_red) {
+        int accepted = 0;
+        for (int32_t t = 0; t < P->max_trials; ++t) {
+            const double beta = P->gamma * pow(P->alpha, (double)st->ell);
+            st->ell += 1;
+            for (int64_t j = 0; j < n; ++j) z[j] = x[j] + beta * v[j];
+            const double fz = orc_objective(P, z);
+            *trials += 1;
+            if (fz <= f_cur) {
+                memcpy(x, z, sizeof(double) * n);
+                f_cur = fz;
+                accepted = 1;
+                *accepts += 1;
+                break;
+            }
+        }
+        if (!accepted) {
+            st->cap_hits += 1;
+            break;
+        }
+        nr += 1;
+    }
+    return f_cur;
+}
+
+/* The perturbation phase alone, as outer iteration st->k would run it, on x
+ * (in place): the point z^k the feasibility step then acts on.  The state's
+ * ell, restarts and cap hits advance as in orc_run; k and the trial totals
+ * do not.  Without an objective nothing changes.  Returns -2 when out of
+ * memory. */
+int orc_perturb(const orc_problem *P, double *x, orc_state *st)
+{
+    if (P->obj == ORC_OBJ_NONE) return 0;
+    double *g = malloc(sizeof(double) * P->n), *v = malloc(sizeof(double) * P->n), *z = malloc(sizeof(double) * P->n);
+    if (!g || !v || !z) {
+        free(g); free(v); free(z);
         return -2;
     }
+    int32_t trials = 0, accepts = 0;
+    perturbation_phase(P, x, st, orc_objective(P, x), g, v, z, &trials, &accepts);
+    free(g); free(v); free(z);
+    return 0;
+}
+
+/* What every iteration reuses: the row norms q[m] and the DROP column
+ * factors zc[n]. */
+void orc_prepare(const orc_problem *P, double *q, double *zc)
+{
     orc_row_sqnorms(P, q);
     drop_factors(P, zc);
+}
+
+/* orc_run with q and zc from orc_prepare. */
+int orc_run_prepared(const orc_problem *P, const double *q, const double *zc, double *x, int64_t K, int32_t perturb,
+                     orc_state *st, double *hist_prox, double *hist_f_start, double *hist_f_end, int32_t *hist_trials,
+                     int32_t *hist_accepts)
+{
+    const int64_t m = P->m, n = P->n;
+    double *r = malloc(sizeof(double) * m), *c = malloc(sizeof(double) * m), *y = malloc(sizeof(double) * n),
+           *g = malloc(sizeof(double) * n), *v = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n),
+           *xp = malloc(sizeof(double) * n);
+    if (!r || !c || !y || !g || !v || !z || !xp) {
+        free(r); free(c); free(y); free(g); free(v); free(z); free(xp);
+        return -2;
+    }
     const int sm = perturb && P->obj != ORC_OBJ_NONE;
     for (int64_t it = 0; it < K; ++it) {
         if (hist_prox) hist_prox[it] = NAN;
@@ -569,7 +722,6 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
         if (hist_trials) hist_trials[it] = 0;
         if (hist_accepts) hist_accepts[it] = 0;
         if (P->stop_on && st->stop_reason) continue;
-        const int64_t k = st->k;
         int32_t trials = 0, accepts = 0;
         double f_start = NAN, f_end = NAN;
         memcpy(xp, x, sizeof(double) * n);
@@ -581,42 +733,7 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
                 if (hist_f_start) hist_f_start[it] = NAN;
                 continue;
             }
-            if (P->restart_every > 0 && k > 0 && k % P->restart_every == 0) {
-                st->restarts += 1;
-                st->ell = st->restarts;
-            }
-            orc_gradient(P, x, g);
-            double gg = 0.0;
-            for (int64_t j = 0; j < n; ++j) gg += g[j] * g[j];
-            double gn = sqrt(gg);
-            if (gn > 0.0) {
-                for (int64_t j = 0; j < n; ++j) v[j] = -g[j] / gn;
-                double f_cur = f_start;
-                int32_t nr = 0;
-                while (nr < P->n_red) {
-                    int accepted = 0;
-                    for (int32_t t = 0; t < P->max_trials; ++t) {
-                        double beta = P->gamma * pow(P->alpha, (double)st->ell);
-                        st->ell += 1;
-                        for (int64_t j = 0; j < n; ++j) z[j] = x[j] + beta * v[j];
-                        double fz = orc_objective(P, z);
-                        trials += 1;
-                        if (fz <= f_cur) {
-                            memcpy(x, z, sizeof(double) * n);
-                            f_cur = fz;
-                            accepted = 1;
-                            accepts += 1;
-                            break;
-                        }
-                    }
-                    if (!accepted) {
-                        st->cap_hits += 1;
-                        break;
-                    }
-                    nr += 1;
-                }
-                f_end = f_cur;
-            }
+            f_end = perturbation_phase(P, x, st, f_start, g, v, z, &trials, &accepts);
         }
         double prox = feas_step(P, q, zc, x, r, c, y);
         if (hist_prox) hist_prox[it] = prox;
@@ -629,8 +746,23 @@ int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_sta
         st->k += 1;
         if (P->stop_on) stop_after_step(P, st, sm, prox, f_start, xp, x);
     }
-    free(q); free(r); free(c); free(y); free(g); free(v); free(z); free(zc); free(xp);
+    free(r); free(c); free(y); free(g); free(v); free(z); free(xp);
     return 0;
+}
+
+int orc_run(const orc_problem *P, double *x, int64_t K, int32_t perturb, orc_state *st, double *hist_prox,
+            double *hist_f_start, double *hist_f_end, int32_t *hist_trials, int32_t *hist_accepts)
+{
+    double *q = malloc(sizeof(double) * P->m), *zc = malloc(sizeof(double) * P->n);
+    if (!q || !zc) {
+        free(q); free(zc);
+        return -2;
+    }
+    orc_prepare(P, q, zc);
+    const int rc = orc_run_prepared(P, q, zc, x, K, perturb, st, hist_prox, hist_f_start, hist_f_end, hist_trials,
+                                    hist_accepts);
+    free(q); free(zc);
+    return rc;
 }
 
 /*

@@ -349,6 +349,63 @@ def test_phase_never_increases_objective(orc):
     assert np.all(h.accepts <= h.trials)
 
 
+def test_perturb_then_step_is_one_iteration(orc):
+    """The perturbation phase alone, then the feasibility step, is one outer
+    iteration (bitwise); on f = ||x||^2 the phase of the first iteration is
+    x (1 - beta/||x||) with beta = gamma (ell = 0), as in the closed form."""
+    w = W.random_sparse(40, 36, 5, seed=14, obj=W.OBJ_TV2D, tv_shape=(6, 6))
+    P = orc.from_workload(w.with_params(n_red=2, restart_every=3))
+    x, st, _ = P.run(w.x0[:, 0], 7)
+    z, sz = P.perturb(x, st)
+    x2, _ = P.step(z)
+    x1, s1, _ = P.run(x, 1, state=st)
+    assert np.array_equal(x1, x2) and sz.ell == s1.ell and sz.restarts == s1.restarts
+    Q = _unconstrained(orc, 5, W.OBJ_SQNORM, gamma=0.3, alpha=0.9)
+    x0 = np.arange(1.0, 6.0)
+    z, sz = Q.perturb(x0)
+    np.testing.assert_allclose(z, x0 * (1 - 0.3 / np.linalg.norm(x0)), rtol=1e-15)
+    assert sz.ell == 1 and sz.k == 0
+
+
+def _proximity_objective_path(P, x0, K, perturb):
+    """(P(x^k), f(x^k)) for k = 1..K along one run."""
+    x, st, out = np.asarray(x0, np.float64), None, []
+    for _ in range(K):
+        x, st, _ = P.run(x, 1, perturb=perturb, state=st)
+        out.append((P.proximity(x), P.objective(x)))
+    return np.array(out)
+
+
+def _best_objective_at_levels(path, levels):
+    """min f(x^k) over the iterates with P(x^k) <= level, per level (NaN where
+    no iterate reaches the level)."""
+    return np.array([path[path[:, 0] <= e, 1].min() if np.any(path[:, 0] <= e) else np.nan for e in levels])
+
+
+@pytest.mark.parametrize("case", ["dense", "ct_tv", "seismic_tv", "rt_linear"])
+def test_superiorized_beats_unperturbed_at_equal_proximity(orc, case):
+    """'Superior' in the sense of Section 2.1.2: from the same x0, at every
+    proximity level on a log grid between the levels both runs reach, the
+    lowest objective of the superiorized run is at most that of the
+    feasibility-seeking run alone, and strictly lower at the finest level.
+    This is the method's aim rather than a theorem; the cases are the small
+    dense, CT, seismic and radiotherapy problems (the dense one over 1000
+    iterations, once beta has decayed enough for its proximity to fall)."""
+    w, K = {"dense": (W.dense_small(), 1000), "ct_tv": (W.ct(N=32, n_angles=24, seed=5, K=60), 60),
+            "seismic_tv": (W.seismic(rows=30, cols=60, n_src=15, n_rec=30, seed=9, K=80, variant="paper"), 80),
+            "rt_linear": (W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=10, K=40), 40)}[case]
+    P = orc.from_workload(w)
+    sm = _proximity_objective_path(P, w.x0[:, 0], K, True)
+    fe = _proximity_objective_path(P, w.x0[:, 0], K, False)
+    hi = min(sm[:, 0].max(), fe[:, 0].max())
+    lo = max(sm[:, 0].min(), fe[:, 0].min())
+    assert lo < hi
+    levels = np.geomspace(hi, lo, 8)
+    a, b = _best_objective_at_levels(sm, levels), _best_objective_at_levels(fe, levels)
+    assert np.all(a <= b * (1 + 1e-12)), (levels, a, b)
+    assert a[-1] < b[-1]
+
+
 def test_checkpoint_resume_bitwise(orc):
     w = W.random_sparse(40, 36, 5, seed=13, obj=W.OBJ_TV2D, tv_shape=(6, 6))
     P = orc.from_workload(w)
@@ -784,13 +841,25 @@ def test_dvc_limits_reduce_to_bands(orc):
         assert sg.trials == sb.trials
 
 
-def test_dvc_rank_uses_float32_values(orc):
-    """Values equal in float32 but not in float64 rank by row index: 0.6 and
-    0.6 + 1e-12 on rows 0 and 1 of an 'at most 1 of 2 above 0.5' group keep
-    row 0 (the lower float64 value)."""
+def test_dvc_rank_uses_exact_values(orc):
+    """The ranking compares exact values: 0.6 and 0.6 + 1e-12 (equal in
+    float32) on rows 0 and 1 of an 'at most 1 of 2 above 0.5' group keep row 1,
+    the higher value, which is the unique nearest point: lowering row 0 costs
+    0.1^2, lowering row 1 (0.1 + 1e-12)^2.  The same holds with the rows'
+    order reversed, and the boundary query reports the two values."""
     P = _identity_dvc(orc, 2, W.DVC_MAX, 0.5, 0.5)
     lo, up = P.bands_at(np.array([0.6, 0.6 + 1e-12]))
+    np.testing.assert_array_equal(up, [0.5, np.inf])
+    lo, up = P.bands_at(np.array([0.6 + 1e-12, 0.6]))
     np.testing.assert_array_equal(up, [np.inf, 0.5])
+    best, _ = _dvc_brute_force(np.array([0.6, 0.6 + 1e-12]), W.DVC_MAX, 1, 0.5)
+    assert 2 * 2 * P.proximity(np.array([0.6, 0.6 + 1e-12])) == pytest.approx(best, rel=1e-12)
+    kth, nxt = P.dvc_boundary(np.array([0.6, 0.6 + 1e-12]))
+    assert kth[0] == 0.6 + 1e-12 and nxt[0] == 0.6
+    # 'at least 1 of 2 at or above 0.9' raises the higher of two near-equal values
+    Q = _identity_dvc(orc, 2, W.DVC_MIN, 0.5, 0.9)
+    lo, up = Q.bands_at(np.array([0.3, 0.3 + 1e-13]))
+    np.testing.assert_array_equal(lo, [-np.inf, 0.9])
 
 
 # ---------------------------------------------------------------------------
