@@ -1,31 +1,45 @@
 """Benchmark: superiorized band+box projection iterations on one MI355X.
 
 A step is one outer iteration of Algorithm 1 over the whole workload: the
-perturbation phase (TV gradient, trial steps, acceptance, apply) followed by the
+perturbation phase (direction, trial steps, acceptance, apply) followed by the
 feasibility step (pass 1: r = A z with the band clip and weights; pass 2:
-A^T of the weighted residual with the box).  The headline workload is
-parallel-beam CT on a 256 x 256 image (180 angles x 363 detectors, 15.0M
-nonzeros, float32 A) with TV perturbations, 200 iterations.
+A^T of the weighted residual with the box; or both in one fused pass over A).
+The headline workload is the radiotherapy configuration: 160 x 160 x 80
+voxels, 9 coplanar beams of 47 x 47 beamlets (2,060,316 x 19,881, ~400M
+nonzeros, float32 A), the infeasible overlap rows, the summed-dose linear
+objective, 300 iterations from x0 = 0 -- the configuration whose operator no
+cache holds.
 
 Prints one JSON line.  `value` is SM iterations per second of the float32 path
-with every input resident in HBM.  The line also carries
-  variants    the bf16-storage path on the same workload;
-  roofline    the dominant pass kernel: algorithmic bytes per launch / its mean
-              launch time (HIP events on the problem's stream), HBM traffic
-              from the committed counter table when it matches the kernels;
-  cpu_baseline the FP64 oracle on this host (the same 200 iterations);
-  batched     8 and 32 CT slices sharing A in one multi-slice problem;
-  serving     a stream of 64 mixed CT solves (128^2/256^2/512^2, 8-32 slices
-              each) through the continuous-batching server: p50/p99 latency
-              and aggregate slice iterations per second;
-  hbm_config  the radiotherapy configuration (2.06M x 19,881, ~400M
-              nonzeros), whose operator does not fit any cache: pass GB/s
-              against the 8 TB/s HBM peak;
-  basic_algorithms  DROP, CQ, EL and EMR steps on the headline workload;
-  seismic     the seismic setup at the paper's shape (8192 x 65536 band
-              rows, DROP, L1 / squared-norm / TV, with and without noise);
-  dose_volume the radiotherapy configuration with dose-volume constraints
-              (EMR), against the same problem without them.
+with every input resident in HBM: `--steps` iterations after `--warmup`
+untimed ones, timed with HIP events on the problem's stream (the start event
+queued behind the warm-up work, no host synchronisation in between), the
+median of five repeats.  The line also carries
+  variants     the bf16-storage path on the same workload, and the CT 256 x 256
+               workload (float32 and bf16);
+  full_job     the whole configured run (300 iterations from x0), float32 and
+               bf16;
+  accuracy     each path's proximity, objective and iterate against the FP64
+               oracle after the same iterations from x0;
+  roofline     the dominant kernel: algorithmic bytes per launch / its mean
+               launch time (HIP events on the problem's stream), HBM traffic
+               from the committed counter table when it matches the kernels;
+  cpu_baseline the FP64 oracle on this host: all threads and one thread, a
+               bounded sample of iterations, the CPU model;
+  superiorization  per configuration, the lowest objective the superiorized
+               run reaches at each proximity level against the unperturbed run;
+  batched      8 and 32 CT slices sharing A in one multi-slice problem;
+  serving      a stream of mixed CT solves (128^2/256^2/512^2, 8-32 slices
+               each) and radiotherapy plans through the continuous-batching
+               server: p50/p99 latency and aggregate slice iterations per
+               second over several arrival seeds;
+  hbm_config   the radiotherapy configuration with the two passes forced;
+  basic_algorithms  DROP, CQ, EL and EMR steps on the CT workload;
+  seismic      the seismic setup at the paper's shape (8192 x 65536 band
+               rows, DROP, L1 / squared-norm / TV, with and without noise) and
+               the straight-ray case;
+  dose_volume  the radiotherapy configuration with dose-volume constraints
+               (EMR), against the same problem without them.
 """
 from __future__ import annotations
 
@@ -121,23 +135,64 @@ def measured_traffic(name, workload):
         return None
 
 
-def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=True, keep_x=False):
-    """Timed run of `steps` iterations (inputs resident in HBM), then the same
-    iterations eagerly with HIP events around each pass launch.  keep_x adds
-    the timed run's final iterate (host float64)."""
+_OPS = {}
+
+
+def op_for(smx, w, storage):
+    """One device operator per (workload, storage), shared by every problem the
+    benchmark makes on it (creating the radiotherapy operator takes seconds)."""
+    key = (w.name, w.m, w.n, w.nnz, storage)
+    op = _OPS.get(key)
+    if op is None:
+        op = _OPS[key] = smx.Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage=storage,
+                                      image=getattr(w, "image", None))
+    return op
+
+
+def drop_ops():
+    for op in _OPS.values():
+        op.close()
+    _OPS.clear()
+
+
+def event_time(p, w, steps, warmup, graph, repeats=5):
+    """Median over `repeats` of the milliseconds `steps` iterations take, from
+    HIP events on the problem's stream: each repeat resets the iterate and
+    state to x0, enqueues `warmup` untimed iterations, queues the start event
+    behind them (no host synchronisation in between), then the `steps`
+    iterations and the end event.  One untimed pass first captures every
+    graph these calls replay."""
+    import statistics
+
     import torch
 
-    p = smx.problem_from_workload(w, storage=storage, refine_iters=0, fused=fused)
+    p.reset(w.x0)
+    p.run(warmup, perturb=True, graph=graph)
+    p.run(steps, perturb=True, graph=graph)
+    p.sync()
+    times = []
+    for _ in range(repeats):
+        p.reset(w.x0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p.run(warmup, perturb=True, graph=graph)
+        e0.record()
+        p.run(steps, perturb=True, graph=graph)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times), times
+
+
+def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=True, keep_x=False, repeats=5):
+    """Event-timed run of `steps` iterations after `warmup` (inputs resident in
+    HBM; event_time), then the same iterations eagerly with HIP events around
+    each pass launch.  keep_x adds the final iterate (host float64) of
+    `warmup + steps` iterations from x0."""
+    p = smx.problem_from_workload(w, storage=storage, refine_iters=0, fused=fused, op=op_for(smx, w, storage))
     shapes = p.autotune(reps=10) if tune else p.describe()
     tiles = shapes.get("tiles")
-    p.run(warmup, perturb=True, graph=graph)  # also captures the graphs
-    p.sync()
-    p.reset(w.x0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p.run(steps, perturb=True, graph=graph)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    ms, reps_ms = event_time(p, w, steps, warmup, graph, repeats)
     p.sync()
     prox, obj = p.query()
     x = p.get_x().cpu().double().numpy() if keep_x else None
@@ -148,9 +203,9 @@ def time_problem(smx, w, storage, steps, warmup, graph=True, tune=True, fused=Tr
     t1, t2, n = p.timing()
     p.set_timing(False)
     p.close()
-    return dict(seconds=dt, it_s=steps / dt, ms_per_step=1e3 * dt / steps, pass1_ms=t1, pass2_ms=t2, launches=n,
-                prox=[float(v) for v in prox], obj=[float(v) for v in obj], shapes=shapes[storage], x=x,
-                tiles=tiles)
+    return dict(seconds=ms * 1e-3, it_s=steps / (ms * 1e-3), ms_per_step=ms / steps, repeats_ms=reps_ms, pass1_ms=t1,
+                pass2_ms=t2, launches=n, prox=[float(v) for v in prox], obj=[float(v) for v in obj],
+                shapes=shapes[storage], x=x, tiles=tiles)
 
 
 def summarise(w, r, storage, B=1):
@@ -204,17 +259,132 @@ def roofline_of(w, r, storage, B=1, workload=None):
                 address_floor_us=round(floor_us, 2), address_frac=round(floor_us / (dms * 1e3), 3))
 
 
-def cpu_baseline(w, K):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, sample_all=10, sample_one=3, accuracy_k=0):
+    """The FP64 oracle on this host: setup (row norms, column copy) timed on
+    its own, then `sample_all` iterations from x0 on every thread the oracle
+    uses and `sample_one` on one thread (per-iteration rates; a whole run at
+    this size is extrapolated from them), then, untimed, the oracle continued
+    to `accuracy_k` iterations for the accuracy comparison.  Returns the
+    record and the oracle's iterate after accuracy_k iterations."""
     import oracle
 
-    P = oracle.from_workload(w)
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
-    x, st, h = P.run(w.x0[:, 0], K)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return dict(value=K / dt, unit="SM iterations/s", cores=cores, kind="oracle",
-                sample=f"{K} iterations of the same workload (FP64, OpenMP over rows)", seconds=dt,
-                prox=P.proximity(x), obj=P.objective(x))
+    P = oracle.from_workload(w)
+    P.prepare()
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, st, _ = P.run(w.x0[:, 0], sample_all)
+    dt_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        P.run(w.x0[:, 0], sample_one)
+        dt_one = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    xa = None
+    if accuracy_k:
+        xa, _, _ = P.run(x, max(accuracy_k - sample_all, 0), state=st)
+    rec = dict(value=round(sample_all / dt_all, 3), unit="SM iterations/s", cores=threads, kind="oracle",
+               sample=f"{sample_all} iterations from x0 on {threads} threads (FP64, OpenMP over rows; setup timed "
+                      f"apart); one thread: {sample_one} iterations; a whole {w.K}-iteration run is extrapolated",
+               seconds=round(dt_all, 3), one_thread=dict(value=round(sample_one / dt_one, 4), seconds=round(dt_one, 3),
+                                                        iterations=sample_one),
+               setup_s=round(setup, 2), cpu_model=cpu_model(), nproc=os.cpu_count(),
+               omp_num_threads=os.environ.get("OMP_NUM_THREADS"),
+               extrapolated_run_s=dict(all_threads=round(w.K * dt_all / sample_all, 1),
+                                       one_thread=round(w.K * dt_one / sample_one, 1)))
+    return rec, xa, P
+
+
+def accuracy_of(P, x, xo):
+    """Relative errors of the device's result x against the oracle's xo: the
+    proximity, the objective and the iterate (norm-wise, and the worst entry
+    on the scale max(|xo_j|, 1e-2 max|xo|))."""
+    import numpy as np
+
+    po, fo = P.proximity(xo), P.objective(xo)
+    scale = np.maximum(np.abs(xo), 1e-2 * max(float(np.abs(xo).max()), 1e-300))
+    return dict(prox_rel=abs(P.proximity(x) - po) / max(abs(po), 1e-300),
+                obj_rel=abs(P.objective(x) - fo) / max(abs(fo), 1e-300),
+                x_rel=float(np.linalg.norm(x - xo) / max(np.linalg.norm(xo), 1e-300)),
+                x_elem=float(np.max(np.abs(x - xo) / scale)))
+
+
+def run_from_x0(smx, w, storage, K, tune=True):
+    """K iterations from x0 (graph replay, no refinement tail): the final
+    iterate (host float64) and the seconds the run took (HIP events)."""
+    import torch
+
+    p = smx.problem_from_workload(w, storage=storage, refine_iters=0, op=op_for(smx, w, storage))
+    if tune:
+        p.autotune(reps=5)
+    p.run(K, perturb=True, graph=True)  # captures the graphs
+    p.sync()
+    p.reset(w.x0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    p.run(K, perturb=True, graph=True)
+    e1.record()
+    e1.synchronize()
+    x = p.get_x().cpu().double().numpy()[:, 0]
+    p.close()
+    return x, e0.elapsed_time(e1) * 1e-3
+
+
+def section_superiorization(smx, w_rt):
+    """Section 2.1.2's sense of superior, on the device at full size: the
+    superiorized run and the feasibility-seeking run alone from the same x0;
+    at each of 8 proximity levels between the ranges both reach, the lowest
+    objective each run attains among its iterates at or below that level.
+    Reported and flagged (`superior`), not enforced: it is the method's aim,
+    not a theorem."""
+    import numpy as np
+
+    import workloads as W
+
+    cases = [("dense_256x128", W.dense_small(), 100), ("ct256_tv", W.ct(N=256, seed=2, K=200), 200),
+             ("seismic_200x400_tv", W.seismic(seed=3, K=500), 500), ("rt_160x160x80_linear", w_rt, 300)]
+    out = {}
+    for name, w, K in cases:
+        paths = {}
+        for perturb in (True, False):
+            p = smx.problem_from_workload(w, storage="f32", refine_iters=0, op=op_for(smx, w, "f32"))
+            path = []
+            for _ in range(K):
+                p.run(1, perturb=perturb)
+                pr, f = p.query()
+                path.append((pr[0], f[0]))
+            p.close()
+            paths[perturb] = np.array(path)
+        sm, fe = paths[True], paths[False]
+        hi, lo = min(sm[:, 0].max(), fe[:, 0].max()), max(sm[:, 0].min(), fe[:, 0].min())
+        rec = dict(K=K, prox_range=[float(lo), float(hi)])
+        if lo < hi:
+            levels = np.geomspace(hi, lo, 8)
+            best = lambda path, e: float(path[path[:, 0] <= e, 1].min())  # noqa: E731
+            a = [best(sm, e) for e in levels]
+            b = [best(fe, e) for e in levels]
+            rec.update(levels=[float(e) for e in levels], min_f_superiorized=a, min_f_feasibility=b,
+                       superior=bool(all(x <= y * (1 + 1e-12) + 1e-300 for x, y in zip(a, b))))
+        else:
+            rec.update(superior=None, note="the two runs' proximity ranges do not overlap")
+        rec.update(final_superiorized=dict(prox=float(sm[-1, 0]), f=float(sm[-1, 1])),
+                   final_feasibility=dict(prox=float(fe[-1, 0]), f=float(fe[-1, 1])))
+        out[name] = rec
+    return out
 
 
 def section_batched(smx, steps, warmup, tune):
@@ -328,7 +498,7 @@ def section_seismic(smx, steps, warmup, tune):
     return out
 
 
-def section_dvc(smx, tune):
+def section_dvc(smx, tune, base):
     """The radiotherapy configuration with the horseshoe plan's dose-volume
     constraints (target D95% >= 0.97, target D5% <= 1.03, organ-at-risk
     D5% <= 0.16: three structures' rows appended to A), EMR steps and the
@@ -337,7 +507,6 @@ def section_dvc(smx, tune):
     import workloads as W
 
     t0 = time.time()
-    base = W.rt_large(seed=4, K=300)
     w = W.rt_with_dvc(base, basic=W.BASIC_EMR)
     out = dict(workload="radiotherapy 160x160x80 + 3 dose-volume constraints, EMR, linear dose objective",
                m=w.m, n=w.n, nnz=w.nnz, dvc_rows=int(sum(g["row_end"] - g["row_begin"] for g in w.dvc)),
@@ -351,35 +520,32 @@ def section_dvc(smx, tune):
     return out
 
 
-def section_hbm(smx, tune):
-    import workloads as W
-
-    t0 = time.time()
-    w = W.rt_large(seed=4, K=300)
-    gen = time.time() - t0
-    out = dict(workload="radiotherapy 160x160x80 voxels, 9 beams x 47x47 beamlets, linear dose objective",
-               m=w.m, n=w.n, nnz=w.nnz, generate_s=round(gen, 1))
+def section_hbm(smx, tune, w):
+    """The radiotherapy configuration with the two passes forced (the fused
+    pass disabled): pass 1 and pass 2 each against the HBM peak."""
+    out = dict(workload="radiotherapy 160x160x80 voxels, 9 beams x 47x47 beamlets, linear dose objective, two passes",
+               m=w.m, n=w.n, nnz=w.nnz)
     for storage in ("f32", "bf16"):
-        for fused in (True, False):
-            t0 = time.time()
-            r = time_problem(smx, w, storage, 100, 5, tune=tune, fused=fused)
-            s = summarise(w, r, storage)
-            s["roofline"] = roofline_of(w, r, storage, workload=RT_WORKLOAD)
-            s["wall_s"] = round(time.time() - t0, 1)
-            out[storage if fused else f"{storage}_two_passes"] = s
+        t0 = time.time()
+        r = time_problem(smx, w, storage, 100, 5, tune=tune, fused=False)
+        s = summarise(w, r, storage)
+        s["roofline"] = roofline_of(w, r, storage, workload=RT_WORKLOAD)
+        s["wall_s"] = round(time.time() - t0, 1)
+        out[f"{storage}_two_passes"] = s
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--sections", default="batched,serving,hbm,basic,seismic,dvc",
-                    help="extra sections beside the headline: batched,serving,hbm,basic,seismic,dvc (empty for none)")
+    ap.add_argument("--sections", default="ct,superiorization,batched,serving,hbm,basic,seismic,dvc",
+                    help="sections beside the headline: ct,superiorization,batched,serving,hbm,basic,seismic,dvc "
+                         "(empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the single-GPU path is what is built "
@@ -394,23 +560,33 @@ def main():
     smx.lib()
     torch.cuda.set_device(0)
     tune = not args.no_tune
-    w = W.ct(N=256, seed=2, K=200)
-    wname = CT_WORKLOAD
     graph = not args.no_graph
+    t0 = time.time()
+    w = W.rt_large(seed=4, K=300)
+    gen_s = time.time() - t0
+    print(f"radiotherapy workload generated in {gen_s:.1f}s: m={w.m} n={w.n} nnz={w.nnz}", file=sys.stderr, flush=True)
     results = {st: time_problem(smx, w, st, args.steps, args.warmup, graph=graph, tune=tune) for st in ("f32", "bf16")}
     main_r = results["f32"]
-    variants = {st: summarise(w, r, st) for st, r in results.items()}
+    variants = {}
     for st, r in results.items():
-        variants[st]["prox"], variants[st]["obj"] = r["prox"][0], r["obj"][0]
-    cpu = None
+        variants[f"rt_{st}"] = summarise(w, r, st)
+        variants[f"rt_{st}"].update(prox=r["prox"][0], obj=r["obj"][0], repeats_ms=[round(v, 4) for v in r["repeats_ms"]])
+    print(f"headline timed: {main_r['it_s']:.1f} it/s f32, {results['bf16']['it_s']:.1f} bf16", file=sys.stderr,
+          flush=True)
+    # the whole configured job, and the accuracy of each path against the oracle after the same iterations
+    acc_k = 120
+    full_job, finals = {}, {}
+    for st in ("f32", "bf16"):
+        x, sec = run_from_x0(smx, w, st, w.K, tune=tune)
+        full_job[st] = dict(iterations=w.K, seconds=round(sec, 4), it_s=round(w.K / sec, 2))
+        finals[st], _ = run_from_x0(smx, w, st, acc_k, tune=False)
+    cpu, accuracy = None, None
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(w, min(args.steps, w.K))
-        cpu = dict(value=round(cb["value"], 3), unit=cb["unit"], cores=cb["cores"], kind="oracle",
-                   sample=cb["sample"], seconds=round(cb["seconds"], 2))
-        if args.steps == w.K:
-            for st, r in results.items():
-                variants[st]["prox_rel_err_vs_oracle"] = abs(r["prox"][0] - cb["prox"]) / abs(cb["prox"])
-                variants[st]["obj_rel_err_vs_oracle"] = abs(r["obj"][0] - cb["obj"]) / abs(cb["obj"])
+        cpu, xo, P = cpu_baseline(w, accuracy_k=acc_k)
+        accuracy = dict(iterations=acc_k, reference="FP64 oracle on the float32 operator",
+                        **{st: {k: float(f"{v:.3e}") for k, v in accuracy_of(P, finals[st], xo).items()}
+                           for st in ("f32", "bf16")})
+        del P
     line = {
         "metric": "SM iterations/s (Ax/A^T r passes, FP32 vs BF16-A); p50/p99 solve latency",
         "value": round(main_r["it_s"], 2),
@@ -424,25 +600,36 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wname, "m": w.m, "n": w.n, "nnz": w.nnz, "B": w.B, "K": w.K, "graph": graph,
-                   "storage": "f32"},
-        "roofline": roofline_of(w, main_r, "f32", workload=CT_WORKLOAD),
+        "config": {"workload": RT_WORKLOAD + "_linear_dose_f32", "m": w.m, "n": w.n, "nnz": w.nnz, "B": w.B,
+                   "K": w.K, "graph": graph, "storage": "f32", "generate_s": round(gen_s, 1)},
+        "roofline": roofline_of(w, main_r, "f32", workload=RT_WORKLOAD),
         "cpu_baseline": cpu,
         "variants": variants,
+        "full_job": full_job,
+        "accuracy": accuracy,
     }
     sections = [s for s in args.sections.split(",") if s]
+    if "ct" in sections:
+        wc = W.ct(N=256, seed=2, K=200)
+        for st in ("f32", "bf16"):
+            r = time_problem(smx, wc, st, args.steps, args.warmup, graph=graph, tune=tune)
+            v = summarise(wc, r, st)
+            v.update(prox=r["prox"][0], obj=r["obj"][0], roofline=roofline_of(wc, r, st, workload=CT_WORKLOAD))
+            variants[f"ct256_{st}"] = v
+    if "superiorization" in sections:
+        line["superiorization"] = section_superiorization(smx, w)
     if "batched" in sections:
         line["batched"] = section_batched(smx, 100, 10, tune)
     if "serving" in sections:
         line["serving"] = section_serving(smx, tune)
     if "hbm" in sections:
-        line["hbm_config"] = section_hbm(smx, tune)
+        line["hbm_config"] = section_hbm(smx, tune, w)
     if "basic" in sections:
         line["basic_algorithms"] = section_basic(smx, 100, 10, tune)
     if "seismic" in sections:
         line["seismic"] = section_seismic(smx, 200, 10, tune)
     if "dvc" in sections:
-        line["dose_volume"] = section_dvc(smx, tune)
+        line["dose_volume"] = section_dvc(smx, tune, w)
     print(json.dumps(line), flush=True)
 
 

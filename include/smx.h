@@ -154,10 +154,10 @@ typedef struct {
     int32_t basic;           /* SMX_BASIC_*; SMX_BASIC_SIMULT (0) is the default */
     /* Stopping rules, checked on the device after every iteration (a stopped
      * slice stays idle; smx_run still returns after its K iterations).
-     * Section 2.2: the proximity P of the iteration <= stop_prox, or the
+     * Section 2.2.1: the proximity P of the iteration <= stop_prox, or the
      * relative change |P^{k+1} - P^k| / max{1, P^k} < stop_dprox for stop_n
      * consecutive iterations, or stop_max_iters iterations (0: none).  A
-     * perturbed run with an objective (Section 2.2.1) stops instead when one
+     * perturbed run with an objective (Section 2.2.3) stops instead when one
      * of the two proximity rules held at the last iteration and the objective
      * change |f(x^{k+1}) - f(x^k)| / max{1, f(x^k)} < stop_dobj; it is checked
      * when the next perturbation phase opens.  stop_var > 0 adds the rule of
@@ -257,6 +257,28 @@ int smx_operator_destroy(smx_operator *op);
  * counted at its maximum). */
 int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32,
                            size_t *bytes);
+
+/*
+ * Device bytes, without allocating anything, of an operator of this shape and
+ * storage (*operator_bytes, an upper bound as smx_operator_footprint's; with
+ * image_rows x image_cols = n, of the image operator smx_operator_create_image
+ * makes, tile layout included; 0 x 0 for a plain operator) and of
+ * a problem with this descriptor on it (*problem_bytes: exactly what
+ * smx_problem_create allocates on the current device -- bands, box, weights,
+ * iterate, gradient, residual, states, D, step weights, the extrapolated
+ * steps' y, the dose-volume buffers, the fused pass's partial vectors, the
+ * panel pass's per-panel sums, every kernel's per-workgroup partials and the
+ * history -- summed from the plan the creation allocates by).  desc may be
+ * NULL (*problem_bytes = 0); its arrays are not read.  Not counted:
+ * smx_autotune's temporary copies of the iterate, residual and states, and
+ * captured graphs.  Used for admission by HBM footprint (the serving pattern).
+ * Errors: SMX_EINVAL for a NULL output, an invalid shape or storage, or an
+ * invalid descriptor field the sizes depend on (B, basic algorithm,
+ * objective, TV image, max_trials, history_cap, dose-volume table), or an
+ * image that does not match n.
+ */
+int smx_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32, int32_t image_rows,
+                  int32_t image_cols, const smx_problem_desc *desc, size_t *operator_bytes, size_t *problem_bytes);
 
 /*
  * Create a problem on an operator.  Validates and copies the descriptor's
@@ -392,18 +414,23 @@ int smx_set_fused(smx_problem *p, int32_t mode);
 /* Pin the launch shape of the fused pass instead of the default or the
  * autotuner's choice: lanes per row (8, 16, 32), entries per load (4, 8) and
  * cap: 0 to read a row's entries again for the scatter, or 256/(lpr*vec) (16
- * or 32 lanes only) to keep 256 entries of each row in registers.  Results
- * do not depend on the shape beyond float64 summation order.  Errors:
- * SMX_ESTATE when the problem has no fused pass, SMX_EINVAL for another
- * shape. */
-int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap);
+ * or 32 lanes only) to keep 256 entries of each row in registers.  With
+ * z_in_lds != 0 (8 or 16 lanes, cap = 256/(lpr*vec), problems whose n is at
+ * most about 20k): every workgroup first copies the whole point z into LDS
+ * beside a float32 copy of y and gathers from there instead of from memory.
+ * Results do not depend on the shape beyond floating-point summation order.
+ * Errors: SMX_ESTATE when the problem has no fused pass, SMX_EINVAL for
+ * another shape. */
+int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap, int32_t z_in_lds);
 
 /* Why each slice stopped (reason[B], SMX_STOP_*; 0 while it runs).
  * Synchronises. */
 int smx_stop_status(smx_problem *p, int32_t *reason);
 
-/* JSON description of the launch shapes in use (NUL-terminated, truncated to
- * cap bytes); *need (if non-NULL) receives the full size. */
+/* JSON description of the launch shapes in use and of the device bytes the
+ * problem ("device_bytes") and its operator ("operator_bytes") hold
+ * (NUL-terminated, truncated to cap bytes); *need (if non-NULL) receives the
+ * full size. */
 int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need);
 
 /* Mean device time (milliseconds) per launch of the two passes (with the

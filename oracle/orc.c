@@ -91,8 +91,8 @@ typedef struct {
     int32_t n_red, restart_every;
     int32_t basic;          /* ORC_BASIC_*: the feasibility-seeking step */
     const double *col_nnz;  /* n, nonzeros per column for DROP, or NULL to count them from val */
-    /* stopping rules (Section 2.2 and the superiorized variant of Section
-     * 2.2.1; the variance rule of Section 2.3.2); stop_on = 0 disables all */
+    /* stopping rules (Section 2.2.1 and the superiorized variant of Section
+     * 2.2.3; the variance rule of Section 2.3.2); stop_on = 0 disables all */
     int32_t stop_on;
     int32_t stop_n;      /* N: consecutive iterations with a small proximity change */
     int32_t stop_max;    /* N_max (0: none) */
@@ -560,9 +560,9 @@ void orc_gradient(const orc_problem *P, const double *x, double *g)
  * objective at x^k, objective after the phase, trials and accepted trials.
  */
 /*
- * Stopping rules, checked when P->stop_on (Section 2.2: P <= P*, or the
+ * Stopping rules, checked when P->stop_on (Section 2.2.1: P <= P*, or the
  * relative proximity change |P^{k+1} - P^k| / max{1, P^k} below Delta P* for
- * N consecutive iterations, or N_max iterations; Section 2.2.1: a superiorized
+ * N consecutive iterations, or N_max iterations; Section 2.2.3: a superiorized
  * run stops when one of the two proximity rules holds and the relative change
  * of the objective |f^{k+1} - f^k| / max{1, f^k}, f^k = f(x^k), is below
  * Delta f*; Section 2.3.2: the variance of omega_i = ||x^i - x^{i-1}|| /

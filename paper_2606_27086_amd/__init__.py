@@ -35,6 +35,7 @@ EXPORTS = [
     "smx_operator_create_image",
     "smx_operator_destroy",
     "smx_operator_footprint",
+    "smx_footprint",
     "smx_problem_create",
     "smx_problem_destroy",
     "smx_create",
@@ -178,6 +179,8 @@ def lib() -> C.CDLL:
     L.smx_operator_create_image.argtypes = [C.POINTER(Csr), i32, i32, i32, i32, vp, C.POINTER(vp)]
     L.smx_operator_destroy.argtypes = [vp]
     L.smx_operator_footprint.argtypes = [i64, i64, i64, i32, i32, C.POINTER(C.c_size_t)]
+    L.smx_footprint.argtypes = [i64, i64, i64, i32, i32, i32, i32, C.POINTER(ProblemDesc), C.POINTER(C.c_size_t),
+                                C.POINTER(C.c_size_t)]
     L.smx_problem_create.argtypes = [vp, C.POINTER(ProblemDesc), vp, C.POINTER(vp)]
     L.smx_problem_destroy.argtypes = [vp]
     L.smx_create.argtypes = [C.POINTER(Csr), i32, C.POINTER(ProblemDesc), vp, C.POINTER(vp)]
@@ -200,7 +203,7 @@ def lib() -> C.CDLL:
     L.smx_slot_get_x.argtypes = [vp, i32, vp, i32]
     L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.smx_set_fused.argtypes = [vp, i32]
-    L.smx_set_fused_shape.argtypes = [vp, i32, i32, i32]
+    L.smx_set_fused_shape.argtypes = [vp, i32, i32, i32, i32]
     L.smx_stop_status.argtypes = [vp, vp]
     for name in EXPORTS:
         if name != "smx_last_error":
@@ -286,6 +289,53 @@ def footprint(m, n, nnz, storage="f32", keep_f32=True) -> int:
     return int(b.value)
 
 
+def _desc(B, lower, upper, weights, box_lo, box_hi, linear_c, lam=1.0, obj=OBJ_NONE, tv_rows=0, tv_cols=0,
+          tv_eps=0.0, gamma=1.0, alpha=0.99, n_red=1, restart_every=0, max_trials=100, refine_iters=-1,
+          history_cap=0, basic=0, stop=None, dvc=None):
+    """The problem descriptor (device pointers or None for the arrays) and the
+    dose-volume table it points to (kept alive by the caller)."""
+    d = ProblemDesc(
+        B=int(B), lower=lower, upper=upper, weights=weights, box_lo=box_lo, box_hi=box_hi, lam=float(lam),
+        obj_kind=int(obj), tv_rows=int(tv_rows), tv_cols=int(tv_cols), tv_eps=float(tv_eps), linear_c=linear_c,
+        gamma=float(gamma), alpha=float(alpha), n_red=int(n_red), restart_every=int(restart_every),
+        max_trials=int(max_trials), refine_iters=int(refine_iters), history_cap=int(history_cap), on_device=1,
+        basic=int(basic),
+    )
+    if stop is not None:  # stopping rules: prox, dprox, n, max_iters, dobj, var
+        d.stop_on = 1
+        d.stop_n = int(stop.get("n", 5))
+        d.stop_max_iters = int(stop.get("max_iters", 0))
+        d.stop_prox = float(stop.get("prox", 1e-6))
+        d.stop_dprox = float(stop.get("dprox", 1e-8))
+        d.stop_dobj = float(stop.get("dobj", 1e-6))
+        d.stop_var = float(stop.get("var", 0.0))
+    tab = None
+    if dvc:
+        tab = (DvcC * len(dvc))()
+        for i, g in enumerate(dvc):
+            tab[i] = DvcC(row_begin=int(g["row_begin"]), row_end=int(g["row_end"]), sense=int(g["sense"]),
+                          fraction=float(g["fraction"]), dose=float(g["dose"]))
+        d.n_dvc = len(dvc)
+        d.dvc = C.cast(tab, C.POINTER(DvcC))
+    return d, tab
+
+
+def problem_footprint(m, n, nnz, storage="f32", keep_f32=True, B=1, image=None, **params) -> tuple:
+    """(operator bytes, problem bytes) the library would allocate for an
+    operator of this shape (image = (rows, cols): an image operator) and a
+    problem with these Problem keyword arguments (bands and other arrays are
+    not needed: only sizes count), on the current device, without allocating
+    anything."""
+    keys = ("lam", "obj", "tv_rows", "tv_cols", "tv_eps", "gamma", "alpha", "n_red", "restart_every", "max_trials",
+            "refine_iters", "history_cap", "basic", "stop", "dvc")
+    d, tab = _desc(B, None, None, None, None, None, None, **{k: v for k, v in params.items() if k in keys})
+    ob, pb = C.c_size_t(), C.c_size_t()
+    ir, ic = (0, 0) if image is None else (int(image[0]), int(image[1]))
+    check(lib().smx_footprint(int(m), int(n), int(nnz), STORE[storage], 1 if keep_f32 else 0, ir, ic, C.byref(d),
+                              C.byref(ob), C.byref(pb)))
+    return int(ob.value), int(pb.value)
+
+
 class Problem:
     """Band+box problem with B slices on an :class:`Operator`."""
 
@@ -310,28 +360,10 @@ class Problem:
         t_blo = _dev(box_lo, torch.float32, device)
         t_bhi = _dev(box_hi, torch.float32, device)
         t_c = _dev(linear_c, torch.float32, device)
-        d = ProblemDesc(
-            B=self.B, lower=_ptr(t_lo), upper=_ptr(t_up), weights=_ptr(t_w), box_lo=_ptr(t_blo),
-            box_hi=_ptr(t_bhi), lam=float(lam), obj_kind=int(obj), tv_rows=int(tv_rows), tv_cols=int(tv_cols),
-            tv_eps=float(tv_eps), linear_c=_ptr(t_c), gamma=float(gamma), alpha=float(alpha), n_red=int(n_red),
-            restart_every=int(restart_every), max_trials=int(max_trials), refine_iters=int(refine_iters),
-            history_cap=int(history_cap), on_device=1, basic=int(basic),
-        )
-        if stop is not None:  # stopping rules: prox, dprox, n, max_iters, dobj, var
-            d.stop_on = 1
-            d.stop_n = int(stop.get("n", 5))
-            d.stop_max_iters = int(stop.get("max_iters", 0))
-            d.stop_prox = float(stop.get("prox", 1e-6))
-            d.stop_dprox = float(stop.get("dprox", 1e-8))
-            d.stop_dobj = float(stop.get("dobj", 1e-6))
-            d.stop_var = float(stop.get("var", 0.0))
-        if dvc:
-            tab = (DvcC * len(dvc))()
-            for i, g in enumerate(dvc):
-                tab[i] = DvcC(row_begin=int(g["row_begin"]), row_end=int(g["row_end"]), sense=int(g["sense"]),
-                              fraction=float(g["fraction"]), dose=float(g["dose"]))
-            d.n_dvc = len(dvc)
-            d.dvc = C.cast(tab, C.POINTER(DvcC))
+        d, self._dvc_tab = _desc(self.B, _ptr(t_lo), _ptr(t_up), _ptr(t_w), _ptr(t_blo), _ptr(t_bhi), _ptr(t_c),
+                                 lam=lam, obj=obj, tv_rows=tv_rows, tv_cols=tv_cols, tv_eps=tv_eps, gamma=gamma,
+                                 alpha=alpha, n_red=n_red, restart_every=restart_every, max_trials=max_trials,
+                                 refine_iters=refine_iters, history_cap=history_cap, basic=basic, stop=stop, dvc=dvc)
         self.history_cap = int(history_cap)
         self.obj = int(obj)
         h = C.c_void_p()
@@ -467,9 +499,9 @@ class Problem:
         check(lib().smx_stop_status(self.handle, r.ctypes.data))
         return r
 
-    def set_fused_shape(self, lpr: int, vec: int, cap: int):
+    def set_fused_shape(self, lpr: int, vec: int, cap: int, z_in_lds: bool = False):
         """Pin the fused pass's launch shape (see smx_set_fused_shape)."""
-        check(lib().smx_set_fused_shape(self.handle, int(lpr), int(vec), int(cap)))
+        check(lib().smx_set_fused_shape(self.handle, int(lpr), int(vec), int(cap), 1 if z_in_lds else 0))
 
     def fused_in_use(self) -> bool:
         d = self.describe()
@@ -496,6 +528,17 @@ class Problem:
             pass
 
 
+def workload_kwargs(w, history_cap: int = 0, refine_iters: int = -1) -> dict:
+    """Problem keyword arguments of a :class:`workloads.Workload`."""
+    return dict(
+        lower=w.lower, upper=w.upper, box_lo=w.box_lo, box_hi=w.box_hi, weights=w.weights, lam=w.lam, obj=w.obj,
+        tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
+        n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
+        refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0), stop=getattr(w, "stop", None),
+        dvc=getattr(w, "dvc", None),
+    )
+
+
 def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device="cuda", op: Operator = None,
                           refine_iters: int = -1, fused: bool = True, **overrides) -> Problem:
     """Build operator + problem for a :class:`workloads.Workload` (all slices);
@@ -503,13 +546,7 @@ def problem_from_workload(w, storage: str = "f32", history_cap: int = 0, device=
     if op is None:
         op = Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage=storage, device=device,
                       image=getattr(w, "image", None))
-    kw = dict(
-        lower=w.lower, upper=w.upper, box_lo=w.box_lo, box_hi=w.box_hi, weights=w.weights, lam=w.lam, obj=w.obj,
-        tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
-        n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
-        refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0), stop=getattr(w, "stop", None),
-        dvc=getattr(w, "dvc", None),
-    )
+    kw = workload_kwargs(w, history_cap, refine_iters)
     kw.update(overrides)
     p = Problem(op, device=device, **kw)
     if not fused:

@@ -224,7 +224,18 @@ struct smx_operator {
         return T;
     }
     std::atomic<int> refs{1};
-    size_t bytes = 0;
+    size_t bytes = 0; // device bytes of every buffer above (device_bytes() after creation)
+    size_t device_bytes() const
+    {
+        size_t t = 0;
+        for (const DevLayout *L : {&csr, &csc, &tiles})
+            for (const DBuf *b : {&L->ptr, &L->idx, &L->val32, &L->val16, &L->packed, &L->rowblk, &L->idx16})
+                t += b->bytes;
+        for (const DBuf *b : {&panel_ptr, &panel_idx16, &panel_packed, &q32, &q16, &zcol, &t_tcol, &t_pptr, &t_rptr,
+                              &t_rlist, &t_idx16})
+            t += b->bytes;
+        return t;
+    }
     int lp_kind() const { return storage == SMX_STORE_BF16 ? VK_BF16 : (storage == SMX_STORE_F16 ? VK_F16 : VK_F32); }
 };
 
@@ -315,6 +326,17 @@ struct smx_problem {
     size_t ev_used = 0;
     double t1_ms = 0, t2_ms = 0;
     int64_t t_launches = 0;
+    // device bytes of every buffer the problem owns (the plan of problem_plan_bytes)
+    size_t device_bytes() const
+    {
+        size_t t = 0;
+        for (const DBuf *b : {&x, &g, &c, &lower, &upper, &box_lo, &box_hi, &lin_c, &w, &D32, &D16, &st, &qout,
+                              &part_pass, &part_query, &part_phase, &part_trial[0], &part_trial[1], &h_prox, &h_fs,
+                              &h_fe, &h_tr, &h_ac, &ypart, &S32, &S16, &ybuf, &ybuf32, &part_y, &part_q, &ypanel,
+                              &xprev, &part_var, &dvc_dose, &dvc_key, &dvc_hist, &dvc_sel, &dvc_part})
+            t += b->bytes;
+        return t;
+    }
     ~smx_problem()
     {
         for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -542,6 +564,32 @@ void upload_tiles(smx_operator *op, TileHost &T, int lp, hipStream_t s)
     }
 }
 
+// Upper bound on the device bytes of an operator with m rows, n columns and
+// nnz entries (lp: a reduced-precision copy, f32: the float32 values kept;
+// image_rows x image_cols > 0: an image operator with the tile layout): every
+// row and column padded by kRowAlign - 1 entries, row blocks at one per row,
+// tiles as small as the smallest tile edge, and each tile's row list as long
+// as its entries.
+size_t operator_bound(int64_t m, int64_t n, int64_t nnz, bool lp, bool f32, int64_t image_rows, int64_t image_cols)
+{
+    const int64_t s1 = nnz + (kRowAlign - 1) * m, s2 = nnz + (kRowAlign - 1) * n;
+    size_t b = layout_bytes(m, s1, f32, lp, lp && n <= 65536, n <= 65536) +
+               layout_bytes(n, s2, f32, lp, lp && m <= 65536, m <= 65536) +
+               size_t(m + 2) * 4 + size_t(n + 2) * 4 +              // row blocks of both layouts
+               size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0)) + // row norms
+               size_t(n) * 4;                                    // DROP column factors
+    if (m > kLdsPassFloats) { // row panels of the column copy: offsets (and 16-bit rows, packed entries)
+        const int64_t np = (m + kLdsPassFloats - 1) / kLdsPassFloats;
+        b += size_t(np + 1) * size_t(n) * 4 + (m > 65536 ? size_t(s2) * (2 + (lp ? 4 : 0)) : 0);
+    }
+    if (image_rows > 0 && image_cols > 0) { // tile layout (tiles of edge 4 at the least)
+        const int64_t T = ((image_rows + 3) / 4) * ((image_cols + 3) / 4);
+        b += size_t(n + 1) * 4 + size_t(n) * 4 + 2 * size_t(T + 1) * 4 + size_t(nnz) * 4 +
+             size_t(s2) * ((f32 ? 6 : 0) + (lp ? 4 : 0));
+    }
+    return b;
+}
+
 int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStream_t s, smx_operator **out,
                     int32_t img_rows = 0, int32_t img_cols = 0)
 {
@@ -659,15 +707,7 @@ int create_operator(const smx_csr *A, int32_t storage, int32_t keep_f32, hipStre
         hip_check(launch_rownorm(op->csr.view(fmt), fmt, op->q16.as<double>(), s), "row norms (reduced precision)");
     }
     hip_check(hipStreamSynchronize(s), "operator setup");
-    op->bytes = layout_bytes(m, op->csr.slots, op->has_f32, lp != VK_F32, op->csr.packed.p != nullptr,
-                             op->csr.idx16.p != nullptr) +
-                layout_bytes(n, op->csc.slots, op->has_f32, lp != VK_F32, op->csc.packed.p != nullptr,
-                             op->csc.idx16.p != nullptr) +
-                size_t(m) * 8 * ((op->has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0)) + size_t(n) * 4;
-    if (op->has_tiles())
-        op->bytes += size_t(op->n + 1) * 4 + size_t(op->tiles.slots) * ((op->has_f32 ? 6 : 0) + (lp != VK_F32 ? 4 : 0)) +
-                     size_t(op->n) * 4 + size_t(op->t_rptr.bytes / 4 + op->t_rlist.bytes / 4 + op->t_ntiles + 1) * 4;
-    op->bytes += op->panel_ptr.bytes + op->panel_idx16.bytes + op->panel_packed.bytes; // row panels (0 when absent)
+    op->bytes = op->device_bytes();
     *out = op.release();
     return SMX_OK;
 }
@@ -930,7 +970,7 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // accumulator type as `base`): 8/16/32 lanes per row with 4 or 8 entries per
 // load re-reading the entries for the scatter, and the register-cached shapes
 // (256 entries of a row in registers).
-std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
+std::vector<FusedCfg> fused_candidates(const FusedCfg &base, int64_t n)
 {
     std::vector<FusedCfg> out;
     for (int lpr : {8, 16, 32})
@@ -939,13 +979,166 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
             t.lpr = lpr;
             t.vec = vec;
             t.cap = 0;
+            t.zl = 0;
             out.push_back(t);
             if (lpr >= 16) {
                 t.cap = 256 / (lpr * vec);
                 out.push_back(t);
             }
         }
+    if (fused_zl_lds_bytes(n) <= fused_lds_limit()) // z in LDS beside a float32 y
+        for (int lpr : {8, 16})
+            for (int vec : {4, 8}) {
+                FusedCfg t = base;
+                t.lpr = lpr;
+                t.vec = vec;
+                t.cap = 256 / (lpr * vec);
+                t.acc64 = 0;
+                t.zl = 1;
+                out.push_back(t);
+            }
     return out;
+}
+
+// The dose-volume constraints of a descriptor as the kernels' table
+// (validated against m rows).
+int build_dvc_table(const smx_problem_desc *d, int64_t m, DvcTable &dt)
+{
+    dt = DvcTable{};
+    if (d->n_dvc < 0 || d->n_dvc > kMaxDvc || (d->n_dvc > 0 && !d->dvc))
+        return fail(SMX_EINVAL, "n_dvc must be in 0..%d with a table", kMaxDvc);
+    dt.n = d->n_dvc;
+    for (int g = 0; g < dt.n; ++g) {
+        const smx_dvc &G = d->dvc[g];
+        if (!(G.row_begin >= 0 && G.row_begin < G.row_end && G.row_end <= m))
+            return fail(SMX_EINVAL, "dose-volume constraint %d: rows [%lld, %lld) not a nonempty block of [0, %lld)", g,
+                        (long long)G.row_begin, (long long)G.row_end, (long long)m);
+        if (g > 0 && G.row_begin != d->dvc[g - 1].row_end)
+            return fail(SMX_EINVAL, "dose-volume constraint %d does not start where constraint %d ends", g, g - 1);
+        if (G.sense != SMX_DVC_MAX && G.sense != SMX_DVC_MIN)
+            return fail(SMX_EINVAL, "dose-volume constraint %d: unknown sense %d", g, G.sense);
+        if (!(G.fraction >= 0.0 && G.fraction <= 1.0))
+            return fail(SMX_EINVAL, "dose-volume constraint %d: fraction must be in [0, 1]", g);
+        if (!std::isfinite(G.dose)) return fail(SMX_EINVAL, "dose-volume constraint %d: dose must be finite", g);
+        if (G.row_end - G.row_begin > (int64_t)0xFFFFFFFFll)
+            return fail(SMX_EINVAL, "dose-volume constraint %d: too many rows", g);
+        const int64_t N = G.row_end - G.row_begin;
+        const double kv = (G.sense == SMX_DVC_MAX) ? std::floor(G.fraction * (double)N) : std::ceil(G.fraction * (double)N);
+        dt.begin[g] = G.row_begin;
+        dt.end[g] = G.row_end;
+        dt.k[g] = (long long)std::min<double>(std::max(kv, 0.0), (double)N);
+        dt.dose[g] = G.dose;
+        dt.sense[g] = G.sense == SMX_DVC_MAX ? 0 : 1;
+        dt.blk_begin[g + 1] = dt.blk_begin[g] + (int)((N + kDvcChunk - 1) / kDvcChunk);
+    }
+    if (dt.n > 0) {
+        dt.nblk = dt.blk_begin[dt.n];
+        dt.lo = dt.begin[0];
+        dt.span = dt.end[dt.n - 1] - dt.begin[0];
+        if (dt.nblk > 65535) return fail(SMX_EINVAL, "dose-volume constraints hold too many rows");
+    }
+    return SMX_OK;
+}
+
+// Launch shape of the fused single pass for a problem of n unknowns and B
+// slices on the current device, or false where it has none: one slice, no
+// dose-volume rows (their ranking precedes c), an LDS copy of y that fits
+// (float64 if it can, else float32), one or two workgroups per CU as the LDS
+// allows.
+bool fused_plan(int64_t n, int B, int n_dvc, FusedCfg &c, size_t &lds_bytes)
+{
+    if (B != 1 || n_dvc > 0) return false;
+    const size_t lim = fused_lds_limit();
+    int acc64 = -1;
+    if (fused_lds_bytes(n, 1) <= lim) acc64 = 1;
+    else if (fused_lds_bytes(n, 0) <= lim) acc64 = 0;
+    if (acc64 < 0) return false;
+    int dev = 0, cus = 0, lds_cu = 0;
+    hip_check(hipGetDevice(&dev), "device");
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        lds_cu = 0;
+    lds_bytes = fused_lds_bytes(n, acc64);
+    const int per_cu = (lds_cu > 0 && size_t(lds_cu) >= 2 * (lds_bytes + 1024)) ? 2 : 1;
+    c = FusedCfg{};
+    c.vec = 4;
+    c.cap = 0;
+    c.grid = std::max(1, std::min(cus * per_cu, kMaxPassGrid));
+    c.acc64 = acc64;
+    return true;
+}
+
+// Whether one-slice problems on the current device get the LDS-staged passes
+// (and, on operators with row panels, the panel pass 2's per-panel sums).
+bool lds_passes_available(int B) { return B == 1 && fused_lds_limit() >= sizeof(float) * size_t(kLdsPassFloats); }
+
+// Row panels of the column copy an operator with m rows holds.
+int64_t panel_count(int64_t m) { return m > kLdsPassFloats ? (m + kLdsPassFloats - 1) / kLdsPassFloats : 0; }
+
+// Device bytes of every buffer create_problem allocates for an operator with
+// m rows, n columns, float32 values (has_f32) and/or the reduced-precision
+// kind lp, and the descriptor d (whose fields the sizes depend on are
+// validated by the caller), in the order it allocates them.  DBuf takes 256
+// bytes for an empty buffer.
+size_t problem_plan_bytes(int64_t m, int64_t n, bool has_f32, int lp, const smx_problem_desc *d, const DvcTable &dt)
+{
+    const size_t B = size_t(d->B), M = size_t(m), N = size_t(n);
+    size_t t = 0;
+    auto add = [&t](size_t b) { t += (b == 0) ? 256 : b; };
+    add(4 * M * B); // lower
+    add(4 * M * B); // upper
+    add(4 * N);     // box_lo
+    add(4 * N);     // box_hi
+    add(8 * M);     // weights
+    if (d->obj_kind == SMX_OBJ_LINEAR) add(4 * N);
+    add(4 * N * B); // x
+    add(4 * N * B); // g
+    add(4 * M * B); // c
+    add(sizeof(SliceState) * 2 * B);
+    if (d->stop_on && d->stop_var > 0.0) {
+        add(4 * N * B);
+        add(8 * 2 * 256 * B);
+    }
+    const int kinds = (has_f32 ? 1 : 0) + (lp != VK_F32 ? 1 : 0);
+    for (int k = 0; k < kinds; ++k) add(4 * M); // D
+    if (d->basic == SMX_BASIC_CQ || d->basic == SMX_BASIC_EMR)
+        for (int k = 0; k < kinds; ++k) add(4 * M); // step weights
+    if (d->basic == SMX_BASIC_EL || d->basic == SMX_BASIC_EMR) {
+        add(8 * N * B);
+        if (d->basic == SMX_BASIC_EMR) add(4 * N * B);
+        add(8 * size_t(kMaxPassGrid) * B);
+        add(8 * size_t(kMaxPassGrid) * B);
+    }
+    if (dt.n > 0) {
+        add(8 * size_t(dt.span) * B);
+        add(8 * size_t(dt.span) * B);
+        add(sizeof(unsigned) * size_t(kDvcBins) * dt.n * B);
+        add(sizeof(DvcSel) * dt.n * B);
+        add(8 * size_t(dt.nblk) * B);
+    }
+    FusedCfg fc;
+    size_t lds = 0;
+    if (fused_plan(n, d->B, dt.n, fc, lds)) add(lds * size_t(fc.grid)); // partial vectors of y
+    if (lds_passes_available(d->B) && panel_count(m) > 0) add(8 * size_t(panel_count(m)) * N);
+    PertParams pp{};
+    pp.obj = d->obj_kind;
+    pp.B = d->B;
+    pp.n = n;
+    pp.tv_rows = d->tv_rows;
+    pp.tv_cols = d->tv_cols;
+    const size_t pgrid = size_t(phase_grid(pp)), trials = size_t(std::max(1, d->max_trials));
+    add(8 * size_t(kMaxPassGrid) * B); // pass partials
+    add(8 * size_t(kMaxPassGrid) * B); // query partials
+    add(8 * pgrid * B * 2);
+    add(8 * pgrid * B * trials);
+    add(8 * pgrid * B * trials);
+    add(8 * 2 * B); // query output
+    if (d->history_cap > 0) {
+        const size_t hc = size_t(d->history_cap) * B;
+        for (int k = 0; k < 3; ++k) add(8 * hc);
+        for (int k = 0; k < 2; ++k) add(4 * hc);
+    }
+    return t;
 }
 
 // Fused single pass for one slice when an LDS copy of y fits (float64 if it
@@ -953,35 +1146,18 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base)
 // workgroups per CU, as many as the LDS allows.
 void setup_fused(smx_problem *p)
 {
-    // the dose-volume rows need their ranking before c: two passes (the
-    // extrapolated steps use the fused pass with a deferred apply)
-    if (p->B != 1 || p->dvc.n > 0) return;
-    const size_t lim = fused_lds_limit();
-    int acc64 = -1;
-    if (fused_lds_bytes(p->n, 1) <= lim) acc64 = 1;
-    else if (fused_lds_bytes(p->n, 0) <= lim) acc64 = 0;
-    if (acc64 < 0) return;
-    int dev = 0, cus = 0, lds_cu = 0;
-    hip_check(hipGetDevice(&dev), "device");
-    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
-    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
-        lds_cu = 0;
-    const size_t bytes = fused_lds_bytes(p->n, acc64);
-    const int per_cu = (lds_cu > 0 && size_t(lds_cu) >= 2 * (bytes + 1024)) ? 2 : 1;
+    FusedCfg c;
+    size_t bytes = 0;
+    if (!fused_plan(p->n, p->B, p->dvc.n, c, bytes)) return;
     const DevLayout &L = p->op->csr;
     const double mean = L.rows > 0 ? double(L.slots) / double(L.rows) : 0.0;
-    FusedCfg c;
     c.lpr = mean <= 64 ? 8 : (mean <= 256 ? 16 : 32);
-    c.vec = 4;
-    c.cap = 0;
-    c.grid = std::max(1, std::min(cus * per_cu, kMaxPassGrid));
-    c.acc64 = acc64;
     bool any = false;
     for (int vk = 0; vk < 3; ++vk) {
         const bool present = (vk == VK_F32) ? p->op->has_f32 : (vk == p->op->lp_kind());
         if (!present) continue;
         bool ok = true;
-        for (const FusedCfg &t : fused_candidates(c))
+        for (const FusedCfg &t : fused_candidates(c, p->n))
             if (prepare_fused(t, fused_fmt(p, vk), p->n) != hipSuccess) ok = false;
         (void)hipGetLastError();
         p->fused_ok[vk] = p->fused[vk] = ok;
@@ -1029,38 +1205,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
                         d->stop_var};
     }
     DvcTable dt{};
-    if (d->n_dvc < 0 || d->n_dvc > kMaxDvc || (d->n_dvc > 0 && !d->dvc))
-        return fail(SMX_EINVAL, "n_dvc must be in 0..%d with a table", kMaxDvc);
-    dt.n = d->n_dvc;
-    for (int g = 0; g < dt.n; ++g) {
-        const smx_dvc &G = d->dvc[g];
-        if (!(G.row_begin >= 0 && G.row_begin < G.row_end && G.row_end <= m))
-            return fail(SMX_EINVAL, "dose-volume constraint %d: rows [%lld, %lld) not a nonempty block of [0, %lld)", g,
-                        (long long)G.row_begin, (long long)G.row_end, (long long)m);
-        if (g > 0 && G.row_begin != d->dvc[g - 1].row_end)
-            return fail(SMX_EINVAL, "dose-volume constraint %d does not start where constraint %d ends", g, g - 1);
-        if (G.sense != SMX_DVC_MAX && G.sense != SMX_DVC_MIN)
-            return fail(SMX_EINVAL, "dose-volume constraint %d: unknown sense %d", g, G.sense);
-        if (!(G.fraction >= 0.0 && G.fraction <= 1.0))
-            return fail(SMX_EINVAL, "dose-volume constraint %d: fraction must be in [0, 1]", g);
-        if (!std::isfinite(G.dose)) return fail(SMX_EINVAL, "dose-volume constraint %d: dose must be finite", g);
-        if (G.row_end - G.row_begin > (int64_t)0xFFFFFFFFll)
-            return fail(SMX_EINVAL, "dose-volume constraint %d: too many rows", g);
-        const int64_t N = G.row_end - G.row_begin;
-        const double kv = (G.sense == SMX_DVC_MAX) ? std::floor(G.fraction * (double)N) : std::ceil(G.fraction * (double)N);
-        dt.begin[g] = G.row_begin;
-        dt.end[g] = G.row_end;
-        dt.k[g] = (long long)std::min<double>(std::max(kv, 0.0), (double)N);
-        dt.dose[g] = G.dose;
-        dt.sense[g] = G.sense == SMX_DVC_MAX ? 0 : 1;
-        dt.blk_begin[g + 1] = dt.blk_begin[g] + (int)((N + kDvcChunk - 1) / kDvcChunk);
-    }
-    if (dt.n > 0) {
-        dt.nblk = dt.blk_begin[dt.n];
-        dt.lo = dt.begin[0];
-        dt.span = dt.end[dt.n - 1] - dt.begin[0];
-        if (dt.nblk > 65535) return fail(SMX_EINVAL, "dose-volume constraints hold too many rows");
-    }
+    if (const int rc = build_dvc_table(d, m, dt); rc != SMX_OK) return rc;
     const bool dev = d->on_device != 0;
     std::vector<float> lo = fetch(d->lower, m * B, dev), up = fetch(d->upper, m * B, dev);
     for (int64_t i = 0; i < m * B; ++i) {
@@ -1224,7 +1369,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         p->dvc_part.alloc(sizeof(double) * size_t(dt.nblk) * B, "dose-volume partials");
     }
     setup_fused(p.get());
-    if (B == 1 && fused_lds_limit() >= sizeof(float) * size_t(kLdsPassFloats)) { // the LDS-staged pass 1
+    if (lds_passes_available(B)) { // the LDS-staged pass 1
         int dev = 0, cus = 0;
         hip_check(hipGetDevice(&dev), "device");
         hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "device attribute");
@@ -1469,7 +1614,7 @@ int autotune_impl(smx_problem *p, int reps)
             if (p->fused_ok[vk] && p->fused_mode == 1) {
                 double bestf = 1e30;
                 FusedCfg bestfc = p->fcfg[vk];
-                for (const FusedCfg &c : fused_candidates(p->fcfg[vk])) {
+                for (const FusedCfg &c : fused_candidates(p->fcfg[vk], n)) {
                     auto launch = [&]() {
                         hip_check(launch_fused(c, view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), n, xs.as<float>(),
                                                p->lower.as<float>(), p->upper.as<float>(), rw, st0,
@@ -1486,8 +1631,8 @@ int autotune_impl(smx_problem *p, int reps)
                     hip_check(hipEventRecord(e1, s), "event");
                     const double t = elapsed();
                     if (tune_log)
-                        fprintf(stderr, "smx tune: kind %d fused lpr %d vec %d cap %d grid %d: %.2f us\n", vk, c.lpr, c.vec,
-                                c.cap, c.grid, t * 1e3);
+                        fprintf(stderr, "smx tune: kind %d fused lpr %d vec %d cap %d zl %d grid %d: %.2f us\n", vk, c.lpr,
+                                c.vec, c.cap, c.zl, c.grid, t * 1e3);
                     if (t < bestf) {
                         bestf = t;
                         bestfc = c;
@@ -1534,13 +1679,13 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         if (vk != VK_F32 && p->op->lp_kind() != vk) continue;
         char tmp[768];
         const PassCfg &a = p->cfg1[vk], &b = p->cfg2[vk];
-        char fz[224];
+        char fz[320];
         if (p->fused_ok[vk]) {
             const FusedCfg &f = p->fcfg[vk];
             snprintf(fz, sizeof fz,
-                     "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"cap\": %d, \"grid\": %d, \"acc\": \"%s\", "
-                     "\"format\": \"%s\"}",
-                     p->fused[vk] ? "true" : "false", f.lpr, f.vec, f.cap, f.grid, f.acc64 ? "f64" : "f32",
+                     "{\"in_use\": %s, \"lpr\": %d, \"vec\": %d, \"cap\": %d, \"zl\": %d, \"grid\": %d, "
+                     "\"acc\": \"%s\", \"format\": \"%s\"}",
+                     p->fused[vk] ? "true" : "false", f.lpr, f.vec, f.cap, f.zl, f.grid, f.acc64 ? "f64" : "f32",
                      fmt_name(fused_fmt(p, vk)));
         } else {
             snprintf(fz, sizeof fz, "null");
@@ -1562,15 +1707,17 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
         out += tmp;
         first = false;
     }
-    char tail[320];
+    char tail[512];
     static const char *basics[5] = {"simult", "drop", "cq", "el", "emr"};
     char tiles[96] = "null";
     if (p->op->has_tiles())
         snprintf(tiles, sizeof tiles, "{\"count\": %d, \"rows\": %lld, \"slots\": %lld}", p->op->t_ntiles,
                  (long long)(p->op->t_rlist.bytes / 4), (long long)p->op->tiles.slots);
     snprintf(tail, sizeof tail,
-             ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\", \"dose_volume\": %d, \"tiles\": %s}",
-             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic], p->dvc.n, tiles);
+             ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\", \"dose_volume\": %d, \"tiles\": %s, "
+             "\"device_bytes\": %zu, \"operator_bytes\": %zu}",
+             p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic], p->dvc.n, tiles,
+             p->device_bytes(), p->op->device_bytes());
     out += tail;
     if (need) *need = out.size() + 1;
     if (buf && cap > 0) {
@@ -1631,18 +1778,45 @@ int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_stor
     if (!bytes) return fail(SMX_EINVAL, "NULL argument");
     if (m < 1 || n < 1 || nnz < 0) return fail(SMX_EINVAL, "invalid shape");
     if (value_storage < SMX_STORE_F32 || value_storage > SMX_STORE_F16) return fail(SMX_EINVAL, "unknown storage");
-    const bool lp = value_storage != SMX_STORE_F32;
-    const bool f32 = !lp || keep_f32;
-    // upper bound on padding: kRowAlign-1 entries per row and per column
-    const int64_t s1 = nnz + (kRowAlign - 1) * m, s2 = nnz + (kRowAlign - 1) * n;
-    *bytes = layout_bytes(m, s1, f32, lp, lp && n <= 65536, n <= 65536) +
-             layout_bytes(n, s2, f32, lp, lp && m <= 65536, m <= 65536) +
-             size_t(m) * 8 * ((f32 ? 1 : 0) + (lp ? 1 : 0)) + size_t(n) * 4;
-    if (m > kLdsPassFloats) { // row panels of the column copy: offsets (and 16-bit rows, packed entries)
-        const int64_t np = (m + kLdsPassFloats - 1) / kLdsPassFloats;
-        *bytes += size_t(np + 1) * size_t(n) * 4 + (m > 65536 ? size_t(s2) * (2 + (lp ? 4 : 0)) : 0);
-    }
+    *bytes = operator_bound(m, n, nnz, value_storage != SMX_STORE_F32, value_storage == SMX_STORE_F32 || keep_f32, 0, 0);
     return SMX_OK;
+}
+
+int smx_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32, int32_t image_rows,
+                  int32_t image_cols, const smx_problem_desc *desc, size_t *operator_bytes, size_t *problem_bytes)
+{
+    if (!operator_bytes || !problem_bytes) return fail(SMX_EINVAL, "NULL argument");
+    if ((image_rows != 0 || image_cols != 0) && (image_rows < 1 || image_cols < 1 || (int64_t)image_rows * image_cols != n))
+        return fail(SMX_EINVAL, "image %d x %d does not match n = %lld", image_rows, image_cols, (long long)n);
+    SMX_GUARD({
+        size_t ob = 0;
+        if (const int rc = smx_operator_footprint(m, n, nnz, value_storage, keep_f32, &ob); rc != SMX_OK) return rc;
+        if (image_rows > 0)
+            ob = operator_bound(m, n, nnz, value_storage != SMX_STORE_F32, value_storage == SMX_STORE_F32 || keep_f32,
+                                image_rows, image_cols);
+        size_t pb = 0;
+        if (desc) {
+            const smx_problem_desc *d = desc;
+            if (!(is_pow2(d->B) && d->B <= 32)) return fail(SMX_EINVAL, "B must be a power of two in 1..32 (got %d)", d->B);
+            if (d->basic < SMX_BASIC_SIMULT || d->basic > SMX_BASIC_EMR)
+                return fail(SMX_EINVAL, "unknown basic algorithm %d", d->basic);
+            if (d->obj_kind < SMX_OBJ_NONE || d->obj_kind > SMX_OBJ_L1)
+                return fail(SMX_EINVAL, "unknown objective %d", d->obj_kind);
+            if (d->obj_kind != SMX_OBJ_NONE && (d->max_trials < 1 || d->max_trials > 1024))
+                return fail(SMX_EINVAL, "max_trials must be in 1..1024 (got %d)", d->max_trials);
+            if (d->obj_kind == SMX_OBJ_TV2D && (d->tv_rows < 1 || d->tv_cols < 1 || (int64_t)d->tv_rows * d->tv_cols != n))
+                return fail(SMX_EINVAL, "TV image %d x %d does not match n = %lld", d->tv_rows, d->tv_cols, (long long)n);
+            if (d->history_cap < 0) return fail(SMX_EINVAL, "history_cap must be >= 0");
+            DvcTable dt{};
+            if (const int rc = build_dvc_table(d, m, dt); rc != SMX_OK) return rc;
+            const bool lp = value_storage != SMX_STORE_F32;
+            const int lk = value_storage == SMX_STORE_BF16 ? VK_BF16 : (value_storage == SMX_STORE_F16 ? VK_F16 : VK_F32);
+            pb = problem_plan_bytes(m, n, !lp || keep_f32 != 0, lk, d, dt);
+        }
+        *operator_bytes = ob;
+        *problem_bytes = pb;
+        return SMX_OK;
+    })
 }
 
 int smx_problem_create(smx_operator *op, const smx_problem_desc *desc, void *stream, smx_problem **out)
@@ -1976,7 +2150,7 @@ int smx_set_fused(smx_problem *p, int32_t mode)
     })
 }
 
-int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap)
+int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap, int32_t z_in_lds)
 {
     if (!p) return fail(SMX_EINVAL, "NULL problem");
     SMX_GUARD({
@@ -1986,14 +2160,14 @@ int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap)
         bool found = false;
         for (int vk = 0; vk < 3; ++vk) {
             if (!p->fused_ok[vk]) continue;
-            for (const FusedCfg &c : fused_candidates(p->fcfg[vk]))
-                if (c.lpr == lpr && c.vec == vec && c.cap == cap) {
+            for (const FusedCfg &c : fused_candidates(p->fcfg[vk], p->n))
+                if (c.lpr == lpr && c.vec == vec && c.cap == cap && c.zl == (z_in_lds ? 1 : 0)) {
                     p->fcfg[vk] = c;
                     found = true;
                 }
         }
         if (!found)
-            return fail(SMX_EINVAL, "unsupported fused shape lpr %d vec %d cap %d", lpr, vec, cap);
+            return fail(SMX_EINVAL, "unsupported fused shape lpr %d vec %d cap %d z_in_lds %d", lpr, vec, cap, z_in_lds);
         hip_check(hipStreamSynchronize(p->stream), "sync");
         for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
         p->graphs.clear();

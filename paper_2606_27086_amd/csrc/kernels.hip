@@ -690,7 +690,7 @@ __device__ inline int slice_runs(const SliceState &S)
 }
 
 // Stopping rules after a feasibility step that recorded proximity `prox`
-// (Section 2.2: P <= P*, or |P^{k+1} - P^k| / max{1, P^k} < Delta P* for N
+// (Section 2.2.1: P <= P*, or |P^{k+1} - P^k| / max{1, P^k} < Delta P* for N
 // consecutive iterations, or N_max iterations).  A superiorized run (a phase
 // ran, so f_start = f(x^k) is set) only notes whether a proximity rule held;
 // its objective condition is checked when the next phase opens.  The variance
@@ -1703,7 +1703,7 @@ __device__ inline void open_phase_state(SliceState &S, const PertParams &pp, dou
         S.f_start = S.f_cur = nan64();
         return;
     }
-    // superiorized stopping rule (Section 2.2.1): a proximity rule held at the
+    // superiorized stopping rule (Section 2.2.3): a proximity rule held at the
     // last iteration and |f(x^k) - f(x^{k-1})| / max{1, f(x^{k-1})} < Delta f*
     if (S.stop_on && S.feas_ok && !isnan(S.f_last) && fabs(f - S.f_last) / fmax(1.0, S.f_last) < S.stop_dobj) {
         S.stop_reason = STOP_SM;
@@ -2910,7 +2910,98 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
     return pass2_vec<F16Tag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
 }
 
+// Fused pass with the gathered vector in LDS.  The plain fused pass gathers
+// z_j through the vector memory path once per stored entry, about one
+// address per CU per clock, which bounds it on long operators.  Here each
+// workgroup (one per CU, 1024 threads) first copies all of z into LDS, beside
+// a float32 copy of y (2 x 4n bytes, n up to about 20k), and gathers from
+// there.  A group of LPR lanes keeps a row's first CAP*LPR*VEC = 256 entries
+// in registers for the scatter of c_i a_i (longer rows read the rest again),
+// lane l holding the chunk slots of lane (l + group) mod LPR, so that
+// neighbouring rows, which list the same columns in the same order, add into
+// different LDS words in one atomic instruction.  y leaves as one float32
+// partial vector per workgroup; k_fused_apply adds them in float64.
+template <int LPR, int VEC, int CAP, typename VT>
+__global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const float *__restrict__ x,
+                                                          const float *__restrict__ lower,
+                                                          const float *__restrict__ upper, RowW w,
+                                                          const SliceState *__restrict__ st,
+                                                          double *__restrict__ partials, float *__restrict__ ypart)
+{
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+    float *zl = reinterpret_cast<float *>(fused_lds);
+    float *y = zl + ((n + 3) & ~3);
+    __shared__ double lds[kFusedBlock / 64];
+    __shared__ int range[2];
+    constexpr int RPB = kFusedBlock / LPR;
+    constexpr int STEP = LPR * VEC;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const int slot = (lane + grp) & (LPR - 1);
+    const bool live = st[0].live != 0;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = 0.f;
+    if (live) stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
+    if (threadIdx.x == 0) { // an equal share of the stored entries
+        const long long total = A.ptr[A.rows];
+        range[0] = first_row_at(A.ptr, (int)A.rows, total * blockIdx.x / gridDim.x);
+        range[1] = first_row_at(A.ptr, (int)A.rows, total * (blockIdx.x + 1) / gridDim.x);
+    }
+    __syncthreads();
+    const int r0 = range[0], r1 = range[1];
+    double pacc[1] = {0.0};
+    if (live) {
+        for (int row = r0 + grp; row < r1; row += RPB) {
+            const int beg = A.ptr[row], end = A.ptr[row + 1];
+            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row];
+            RowRegs<VEC, CAP> R;
+            fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, R);
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc = fma((double)R.v[q][e], (double)zl[R.c[q][e]], acc);
+            const bool tail = end - beg > CAP * STEP;
+            if (tail)
+                for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
+                    float v[VEC];
+                    int c[VEC];
+                    Entries<VT, VEC>::load(A, p, v, c);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc = fma((double)v[e], (double)zl[c[e]], acc);
+                }
+            const double r = group_sum<LPR>(acc) * (double)A.vscale_inv;
+            const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+            const double dt = (double)d * t, ct = (double)sw * t;
+            if (lane == 0) pacc[0] += dt * t;
+            if (ct != 0.0) {
+                const double sc = ct * (double)A.vscale_inv;
+#pragma unroll
+                for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (R.v[q][e] != 0.f) atomicAdd(&y[R.c[q][e]], (float)(sc * (double)R.v[q][e]));
+                if (tail)
+                    for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
+                        float v[VEC];
+                        int c[VEC];
+                        Entries<VT, VEC>::load(A, p, v, c);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            if (v[e] != 0.f) atomicAdd(&y[c[e]], (float)(sc * (double)v[e]));
+                    }
+            }
+        }
+    }
+    block_sum<1, kFusedBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
+    if (!live) return;
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+    float *out = ypart + (long long)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
+}
+
 size_t fused_lds_bytes(int64_t n, int acc64) { return size_t(n) * (acc64 ? sizeof(double) : sizeof(float)); }
+
+size_t fused_zl_lds_bytes(int64_t n) { return 2 * size_t((n + 3) & ~int64_t(3)) * sizeof(float); }
 
 int fused_apply_grid(int64_t n) { return (int)grid_for(n, 64, 4096); }
 
@@ -2937,9 +3028,32 @@ struct FusedArgs {
 
 // prepare != 0: only raise the kernel's dynamic-LDS attribute (done outside
 // any stream capture, before the first launch of this shape)
+template <int LPR, typename VT, int VEC>
+hipError_t fused_zl_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
+{
+    constexpr int CAP = 256 / (LPR * VEC);
+    if constexpr (LPR > 16 || CAP < 1) {
+        return hipErrorInvalidValue;
+    } else {
+        if (cfg.cap != CAP) return hipErrorInvalidValue;
+        auto kern = k_fused_zl<LPR, VEC, CAP, VT>;
+        const size_t bytes = fused_zl_lds_bytes(a.n);
+        if (prepare)
+            return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kFusedBlock), bytes, s, *a.A, (int)a.n, a.x, a.lower, a.upper,
+                           a.w, a.st, a.partials, static_cast<float *>(a.ypart));
+        return hipGetLastError();
+    }
+}
+
 template <int LPR, typename VT, int VEC, typename AccT>
 hipError_t fused_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
 {
+    if (cfg.zl) {
+        if constexpr (sizeof(AccT) != sizeof(float)) return hipErrorInvalidValue; // float32 partials only
+        else return fused_zl_go<LPR, VT, VEC>(cfg, a, prepare, s);
+    }
     auto kern = k_fused<LPR, VEC, VT, AccT>;
     if (cfg.cap > 0) {
         // register-cached shapes hold CAP*LPR*VEC = 256 entries of a row; with

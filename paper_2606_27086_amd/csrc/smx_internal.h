@@ -190,6 +190,7 @@ struct FusedCfg {
                // registers (cap * lpr * vec = 256 entries)
     int grid;  // workgroups, each with an LDS copy of y
     int acc64; // 1: float64 LDS accumulators, 0: float32
+    int zl = 0; // 1: z staged in LDS beside a float32 y (k_fused_zl; acc64 = 0, cap = 256/(lpr*vec), lpr <= 16)
 };
 
 // Column layout grouped by image tiles (A^T for an operator whose unknowns
@@ -293,6 +294,8 @@ hipError_t launch_step_apply(int64_t n, int B, const double *y, float *x, const 
 // workgroup, and one partial vector of y = A^T c per workgroup in ypart
 // (grid x n, float64 or float32 by cfg.acc64).  lds_bytes: dynamic LDS it needs.
 size_t fused_lds_bytes(int64_t n, int acc64);
+// dynamic LDS of the fused pass with z in LDS (z and a float32 y)
+size_t fused_zl_lds_bytes(int64_t n);
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
                         const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
                         hipStream_t s);

@@ -6,9 +6,10 @@ run for K outer iterations.  The server keeps one *group* per operator: the
 operator on the device plus one multi-slot problem (capacity B slots, its own
 HIP stream).  Scheduling, all on the host:
 
-* admission by HBM footprint: a group is created only if its device bytes fit
-  in the budget next to the groups already resident; idle groups are evicted
-  when another operator needs the room;
+* admission by HBM footprint: a group is created only if its device bytes
+  (the library's allocation plan, ``smx_footprint``) fit in the budget next
+  to the groups already resident; idle groups are evicted when another
+  operator needs the room;
 * a request is admitted into its group when enough slots are free; its slices
   are loaded into free slots with a budget of K iterations
   (``smx_slot_load``), so each slot stops on the device at exactly K;
@@ -29,7 +30,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from . import Operator, Problem, footprint
+from . import Operator, Problem, problem_footprint
 
 
 @dataclass
@@ -66,15 +67,6 @@ class Request:
     @property
     def S(self) -> int:
         return int(self.lower.shape[1])
-
-
-def problem_bytes(m: int, n: int, B: int, max_trials: int = 100, tv_tiles: int = 0) -> int:
-    """Device bytes of one multi-slot problem (bands, iterate, gradient,
-    residual, weights, D, state, partial sums)."""
-    per_slice = 4 * (2 * m + 3 * n)
-    fixed = 8 * m + 2 * 4 * m + 2 * 4 * n
-    parts = 8 * (2 * 4096 * B + (tv_tiles or 512) * B * (2 + 2 * max_trials))
-    return per_slice * B + fixed + parts + 4096
 
 
 class Group:
@@ -122,15 +114,19 @@ class Server:
         self.groups: Dict[str, Group] = {}
         self.done: List[Request] = []
         self.rejected: List[Request] = []
+        self._bytes: Dict[str, int] = {}
 
     # -- footprint ---------------------------------------------------------
     def group_bytes(self, spec: OperatorSpec) -> int:
-        tiles = 0
-        if spec.params.get("obj") == 2:
-            r, c = spec.params["tv_rows"], spec.params["tv_cols"]
-            tiles = ((r + 15) // 16) * ((c + 15) // 16)
-        return footprint(spec.m, spec.n, spec.nnz, self.storage, keep_f32=True) + problem_bytes(
-            spec.m, spec.n, self.slots, spec.params.get("max_trials", 100), tiles)
+        """Device bytes of a group, from the library's own allocation plan
+        (smx_footprint): its operator (an upper bound) and its B-slot problem.
+        The autotuner's temporary copies and captured graphs come on top."""
+        b = self._bytes.get(spec.key)
+        if b is None:
+            ob, pb = problem_footprint(spec.m, spec.n, spec.nnz, self.storage, keep_f32=True, B=self.slots,
+                                       refine_iters=0, **spec.params)
+            b = self._bytes[spec.key] = ob + pb
+        return b
 
     def resident_bytes(self) -> int:
         return sum(self.group_bytes(g.spec) for g in self.groups.values())

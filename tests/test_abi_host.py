@@ -174,3 +174,23 @@ def test_image_shape_rejected_on_host(smx, shape):
     rc = smx.lib().smx_operator_create_image(C.byref(csr), 0, 1, shape[0], shape[1], None, C.byref(h))
     assert rc == smx.EINVAL and "image" in smx.lib().smx_last_error().decode()
     assert not h.value
+
+
+def test_problem_footprint_without_device(smx):
+    """The problem's share of smx_footprint grows with the slots and with the
+    buffers a basic algorithm, the history and the stopping rules add; invalid
+    descriptor fields are rejected."""
+    ob, p1 = smx.problem_footprint(5000, 3000, 60000, "f32", B=1)
+    _, p8 = smx.problem_footprint(5000, 3000, 60000, "f32", B=8)
+    _, pe = smx.problem_footprint(5000, 3000, 60000, "f32", B=1, basic=4)
+    _, ph = smx.problem_footprint(5000, 3000, 60000, "f32", B=1, history_cap=100)
+    _, pv = smx.problem_footprint(5000, 3000, 60000, "f32", B=1, stop=dict(var=1e-3))
+    assert ob == smx.footprint(5000, 3000, 60000, "f32")
+    assert p8 > 8 * 4 * (2 * 5000 + 2 * 3000) and p1 < p8
+    assert pe - p1 >= 8 * 3000 + 4 * 3000 + 4 * 5000 and ph - p1 == 100 * (3 * 8 + 2 * 4)
+    assert pv - p1 >= 4 * 3000
+    for bad in (dict(B=3), dict(basic=9), dict(obj=2, tv_rows=7, tv_cols=7), dict(history_cap=-1),
+                dict(dvc=[dict(row_begin=0, row_end=6000, sense=0, fraction=0.5, dose=1.0)])):
+        with pytest.raises(smx.SmxError) as e:
+            smx.problem_footprint(5000, 3000, 60000, "f32", **bad)
+        assert e.value.code == smx.EINVAL, bad

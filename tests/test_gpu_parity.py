@@ -37,6 +37,77 @@ def rel(a, b, floor=0.0):
     return float(np.linalg.norm(np.asarray(a, float) - np.asarray(b, float)) / max(np.linalg.norm(b), floor, 1e-300))
 
 
+ELEM_FLOOR = 1e-2
+
+
+def sup(a, b):
+    """Largest entry error of a against b on the scale of b's largest entry."""
+    a, b = np.asarray(a, float).reshape(-1), np.asarray(b, float).reshape(-1)
+    return float(np.max(np.abs(a - b)) / max(float(np.abs(b).max()), 1e-300)) if b.size else 0.0
+
+
+
+def elem(a, b):
+    """Worst element-wise relative difference of a against the reference b:
+    max_j |a_j - b_j| / max(|b_j|, ELEM_FLOOR max|b|).  Entries below 1 % of
+    the largest are compared on that scale: their float32 rounding inherits
+    the magnitude of the terms that cancel in them (a step's y_j sums
+    contributions on the scale of the whole iterate), so 1e-5 of it is about
+    two float32 units of the largest entry, while a wrong entry (a missed
+    column, a boundary pixel) is off by far more."""
+    a, b = np.asarray(a, float).reshape(-1), np.asarray(b, float).reshape(-1)
+    if b.size == 0:
+        return 0.0
+    scale = np.maximum(np.abs(b), ELEM_FLOOR * max(float(np.abs(b).max()), 1e-300))
+    return float(np.max(np.abs(a - b) / scale))
+
+
+# Dose-volume constraints: the device ranks a structure's rows by their values
+# rounded to float32, the oracle by exact values.  Where the k-th and (k+1)-th
+# highest values of a structure lie closer than this (relative), and the choice
+# between them changes a band (the (k+1)-th lies above the dose of an "at
+# most" constraint, or the k-th below the dose of an "at least" one), both
+# choices are nearest points of the set to within float32 resolution.
+TIE_REL = 1e-5
+
+
+def dvc_margin(P, dvc, z):
+    """Smallest relative gap between the k-th and (k+1)-th value over the
+    constraints whose choice between them changes a band at the point z
+    (inf when none does)."""
+    if not dvc:
+        return np.inf
+    kth, nxt = P.dvc_boundary(z)
+    out = np.inf
+    for g, d in enumerate(dvc):
+        a, b = kth[g], nxt[g]
+        if not (np.isfinite(a) and np.isfinite(b)):
+            continue
+        if d["sense"] == W.DVC_MAX and not b > d["dose"]:
+            continue
+        if d["sense"] == W.DVC_MIN and not a < d["dose"]:
+            continue
+        out = min(out, abs(a - b) / max(abs(a), abs(b), 1e-30))
+    return out
+
+
+def dvc_trajectory_margin(w, K, perturb=True, s=0, value_round=None, refine=0):
+    """The smallest dvc_margin over the points the feasibility steps of the
+    oracle's run act on (its iterate rounded to float32 after every
+    iteration, as the device stores it)."""
+    P32 = oracle.from_workload(w, s)
+    Pr = P32 if value_round is None else oracle.from_workload(w, s, value_round=value_round)
+    x = w.x0[:, s].astype(np.float32).astype(np.float64)
+    st, worst = None, np.inf
+    for k in range(K):
+        P = Pr if k < K - refine else P32
+        z = P.perturb(x, st)[0] if perturb else x
+        worst = min(worst, dvc_margin(P, w.dvc, z))
+        x, st, _ = P.run(x, 1, perturb=perturb, state=st)
+        x = x.astype(np.float32).astype(np.float64)
+    return worst
+
+
 def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1, fused=True):
     p = smx.problem_from_workload(w, storage=storage, history_cap=K, refine_iters=refine_iters, fused=fused)
     p.run(K, perturb=perturb, graph=graph)
@@ -84,6 +155,8 @@ def storage_deviation(w, K, perturb=True, s=0, value_round=None, refine=0):
     dx = rel(x, x64)
     dp = abs(P32.proximity(x) - P32.proximity(x64)) / max(abs(P32.proximity(x64)), 1e-300)
     df = abs(P32.objective(x) - P32.objective(x64)) / max(abs(P32.objective(x64)), 1e-300)
+    storage_deviation.elem = elem(x, x64)
+    storage_deviation.sup = sup(x, x64)
     return dx, dp, df
 
 
@@ -97,7 +170,17 @@ def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=N
     the emulation rounds one), and the objective must agree to first order
     with the iterate's difference: |df| <= 2 ||grad f|| ||dx|| + tol |f|, and
     so must the final proximity (grad P = -A^T D t).  The strict
-    per-iteration check is the lockstep test."""
+    per-iteration check is the lockstep test.  The iterate is compared
+    norm-wise, by its largest entry error against its largest entry (sup)
+    and element by element (elem); the last two within max(tol, 30 x the
+    same deviation float32 storage of the iterate alone forces: the kernels'
+    element-wise deviations run up to ~16 x that emulation's over the parity
+    cases, as their norm-wise ones run up to ~12 x, and on TV, EL and EMR
+    problems, whose steps amplify rounding where the iterate is nearly flat
+    or the system inconsistent, both concentrate on a few entries).  With dose-volume constraints
+    the case must keep every ranking decision of the oracle's run clear of
+    float32 near-ties (dvc_trajectory_margin above TIE_REL), so that the
+    device and the oracle pick the same nearest point."""
     say(f"{w.name} m={w.m} n={w.n} nnz={w.nnz} K={K} perturb={perturb} obj={w.obj} storage={storage} "
         f"fused={fused}")
     x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters, fused=fused)
@@ -105,19 +188,28 @@ def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=N
     if storage != "f32":
         refine = refine_iters if refine_iters >= 0 else (K + 19) // 20
     for s in range(w.B):
+        if getattr(w, "dvc", None):
+            mg = dvc_trajectory_margin(w, K, perturb, s, value_round=value_round, refine=refine)
+            print(f"  slice {s}: smallest dose-volume ranking margin {mg:.2e}", flush=True)
+            assert mg > TIE_REL, f"the case passes a float32 near-tie of a ranking ({mg:.2e}); choose another seed"
         xo, sto, ho, P = oracle_run(w, K, perturb, s, value_round=value_round, refine=refine)
         tx = tp = tol
-        r = rel(x[:, s], xo)
+        r, re = rel(x[:, s], xo), elem(x[:, s], xo)
         f_slack = 0.0
+        dx, dp, df = storage_deviation(w, K, perturb, s, value_round=value_round, refine=refine)
+        te, ts = max(tol, 30 * storage_deviation.elem), max(tol, 30 * storage_deviation.sup)
         if sensitive:
-            dx, dp, df = storage_deviation(w, K, perturb, s, value_round=value_round, refine=refine)
             tx, tp = max(tol, 10 * dx), max(tol, 10 * dp)
             f_slack = 2.0 * np.linalg.norm(P.gradient(xo)) * np.linalg.norm(x[:, s] - xo)
-            print(f"  storage-only deviation x {dx:.2e} prox {dp:.2e} f {df:.2e}", flush=True)
-        print(f"  slice {s}: iterate rel err {r:.3e} (tol {tx:.1e})", flush=True)
+        print(f"  storage-only deviation x {dx:.2e} (element-wise {storage_deviation.elem:.2e}) "
+              f"prox {dp:.2e} f {df:.2e}", flush=True)
+        print(f"  slice {s}: iterate rel err {r:.3e} (tol {tx:.1e}), element-wise {re:.3e} (tol {te:.1e}), "
+              f"largest entry error {sup(x[:, s], xo):.3e} (tol {ts:.1e})", flush=True)
         assert np.array_equal(h["trials"][:, s], ho.trials), "trial sequence differs"
         assert np.array_equal(h["accepts"][:, s], ho.accepts), "accept sequence differs"
         assert r <= tx, f"slice {s}: iterate rel err {r:.3e}"
+        assert sup(x[:, s], xo) <= ts, f"slice {s}: largest entry error {sup(x[:, s], xo):.3e} of the largest entry"
+        assert re <= te, f"slice {s}: element-wise iterate err {re:.3e}"
         assert st[s]["ell"] == sto.ell and st[s]["restarts"] == sto.restarts and st[s]["k"] == K
         assert st[s]["cap_hits"] == sto.cap_hits
         pfloor = 1e-6 * max(abs(ho.prox[0]), 1e-300)
@@ -186,33 +278,71 @@ def step_from_oracle(p, P, x, so, graph=False, perturb=True):
     """One iteration from an oracle-made point: x (float32 values) and state so
     are loaded into the device, which runs one iteration; the oracle runs the
     same iteration from the same point.  Returns (device x, device state,
-    oracle x, oracle state)."""
+    oracle x, oracle state, the oracle's proximity at the point its step acted
+    on).  The device records its own in its history at index so.k when its
+    history holds that many iterations."""
     p.set_state([device_state(so)], x.astype(np.float32).reshape(-1, 1))
-    xo, so1, _ = P.run(x.astype(np.float64), 1, perturb=perturb, state=so)
+    xo, so1, ho = P.run(x.astype(np.float64), 1, perturb=perturb, state=so)
     p.run(1, perturb=perturb, graph=graph)
     states1, xg = p.get_state()
-    return xg[:, 0].astype(np.float64), states1[0], xo, so1
+    return xg[:, 0].astype(np.float64), states1[0], xo, so1, float(ho.prox[0])
+
+
+def near_tie_step(P, w, x, so, perturb=True):
+    """Whether the feasibility step from the oracle point (x, so) meets a
+    dose-volume ranking near-tie (dvc_margin below TIE_REL)."""
+    if not getattr(w, "dvc", None):
+        return False
+    z = P.perturb(x, so)[0] if perturb else x
+    return dvc_margin(P, w.dvc, z) < TIE_REL
+
+
+def check_step(xg, sg, xo, so1, tie, tol, k):
+    """One oracle-driven iteration: decisions exactly and, unless the step met
+    a dose-volume near-tie (where either of the near-equal rows may keep its
+    value and the two nearest points differ in that row's band), the iterate
+    norm-wise and element-wise to tol.  The step's proximity (unique: the
+    distance to a nearest point) is compared from the histories afterwards
+    (check_step_proximities).  Returns the norm-wise difference (0 at a
+    near-tie)."""
+    assert sg["trials"] == so1.trials and sg["accepts"] == so1.accepts, k
+    assert sg["ell"] == so1.ell and sg["restarts"] == so1.restarts and sg["k"] == so1.k, k
+    if tie:
+        print(f"  iteration {k}: dose-volume near-tie, iterate not compared", flush=True)
+        return 0.0
+    r, re = rel(xg, xo), elem(xg, xo)
+    assert r <= tol, f"iteration {k}: rel err {r:.3e}"
+    assert re <= tol, f"iteration {k}: element-wise err {re:.3e}"
+    return r
+
+
+def check_step_proximities(p, ks, prox_oracle, tol):
+    """The proximity each oracle-driven step recorded on the device (history
+    index k) against the oracle's, to tol (relative)."""
+    hp = p.history()["prox"][:, 0]
+    for k, po in zip(ks, prox_oracle):
+        assert abs(hp[k] - po) <= tol * max(abs(po), 1e-300), (k, hp[k], po)
 
 
 def lockstep(smx, w, K, tol=RTOL):
     """Per-iteration check driven by the oracle: the oracle runs its own
     trajectory with the iterate rounded to float32 after every iteration; each
     of its iterates and states is loaded into the device, which runs that one
-    iteration.  The iterates must agree to tol and the decisions (trials,
-    accepts, ell, restarts) exactly."""
-    p = smx.problem_from_workload(w, history_cap=0)
+    iteration.  The iterates must agree to tol (norm-wise and element by
+    element), every step's proximity to tol and the decisions (trials,
+    accepts, ell, restarts) exactly (check_step)."""
+    p = smx.problem_from_workload(w, history_cap=K)
     P = oracle.from_workload(w)
     x = w.x0[:, 0].astype(np.float32).astype(np.float64)
     so = oracle.State()
-    worst = 0.0
+    worst, po = 0.0, []
     for k in range(K):
-        xg, sg, xo, so1 = step_from_oracle(p, P, x, so)
-        r = rel(xg, xo)
-        worst = max(worst, r)
-        assert sg["trials"] == so1.trials and sg["accepts"] == so1.accepts, k
-        assert sg["ell"] == so1.ell and sg["restarts"] == so1.restarts and sg["k"] == so1.k, k
-        assert r <= tol, f"iteration {k}: rel err {r:.3e}"
+        tie = near_tie_step(P, w, x, so)
+        xg, sg, xo, so1, pk = step_from_oracle(p, P, x, so)
+        worst = max(worst, check_step(xg, sg, xo, so1, tie, tol, k))
+        po.append(pk)
         x, so = xo.astype(np.float32).astype(np.float64), so1
+    check_step_proximities(p, range(K), po, tol)
     p.close()
     return worst
 
@@ -600,15 +730,16 @@ def test_set_fused_switches_kernels(smx):
     p.close()
 
 
-FUSED_SHAPES = [(8, 4, 0), (8, 8, 0), (16, 4, 0), (16, 4, 4), (16, 8, 0), (16, 8, 2), (32, 4, 0), (32, 4, 2),
-                (32, 8, 0), (32, 8, 1)]
+FUSED_SHAPES = [(8, 4, 0, 0), (8, 8, 0, 0), (16, 4, 0, 0), (16, 4, 4, 0), (16, 8, 0, 0), (16, 8, 2, 0), (32, 4, 0, 0),
+                (32, 4, 2, 0), (32, 8, 0, 0), (32, 8, 1, 0), (8, 4, 8, 1), (8, 8, 4, 1), (16, 4, 4, 1), (16, 8, 2, 1)]
 
 
 @pytest.mark.parametrize("case", ["rt", "long_rows"])
 def test_every_fused_shape(smx, case):
     """Each launch shape of the fused pass (entries re-read or kept in
-    registers, 8-32 lanes per row) against the oracle; the long-row case has
-    rows beyond the 256 entries the register-cached shapes hold."""
+    registers, 8-32 lanes per row, z gathered from memory or from LDS)
+    against the oracle; the long-row case has rows beyond the 256 entries the
+    register-cached shapes hold."""
     if case == "rt":
         w = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=60, K=12)
         storage, vr = "bf16", "bf16"
@@ -617,12 +748,14 @@ def test_every_fused_shape(smx, case):
                             obj=W.OBJ_SQNORM, K=10)
         storage, vr = "f32", None
     xo, sto, ho, P = oracle_run(w, w.K, value_round=vr)
-    for lpr, vec, cap in FUSED_SHAPES:
-        say(f"{case} fused shape lpr={lpr} vec={vec} cap={cap}")
+    storage_deviation(w, w.K, value_round=vr)
+    te = max(RTOL, 30 * storage_deviation.elem)
+    for lpr, vec, cap, zl in FUSED_SHAPES:
+        say(f"{case} fused shape lpr={lpr} vec={vec} cap={cap} z_in_lds={zl}")
         p = smx.problem_from_workload(w, storage=storage, history_cap=w.K, refine_iters=0)
-        p.set_fused_shape(lpr, vec, cap)
+        p.set_fused_shape(lpr, vec, cap, zl)
         info = p.describe()[storage]["fused"]
-        assert info["in_use"] and (info["lpr"], info["vec"], info["cap"]) == (lpr, vec, cap)
+        assert info["in_use"] and (info["lpr"], info["vec"], info["cap"], info["zl"]) == (lpr, vec, cap, zl)
         p.run(w.K)
         p.sync()
         x = p.get_x().cpu().numpy()[:, 0].astype(np.float64)
@@ -630,7 +763,7 @@ def test_every_fused_shape(smx, case):
         p.close()
         assert np.array_equal(h["trials"][:, 0], ho.trials)
         r = rel(x, xo)
-        assert r <= RTOL, (lpr, vec, cap, r)
+        assert r <= RTOL and elem(x, xo) <= te, (lpr, vec, cap, zl, r, elem(x, xo), te)
         np.testing.assert_allclose(h["prox"][:, 0], ho.prox, rtol=RTOL, atol=1e-6 * abs(ho.prox[0]))
     p = smx.problem_from_workload(w, storage=storage)
     with pytest.raises(smx.SmxError):
@@ -873,7 +1006,14 @@ def _dvc_random(B=1, K=20, obj=W.OBJ_SQNORM, seed=81):
 
 
 def _dvc_rt(basic, K=30):
-    return W.rt_with_dvc(W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=70, K=K), basic=basic)
+    """The small radiotherapy case with the horseshoe plan's constraints from
+    a seeded starting point: the phantom and beams are symmetric, so from
+    x0 = 0 the first perturbed point gives mirror voxels doses equal in exact
+    arithmetic that rounding alone orders (a tie either nearest point
+    resolves); this starting point keeps every ranking of the run clear of
+    float32 near-ties (checked by check_parity)."""
+    w = W.rt_with_dvc(W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=70, K=K), basic=basic)
+    return w.with_params(x0=W.synthetic_iterate(w, seed=79, spread=0.3))
 
 
 def test_dvc_random_parity(smx):
@@ -886,9 +1026,8 @@ def test_dvc_random_parity(smx):
 
 @pytest.mark.parametrize("method", ["simult", "emr"])
 def test_dvc_rt_parity(smx, method):
-    """The radiotherapy case with the horseshoe plan's dose-volume constraints
-    (all doses 0 at x0 = 0: the first ranking is by row alone), the linear
-    objective, and the weighted simultaneous or the EMR step."""
+    """The radiotherapy case with the horseshoe plan's dose-volume constraints,
+    the linear objective, and the weighted simultaneous or the EMR step."""
     w = _dvc_rt(BASIC_CASES.get(method, W.BASIC_SIMULT))
     check_parity(smx, w, w.K, sensitive=method == "emr")
 

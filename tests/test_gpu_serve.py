@@ -76,3 +76,39 @@ def test_footprint_admission_and_eviction(srv):
     stats = tiny.run(_requests(srv, reqs))
     assert stats["requests"] == 0 and stats["rejected"] == len(reqs)
     tiny.close()
+
+
+def test_mix_bf16_against_float32_oracle(srv):
+    """The served path as the benchmark runs it (bf16-stored A, no refinement
+    tail): each result equals its solo run bitwise, and every slice's
+    proximity and objective are within 2e-2 of the oracle's run on the
+    float32 operator."""
+    ops, reqs, pools = W.serving_mix(sizes=(24, 32), n_requests=8, slices=(2, 4), pool=6, K=30, seed=9,
+                                     n_angles=20, rate_hz=400.0)
+    say("serving mix, bf16")
+    specs = _specs(srv, ops)
+    server = srv.Server(specs, hbm_budget=1 << 34, slots=8, chunk=5, storage="bf16", autotune=False)
+    stats = server.run(_requests(srv, reqs))
+    server.close()
+    print(f"  {stats}", flush=True)
+    assert stats["requests"] == len(reqs) and stats["rejected"] == 0
+    done = {r.rid: r for r in server.done}
+    for rid in (0, 5):
+        solo = srv.Server(specs, hbm_budget=1 << 34, slots=8, chunk=5, storage="bf16", autotune=False)
+        solo.run(_requests(srv, [dict(reqs[rid], t_arrival=0.0)]))
+        assert np.array_equal(solo.done[0].result, done[rid].result), rid
+        solo.close()
+    worst = 0.0
+    for r in reqs:
+        w = pools[r["op_key"]]
+        for j, s in enumerate(r["pool_index"]):
+            ws = w.slice(int(s))
+            P = oracle.from_workload(ws)
+            xo, _, _ = P.run(ws.x0[:, 0], r["K"])
+            xs = done[r["rid"]].result[:, j].astype(np.float64)
+            po, fo = P.proximity(xo), P.objective(xo)
+            ep = abs(P.proximity(xs) - po) / abs(po)
+            ef = abs(P.objective(xs) - fo) / abs(fo)
+            worst = max(worst, ep, ef)
+            assert ep <= 2e-2 and ef <= 2e-2, (r["rid"], j, ep, ef)
+    print(f"  worst proximity/objective rel err against the float32 oracle: {worst:.2e}", flush=True)

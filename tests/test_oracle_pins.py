@@ -206,7 +206,18 @@ def _feasible(A, lo, up, box, tol=1e-9):
 def test_lp_feasibility_brute_force(orc):
     """Vertex enumeration decides feasibility of tiny systems; the unperturbed
     simultaneous method must drive the proximity to 0 exactly on the feasible
-    ones, and to the box-constrained minimum of the proximity otherwise."""
+    ones, and to the box-constrained minimum of the proximity otherwise.
+    Runs the oracle on one thread: its parallel loops only add overhead to
+    systems of a few rows (results do not depend on the thread count)."""
+    threads = orc.max_threads()
+    orc.set_threads(1)
+    try:
+        _lp_cases(orc)
+    finally:
+        orc.set_threads(threads)
+
+
+def _lp_cases(orc):
     n_feas = n_infeas = 0
     for seed in range(100, 140):
         rng = np.random.default_rng(seed)
@@ -637,7 +648,7 @@ def test_drop_counts_nonzeros_before_rounding(orc):
 
 
 # ---------------------------------------------------------------------------
-# Stopping rules (Section 2.2; superiorized rule of Section 2.2.1; variance
+# Stopping rules (Section 2.2.1; superiorized rule of Section 2.2.3; variance
 # rule of Section 2.3.2)
 # ---------------------------------------------------------------------------
 
