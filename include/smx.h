@@ -362,6 +362,26 @@ int smx_problem_dims(const smx_problem *p, int64_t *m, int64_t *n, int64_t *nnz,
 int smx_slot_load(smx_problem *p, int32_t slot, const float *lower, const float *upper, const float *x0,
                   int32_t on_device, int64_t budget);
 
+/*
+ * smx_slot_load without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the staging of the slot's bands and starting point
+ * (2m + n floats, which smx_slot_load allocates per call) and the flags of
+ * their validation live in a fixed 32 MiB scratch array inside the library,
+ * one per device, resident from the first smx_problem_create on that device
+ * until the process ends.  Arguments,
+ * results and errors as smx_slot_load (host or device input, copied in order
+ * on the problem's stream; returns after the copies complete), and
+ * SMX_EINVAL, with nothing changed, when 256 + 4(2m + n) bytes (each part
+ * rounded up to 256) exceed the scratch: 2m + n up to about 8.39M floats.
+ * Bounds are checked on the device after staging; an invalid slot is
+ * reported before anything in the problem changes.  Every call on a device
+ * shares that device's scratch and leaves its contents there: calls that
+ * overlap on one device (from several threads) race.
+ */
+int smx_slot_load_noalloc(smx_problem *p, int32_t slot, const float *lower, const float *upper, const float *x0,
+                          int32_t on_device, int64_t budget);
+
 /* Stop advancing a slot (its iterate and state stay as they are). */
 int smx_slot_disable(smx_problem *p, int32_t slot);
 

@@ -57,6 +57,7 @@ EXPORTS = [
     "smx_set_fused_shape",
     "smx_stop_status",
     "smx_slot_load",
+    "smx_slot_load_noalloc",
     "smx_slot_disable",
     "smx_slot_status",
     "smx_slot_get_x",
@@ -198,6 +199,7 @@ def lib() -> C.CDLL:
     L.smx_get_timing.argtypes = [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i64)]
     L.smx_autotune.argtypes = [vp, i32]
     L.smx_slot_load.argtypes = [vp, i32, vp, vp, vp, i32, i64]
+    L.smx_slot_load_noalloc.argtypes = [vp, i32, vp, vp, vp, i32, i64]
     L.smx_slot_disable.argtypes = [vp, i32]
     L.smx_slot_status.argtypes = [vp, vp, vp]
     L.smx_slot_get_x.argtypes = [vp, i32, vp, i32]
@@ -464,6 +466,24 @@ class Problem:
         assert lo.size == self.m and up.size == self.m and xx.size == self.n
         check(lib().smx_slot_load(self.handle, int(slot), lo.ctypes.data, up.ctypes.data, xx.ctypes.data, 0,
                                   int(budget)))
+
+    def slot_load_noalloc(self, slot: int, lower, upper, x0, budget: int):
+        """slot_load through the entry point that allocates nothing (its
+        staging lives in the library's fixed device scratch).  Device tensors
+        are passed as device pointers, anything else as host arrays."""
+        import torch
+
+        arrs = [lower, upper, x0]
+        if all(isinstance(a, torch.Tensor) and a.is_cuda for a in arrs):
+            ts = [a.to(torch.float32).contiguous().reshape(-1) for a in arrs]
+            assert ts[0].numel() == self.m and ts[1].numel() == self.m and ts[2].numel() == self.n
+            check(lib().smx_slot_load_noalloc(self.handle, int(slot), _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2]), 1,
+                                              int(budget)))
+            return
+        lo, up, xx = (np.ascontiguousarray(np.asarray(a, np.float32).reshape(-1)) for a in arrs)
+        assert lo.size == self.m and up.size == self.m and xx.size == self.n
+        check(lib().smx_slot_load_noalloc(self.handle, int(slot), lo.ctypes.data, up.ctypes.data, xx.ctypes.data, 0,
+                                          int(budget)))
 
     def slot_disable(self, slot: int):
         check(lib().smx_slot_disable(self.handle, int(slot)))

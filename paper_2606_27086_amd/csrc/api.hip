@@ -18,11 +18,16 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 using namespace smx;
+
+// The fixed device scratch of smx_slot_load_noalloc (32 MiB).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -187,6 +192,33 @@ float f16_scale_for(const std::vector<float> &v)
     const double mant = std::frexp((double)amax, &e);
     const int ce = (mant == 0.5) ? e - 1 : e; // ceil(log2(amax))
     return (float)std::ldexp(1.0, 14 - ce);
+}
+
+// Device scratch of smx_slot_load_noalloc: a fixed array in the library's
+// code object (each device that loads the library holds its own copy until
+// the process ends), so that entry point needs no allocation.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device, never through the array's name.
+constexpr size_t kScratchHead = 256; // flags of the staged-band check
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device (looked up once per
+// device, with that device current).
+void *scratch_on_current_device()
+{
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) throw HipError{hipErrorInvalidDevice, "scratch: device index"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
 }
 
 } // namespace
@@ -1422,6 +1454,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     p->hist.accepts = p->h_ac.as<int>();
     p->hist.cap = d->history_cap;
     hip_check(hipStreamSynchronize(s), "problem setup");
+    (void)scratch_on_current_device(); // the no-alloc slot load's scratch is resident from here on
     op->refs.fetch_add(1);
     *out = p.release();
     return SMX_OK;
@@ -2086,6 +2119,45 @@ int smx_slot_load(smx_problem *p, int32_t slot, const float *lower, const float 
         hip_check(launch_put_column(p->upper.as<float>(), tmp.as<float>(), m, p->B, slot, s), "slot bounds");
         hip_check(hipMemcpyAsync(tmp.p, xs.data(), sizeof(float) * n, hipMemcpyHostToDevice, s), "slot x0");
         hip_check(launch_put_column(p->x.as<float>(), tmp.as<float>(), n, p->B, slot, s), "slot x0");
+        hip_check(launch_reset_slot(p->state(p->cur), slot, budget, s), "slot reset");
+        hip_check(hipStreamSynchronize(s), "slot load");
+        return SMX_OK;
+    })
+}
+
+int smx_slot_load_noalloc(smx_problem *p, int32_t slot, const float *lower, const float *upper, const float *x0,
+                          int32_t on_device, int64_t budget)
+{
+    if (!p || !lower || !upper || !x0) return fail(SMX_EINVAL, "NULL argument");
+    if (slot < 0 || slot >= p->B) return fail(SMX_EINVAL, "slot %d outside [0, %d)", slot, p->B);
+    if (budget < 0) return fail(SMX_EINVAL, "budget must be >= 0");
+    const int64_t m = p->m, n = p->n;
+    // staging: [check flags][lower m][upper m][x0 n], each part 256-byte aligned
+    const size_t off_lo = kScratchHead, off_up = off_lo + size_t(round_up(m * 4, 256)),
+                 off_x = off_up + size_t(round_up(m * 4, 256)), need = off_x + size_t(round_up(n * 4, 256));
+    if (need > kScratchBytes)
+        return fail(SMX_EINVAL, "slot of %lld rows and %lld columns needs %zu bytes of staging; the static scratch "
+                    "holds %zu (2m + n up to about %zu floats)", (long long)m, (long long)n, need, kScratchBytes,
+                    (kScratchBytes - kScratchHead) / 4);
+    SMX_GUARD({
+        unsigned char *base = static_cast<unsigned char *>(scratch_on_current_device());
+        float *slo = reinterpret_cast<float *>(base + off_lo), *sup = reinterpret_cast<float *>(base + off_up),
+              *sx = reinterpret_cast<float *>(base + off_x);
+        unsigned *flag = reinterpret_cast<unsigned *>(base);
+        hipStream_t s = p->stream;
+        const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        hip_check(hipMemcpyAsync(slo, lower, sizeof(float) * m, kind, s), "slot bounds");
+        hip_check(hipMemcpyAsync(sup, upper, sizeof(float) * m, kind, s), "slot bounds");
+        hip_check(hipMemcpyAsync(sx, x0, sizeof(float) * n, kind, s), "slot x0");
+        hip_check(launch_check_bands(slo, sup, m, flag, s), "slot bounds check");
+        unsigned h[2] = {0u, 0u};
+        hip_check(hipMemcpyAsync(h, flag, sizeof h, hipMemcpyDeviceToHost, s), "slot bounds check");
+        hip_check(hipStreamSynchronize(s), "slot bounds check");
+        if (h[0] & 1u) return fail(SMX_EINVAL, "NaN bound at %u", h[1]);
+        if (h[0] & 2u) return fail(SMX_EINVAL, "lower > upper at %u", h[1]);
+        hip_check(launch_put_column(p->lower.as<float>(), slo, m, p->B, slot, s), "slot bounds");
+        hip_check(launch_put_column(p->upper.as<float>(), sup, m, p->B, slot, s), "slot bounds");
+        hip_check(launch_put_column(p->x.as<float>(), sx, n, p->B, slot, s), "slot x0");
         hip_check(launch_reset_slot(p->state(p->cur), slot, budget, s), "slot reset");
         hip_check(hipStreamSynchronize(s), "slot load");
         return SMX_OK;

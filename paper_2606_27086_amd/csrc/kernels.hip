@@ -2259,6 +2259,30 @@ __global__ void k_put_column(float *__restrict__ dst, const float *__restrict__ 
         dst[i * B + s] = src[i];
 }
 
+// Validation of a slot's bands staged on the device.  flag[0] collects bit 0
+// for a NaN bound and bit 1 for lower > upper, flag[1] the lowest row with
+// either; k_slot_flag_clear sets them to {0, 0xffffffff} first.
+__global__ void k_slot_flag_clear(unsigned *flag)
+{
+    if (threadIdx.x == 0) {
+        flag[0] = 0u;
+        flag[1] = 0xffffffffu;
+    }
+}
+
+__global__ void k_check_bands(const float *__restrict__ lo, const float *__restrict__ up, long long m,
+                              unsigned *__restrict__ flag)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (long long)gridDim.x * blockDim.x) {
+        const float a = lo[i], b = up[i];
+        const unsigned bits = (isnan(a) || isnan(b)) ? 1u : (a > b ? 2u : 0u);
+        if (bits) {
+            atomicOr(&flag[0], bits);
+            atomicMin(&flag[1], (unsigned)i);
+        }
+    }
+}
+
 __global__ void k_get_column(float *__restrict__ dst, const float *__restrict__ src, long long rows, int B, int s)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (long long)gridDim.x * blockDim.x)
@@ -2372,6 +2396,13 @@ hipError_t launch_put_column(float *dst, const float *src, int64_t rows, int B, 
 {
     hipLaunchKernelGGL(k_put_column, dim3(grid_for(rows, kBlock, 2048)), dim3(kBlock), 0, s, dst, src, (long long)rows, B,
                        slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_bands(const float *lo, const float *up, int64_t m, unsigned *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slot_flag_clear, dim3(1), dim3(64), 0, s, flag);
+    hipLaunchKernelGGL(k_check_bands, dim3(grid_for(m, kBlock, 2048)), dim3(kBlock), 0, s, lo, up, (long long)m, flag);
     return hipGetLastError();
 }
 

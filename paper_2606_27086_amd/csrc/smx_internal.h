@@ -238,6 +238,9 @@ hipError_t launch_fill(float *p, float v, int64_t count, hipStream_t s);
 // slots of a multi-slice problem (serving)
 hipError_t launch_put_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s);
 hipError_t launch_get_column(float *dst, const float *src, int64_t rows, int B, int slot, hipStream_t s);
+// flag[0..1] = {bit 0: a NaN bound, bit 1: lower > upper; the lowest such row}
+// for m staged bands (flag is cleared first, in the same stream)
+hipError_t launch_check_bands(const float *lo, const float *up, int64_t m, unsigned *flag, hipStream_t s);
 hipError_t launch_reset_slot(SliceState *st, int slot, int64_t budget, hipStream_t s);
 hipError_t launch_disable_slot(SliceState *st, int slot, hipStream_t s);
 
