@@ -100,6 +100,8 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
         f = shapes["fused"]
         acc = "double" if f["acc"] == "f64" else "float"
         if pass_no == 1:
+            if f.get("zl", 0):
+                return f"smx::k_fused_zl<{f['lpr']}, {f['vec']}, {VALUE_TAG[f['format']]}>"
             if f.get("cap", 0):
                 return f"smx::k_fused_rc<{f['lpr']}, {f['vec']}, {f['cap']}, {VALUE_TAG[f['format']]}, {acc}>"
             return f"smx::k_fused<{f['lpr']}, {f['vec']}, {VALUE_TAG[f['format']]}, {acc}>"
@@ -224,11 +226,14 @@ CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 
 def gathers_of(w, shapes, dpass, tiles):
     """Global gathers (one address each) a launch of the dominant kernel makes:
-    one per nonzero for the row passes and the fused pass, one per (tile, row)
+    one per nonzero for the row passes and the fused pass (none when the fused
+    pass stages z in LDS), one per (tile, row)
     pair for the image-tile pass 2, and for the LDS-staged passes one per
     nonzero whose column (pass 1) or row (pass 2) lies beyond the staged part
     of the gathered vector (none for the row-panel pass 2)."""
     shape = shapes[f"pass{dpass}"]
+    if dpass == 1 and fused_in_use(shapes) and shapes["fused"].get("zl", 0):
+        return 0  # z staged in LDS: every gather reads LDS
     if dpass == 2 and shape["mode"] == "tiles" and not fused_in_use(shapes):
         return tiles["rows"]
     if dpass == 1 and shape["mode"] == "lds" and not fused_in_use(shapes):

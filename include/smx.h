@@ -81,6 +81,10 @@ extern "C" {
 #define SMX_BASIC_EL 3
 #define SMX_BASIC_EMR 4
 
+/* perturbation step sizes (smx_problem_desc.step_rule) */
+#define SMX_STEP_POWER 0
+#define SMX_STEP_ADAPTIVE 1
+
 /* smx_run flags */
 #define SMX_RUN_PERTURB 1u /* run the perturbation phase of Algorithm 1 */
 #define SMX_RUN_GRAPH 2u   /* replay captured HIP graphs of several iterations */
@@ -177,6 +181,17 @@ typedef struct {
     int32_t n_dvc;
     int32_t reserved_dvc;    /* 0 */
     const smx_dvc *dvc;
+    /* Step size of the perturbation phase (Section 2.1.2): SMX_STEP_POWER, the
+     * power law gamma alpha^ell of Algorithm 1; or SMX_STEP_ADAPTIVE, the
+     * subgradient-projection step beta_k = (f(x^k) - f_ref) / ||g(x^k)|| when
+     * f(x^k) > f_ref and no step otherwise, where f_ref is the objective value
+     * at which the previous perturbation phase ended (f(x^0) before the first
+     * phase, so the first iteration does not perturb).  The adaptive phase
+     * tries that one step along v = -g/||g|| and keeps it when f does not
+     * increase (n_red, max_trials, gamma and alpha do not apply; ell counts
+     * the trial). */
+    int32_t step_rule;
+    int32_t reserved_step;   /* 0 */
 } smx_problem_desc;
 
 /* Per-slice iteration state, as checkpointed by smx_get_state. */
@@ -197,6 +212,8 @@ typedef struct {
     double f_last;       /* f(x^k) of the last perturbation phase (NaN if none) */
     double var_n, var_mean, var_m2; /* running count, mean and squared deviations of
                                        the relative iterate changes */
+    double f_ref;        /* f where the last perturbation phase ended (NaN before the
+                            first): the adaptive step's reference value */
 } smx_slice_state;
 
 /* why a slice stopped (smx_stop_status) */
@@ -435,9 +452,9 @@ int smx_set_fused(smx_problem *p, int32_t mode);
  * autotuner's choice: lanes per row (8, 16, 32), entries per load (4, 8) and
  * cap: 0 to read a row's entries again for the scatter, or 256/(lpr*vec) (16
  * or 32 lanes only) to keep 256 entries of each row in registers.  With
- * z_in_lds != 0 (8 or 16 lanes, cap = 256/(lpr*vec), problems whose n is at
- * most about 20k): every workgroup first copies the whole point z into LDS
- * beside a float32 copy of y and gathers from there instead of from memory.
+ * z_in_lds != 0 (cap 0, problems whose n is at most about 20k): every
+ * workgroup first copies the whole point z into LDS beside a float32 copy of
+ * y and gathers from there instead of from memory.
  * Results do not depend on the shape beyond floating-point summation order.
  * Errors: SMX_ESTATE when the problem has no fused pass, SMX_EINVAL for
  * another shape. */

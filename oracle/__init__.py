@@ -29,6 +29,7 @@ STOP_PROX, STOP_DPROX, STOP_MAXIT, STOP_VAR, STOP_SM = 1, 2, 3, 4, 5
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 BASIC_ART = 5  # sequential projections, one sweep per iteration (the oracle only)
 DVC_MAX, DVC_MIN = 0, 1
+STEP_POWER, STEP_ADAPTIVE = 0, 1  # perturbation step size: power law, adaptive (Section 2.1.2)
 
 
 def build(force: bool = True) -> str:
@@ -91,6 +92,8 @@ class _Problem(C.Structure):
         ("csc_ptr", C.POINTER(C.c_int64)),
         ("csc_row", C.POINTER(C.c_int32)),
         ("csc_val", C.POINTER(C.c_double)),
+        ("step_rule", C.c_int32),
+        ("pad2_", C.c_int32),
     ]
 
 
@@ -113,12 +116,14 @@ class State(C.Structure):
         ("var_n", C.c_double),
         ("var_mean", C.c_double),
         ("var_m2", C.c_double),
+        ("f_ref", C.c_double),
     ]
 
     def __init__(self):
         super().__init__()
         self.p_last = float("nan")
         self.f_last = float("nan")
+        self.f_ref = float("nan")
 
     def copy(self) -> "State":
         s = State()
@@ -235,6 +240,7 @@ class Problem:
         col_nnz=None,
         stop=None,
         dvc=None,
+        step_rule=STEP_POWER,
     ):
         self.m, self.n = int(m), int(n)
         self.row_ptr = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
@@ -272,6 +278,7 @@ class Problem:
             restart_every=int(restart_every),
             basic=int(basic),
             col_nnz=_dp(self.col_nnz),
+            step_rule=int(step_rule),
         )
         self.dvc = None
         if dvc:
@@ -474,4 +481,5 @@ def from_workload(w, s: int = 0, value_round: Optional[str] = None) -> Problem:
         col_nnz=col_nnz,
         stop=getattr(w, "stop", None),
         dvc=getattr(w, "dvc", None),
+        step_rule=getattr(w, "step_rule", STEP_POWER),
     )

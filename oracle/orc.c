@@ -59,6 +59,10 @@
 #define ORC_BASIC_EMR 4    /* Landweber with error-minimising relaxation */
 #define ORC_BASIC_ART 5    /* sequential projections (Kaczmarz / ART), one sweep per iteration; oracle only */
 
+/* step-size rules of the perturbation phase (Section 2.1.2) */
+#define ORC_STEP_POWER 0    /* beta = gamma * alpha^ell, ell one per trial */
+#define ORC_STEP_ADAPTIVE 1 /* beta = (f(x^k) - f_ref) / ||g(x^k)|| when f(x^k) > f_ref, else no step */
+
 /* dose-volume constraint senses (Section 2.3.3) */
 #define ORC_DVC_MAX 0 /* D_V <= d: at most floor(V N_S) rows of the structure above d */
 #define ORC_DVC_MIN 1 /* D_V >= d: at least ceil(V N_S) rows of the structure at or above d */
@@ -110,6 +114,8 @@ typedef struct {
     const int64_t *csc_ptr;
     const int32_t *csc_row;
     const double *csc_val;
+    int32_t step_rule; /* ORC_STEP_* */
+    int32_t pad2_;
 } orc_problem;
 
 typedef struct {
@@ -127,6 +133,7 @@ typedef struct {
     double p_last;       /* proximity recorded at the last iteration (NaN before the first) */
     double f_last;       /* f(x^k) of the last iteration's phase */
     double var_n, var_mean, var_m2; /* running count, mean and squared deviations of omega */
+    double f_ref; /* f where the last perturbation phase ended (NaN before the first): the adaptive step's reference */
 } orc_state;
 
 #define ORC_STOP_PROX 1    /* P <= P* */
@@ -630,11 +637,30 @@ void orc_stop_reset(orc_state *st)
  *     beta = gamma * alpha^ell, ell growing by one per trial, and accepts the
  *     first z with f(z) <= f(x^{k,n}); the number of trials per reduction step
  *     is capped at max_trials, and a step that reaches the cap ends the phase.
+ * With the adaptive rule (ORC_STEP_ADAPTIVE; the step size of Nikazad et al.
+ * in Section 2.1.2, whose reference value the paper does not define) the
+ * phase instead tries the one step beta = (f(x^k) - f_ref) / ||g|| along v
+ * when f(x^k) > f_ref, accepted under the same test f(z) <= f(x^k) (a
+ * rejected step leaves x^k), and then sets f_ref to f after the phase: the
+ * value the point the feasibility step acts on has.  Before the first phase
+ * f_ref is f(x^0), so the first iteration does not perturb.  ell counts the
+ * trial; n_red, max_trials and the power law do not apply.
  * Returns f after the phase (f_start when nothing was accepted); counts the
  * trials and accepted trials.  Scratch: g, v, z of length n.
  */
+static double phase_steps(const orc_problem *P, double *x, orc_state *st, double f_start, double *g, double *v,
+                          double *z, int32_t *trials, int32_t *accepts);
+
 static double perturbation_phase(const orc_problem *P, double *x, orc_state *st, double f_start, double *g, double *v,
                                  double *z, int32_t *trials, int32_t *accepts)
+{
+    const double f = phase_steps(P, x, st, f_start, g, v, z, trials, accepts);
+    st->f_ref = f; /* where this phase ended (the adaptive step's next reference) */
+    return f;
+}
+
+static double phase_steps(const orc_problem *P, double *x, orc_state *st, double f_start, double *g, double *v,
+                          double *z, int32_t *trials, int32_t *accepts)
 {
     const int64_t n = P->n, k = st->k;
     if (P->restart_every > 0 && k > 0 && k % P->restart_every == 0) {
@@ -645,6 +671,22 @@ static double perturbation_phase(const orc_problem *P, double *x, orc_state *st,
     double gg = 0.0;
     for (int64_t j = 0; j < n; ++j) gg += g[j] * g[j];
     const double gn = sqrt(gg);
+    if (P->step_rule == ORC_STEP_ADAPTIVE) {
+        double f_cur = f_start;
+        if (!isnan(st->f_ref) && gn > 0.0 && f_start > st->f_ref) {
+            const double beta = (f_start - st->f_ref) / gn;
+            for (int64_t j = 0; j < n; ++j) z[j] = x[j] - beta * g[j] / gn;
+            const double fz = orc_objective(P, z);
+            st->ell += 1;
+            *trials += 1;
+            if (fz <= f_start) {
+                memcpy(x, z, sizeof(double) * n);
+                f_cur = fz;
+                *accepts += 1;
+            }
+        }
+        return f_cur;
+    }
     if (!(gn > 0.0)) return f_start;
     for (int64_t j = 0; j < n; ++j) v[j] = -g[j] / gn;
     double f_cur = f_start;

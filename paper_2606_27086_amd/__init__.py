@@ -64,6 +64,9 @@ EXPORTS = [
 ]
 
 
+STEP_POWER, STEP_ADAPTIVE = 0, 1  # smx_problem_desc.step_rule
+
+
 class SmxError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{_CODE_NAMES.get(code, code)}: {msg}")
@@ -126,6 +129,8 @@ class ProblemDesc(C.Structure):
         ("n_dvc", C.c_int32),
         ("reserved_dvc", C.c_int32),
         ("dvc", C.POINTER(DvcC)),
+        ("step_rule", C.c_int32),
+        ("reserved_step", C.c_int32),
     ]
 
 
@@ -146,12 +151,14 @@ class SliceStateC(C.Structure):
         ("var_n", C.c_double),
         ("var_mean", C.c_double),
         ("var_m2", C.c_double),
+        ("f_ref", C.c_double),
     ]
 
     def __init__(self):
         super().__init__()
         self.p_last = float("nan")
         self.f_last = float("nan")
+        self.f_ref = float("nan")
 
     def as_dict(self) -> dict:
         """Fields as Python numbers (NaN as None, so equal states compare equal)."""
@@ -293,7 +300,7 @@ def footprint(m, n, nnz, storage="f32", keep_f32=True) -> int:
 
 def _desc(B, lower, upper, weights, box_lo, box_hi, linear_c, lam=1.0, obj=OBJ_NONE, tv_rows=0, tv_cols=0,
           tv_eps=0.0, gamma=1.0, alpha=0.99, n_red=1, restart_every=0, max_trials=100, refine_iters=-1,
-          history_cap=0, basic=0, stop=None, dvc=None):
+          history_cap=0, basic=0, stop=None, dvc=None, step_rule=0):
     """The problem descriptor (device pointers or None for the arrays) and the
     dose-volume table it points to (kept alive by the caller)."""
     d = ProblemDesc(
@@ -301,7 +308,7 @@ def _desc(B, lower, upper, weights, box_lo, box_hi, linear_c, lam=1.0, obj=OBJ_N
         obj_kind=int(obj), tv_rows=int(tv_rows), tv_cols=int(tv_cols), tv_eps=float(tv_eps), linear_c=linear_c,
         gamma=float(gamma), alpha=float(alpha), n_red=int(n_red), restart_every=int(restart_every),
         max_trials=int(max_trials), refine_iters=int(refine_iters), history_cap=int(history_cap), on_device=1,
-        basic=int(basic),
+        basic=int(basic), step_rule=int(step_rule),
     )
     if stop is not None:  # stopping rules: prox, dprox, n, max_iters, dobj, var
         d.stop_on = 1
@@ -329,7 +336,7 @@ def problem_footprint(m, n, nnz, storage="f32", keep_f32=True, B=1, image=None, 
     not needed: only sizes count), on the current device, without allocating
     anything."""
     keys = ("lam", "obj", "tv_rows", "tv_cols", "tv_eps", "gamma", "alpha", "n_red", "restart_every", "max_trials",
-            "refine_iters", "history_cap", "basic", "stop", "dvc")
+            "refine_iters", "history_cap", "basic", "stop", "dvc", "step_rule")
     d, tab = _desc(B, None, None, None, None, None, None, **{k: v for k, v in params.items() if k in keys})
     ob, pb = C.c_size_t(), C.c_size_t()
     ir, ic = (0, 0) if image is None else (int(image[0]), int(image[1]))
@@ -344,7 +351,7 @@ class Problem:
     def __init__(self, op: Operator, lower, upper, box_lo=None, box_hi=None, weights=None, lam=1.0,
                  obj=OBJ_NONE, tv_rows=0, tv_cols=0, tv_eps=0.0, linear_c=None, gamma=1.0, alpha=0.99,
                  n_red=1, restart_every=0, max_trials=100, refine_iters=-1, history_cap=0, B=None,
-                 device="cuda", stream=None, basic=0, stop=None, dvc=None):
+                 device="cuda", stream=None, basic=0, stop=None, dvc=None, step_rule=0):
         """dvc: dose-volume constraints, dicts with row_begin, row_end, sense
         (DVC_MAX / DVC_MIN), fraction and dose; their row blocks consecutive."""
         import torch
@@ -365,7 +372,8 @@ class Problem:
         d, self._dvc_tab = _desc(self.B, _ptr(t_lo), _ptr(t_up), _ptr(t_w), _ptr(t_blo), _ptr(t_bhi), _ptr(t_c),
                                  lam=lam, obj=obj, tv_rows=tv_rows, tv_cols=tv_cols, tv_eps=tv_eps, gamma=gamma,
                                  alpha=alpha, n_red=n_red, restart_every=restart_every, max_trials=max_trials,
-                                 refine_iters=refine_iters, history_cap=history_cap, basic=basic, stop=stop, dvc=dvc)
+                                 refine_iters=refine_iters, history_cap=history_cap, basic=basic, stop=stop, dvc=dvc,
+                                 step_rule=step_rule)
         self.history_cap = int(history_cap)
         self.obj = int(obj)
         h = C.c_void_p()
@@ -430,7 +438,7 @@ class Problem:
     def set_state(self, states, x):
         st = (SliceStateC * self.B)()
         for i, s in enumerate(states):
-            st[i].p_last = st[i].f_last = float("nan")
+            st[i].p_last = st[i].f_last = st[i].f_ref = float("nan")
             for k, v in s.items():
                 t = dict(SliceStateC._fields_)[k]
                 setattr(st[i], k, (float("nan") if v is None else float(v)) if t is C.c_double else int(v))
@@ -555,7 +563,7 @@ def workload_kwargs(w, history_cap: int = 0, refine_iters: int = -1) -> dict:
         tv_rows=w.tv_rows, tv_cols=w.tv_cols, tv_eps=w.tv_eps, linear_c=w.linear_c, gamma=w.gamma, alpha=w.alpha,
         n_red=w.n_red, restart_every=w.restart_every, max_trials=w.max_trials, history_cap=history_cap,
         refine_iters=refine_iters, B=w.B, basic=getattr(w, "basic", 0), stop=getattr(w, "stop", None),
-        dvc=getattr(w, "dvc", None),
+        dvc=getattr(w, "dvc", None), step_rule=getattr(w, "step_rule", 0),
     )
 
 

@@ -1019,12 +1019,12 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base, int64_t n)
             }
         }
     if (fused_zl_lds_bytes(n) <= fused_lds_limit()) // z in LDS beside a float32 y
-        for (int lpr : {8, 16})
+        for (int lpr : {8, 16, 32})
             for (int vec : {4, 8}) {
                 FusedCfg t = base;
                 t.lpr = lpr;
                 t.vec = vec;
-                t.cap = 256 / (lpr * vec);
+                t.cap = 0;
                 t.acc64 = 0;
                 t.zl = 1;
                 out.push_back(t);
@@ -1158,7 +1158,8 @@ size_t problem_plan_bytes(int64_t m, int64_t n, bool has_f32, int lp, const smx_
     pp.n = n;
     pp.tv_rows = d->tv_rows;
     pp.tv_cols = d->tv_cols;
-    const size_t pgrid = size_t(phase_grid(pp)), trials = size_t(std::max(1, d->max_trials));
+    const size_t pgrid = size_t(phase_grid(pp)),
+                 trials = d->step_rule == SMX_STEP_ADAPTIVE ? 1 : size_t(std::max(1, d->max_trials));
     add(8 * size_t(kMaxPassGrid) * B); // pass partials
     add(8 * size_t(kMaxPassGrid) * B); // query partials
     add(8 * pgrid * B * 2);
@@ -1224,6 +1225,8 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         if (!(d->tv_eps >= 0.0) || !std::isfinite(d->tv_eps)) return fail(SMX_EINVAL, "tv_eps must be >= 0");
     }
     if (d->obj_kind == SMX_OBJ_LINEAR && !d->linear_c) return fail(SMX_EINVAL, "LINEAR objective needs linear_c");
+    if (d->step_rule != SMX_STEP_POWER && d->step_rule != SMX_STEP_ADAPTIVE)
+        return fail(SMX_EINVAL, "unknown step rule %d", d->step_rule);
     if (!d->lower || !d->upper) return fail(SMX_EINVAL, "lower and upper bounds are required");
     if (d->history_cap < 0) return fail(SMX_EINVAL, "history_cap must be >= 0");
     StopParams sp{};
@@ -1294,6 +1297,11 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     pp.n_red = std::max(1, d->n_red);
     pp.restart_every = d->restart_every;
     pp.max_trials = std::max(1, d->max_trials);
+    pp.adaptive = d->step_rule == SMX_STEP_ADAPTIVE ? 1 : 0;
+    if (pp.adaptive) { // one step per phase
+        pp.n_red = 1;
+        pp.max_trials = 1;
+    }
     pp.first_width = std::min(pp.max_trials, kFirstWidth);
     upload(p->lower, lo, s, "bounds");
     upload(p->upper, up, s, "bounds");
@@ -2031,6 +2039,7 @@ int smx_get_state(smx_problem *p, smx_slice_state *states, float *x)
                 states[s].var_n = st[s].var_n;
                 states[s].var_mean = st[s].var_mean;
                 states[s].var_m2 = st[s].var_m2;
+                states[s].f_ref = st[s].f_ref;
             }
         if (x) hip_check(hipMemcpy(x, p->x.p, sizeof(float) * p->n * p->B, hipMemcpyDeviceToHost), "read x");
         return SMX_OK;
@@ -2064,6 +2073,7 @@ int smx_set_state(smx_problem *p, const smx_slice_state *states, const float *x)
                 st[s].var_n = states[s].var_n;
                 st[s].var_mean = states[s].var_mean;
                 st[s].var_m2 = states[s].var_m2;
+                st[s].f_ref = states[s].f_ref;
                 st[s].phase = 0;
                 st[s].live = (st[s].enabled && st[s].k < st[s].k_end && st[s].stop_reason == STOP_NONE) ? 1 : 0;
             }

@@ -742,6 +742,7 @@ __device__ inline void finish_iteration(const SliceState *__restrict__ st_in, Sl
                 S.k += 1;
                 if (S.stop_on) stop_rules_after_step(S, prox);
             }
+            if (!isnan(S.f_cur)) S.f_ref = S.f_cur; // where this iteration's phase ended
             S.f_start = S.f_cur = nan64();
             S.trials_it = 0;
             S.accepts_it = 0;
@@ -1625,7 +1626,12 @@ __global__ __launch_bounds__(kBlock) void k_query_prox(SliceState *__restrict__ 
 // ([value][slice*tiles + tile]) so the re-derivation reads them coalesced.
 // ---------------------------------------------------------------------------
 
-__device__ inline double trial_beta(const PertParams &pp, long long e) { return pp.gamma * pow(pp.alpha, (double)e); }
+// Step of trial e (the trial exponent): the power law gamma alpha^e, or the
+// phase's adaptive step (Section 2.1.2), the same for its one trial.
+__device__ inline double trial_beta(const PertParams &pp, const SliceState &S, long long e)
+{
+    return pp.adaptive ? S.beta_ad : pp.gamma * pow(pp.alpha, (double)e);
+}
 
 // Number of trials a trial launch evaluates for slice state S: a short batch
 // when a reduction step starts, all remaining ones (up to the cap) after that.
@@ -1720,6 +1726,10 @@ __device__ inline void open_phase_state(SliceState &S, const PertParams &pp, dou
     S.f_start = S.f_cur = f;
     if (!isfinite(f) || !isfinite(S.gn)) S.nonfinite = 1;
     S.phase = (S.gn > 0.0 && isfinite(S.gn)) ? 1 : 0;
+    if (pp.adaptive) { // one step to the reference value, none before there is one or when f is at or below it
+        if (S.phase && !isnan(S.f_ref) && f > S.f_ref) S.beta_ad = (f - S.f_ref) / S.gn;
+        else S.phase = 0;
+    }
 }
 
 // Every workgroup: the state after the previous trial launch of slice s, in
@@ -1752,7 +1762,7 @@ __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, con
     if (threadIdx.x == 0) {
         SliceState &S = sS;
         if (acc_t >= 0) {
-            S.s_acc = S.s_acc + trial_beta(pp, S.ell + acc_t);
+            S.s_acc = S.s_acc + trial_beta(pp, S, S.ell + acc_t);
             S.f_cur = acc_f;
             if (!isfinite(acc_f)) S.nonfinite = 1;
             S.ell += acc_t + 1;
@@ -1770,7 +1780,7 @@ __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, con
             S.trials += ntr;
             S.step_tried += ntr;
             if (S.step_tried >= pp.max_trials) {
-                S.cap_hits += 1;
+                if (!pp.adaptive) S.cap_hits += 1; // a rejected adaptive step simply ends the phase
                 S.need_last = pp.max_trials;
                 S.phase = 0;
             }
@@ -2006,7 +2016,7 @@ __global__ __launch_bounds__(kTrialBlock) void k_trial_tv(float *__restrict__ x,
     publish_state(S, st_out, s, false);
     const long long nslots = (long long)B * nt, slot = (long long)s * nt + blockIdx.x;
     const double inv_gn = 1.0 / S.gn;
-    for (int t = threadIdx.x; t < ntr; t += kTrialBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
+    for (int t = threadIdx.x; t < ntr; t += kTrialBlock) coef[t] = S.s_acc + trial_beta(pp, S, S.ell + t);
     __syncthreads();
     double x00[4], x10[4], x01[4], v00[4], v10[4], v01[4];
     bool has[4];
@@ -2103,7 +2113,7 @@ __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, co
     if (ntr == 0) return;
     const long long nslots = (long long)B * nt, slot = (long long)s * nt + blockIdx.x;
     const double inv_gn = 1.0 / S.gn;
-    for (int t = threadIdx.x; t < ntr; t += kBlock) coef[t] = S.s_acc + trial_beta(pp, S.ell + t);
+    for (int t = threadIdx.x; t < ntr; t += kBlock) coef[t] = S.s_acc + trial_beta(pp, S, S.ell + t);
     __syncthreads();
     for (int t0 = 0; t0 < ntr; t0 += kTrialChunk) {
         double acc[kTrialChunk];
@@ -2247,7 +2257,8 @@ __global__ void k_init_state(SliceState *st, int B, StopParams sp)
     S.stop_var = sp.var;
     S.stop_reason = STOP_NONE;
     S.dp_run = S.feas_ok = S.ran = 0;
-    S.p_last = S.f_last = __longlong_as_double(0x7ff8000000000000LL);
+    S.p_last = S.f_last = S.f_ref = __longlong_as_double(0x7ff8000000000000LL);
+    S.beta_ad = 0.0;
     S.var_n = S.var_mean = S.var_m2 = 0.0;
     st[s] = S;
 }
@@ -2315,7 +2326,8 @@ __global__ void k_reset_slot(SliceState *st, int s, long long budget)
     S.need_last = 0;
     S.stop_reason = STOP_NONE;
     S.dp_run = S.feas_ok = S.ran = 0;
-    S.p_last = S.f_last = __longlong_as_double(0x7ff8000000000000LL);
+    S.p_last = S.f_last = S.f_ref = __longlong_as_double(0x7ff8000000000000LL);
+    S.beta_ad = 0.0;
     S.var_n = S.var_mean = S.var_m2 = 0.0;
     st[s] = S;
 }
@@ -2945,14 +2957,15 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
 // z_j through the vector memory path once per stored entry, about one
 // address per CU per clock, which bounds it on long operators.  Here each
 // workgroup (one per CU, 1024 threads) first copies all of z into LDS, beside
-// a float32 copy of y (2 x 4n bytes, n up to about 20k), and gathers from
-// there.  A group of LPR lanes keeps a row's first CAP*LPR*VEC = 256 entries
-// in registers for the scatter of c_i a_i (longer rows read the rest again),
-// lane l holding the chunk slots of lane (l + group) mod LPR, so that
-// neighbouring rows, which list the same columns in the same order, add into
-// different LDS words in one atomic instruction.  y leaves as one float32
-// partial vector per workgroup; k_fused_apply adds them in float64.
-template <int LPR, int VEC, int CAP, typename VT>
+// a float32 copy of y (2 x 4n bytes, n up to about 20k), and runs the rows as
+// the LDS-staged pass 1 does (LPR lanes per row, four loads of VEC entries in
+// flight per lane, rows strided over the grid), gathering from LDS; a row
+// outside its band then reads its entries again (from the cache) and adds
+// c_i a_i into y with LDS atomics, each group of a wave starting at another
+// chunk so that neighbouring rows, which list the same columns in the same
+// order, touch different words at once.  y leaves as one float32 partial
+// vector per workgroup; k_fused_apply adds them in float64.
+template <int LPR, int VEC, typename VT>
 __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const float *__restrict__ x,
                                                           const float *__restrict__ lower,
                                                           const float *__restrict__ upper, RowW w,
@@ -2963,63 +2976,50 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
     float *zl = reinterpret_cast<float *>(fused_lds);
     float *y = zl + ((n + 3) & ~3);
     __shared__ double lds[kFusedBlock / 64];
-    __shared__ int range[2];
     constexpr int RPB = kFusedBlock / LPR;
     constexpr int STEP = LPR * VEC;
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
-    const int slot = (lane + grp) & (LPR - 1);
     const bool live = st[0].live != 0;
     for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = 0.f;
-    if (live) stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
-    if (threadIdx.x == 0) { // an equal share of the stored entries
-        const long long total = A.ptr[A.rows];
-        range[0] = first_row_at(A.ptr, (int)A.rows, total * blockIdx.x / gridDim.x);
-        range[1] = first_row_at(A.ptr, (int)A.rows, total * (blockIdx.x + 1) / gridDim.x);
-    }
-    __syncthreads();
-    const int r0 = range[0], r1 = range[1];
     double pacc[1] = {0.0};
     if (live) {
-        for (int row = r0 + grp; row < r1; row += RPB) {
+        stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
+        __syncthreads();
+        const long long stride = (long long)gridDim.x * RPB;
+        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
             const int beg = A.ptr[row], end = A.ptr[row + 1];
-            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row];
-            RowRegs<VEC, CAP> R;
-            fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, R);
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < CAP; ++q)
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) acc = fma((double)R.v[q][e], (double)zl[R.c[q][e]], acc);
-            const bool tail = end - beg > CAP * STEP;
-            if (tail)
-                for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
+            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
+            if (lane == 0) {
+                lo = lower[row];
+                up = upper[row];
+                d = w.D[row];
+                sw = w.S[row];
+            }
+            const double r =
+                group_sum<LPR>(row_dot_split<LPR, VEC, VT>(A, beg, end, lane, x, zl, n)) * (double)A.vscale_inv;
+            double ct = 0.0;
+            if (lane == 0) {
+                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+                pacc[0] += (double)d * t * t;
+                ct = (double)sw * t;
+            }
+            ct = __shfl(ct, 0, LPR);
+            if (ct != 0.0 && end > beg) {
+                const double sc = ct * (double)A.vscale_inv;
+                const int nch = (end - beg + STEP - 1) / STEP;
+                int q = grp % nch;
+                for (int u = 0; u < nch; ++u) {
+                    const int p = beg + q * STEP + lane * VEC;
+                    if (++q == nch) q = 0;
+                    if (p >= end) continue;
                     float v[VEC];
                     int c[VEC];
                     Entries<VT, VEC>::load(A, p, v, c);
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) acc = fma((double)v[e], (double)zl[c[e]], acc);
-                }
-            const double r = group_sum<LPR>(acc) * (double)A.vscale_inv;
-            const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-            const double dt = (double)d * t, ct = (double)sw * t;
-            if (lane == 0) pacc[0] += dt * t;
-            if (ct != 0.0) {
-                const double sc = ct * (double)A.vscale_inv;
-#pragma unroll
-                for (int q = 0; q < CAP; ++q)
-#pragma unroll
                     for (int e = 0; e < VEC; ++e)
-                        if (R.v[q][e] != 0.f) atomicAdd(&y[R.c[q][e]], (float)(sc * (double)R.v[q][e]));
-                if (tail)
-                    for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
-                        float v[VEC];
-                        int c[VEC];
-                        Entries<VT, VEC>::load(A, p, v, c);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e)
-                            if (v[e] != 0.f) atomicAdd(&y[c[e]], (float)(sc * (double)v[e]));
-                    }
+                        if (v[e] != 0.f) atomicAdd(&y[c[e]], (float)(sc * (double)v[e]));
+                }
             }
         }
     }
@@ -3062,20 +3062,15 @@ struct FusedArgs {
 template <int LPR, typename VT, int VEC>
 hipError_t fused_zl_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
 {
-    constexpr int CAP = 256 / (LPR * VEC);
-    if constexpr (LPR > 16 || CAP < 1) {
-        return hipErrorInvalidValue;
-    } else {
-        if (cfg.cap != CAP) return hipErrorInvalidValue;
-        auto kern = k_fused_zl<LPR, VEC, CAP, VT>;
-        const size_t bytes = fused_zl_lds_bytes(a.n);
-        if (prepare)
-            return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kFusedBlock), bytes, s, *a.A, (int)a.n, a.x, a.lower, a.upper,
-                           a.w, a.st, a.partials, static_cast<float *>(a.ypart));
-        return hipGetLastError();
-    }
+    if (cfg.cap != 0) return hipErrorInvalidValue;
+    auto kern = k_fused_zl<LPR, VEC, VT>;
+    const size_t bytes = fused_zl_lds_bytes(a.n);
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)bytes);
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kFusedBlock), bytes, s, *a.A, (int)a.n, a.x, a.lower, a.upper, a.w,
+                       a.st, a.partials, static_cast<float *>(a.ypart));
+    return hipGetLastError();
 }
 
 template <int LPR, typename VT, int VEC, typename AccT>

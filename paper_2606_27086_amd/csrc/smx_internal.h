@@ -70,6 +70,8 @@ struct SliceState {
     double stop_prox, stop_dprox, stop_dobj, stop_var;
     double p_last, f_last;            // last recorded proximity; f(x^k) of the last phase
     double var_n, var_mean, var_m2;   // running statistics of the relative iterate changes
+    double f_ref;   // f where the last perturbation phase ended (NaN before the first): the adaptive step's reference
+    double beta_ad; // the adaptive step of the current phase
 };
 
 enum StopReason : int { STOP_NONE = 0, STOP_PROX = 1, STOP_DPROX = 2, STOP_MAXIT = 3, STOP_VAR = 4, STOP_SM = 5 };
@@ -90,6 +92,7 @@ struct PertParams {
     double gamma, alpha;
     int n_red, restart_every, max_trials;
     int first_width; // trials evaluated by a trial launch that starts a reduction step
+    int adaptive;    // 1: the adaptive step (one trial per phase, beta from the state); 0: the power law
 };
 
 struct Hist {
@@ -190,7 +193,7 @@ struct FusedCfg {
                // registers (cap * lpr * vec = 256 entries)
     int grid;  // workgroups, each with an LDS copy of y
     int acc64; // 1: float64 LDS accumulators, 0: float32
-    int zl = 0; // 1: z staged in LDS beside a float32 y (k_fused_zl; acc64 = 0, cap = 256/(lpr*vec), lpr <= 16)
+    int zl = 0; // 1: z staged in LDS beside a float32 y (k_fused_zl; acc64 = 0, cap = 0)
 };
 
 // Column layout grouped by image tiles (A^T for an operator whose unknowns

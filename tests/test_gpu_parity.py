@@ -262,7 +262,7 @@ def test_ct_small_tv_paper_parameters(smx):
 
 
 STATE_FIELDS = ("k", "ell", "restarts", "trials", "accepts", "cap_hits", "stop_reason", "dp_run", "feas_ok",
-                "p_last", "f_last", "var_n", "var_mean", "var_m2")
+                "p_last", "f_last", "var_n", "var_mean", "var_m2", "f_ref")
 
 
 def device_state(so):
@@ -731,7 +731,7 @@ def test_set_fused_switches_kernels(smx):
 
 
 FUSED_SHAPES = [(8, 4, 0, 0), (8, 8, 0, 0), (16, 4, 0, 0), (16, 4, 4, 0), (16, 8, 0, 0), (16, 8, 2, 0), (32, 4, 0, 0),
-                (32, 4, 2, 0), (32, 8, 0, 0), (32, 8, 1, 0), (8, 4, 8, 1), (8, 8, 4, 1), (16, 4, 4, 1), (16, 8, 2, 1)]
+                (32, 4, 2, 0), (32, 8, 0, 0), (32, 8, 1, 0), (8, 4, 0, 1), (8, 8, 0, 1), (16, 4, 0, 1), (32, 8, 0, 1)]
 
 
 @pytest.mark.parametrize("case", ["rt", "long_rows"])
@@ -768,6 +768,55 @@ def test_every_fused_shape(smx, case):
     p = smx.problem_from_workload(w, storage=storage)
     with pytest.raises(smx.SmxError):
         p.set_fused_shape(8, 4, 8)
+    p.close()
+
+
+# ---------------------------------------------------------------------------
+# adaptive step size (Section 2.1.2; the sixth strategy of the CT experiment)
+# ---------------------------------------------------------------------------
+
+ADAPTIVE_CASES = {
+    "dense_sqnorm": lambda: W.dense_small(K=60),
+    "ct_tv_emr": lambda: W.ct(N=48, n_angles=36, seed=7, K=40).with_params(basic=W.BASIC_EMR),
+    "ct_tv": lambda: W.ct(N=48, n_angles=36, seed=8, K=40),
+    "rt_linear": lambda: W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=10, K=30),
+    "edge_rows_l1": lambda: W.random_sparse(3000, 2000, 12, seed=44, empty_frac=0.08, long_rows=2, obj=W.OBJ_L1,
+                                            K=25),
+}
+
+
+@pytest.mark.parametrize("case", list(ADAPTIVE_CASES))
+def test_adaptive_step_parity(smx, case):
+    """The adaptive step (beta = (f(x^k) - f_ref)/||g|| toward where the last
+    phase ended) against the oracle: decisions, iterate, proximities; TV and
+    EMR with the conditioning-aware tolerance.  Then two slices at once."""
+    w = ADAPTIVE_CASES[case]().with_params(step_rule=W.STEP_ADAPTIVE)
+    sensitive = w.obj == W.OBJ_TV2D or getattr(w, "basic", 0) == W.BASIC_EMR
+    x, h = check_parity(smx, w, w.K, sensitive=sensitive)
+    assert h["trials"][0, 0] == 0 and np.all(h["trials"] <= 1)
+    if case == "ct_tv":
+        wb = W.ct(N=48, n_angles=36, seed=8, K=40, B=2).with_params(step_rule=W.STEP_ADAPTIVE)
+        check_parity(smx, wb, wb.K, sensitive=True)
+
+
+def test_adaptive_step_lockstep(smx):
+    """Oracle-driven single iterations (CT-48, TV, EMR, adaptive step): every
+    iterate, proximity, decision and the reference value f_ref at 1e-5."""
+    w = W.ct(N=48, n_angles=36, seed=7, K=30).with_params(basic=W.BASIC_EMR, step_rule=W.STEP_ADAPTIVE)
+    say("ct48 lockstep, EMR, adaptive step")
+    p = smx.problem_from_workload(w, history_cap=w.K)
+    P = oracle.from_workload(w)
+    x = w.x0[:, 0].astype(np.float32).astype(np.float64)
+    so = oracle.State()
+    po = []
+    for k in range(w.K):
+        xg, sg, xo, so1, pk = step_from_oracle(p, P, x, so)
+        check_step(xg, sg, xo, so1, False, RTOL, k)
+        if not np.isnan(so1.f_ref):
+            assert abs(sg["f_ref"] - so1.f_ref) <= RTOL * abs(so1.f_ref), (k, sg["f_ref"], so1.f_ref)
+        po.append(pk)
+        x, so = xo.astype(np.float32).astype(np.float64), so1
+    check_step_proximities(p, range(w.K), po, RTOL)
     p.close()
 
 

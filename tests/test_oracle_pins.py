@@ -360,6 +360,76 @@ def test_phase_never_increases_objective(orc):
     assert np.all(h.accepts <= h.trials)
 
 
+# ---------------------------------------------------------------------------
+# Adaptive step size (Section 2.1.2): beta = (f(x^k) - f_ref)/||g|| when
+# f(x^k) > f_ref, else no step; f_ref is f after the previous phase, f(x^0)
+# before the first
+# ---------------------------------------------------------------------------
+
+def test_adaptive_step_sqnorm_closed_form(orc):
+    """f = ||x||^2: g = 2x, v = -x/||x||, so the step to f_ref = c lands on
+    z = x (||x||^2 + c) / (2 ||x||^2), always accepted (f(z) <= f(x) iff
+    c <= ||x||^2), and f_ref becomes f(z).  The first phase (no reference
+    yet) does not move; a point already at or below the reference is not
+    moved, and the reference becomes its value."""
+    P = _unconstrained(orc, 5, W.OBJ_SQNORM, step_rule=orc.STEP_ADAPTIVE)
+    x0 = np.array([1.0, -2.0, 0.5, 3.0, -1.5])
+    z, st = P.perturb(x0)
+    assert np.array_equal(z, x0) and st.f_ref == np.dot(x0, x0) and st.ell == 0
+    r2 = float(np.dot(x0, x0))
+    for c in (0.0, 0.3 * r2, 0.99 * r2):
+        st = orc.State()
+        st.f_ref = c
+        z, s1 = P.perturb(x0, st)
+        np.testing.assert_allclose(z, x0 * (r2 + c) / (2 * r2), rtol=1e-14)
+        assert s1.f_ref == pytest.approx((r2 + c) ** 2 / (4 * r2), rel=1e-14) and s1.ell == 1
+    st = orc.State()
+    st.f_ref = 2 * r2
+    z, s1 = P.perturb(x0, st)
+    assert np.array_equal(z, x0) and s1.f_ref == r2 and s1.ell == 0
+
+
+def test_adaptive_step_linear_reaches_the_reference(orc):
+    """f = c^T x: g = c, so the step beta = (c^T x - f_ref)/||c|| along
+    -c/||c|| lands exactly on the level f_ref (f decreases by beta ||c||)."""
+    rng = np.random.default_rng(3)
+    c = rng.uniform(0.1, 1.0, 6)
+    P = _unconstrained(orc, 6, W.OBJ_LINEAR, linear_c=c, step_rule=orc.STEP_ADAPTIVE)
+    x = rng.uniform(0.0, 2.0, 6)
+    st = orc.State()
+    st.f_ref = 0.25 * float(c @ x)
+    z, s1 = P.perturb(x, st)
+    assert float(c @ z) == pytest.approx(0.25 * float(c @ x), rel=1e-13)
+    np.testing.assert_allclose(z, x - (0.75 * float(c @ x) / float(c @ c)) * c, rtol=1e-13)
+    assert s1.f_ref == pytest.approx(float(c @ z), rel=1e-15)
+
+
+def test_adaptive_step_run(orc):
+    """A superiorized run with the adaptive step (TV on a small CT image): at
+    most one trial per iteration, none in the first; every phase ends at or
+    below where it started; each phase's reference is where the previous
+    phase ended (the first step aims at f(x^0)), checked by replaying each
+    phase alone from the run's states; the run is resumable."""
+    w = W.ct(N=24, n_angles=16, seed=5, K=25).with_params(step_rule=W.STEP_ADAPTIVE)
+    P = orc.from_workload(w)
+    x, st, h = P.run(w.x0[:, 0], 25)
+    assert h.trials[0] == 0 and np.all(h.trials <= 1) and h.trials.sum() > 5 and h.accepts.sum() > 0
+    ok = ~np.isnan(h.f_start)
+    assert np.all(h.f_end[ok] <= h.f_start[ok])
+    xs, ss = w.x0[:, 0].astype(np.float64), None
+    for k in range(25):
+        ref = (ss.f_ref if ss is not None else np.nan)
+        z, sz = P.perturb(xs, ss)
+        assert sz.f_ref == pytest.approx(h.f_end[k], rel=1e-14)
+        if k > 0 and h.trials[k]:
+            assert h.f_start[k] > ref
+        xs, ss, _ = P.run(xs, 1, state=ss)
+    assert np.array_equal(xs, x)
+    x1, s1, _ = P.run(w.x0[:, 0], 10)
+    x2, _, _ = P.run(x1, 15, state=s1)
+    assert np.array_equal(x2, x)
+
+
 def test_perturb_then_step_is_one_iteration(orc):
     """The perturbation phase alone, then the feasibility step, is one outer
     iteration (bitwise); on f = ||x||^2 the phase of the first iteration is

@@ -76,9 +76,10 @@ def test_dense_case_is_consistent():
     assert np.all((w.x_true >= 0) & (w.x_true <= 1))
 
 
-def test_rt_cpp_generator_matches_numpy_model():
-    a = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=10)
-    b = W.rt_large(grid=(20, 20, 10), beamlets=(6, 6), spacing=2.4, rho=2.0, r_cut=6.4)
+@pytest.mark.parametrize("angle", [0.0, 0.37])
+def test_rt_cpp_generator_matches_numpy_model(angle):
+    a = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=10, angle_offset=angle)
+    b = W.rt_large(grid=(20, 20, 10), beamlets=(6, 6), spacing=2.4, rho=2.0, r_cut=6.4, angle_offset=angle)
     for f in ("row_ptr", "col_idx", "lower", "upper"):
         assert np.array_equal(getattr(a, f), getattr(b, f)), f
     np.testing.assert_allclose(b.val, a.val, rtol=1e-6)

@@ -23,6 +23,7 @@ import numpy as np
 OBJ_NONE, OBJ_SQNORM, OBJ_TV2D, OBJ_LINEAR, OBJ_L1 = 0, 1, 2, 3, 4
 BASIC_SIMULT, BASIC_DROP, BASIC_CQ, BASIC_EL, BASIC_EMR = 0, 1, 2, 3, 4
 DVC_MAX, DVC_MIN = 0, 1  # dose-volume constraint senses: D_V <= d, D_V >= d
+STEP_POWER, STEP_ADAPTIVE = 0, 1  # perturbation step size: power law gamma alpha^ell, adaptive (Section 2.1.2)
 OBJ_NAMES = {OBJ_NONE: "none", OBJ_SQNORM: "sqnorm", OBJ_TV2D: "tv2d", OBJ_LINEAR: "linear", OBJ_L1: "l1"}
 
 
@@ -61,6 +62,7 @@ class Workload:
     K: int = 100
     weights: Optional[np.ndarray] = None  # float64 [m]; None means uniform 1/m
     basic: int = 0  # BASIC_*: the feasibility-seeking step
+    step_rule: int = STEP_POWER  # STEP_*: the perturbation's step size
     stop: Optional[dict] = None  # stopping rules: prox, dprox, n, max_iters, dobj, var (None: fixed K)
     # dose-volume constraints: dicts with row_begin, row_end (the structure's
     # rows), sense (DVC_MAX / DVC_MIN), fraction (V) and dose (d)
@@ -543,6 +545,15 @@ def rt_with_dvc(w: "Workload", basic: int = BASIC_EMR) -> "Workload":
     return out.with_params(basic=basic, gamma=1.0, alpha=0.7, restart_every=500)
 
 
+def rt_plan(seed: int, K: int = 300, n_beams: int = 9) -> "Workload":
+    """A radiotherapy plan of the 160 x 160 x 80 configuration's shape for a
+    serving stream (one operator per plan): the beam set rotated by a seeded
+    angle in [0, 2 pi / n_beams)."""
+    rng = np.random.default_rng(seed)
+    w = rt_large(seed=seed, K=K, n_beams=n_beams, angle_offset=float(rng.uniform(0.0, 2 * np.pi / n_beams)))
+    return replace(w, name=f"rt_plan{seed}")
+
+
 def synthetic_iterate(w: "Workload", seed: int, spread: float = 0.1) -> np.ndarray:
     """A seeded point of the kind an iteration passes through: the true
     solution (0.5 where none is known) times (1 + spread * N(0, 1)), clipped
@@ -693,11 +704,13 @@ def rt(
     infeasible: bool = True,
     K: int = 300,
     variant: str = "default",
+    angle_offset: float = 0.0,
 ) -> Workload:
     """Synthetic dose-influence matrix and dose bands for fluence planning.
 
     Voxels of an X*Y*Z grid (unit spacing) are rows; beamlets of ``n_beams``
-    coplanar beams (equal angular steps around the z axis) on a
+    coplanar beams (equal angular steps around the z axis, the first at
+    ``angle_offset`` radians) on a
     ``beamlets[0] x beamlets[1]`` grid of the given spacing are columns.
     a_ij = exp(-mu * depth) * exp(-r / rho) for voxels within lateral distance
     ``r_cut`` of the beamlet axis.  The matrix is scaled so that x = 1 gives a
@@ -725,7 +738,7 @@ def rt(
     per_row_cols = []
     per_row_vals = []
     for b in range(n_beams):
-        th = 2 * np.pi * b / n_beams
+        th = angle_offset + 2 * np.pi * b / n_beams
         e_d = np.array([np.cos(th), np.sin(th)])  # beam travels along +e_d
         e_u = np.array([-np.sin(th), np.cos(th)])
         depth = PX * e_d[0] + PY * e_d[1] + half
@@ -894,6 +907,7 @@ def rt_large(
     infeasible: bool = True,
     K: int = 300,
     variant: str = "default",
+    angle_offset: float = 0.0,
 ) -> Workload:
     """The rt() model at full size, generated row by row in C++ (OpenMP).
 
@@ -909,10 +923,10 @@ def rt_large(
     class _P(C.Structure):
         _fields_ = [("X", C.c_int32), ("Y", C.c_int32), ("Z", C.c_int32), ("n_beams", C.c_int32),
                     ("nbu", C.c_int32), ("nbw", C.c_int32), ("spacing", C.c_double), ("mu", C.c_double),
-                    ("rho", C.c_double), ("r_cut", C.c_double)]
+                    ("rho", C.c_double), ("r_cut", C.c_double), ("angle0", C.c_double)]
 
     X, Y, Z = grid
-    P = _P(X, Y, Z, n_beams, beamlets[0], beamlets[1], spacing, mu, rho, r_cut)
+    P = _P(X, Y, Z, n_beams, beamlets[0], beamlets[1], spacing, mu, rho, r_cut, angle_offset)
     nv = X * Y * Z
     n = n_beams * beamlets[0] * beamlets[1]
     counts = np.zeros(nv, np.int64)

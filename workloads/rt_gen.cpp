@@ -4,7 +4,7 @@
 //
 // Model (the same as workloads.rt in Python): voxel centres of an X*Y*Z grid
 // with unit spacing, centred at the origin; n_beams coplanar beams at equal
-// angular steps around the z axis; each beam a grid of nbu x nbw beamlets with
+// angular steps around the z axis, the first at angle0; each beam a grid of nbu x nbw beamlets with
 // the given spacing.  For voxel p and beamlet (b, bu, bw):
 //   depth = p . e_d + half,  u = p . e_u,  w = p_z,
 //   fu = u/spacing + (nbu-1)/2,  fw = w/spacing + (nbw-1)/2,
@@ -20,6 +20,7 @@ struct RtParams {
     int32_t X, Y, Z;
     int32_t n_beams, nbu, nbw;
     double spacing, mu, rho, r_cut;
+    double angle0; // angle of the first beam (radians)
 };
 
 namespace {
@@ -40,7 +41,7 @@ inline void row_entries(const RtParams &P, int64_t v, Emit emit)
     const double half = 0.5 * (P.X > P.Y ? P.X : P.Y);
     const int reach = (int)std::ceil(P.r_cut / P.spacing) + 1;
     for (int b = 0; b < P.n_beams; ++b) {
-        const double th = 2.0 * M_PI * b / P.n_beams;
+        const double th = P.angle0 + 2.0 * M_PI * b / P.n_beams;
         const double ed0 = std::cos(th), ed1 = std::sin(th);
         const double eu0 = -std::sin(th), eu1 = std::cos(th);
         const double depth = px * ed0 + py * ed1 + half;
