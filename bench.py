@@ -288,6 +288,7 @@ def cpu_baseline(w, sample_all=10, sample_one=3, accuracy_k=0):
     P = oracle.from_workload(w)
     P.prepare()
     setup = time.perf_counter() - t0
+    progress(f"oracle setup {setup:.1f}s")
     t0 = time.perf_counter()
     x, st, _ = P.run(w.x0[:, 0], sample_all)
     dt_all = time.perf_counter() - t0
@@ -298,9 +299,13 @@ def cpu_baseline(w, sample_all=10, sample_one=3, accuracy_k=0):
         dt_one = time.perf_counter() - t0
     finally:
         oracle.set_threads(threads)
+    progress(f"oracle timed: {sample_all} iterations in {dt_all:.1f}s, one thread {sample_one} in {dt_one:.1f}s")
     xa = None
     if accuracy_k:
-        xa, _, _ = P.run(x, max(accuracy_k - sample_all, 0), state=st)
+        xa, st_a = x, st
+        for k0 in range(sample_all, accuracy_k, 20):  # in pieces, with a progress line each
+            xa, st_a, _ = P.run(xa, min(20, accuracy_k - k0), state=st_a)
+            progress(f"oracle at iteration {min(k0 + 20, accuracy_k)} of {accuracy_k}")
     rec = dict(value=round(sample_all / dt_all, 3), unit="SM iterations/s", cores=threads, kind="oracle",
                sample=f"{sample_all} iterations from x0 on {threads} threads (FP64, OpenMP over rows; setup timed "
                       f"apart); one thread: {sample_one} iterations; a whole {w.K}-iteration run is extrapolated",
@@ -389,6 +394,7 @@ def section_superiorization(smx, w_rt):
         rec.update(final_superiorized=dict(prox=float(sm[-1, 0]), f=float(sm[-1, 1])),
                    final_feasibility=dict(prox=float(fe[-1, 0]), f=float(fe[-1, 1])))
         out[name] = rec
+        progress(f"superiorization {name}: superior={rec.get('superior')}")
     return out
 
 
@@ -400,10 +406,18 @@ def section_batched(smx, steps, warmup, tune):
         w = W.ct(N=256, seed=2, B=B, K=200)
         r = time_problem(smx, w, storage, steps, warmup, tune=tune)
         out[f"ct256_B{B}_{storage}"] = summarise(w, r, storage, B)
+        progress(f"batched B={B} {storage}: {r['it_s'] * B:.0f} slice-it/s")
     return out
 
 
-def section_serving(smx, tune):
+def section_serving(smx, tune, seeds=5):
+    """Continuous batching: 64 CT solves (128^2 / 256^2 / 512^2, 8-32 slices
+    each, one multi-slot group per operator) and four radiotherapy plans of
+    the 160 x 160 x 80 shape (seeded beam rotations, one operator and one
+    slot each), bf16 A.  First all at t = 0 (capacity), then Poisson
+    arrivals at 80 % of that request rate for `seeds` arrival seeds (the
+    order of the requests shuffled per seed); p50/p99 latency per seed and
+    over every request of every seed."""
     import numpy as np
 
     import paper_2606_27086_amd.serve as srv
@@ -412,41 +426,78 @@ def section_serving(smx, tune):
     ops, reqs, _ = W.serving_mix(sizes=(128, 256, 512), n_requests=64, slices=(8, 32), pool=32, K=200, seed=5)
     specs = {k: srv.OperatorSpec(key=k, m=o["m"], n=o["n"], row_ptr=o["row_ptr"], col_idx=o["col_idx"], val=o["val"],
                                  params=o["params"]) for k, o in ops.items()}
-    server = srv.Server(specs, hbm_budget=200 << 30, slots=32, chunk=10, storage="bf16", autotune=tune)
+    base = [dict(r) for r in reqs]
+    for i, sd in enumerate((41, 42, 43, 44)):
+        wp = W.rt_plan(sd, K=300)
+        key = f"rt_plan{sd}"
+        specs[key] = srv.OperatorSpec(
+            key=key, m=wp.m, n=wp.n, row_ptr=wp.row_ptr, col_idx=wp.col_idx, val=wp.val, slots=1,
+            params=dict(box_lo=wp.box_lo, box_hi=wp.box_hi, lam=wp.lam, obj=wp.obj, linear_c=wp.linear_c,
+                        gamma=wp.gamma, alpha=wp.alpha, n_red=wp.n_red, restart_every=wp.restart_every,
+                        max_trials=wp.max_trials))
+        base.append(dict(rid=1000 + i, op_key=key, lower=wp.lower, upper=wp.upper, x0=wp.x0, K=wp.K))
+        progress(f"serving: plan {key} generated")
+    server = srv.Server(specs, hbm_budget=240 << 30, slots=32, chunk=10, storage="bf16", autotune=tune)
+    for k in sorted(specs):  # one group per operator, created (and tuned) one at a time
+        server._group_for(k)
+        progress(f"serving: group {k} created")
     warm = []
-    for i, k in enumerate(sorted(ops)):  # groups created, tuned and graphs captured before timing
-        r = next(r for r in reqs if r["op_key"] == k)
+    for i, k in enumerate(sorted(specs)):  # groups created, tuned and graphs captured before timing
+        r = next(r for r in base if r["op_key"] == k)
         warm.append(srv.Request(rid=-1 - i, op_key=k, lower=r["lower"][:, :1], upper=r["upper"][:, :1],
                                 x0=r["x0"][:, :1], K=20))
     server.run(warm)
     server.done.clear()
 
-    def requests():
+    def requests(order=None, times=None):
+        rs = [base[i] for i in (order if order is not None else range(len(base)))]
         return [srv.Request(rid=r["rid"], op_key=r["op_key"], lower=r["lower"], upper=r["upper"], x0=r["x0"],
-                            K=r["K"], t_arrival=0.0) for r in reqs]
+                            K=r["K"], t_arrival=0.0 if times is None else float(t)) for r, t in
+                zip(rs, times if times is not None else [0.0] * len(rs))]
 
     def clean(d):
         return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
 
+    def latencies():
+        return np.array([r.t_done - r.t_arrival for r in server.done]), \
+            np.array([r.t_done - r.t_arrival for r in server.done if r.op_key.startswith("rt_plan")])
+
+    progress("serving: groups warmed")
     burst = server.run(requests())
     server.done.clear()
     rate = 0.8 * burst["requests"] / burst["elapsed_s"]
-    rq = requests()
-    rng = np.random.default_rng(1)
-    t = 0.0
-    for r in rq:
-        t += rng.exponential(1.0 / rate)
-        r.t_arrival = t
-    poisson = server.run(rq)
+    progress(f"serving burst: {burst['slice_it_s']:.0f} slice-it/s, p99 {burst['p99_ms']:.0f} ms")
+    per_seed, pooled, pooled_rt = [], [], []
+    for sd in range(1, seeds + 1):
+        rng = np.random.default_rng(sd)
+        order = rng.permutation(len(base))
+        times = np.cumsum(rng.exponential(1.0 / rate, len(base)))
+        st = server.run(requests(order, times))
+        lat, lat_rt = latencies()
+        pooled.append(lat)
+        pooled_rt.append(lat_rt)
+        server.done.clear()
+        per_seed.append(dict(seed=sd, **clean(st)))
+        progress(f"serving seed {sd}: p50 {st['p50_ms']:.0f} ms, p99 {st['p99_ms']:.0f} ms")
     server.close()
-    return dict(workload="64 CT solves: 128^2/256^2/512^2, 8-32 slices each, K=200, bf16 A, 32 slots per operator",
-                burst=clean(burst), poisson=dict(rate_hz=round(rate, 3), **clean(poisson)))
+    lat = np.concatenate(pooled)
+    lat_rt = np.concatenate(pooled_rt)
+    return dict(workload="64 CT solves (128^2/256^2/512^2, 8-32 slices, K=200) + 4 radiotherapy plans (160x160x80, "
+                         "K=300), bf16 A, 32 slots per CT operator, 1 per plan",
+                burst=clean(burst), poisson=dict(rate_hz=round(rate, 3), seeds=per_seed,
+                                                 pooled=dict(samples=int(lat.size),
+                                                             p50_ms=round(float(np.percentile(lat, 50) * 1e3), 3),
+                                                             p99_ms=round(float(np.percentile(lat, 99) * 1e3), 3),
+                                                             rt_plans_p50_ms=round(float(np.percentile(lat_rt, 50) * 1e3), 3),
+                                                             rt_plans_max_ms=round(float(lat_rt.max() * 1e3), 3))))
 
 
 def section_basic(smx, steps, warmup, tune):
-    """The other basic algorithms on the headline CT workload (float32, one
-    slice): SM iterations/s and the proximity after the run.  EMR reads A three
-    times per iteration, EL and EMR keep y between launches."""
+    """The other basic algorithms on the CT workload (float32, one slice): SM
+    iterations/s and the proximity after the run.  EMR reads A three times
+    per iteration, EL and EMR keep y between launches.  Then EMR with two
+    perturbation strategies: the power law with restarts and the adaptive
+    step."""
     import workloads as W
 
     w = W.ct(N=256, seed=2, K=200)
@@ -454,6 +505,16 @@ def section_basic(smx, steps, warmup, tune):
     for name, basic in (("simult", W.BASIC_SIMULT), ("drop", W.BASIC_DROP), ("cq", W.BASIC_CQ),
                         ("el", W.BASIC_EL), ("emr", W.BASIC_EMR)):
         wb = w.with_params(basic=basic, lam=float(w.m) if basic == W.BASIC_DROP else w.lam)
+        r = time_problem(smx, wb, "f32", steps, warmup, tune=tune)
+        out[name] = dict(it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5), prox=r["prox"][0],
+                         obj=r["obj"][0], fused=fused_in_use(r["shapes"]))
+        progress(f"basic {name}: {r['it_s']:.0f} it/s")
+    # perturbation strategies with EMR (the CT experiment of Section 2.3.2):
+    # the power law with restarts (gamma 5, alpha 0.99, 4 reduction steps,
+    # restart every 50) against the adaptive step
+    for name, kw in (("emr_strategy1", dict(gamma=5.0, alpha=0.99, n_red=4, restart_every=50)),
+                     ("emr_adaptive", dict(step_rule=W.STEP_ADAPTIVE))):
+        wb = w.with_params(basic=W.BASIC_EMR, **kw)
         r = time_problem(smx, wb, "f32", steps, warmup, tune=tune)
         out[name] = dict(it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5), prox=r["prox"][0],
                          obj=r["obj"][0], fused=fused_in_use(r["shapes"]))
@@ -491,6 +552,7 @@ def section_seismic(smx, steps, warmup, tune):
             it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5), rel_err_true=round(err, 5),
             prox=r["prox"][0], obj=r["obj"][0], fused=fused_in_use(r["shapes"]),
             format=r["shapes"]["pass1"]["format"])
+        progress(f"seismic {name} noise {noise} {storage}: {r['it_s']:.0f} it/s")
     # straight-ray travel-time tomography: 200 x 400 cells, 100 sources x 200
     # receivers (20,000 rays), TV, float32 against bf16-stored A, 500 iterations
     t0 = time.time()
@@ -522,6 +584,7 @@ def section_dvc(smx, tune, base):
             out[f"{name}_{storage}"] = dict(it_s=round(r["it_s"], 2), ms_per_step=round(r["ms_per_step"], 5),
                                             pass1_ms=round(r["pass1_ms"], 5), pass2_ms=round(r["pass2_ms"], 5),
                                             prox=r["prox"][0], obj=r["obj"][0])
+            progress(f"dose-volume {name} {storage}: {r['it_s']:.0f} it/s")
     return out
 
 
@@ -537,7 +600,64 @@ def section_hbm(smx, tune, w):
         s["roofline"] = roofline_of(w, r, storage, workload=RT_WORKLOAD)
         s["wall_s"] = round(time.time() - t0, 1)
         out[f"{storage}_two_passes"] = s
+        progress(f"two passes {storage}: {s['it_s']} it/s")
     return out
+
+
+_T0 = time.time()
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[{time.time() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+PMC_COPY_BYTES = 512 * 1024 * 1024
+PMC_MARK_BYTES = 64 * 1024 * 1024
+
+
+def pmc_probe():
+    """The launches a hardware-counter run measures (rocprofv3 --pmc, one
+    counter set per run; summarised by pmc_summary.py): a 512 MiB device
+    copy (the reference that scales FETCH_SIZE / WRITE_SIZE to bytes), eager
+    iterations of the CT 256 x 256 workload (float32 and bf16, autotuned), a
+    64 MiB copy marking the boundary, then eager iterations of the
+    radiotherapy workload (float32 and bf16 with the fused pass, and with
+    the two passes), so that every pass launch is its own dispatch."""
+    import torch
+
+    import paper_2606_27086_amd as smx
+    import workloads as W
+
+    smx.lib()
+    torch.cuda.set_device(0)
+
+    def copy(nbytes):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy {nbytes} bytes", file=sys.stderr, flush=True)
+
+    def iterate(w, storage, iters, reps, fused=True):
+        p = smx.problem_from_workload(w, storage=storage, refine_iters=0, fused=fused, op=op_for(smx, w, storage))
+        p.autotune(reps=reps)
+        p.run(iters, perturb=True, graph=False)
+        p.sync()
+        print(w.name, storage, "fused" if fused else "two passes", json.dumps(p.describe()), file=sys.stderr,
+              flush=True)
+        p.close()
+
+    copy(PMC_COPY_BYTES)
+    wc = W.ct(N=256, seed=2, K=200)
+    for st in ("f32", "bf16"):
+        iterate(wc, st, 5, 3)
+    copy(PMC_MARK_BYTES)
+    wr = W.rt_large(seed=4, K=300)
+    for st in ("f32", "bf16"):
+        for fused in (True, False):
+            iterate(wr, st, 3, 2, fused)
 
 
 def main():
@@ -548,10 +668,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run only the launches a hardware-counter run measures (see pmc_probe) and exit")
     ap.add_argument("--sections", default="ct,superiorization,batched,serving,hbm,basic,seismic,dvc",
                     help="sections beside the headline: ct,superiorization,batched,serving,hbm,basic,seismic,dvc "
                          "(empty for none)")
     args = ap.parse_args()
+    if args.pmc_probe:
+        pmc_probe()
+        return
     if args.gpus != 1:
         print("this benchmark runs on one GPU: the single-GPU path is what is built "
               "(the row-sharded multi-GPU design is documented, not built)", file=sys.stderr)
@@ -569,15 +694,14 @@ def main():
     t0 = time.time()
     w = W.rt_large(seed=4, K=300)
     gen_s = time.time() - t0
-    print(f"radiotherapy workload generated in {gen_s:.1f}s: m={w.m} n={w.n} nnz={w.nnz}", file=sys.stderr, flush=True)
+    progress(f"radiotherapy workload generated in {gen_s:.1f}s: m={w.m} n={w.n} nnz={w.nnz}")
     results = {st: time_problem(smx, w, st, args.steps, args.warmup, graph=graph, tune=tune) for st in ("f32", "bf16")}
     main_r = results["f32"]
     variants = {}
     for st, r in results.items():
         variants[f"rt_{st}"] = summarise(w, r, st)
         variants[f"rt_{st}"].update(prox=r["prox"][0], obj=r["obj"][0], repeats_ms=[round(v, 4) for v in r["repeats_ms"]])
-    print(f"headline timed: {main_r['it_s']:.1f} it/s f32, {results['bf16']['it_s']:.1f} bf16", file=sys.stderr,
-          flush=True)
+    progress(f"headline timed: {main_r['it_s']:.1f} it/s f32, {results['bf16']['it_s']:.1f} bf16")
     # the whole configured job, and the accuracy of each path against the oracle after the same iterations
     acc_k = 120
     full_job, finals = {}, {}
@@ -585,9 +709,11 @@ def main():
         x, sec = run_from_x0(smx, w, st, w.K, tune=tune)
         full_job[st] = dict(iterations=w.K, seconds=round(sec, 4), it_s=round(w.K / sec, 2))
         finals[st], _ = run_from_x0(smx, w, st, acc_k, tune=False)
+        progress(f"full job {st}: {full_job[st]['it_s']} it/s")
     cpu, accuracy = None, None
     if not args.no_cpu_baseline:
         cpu, xo, P = cpu_baseline(w, accuracy_k=acc_k)
+        progress(f"oracle: {cpu['value']} it/s on {cpu['cores']} threads, {cpu['one_thread']['value']} on one")
         accuracy = dict(iterations=acc_k, reference="FP64 oracle on the float32 operator",
                         **{st: {k: float(f"{v:.3e}") for k, v in accuracy_of(P, finals[st], xo).items()}
                            for st in ("f32", "bf16")})
@@ -614,6 +740,7 @@ def main():
         "accuracy": accuracy,
     }
     sections = [s for s in args.sections.split(",") if s]
+    progress("headline record done; sections: " + ",".join(sections))
     if "ct" in sections:
         wc = W.ct(N=256, seed=2, K=200)
         for st in ("f32", "bf16"):
@@ -623,18 +750,25 @@ def main():
             variants[f"ct256_{st}"] = v
     if "superiorization" in sections:
         line["superiorization"] = section_superiorization(smx, w)
+        progress("superiorization done")
     if "batched" in sections:
         line["batched"] = section_batched(smx, 100, 10, tune)
+        progress("batched done")
     if "serving" in sections:
         line["serving"] = section_serving(smx, tune)
+        progress("serving done")
     if "hbm" in sections:
         line["hbm_config"] = section_hbm(smx, tune, w)
+        progress("two-pass radiotherapy done")
     if "basic" in sections:
         line["basic_algorithms"] = section_basic(smx, 100, 10, tune)
+        progress("basic algorithms done")
     if "seismic" in sections:
         line["seismic"] = section_seismic(smx, 200, 10, tune)
+        progress("seismic done")
     if "dvc" in sections:
         line["dose_volume"] = section_dvc(smx, tune, w)
+        progress("dose-volume done")
     print(json.dumps(line), flush=True)
 
 

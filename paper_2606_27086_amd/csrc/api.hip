@@ -1302,7 +1302,9 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
         pp.n_red = 1;
         pp.max_trials = 1;
     }
-    pp.first_width = std::min(pp.max_trials, kFirstWidth);
+    // a linear objective accepts its first trial (f(z) - f(x) = -beta ||c||): one
+    // trial per first launch instead of a speculative batch
+    pp.first_width = pp.obj == OBJ_LINEAR ? 1 : std::min(pp.max_trials, kFirstWidth);
     upload(p->lower, lo, s, "bounds");
     upload(p->upper, up, s, "bounds");
     upload(p->box_lo, blo, s, "box");

@@ -44,6 +44,7 @@ class OperatorSpec:
     col_idx: np.ndarray
     val: np.ndarray
     params: dict  # Problem keyword arguments other than bands (box, obj, gamma, ...)
+    slots: Optional[int] = None  # slots of this operator's group (None: the server's default)
 
     @property
     def nnz(self) -> int:
@@ -116,6 +117,9 @@ class Server:
         self.rejected: List[Request] = []
         self._bytes: Dict[str, int] = {}
 
+    def slots_of(self, spec: OperatorSpec) -> int:
+        return int(spec.slots or self.slots)
+
     # -- footprint ---------------------------------------------------------
     def group_bytes(self, spec: OperatorSpec) -> int:
         """Device bytes of a group, from the library's own allocation plan
@@ -123,7 +127,7 @@ class Server:
         The autotuner's temporary copies and captured graphs come on top."""
         b = self._bytes.get(spec.key)
         if b is None:
-            ob, pb = problem_footprint(spec.m, spec.n, spec.nnz, self.storage, keep_f32=True, B=self.slots,
+            ob, pb = problem_footprint(spec.m, spec.n, spec.nnz, self.storage, keep_f32=True, B=self.slots_of(spec),
                                        refine_iters=0, **spec.params)
             b = self._bytes[spec.key] = ob + pb
         return b
@@ -147,7 +151,7 @@ class Server:
             victim = min(idle, key=lambda x: x.last_used)
             victim.close()
             del self.groups[victim.spec.key]
-        g = Group(spec, self.slots, self.storage, self.device)
+        g = Group(spec, self.slots_of(spec), self.storage, self.device)
         if self.autotune:
             g.prob.autotune(reps=5)
         self.groups[key] = g
@@ -173,7 +177,7 @@ class Server:
             while waiting:
                 r = waiting.popleft()
                 spec = self.specs[r.op_key]
-                if r.S > self.slots or self.group_bytes(spec) > self.hbm_budget:
+                if r.S > self.slots_of(spec) or self.group_bytes(spec) > self.hbm_budget:
                     self.rejected.append(r)
                     continue
                 g = self._group_for(r.op_key)

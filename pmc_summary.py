@@ -1,7 +1,8 @@
 """Per-dispatch HBM traffic of the pass kernels (two passes and fused pass)
-from two rocprofv3 --pmc runs of pmc_probe.py (FETCH_SIZE, then WRITE_SIZE, KiB
-per dispatch), each scaled by what the same counter reads for the probe's plain
-device copy of known size, per workload (CT 256x256, radiotherapy).
+from two rocprofv3 --pmc runs of `bench.py --pmc-probe` (FETCH_SIZE, then
+WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for
+the probe's plain device copy of known size, per workload (CT 256x256,
+radiotherapy).
 
 Writes a JSON table keyed by kernel template, stamped with the SHA-256 of the
 kernel source it was measured on (a changed kernel invalidates it).
