@@ -1315,29 +1315,29 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
 // (loads issued four at a time, added in order) and the four sums are added in
 // a fixed order.  Workgroup 0 also closes the outer iteration.
 template <typename AccT>
-__global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__ ypart, int G, int n,
+__global__ __launch_bounds__(kApplyBlock) void k_fused_apply(const AccT *__restrict__ ypart, int G, int n,
                                                         float *__restrict__ x, ColStep cs,
                                                         const SliceState *__restrict__ st_in,
                                                         SliceState *__restrict__ st_out,
                                                         const double *__restrict__ part1, int nparts1, Hist h)
 {
-    __shared__ double red[kBlock / 64][64];
-    __shared__ double lds[4];
+    __shared__ double red[kApplyBlock / 64][64];
+    __shared__ double lds[kApplyBlock / 64];
     const int wid = threadIdx.x >> 6, wl = threadIdx.x & 63;
     double ysq = 0.0; // deferred mode: this thread's share of ||y||^2
     if (st_in[0].live) {
         for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
             const int j = j0 + wl;
-            constexpr int W = kBlock / 64;
+            constexpr int W = kApplyBlock / 64;
             double sum = 0.0;
-            if (j < n) {
+            if (j < n) { // wave w adds partials w, w + W, ... (eight loads in flight)
                 int g = wid;
-                for (; g + 3 * W < G; g += 4 * W) {
-                    double v[4];
+                for (; g + 7 * W < G; g += 8 * W) {
+                    double v[8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = (double)ypart[(long long)(g + u * W) * n + j];
+                    for (int u = 0; u < 8; ++u) v[u] = (double)ypart[(long long)(g + u * W) * n + j];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) sum += v[u];
+                    for (int u = 0; u < 8; ++u) sum += v[u];
                 }
                 for (; g < G; g += W) sum += (double)ypart[(long long)g * n + j];
             }
@@ -1362,10 +1362,10 @@ __global__ __launch_bounds__(kBlock) void k_fused_apply(const AccT *__restrict__
     }
     if (cs.defer) {
         double v[1] = {ysq};
-        block_sum<1>(v, lds);
+        block_sum<1, kApplyBlock>(v, lds);
         if (threadIdx.x == 0) cs.ypart[blockIdx.x] = v[0];
     } else if (blockIdx.x == 0) {
-        finish_iteration(st_in, st_out, 1, part1, nparts1, h, lds);
+        finish_iteration<kApplyBlock>(st_in, st_out, 1, part1, nparts1, h, lds);
     }
 }
 
@@ -3159,10 +3159,10 @@ hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart,
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)fused_apply_grid(n);
     if (cfg.acc64)
-        hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kBlock), 0, s, static_cast<const double *>(ypart),
+        hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const double *>(ypart),
                            cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
     else
-        hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kBlock), 0, s, static_cast<const float *>(ypart),
+        hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const float *>(ypart),
                            cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
     return hipGetLastError();
 }

@@ -16,6 +16,7 @@ constexpr int kTrialBlock = 1024; // threads of a TV trial workgroup (one 16 x 1
 constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
 constexpr int kFusedBlock = 1024; // threads of a fused-pass workgroup (one per CU: its LDS holds y)
 constexpr int kFusedRcBlock = 512; // the same for the register-cached fused pass
+constexpr int kApplyBlock = 1024;  // threads of the fused pass's apply kernel (16 waves share a column's partials)
 
 // Stored formats of A's entries.  The packed kinds hold one 32-bit word per
 // entry: the 16-bit value in the low half, a 16-bit index in the high half
