@@ -105,6 +105,8 @@ def kernel_name(pass_no, shape, B=1, shapes=None):
         f = shapes["fused"]
         acc = "double" if f["acc"] == "f64" else "float"
         if pass_no == 1:
+            if f.get("zl", 0) and f.get("cap", 0):
+                return f"smx::k_fused_zlr<{f['lpr']}, {f['vec']}, {f['cap']}, {VALUE_TAG[f['format']]}>"
             if f.get("zl", 0):
                 return f"smx::k_fused_zl<{f['lpr']}, {f['vec']}, {VALUE_TAG[f['format']]}>"
             if f.get("cap", 0):
@@ -758,7 +760,7 @@ def main():
     for st in ("f32", "bf16"):
         x, sec = run_from_x0(smx, w, st, w.K, tune=tune)
         full_job[st] = dict(iterations=w.K, seconds=round(sec, 4), it_s=round(w.K / sec, 2))
-        finals[st], _ = run_from_x0(smx, w, st, acc_k, tune=False)
+        finals[st], _ = run_from_x0(smx, w, st, acc_k, tune=tune)
         progress(f"full job {st}: {full_job[st]['it_s']} it/s")
     cpu, accuracy = None, None
     if not args.no_cpu_baseline:

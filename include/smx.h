@@ -85,6 +85,12 @@ extern "C" {
 #define SMX_STEP_POWER 0
 #define SMX_STEP_ADAPTIVE 1
 
+/* launch form of the perturbation phase (smx_set_phase_form) */
+#define SMX_PHASE_AUTO 0       /* one launch for short flat problems, else one launch per trial batch */
+#define SMX_PHASE_ONE_LAUNCH 1 /* one launch per phase (squared norm, L1, linear; n <= 20,000) */
+#define SMX_PHASE_BATCHES 2    /* a direction launch, trial launches, a closing launch */
+#define SMX_PHASE_CLOSED_FORM 3 /* linear objective: a direction launch, then the trials in closed form */
+
 /* smx_run flags */
 #define SMX_RUN_PERTURB 1u /* run the perturbation phase of Algorithm 1 */
 #define SMX_RUN_GRAPH 2u   /* replay captured HIP graphs of several iterations */
@@ -448,13 +454,42 @@ int smx_autotune(smx_problem *p, int32_t reps);
  * fused pass is available (mode 1 then changes nothing). */
 int smx_set_fused(smx_problem *p, int32_t mode);
 
+/* Launch form of the perturbation phase of Algorithm 1 (Section 2.1.2: the
+ * normalised negative (sub)gradient, the trial steps with the nonascent test,
+ * n_red reduction steps).  The phase is a chain of reductions over x: the
+ * direction's norm and f(x^k), then f at each batch of trial points.
+ *   SMX_PHASE_BATCHES: a direction launch, trial launches over the whole
+ *     device (one for a short first batch of each reduction step, one for the
+ *     rest up to the trial cap), a closing launch;
+ *   SMX_PHASE_ONE_LAUNCH: the whole phase in one workgroup per slice, x and
+ *     the direction in its LDS, trials in batches of 8 (squared norm, L1 and
+ *     linear objectives, n <= 20,000);
+ *   SMX_PHASE_CLOSED_FORM (linear objective f = c^T x): the direction
+ *     launch (f(x^k), ||c||), then one launch in which every workgroup takes
+ *     each trial's value from f(x + t v) = f(x) - t ||c|| (v = -c/||c||), so
+ *     no trial needs a pass over x, and adds the accepted step;
+ *   SMX_PHASE_AUTO (the default): ONE_LAUNCH for those objectives up to
+ *     n = 8,192 (there the chain of launches, not the arithmetic, sets the
+ *     phase's time; one workgroup reads x at one compute unit's rate, so on
+ *     longer vectors it is no faster than the chain), else CLOSED_FORM for
+ *     the linear objective, else BATCHES.
+ * Every form accepts the same trial (the first acceptable one in order) and
+ * keeps the same state; they differ in the order of the float64 sums of f
+ * (and CLOSED_FORM in taking a trial's value from the identity), so a
+ * decision taken within rounding of the acceptance threshold can differ
+ * between them.  Errors: SMX_EINVAL for another form, SMX_ESTATE for
+ * ONE_LAUNCH on an objective or size it does not take or CLOSED_FORM on
+ * another objective. */
+int smx_set_phase_form(smx_problem *p, int32_t form);
+
 /* Pin the launch shape of the fused pass instead of the default or the
  * autotuner's choice: lanes per row (8, 16, 32), entries per load (4, 8) and
  * cap: 0 to read a row's entries again for the scatter, or 256/(lpr*vec) (16
  * or 32 lanes only) to keep 256 entries of each row in registers.  With
- * z_in_lds != 0 (cap 0, problems whose n is at most about 20k): every
- * workgroup first copies the whole point z into LDS beside a float32 copy of
- * y and gathers from there instead of from memory.
+ * z_in_lds != 0 (problems whose n is at most about 20k): every workgroup
+ * first copies the whole point z into LDS beside a float32 copy of y and
+ * gathers from there instead of from memory; cap is then 0 or 16/vec (each
+ * lane keeps 16 entries of its row in registers for the scatter).
  * Results do not depend on the shape beyond floating-point summation order.
  * Errors: SMX_ESTATE when the problem has no fused pass, SMX_EINVAL for
  * another shape. */
@@ -464,8 +499,9 @@ int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap, i
  * Synchronises. */
 int smx_stop_status(smx_problem *p, int32_t *reason);
 
-/* JSON description of the launch shapes in use and of the device bytes the
- * problem ("device_bytes") and its operator ("operator_bytes") hold
+/* JSON description of the launch shapes in use, of the device bytes the
+ * problem ("device_bytes") and its operator ("operator_bytes") hold and of
+ * the launches one perturbation phase takes ("phase_launches")
  * (NUL-terminated, truncated to cap bytes); *need (if non-NULL) receives the
  * full size. */
 int smx_describe(const smx_problem *p, char *buf, size_t cap, size_t *need);

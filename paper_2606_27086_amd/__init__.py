@@ -55,6 +55,7 @@ EXPORTS = [
     "smx_describe",
     "smx_set_fused",
     "smx_set_fused_shape",
+    "smx_set_phase_form",
     "smx_stop_status",
     "smx_slot_load",
     "smx_slot_load_noalloc",
@@ -65,6 +66,7 @@ EXPORTS = [
 
 
 STEP_POWER, STEP_ADAPTIVE = 0, 1  # smx_problem_desc.step_rule
+PHASE_AUTO, PHASE_ONE_LAUNCH, PHASE_BATCHES, PHASE_CLOSED_FORM = 0, 1, 2, 3  # smx_set_phase_form
 
 
 class SmxError(RuntimeError):
@@ -213,6 +215,7 @@ def lib() -> C.CDLL:
     L.smx_describe.argtypes = [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     L.smx_set_fused.argtypes = [vp, i32]
     L.smx_set_fused_shape.argtypes = [vp, i32, i32, i32, i32]
+    L.smx_set_phase_form.argtypes = [vp, i32]
     L.smx_stop_status.argtypes = [vp, vp]
     for name in EXPORTS:
         if name != "smx_last_error":
@@ -520,6 +523,13 @@ class Problem:
         """Fused single pass for one-slice problems where it is available (on),
         or always the two bitwise-reproducible passes (off)."""
         check(lib().smx_set_fused(self.handle, 1 if on else 0))
+
+    def set_phase_form(self, form: int):
+        """Perturbation phase in one launch per slice (PHASE_ONE_LAUNCH), as a
+        chain of trial-batch launches (PHASE_BATCHES), with the linear
+        objective's trials in closed form (PHASE_CLOSED_FORM), or chosen by
+        objective and size (PHASE_AUTO)."""
+        check(lib().smx_set_phase_form(self.handle, int(form)))
 
     def stop_status(self) -> np.ndarray:
         """Why each slice stopped (STOP_*; 0 while it runs)."""

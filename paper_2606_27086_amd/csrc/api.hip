@@ -293,6 +293,7 @@ struct smx_problem {
     // fused single pass (one slice, y in LDS): usable, and in use, per value kind
     bool fused_ok[3] = {false, false, false}, fused[3] = {false, false, false};
     int fused_mode = 1; // 0: always the two passes
+    int phase_form = SMX_PHASE_AUTO; // one launch per perturbation phase where eligible, or one per trial batch
     FusedCfg fcfg[3]{};
     DBuf ypart; // grid x n partial vectors of y = A^T c
     // basic algorithm (SMX_BASIC_*) and what its step needs beyond D
@@ -817,18 +818,74 @@ void enqueue_extrapolated_step(smx_problem *p, int vk, const RowW &rw, int npart
               "extrapolated step");
 }
 
+enum PhaseKind { PHASE_CHAIN, PHASE_SMALL, PHASE_LINEAR };
+
+// How the problem's perturbation phase runs: as asked, or by default in one
+// launch for flat objectives on vectors up to kSmallPhaseAutoN (one
+// workgroup streams x at one CU's rate, about 15 GB/s from memory, so its
+// time grows with n: ~6 us at n = 324, ~28 us at n = 19,881, where the
+// launch chain takes ~22-25 us whatever n), the linear objective beyond that
+// with its trials in closed form, anything else as the chain of launches.
+PhaseKind phase_kind(const smx_problem *p)
+{
+    switch (p->phase_form) {
+    case SMX_PHASE_BATCHES: return PHASE_CHAIN;
+    case SMX_PHASE_ONE_LAUNCH: return PHASE_SMALL;   // eligibility checked when set
+    case SMX_PHASE_CLOSED_FORM: return PHASE_LINEAR; // likewise
+    default:
+        if (phase_in_one_launch(p->pp) && p->n <= kSmallPhaseAutoN) return PHASE_SMALL;
+        return p->pp.obj == OBJ_LINEAR ? PHASE_LINEAR : PHASE_CHAIN;
+    }
+}
+
+// Trial launches of the chain: each reduction step needs at most two (a short
+// batch, then every remaining trial up to the cap).
+int chain_trial_launches(const smx_problem *p)
+{
+    return (p->pp.max_trials > p->pp.first_width ? 2 : 1) * p->pp.n_red;
+}
+
+// State-buffer flips of one perturbation phase: one per launch that moves
+// the state (the chain's trial launches and its closing launch).
+int phase_flips(const smx_problem *p)
+{
+    return phase_kind(p) == PHASE_CHAIN ? chain_trial_launches(p) + 1 : 1;
+}
+
+// Launches of one perturbation phase.
+int phase_launch_count(const smx_problem *p)
+{
+    switch (phase_kind(p)) {
+    case PHASE_SMALL: return 1;
+    case PHASE_LINEAR: return 2;
+    default: return chain_trial_launches(p) + 2;
+    }
+}
+
 // Enqueue one outer iteration with value kind vk on stream s, starting from
 // state buffer `cur`; returns the buffer current after it.
 int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, bool timed, int cur)
 {
     const float *gvec = (p->pp.obj == OBJ_LINEAR) ? p->lin_c.as<float>() : p->g.as<float>();
-    if (perturb && p->pp.obj != OBJ_NONE) {
+    const PhaseKind pk = phase_kind(p);
+    if (perturb && p->pp.obj != OBJ_NONE && pk == PHASE_SMALL) {
+        hip_check(launch_phase_small(p->pp, p->x.as<float>(), p->lin_c.as<float>(), p->state(cur), p->state(cur ^ 1),
+                                     s),
+                  "phase");
+        cur ^= 1;
+    } else if (perturb && p->pp.obj != OBJ_NONE && pk == PHASE_LINEAR) {
         hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(), p->state(cur), 0,
                                p->part_phase.as<double>(), s),
                   "phase");
-        // each reduction step needs at most two trial launches (a short batch,
-        // then every remaining trial up to the cap); a last launch closes the phase
-        const int launches = (p->pp.max_trials > p->pp.first_width ? 2 : 1) * p->pp.n_red;
+        hip_check(launch_trial_linear(p->pp, p->x.as<float>(), p->lin_c.as<float>(), p->state(cur), p->state(cur ^ 1),
+                                      p->part_phase.as<double>(), s),
+                  "linear phase");
+        cur ^= 1;
+    } else if (perturb && p->pp.obj != OBJ_NONE) {
+        hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(), p->state(cur), 0,
+                               p->part_phase.as<double>(), s),
+                  "phase");
+        const int launches = chain_trial_launches(p);
         const double *prev = p->part_phase.as<double>();
         for (int t = 0; t < launches; ++t) {
             double *out = p->part_trial[t & 1].as<double>();
@@ -915,8 +972,7 @@ hipGraphExec_t graph_for(smx_problem *p, int vk, bool perturb, int iters, int cu
     int after = cur;
     {
         const bool pert = perturb && p->pp.obj != OBJ_NONE;
-        const int launches = (p->pp.max_trials > p->pp.first_width ? 2 : 1) * p->pp.n_red;
-        const int flips = (pert ? launches + 1 : 0) + 1;
+        const int flips = (pert ? phase_flips(p) : 0) + 1;
         if ((flips * iters) & 1) after ^= 1;
     }
     *cur_after = after;
@@ -1027,6 +1083,8 @@ std::vector<FusedCfg> fused_candidates(const FusedCfg &base, int64_t n)
                 t.cap = 0;
                 t.acc64 = 0;
                 t.zl = 1;
+                out.push_back(t);
+                t.cap = fused_zl_cap(lpr, vec); // the row's first entries kept in registers
                 out.push_back(t);
             }
     return out;
@@ -1305,6 +1363,7 @@ int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, s
     // a linear objective accepts its first trial (f(z) - f(x) = -beta ||c||): one
     // trial per first launch instead of a speculative batch
     pp.first_width = pp.obj == OBJ_LINEAR ? 1 : std::min(pp.max_trials, kFirstWidth);
+    if (phase_in_one_launch(pp)) hip_check(prepare_phase_small(), "one-launch phase");
     upload(p->lower, lo, s, "bounds");
     upload(p->upper, up, s, "bounds");
     upload(p->box_lo, blo, s, "box");
@@ -1758,9 +1817,9 @@ int describe_impl(const smx_problem *p, char *buf, size_t cap, size_t *need)
                  (long long)(p->op->t_rlist.bytes / 4), (long long)p->op->tiles.slots);
     snprintf(tail, sizeof tail,
              ", \"tuned\": %s, \"row_blocks\": [%d, %d], \"basic\": \"%s\", \"dose_volume\": %d, \"tiles\": %s, "
-             "\"device_bytes\": %zu, \"operator_bytes\": %zu}",
+             "\"device_bytes\": %zu, \"operator_bytes\": %zu, \"phase_launches\": %d}",
              p->tuned ? "true" : "false", p->op->csr.nblk, p->op->csc.nblk, basics[p->basic], p->dvc.n, tiles,
-             p->device_bytes(), p->op->device_bytes());
+             p->device_bytes(), p->op->device_bytes(), p->pp.obj == OBJ_NONE ? 0 : phase_launch_count(p));
     out += tail;
     if (need) *need = out.size() + 1;
     if (buf && cap > 0) {
@@ -2234,9 +2293,32 @@ int smx_set_fused(smx_problem *p, int32_t mode)
     })
 }
 
+int smx_set_phase_form(smx_problem *p, int32_t form)
+{
+    if (!p) return fail(SMX_EINVAL, "NULL problem");
+    if (form < SMX_PHASE_AUTO || form > SMX_PHASE_CLOSED_FORM)
+        return fail(SMX_EINVAL, "phase form must be SMX_PHASE_AUTO, _ONE_LAUNCH, _BATCHES or _CLOSED_FORM (got %d)",
+                    form);
+    SMX_GUARD({
+        if (form == SMX_PHASE_ONE_LAUNCH && !phase_in_one_launch(p->pp))
+            return fail(SMX_ESTATE, "the one-launch phase takes the squared-norm, L1 and linear objectives with "
+                                    "n <= %d (objective %d, n = %lld)",
+                        kSmallPhaseMaxN, p->pp.obj, (long long)p->n);
+        if (form == SMX_PHASE_CLOSED_FORM && p->pp.obj != OBJ_LINEAR)
+            return fail(SMX_ESTATE, "trials in closed form need the linear objective (objective %d)", p->pp.obj);
+        p->phase_form = form;
+        // the launch sequence is baked into captured graphs
+        hip_check(hipStreamSynchronize(p->stream), "sync");
+        for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+        p->graphs.clear();
+        return SMX_OK;
+    })
+}
+
 int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap, int32_t z_in_lds)
 {
     if (!p) return fail(SMX_EINVAL, "NULL problem");
+    if (z_in_lds < 0 || z_in_lds > 1) return fail(SMX_EINVAL, "z_in_lds must be 0 or 1 (got %d)", z_in_lds);
     SMX_GUARD({
         bool any = false;
         for (int vk = 0; vk < 3; ++vk) any = any || p->fused_ok[vk];
@@ -2245,7 +2327,7 @@ int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap, i
         for (int vk = 0; vk < 3; ++vk) {
             if (!p->fused_ok[vk]) continue;
             for (const FusedCfg &c : fused_candidates(p->fcfg[vk], p->n))
-                if (c.lpr == lpr && c.vec == vec && c.cap == cap && c.zl == (z_in_lds ? 1 : 0)) {
+                if (c.lpr == lpr && c.vec == vec && c.cap == cap && c.zl == z_in_lds) {
                     p->fcfg[vk] = c;
                     found = true;
                 }

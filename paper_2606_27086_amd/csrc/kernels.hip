@@ -1740,6 +1740,39 @@ __device__ inline void open_phase_state(SliceState &S, const PertParams &pp, dou
     }
 }
 
+// The state after a batch of ntr trials (steps ell .. ell+ntr-1 of the power
+// law, or the one adaptive step) was evaluated: acc_t is the first trial in
+// order whose objective does not exceed f_cur (-1 when none does), acc_f its
+// objective.  Accepting ends the reduction step (and the phase after n_red of
+// them); a step that reaches the trial cap unaccepted ends the phase.
+__device__ inline void record_decision(SliceState &S, const PertParams &pp, int ntr, int acc_t, double acc_f)
+{
+    if (acc_t >= 0) {
+        S.s_acc = S.s_acc + trial_beta(pp, S, S.ell + acc_t);
+        S.f_cur = acc_f;
+        if (!isfinite(acc_f)) S.nonfinite = 1;
+        S.ell += acc_t + 1;
+        S.trials_it += acc_t + 1;
+        S.trials += acc_t + 1;
+        S.accepts_it += 1;
+        S.accepts += 1;
+        S.n_done += 1;
+        S.need_last = S.step_tried + acc_t + 1;
+        S.step_tried = 0;
+        if (S.n_done >= pp.n_red) S.phase = 0;
+    } else {
+        S.ell += ntr;
+        S.trials_it += ntr;
+        S.trials += ntr;
+        S.step_tried += ntr;
+        if (S.step_tried >= pp.max_trials) {
+            if (!pp.adaptive) S.cap_hits += 1; // a rejected adaptive step simply ends the phase
+            S.need_last = pp.max_trials;
+            S.phase = 0;
+        }
+    }
+}
+
 // Every workgroup: the state after the previous trial launch of slice s, in
 // sS (LDS).  The first trial in order whose objective does not exceed f_cur is
 // accepted; reading stops at the chunk holding it.
@@ -1767,33 +1800,7 @@ __device__ inline void derive_decision(SliceState &sS, const PertParams &pp, con
         __syncthreads();
         if (acc_t >= 0) break;
     }
-    if (threadIdx.x == 0) {
-        SliceState &S = sS;
-        if (acc_t >= 0) {
-            S.s_acc = S.s_acc + trial_beta(pp, S, S.ell + acc_t);
-            S.f_cur = acc_f;
-            if (!isfinite(acc_f)) S.nonfinite = 1;
-            S.ell += acc_t + 1;
-            S.trials_it += acc_t + 1;
-            S.trials += acc_t + 1;
-            S.accepts_it += 1;
-            S.accepts += 1;
-            S.n_done += 1;
-            S.need_last = S.step_tried + acc_t + 1;
-            S.step_tried = 0;
-            if (S.n_done >= pp.n_red) S.phase = 0;
-        } else {
-            S.ell += ntr;
-            S.trials_it += ntr;
-            S.trials += ntr;
-            S.step_tried += ntr;
-            if (S.step_tried >= pp.max_trials) {
-                if (!pp.adaptive) S.cap_hits += 1; // a rejected adaptive step simply ends the phase
-                S.need_last = pp.max_trials;
-                S.phase = 0;
-            }
-        }
-    }
+    if (threadIdx.x == 0) record_decision(sS, pp, ntr, acc_t, acc_f);
     __syncthreads();
 }
 
@@ -2092,6 +2099,41 @@ __global__ __launch_bounds__(kTrialBlock) void k_trial_close(float *__restrict__
     publish_state(S, st_out, s, apply);
 }
 
+// The phase of the linear objective f(x) = c^T x after its direction launch,
+// in one launch.  On v = -c/||c|| the objective at a trial point is known in
+// closed form, f(x + t v) = f(x) - t ||c||, so no trial needs a pass over x:
+// every workgroup opens the phase from the direction launch's partials (the
+// same sums in the same order), runs the reduction steps' trials on those
+// values, and adds the accepted step to its own part of x.
+__global__ __launch_bounds__(kBlock) void k_trial_linear(float *__restrict__ x, const float *__restrict__ c,
+                                                         const SliceState *__restrict__ st_in,
+                                                         SliceState *__restrict__ st_out, PertParams pp,
+                                                         const double *__restrict__ part_phase)
+{
+    __shared__ double tot[kTrialChunk];
+    __shared__ SliceState sS;
+    const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
+    derive_state<kBlock>(sS, st_in, pp, 1, part_phase, s, nt, tot);
+    if (threadIdx.x == 0) {
+        SliceState &S = sS;
+        const double f = S.f_cur; // f(x^k)
+        while (S.phase) { // one trial a round: bounded by n_red acceptances or the trial cap
+            const double t = S.s_acc + trial_beta(pp, S, S.ell);
+            const double ft = f - t * S.gn;
+            record_decision(S, pp, 1, ft <= S.f_cur ? 0 : -1, ft);
+        }
+    }
+    __syncthreads();
+    const SliceState &S = sS;
+    const bool apply = must_apply(S);
+    if (apply) {
+        const double inv_gn = 1.0 / S.gn;
+        for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < pp.n; j += (long long)gridDim.x * kBlock)
+            x[j * B + s] = (float)((double)x[j * B + s] + S.s_acc * (-(double)c[j] * inv_gn));
+    }
+    publish_state(S, st_out, s, apply);
+}
+
 // Trial launch for the squared norm and the linear objective (flat vectors).
 __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, const float *__restrict__ g,
                                                        const SliceState *__restrict__ st_in,
@@ -2145,6 +2187,118 @@ __global__ __launch_bounds__(kBlock) void k_trial_flat(float *__restrict__ x, co
             for (int w = 0; w < kTrialChunk; ++w)
                 if (t0 + w < ntr) part_out[(long long)(t0 + w) * nslots + slot] = acc[w];
         }
+    }
+}
+
+// The whole perturbation phase of a flat objective in one launch, for short
+// vectors (n <= kSmallPhaseMaxN): one workgroup per slice copies its entries
+// of x and of the direction into LDS (float32, 8n bytes), forms ||g||^2 and
+// f(x^k), opens the phase, evaluates every reduction step's trials in
+// batches of kSmallTrials (the first acceptable trial in order is taken, as
+// in the launch-per-batch form: the batching only decides how many trials
+// are evaluated speculatively), and adds the accepted step to x.  The same
+// arithmetic per entry as k_phase_flat / k_trial_flat; only the order of the
+// float64 sums differs.  One workgroup is a latency chain, so every thread
+// issues all of its loads of x (and c) before using any.  Reads state
+// st_in[s], writes st_out[s].
+template <int OBJ>
+__global__ __launch_bounds__(kSmallPhaseBlock) void k_phase_small(float *__restrict__ x,
+                                                                  const float *__restrict__ lin_c,
+                                                                  const SliceState *__restrict__ st_in,
+                                                                  SliceState *__restrict__ st_out, PertParams pp)
+{
+    constexpr int BS = kSmallPhaseBlock, T = kSmallTrials, U = (kSmallPhaseMaxN + BS - 1) / BS;
+    extern __shared__ __align__(16) unsigned char phase_lds[];
+    __shared__ double lds[(BS / 64) * T];
+    __shared__ double coef[T];
+    __shared__ SliceState sS;
+    const int s = blockIdx.y, B = pp.B, n = (int)pp.n;
+    float *xs = reinterpret_cast<float *>(phase_lds);
+    float *gs = xs + n;
+    if (threadIdx.x == 0) sS = st_in[s];
+    __syncthreads();
+    double v[2] = {0.0, 0.0}; // sum g^2, f(x^k)
+    if (sS.live) {
+        for (int j0 = threadIdx.x; j0 < n; j0 += U * BS) {
+            float xf[U], cf[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = min(j0 + u * BS, n - 1);
+                xf[u] = x[(long long)j * B + s];
+                if constexpr (OBJ == OBJ_LINEAR) cf[u] = lin_c[j];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = j0 + u * BS;
+                if (j >= n) break;
+                const double xj = (double)xf[u];
+                float gf;
+                if constexpr (OBJ == OBJ_SQNORM) {
+                    v[1] += xj * xj;
+                    gf = (float)(2.0 * xj);
+                } else if constexpr (OBJ == OBJ_L1) { // subgradient sign(x), 0 at 0
+                    v[1] += fabs(xj);
+                    gf = xj > 0.0 ? 1.f : (xj < 0.0 ? -1.f : 0.f);
+                } else {
+                    gf = cf[u];
+                    v[1] += (double)gf * xj;
+                }
+                v[0] += (double)gf * (double)gf;
+                xs[j] = xf[u];
+                gs[j] = gf;
+            }
+        }
+    }
+    block_sum<2, BS>(v, lds); // its barriers also publish xs and gs
+    if (threadIdx.x == 0) open_phase_state(sS, pp, v[0], v[1]);
+    __syncthreads();
+    while (sS.phase) { // sS changes only in thread 0, between barriers
+        const int ntr = min(T, pp.max_trials - sS.step_tried);
+        if (threadIdx.x < ntr) coef[threadIdx.x] = sS.s_acc + trial_beta(pp, sS, sS.ell + threadIdx.x);
+        __syncthreads();
+        const double inv_gn = 1.0 / sS.gn;
+        double acc[T], cw[T];
+#pragma unroll
+        for (int w = 0; w < T; ++w) {
+            acc[w] = 0.0;
+            cw[w] = w < ntr ? coef[w] : 0.0;
+        }
+#pragma unroll 4
+        for (int j = threadIdx.x; j < n; j += BS) {
+            const double xj = (double)xs[j], gj = (double)gs[j], vj = -gj * inv_gn;
+#pragma unroll
+            for (int w = 0; w < T; ++w) {
+                if (w < ntr) {
+                    const double z = xj + cw[w] * vj;
+                    if constexpr (OBJ == OBJ_LINEAR) acc[w] += gj * z;
+                    else if constexpr (OBJ == OBJ_L1) acc[w] += fabs(z);
+                    else acc[w] += z * z;
+                }
+            }
+        }
+        block_sum<T, BS>(acc, lds);
+        if (threadIdx.x == 0) {
+            int t = -1;
+            for (int w = 0; w < ntr; ++w)
+                if (acc[w] <= sS.f_cur) {
+                    t = w;
+                    break;
+                }
+            record_decision(sS, pp, ntr, t, t >= 0 ? acc[t] : 0.0);
+        }
+        __syncthreads();
+    }
+    const bool apply = must_apply(sS);
+    if (apply) {
+        const double inv_gn = 1.0 / sS.gn;
+#pragma unroll 4
+        for (int j = threadIdx.x; j < n; j += BS)
+            x[(long long)j * B + s] = (float)((double)xs[j] + sS.s_acc * (-(double)gs[j] * inv_gn));
+    }
+    if (threadIdx.x == 0) {
+        SliceState o = sS;
+        if (apply) o.applied = 1;
+        st_out[s] = o;
     }
 }
 
@@ -3024,6 +3178,99 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
     for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
 }
 
+// k_fused_zl with each row's first CAP chunks (CAP * LPR * VEC entries) held
+// in registers between the dot product and the scatter, so a row outside its
+// band adds c_i a_i without reading its entries again: on an operator whose
+// rows re-read from the cache outgrow L2, part of those re-reads come from
+// HBM.  Within a group, lane l holds the chunk slots of lane (l + group) mod
+// LPR (fetch_entries), so neighbouring rows, which list the same columns in
+// the same order, hit different LDS addresses in one atomic instruction.
+// Entries past CAP chunks are read again as in k_fused_zl.
+template <int LPR, int VEC, int CAP, typename VT>
+__global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, const float *__restrict__ x,
+                                                           const float *__restrict__ lower,
+                                                           const float *__restrict__ upper, RowW w,
+                                                           const SliceState *__restrict__ st,
+                                                           double *__restrict__ partials, float *__restrict__ ypart)
+{
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+    float *zl = reinterpret_cast<float *>(fused_lds);
+    float *y = zl + ((n + 3) & ~3);
+    __shared__ double lds[kFusedBlock / 64];
+    constexpr int RPB = kFusedBlock / LPR;
+    constexpr int STEP = LPR * VEC;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    const int slot = (lane + grp) & (LPR - 1);
+    const bool live = st[0].live != 0;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = 0.f;
+    double pacc[1] = {0.0};
+    if (live) {
+        stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
+        __syncthreads();
+        const long long stride = (long long)gridDim.x * RPB;
+        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
+            const int beg = A.ptr[row], end = A.ptr[row + 1];
+            RowRegs<VEC, CAP> R;
+            fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, R);
+            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
+            if (lane == 0) {
+                lo = lower[row];
+                up = upper[row];
+                d = w.D[row];
+                sw = w.S[row];
+            }
+            double acc[2] = {0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) // padding slots hold value 0 at column 0
+                    acc[q & 1] = fma((double)R.v[q][e], (double)zl[R.c[q][e]], acc[q & 1]);
+            const bool tail = end - beg > CAP * STEP;
+            if (tail) { // one chunk at a time: the held entries keep most registers
+                for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
+                    float v[VEC];
+                    int c[VEC];
+                    Entries<VT, VEC>::load(A, p, v, c);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[0] = fma((double)v[e], (double)zl[c[e]], acc[0]);
+                }
+            }
+            const double r = group_sum<LPR>(acc[0] + acc[1]) * (double)A.vscale_inv;
+            double ct = 0.0;
+            if (lane == 0) {
+                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+                pacc[0] += (double)d * t * t;
+                ct = (double)sw * t;
+            }
+            ct = __shfl(ct, 0, LPR);
+            if (ct != 0.0) {
+                const double sc = ct * (double)A.vscale_inv;
+#pragma unroll
+                for (int q = 0; q < CAP; ++q)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        if (R.v[q][e] != 0.f) lds_add(&y[R.c[q][e]], sc * (double)R.v[q][e]);
+                if (tail) {
+                    for (int p = beg + CAP * STEP + lane * VEC; p < end; p += STEP) {
+                        float v[VEC];
+                        int c[VEC];
+                        Entries<VT, VEC>::load(A, p, v, c);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            if (v[e] != 0.f) lds_add(&y[c[e]], sc * (double)v[e]);
+                    }
+                }
+            }
+        }
+    }
+    block_sum<1, kFusedBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
+    if (!live) return;
+    if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+    float *out = ypart + (long long)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
+}
+
 size_t fused_lds_bytes(int64_t n, int acc64) { return size_t(n) * (acc64 ? sizeof(double) : sizeof(float)); }
 
 size_t fused_zl_lds_bytes(int64_t n) { return 2 * size_t((n + 3) & ~int64_t(3)) * sizeof(float); }
@@ -3056,8 +3303,9 @@ struct FusedArgs {
 template <int LPR, typename VT, int VEC>
 hipError_t fused_zl_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStream_t s)
 {
-    if (cfg.cap != 0) return hipErrorInvalidValue;
-    auto kern = k_fused_zl<LPR, VEC, VT>;
+    constexpr int CAP = fused_zl_cap(LPR, VEC);
+    if (cfg.cap != 0 && cfg.cap != CAP) return hipErrorInvalidValue;
+    auto kern = cfg.cap ? k_fused_zlr<LPR, VEC, CAP, VT> : k_fused_zl<LPR, VEC, VT>;
     const size_t bytes = fused_zl_lds_bytes(a.n);
     if (prepare)
         return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -3503,6 +3751,51 @@ hipError_t launch_iter_norms(const float *x, const float *xprev, int64_t n, int 
 hipError_t launch_stop_var(SliceState *st, int B, const double *partials, int nparts, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stop_var, dim3(1), dim3(kBlock), 0, s, st, B, partials, nparts);
+    return hipGetLastError();
+}
+
+bool phase_in_one_launch(const PertParams &pp)
+{
+    return (pp.obj == OBJ_SQNORM || pp.obj == OBJ_L1 || pp.obj == OBJ_LINEAR) && pp.n >= 1 &&
+           pp.n <= kSmallPhaseMaxN;
+}
+
+static size_t phase_small_lds(const PertParams &pp) { return 2 * sizeof(float) * size_t(pp.n); }
+
+hipError_t prepare_phase_small()
+{
+    // the largest size any problem asks for: the attribute is the kernel's, not a problem's
+    const int bytes = (int)(2 * sizeof(float) * kSmallPhaseMaxN);
+    for (const void *k : {reinterpret_cast<const void *>(k_phase_small<OBJ_SQNORM>),
+                          reinterpret_cast<const void *>(k_phase_small<OBJ_L1>),
+                          reinterpret_cast<const void *>(k_phase_small<OBJ_LINEAR>)}) {
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_phase_small(const PertParams &pp, float *x, const float *lin_c, const SliceState *st_in,
+                              SliceState *st_out, hipStream_t s)
+{
+    if (!phase_in_one_launch(pp) || pp.max_trials < 1 || pp.max_trials > 1024 || pp.B < 1) return hipErrorInvalidValue;
+    const dim3 grid(1, pp.B), block(kSmallPhaseBlock);
+    const size_t lds = phase_small_lds(pp);
+    if (pp.obj == OBJ_SQNORM)
+        hipLaunchKernelGGL(k_phase_small<OBJ_SQNORM>, grid, block, lds, s, x, lin_c, st_in, st_out, pp);
+    else if (pp.obj == OBJ_L1)
+        hipLaunchKernelGGL(k_phase_small<OBJ_L1>, grid, block, lds, s, x, lin_c, st_in, st_out, pp);
+    else
+        hipLaunchKernelGGL(k_phase_small<OBJ_LINEAR>, grid, block, lds, s, x, lin_c, st_in, st_out, pp);
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_linear(const PertParams &pp, float *x, const float *c, const SliceState *st_in,
+                               SliceState *st_out, const double *part_phase, hipStream_t s)
+{
+    if (pp.obj != OBJ_LINEAR || pp.max_trials < 1 || pp.max_trials > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_trial_linear, dim3(phase_grid(pp), pp.B), dim3(kBlock), 0, s, x, c, st_in, st_out, pp,
+                       part_phase);
     return hipGetLastError();
 }
 

@@ -16,6 +16,10 @@ constexpr int kTrialBlock = 1024; // threads of a TV trial workgroup (one 16 x 1
 constexpr int kTile = 16;      // TV tile edge (kTile*kTile = kBlock)
 constexpr int kFusedBlock = 1024; // threads of a fused-pass workgroup (one per CU: its LDS holds y)
 constexpr int kFusedRcBlock = 512; // the same for the register-cached fused pass
+constexpr int kSmallPhaseBlock = 1024; // threads of the one-launch perturbation phase (one workgroup per slice)
+constexpr int kSmallPhaseMaxN = 20000; // longest x it takes (x and the direction in LDS, 8 bytes an entry)
+constexpr int kSmallPhaseAutoN = 8192; // longest x it is the default for
+constexpr int kSmallTrials = 8;        // trials per batch there
 constexpr int kApplyBlock = 1024;  // threads of the fused pass's apply kernel (16 waves share a column's partials)
 
 // Stored formats of A's entries.  The packed kinds hold one 32-bit word per
@@ -191,10 +195,10 @@ struct FusedCfg {
     int lpr;   // lanes per row: 8, 16 or 32
     int vec;   // entries per lane per load: 4 or 8
     int cap;   // 0: entries re-read for the scatter; else chunks per lane kept in
-               // registers (cap * lpr * vec = 256 entries)
+               // registers (cap * lpr * vec = 256 entries; with zl, 16 a lane)
     int grid;  // workgroups, each with an LDS copy of y
     int acc64; // 1: float64 LDS accumulators, 0: float32
-    int zl = 0; // 1: z staged in LDS beside a float32 y (k_fused_zl; acc64 = 0, cap = 0)
+    int zl = 0; // 1: z staged in LDS beside a float32 y (k_fused_zl, k_fused_zlr; acc64 = 0)
 };
 
 // Column layout grouped by image tiles (A^T for an operator whose unknowns
@@ -303,6 +307,10 @@ hipError_t launch_step_apply(int64_t n, int B, const double *y, float *x, const 
 size_t fused_lds_bytes(int64_t n, int acc64);
 // dynamic LDS of the fused pass with z in LDS (z and a float32 y)
 size_t fused_zl_lds_bytes(int64_t n);
+// chunks of a row the fused pass with z in LDS keeps in registers for the
+// scatter (cap != 0): 16 entries a lane (more, beside the LDS reads in
+// flight, would not fit the 128 registers of a 1024-thread workgroup's lane)
+constexpr int fused_zl_cap(int lpr, int vec) { return lpr > 0 ? 16 / vec : 0; }
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
                         const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
                         hipStream_t s);
@@ -347,6 +355,18 @@ hipError_t launch_eval_objective(SliceState *st, const PertParams &pp, const dou
 // [max_trials][B*tiles] into part_out), or adds the accepted step to x once
 // the phase is over.  The derived state goes to st_out.
 // the closing launch of a phase (one workgroup per slice)
+// Whether the perturbation phase runs as one launch (flat objectives, short
+// vectors), and that launch: state st_in in, st_out out.
+bool phase_in_one_launch(const PertParams &pp);
+// raises the one-launch phase's dynamic LDS limit on the current device to
+// what the longest x takes (outside any capture)
+hipError_t prepare_phase_small();
+hipError_t launch_phase_small(const PertParams &pp, float *x, const float *lin_c, const SliceState *st_in,
+                              SliceState *st_out, hipStream_t s);
+// The linear objective's phase after launch_phase (its partials in
+// part_phase): trials in closed form, the accepted step added to x.
+hipError_t launch_trial_linear(const PertParams &pp, float *x, const float *c, const SliceState *st_in,
+                               SliceState *st_out, const double *part_phase, hipStream_t s);
 hipError_t launch_trial_close(const PertParams &pp, float *x, const float *g, const SliceState *st_in,
                               SliceState *st_out, const double *part_prev, hipStream_t s);
 hipError_t launch_trial(const PertParams &pp, float *x, const float *g, const SliceState *st_in, SliceState *st_out,

@@ -108,8 +108,10 @@ def dvc_trajectory_margin(w, K, perturb=True, s=0, value_round=None, refine=0):
     return worst
 
 
-def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1, fused=True):
+def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1, fused=True, phase_form=None):
     p = smx.problem_from_workload(w, storage=storage, history_cap=K, refine_iters=refine_iters, fused=fused)
+    if phase_form is not None:
+        p.set_phase_form(phase_form)
     p.run(K, perturb=perturb, graph=graph)
     p.sync()
     x = p.get_x().cpu().numpy().astype(np.float64)
@@ -161,7 +163,7 @@ def storage_deviation(w, K, perturb=True, s=0, value_round=None, refine=0):
 
 
 def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=None, refine_iters=-1,
-                 sensitive=False, fused=True):
+                 sensitive=False, fused=True, phase_form=None):
     """End-to-end parity.  With sensitive=True (TV problems, whose gradient
     amplifies rounding of the iterate), the iterate and proximity tolerances
     are max(tol, 10 x the deviation float32 storage of the iterate alone
@@ -182,8 +184,9 @@ def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=N
     float32 near-ties (dvc_trajectory_margin above TIE_REL), so that the
     device and the oracle pick the same nearest point."""
     say(f"{w.name} m={w.m} n={w.n} nnz={w.nnz} K={K} perturb={perturb} obj={w.obj} storage={storage} "
-        f"fused={fused}")
-    x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters, fused=fused)
+        f"fused={fused} phase_form={phase_form}")
+    x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters, fused=fused,
+                                  phase_form=phase_form)
     refine = 0
     if storage != "f32":
         refine = refine_iters if refine_iters >= 0 else (K + 19) // 20
@@ -730,16 +733,85 @@ def test_set_fused_switches_kernels(smx):
     p.close()
 
 
+PHASE_CASES = {
+    "rt_linear": lambda: W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=10, K=40),
+    "sqnorm_two_steps": lambda: W.random_sparse(3000, 2000, 12, seed=41, empty_frac=0.08, long_rows=2,
+                                                obj=W.OBJ_SQNORM, K=25),
+    "l1": lambda: W.random_sparse(3000, 2000, 12, seed=44, empty_frac=0.08, long_rows=2, obj=W.OBJ_L1, K=25),
+    "dense_sqnorm": lambda: W.dense_small(),
+    "batched_l1": lambda: W.random_sparse(2000, 1500, 10, seed=48, B=4, obj=W.OBJ_L1, K=20),
+    "sqnorm_longest_x": lambda: W.random_sparse(4000, 20000, 40, seed=45, obj=W.OBJ_SQNORM, K=12),
+}
+
+
+PHASE_FORM_RUNS = [(c, f) for c in PHASE_CASES for f in ("one_launch", "batches")] + \
+    [("rt_linear", "closed_form"), ("linear_two_steps", "closed_form"), ("linear_two_steps", "batches")]
+PHASE_CASES["linear_two_steps"] = lambda: W.random_sparse(3000, 2000, 12, seed=42, empty_frac=0.08, long_rows=2,
+                                                         obj=W.OBJ_LINEAR, K=25)
+
+
+@pytest.mark.parametrize("case,form", PHASE_FORM_RUNS)
+def test_phase_forms_parity(smx, case, form):
+    """The perturbation phase in one launch per slice, as the chain of
+    trial-batch launches and, for the linear objective, with its trials in
+    closed form: each against the oracle, with the same trial and acceptance
+    sequence (n = 20,000 is the longest x the one-launch form takes; the
+    linear cases have restarts and two reduction steps)."""
+    w = PHASE_CASES[case]()
+    f = {"one_launch": smx.PHASE_ONE_LAUNCH, "batches": smx.PHASE_BATCHES,
+         "closed_form": smx.PHASE_CLOSED_FORM}[form]
+    check_parity(smx, w, w.K, phase_form=f)
+
+
+def test_phase_form_choice_and_args(smx):
+    """Auto picks one launch for flat objectives up to n = 8,192, the closed
+    form for the linear objective beyond, and the batches otherwise; one
+    launch can be asked for up to n = 20,000, the closed form for the linear
+    objective, and each is refused where it does not apply."""
+    for w, launches, eligible in ((W.random_sparse(300, 200, 8, seed=46, obj=W.OBJ_SQNORM, K=3), 1, True),
+                                  (W.random_sparse(300, 8193, 8, seed=49, obj=W.OBJ_LINEAR, K=3), None, True),
+                                  (W.random_sparse(300, 20001, 8, seed=47, obj=W.OBJ_L1, K=3), None, False),
+                                  (W.ct(N=24, n_angles=16, seed=59, K=5), None, False)):
+        p = smx.problem_from_workload(w)
+        d = p.describe()
+        if launches is not None:
+            assert d["phase_launches"] == launches
+        else:
+            assert d["phase_launches"] > 1
+        if eligible:
+            p.set_phase_form(smx.PHASE_ONE_LAUNCH)
+            assert p.describe()["phase_launches"] == 1
+        else:
+            with pytest.raises(smx.SmxError, match="ESTATE"):
+                p.set_phase_form(smx.PHASE_ONE_LAUNCH)
+        if w.obj == W.OBJ_LINEAR:
+            p.set_phase_form(smx.PHASE_CLOSED_FORM)
+            assert p.describe()["phase_launches"] == 2
+        else:
+            with pytest.raises(smx.SmxError, match="ESTATE"):
+                p.set_phase_form(smx.PHASE_CLOSED_FORM)
+        p.set_phase_form(smx.PHASE_BATCHES)
+        assert p.describe()["phase_launches"] > 1
+        p.set_phase_form(smx.PHASE_AUTO)
+        assert p.describe()["phase_launches"] == d["phase_launches"]
+        with pytest.raises(smx.SmxError, match="EINVAL"):
+            p.set_phase_form(4)
+        p.run(2, perturb=True, graph=True)
+        p.sync()
+        p.close()
+
+
 FUSED_SHAPES = [(8, 4, 0, 0), (8, 8, 0, 0), (16, 4, 0, 0), (16, 4, 4, 0), (16, 8, 0, 0), (16, 8, 2, 0), (32, 4, 0, 0),
-                (32, 4, 2, 0), (32, 8, 0, 0), (32, 8, 1, 0), (8, 4, 0, 1), (8, 8, 0, 1), (16, 4, 0, 1), (32, 8, 0, 1)]
+                (32, 4, 2, 0), (32, 8, 0, 0), (32, 8, 1, 0), (8, 4, 0, 1), (8, 8, 0, 1), (16, 4, 0, 1), (32, 8, 0, 1),
+                (8, 4, 4, 1), (8, 8, 2, 1), (16, 4, 4, 1), (16, 8, 2, 1), (32, 4, 4, 1), (32, 8, 2, 1)]
 
 
 @pytest.mark.parametrize("case", ["rt", "long_rows"])
 def test_every_fused_shape(smx, case):
     """Each launch shape of the fused pass (entries re-read or kept in
     registers, 8-32 lanes per row, z gathered from memory or from LDS)
-    against the oracle; the long-row case has rows beyond the 256 entries the
-    register-cached shapes hold."""
+    against the oracle; the long-row case has rows beyond the entries the
+    register-cached shapes hold (256, or 16 a lane with z in LDS)."""
     if case == "rt":
         w = W.rt(grid=(20, 20, 10), beamlets=(6, 6), seed=60, K=12)
         storage, vr = "bf16", "bf16"
@@ -768,6 +840,10 @@ def test_every_fused_shape(smx, case):
     p = smx.problem_from_workload(w, storage=storage)
     with pytest.raises(smx.SmxError):
         p.set_fused_shape(8, 4, 8)
+    with pytest.raises(smx.SmxError):
+        p.set_fused_shape(8, 4, 8, 1)
+    with pytest.raises(smx.SmxError):
+        smx.check(smx.lib().smx_set_fused_shape(p.handle, 8, 4, 0, 2))
     p.close()
 
 
