@@ -275,6 +275,19 @@ int smx_operator_create_image(const smx_csr *A, int32_t value_storage, int32_t k
  * (operators are reference counted).  NULL is accepted. */
 int smx_operator_destroy(smx_operator *op);
 
+/* Free an operator's row-panel layout of the column copy (operators with
+ * more than 40,448 rows build it for the one-slice row-panel pass 2: offsets
+ * of every column in every panel, and for rows past 16 bits a copy of the
+ * rows as 16-bit offsets within their panel, packed beside reduced-precision
+ * values) for callers whose problems will not use that pass: multi-slice
+ * problems never do, one-slice problems choose the fused pass or the column
+ * pass without it.  On the radiotherapy operator with bf16 values that is
+ * about 2.4 GB.  Problems created afterwards simply lack the panel pass.
+ * Errors: SMX_EINVAL for NULL, SMX_ESTATE while any problem created from the
+ * operator exists (it may be using the layout).  SMX_OK when there is no
+ * layout to free. */
+int smx_operator_release_panels(smx_operator *op);
+
 /* Device bytes the operator would take for A of this shape and storage,
  * without allocating anything (an upper bound: row and column padding is
  * counted at its maximum). */

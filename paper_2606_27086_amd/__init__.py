@@ -34,6 +34,7 @@ EXPORTS = [
     "smx_operator_create",
     "smx_operator_create_image",
     "smx_operator_destroy",
+    "smx_operator_release_panels",
     "smx_operator_footprint",
     "smx_footprint",
     "smx_problem_create",
@@ -188,6 +189,7 @@ def lib() -> C.CDLL:
     L.smx_operator_create.argtypes = [C.POINTER(Csr), i32, i32, vp, C.POINTER(vp)]
     L.smx_operator_create_image.argtypes = [C.POINTER(Csr), i32, i32, i32, i32, vp, C.POINTER(vp)]
     L.smx_operator_destroy.argtypes = [vp]
+    L.smx_operator_release_panels.argtypes = [vp]
     L.smx_operator_footprint.argtypes = [i64, i64, i64, i32, i32, C.POINTER(C.c_size_t)]
     L.smx_footprint.argtypes = [i64, i64, i64, i32, i32, i32, i32, C.POINTER(ProblemDesc), C.POINTER(C.c_size_t),
                                 C.POINTER(C.c_size_t)]
@@ -282,6 +284,11 @@ class Operator:
             check(lib().smx_operator_create_image(C.byref(csr), STORE[storage], 1 if keep_f32 else 0,
                                                   int(image[0]), int(image[1]), _stream_ptr(stream), C.byref(h)))
         self.handle = h
+
+    def release_panels(self):
+        """Free the row-panel layout of the column copy (smx_operator_release_panels):
+        for operators whose problems are multi-slice or will not use that pass."""
+        check(lib().smx_operator_release_panels(self.handle))
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:

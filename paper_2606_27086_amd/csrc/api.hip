@@ -1875,6 +1875,22 @@ int smx_operator_destroy(smx_operator *op)
     SMX_GUARD(release_operator(op); return SMX_OK;)
 }
 
+int smx_operator_release_panels(smx_operator *op)
+{
+    if (!op) return fail(SMX_EINVAL, "NULL operator");
+    SMX_GUARD({
+        if (op->refs.load() != 1)
+            return fail(SMX_ESTATE, "problems created from this operator still exist (%d references)",
+                        op->refs.load() - 1);
+        op->panel_ptr.release();
+        op->panel_idx16.release();
+        op->panel_packed.release();
+        op->panel_np = 0;
+        op->panel_P = 0;
+        return SMX_OK;
+    })
+}
+
 int smx_operator_footprint(int64_t m, int64_t n, int64_t nnz, int32_t value_storage, int32_t keep_f32, size_t *bytes)
 {
     if (!bytes) return fail(SMX_EINVAL, "NULL argument");

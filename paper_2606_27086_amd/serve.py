@@ -80,6 +80,8 @@ class Group:
         with torch.cuda.stream(self.stream):
             self.op = Operator(spec.m, spec.n, spec.row_ptr, spec.col_idx, spec.val, storage=storage,
                                keep_f32=True, device=device, stream=self.stream)
+            if B > 1:  # the row-panel pass 2 serves one-slice problems only
+                self.op.release_panels()
             zeros_m = np.zeros((spec.m, B), np.float32)
             self.prob = Problem(self.op, lower=zeros_m, upper=zeros_m, B=B, device=device, stream=self.stream,
                                 refine_iters=0, **spec.params)

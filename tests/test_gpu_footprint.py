@@ -90,3 +90,35 @@ def test_footprint_against_device_free_memory(smx, shape):
     assert pb == d["device_bytes"]
     assert abs(d_pb - pb) <= 0.02 * pb + (16 << 20)
     assert d_op <= ob + (16 << 20)
+
+
+def test_release_panels(smx):
+    """An operator's row-panel layout freed before any problem uses it: the
+    operator holds fewer bytes, problems on it run the column pass 2 instead
+    and still match the oracle; refused while a problem exists; a second
+    release frees nothing and succeeds."""
+    from test_gpu_parity import RTOL, oracle_run, rel
+
+    w = W.random_sparse(100001, 700, 6, seed=50, obj=W.OBJ_SQNORM, K=5)
+    say(f"release panels m={w.m} n={w.n}")
+    op = smx.Operator(w.m, w.n, w.row_ptr, w.col_idx, w.val, storage="bf16")
+    p = smx.problem_from_workload(w, storage="bf16", op=op, fused=False)
+    before = p.describe()["operator_bytes"]
+    with pytest.raises(smx.SmxError, match="ESTATE"):
+        op.release_panels()
+    p.close()
+    op.release_panels()
+    op.release_panels()
+    q = smx.problem_from_workload(w, storage="f32", op=op, fused=False, history_cap=w.K)
+    d = q.describe()
+    assert d["operator_bytes"] < before
+    assert all(d[st]["pass2"]["mode"] != "panels" for st in ("f32", "bf16") if st in d)
+    q.autotune(reps=2)
+    assert all(q.describe()[st]["pass2"]["mode"] != "panels" for st in ("f32", "bf16") if st in d)
+    q.run(w.K)
+    q.sync()
+    x = q.get_x().cpu().numpy()[:, 0].astype(np.float64)
+    q.close()
+    op.close()
+    xo, _, _, _ = oracle_run(w, w.K)
+    assert rel(x, xo) <= RTOL

@@ -445,6 +445,34 @@ def test_graph_replay_is_bitwise_eager(smx):
     assert np.array_equal(he["prox"], hg["prox"])
 
 
+@pytest.mark.parametrize("form", ["one_launch", "closed_form"])
+def test_phase_forms_graph_and_resume_bitwise(smx, form):
+    """The one-launch and closed-form phases (two passes, so every sum has a
+    fixed order): graph replay equals eager launches, and a run stopped,
+    checkpointed and resumed equals the run straight through, bit for bit."""
+    w = W.random_sparse(3000, 2000, 12, seed=43, empty_frac=0.08, long_rows=2, obj=W.OBJ_LINEAR, K=23)
+    f = smx.PHASE_ONE_LAUNCH if form == "one_launch" else smx.PHASE_CLOSED_FORM
+    say(f"graph, eager and resume with the {form} phase")
+    xe, pe, fe, he, se = gpu_run(smx, w, w.K, graph=False, fused=False, phase_form=f)
+    xg, pg, fg, hg, sg = gpu_run(smx, w, w.K, graph=True, fused=False, phase_form=f)
+    assert np.array_equal(xe, xg) and np.array_equal(he["prox"], hg["prox"]) and se == sg
+    p = smx.problem_from_workload(w, history_cap=0, fused=False)
+    p.set_phase_form(f)
+    p.run(9, graph=True)
+    p.sync()
+    states, x1 = p.get_state()
+    p.close()
+    q = smx.problem_from_workload(w, history_cap=0, fused=False)
+    q.set_phase_form(f)
+    q.set_state(states, x1)
+    q.run(w.K - 9, graph=True)
+    q.sync()
+    xb = q.get_x().cpu().numpy().astype(np.float64)
+    sb, _ = q.get_state()
+    q.close()
+    assert np.array_equal(xe, xb) and sb == se
+
+
 def test_repeat_is_bitwise(smx):
     w = W.random_sparse(2000, 1500, 20, seed=14, obj=W.OBJ_TV2D, tv_shape=(30, 50), K=20)
     say("repeat (two passes)")
