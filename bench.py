@@ -25,7 +25,9 @@ five repeats.  The line also carries
                oracle after the same iterations from x0;
   roofline     the dominant kernel: algorithmic bytes per launch / its mean
                launch time (HIP events on the problem's stream), HBM traffic
-               from the committed counter table when it matches the kernels;
+               from the committed counter table when it matches the kernels,
+               and the rate of a read-only stream over 4 GiB on this device
+               (read_ceiling);
   cpu_baseline the FP64 oracle on this host: all threads and one thread, a
                bounded sample of iterations at the same point of its own run
                from x0, the CPU model;
@@ -275,6 +277,36 @@ def roofline_of(w, r, storage, B=1, workload=None):
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(kname, workload), algorithmic_bytes=int(dbytes),
                 step_gbs=round((b1 + b2) / ((t1 + t2) * 1e-3) / 1e9, 1),
                 address_floor_us=round(floor_us, 2), address_frac=round(floor_us / (dms * 1e3), 3))
+
+
+def read_ceiling(smx, gib=4, reps=10):
+    """The rate at which a kernel that only reads HBM moves bytes here:
+    smx_read_rate_probe over a gib GiB buffer of ones at several grid sizes,
+    HIP events around reps launches on the current stream, the best grid's
+    mean; the partial sums are checked against the element count."""
+    import torch
+
+    n = (gib << 30) // 4
+    buf = torch.ones(n, dtype=torch.float32, device="cuda")
+    best = None
+    for grid in (2048, 8192, 16384, 32768):
+        part = torch.zeros(grid, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            smx.read_rate_probe(buf, part, grid)
+        torch.cuda.synchronize()
+        assert float(part.double().sum()) == float(n), "read probe lost words"
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            smx.read_rate_probe(buf, part, grid)
+        e1.record()
+        e1.synchronize()
+        gbs = 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        if best is None or gbs > best["gbs"]:
+            best = dict(gbs=round(gbs, 1), grid=grid, bytes=4 * n)
+    del buf
+    torch.cuda.empty_cache()
+    return best
 
 
 def cpu_model() -> str:
@@ -746,6 +778,8 @@ def main():
     # lower bound (the large early perturbation steps push every fluence below
     # zero); the timed window starts after the iterate has left it.
     settle = HEADLINE_SETTLE
+    ceiling = read_ceiling(smx)
+    progress(f"read-only stream ceiling: {ceiling['gbs']} GB/s (grid {ceiling['grid']})")
     results = {st: time_problem(smx, w, st, args.steps, args.warmup, graph=graph, tune=tune, settle=settle)
                for st in ("f32", "bf16")}
     main_r = results["f32"]
@@ -786,7 +820,7 @@ def main():
         "config": {"workload": RT_WORKLOAD + "_linear_dose_f32", "m": w.m, "n": w.n, "nnz": w.nnz, "B": w.B,
                    "K": w.K, "graph": graph, "storage": "f32", "generate_s": round(gen_s, 1),
                    "timed_iterations": [settle + args.warmup, settle + args.warmup + args.steps]},
-        "roofline": roofline_of(w, main_r, "f32", workload=RT_WORKLOAD),
+        "roofline": dict(roofline_of(w, main_r, "f32", workload=RT_WORKLOAD), read_ceiling=ceiling),
         "cpu_baseline": cpu,
         "variants": variants,
         "full_job": full_job,

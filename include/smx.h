@@ -233,6 +233,18 @@ typedef struct {
 /* Library version.  Both pointers must be non-NULL. */
 int smx_version(int *major, int *minor);
 
+/* Measurement aid, not a step of the method: one read-only pass over bytes
+ * of device memory at buf (16-byte aligned, a positive multiple of 16 bytes)
+ * by grid workgroups of 256 threads, each thread reading 16-byte words four
+ * at a time and each workgroup storing the float sum of what it read into
+ * partials[grid] (device memory, caller-owned).  Enqueued on stream (NULL:
+ * the default stream), no synchronisation: timing it with events around the
+ * call gives the rate at which a kernel that only reads HBM moves bytes on
+ * this device, the ceiling the passes' achieved bandwidth is compared with.
+ * Errors: SMX_EINVAL for NULL pointers, a misaligned or empty buffer, or grid
+ * outside 1..65535; SMX_EDEVICE for a launch failure. */
+int smx_read_rate_probe(const void *buf, size_t bytes, float *partials, int32_t grid, void *stream);
+
 /* Message of the last failed call on this thread ("" if none).  The pointer
  * stays valid until the next smx_* call on this thread. */
 const char *smx_last_error(void);

@@ -31,6 +31,7 @@ _CODE_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "
 EXPORTS = [
     "smx_version",
     "smx_last_error",
+    "smx_read_rate_probe",
     "smx_operator_create",
     "smx_operator_create_image",
     "smx_operator_destroy",
@@ -190,6 +191,7 @@ def lib() -> C.CDLL:
     L.smx_operator_create_image.argtypes = [C.POINTER(Csr), i32, i32, i32, i32, vp, C.POINTER(vp)]
     L.smx_operator_destroy.argtypes = [vp]
     L.smx_operator_release_panels.argtypes = [vp]
+    L.smx_read_rate_probe.argtypes = [vp, C.c_size_t, vp, i32, vp]
     L.smx_operator_footprint.argtypes = [i64, i64, i64, i32, i32, C.POINTER(C.c_size_t)]
     L.smx_footprint.argtypes = [i64, i64, i64, i32, i32, i32, i32, C.POINTER(ProblemDesc), C.POINTER(C.c_size_t),
                                 C.POINTER(C.c_size_t)]
@@ -300,6 +302,16 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def read_rate_probe(buf, partials, grid: int, stream=None) -> None:
+    """One read-only pass over the device tensor buf (smx_read_rate_probe);
+    partials: a float32 device tensor of at least grid entries."""
+    import torch
+
+    assert buf.is_cuda and partials.is_cuda and partials.dtype == torch.float32 and partials.numel() >= grid
+    check(lib().smx_read_rate_probe(_ptr(buf), buf.numel() * buf.element_size(), _ptr(partials), int(grid),
+                                    _stream_ptr(stream)))
 
 
 def footprint(m, n, nnz, storage="f32", keep_f32=True) -> int:

@@ -1856,6 +1856,19 @@ int smx_version(int *major, int *minor)
 
 const char *smx_last_error(void) { return g_err.c_str(); }
 
+int smx_read_rate_probe(const void *buf, size_t bytes, float *partials, int32_t grid, void *stream)
+{
+    if (!buf || !partials) return fail(SMX_EINVAL, "NULL argument");
+    if ((reinterpret_cast<uintptr_t>(buf) & 15) != 0 || bytes == 0 || (bytes & 15) != 0)
+        return fail(SMX_EINVAL, "the buffer must be 16-byte aligned and hold a positive multiple of 16 bytes");
+    if (grid < 1 || grid > 65535) return fail(SMX_EINVAL, "grid must be in 1..65535 (got %d)", grid);
+    SMX_GUARD({
+        hip_check(launch_stream_read(buf, (int64_t)bytes, partials, grid, static_cast<hipStream_t>(stream)),
+                  "read rate probe");
+        return SMX_OK;
+    })
+}
+
 int smx_operator_create(const smx_csr *A, int32_t value_storage, int32_t keep_f32, void *stream, smx_operator **out)
 {
     SMX_GUARD(return create_operator(A, value_storage, keep_f32, (hipStream_t)stream, out);)

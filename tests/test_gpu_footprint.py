@@ -122,3 +122,23 @@ def test_release_panels(smx):
     op.close()
     xo, _, _, _ = oracle_run(w, w.K)
     assert rel(x, xo) <= RTOL
+
+
+def test_read_rate_probe(smx):
+    """The read-only stream of the measurement aid reads every word: its
+    per-workgroup sums add up to the buffer's sum; misaligned or ragged
+    buffers and bad grids are refused."""
+    import torch
+
+    g = torch.Generator().manual_seed(5)
+    buf = torch.rand(1 << 20 | 4, generator=g).cuda()  # 16-byte multiple with a ragged tail
+    part = torch.zeros(300, dtype=torch.float32, device="cuda")
+    smx.read_rate_probe(buf, part, 300)
+    torch.cuda.synchronize()
+    assert abs(float(part.double().sum()) - float(buf.double().sum())) <= 1e-5 * float(buf.double().sum())
+    with pytest.raises(smx.SmxError, match="EINVAL"):
+        smx.read_rate_probe(buf[1:-3], part, 300)  # 4-byte offset
+    with pytest.raises(smx.SmxError, match="EINVAL"):
+        smx.read_rate_probe(buf[:-1], part, 300)  # not a multiple of 16 bytes
+    with pytest.raises(smx.SmxError, match="EINVAL"):
+        smx.check(smx.lib().smx_read_rate_probe(buf.data_ptr(), 64, part.data_ptr(), 0, None))
