@@ -1856,6 +1856,41 @@ int smx_version(int *major, int *minor)
 
 const char *smx_last_error(void) { return g_err.c_str(); }
 
+namespace {
+
+// Read-only stream over a buffer: the rate at which a kernel that only reads
+// HBM moves bytes on this device, the ceiling the passes' bandwidth is set
+// against.  Each thread adds the 16-byte words it reads, four in flight; the
+// workgroup's sum (so that no load can be dropped) goes through LDS.
+__global__ __launch_bounds__(256) void k_stream_read(const float4 *__restrict__ v, long long n4,
+                                                     float *__restrict__ partials)
+{
+    __shared__ float lds[256];
+    float a = 0.f;
+    const long long stride = (long long)gridDim.x * 256;
+    long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        float4 t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = v[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a += (t[u].x + t[u].y) + (t[u].z + t[u].w);
+    }
+    for (; i < n4; i += stride) {
+        const float4 t = v[i];
+        a += (t.x + t.y) + (t.z + t.w);
+    }
+    lds[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = lds[0];
+}
+
+} // namespace
+
 int smx_read_rate_probe(const void *buf, size_t bytes, float *partials, int32_t grid, void *stream)
 {
     if (!buf || !partials) return fail(SMX_EINVAL, "NULL argument");
@@ -1863,8 +1898,9 @@ int smx_read_rate_probe(const void *buf, size_t bytes, float *partials, int32_t 
         return fail(SMX_EINVAL, "the buffer must be 16-byte aligned and hold a positive multiple of 16 bytes");
     if (grid < 1 || grid > 65535) return fail(SMX_EINVAL, "grid must be in 1..65535 (got %d)", grid);
     SMX_GUARD({
-        hip_check(launch_stream_read(buf, (int64_t)bytes, partials, grid, static_cast<hipStream_t>(stream)),
-                  "read rate probe");
+        hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream),
+                           static_cast<const float4 *>(buf), (long long)(bytes / 16), partials);
+        hip_check(hipGetLastError(), "read rate probe");
         return SMX_OK;
     })
 }

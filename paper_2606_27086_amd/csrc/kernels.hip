@@ -3733,40 +3733,6 @@ __global__ __launch_bounds__(kBlock) void k_stop_var(SliceState *__restrict__ st
     }
 }
 
-// Read-only stream over a buffer: the rate at which a kernel that only reads
-// HBM moves bytes on this device, the ceiling the passes' bandwidth is set
-// against.  Each thread adds the 16-byte words it reads, four in flight, and
-// each workgroup leaves one partial sum (so no load can be dropped).
-__global__ __launch_bounds__(kBlock) void k_stream_read(const float4 *__restrict__ v, long long n4,
-                                                        float *__restrict__ partials)
-{
-    __shared__ double lds[kBlock / 64];
-    float a = 0.f;
-    const long long stride = (long long)gridDim.x * kBlock;
-    long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + 3 * stride < n4; i += 4 * stride) {
-        float4 t[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = v[i + u * stride];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a += (t[u].x + t[u].y) + (t[u].z + t[u].w);
-    }
-    for (; i < n4; i += stride) {
-        const float4 t = v[i];
-        a += (t.x + t.y) + (t.z + t.w);
-    }
-    double sum[1] = {(double)a};
-    block_sum<1>(sum, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = (float)sum[0];
-}
-
-hipError_t launch_stream_read(const void *buf, int64_t bytes, float *partials, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(kBlock), 0, s, static_cast<const float4 *>(buf),
-                       (long long)(bytes / 16), partials);
-    return hipGetLastError();
-}
-
 hipError_t launch_copy(float *dst, const float *src, int64_t count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy, dim3(grid_for(count, kBlock, 4096)), dim3(kBlock), 0, s, dst, src, (long long)count);

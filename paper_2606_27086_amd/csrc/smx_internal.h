@@ -239,8 +239,6 @@ hipError_t launch_init_state(SliceState *st, int B, StopParams sp, hipStream_t s
 // per-workgroup partials of ||x - xprev||^2 and ||x||^2 (norms) and, in one
 // workgroup, the running variance of their ratio and the stop decision
 hipError_t launch_copy(float *dst, const float *src, int64_t count, hipStream_t s);
-// read-only stream over bytes of buf (16-byte words), one float partial sum per workgroup
-hipError_t launch_stream_read(const void *buf, int64_t bytes, float *partials, int grid, hipStream_t s);
 hipError_t launch_iter_norms(const float *x, const float *xprev, int64_t n, int B, double *partials, int *nparts,
                              hipStream_t s);
 hipError_t launch_stop_var(SliceState *st, int B, const double *partials, int nparts, hipStream_t s);
