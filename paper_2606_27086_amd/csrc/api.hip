@@ -917,11 +917,18 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
                                p->lower.as<float>(), p->upper.as<float>(), rw, p->state(cur),
                                p->part_pass.as<double>(), p->ypart.p, s),
                   "fused pass");
-        if (timed) {
-            hip_check(hipEventRecord(e[1], s), "event");
-            hip_check(hipEventRecord(e[2], s), "event");
+        if (timed) hip_check(hipEventRecord(e[1], s), "event");
+        int nvec = p->fcfg[vk].grid;
+        if (p->dvc.n > 0) { // rank the dose-volume rows, then add their c_i a_i as a second set of partials
+            p->enqueue_dvc(vk, p->part_pass.as<double>(), p->fcfg[vk].grid, cur, 0, s);
+            hip_check(launch_scatter_rows(view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), p->n, p->dvc.lo,
+                                          p->dvc.lo + p->dvc.span, p->c.as<float>(), p->state(cur),
+                                          p->ypart.as<float>() + size_t(nvec) * size_t(p->n), nvec, s),
+                      "dose-volume rows");
+            nvec *= 2;
         }
-        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, p->x.as<float>(), p->col_step(extrap),
+        if (timed) hip_check(hipEventRecord(e[2], s), "event");
+        hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, nvec, p->x.as<float>(), p->col_step(extrap),
                                      p->state(cur), p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s),
                   "fused apply");
         if (timed) hip_check(hipEventRecord(e[3], s), "event");
@@ -1057,10 +1064,12 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // Launch shapes of the fused pass tried by the autotuner (same grid and
 // accumulator type as `base`): 8/16/32 lanes per row with 4 or 8 entries per
 // load re-reading the entries for the scatter, and the register-cached shapes
-// (256 entries of a row in registers).
-std::vector<FusedCfg> fused_candidates(const FusedCfg &base, int64_t n)
+// (256 entries of a row in registers); zl_only: only the shapes with z in LDS
+// (the ones that store dose-volume rows' values).
+std::vector<FusedCfg> fused_candidates(const FusedCfg &base, int64_t n, bool zl_only = false)
 {
     std::vector<FusedCfg> out;
+    if (!zl_only)
     for (int lpr : {8, 16, 32})
         for (int vec : {4, 8}) {
             FusedCfg t = base;
@@ -1137,7 +1146,10 @@ int build_dvc_table(const smx_problem_desc *d, int64_t m, DvcTable &dt)
 // allows.
 bool fused_plan(int64_t n, int B, int n_dvc, FusedCfg &c, size_t &lds_bytes)
 {
-    if (B != 1 || n_dvc > 0) return false;
+    if (B != 1) return false;
+    // dose-volume rows: the shapes with z in LDS store their values for the
+    // ranking, and a second kernel adds their c_i a_i once it has set them
+    if (n_dvc > 0 && fused_zl_lds_bytes(n) > fused_lds_limit()) return false;
     const size_t lim = fused_lds_limit();
     int acc64 = -1;
     if (fused_lds_bytes(n, 1) <= lim) acc64 = 1;
@@ -1243,13 +1255,20 @@ void setup_fused(smx_problem *p)
     const DevLayout &L = p->op->csr;
     const double mean = L.rows > 0 ? double(L.slots) / double(L.rows) : 0.0;
     c.lpr = mean <= 64 ? 8 : (mean <= 256 ? 16 : 32);
+    const bool dvc = p->dvc.n > 0;
+    if (dvc) { // z in LDS: two sets of float32 partials fit the float64 plan's bytes
+        c.zl = 1;
+        c.acc64 = 0;
+        c.lpr = 8;
+    }
     bool any = false;
     for (int vk = 0; vk < 3; ++vk) {
         const bool present = (vk == VK_F32) ? p->op->has_f32 : (vk == p->op->lp_kind());
         if (!present) continue;
         bool ok = true;
-        for (const FusedCfg &t : fused_candidates(c, p->n))
+        for (const FusedCfg &t : fused_candidates(c, p->n, dvc))
             if (prepare_fused(t, fused_fmt(p, vk), p->n) != hipSuccess) ok = false;
+        if (dvc && prepare_scatter_rows(fused_fmt(p, vk), p->n) != hipSuccess) ok = false;
         (void)hipGetLastError();
         p->fused_ok[vk] = p->fused[vk] = ok;
         p->fcfg[vk] = c;
@@ -1716,13 +1735,22 @@ int autotune_impl(smx_problem *p, int reps)
             if (p->fused_ok[vk] && p->fused_mode == 1) {
                 double bestf = 1e30;
                 FusedCfg bestfc = p->fcfg[vk];
-                for (const FusedCfg &c : fused_candidates(p->fcfg[vk], n)) {
+                for (const FusedCfg &c : fused_candidates(p->fcfg[vk], n, p->dvc.n > 0)) {
                     auto launch = [&]() {
                         hip_check(launch_fused(c, view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), n, xs.as<float>(),
                                                p->lower.as<float>(), p->upper.as<float>(), rw, st0,
                                                p->part_query.as<double>(), p->ypart.p, s),
                                   "tuning fused pass");
-                        hip_check(launch_fused_apply(c, n, p->ypart.p, xs.as<float>(), cstep, st0, st1,
+                        int nvec = c.grid;
+                        if (p->dvc.n > 0) { // the dose-volume rows' own scatter
+                            hip_check(launch_scatter_rows(view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk),
+                                                          n, p->dvc.lo, p->dvc.lo + p->dvc.span, p->c.as<float>(),
+                                                          st0, p->ypart.as<float>() + size_t(c.grid) * size_t(n),
+                                                          c.grid, s),
+                                      "tuning dose-volume rows");
+                            nvec *= 2;
+                        }
+                        hip_check(launch_fused_apply(c, n, p->ypart.p, nvec, xs.as<float>(), cstep, st0, st1,
                                                      p->part_query.as<double>(), none, s),
                                   "tuning fused apply");
                     };
@@ -2391,7 +2419,7 @@ int smx_set_fused_shape(smx_problem *p, int32_t lpr, int32_t vec, int32_t cap, i
         bool found = false;
         for (int vk = 0; vk < 3; ++vk) {
             if (!p->fused_ok[vk]) continue;
-            for (const FusedCfg &c : fused_candidates(p->fcfg[vk], p->n))
+            for (const FusedCfg &c : fused_candidates(p->fcfg[vk], p->n, p->dvc.n > 0))
                 if (c.lpr == lpr && c.vec == vec && c.cap == cap && c.zl == z_in_lds) {
                     p->fcfg[vk] = c;
                     found = true;

@@ -3115,6 +3115,23 @@ hipError_t launch_pass2(const PassCfg &cfg, const SpView &At, const RowBlocks &R
     return pass2_vec<F16Tag, 4>(cfg, At, c, x, cs, st_in, st_out, part1, nparts1, h, s);
 }
 
+// Row epilogue of the fused passes with z in LDS (one slice): the row's
+// c_i (its step weight times the distance to its band) and its proximity
+// term added to pacc; a dose-volume row only stores its value r for the
+// ranking and adds nothing here (k_scatter_rows adds its c_i a_i once the
+// ranking has set its band).
+__device__ inline double fused_epilogue(const RowW &w, long long row, double r, float lo, float up, float d, float sw,
+                                        double &pacc)
+{
+    if (w.dose && row >= w.dose_lo && row < w.dose_hi) {
+        w.dose[row - w.dose_lo] = r;
+        return 0.0;
+    }
+    const double t = fmin(fmax(r, (double)lo), (double)up) - r;
+    pacc += (double)d * t * t;
+    return (double)sw * t;
+}
+
 // Fused pass with the gathered vector in LDS.  The plain fused pass gathers
 // z_j through the vector memory path once per stored entry, about one
 // address per CU per clock, which bounds it on long operators.  Here each
@@ -3161,11 +3178,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
             const double r =
                 group_sum<LPR>(row_dot_split<LPR, VEC, VT>(A, beg, end, lane, x, zl, n)) * (double)A.vscale_inv;
             double ct = 0.0;
-            if (lane == 0) {
-                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-                pacc[0] += (double)d * t * t;
-                ct = (double)sw * t;
-            }
+            if (lane == 0) ct = fused_epilogue(w, row, r, lo, up, d, sw, pacc[0]);
             ct = __shfl(ct, 0, LPR);
             if (ct != 0.0 && end > beg)
                 scatter_row<LPR, VEC, VT, float>(A, beg, end, lane, grp, ct * (double)A.vscale_inv, y);
@@ -3238,11 +3251,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, cons
             }
             const double r = group_sum<LPR>(acc[0] + acc[1]) * (double)A.vscale_inv;
             double ct = 0.0;
-            if (lane == 0) {
-                const double t = fmin(fmax(r, (double)lo), (double)up) - r;
-                pacc[0] += (double)d * t * t;
-                ct = (double)sw * t;
-            }
+            if (lane == 0) ct = fused_epilogue(w, row, r, lo, up, d, sw, pacc[0]);
             ct = __shfl(ct, 0, LPR);
             if (ct != 0.0) {
                 const double sc = ct * (double)A.vscale_inv;
@@ -3267,6 +3276,37 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, cons
     block_sum<1, kFusedBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
     if (!live) return;
     if (threadIdx.x == 0) partials[blockIdx.x] = pacc[0];
+    float *out = ypart + (long long)blockIdx.x * n;
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
+}
+
+// y += sum of c_i a_i over rows [r_lo, r_hi) with c_i already set (the
+// dose-volume rows of a problem taking the fused pass, after their ranking):
+// one 1024-thread workgroup per CU adds its share of the rows (strided over
+// the grid) into an LDS copy of y and leaves it as one float32 partial
+// vector, beside the fused pass's own.
+template <int LPR, int VEC, typename VT>
+__global__ __launch_bounds__(kFusedBlock) void k_scatter_rows(SpView A, int n, long long r_lo, long long r_hi,
+                                                              const float *__restrict__ c,
+                                                              const SliceState *__restrict__ st,
+                                                              float *__restrict__ ypart)
+{
+    extern __shared__ __align__(16) unsigned char scat_lds[];
+    float *y = reinterpret_cast<float *>(scat_lds);
+    constexpr int RPB = kFusedBlock / LPR;
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    if (st[0].live == 0) return; // the same in every workgroup: the apply reads nothing then
+    for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = 0.f;
+    __syncthreads();
+    const long long stride = (long long)gridDim.x * RPB;
+    for (long long row = r_lo + (long long)blockIdx.x * RPB + grp; row < r_hi; row += stride) {
+        const float ci = c[row];
+        const int beg = A.ptr[row], end = A.ptr[row + 1];
+        if (ci != 0.f && end > beg)
+            scatter_row<LPR, VEC, VT, float>(A, beg, end, lane, grp, (double)ci * (double)A.vscale_inv, y);
+    }
+    __syncthreads();
     float *out = ypart + (long long)blockIdx.x * n;
     for (int j = threadIdx.x; j < n; j += kFusedBlock) out[j] = y[j];
 }
@@ -3400,19 +3440,64 @@ hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n,
     return fused_dispatch(cfg, vk, a, 0, s);
 }
 
-hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, ColStep cs,
+hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, int nvec, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
                               hipStream_t s)
 {
-    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1) return hipErrorInvalidValue;
+    if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1 || nvec < cfg.grid || nvec > 2 * cfg.grid ||
+        (cfg.acc64 && nvec != cfg.grid))
+        return hipErrorInvalidValue;
     const unsigned grid = (unsigned)fused_apply_grid(n);
     if (cfg.acc64)
         hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const double *>(ypart),
-                           cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
+                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
     else
         hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const float *>(ypart),
-                           cfg.grid, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
+                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
     return hipGetLastError();
+}
+
+namespace {
+template <typename VT>
+hipError_t scatter_rows_go(int prepare, const SpView &A, int64_t n, long long r_lo, long long r_hi, const float *c,
+                           const SliceState *st, float *ypart, int grid, hipStream_t s)
+{
+    auto kern = k_scatter_rows<8, 4, VT>;
+    const size_t bytes = sizeof(float) * size_t(n);
+    if (prepare)
+        return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)bytes);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFusedBlock), bytes, s, A, (int)n, r_lo, r_hi, c, st, ypart);
+    return hipGetLastError();
+}
+
+hipError_t scatter_rows_dispatch(int prepare, const SpView &A, int vk, int64_t n, long long r_lo, long long r_hi,
+                                 const float *c, const SliceState *st, float *ypart, int grid, hipStream_t s)
+{
+    if (n < 1 || (!prepare && (grid < 1 || grid > kMaxPassGrid || r_lo < 0 || r_hi > A.rows || r_lo > r_hi)))
+        return hipErrorInvalidValue;
+    switch (vk) {
+    case VK_F32: return scatter_rows_go<float>(prepare, A, n, r_lo, r_hi, c, st, ypart, grid, s);
+    case VK_BF16: return scatter_rows_go<Bf16Tag>(prepare, A, n, r_lo, r_hi, c, st, ypart, grid, s);
+    case VK_F16: return scatter_rows_go<F16Tag>(prepare, A, n, r_lo, r_hi, c, st, ypart, grid, s);
+    case VK_BF16P: return scatter_rows_go<Bf16PTag>(prepare, A, n, r_lo, r_hi, c, st, ypart, grid, s);
+    case VK_F16P: return scatter_rows_go<F16PTag>(prepare, A, n, r_lo, r_hi, c, st, ypart, grid, s);
+    case VK_F32U16: return scatter_rows_go<F32U16Tag>(prepare, A, n, r_lo, r_hi, c, st, ypart, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+} // namespace
+
+hipError_t prepare_scatter_rows(int vk, int64_t n)
+{
+    SpView none{};
+    return scatter_rows_dispatch(1, none, vk, n, 0, 0, nullptr, nullptr, nullptr, 0, nullptr);
+}
+
+hipError_t launch_scatter_rows(const SpView &A, int vk, int64_t n, long long r_lo, long long r_hi, const float *c,
+                               const SliceState *st, float *ypart, int grid, hipStream_t s)
+{
+    return scatter_rows_dispatch(0, A, vk, n, r_lo, r_hi, c, st, ypart, grid, s);
 }
 
 hipError_t launch_step_apply(int64_t n, int B, const double *y, float *x, const float *lo, const float *hi,

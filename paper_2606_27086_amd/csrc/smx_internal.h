@@ -320,9 +320,14 @@ int fused_apply_grid(int64_t n);
 // iteration; in deferred mode (cs.defer) y itself into cs.ybuf (and ybuf32)
 // with fused_apply_grid(n) partials of ||y||^2 in cs.ypart (the extrapolated
 // steps then apply x in k_step_apply)
-hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, float *x, ColStep cs,
+hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, int nvec, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
                               hipStream_t s);
+// y partials of rows [r_lo, r_hi) whose c is set (the dose-volume rows of a
+// fused-pass problem, after their ranking): grid float32 vectors of n at ypart
+hipError_t prepare_scatter_rows(int vk, int64_t n);
+hipError_t launch_scatter_rows(const SpView &A, int vk, int64_t n, long long r_lo, long long r_hi, const float *c,
+                               const SliceState *st, float *ypart, int grid, hipStream_t s);
 // largest dynamic LDS one fused workgroup may take on the current device, after
 // the kernel's attributes are raised to it (0 if that fails)
 size_t fused_lds_limit();

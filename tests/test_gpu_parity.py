@@ -1169,20 +1169,27 @@ def _dvc_rt(basic, K=30):
     return w.with_params(x0=W.synthetic_iterate(w, seed=79, spread=0.3))
 
 
-def test_dvc_random_parity(smx):
+@pytest.mark.parametrize("fused", [True, False])
+def test_dvc_random_parity(smx, fused):
     """Two dose-volume constraints beside ordinary bands, squared-norm
-    perturbations: the iterate, every proximity and the decisions match."""
+    perturbations: the iterate, every proximity and the decisions match, with
+    the fused pass (z in LDS: the constraint rows' values stored during the
+    pass, their c_i a_i added by a second kernel after the ranking) and with
+    the two passes."""
     w = _dvc_random()
-    assert _fused_info(smx, w) is None  # ranking before c: the two passes
-    check_parity(smx, w, w.K)
+    info = _fused_info(smx, w)
+    assert info is not None and info["zl"] == 1  # only the shapes that store the rows' values
+    check_parity(smx, w, w.K, fused=fused)
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("method", ["simult", "emr"])
-def test_dvc_rt_parity(smx, method):
+def test_dvc_rt_parity(smx, method, fused):
     """The radiotherapy case with the horseshoe plan's dose-volume constraints,
-    the linear objective, and the weighted simultaneous or the EMR step."""
+    the linear objective, and the weighted simultaneous or the EMR step, with
+    the fused pass and with the two passes."""
     w = _dvc_rt(BASIC_CASES.get(method, W.BASIC_SIMULT))
-    check_parity(smx, w, w.K, sensitive=method == "emr")
+    check_parity(smx, w, w.K, sensitive=method == "emr", fused=fused)
 
 
 def test_dvc_rt_emr_lockstep(smx):
@@ -1204,7 +1211,7 @@ def test_dvc_bf16(smx):
 
 def test_dvc_query_and_graph(smx):
     """The proximity at a loaded point counts the constraints' projections;
-    graph replay equals eager bitwise."""
+    graph replay equals eager bitwise (two passes)."""
     w = _dvc_random(K=25, seed=84)
     say("dose-volume query and graph replay")
     x = W.synthetic_iterate(w, seed=85)
@@ -1214,8 +1221,8 @@ def test_dvc_query_and_graph(smx):
     p.close()
     P = oracle.from_workload(w)
     assert prox[0] == pytest.approx(P.proximity(x[:, 0].astype(np.float64)), rel=2e-6)
-    xe, _, _, he, _ = gpu_run(smx, w, w.K, graph=False)
-    xg, _, _, hg, _ = gpu_run(smx, w, w.K, graph=True)
+    xe, _, _, he, _ = gpu_run(smx, w, w.K, graph=False, fused=False)  # the two passes: sums in a fixed order
+    xg, _, _, hg, _ = gpu_run(smx, w, w.K, graph=True, fused=False)
     assert np.array_equal(xe, xg) and np.array_equal(he["prox"], hg["prox"])
 
 
