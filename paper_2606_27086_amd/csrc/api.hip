@@ -296,6 +296,7 @@ struct smx_problem {
     int phase_form = SMX_PHASE_AUTO; // one launch per perturbation phase where eligible, or one per trial batch
     FusedCfg fcfg[3]{};
     DBuf ypart; // grid x n partial vectors of y = A^T c
+    DBuf part_lin; // the linear objective's direction partials written by the fused pass's apply kernel
     // basic algorithm (SMX_BASIC_*) and what its step needs beyond D
     int basic = SMX_BASIC_SIMULT;
     DBuf S32, S16; // step weights when they differ from D (CQ: 1/||A||_F^2, EMR: w)
@@ -365,7 +366,8 @@ struct smx_problem {
         size_t t = 0;
         for (const DBuf *b : {&x, &g, &c, &lower, &upper, &box_lo, &box_hi, &lin_c, &w, &D32, &D16, &st, &qout,
                               &part_pass, &part_query, &part_phase, &part_trial[0], &part_trial[1], &h_prox, &h_fs,
-                              &h_fe, &h_tr, &h_ac, &ypart, &S32, &S16, &ybuf, &ybuf32, &part_y, &part_q, &ypanel,
+                              &h_fe, &h_tr, &h_ac, &ypart, &part_lin, &S32, &S16, &ybuf, &ybuf32, &part_y, &part_q,
+                              &ypanel,
                               &xprev, &part_var, &dvc_dose, &dvc_key, &dvc_hist, &dvc_sel, &dvc_part})
             t += b->bytes;
         return t;
@@ -852,12 +854,24 @@ int phase_flips(const smx_problem *p)
     return phase_kind(p) == PHASE_CHAIN ? chain_trial_launches(p) + 1 : 1;
 }
 
+// Whether iterations of value kind vk take the linear objective's direction
+// partials from the previous iteration's apply kernel (fused pass, the step
+// applied there), so that the phase is the one closed-form launch.
+bool lin_from_apply(const smx_problem *p, int vk)
+{
+    const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
+    return phase_kind(p) == PHASE_LINEAR && p->fused[vk] && !extrap && p->part_lin.p;
+}
+
 // Launches of one perturbation phase.
 int phase_launch_count(const smx_problem *p)
 {
     switch (phase_kind(p)) {
     case PHASE_SMALL: return 1;
-    case PHASE_LINEAR: return 2;
+    case PHASE_LINEAR:
+        for (int vk = 0; vk < 3; ++vk)
+            if (lin_from_apply(p, vk)) return 1;
+        return 2;
     default: return chain_trial_launches(p) + 2;
     }
 }
@@ -874,12 +888,19 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
                   "phase");
         cur ^= 1;
     } else if (perturb && p->pp.obj != OBJ_NONE && pk == PHASE_LINEAR) {
-        hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(), p->state(cur), 0,
-                               p->part_phase.as<double>(), s),
-                  "phase");
-        hip_check(launch_trial_linear(p->pp, p->x.as<float>(), p->lin_c.as<float>(), p->state(cur), p->state(cur ^ 1),
-                                      p->part_phase.as<double>(), s),
-                  "linear phase");
+        if (lin_from_apply(p, vk)) { // the partials of x^k came from the last apply (or the run's start)
+            hip_check(launch_trial_linear(p->pp, p->x.as<float>(), p->lin_c.as<float>(), p->state(cur),
+                                          p->state(cur ^ 1), p->part_lin.as<double>(), s,
+                                          fused_apply_grid(p->n)),
+                      "linear phase");
+        } else {
+            hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(), p->state(cur), 0,
+                                   p->part_phase.as<double>(), s),
+                      "phase");
+            hip_check(launch_trial_linear(p->pp, p->x.as<float>(), p->lin_c.as<float>(), p->state(cur),
+                                          p->state(cur ^ 1), p->part_phase.as<double>(), s),
+                      "linear phase");
+        }
         cur ^= 1;
     } else if (perturb && p->pp.obj != OBJ_NONE) {
         hip_check(launch_phase(p->pp, p->x.as<float>(), p->g.as<float>(), p->lin_c.as<float>(), p->state(cur), 0,
@@ -928,8 +949,10 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
             nvec *= 2;
         }
         if (timed) hip_check(hipEventRecord(e[2], s), "event");
+        const bool lin = lin_from_apply(p, vk);
         hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, nvec, p->x.as<float>(), p->col_step(extrap),
-                                     p->state(cur), p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s),
+                                     p->state(cur), p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s,
+                                     lin ? p->lin_c.as<float>() : nullptr, lin ? p->part_lin.as<double>() : nullptr),
                   "fused apply");
         if (timed) hip_check(hipEventRecord(e[3], s), "event");
         if (extrap) enqueue_extrapolated_step(p, vk, rw, p->fcfg[vk].grid, fused_apply_grid(p->n), cur, s);
@@ -1028,6 +1051,11 @@ int run_impl(smx_problem *p, int32_t K, uint32_t flags)
         int64_t end = it;
         while (end < K && vk_for_iteration(p, end, K, ref) == vk) ++end;
         int64_t left = end - it;
+        // the first phase of the run of iterations needs its direction partials of x
+        if (perturb && lin_from_apply(p, vk))
+            hip_check(launch_lin_partials(p->x.as<float>(), p->lin_c.as<float>(), p->n, p->part_lin.as<double>(),
+                                          p->stream),
+                      "direction partials");
         if (graph) {
             while (left > 0) {
                 const int chunk = (int)std::min<int64_t>(left, kGraphChunk);
@@ -1220,7 +1248,10 @@ size_t problem_plan_bytes(int64_t m, int64_t n, bool has_f32, int lp, const smx_
     }
     FusedCfg fc;
     size_t lds = 0;
-    if (fused_plan(n, d->B, dt.n, fc, lds)) add(lds * size_t(fc.grid)); // partial vectors of y
+    if (fused_plan(n, d->B, dt.n, fc, lds)) {
+        add(lds * size_t(fc.grid)); // partial vectors of y
+        if (d->obj_kind == SMX_OBJ_LINEAR) add(8 * 2 * size_t(fused_apply_grid(n))); // direction partials
+    }
     if (lds_passes_available(d->B) && panel_count(m) > 0) add(8 * size_t(panel_count(m)) * N);
     PertParams pp{};
     pp.obj = d->obj_kind;
@@ -1275,6 +1306,8 @@ void setup_fused(smx_problem *p)
         any = any || ok;
     }
     if (any) p->ypart.alloc(bytes * size_t(c.grid), "fused partial vectors");
+    if (any && p->pp.obj == OBJ_LINEAR) // the next phase's direction partials, from the apply kernel
+        p->part_lin.alloc(sizeof(double) * 2 * size_t(fused_apply_grid(p->n)), "direction partials");
 }
 
 int create_problem(smx_operator *op, const smx_problem_desc *d, hipStream_t s, smx_problem **out)

@@ -1310,6 +1310,38 @@ __global__ __launch_bounds__(kFusedRcBlock) void k_fused_rc(SpView A, int n, con
     for (int j = threadIdx.x; j < n; j += kFusedRcBlock) out[j] = y[j];
 }
 
+// Direction partials of the linear objective f = c^T x for the next
+// perturbation phase: this workgroup's sums of c_j^2 and c_j x_j over the
+// unknowns j0 + l (l < 64, j0 = 64 blockIdx.x, stepping 64 gridDim.x),
+// added by the first wave's lanes in that order and then over the
+// workgroup, stored as the direction launch's partials would be (slot
+// blockIdx.x of 2 x gridDim.x).  k_fused_apply calls it after writing x and
+// k_lin_partials alone, with the same sums in the same order.
+__device__ inline void lin_partials_block(const float *__restrict__ x, const float *__restrict__ c, int n,
+                                          double *__restrict__ part, double *lds)
+{
+    double v[2] = {0.0, 0.0}; // sum c^2, c^T x
+    if ((threadIdx.x >> 6) == 0)
+        for (int j = blockIdx.x * 64 + (int)threadIdx.x; j < n; j += gridDim.x * 64) {
+            const double cj = (double)c[j];
+            v[0] += cj * cj;
+            v[1] += cj * (double)x[j];
+        }
+    block_sum<2, kApplyBlock>(v, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[gridDim.x + blockIdx.x] = v[1];
+    }
+}
+
+__global__ __launch_bounds__(kApplyBlock) void k_lin_partials(const float *__restrict__ x,
+                                                              const float *__restrict__ c, int n,
+                                                              double *__restrict__ part)
+{
+    __shared__ double lds[kApplyBlock / 64 * 2];
+    lin_partials_block(x, c, n, part, lds);
+}
+
 // x = clip(z + lambda * Z_j * sum_g ypart[g], lo, hi) (Z_j = 1 unless DROP);
 // 64 unknowns per workgroup, the four waves each sum every fourth partial
 // (loads issued four at a time, added in order) and the four sums are added in
@@ -1319,10 +1351,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_fused_apply(const AccT *__restr
                                                         float *__restrict__ x, ColStep cs,
                                                         const SliceState *__restrict__ st_in,
                                                         SliceState *__restrict__ st_out,
-                                                        const double *__restrict__ part1, int nparts1, Hist h)
+                                                        const double *__restrict__ part1, int nparts1, Hist h,
+                                                        const float *__restrict__ lin_c, double *__restrict__ lin_part)
 {
     __shared__ double red[kApplyBlock / 64][64];
-    __shared__ double lds[kApplyBlock / 64];
+    __shared__ double lds[kApplyBlock / 64 * 2];
     const int wid = threadIdx.x >> 6, wl = threadIdx.x & 63;
     double ysq = 0.0; // deferred mode: this thread's share of ||y||^2
     if (st_in[0].live) {
@@ -1360,6 +1393,9 @@ __global__ __launch_bounds__(kApplyBlock) void k_fused_apply(const AccT *__restr
             __syncthreads();
         }
     }
+    // the next phase's direction partials from the x just written (each
+    // lane rereads its own entries)
+    if (lin_part) lin_partials_block(x, lin_c, n, lin_part, lds);
     if (cs.defer) {
         double v[1] = {ysq};
         block_sum<1, kApplyBlock>(v, lds);
@@ -3442,18 +3478,26 @@ hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n,
 
 hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, int nvec, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
-                              hipStream_t s)
+                              hipStream_t s, const float *lin_c, double *lin_part)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1 || nvec < cfg.grid || nvec > 2 * cfg.grid ||
-        (cfg.acc64 && nvec != cfg.grid))
+        (cfg.acc64 && nvec != cfg.grid) || (lin_part && (!lin_c || cs.defer)))
         return hipErrorInvalidValue;
     const unsigned grid = (unsigned)fused_apply_grid(n);
     if (cfg.acc64)
         hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const double *>(ypart),
-                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
+                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h, lin_c, lin_part);
     else
         hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const float *>(ypart),
-                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h);
+                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h, lin_c, lin_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_lin_partials(const float *x, const float *c, int64_t n, double *part, hipStream_t s)
+{
+    if (n < 1 || !x || !c || !part) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lin_partials, dim3((unsigned)fused_apply_grid(n)), dim3(kApplyBlock), 0, s, x, c, (int)n,
+                       part);
     return hipGetLastError();
 }
 
@@ -3876,11 +3920,12 @@ hipError_t launch_phase_small(const PertParams &pp, float *x, const float *lin_c
 }
 
 hipError_t launch_trial_linear(const PertParams &pp, float *x, const float *c, const SliceState *st_in,
-                               SliceState *st_out, const double *part_phase, hipStream_t s)
+                               SliceState *st_out, const double *part_phase, hipStream_t s, int nt)
 {
     if (pp.obj != OBJ_LINEAR || pp.max_trials < 1 || pp.max_trials > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_trial_linear, dim3(phase_grid(pp), pp.B), dim3(kBlock), 0, s, x, c, st_in, st_out, pp,
-                       part_phase);
+    if (nt == 0) nt = phase_grid(pp); // the direction launch's partials
+    if (nt < 1 || nt > 65535 || (nt != phase_grid(pp) && pp.B != 1)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_trial_linear, dim3(nt, pp.B), dim3(kBlock), 0, s, x, c, st_in, st_out, pp, part_phase);
     return hipGetLastError();
 }
 

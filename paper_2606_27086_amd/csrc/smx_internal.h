@@ -320,9 +320,14 @@ int fused_apply_grid(int64_t n);
 // iteration; in deferred mode (cs.defer) y itself into cs.ybuf (and ybuf32)
 // with fused_apply_grid(n) partials of ||y||^2 in cs.ypart (the extrapolated
 // steps then apply x in k_step_apply)
+// lin_part (with lin_c): also the linear objective's direction partials of
+// the x written, for the next phase (fused_apply_grid(n) slots, not in the
+// deferred mode)
 hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, int nvec, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
-                              hipStream_t s);
+                              hipStream_t s, const float *lin_c = nullptr, double *lin_part = nullptr);
+// the same direction partials of x alone (one slice)
+hipError_t launch_lin_partials(const float *x, const float *c, int64_t n, double *part, hipStream_t s);
 // y partials of rows [r_lo, r_hi) whose c is set (the dose-volume rows of a
 // fused-pass problem, after their ranking): grid float32 vectors of n at ypart
 hipError_t prepare_scatter_rows(int vk, int64_t n);
@@ -371,7 +376,7 @@ hipError_t launch_phase_small(const PertParams &pp, float *x, const float *lin_c
 // The linear objective's phase after launch_phase (its partials in
 // part_phase): trials in closed form, the accepted step added to x.
 hipError_t launch_trial_linear(const PertParams &pp, float *x, const float *c, const SliceState *st_in,
-                               SliceState *st_out, const double *part_phase, hipStream_t s);
+                               SliceState *st_out, const double *part_phase, hipStream_t s, int nt = 0);
 hipError_t launch_trial_close(const PertParams &pp, float *x, const float *g, const SliceState *st_in,
                               SliceState *st_out, const double *part_prev, hipStream_t s);
 hipError_t launch_trial(const PertParams &pp, float *x, const float *g, const SliceState *st_in, SliceState *st_out,

@@ -791,6 +791,35 @@ def test_phase_forms_parity(smx, case, form):
     check_parity(smx, w, w.K, phase_form=f)
 
 
+def test_closed_form_partials_from_apply(smx):
+    """The closed-form linear phase on the fused pass takes its direction
+    partials from the previous iteration's apply kernel (and from a
+    partials launch where a run, or a run of iterations of one value kind,
+    starts): against the oracle with the bf16 operator and a float32
+    refinement tail (a change of value kind mid-run), and across a
+    checkpoint and resume."""
+    w = W.random_sparse(6000, 9000, 20, seed=51, empty_frac=0.05, obj=W.OBJ_LINEAR, K=24)
+    p = smx.problem_from_workload(w)
+    assert p.fused_in_use() and p.describe()["phase_launches"] == 1
+    p.close()
+    check_parity(smx, w, w.K, storage="bf16", value_round="bf16", refine_iters=5)
+    say("closed-form phase on the fused pass, checkpoint and resume")
+    p = smx.problem_from_workload(w, history_cap=0)
+    p.run(10, graph=True)
+    p.sync()
+    states, x1 = p.get_state()
+    p.close()
+    q = smx.problem_from_workload(w, history_cap=0)
+    q.set_state(states, x1)
+    q.run(w.K - 10, graph=True)
+    q.sync()
+    x = q.get_x().cpu().numpy()[:, 0].astype(np.float64)
+    sq, _ = q.get_state()
+    q.close()
+    xo, sto, ho, _ = oracle_run(w, w.K)
+    assert rel(x, xo) <= RTOL and sq[0]["ell"] == sto.ell and sq[0]["trials"] == sto.trials
+
+
 def test_phase_form_choice_and_args(smx):
     """Auto picks one launch for flat objectives up to n = 8,192, the closed
     form for the linear objective beyond, and the batches otherwise; one
@@ -804,6 +833,8 @@ def test_phase_form_choice_and_args(smx):
         d = p.describe()
         if launches is not None:
             assert d["phase_launches"] == launches
+        elif w.obj == W.OBJ_LINEAR:  # closed form: one launch when the apply kernel leaves the partials
+            assert d["phase_launches"] == (1 if p.fused_in_use() else 2)
         else:
             assert d["phase_launches"] > 1
         if eligible:
@@ -814,7 +845,8 @@ def test_phase_form_choice_and_args(smx):
                 p.set_phase_form(smx.PHASE_ONE_LAUNCH)
         if w.obj == W.OBJ_LINEAR:
             p.set_phase_form(smx.PHASE_CLOSED_FORM)
-            assert p.describe()["phase_launches"] == 2
+            # one launch where the fused pass's apply kernel leaves the direction partials
+            assert p.describe()["phase_launches"] == (1 if p.fused_in_use() else 2)
         else:
             with pytest.raises(smx.SmxError, match="ESTATE"):
                 p.set_phase_form(smx.PHASE_CLOSED_FORM)
