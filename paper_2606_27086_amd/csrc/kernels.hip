@@ -438,8 +438,18 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
     double pacc[1] = {0.0};
     if (live) {
         const long long stride = (long long)gridDim.x * RPB;
-        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
-            const int beg = A.ptr[row], end = A.ptr[row + 1];
+        long long row = (long long)blockIdx.x * RPB + grp;
+        int beg = 0, end = 0;
+        if (row < A.rows) {
+            beg = A.ptr[row];
+            end = A.ptr[row + 1];
+        }
+        for (; row < A.rows; row += stride) {
+            int nbeg = 0, nend = 0; // the next row's offsets, in flight meanwhile
+            if (row + stride < A.rows) {
+                nbeg = A.ptr[row + stride];
+                nend = A.ptr[row + stride + 1];
+            }
             float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
             if (lane == 0) { // epilogue operands, fetched while the row streams
                 lo = lower[row];
@@ -449,6 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
             }
             const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
             if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
+            beg = nbeg;
+            end = nend;
         }
     }
     block_sum<1>(pacc, lds);
@@ -533,8 +545,18 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass1_lds(SpView A, const flo
         stage_vector<kLdsPassBlock>(xl4, x, P);
         __syncthreads();
         const long long stride = (long long)gridDim.x * RPB;
-        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
-            const int beg = A.ptr[row], end = A.ptr[row + 1];
+        long long row = (long long)blockIdx.x * RPB + grp;
+        int beg = 0, end = 0;
+        if (row < A.rows) {
+            beg = A.ptr[row];
+            end = A.ptr[row + 1];
+        }
+        for (; row < A.rows; row += stride) {
+            int nbeg = 0, nend = 0; // the next row's offsets, in flight meanwhile
+            if (row + stride < A.rows) {
+                nbeg = A.ptr[row + stride];
+                nend = A.ptr[row + stride + 1];
+            }
             float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
             if (lane == 0) {
                 lo = lower[row];
@@ -545,6 +567,8 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass1_lds(SpView A, const flo
             const double r =
                 group_sum<LPR>(row_dot_split<LPR, VEC, VT>(A, beg, end, lane, x, xl, P)) * (double)A.vscale_inv;
             if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
+            beg = nbeg;
+            end = nend;
         }
     }
     block_sum<1, kLdsPassBlock>(pacc, lds);
@@ -841,8 +865,18 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass2_lds(SpView At, const fl
         const int lane = threadIdx.x & (LPR - 1);
         const int grp = threadIdx.x / LPR;
         const long long stride = (long long)gridDim.x * RPB;
-        for (long long col = (long long)blockIdx.x * RPB + grp; col < At.rows; col += stride) {
-            const int beg = At.ptr[col], end = At.ptr[col + 1];
+        long long col = (long long)blockIdx.x * RPB + grp;
+        int beg = 0, end = 0;
+        if (col < At.rows) {
+            beg = At.ptr[col];
+            end = At.ptr[col + 1];
+        }
+        for (; col < At.rows; col += stride) {
+            int nbeg = 0, nend = 0; // the next column's offsets, in flight meanwhile
+            if (col + stride < At.rows) {
+                nbeg = At.ptr[col + stride];
+                nend = At.ptr[col + stride + 1];
+            }
             float xo = 0.f, l = 0.f, u = 0.f;
             if (lane == 0 && !cs.defer) {
                 xo = x[col];
@@ -852,6 +886,8 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass2_lds(SpView At, const fl
             const double y =
                 group_sum<LPR>(row_dot_split<LPR, VEC, VT>(At, beg, end, lane, c, cl, P)) * (double)At.vscale_inv;
             if (lane == 0) yacc += epi2(cs, col, col, y, xo, l, u, x);
+            beg = nbeg;
+            end = nend;
         }
     }
     end_pass2<kLdsPassBlock>(cs, yacc, st_in, st_out, part1, nparts1, h, lds);
@@ -3202,8 +3238,18 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
         stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
         __syncthreads();
         const long long stride = (long long)gridDim.x * RPB;
-        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
-            const int beg = A.ptr[row], end = A.ptr[row + 1];
+        long long row = (long long)blockIdx.x * RPB + grp;
+        int beg = 0, end = 0;
+        if (row < A.rows) {
+            beg = A.ptr[row];
+            end = A.ptr[row + 1];
+        }
+        for (; row < A.rows; row += stride) {
+            int nbeg = 0, nend = 0; // the next row's offsets, in flight meanwhile
+            if (row + stride < A.rows) {
+                nbeg = A.ptr[row + stride];
+                nend = A.ptr[row + stride + 1];
+            }
             float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
             if (lane == 0) {
                 lo = lower[row];
@@ -3218,6 +3264,8 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
             ct = __shfl(ct, 0, LPR);
             if (ct != 0.0 && end > beg)
                 scatter_row<LPR, VEC, VT, float>(A, beg, end, lane, grp, ct * (double)A.vscale_inv, y);
+            beg = nbeg;
+            end = nend;
         }
     }
     block_sum<1, kFusedBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
@@ -3258,10 +3306,22 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, cons
         stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
         __syncthreads();
         const long long stride = (long long)gridDim.x * RPB;
-        for (long long row = (long long)blockIdx.x * RPB + grp; row < A.rows; row += stride) {
-            const int beg = A.ptr[row], end = A.ptr[row + 1];
+        long long row = (long long)blockIdx.x * RPB + grp;
+        int beg = 0, end = 0;
+        if (row < A.rows) {
+            beg = A.ptr[row];
+            end = A.ptr[row + 1];
+        }
+        for (; row < A.rows; row += stride) {
             RowRegs<VEC, CAP> R;
             fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, R);
+            // the next row's offsets, in flight while this row is reduced and
+            // scattered: its entries can then be requested at once
+            int nbeg = 0, nend = 0;
+            if (row + stride < A.rows) {
+                nbeg = A.ptr[row + stride];
+                nend = A.ptr[row + stride + 1];
+            }
             float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
             if (lane == 0) {
                 lo = lower[row];
@@ -3307,6 +3367,8 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, cons
                     }
                 }
             }
+            beg = nbeg;
+            end = nend;
         }
     }
     block_sum<1, kFusedBlock>(pacc, lds); // its barriers also order the LDS adds before the copy-out
