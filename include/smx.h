@@ -492,7 +492,11 @@ int smx_set_fused(smx_problem *p, int32_t mode);
  *   SMX_PHASE_CLOSED_FORM (linear objective f = c^T x): the direction
  *     launch (f(x^k), ||c||), then one launch in which every workgroup takes
  *     each trial's value from f(x + t v) = f(x) - t ||c|| (v = -c/||c||), so
- *     no trial needs a pass over x, and adds the accepted step;
+ *     no trial needs a pass over x, and adds the accepted step.  On the
+ *     fused pass (not EL or EMR) the previous iteration's apply kernel
+ *     leaves the direction's partial sums, so the direction launch goes;
+ *     with z in LDS the pass itself opens the phase and stages
+ *     z = x + s v, and the phase takes no launch of its own;
  *   SMX_PHASE_AUTO (the default): ONE_LAUNCH for those objectives up to
  *     n = 8,192 (there the chain of launches, not the arithmetic, sets the
  *     phase's time; one workgroup reads x at one compute unit's rate, so on

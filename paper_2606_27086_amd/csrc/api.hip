@@ -863,14 +863,22 @@ bool lin_from_apply(const smx_problem *p, int vk)
     return phase_kind(p) == PHASE_LINEAR && p->fused[vk] && !extrap && p->part_lin.p;
 }
 
-// Launches of one perturbation phase.
+// Whether iterations of value kind vk take that phase inside the fused pass
+// (shapes with z in LDS): every workgroup of the pass opens the phase from the
+// partials and stages z = x + s v, and the apply kernel forms z_j again, so
+// the phase costs no launch of its own.
+bool lin_in_pass(const smx_problem *p, int vk) { return lin_from_apply(p, vk) && p->fcfg[vk].zl; }
+
+// Launches of one perturbation phase (of the first value kind that runs).
 int phase_launch_count(const smx_problem *p)
 {
     switch (phase_kind(p)) {
     case PHASE_SMALL: return 1;
     case PHASE_LINEAR:
-        for (int vk = 0; vk < 3; ++vk)
+        for (int vk = 0; vk < 3; ++vk) {
+            if (lin_in_pass(p, vk)) return 0;
             if (lin_from_apply(p, vk)) return 1;
+        }
         return 2;
     default: return chain_trial_launches(p) + 2;
     }
@@ -887,6 +895,8 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
                                      s),
                   "phase");
         cur ^= 1;
+    } else if (perturb && p->pp.obj != OBJ_NONE && pk == PHASE_LINEAR && lin_in_pass(p, vk)) {
+        // taken inside the fused pass below
     } else if (perturb && p->pp.obj != OBJ_NONE && pk == PHASE_LINEAR) {
         if (lin_from_apply(p, vk)) { // the partials of x^k came from the last apply (or the run's start)
             hip_check(launch_trial_linear(p->pp, p->x.as<float>(), p->lin_c.as<float>(), p->state(cur),
@@ -934,10 +944,20 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
     }
     const bool extrap = p->basic == SMX_BASIC_EL || p->basic == SMX_BASIC_EMR;
     if (p->fused[vk]) {
+        const bool lin_pass = perturb && p->pp.obj != OBJ_NONE && pk == PHASE_LINEAR && lin_in_pass(p, vk);
+        LinPhase lp{};
+        if (lin_pass) {
+            lp.c = p->lin_c.as<float>();
+            lp.part = p->part_lin.as<double>();
+            lp.nparts = fused_apply_grid(p->n);
+            lp.st_out = p->state(cur ^ 1);
+            lp.pp = p->pp;
+        }
         hip_check(launch_fused(p->fcfg[vk], view_for(p->op, false, fused_fmt(p, vk)), fused_fmt(p, vk), p->n, p->x.as<float>(),
                                p->lower.as<float>(), p->upper.as<float>(), rw, p->state(cur),
-                               p->part_pass.as<double>(), p->ypart.p, s),
+                               p->part_pass.as<double>(), p->ypart.p, s, lin_pass ? &lp : nullptr),
                   "fused pass");
+        if (lin_pass) cur ^= 1; // the phase's state
         if (timed) hip_check(hipEventRecord(e[1], s), "event");
         int nvec = p->fcfg[vk].grid;
         if (p->dvc.n > 0) { // rank the dose-volume rows, then add their c_i a_i as a second set of partials
@@ -952,7 +972,8 @@ int enqueue_iteration_core(smx_problem *p, hipStream_t s, int vk, bool perturb, 
         const bool lin = lin_from_apply(p, vk);
         hip_check(launch_fused_apply(p->fcfg[vk], p->n, p->ypart.p, nvec, p->x.as<float>(), p->col_step(extrap),
                                      p->state(cur), p->state(cur ^ 1), p->part_pass.as<double>(), p->hist, s,
-                                     lin ? p->lin_c.as<float>() : nullptr, lin ? p->part_lin.as<double>() : nullptr),
+                                     lin ? p->lin_c.as<float>() : nullptr, lin ? p->part_lin.as<double>() : nullptr,
+                                     lin_pass ? 1 : 0),
                   "fused apply");
         if (timed) hip_check(hipEventRecord(e[3], s), "event");
         if (extrap) enqueue_extrapolated_step(p, vk, rw, p->fcfg[vk].grid, fused_apply_grid(p->n), cur, s);

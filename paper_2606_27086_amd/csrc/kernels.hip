@@ -486,6 +486,44 @@ __device__ inline void stage_vector(float4 *dst, const float *__restrict__ v, in
     if (threadIdx.x < (P & 3)) reinterpret_cast<float *>(dst)[4 * q4 + threadIdx.x] = v[4 * q4 + threadIdx.x];
 }
 
+// One unknown of the linear objective's trial point z = x + s v, v = -c/||c||
+// (inv_gn = 1/||c||): the one expression every kernel forming z uses, so the
+// pass that stages z and the apply kernel that forms it again agree bit for bit.
+__device__ inline float linear_step_point(float xj, float cj, double s_acc, double inv_gn)
+{
+    return (float)((double)xj + s_acc * (-(double)cj * inv_gn));
+}
+
+// stage_vector of z = x + s v for the linear objective (x and c both read as
+// float4, four loads of each in flight per thread).
+template <int BS>
+__device__ inline void stage_linear_point(float4 *dst, const float *__restrict__ x, const float *__restrict__ c, int P,
+                                          double s_acc, double inv_gn)
+{
+    const int q4 = P >> 2;
+    const float4 *x4 = reinterpret_cast<const float4 *>(x);
+    const float4 *c4 = reinterpret_cast<const float4 *>(c);
+    for (int e0 = threadIdx.x; e0 < q4; e0 += 4 * BS) {
+        float4 tx[4], tc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            tx[u] = x4[min(e0 + u * BS, q4 - 1)];
+            tc[u] = c4[min(e0 + u * BS, q4 - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e0 + u * BS < q4)
+                dst[e0 + u * BS] = make_float4(linear_step_point(tx[u].x, tc[u].x, s_acc, inv_gn),
+                                               linear_step_point(tx[u].y, tc[u].y, s_acc, inv_gn),
+                                               linear_step_point(tx[u].z, tc[u].z, s_acc, inv_gn),
+                                               linear_step_point(tx[u].w, tc[u].w, s_acc, inv_gn));
+    }
+    if (threadIdx.x < (P & 3)) {
+        const int j = 4 * q4 + threadIdx.x;
+        reinterpret_cast<float *>(dst)[j] = linear_step_point(x[j], c[j], s_acc, inv_gn);
+    }
+}
+
 // Row dot product whose gathers read the vector's first P entries from an
 // LDS copy (xl) and the rest from memory; otherwise row_dot_chunked.
 template <int LPR, int VEC, typename VT>
@@ -1388,12 +1426,21 @@ __global__ __launch_bounds__(kApplyBlock) void k_fused_apply(const AccT *__restr
                                                         const SliceState *__restrict__ st_in,
                                                         SliceState *__restrict__ st_out,
                                                         const double *__restrict__ part1, int nparts1, Hist h,
-                                                        const float *__restrict__ lin_c, double *__restrict__ lin_part)
+                                                        const float *__restrict__ lin_c, double *__restrict__ lin_part,
+                                                        int lin_z)
 {
     __shared__ double red[kApplyBlock / 64][64];
     __shared__ double lds[kApplyBlock / 64 * 2];
     const int wid = threadIdx.x >> 6, wl = threadIdx.x & 63;
     double ysq = 0.0; // deferred mode: this thread's share of ||y||^2
+    // the linear phase taken in the pass: x still holds x^k, z_j is formed here
+    bool zstep = false;
+    double zs = 0.0, zinv = 0.0;
+    if (lin_z && st_in[0].applied && st_in[0].s_acc != 0.0) {
+        zstep = true;
+        zs = st_in[0].s_acc;
+        zinv = 1.0 / st_in[0].gn;
+    }
     if (st_in[0].live) {
         for (int j0 = blockIdx.x * 64; j0 < n; j0 += gridDim.x * 64) {
             const int j = j0 + wl;
@@ -1422,7 +1469,8 @@ __global__ __launch_bounds__(kApplyBlock) void k_fused_apply(const AccT *__restr
                     ysq += yv * yv;
                 } else {
                     if (cs.zcol) yv *= (double)cs.zcol[j];
-                    const double z = fma((double)cs.lambda, yv, (double)x[j]);
+                    const float zj = zstep ? linear_step_point(x[j], lin_c[j], zs, zinv) : x[j];
+                    const double z = fma((double)cs.lambda, yv, (double)zj);
                     x[j] = (float)fmin(fmax(z, (double)cs.lo[j]), (double)cs.hi[j]);
                 }
             }
@@ -1746,24 +1794,33 @@ int phase_grid(const PertParams &pp)
 // of BS threads; every thread must call it, and tot is valid for every thread
 // on return.  Row v0+r is summed by wave r mod (BS/64): lane l adds tiles
 // l, l+64, ... in order, then the lanes are added by wave_sum.  The rows of a
-// wave are loaded together, so their loads overlap.
+// wave, and U tiles of each, are loaded together, so their loads overlap.
 template <int BS>
 __device__ inline void chunk_totals(const double *__restrict__ part, long long nslots, int s, int nt, int v0, int nv,
                                     double *tot)
 {
     constexpr int W = BS / 64, RPW = (kTrialChunk + W - 1) / W;
+    constexpr int U = RPW >= 16 ? 1 : 16 / RPW;
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double a[RPW];
 #pragma unroll
     for (int q = 0; q < RPW; ++q) a[q] = 0.0;
     if (wid < nv) {
-        for (int b = lane; b < nt; b += 64) {
-            double v[RPW];
+        for (int b0 = lane; b0 < nt; b0 += 64 * U) {
+            double v[U][RPW];
 #pragma unroll
-            for (int q = 0; q < RPW; ++q)
-                v[q] = part[(long long)(v0 + min(wid + W * q, nv - 1)) * nslots + (long long)s * nt + b];
+            for (int u = 0; u < U; ++u) {
+                const int b = min(b0 + 64 * u, nt - 1); // past nt: loaded, not added
 #pragma unroll
-            for (int q = 0; q < RPW; ++q) a[q] += v[q];
+                for (int q = 0; q < RPW; ++q)
+                    v[u][q] = part[(long long)(v0 + min(wid + W * q, nv - 1)) * nslots + (long long)s * nt + b];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (b0 + 64 * u < nt) {
+#pragma unroll
+                    for (int q = 0; q < RPW; ++q) a[q] += v[u][q];
+                }
         }
         wave_sum<RPW>(a);
         if (lane == 0) {
@@ -1884,13 +1941,13 @@ __device__ inline void derive_state(SliceState &sS, const SliceState *__restrict
                                     int first, const double *__restrict__ part_prev, int s, int nt, double *tot)
 {
     if (threadIdx.x == 0) sS = st_in[s];
-    __syncthreads();
     const long long nslots = (long long)pp.B * nt;
-    if (first) {
+    if (first) { // the state's loads overlap the partials' (thread 0 alone reads sS before the barriers)
         chunk_totals<BS>(part_prev, nslots, s, nt, 0, 2, tot);
         if (threadIdx.x == 0) open_phase_state(sS, pp, tot[0], tot[1]);
         __syncthreads();
     } else {
+        __syncthreads();
         derive_decision<BS>(sS, pp, part_prev, nslots, s, nt, tot);
     }
 }
@@ -2171,21 +2228,19 @@ __global__ __launch_bounds__(kTrialBlock) void k_trial_close(float *__restrict__
     publish_state(S, st_out, s, apply);
 }
 
-// The phase of the linear objective f(x) = c^T x after its direction launch,
-// in one launch.  On v = -c/||c|| the objective at a trial point is known in
-// closed form, f(x + t v) = f(x) - t ||c||, so no trial needs a pass over x:
-// every workgroup opens the phase from the direction launch's partials (the
-// same sums in the same order), runs the reduction steps' trials on those
-// values, and adds the accepted step to its own part of x.
-__global__ __launch_bounds__(kBlock) void k_trial_linear(float *__restrict__ x, const float *__restrict__ c,
-                                                         const SliceState *__restrict__ st_in,
-                                                         SliceState *__restrict__ st_out, PertParams pp,
-                                                         const double *__restrict__ part_phase)
+// The phase of the linear objective f(x) = c^T x from its direction partials
+// (sum c_j^2 and sum c_j x_j per workgroup of the launch that left them).  On
+// v = -c/||c|| the objective at a trial point is known in closed form,
+// f(x + t v) = f(x) - t ||c||, so no trial needs a pass over x: every
+// workgroup opens the phase from the partials (the same sums in the same
+// order) and runs the reduction steps' trials on those values; workgroup 0
+// publishes the state.  Returns whether the accepted step s v is to be added.
+template <int BS>
+__device__ inline bool linear_phase(SliceState &sS, const SliceState *__restrict__ st_in, const PertParams &pp,
+                                   const double *__restrict__ part, int s, int nt, double *tot,
+                                   SliceState *__restrict__ st_out)
 {
-    __shared__ double tot[kTrialChunk];
-    __shared__ SliceState sS;
-    const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
-    derive_state<kBlock>(sS, st_in, pp, 1, part_phase, s, nt, tot);
+    derive_state<BS>(sS, st_in, pp, 1, part, s, nt, tot);
     if (threadIdx.x == 0) {
         SliceState &S = sS;
         const double f = S.f_cur; // f(x^k)
@@ -2196,14 +2251,26 @@ __global__ __launch_bounds__(kBlock) void k_trial_linear(float *__restrict__ x, 
         }
     }
     __syncthreads();
-    const SliceState &S = sS;
-    const bool apply = must_apply(S);
-    if (apply) {
-        const double inv_gn = 1.0 / S.gn;
+    const bool apply = must_apply(sS);
+    publish_state(sS, st_out, s, apply);
+    return apply;
+}
+
+// The linear phase in one launch: each workgroup adds the step to its own
+// part of x.
+__global__ __launch_bounds__(kBlock) void k_trial_linear(float *__restrict__ x, const float *__restrict__ c,
+                                                         const SliceState *__restrict__ st_in,
+                                                         SliceState *__restrict__ st_out, PertParams pp,
+                                                         const double *__restrict__ part_phase)
+{
+    __shared__ double tot[kTrialChunk];
+    __shared__ SliceState sS;
+    const int s = blockIdx.y, B = pp.B, nt = gridDim.x;
+    if (linear_phase<kBlock>(sS, st_in, pp, part_phase, s, nt, tot, st_out)) {
+        const double inv_gn = 1.0 / sS.gn, s_acc = sS.s_acc;
         for (long long j = (long long)blockIdx.x * kBlock + threadIdx.x; j < pp.n; j += (long long)gridDim.x * kBlock)
-            x[j * B + s] = (float)((double)x[j * B + s] + S.s_acc * (-(double)c[j] * inv_gn));
+            x[j * B + s] = linear_step_point(x[j * B + s], c[j], s_acc, inv_gn);
     }
-    publish_state(S, st_out, s, apply);
 }
 
 // Trial launch for the squared norm and the linear objective (flat vectors).
@@ -3221,21 +3288,26 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
                                                           const float *__restrict__ lower,
                                                           const float *__restrict__ upper, RowW w,
                                                           const SliceState *__restrict__ st,
-                                                          double *__restrict__ partials, float *__restrict__ ypart)
+                                                          double *__restrict__ partials, float *__restrict__ ypart,
+                                                          LinPhase L)
 {
     extern __shared__ __align__(16) unsigned char fused_lds[];
     float *zl = reinterpret_cast<float *>(fused_lds);
     float *y = zl + ((n + 3) & ~3);
     __shared__ double lds[kFusedBlock / 64];
+    __shared__ double tot[kTrialChunk];
+    __shared__ SliceState sS;
     constexpr int RPB = kFusedBlock / LPR;
     constexpr int STEP = LPR * VEC;
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
-    const bool live = st[0].live != 0;
+    const bool step = L.c && linear_phase<kFusedBlock>(sS, st, L.pp, L.part, 0, L.nparts, tot, L.st_out);
+    const bool live = (L.c ? sS.live : st[0].live) != 0;
     for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = 0.f;
     double pacc[1] = {0.0};
     if (live) {
-        stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
+        if (step) stage_linear_point<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, L.c, n, sS.s_acc, 1.0 / sS.gn);
+        else stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
         __syncthreads();
         const long long stride = (long long)gridDim.x * RPB;
         long long row = (long long)blockIdx.x * RPB + grp;
@@ -3288,22 +3360,27 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, cons
                                                            const float *__restrict__ lower,
                                                            const float *__restrict__ upper, RowW w,
                                                            const SliceState *__restrict__ st,
-                                                           double *__restrict__ partials, float *__restrict__ ypart)
+                                                           double *__restrict__ partials, float *__restrict__ ypart,
+                                                           LinPhase L)
 {
     extern __shared__ __align__(16) unsigned char fused_lds[];
     float *zl = reinterpret_cast<float *>(fused_lds);
     float *y = zl + ((n + 3) & ~3);
     __shared__ double lds[kFusedBlock / 64];
+    __shared__ double tot[kTrialChunk];
+    __shared__ SliceState sS;
     constexpr int RPB = kFusedBlock / LPR;
     constexpr int STEP = LPR * VEC;
     const int lane = threadIdx.x & (LPR - 1);
     const int grp = threadIdx.x / LPR;
     const int slot = (lane + grp) & (LPR - 1);
-    const bool live = st[0].live != 0;
+    const bool step = L.c && linear_phase<kFusedBlock>(sS, st, L.pp, L.part, 0, L.nparts, tot, L.st_out);
+    const bool live = (L.c ? sS.live : st[0].live) != 0;
     for (int j = threadIdx.x; j < n; j += kFusedBlock) y[j] = 0.f;
     double pacc[1] = {0.0};
     if (live) {
-        stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
+        if (step) stage_linear_point<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, L.c, n, sS.s_acc, 1.0 / sS.gn);
+        else stage_vector<kFusedBlock>(reinterpret_cast<float4 *>(zl), x, n);
         __syncthreads();
         const long long stride = (long long)gridDim.x * RPB;
         long long row = (long long)blockIdx.x * RPB + grp;
@@ -3434,6 +3511,7 @@ struct FusedArgs {
     const SliceState *st;
     double *partials;
     void *ypart;
+    LinPhase lp; // lp.c == nullptr: no phase in the pass
 };
 
 // prepare != 0: only raise the kernel's dynamic-LDS attribute (done outside
@@ -3449,7 +3527,7 @@ hipError_t fused_zl_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hip
         return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)bytes);
     hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(kFusedBlock), bytes, s, *a.A, (int)a.n, a.x, a.lower, a.upper, a.w,
-                       a.st, a.partials, static_cast<float *>(a.ypart));
+                       a.st, a.partials, static_cast<float *>(a.ypart), a.lp);
     return hipGetLastError();
 }
 
@@ -3460,6 +3538,7 @@ hipError_t fused_go(const FusedCfg &cfg, const FusedArgs &a, int prepare, hipStr
         if constexpr (sizeof(AccT) != sizeof(float)) return hipErrorInvalidValue; // float32 partials only
         else return fused_zl_go<LPR, VT, VEC>(cfg, a, prepare, s);
     }
+    if (a.lp.c) return hipErrorInvalidValue; // the linear phase rides only on the shapes with z in LDS
     auto kern = k_fused<LPR, VEC, VT, AccT>;
     if (cfg.cap > 0) {
         // register-cached shapes hold CAP*LPR*VEC = 256 entries of a row; with
@@ -3525,33 +3604,36 @@ hipError_t fused_dispatch(const FusedCfg &cfg, int vk, const FusedArgs &a, int p
 hipError_t prepare_fused(const FusedCfg &cfg, int vk, int64_t n)
 {
     SpView none{};
-    FusedArgs a{&none, n, nullptr, nullptr, nullptr, RowW{nullptr, nullptr, 0}, nullptr, nullptr, nullptr};
+    FusedArgs a{&none, n, nullptr, nullptr, nullptr, RowW{nullptr, nullptr, 0}, nullptr, nullptr, nullptr, LinPhase{}};
     return fused_dispatch(cfg, vk, a, 1, nullptr);
 }
 
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
                         const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
-                        hipStream_t s)
+                        hipStream_t s, const LinPhase *lp)
 {
     if (w.qform) return hipErrorInvalidValue; // the fused pass makes c, never the quadratic form
-    FusedArgs a{&A, n, x, lower, upper, w, st, partials, ypart};
+    if (lp && (!lp->c || !lp->part || !lp->st_out || lp->pp.obj != OBJ_LINEAR || lp->pp.B != 1 || lp->pp.n != n ||
+               lp->nparts < 1 || lp->nparts > 65535 || lp->pp.max_trials < 1 || lp->pp.max_trials > 1024 || !cfg.zl))
+        return hipErrorInvalidValue;
+    FusedArgs a{&A, n, x, lower, upper, w, st, partials, ypart, lp ? *lp : LinPhase{}};
     return fused_dispatch(cfg, vk, a, 0, s);
 }
 
 hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, int nvec, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
-                              hipStream_t s, const float *lin_c, double *lin_part)
+                              hipStream_t s, const float *lin_c, double *lin_part, int lin_z)
 {
     if (cfg.grid < 1 || cfg.grid > kMaxPassGrid || n < 1 || nvec < cfg.grid || nvec > 2 * cfg.grid ||
-        (cfg.acc64 && nvec != cfg.grid) || (lin_part && (!lin_c || cs.defer)))
+        (cfg.acc64 && nvec != cfg.grid) || (lin_part && (!lin_c || cs.defer)) || (lin_z && (!lin_c || cs.defer)))
         return hipErrorInvalidValue;
     const unsigned grid = (unsigned)fused_apply_grid(n);
     if (cfg.acc64)
         hipLaunchKernelGGL(k_fused_apply<double>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const double *>(ypart),
-                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h, lin_c, lin_part);
+                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h, lin_c, lin_part, lin_z);
     else
         hipLaunchKernelGGL(k_fused_apply<float>, dim3(grid), dim3(kApplyBlock), 0, s, static_cast<const float *>(ypart),
-                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h, lin_c, lin_part);
+                           nvec, (int)n, x, cs, st_in, st_out, part1, cfg.grid, h, lin_c, lin_part, lin_z);
     return hipGetLastError();
 }
 

@@ -100,6 +100,18 @@ struct PertParams {
     int adaptive;    // 1: the adaptive step (one trial per phase, beta from the state); 0: the power law
 };
 
+// The linear objective's perturbation phase taken inside the fused pass with
+// z in LDS (one slice): the direction partials the last apply kernel left
+// (sum c_j^2 and sum c_j x_j per workgroup), and the state buffer the phase's
+// state goes to.  c == nullptr: no phase in the pass.
+struct LinPhase {
+    const float *c;
+    const double *part;
+    int nparts;
+    SliceState *st_out;
+    PertParams pp;
+};
+
 struct Hist {
     double *prox;
     double *f_start;
@@ -311,9 +323,12 @@ size_t fused_zl_lds_bytes(int64_t n);
 // scatter (cap != 0): 16 entries a lane (more, beside the LDS reads in
 // flight, would not fit the 128 registers of a 1024-thread workgroup's lane)
 constexpr int fused_zl_cap(int lpr, int vec) { return lpr > 0 ? 16 / vec : 0; }
+// lp (shapes with z in LDS, one slice): the linear objective's phase opened
+// from its partials and z = x + s v staged instead of x; the phase's state
+// goes to lp->st_out.
 hipError_t launch_fused(const FusedCfg &cfg, const SpView &A, int vk, int64_t n, const float *x, const float *lower,
                         const float *upper, RowW w, const SliceState *st, double *partials, void *ypart,
-                        hipStream_t s);
+                        hipStream_t s, const LinPhase *lp = nullptr);
 // workgroups of the fused pass's apply kernel (its ||y||^2 partials in deferred mode)
 int fused_apply_grid(int64_t n);
 // x = clip(z + lambda * sum of the partial vectors, lo, hi), closing the
@@ -323,9 +338,12 @@ int fused_apply_grid(int64_t n);
 // lin_part (with lin_c): also the linear objective's direction partials of
 // the x written, for the next phase (fused_apply_grid(n) slots, not in the
 // deferred mode)
+// lin_z != 0 (with lin_c): x holds x^k and the pass took the linear phase, so
+// z_j = x_j + s v_j is formed here from the phase's state in st_in.
 hipError_t launch_fused_apply(const FusedCfg &cfg, int64_t n, const void *ypart, int nvec, float *x, ColStep cs,
                               const SliceState *st_in, SliceState *st_out, const double *part1, Hist h,
-                              hipStream_t s, const float *lin_c = nullptr, double *lin_part = nullptr);
+                              hipStream_t s, const float *lin_c = nullptr, double *lin_part = nullptr,
+                              int lin_z = 0);
 // the same direction partials of x alone (one slice)
 hipError_t launch_lin_partials(const float *x, const float *c, int64_t n, double *part, hipStream_t s);
 // y partials of rows [r_lo, r_hi) whose c is set (the dose-volume rows of a

@@ -108,10 +108,13 @@ def dvc_trajectory_margin(w, K, perturb=True, s=0, value_round=None, refine=0):
     return worst
 
 
-def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1, fused=True, phase_form=None):
+def gpu_run(smx, w, K, perturb=True, storage="f32", graph=False, refine_iters=-1, fused=True, phase_form=None,
+            fused_shape=None):
     p = smx.problem_from_workload(w, storage=storage, history_cap=K, refine_iters=refine_iters, fused=fused)
     if phase_form is not None:
         p.set_phase_form(phase_form)
+    if fused_shape is not None:
+        p.set_fused_shape(*fused_shape)
     p.run(K, perturb=perturb, graph=graph)
     p.sync()
     x = p.get_x().cpu().numpy().astype(np.float64)
@@ -163,7 +166,7 @@ def storage_deviation(w, K, perturb=True, s=0, value_round=None, refine=0):
 
 
 def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=None, refine_iters=-1,
-                 sensitive=False, fused=True, phase_form=None):
+                 sensitive=False, fused=True, phase_form=None, fused_shape=None):
     """End-to-end parity.  With sensitive=True (TV problems, whose gradient
     amplifies rounding of the iterate), the iterate and proximity tolerances
     are max(tol, 10 x the deviation float32 storage of the iterate alone
@@ -184,9 +187,9 @@ def check_parity(smx, w, K, perturb=True, tol=RTOL, storage="f32", value_round=N
     float32 near-ties (dvc_trajectory_margin above TIE_REL), so that the
     device and the oracle pick the same nearest point."""
     say(f"{w.name} m={w.m} n={w.n} nnz={w.nnz} K={K} perturb={perturb} obj={w.obj} storage={storage} "
-        f"fused={fused} phase_form={phase_form}")
+        f"fused={fused} phase_form={phase_form} fused_shape={fused_shape}")
     x, prox, obj, h, st = gpu_run(smx, w, K, perturb, storage=storage, refine_iters=refine_iters, fused=fused,
-                                  phase_form=phase_form)
+                                  phase_form=phase_form, fused_shape=fused_shape)
     refine = 0
     if storage != "f32":
         refine = refine_iters if refine_iters >= 0 else (K + 19) // 20
@@ -791,25 +794,41 @@ def test_phase_forms_parity(smx, case, form):
     check_parity(smx, w, w.K, phase_form=f)
 
 
-def test_closed_form_partials_from_apply(smx):
+def linear_phase_launches(p):
+    """Launches of the closed-form linear phase the library reports for p: none
+    when the fused pass with z in LDS takes it, one when the fused pass's apply
+    kernel only leaves it the direction partials, two otherwise."""
+    for v in p.describe().values():
+        if isinstance(v, dict) and isinstance(v.get("fused"), dict) and v["fused"]["in_use"]:
+            return 0 if v["fused"]["zl"] else 1
+    return 2
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 2, 1), (8, 4, 0, 1), (8, 4, 0, 0)])
+def test_closed_form_partials_from_apply(smx, shape):
     """The closed-form linear phase on the fused pass takes its direction
     partials from the previous iteration's apply kernel (and from a
     partials launch where a run, or a run of iterations of one value kind,
-    starts): against the oracle with the bf16 operator and a float32
-    refinement tail (a change of value kind mid-run), and across a
-    checkpoint and resume."""
+    starts); with z in LDS the pass itself opens the phase and stages
+    z = x + s v, and the apply kernel forms z_j again (no launch of its
+    own), with z gathered one closed-form launch adds the step: against the
+    oracle with the bf16 operator and a float32 refinement tail (a change of
+    value kind mid-run), and across a checkpoint and resume."""
     w = W.random_sparse(6000, 9000, 20, seed=51, empty_frac=0.05, obj=W.OBJ_LINEAR, K=24)
     p = smx.problem_from_workload(w)
-    assert p.fused_in_use() and p.describe()["phase_launches"] == 1
+    p.set_fused_shape(*shape)
+    assert p.fused_in_use() and p.describe()["phase_launches"] == (0 if shape[3] else 1)
     p.close()
-    check_parity(smx, w, w.K, storage="bf16", value_round="bf16", refine_iters=5)
-    say("closed-form phase on the fused pass, checkpoint and resume")
+    check_parity(smx, w, w.K, storage="bf16", value_round="bf16", refine_iters=5, fused_shape=shape)
+    say(f"closed-form phase on the fused pass {shape}, checkpoint and resume")
     p = smx.problem_from_workload(w, history_cap=0)
+    p.set_fused_shape(*shape)
     p.run(10, graph=True)
     p.sync()
     states, x1 = p.get_state()
     p.close()
     q = smx.problem_from_workload(w, history_cap=0)
+    q.set_fused_shape(*shape)
     q.set_state(states, x1)
     q.run(w.K - 10, graph=True)
     q.sync()
@@ -833,8 +852,8 @@ def test_phase_form_choice_and_args(smx):
         d = p.describe()
         if launches is not None:
             assert d["phase_launches"] == launches
-        elif w.obj == W.OBJ_LINEAR:  # closed form: one launch when the apply kernel leaves the partials
-            assert d["phase_launches"] == (1 if p.fused_in_use() else 2)
+        elif w.obj == W.OBJ_LINEAR:  # closed form: in the fused pass, or after its apply kernel's partials
+            assert d["phase_launches"] == linear_phase_launches(p)
         else:
             assert d["phase_launches"] > 1
         if eligible:
@@ -845,8 +864,7 @@ def test_phase_form_choice_and_args(smx):
                 p.set_phase_form(smx.PHASE_ONE_LAUNCH)
         if w.obj == W.OBJ_LINEAR:
             p.set_phase_form(smx.PHASE_CLOSED_FORM)
-            # one launch where the fused pass's apply kernel leaves the direction partials
-            assert p.describe()["phase_launches"] == (1 if p.fused_in_use() else 2)
+            assert p.describe()["phase_launches"] == linear_phase_launches(p)
         else:
             with pytest.raises(smx.SmxError, match="ESTATE"):
                 p.set_phase_form(smx.PHASE_CLOSED_FORM)
