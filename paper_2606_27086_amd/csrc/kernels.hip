@@ -2201,11 +2201,11 @@ __global__ __launch_bounds__(kTrialBlock) void k_trial_tv(float *__restrict__ x,
 }
 
 // Closing launch of a phase: the decision of the last trial launch and, when
-// the phase ends there, the accepted step added to the whole of x (the same
-// arithmetic as the trial launches' own apply).  One workgroup per slice: in
-// most iterations an earlier trial launch has applied the step already and
-// this launch only carries the state over.  nt: workgroups per slice of the
-// trial launches (their partials' layout).
+// the phase ends there, the accepted step added to x (the same arithmetic as
+// the trial launches' own apply), each workgroup on its own part of x.  Where
+// an earlier trial launch has applied the step already, the launch only
+// carries the state over (workgroup 0 publishes it).  nt: workgroups per slice
+// of the trial launches (their partials' layout).
 __global__ __launch_bounds__(kTrialBlock) void k_trial_close(float *__restrict__ x, const float *__restrict__ g,
                                                              const SliceState *__restrict__ st_in,
                                                              SliceState *__restrict__ st_out, PertParams pp, int nt,
@@ -2220,7 +2220,8 @@ __global__ __launch_bounds__(kTrialBlock) void k_trial_close(float *__restrict__
     const bool apply = must_apply(S);
     if (apply) {
         const double inv_gn = 1.0 / S.gn;
-        for (long long j = threadIdx.x; j < pp.n; j += kTrialBlock) {
+        for (long long j = (long long)blockIdx.x * kTrialBlock + threadIdx.x; j < pp.n;
+             j += (long long)gridDim.x * kTrialBlock) {
             const double gj = lin ? (double)g[j] : (double)g[j * B + s];
             x[j * B + s] = (float)((double)x[j * B + s] + S.s_acc * (-gj * inv_gn));
         }
@@ -4077,7 +4078,9 @@ hipError_t launch_trial_close(const PertParams &pp, float *x, const float *g, co
                               SliceState *st_out, const double *part_prev, hipStream_t s)
 {
     if (pp.max_trials < 1 || pp.max_trials > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_trial_close, dim3(1, pp.B), dim3(kTrialBlock), 0, s, x, g, st_in, st_out, pp,
+    const long long g_need = (pp.n + kTrialBlock - 1) / kTrialBlock; // one unknown a thread, at most 256 workgroups
+    const unsigned grid = (unsigned)std::max(1LL, std::min(g_need, 256LL));
+    hipLaunchKernelGGL(k_trial_close, dim3(grid, pp.B), dim3(kTrialBlock), 0, s, x, g, st_in, st_out, pp,
                        (int)phase_grid(pp), part_prev);
     return hipGetLastError();
 }
