@@ -276,6 +276,115 @@ struct Entries<F16PTag, VEC> {
     }
 };
 
+// VEC stored entries at p as loaded, before any arithmetic on them (the
+// bit patterns of the values, the index words), and their decoding.  Loops
+// that keep several chunks in flight issue every chunk's loads first, each
+// under its own predicate, and decode afterwards: a decode inside the
+// predicated block would wait for that chunk's load before the next chunk's
+// loads are issued, one memory round trip per chunk.  A chunk left
+// unloaded decodes to value 0 at index 0.
+template <typename VT, int VEC>
+struct EntryRaw {
+    static_assert(VEC == 4 || VEC == 8, "VEC");
+    static constexpr int NV = std::is_same<VT, float>::value || std::is_same<VT, F32U16Tag>::value ? VEC
+                              : (std::is_same<VT, Bf16PTag>::value || std::is_same<VT, F16PTag>::value) ? VEC
+                                                                                                          : VEC / 2;
+    static constexpr bool kIdx32 = !(std::is_same<VT, F32U16Tag>::value || std::is_same<VT, Bf16PTag>::value ||
+                                     std::is_same<VT, F16PTag>::value);
+    static constexpr int NI = kIdx32 ? VEC : (std::is_same<VT, F32U16Tag>::value ? VEC / 2 : 0);
+    uint32_t vw[NV];
+    uint32_t iw[NI > 0 ? NI : 1];
+
+    __device__ inline void zero()
+    {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vw[k] = 0u;
+#pragma unroll
+        for (int k = 0; k < (NI > 0 ? NI : 1); ++k) iw[k] = 0u;
+    }
+    __device__ inline void load(const SpView &A, int p)
+    {
+        if constexpr (std::is_same<VT, Bf16PTag>::value || std::is_same<VT, F16PTag>::value) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(static_cast<const uint32_t *>(A.val) + p);
+#pragma unroll
+            for (int h = 0; h < VEC / 4; ++h) {
+                const uint4 a = q[h];
+                vw[4 * h] = a.x; vw[4 * h + 1] = a.y; vw[4 * h + 2] = a.z; vw[4 * h + 3] = a.w;
+            }
+        } else {
+            if constexpr (NV == VEC) { // 32-bit values
+                const uint4 *q = reinterpret_cast<const uint4 *>(static_cast<const uint32_t *>(A.val) + p);
+#pragma unroll
+                for (int h = 0; h < VEC / 4; ++h) {
+                    const uint4 a = q[h];
+                    vw[4 * h] = a.x; vw[4 * h + 1] = a.y; vw[4 * h + 2] = a.z; vw[4 * h + 3] = a.w;
+                }
+            } else { // 16-bit values, two a word
+                const uint16_t *b = static_cast<const uint16_t *>(A.val) + p;
+                if constexpr (VEC == 8) {
+                    const uint4 a = *reinterpret_cast<const uint4 *>(b);
+                    vw[0] = a.x; vw[1] = a.y; vw[2] = a.z; vw[3] = a.w;
+                } else {
+                    const uint2 a = *reinterpret_cast<const uint2 *>(b);
+                    vw[0] = a.x; vw[1] = a.y;
+                }
+            }
+            if constexpr (kIdx32) {
+                const uint4 *q = reinterpret_cast<const uint4 *>(A.idx + p);
+#pragma unroll
+                for (int h = 0; h < VEC / 4; ++h) {
+                    const uint4 a = q[h];
+                    iw[4 * h] = a.x; iw[4 * h + 1] = a.y; iw[4 * h + 2] = a.z; iw[4 * h + 3] = a.w;
+                }
+            } else { // 16-bit indices, two a word
+                const uint16_t *ib = reinterpret_cast<const uint16_t *>(A.idx) + p;
+                if constexpr (VEC == 8) {
+                    const uint4 a = *reinterpret_cast<const uint4 *>(ib);
+                    iw[0] = a.x; iw[1] = a.y; iw[2] = a.z; iw[3] = a.w;
+                } else {
+                    const uint2 a = *reinterpret_cast<const uint2 *>(ib);
+                    iw[0] = a.x; iw[1] = a.y;
+                }
+            }
+        }
+    }
+    __device__ inline void decode(float (&v)[VEC], int (&c)[VEC]) const
+    {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            if constexpr (std::is_same<VT, Bf16PTag>::value) {
+                v[e] = bf16_lo(vw[e]);
+                c[e] = (int)(vw[e] >> 16);
+            } else if constexpr (std::is_same<VT, F16PTag>::value) {
+                v[e] = f16_lo(vw[e]);
+                c[e] = (int)(vw[e] >> 16);
+            } else {
+                if constexpr (NV == VEC) v[e] = __uint_as_float(vw[e]);
+                else if constexpr (std::is_same<VT, Bf16Tag>::value) v[e] = (e & 1) ? bf16_hi(vw[e >> 1]) : bf16_lo(vw[e >> 1]);
+                else v[e] = (e & 1) ? f16_hi(vw[e >> 1]) : f16_lo(vw[e >> 1]);
+                if constexpr (kIdx32) c[e] = (int)iw[e];
+                else c[e] = (int)((e & 1) ? (iw[e >> 1] >> 16) : (iw[e >> 1] & 0xFFFFu));
+            }
+        }
+    }
+};
+
+// U chunks of VEC entries (chunk u at p + u * step, loaded where ok[u]):
+// every load issued, then every chunk decoded.
+template <typename VT, int VEC, int U>
+__device__ inline void load_chunks(const SpView &A, int p, int step, const bool (&ok)[U], float (&v)[U][VEC],
+                                   int (&c)[U][VEC])
+{
+    EntryRaw<VT, VEC> raw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        raw[u].zero();
+        if (ok[u]) raw[u].load(A, p + u * step);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) raw[u].decode(v[u], c[u]);
+}
+
 // One entry at p: its value as float and its index.
 template <typename VT>
 __device__ inline void entry1(const SpView &A, int p, float &v, int &c);
@@ -368,10 +477,8 @@ __device__ inline double row_dot_chunked(const SpView &A, int beg, int end, int 
         int c[4][VEC];
         bool ok[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ok[u] = p + u * STEP < end;
-            if (ok[u]) Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
-        }
+        for (int u = 0; u < 4; ++u) ok[u] = p + u * STEP < end;
+        load_chunks<VT, VEC, 4>(A, p, STEP, ok, v, c);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (ok[u]) {
@@ -450,13 +557,10 @@ __global__ __launch_bounds__(kBlock) void k_pass1(SpView A, const float *__restr
                 nbeg = A.ptr[row + stride];
                 nend = A.ptr[row + stride + 1];
             }
-            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
-            if (lane == 0) { // epilogue operands, fetched while the row streams
-                lo = lower[row];
-                up = upper[row];
-                d = w.D[row];
-                sw = w.S[row];
-            }
+            // epilogue operands, fetched while the row streams (every lane of the
+            // group reads the same words: no predicated block whose conversions
+            // would wait for them before the row's loads are issued)
+            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row];
             const double r = group_sum<LPR>(row_dot<LPR, VEC, VT>(A, beg, end, lane, x)) * (double)A.vscale_inv;
             if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
             beg = nbeg;
@@ -538,10 +642,8 @@ __device__ inline double row_dot_split(const SpView &A, int beg, int end, int la
         int c[4][VEC];
         bool ok[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ok[u] = p + u * STEP < end;
-            if (ok[u]) Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
-        }
+        for (int u = 0; u < 4; ++u) ok[u] = p + u * STEP < end;
+        load_chunks<VT, VEC, 4>(A, p, STEP, ok, v, c);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (ok[u]) {
@@ -595,13 +697,7 @@ __global__ __launch_bounds__(kLdsPassBlock) void k_pass1_lds(SpView A, const flo
                 nbeg = A.ptr[row + stride];
                 nend = A.ptr[row + stride + 1];
             }
-            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
-            if (lane == 0) {
-                lo = lower[row];
-                up = upper[row];
-                d = w.D[row];
-                sw = w.S[row];
-            }
+            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row]; // read by every lane
             const double r =
                 group_sum<LPR>(row_dot_split<LPR, VEC, VT>(A, beg, end, lane, x, xl, P)) * (double)A.vscale_inv;
             if (lane == 0) pacc[0] += epi1(w, r, lo, up, d, sw, c + row, row, 0, 1);
@@ -946,10 +1042,8 @@ __device__ inline double seg_dot_lds(const SpView &A, int beg, int end, int lane
         int c[4][VEC];
         bool ok[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            ok[u] = p + u * STEP < end;
-            if (ok[u]) Entries<VT, VEC>::load(A, p + u * STEP, v[u], c[u]);
-        }
+        for (int u = 0; u < 4; ++u) ok[u] = p + u * STEP < end;
+        load_chunks<VT, VEC, 4>(A, p, STEP, ok, v, c);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (ok[u]) {
@@ -1255,19 +1349,10 @@ struct RowRegs {
 template <int LPR, int VEC, int CAP, typename VT>
 __device__ inline void fetch_entries(const SpView &A, int beg, int end, int slot, RowRegs<VEC, CAP> &R)
 {
+    bool ok[CAP];
 #pragma unroll
-    for (int q = 0; q < CAP; ++q) {
-        const int p = beg + (q * LPR + slot) * VEC;
-        if (p < end) {
-            Entries<VT, VEC>::load(A, p, R.v[q], R.c[q]);
-        } else {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                R.v[q][e] = 0.f;
-                R.c[q][e] = 0;
-            }
-        }
-    }
+    for (int q = 0; q < CAP; ++q) ok[q] = beg + (q * LPR + slot) * VEC < end;
+    load_chunks<VT, VEC, CAP>(A, beg + slot * VEC, LPR * VEC, ok, R.v, R.c);
 }
 
 template <int LPR, int VEC, int CAP, typename VT, typename AccT>
@@ -3323,13 +3408,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zl(SpView A, int n, const
                 nbeg = A.ptr[row + stride];
                 nend = A.ptr[row + stride + 1];
             }
-            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
-            if (lane == 0) {
-                lo = lower[row];
-                up = upper[row];
-                d = w.D[row];
-                sw = w.S[row];
-            }
+            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row]; // read by every lane
             const double r =
                 group_sum<LPR>(row_dot_split<LPR, VEC, VT>(A, beg, end, lane, x, zl, n)) * (double)A.vscale_inv;
             double ct = 0.0;
@@ -3391,22 +3470,25 @@ __global__ __launch_bounds__(kFusedBlock) void k_fused_zlr(SpView A, int n, cons
             end = A.ptr[row + 1];
         }
         for (; row < A.rows; row += stride) {
-            RowRegs<VEC, CAP> R;
-            fetch_entries<LPR, VEC, CAP, VT>(A, beg, end, slot, R);
-            // the next row's offsets, in flight while this row is reduced and
-            // scattered: its entries can then be requested at once
+            // the row's entries, the next row's offsets (in flight while this row
+            // is reduced and scattered, so its entries are requested at once) and
+            // the epilogue operands: all requested before any of them is used
+            EntryRaw<VT, VEC> raw[CAP];
+#pragma unroll
+            for (int q = 0; q < CAP; ++q) {
+                raw[q].zero();
+                const int p = beg + (q * LPR + slot) * VEC;
+                if (p < end) raw[q].load(A, p);
+            }
             int nbeg = 0, nend = 0;
             if (row + stride < A.rows) {
                 nbeg = A.ptr[row + stride];
                 nend = A.ptr[row + stride + 1];
             }
-            float lo = 0.f, up = 0.f, d = 0.f, sw = 0.f;
-            if (lane == 0) {
-                lo = lower[row];
-                up = upper[row];
-                d = w.D[row];
-                sw = w.S[row];
-            }
+            const float lo = lower[row], up = upper[row], d = w.D[row], sw = w.S[row]; // read by every lane
+            RowRegs<VEC, CAP> R;
+#pragma unroll
+            for (int q = 0; q < CAP; ++q) raw[q].decode(R.v[q], R.c[q]);
             double acc[2] = {0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < CAP; ++q)
