@@ -422,6 +422,17 @@ def test_lowp_matches_oracle_on_rounded_operator(smx, storage):
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_lowp_wide_operator_32bit_indices(smx, storage):
+    """Reduced-precision values beside 32-bit column indices (n above the
+    16-bit index range, so neither the packed words nor the 16-bit index
+    arrays serve; the rows' chunks are loaded as raw words and decoded after
+    all of them are requested): against the oracle on the rounded
+    operator."""
+    w = W.random_sparse(4000, 70000, 40, seed=71, long_rows=4, long_len=900, obj=W.OBJ_L1, K=12)
+    check_parity(smx, w, w.K, storage=storage, value_round=storage)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_lowp_against_float_operator(smx, storage):
     """Against the oracle on the float32 operator: proximity and objective
     within 2e-2 after K iterations (with the float32 refinement tail)."""
